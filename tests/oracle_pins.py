@@ -1,0 +1,332 @@
+"""Pins of the FP64 oracle against facts outside the oracle itself.
+
+Each ``pin_*`` function raises AssertionError when the oracle disagrees with
+a library routine, a closed form, an invariant of the method or a brute-force
+answer.  ``test_oracle_pins.py`` runs them; ``test_oracle_mutations.py``
+plants plausible mistakes in the oracle and checks that some pin fails.
+"""
+from __future__ import annotations
+
+import math
+from fractions import Fraction
+
+import numpy as np
+
+import synth
+from oracle import container, dls
+from oracle.jacobi import cyclic_jacobi
+
+SHAPES = [(16, 64), (16, 16), (4, 64), (32, 128), (5, 7), (1, 9), (16, 512)]
+
+
+def _rand_block(rng, w, m, kind="smooth"):
+    if kind == "smooth":
+        t = np.arange(w)[:, None]
+        p = np.arange(m)[None, :]
+        x = np.zeros((w, m))
+        for _ in range(4):
+            x += rng.normal() * np.cos(rng.uniform(0, 0.3) * t + rng.uniform(0, 0.2) * p
+                                       + rng.uniform(0, 6.28))
+        return x + 1e-4 * rng.normal(size=(w, m))
+    return rng.normal(size=(w, m))
+
+
+# -- eigenpairs -----------------------------------------------------------
+def pin_eigenvalues_vs_svd():
+    """lam_k(X X^T) = sigma_k(X)^2 (LAPACK gesdd, a different driver)."""
+    rng = np.random.default_rng(7)
+    for (w, m) in SHAPES:
+        for kind in ("smooth", "normal"):
+            x = _rand_block(rng, w, m, kind)
+            lam, V = dls.eig_desc(x @ x.T)
+            s = np.linalg.svd(x, compute_uv=False)
+            ref = np.zeros(w)
+            ref[:s.size] = s ** 2
+            assert np.allclose(lam, ref, rtol=0, atol=1e-12 * ref[0]), (w, m, kind)
+
+
+def pin_eigenvectors_orthonormal_and_residual():
+    """||V^T V - I||_max <= 1e-12 and G V = V diag(lam) to 1e-12 ||G||."""
+    rng = np.random.default_rng(8)
+    for (w, m) in SHAPES:
+        x = _rand_block(rng, w, m)
+        G = x @ x.T
+        lam, V = dls.eig_desc(G)
+        assert np.abs(V.T @ V - np.eye(w)).max() <= 1e-12
+        assert np.abs(G @ V - V * lam[None, :]).max() <= 1e-12 * max(1.0, lam[0])
+        for k in range(w):
+            i = int(np.argmax(np.abs(V[:, k])))
+            assert V[i, k] > 0
+
+
+def pin_eigenvalues_vs_jacobi():
+    """LAPACK eigenvalues equal an independent cyclic Jacobi's."""
+    rng = np.random.default_rng(9)
+    for (w, m) in [(16, 64), (8, 8), (5, 7)]:
+        x = _rand_block(rng, w, m, "normal")
+        G = x @ x.T
+        lam, _ = dls.eig_desc(G)
+        jl, jv = cyclic_jacobi(G)
+        jl = np.sort(jl)[::-1]
+        assert np.allclose(lam, np.maximum(jl, 0), rtol=0, atol=1e-11 * lam[0])
+
+
+# -- rank rule ------------------------------------------------------------
+def pin_rank_bruteforce():
+    """Chosen r is the smallest with ||X - V_r V_r^T X||_F^2 <= tau.
+
+    The discarded energy is computed by explicit projection (Eckart-Young
+    says it equals the eigenvalue tail) and the answer is cross-checked by a
+    bisection over the monotone criterion, the search the paper uses.
+    """
+    rng = np.random.default_rng(10)
+    for (w, m) in SHAPES:
+        x = _rand_block(rng, w, m)
+        lam, V = dls.eig_desc(x @ x.T)
+        rcap = min(w, m)
+        errs = []
+        for r in range(0, rcap + 1):
+            P = V[:, :r] @ V[:, :r].T
+            e = float(np.sum((x - P @ x) ** 2))
+            errs.append(e)
+            tail = dls.tail_energies(lam)[r]
+            assert abs(e - tail) <= 1e-10 * max(1.0, lam[0]), (w, m, r)
+        for eps in (1e-1, 1e-2, 1e-3, 3e-5):
+            tau = dls.KAPPA * eps * eps * m * w
+            r = dls.choose_rank(lam, tau, rcap)
+            ok = [rr for rr in range(1, rcap + 1) if errs[rr] <= tau + 1e-12 * lam[0]]
+            expect = ok[0] if ok else rcap
+            assert r == expect, (w, m, eps, r, expect)
+            lo, hi = 1, rcap
+            while lo < hi:
+                mid = (lo + hi) // 2
+                if dls.tail_energies(lam)[mid] <= tau:
+                    hi = mid
+                else:
+                    lo = mid + 1
+            assert lo == r
+
+
+def pin_exact_rank_data():
+    """X = sum_{k<=r0} s_k a_k b_k^T reconstructs to round-off with r = r0.
+
+    eps = 1e-6 puts tau = eps^2 M W far above the Gram's round-off
+    eigenvalues (~1e-16 lam_1) and far below s_min^2 >= 1.
+    """
+    rng = np.random.default_rng(11)
+    for (w, m, r0) in [(16, 64, 3), (16, 512, 1), (32, 128, 7), (8, 8, 8)]:
+        a, _ = np.linalg.qr(rng.normal(size=(w, r0)))
+        b, _ = np.linalg.qr(rng.normal(size=(m, r0)))
+        s = rng.uniform(1, 10, size=r0)
+        x = (a * s) @ b.T
+        c = dls.encode_block(x, 1e-6, min(w, 32), np.float64)
+        assert c.r == r0
+        rec = c.V[:, :c.r] @ c.A.T
+        assert np.abs(rec - x).max() <= 1e-12 * np.abs(x).max()
+        assert np.abs(c.V[:, :c.r].T @ c.V[:, :c.r] - np.eye(c.r)).max() <= 1e-12
+
+
+# -- quantizers and the absolute bound -----------------------------------
+def _blocks_for_bound(rng):
+    out = []
+    for (w, m) in SHAPES:
+        x = _rand_block(rng, w, m)
+        out.append((x, 1e-3 * np.ptp(x)))
+        out.append((x, 1e-6 * np.ptp(x)))
+        out.append((x + 1e7, 1e-3 * np.ptp(x)))           # large offset
+        out.append((_rand_block(rng, w, m, "normal"), 0.5))
+    return out
+
+
+def pin_pointwise_bound():
+    """|x - out| <= eps at every point, for both storage dtypes."""
+    rng = np.random.default_rng(12)
+    for x, eps in _blocks_for_bound(rng):
+        for dt in (np.float64, np.float32):
+            xs = x.astype(dt)
+            c = dls.encode_block(xs, float(eps), 32, dt)
+            out = dls.decode_block(c.r, c.qV, c.qA, c.codes, c.esc_values, float(eps), dt)
+            err = np.abs(xs.astype(np.float64) - out.astype(np.float64)).max()
+            assert err <= eps, (x.shape, eps, dt, err)
+            assert np.array_equal(out, c.out)
+
+
+def pin_escapes_rare_on_smooth_data():
+    """With a sound residual step, FP64 smooth data needs no escapes."""
+    rng = np.random.default_rng(13)
+    for (w, m) in SHAPES:
+        x = _rand_block(rng, w, m)
+        c = dls.encode_block(x, 1e-3 * float(np.ptp(x)), 32, np.float64)
+        assert c.esc_values.size == 0
+        q = dls.unzigzag16(c.codes)
+        assert np.abs(q).max() <= 4
+
+
+def pin_lattice_one_rounding():
+    """out = round(exact (S + 2^17 q) * eps * 2^-16): one correctly rounded product.
+
+    Checked with exact rational arithmetic on tiny blocks whose S and q are
+    recomputed here with Python integers.  The rank is capped at 1 on a rank-2
+    block so that the residual codes are nonzero and the code step (2 eps =
+    2^17 c) is exercised.
+    """
+    base = np.array([[1.0, 2.0, -1.0], [2.0, 4.0, 0.5]])
+    for pert, eps, rcap in ((1e-3, 0.01, 2), (0.07, 0.01, 1), (0.3, 0.02, 1)):
+        x = base + np.array([[0.0, pert, 0.0], [-pert, 0.0, 2 * pert]])
+        c = dls.encode_block(x, eps, rcap, np.float64)
+        qV = [[int(v) for v in row] for row in c.qV]
+        qA = [[int(v) for v in row] for row in c.qA]
+        q = dls.unzigzag16(c.codes)
+        if rcap == 1:
+            assert np.abs(q).max() >= 1
+        cf = Fraction(eps) / (1 << 16)
+        for t in range(2):
+            for p in range(3):
+                S = sum(qV[t][k] * qA[p][k] for k in range(c.r))
+                exact = Fraction(S + (1 << 17) * int(q[t, p])) * cf
+                assert float(exact) == c.out[t, p]
+                assert abs(Fraction(x[t, p]) - Fraction(c.out[t, p])) <= Fraction(eps)
+        # basis and coefficient quantizers: round half to even of V 2^16 and A / eps
+        assert np.array_equal(c.qV, np.rint(c.V[:, :c.r] * 65536.0).astype(np.int64))
+        assert np.array_equal(c.qA, np.rint(c.A / eps).astype(np.int64))
+
+
+def pin_hand_worked_rank_one():
+    """X = [[1, 2], [2, 4]]: G = [[5, 10], [10, 20]], lam = (25, 0), v1 = (1, 2)/sqrt 5.
+
+    A = X^T v1 = (sqrt 5, 2 sqrt 5); with eps = 0.5: qV = rint(65536 v1) =
+    (29309, 58617) (65536/sqrt 5 = 29308.59), qA = rint(2 A) = (4, 9).
+    """
+    x = np.array([[1.0, 2.0], [2.0, 4.0]])
+    c = dls.encode_block(x, 0.5, 2, np.float64)
+    assert c.r == 1
+    assert np.allclose(c.lam, [25.0, 0.0], atol=1e-13)
+    assert np.allclose(c.V[:, 0], np.array([1.0, 2.0]) / math.sqrt(5.0), atol=1e-15)
+    assert np.allclose(c.A[:, 0], [math.sqrt(5.0), 2 * math.sqrt(5.0)], atol=1e-14)
+    assert c.qV[:, 0].tolist() == [29309, 58617]
+    assert c.qA[:, 0].tolist() == [4, 9]
+    S = np.array([[29309 * 4, 29309 * 9], [58617 * 4, 58617 * 9]])
+    xhat = S * (0.5 / 65536.0)
+    q = np.rint((x - xhat) / 1.0)
+    assert np.array_equal(dls.unzigzag16(c.codes), q)
+
+
+def pin_special_blocks():
+    """Constant block: r = 1, lam_1 = c^2 M W.  Zero block: r = 1, qA = 0.  W_b = 1: r = 1."""
+    w, m, cst = 16, 64, 0.75
+    x = np.full((w, m), cst)
+    c = dls.encode_block(x, 1e-3, 16, np.float64)
+    assert c.r == 1 and abs(c.lam[0] - cst * cst * m * w) <= 1e-12 * cst * cst * m * w
+    assert np.all(c.lam[1:] <= 1e-12)
+    assert c.esc_values.size == 0
+    z = dls.encode_block(np.zeros((w, m)), 1e-3, 16, np.float64)
+    assert z.r == 1 and not z.qA.any() and not z.codes.any()
+    one = dls.encode_block(np.random.default_rng(3).normal(size=(1, m)), 1e-3, 16, np.float64)
+    assert one.r == 1
+    nan = np.ones((4, 8))
+    nan[2, 3] = np.nan
+    rb = dls.encode_block(nan, 1e-3, 16, np.float64)
+    assert rb.r == 0 and rb.esc_values.size == 32
+    out = dls.decode_block(0, rb.qV, rb.qA, rb.codes, rb.esc_values, 1e-3, np.float64)
+    assert np.array_equal(out, nan, equal_nan=True)
+
+
+# -- plan -----------------------------------------------------------------
+def pin_gradient_and_percentile():
+    rng = np.random.default_rng(14)
+    f = rng.normal(size=(5, 6, 7))
+    g = dls.gradient_magnitude(f)
+    gz, gy, gx = np.gradient(f, edge_order=1)
+    assert np.allclose(g, np.sqrt(gx ** 2 + gy ** 2 + gz ** 2), rtol=1e-14, atol=0)
+    f2 = rng.normal(size=(1, 9, 11))
+    g2 = dls.gradient_magnitude(f2)
+    gy2, gx2 = np.gradient(f2[0], edge_order=1)
+    assert np.allclose(g2[0], np.sqrt(gx2 ** 2 + gy2 ** 2), rtol=1e-14, atol=0)
+    for n in (1000, 1001, 37, 2):
+        v = rng.normal(size=n)
+        assert dls.percentile80(v) == np.percentile(v, 80, method="lower")
+
+
+def _localized_field(nx, ny, nz):
+    """A few narrow Gaussian bumps on a smooth background (refines locally)."""
+    rng = np.random.default_rng(15)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    f = 0.01 * np.sin(0.05 * x + 0.03 * y + 0.02 * z)
+    for _ in range(3):
+        c = rng.uniform(0, 1, 3) * [nx, ny, nz]
+        w = rng.uniform(1.5, 3.0)
+        d2 = (x - c[0]) ** 2 + (y - c[1]) ** 2 + ((z - c[2]) ** 2 if nz > 1 else 0)
+        f += np.exp(-d2 / (2 * w * w))
+    return f
+
+
+def pin_adaptive_plan():
+    """Leaves tile the domain once, respect [pmin, pmax], are sorted, follow the rule."""
+    for (nz, ny, nx, pmax, pmin) in [(1, 64, 96, 32, 4), (1, 50, 37, 16, 4), (24, 20, 32, 16, 4)]:
+        f = _localized_field(nx, ny, nz)
+        p = dls.Params(nx=nx, ny=ny, nz=nz, nt=1, nvars=1, dtype="f64", px=pmax,
+                       py=pmax, pz=pmax if nz > 1 else 1, window=1, eps=[1.0],
+                       pmin=pmin, adaptive=True)
+        leaves, bits = dls.adaptive_leaves(f, p)
+        cover = np.zeros((nz, ny, nx), np.int32)
+        for (x0, y0, z0, ex, ey, ez, e) in leaves:
+            cover[z0:z0 + ez, y0:y0 + ey, x0:x0 + ex] += 1
+        assert (cover == 1).all()
+        keys = [(L[2], L[1], L[0]) for L in leaves]
+        assert keys == sorted(keys)
+        g = dls.gradient_magnitude(f)
+        thr = float(np.percentile(g, 80, method="lower"))
+        nsplit = 0
+        for (x0, y0, z0, ex, ey, ez, e) in leaves:
+            assert pmin <= e <= pmax and e & (e - 1) == 0
+            assert x0 % e == 0 and y0 % e == 0 and (nz == 1 or z0 % e == 0)
+            assert ex == min(e, nx - x0) and ey == min(e, ny - y0)
+            if e > pmin:      # not split: mean gradient at or below the threshold
+                assert g[z0:z0 + ez, y0:y0 + ey, x0:x0 + ex].mean() <= thr
+            if e < pmax:      # its parent was split: parent mean above the threshold
+                h = 2 * e
+                px0, py0 = x0 - x0 % h, y0 - y0 % h
+                pz0 = z0 - z0 % h if nz > 1 else 0
+                pz1 = pz0 + h if nz > 1 else 1
+                assert g[pz0:pz1, py0:py0 + h, px0:px0 + h].mean() > thr
+                nsplit += 1
+        assert nsplit > 0
+        assert dls.leaves_from_bits(p, bits) == leaves
+
+
+# -- container ------------------------------------------------------------
+def _c1_small(adaptive=False, dtype=np.float64):
+    f = synth.blobs2d(nx=40, ny=36, nt=20, seed=2, dtype=dtype)
+    rng_ = synth.range_of(f)
+    p = dls.Params(nx=40, ny=36, nz=1, nt=20, nvars=1,
+                   dtype="f64" if dtype == np.float64 else "f32",
+                   px=16 if adaptive else 8, py=16 if adaptive else 8, pz=1,
+                   window=16, eps=[1e-3 * rng_[0]], pmin=4, adaptive=adaptive)
+    return f, p
+
+
+def pin_container_round_trip():
+    for adaptive in (False, True):
+        for dt in (np.float64, np.float32):
+            f, p = _c1_small(adaptive, dt)
+            enc = dls.encode(f, p)
+            buf = container.pack(enc)
+            dec = container.unpack(buf)
+            assert len(dec.blocks) == len(enc.blocks)
+            for a, b in zip(enc.codes, dec.codes):
+                assert a.r == b.r
+                assert np.array_equal(a.qV, b.qV) and np.array_equal(a.qA, b.qA)
+                assert np.array_equal(a.codes, b.codes)
+                assert np.array_equal(a.esc_values, b.esc_values)
+            out = dls.reconstruct(dec)
+            assert np.array_equal(out, dls.reconstruct(enc))
+            assert np.abs(out.astype(np.float64) - f.astype(np.float64)).max() <= p.eps[0]
+
+
+ALL_PINS = [
+    pin_eigenvalues_vs_svd, pin_eigenvectors_orthonormal_and_residual,
+    pin_eigenvalues_vs_jacobi, pin_rank_bruteforce, pin_exact_rank_data,
+    pin_pointwise_bound, pin_escapes_rare_on_smooth_data, pin_lattice_one_rounding,
+    pin_hand_worked_rank_one, pin_special_blocks, pin_gradient_and_percentile,
+    pin_adaptive_plan, pin_container_round_trip,
+]

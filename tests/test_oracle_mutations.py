@@ -1,0 +1,59 @@
+"""Plant plausible mistakes in the oracle and check that a pin catches each.
+
+Each mutation rewrites one line of one oracle function (a dropped term, a
+wrong sign or index, a transposed operand, a wrong constant), re-executes the
+function in the oracle's namespace, runs every pin, and requires at least one
+pin to fail.  The oracle is restored afterwards.
+"""
+import inspect
+import os
+import sys
+import textwrap
+
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+import oracle_pins as P  # noqa: E402
+from oracle import dls  # noqa: E402
+
+MUTATIONS = [
+    ("tail_energies", "t[r] = t[r + 1] + lam[r]", "t[r] = t[r + 1] + lam[min(r + 1, lam.size - 1)]"),
+    ("choose_rank", "if tail[r] <= tau:", "if tail[r - 1] <= tau:"),
+    ("encode_block", "A = x.T @ Vr", "A = x.T @ V[:, 1:r + 1] if V.shape[1] > r else x.T @ Vr"),
+    ("encode_block", "q = np.rint((x - xhat) * (1.0 / (2.0 * eps)))", "q = np.rint((x - xhat) * (1.0 / eps))"),
+    ("encode_block", "xhat = S.astype(np.float64) * c", "xhat = -S.astype(np.float64) * c"),
+    ("encode_block", "qV = np.rint(Vr * float(1 << BASIS_BITS)).astype(np.int64)",
+     "qV = np.rint(Vr * float(1 << (BASIS_BITS - 1))).astype(np.int64)"),
+    ("encode_block", "tau = KAPPA * eps * eps * m * wb", "tau = KAPPA * eps * m * wb"),
+    ("encode_block", "G = x @ x.T", "G = x @ x.T - np.diag(np.diag(x @ x.T)) * 0.5"),
+    ("eig_desc", "order = np.argsort(-lam, kind=\"stable\")", "order = np.argsort(lam, kind=\"stable\")"),
+    ("canonical_signs", "if V[i, k] < 0:", "if V[i, k] > 0:"),
+    ("gradient_magnitude", "d[s(1, n - 1)] = (f[s(2, n)] - f[s(0, n - 2)]) * 0.5",
+     "d[s(1, n - 1)] = (f[s(2, n)] - f[s(0, n - 2)])"),
+    ("percentile80", "int(math.floor(0.8 * (v.size - 1)))", "int(math.ceil(0.8 * (v.size - 1)))"),
+    ("lattice_values", "n = S + q * (1 << RES_SHIFT)", "n = S + q * (1 << (RES_SHIFT - 1))"),
+    ("zigzag16", "-2 * q - 1", "-2 * q + 1"),
+]
+
+
+def _mutate(name, old, new):
+    fn = getattr(dls, name)
+    src = textwrap.dedent(inspect.getsource(fn))
+    assert old in src, (name, old)
+    ns = dict(vars(dls))
+    exec(compile(src.replace(old, new), "<mutant>", "exec"), ns)
+    return fn, ns[name]
+
+
+@pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] + ":" + m[2][:30] for m in MUTATIONS])
+def test_mutation_is_caught(name, old, new, monkeypatch):
+    orig, mutant = _mutate(name, old, new)
+    monkeypatch.setattr(dls, name, mutant)
+    # functions that call the mutated one resolve it through the module globals
+    caught = []
+    for pin in P.ALL_PINS:
+        try:
+            pin()
+        except Exception:  # AssertionError or a crash both count as caught
+            caught.append(pin.__name__)
+    assert caught, "no pin caught mutation %s: %s -> %s" % (name, old, new)

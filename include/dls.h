@@ -1,0 +1,176 @@
+/*
+ * dls.h -- C ABI of libdls, the MI355X (gfx950) encoder/decoder of
+ * Discontinuous DLS (data-informed local subspaces), an error-bounded lossy
+ * compressor for structured-grid fields.
+ *
+ * The problem statement follows Alg. 1 of the paper (inputs: snapshots, patch
+ * size, target error; outputs: coefficients and the orthonormal basis) and
+ * Alg. 2 (the inverse), extended with a time window and an absolute
+ * pointwise error bound per variable:
+ *
+ *   for every spatial patch x time window (a "block") the library gathers the
+ *   snapshot matrix X (W_b x M_b), forms its Gram product X X^T (the
+ *   cross-product SVD of Sec. 2.7.1), eigensolves it for a local basis
+ *   (Sec. 2.3, Eqs. (2)-(3)), truncates it to the smallest rank r whose
+ *   discarded energy meets the local tolerance (Sec. 2.4 Eq. (4), Sec. 2.5
+ *   Eq. (6)), projects (Eq. (5)), quantizes basis and coefficients (the
+ *   bit-grooming step of Sec. 2.5), reconstructs on an integer lattice and
+ *   quantizes the pointwise residual so that every returned value lies
+ *   within abs_eps[v] of the input.  Batches of 1000 blocks are deflated on
+ *   host threads (gzip's algorithm, Sec. 2.5) behind an addressable header
+ *   (Sec. 2.7.2).
+ *
+ * Conventions shared by every entry point:
+ *   - Every call returns a dls_status; 0 is success.  No C++ exception
+ *     crosses the ABI.  On failure dls_last_error() describes the cause.
+ *   - Field layout: F[var][t][z][y][x], x fastest, contiguous, on the device;
+ *     element type float (DLS_F32) or double (DLS_F64).  2D fields use nz = 1
+ *     and pz = 1.
+ *   - A `stream` argument is a hipStream_t (NULL = the default stream),
+ *     owned by the caller.  Calls are synchronous: they return after their
+ *     device work on that stream has completed.
+ *   - Device pointers are owned by the caller unless stated otherwise.
+ *   - Not thread-safe on the same dls_ctx; distinct contexts may be used
+ *     concurrently from different host threads.
+ */
+#ifndef DLS_H
+#define DLS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DLS_OK = 0,
+  DLS_EINVAL = -1,       /* invalid argument; nothing was written           */
+  DLS_ENOMEM = -2,       /* host or device allocation failed                */
+  DLS_EDEVICE = -3,      /* a HIP call or kernel launch failed              */
+  DLS_ECORRUPT = -4,     /* stream truncated or inconsistent                */
+  DLS_EUNSUPPORTED = -5  /* valid request this build does not implement     */
+} dls_status;
+
+typedef enum { DLS_F32 = 0, DLS_F64 = 1 } dls_dtype;
+
+/* Input precision of the Gram and projection contractions (both accumulate
+ * in FP32 on the matrix cores; the eigensolve, the lattice reconstruction
+ * and the bound check are FP64 in every mode). */
+typedef enum { DLS_PREC_FP32 = 0, DLS_PREC_BF16 = 1 } dls_precision;
+
+/* dls_params.flags */
+enum {
+  DLS_ADAPTIVE = 1   /* quadtree (2D) / octree (3D) patches between pmin and
+                        px, split where the mean gradient magnitude of
+                        snapshot 0 exceeds its 80th percentile             */
+};
+
+typedef struct dls_params {
+  uint32_t struct_size;    /* = sizeof(dls_params); ABI versioning          */
+  int32_t nvars;           /* variables, >= 1                               */
+  int64_t nx, ny, nz, nt;  /* grid (x fastest) and time steps, all >= 1     */
+  int32_t dtype;           /* dls_dtype                                     */
+  int32_t px, py, pz;      /* patch edge (uniform) or largest leaf edge
+                              (DLS_ADAPTIVE: px = py = pz (2D: pz = 1),
+                              power of two); 1..32, pz = 1 when nz = 1      */
+  int32_t pmin;            /* smallest leaf edge (DLS_ADAPTIVE), power of 2 */
+  int32_t window;          /* W: time steps per window, 1..32; the last
+                              window is truncated                           */
+  int32_t r_max;           /* rank cap, 0 -> min(window, 32)                */
+  int32_t precision;       /* dls_precision                                 */
+  uint32_t flags;          /* DLS_ADAPTIVE                                  */
+  const double* abs_eps;   /* host array of nvars absolute bounds, each
+                              finite and > 0; read during the call only    */
+} dls_params;
+
+/* Per-call results of dls_encode, in device memory owned by the context
+ * (valid until the next dls_encode on it or dls_ctx_destroy).  Offsets are
+ * in bytes into the named buffers.  Diagnostics for tests and benchmarks. */
+typedef struct dls_encode_info {
+  int64_t nblocks;          /* blocks: variable, then window, then patch    */
+  int64_t nescapes;         /* escaped points (stored verbatim)             */
+  int64_t nraw;             /* raw blocks (non-finite input)                */
+  int64_t wpad;             /* 16 or 32: padded Gram order                  */
+  const uint8_t* d_rank;    /* [nblocks] rank r (0 = raw block)             */
+  const double* d_lam;      /* [nblocks][wpad] eigenvalues of X X^T, desc   */
+  const double* d_basis;    /* [nblocks][wpad][wpad] eigenvectors, column k
+                               at [k][t], canonical signs                   */
+  const int32_t* d_desc;    /* [nblocks][8] x0, y0, z0, t0, extents (px | py<<8 |
+                               pz<<16 | w<<24), var, M_b, vector flag      */
+  int64_t qa_bytes, codes_bytes;
+  const uint8_t* d_qa;      /* qA planes, per block at d_qa_off[b]          */
+  const uint8_t* d_codes;   /* residual code planes, per block at d_code_off */
+  const int64_t* d_qa_off;  /* [nblocks]                                    */
+  const int64_t* d_code_off;/* [nblocks]                                    */
+  const float* d_coef;      /* [sum M_b r_b] FP32 coefficients A[k][p] at
+                               d_qa_off[b]/4 when requested, else NULL      */
+  double gpu_ms;            /* device time of the whole encode (HIP events) */
+  double stage_ms[4];       /* HIP-event time of each stage on the caller's
+                               stream: Gram, eigensolve + rank, offset scan,
+                               projection / quantization / residual codes   */
+} dls_encode_info;
+
+typedef struct dls_ctx dls_ctx;
+
+/* Create / destroy an encoder context holding device workspace, reused
+ * across calls with the same parameters.  `device` is the HIP device
+ * ordinal the context's memory lives on. */
+dls_status dls_ctx_create(int device, dls_ctx** out);
+void dls_ctx_destroy(dls_ctx* ctx);
+
+/* Device half of compression (Alg. 1 step 3 for every block): plan, Gram,
+ * eigensolve, rank, projection, quantization, lattice reconstruction,
+ * residual codes and escapes, leaving the packed payload in the context's
+ * device buffers.  d_field: device pointer to the field (layout above).
+ * keep_coef != 0 also stores the FP32 coefficients A for diagnostics.
+ * Errors: DLS_EINVAL (params), DLS_ENOMEM, DLS_EDEVICE. */
+dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* p,
+                      void* stream, int keep_coef);
+
+/* Diagnostics of the last dls_encode on ctx (pointers into ctx memory). */
+dls_status dls_encode_info_get(const dls_ctx* ctx, dls_encode_info* info);
+
+/* Host half of compression: copy the payload of the last dls_encode to host,
+ * deflate each batch of 1000 blocks on host threads and write the stream
+ * (header, per-batch offset table, zlib streams; Sec. 2.7.2).  *out is a
+ * library-owned host buffer; release it with dls_free. */
+dls_status dls_finalize(dls_ctx* ctx, uint8_t** out, size_t* out_bytes);
+
+/* dls_encode + dls_finalize with a temporary context. */
+dls_status dls_compress(const void* d_field, const dls_params* p, void* stream,
+                        uint8_t** out, size_t* out_bytes);
+
+/* Read the header of a stream (host buffer in[0..in_bytes)).  Writes the
+ * problem statement to *p_out (abs_eps is set to NULL), the bounds to
+ * eps_out[0..min(nvars, eps_cap)) when eps_out is not NULL, and the block
+ * count to *nblocks when not NULL.  DLS_ECORRUPT on a bad header. */
+dls_status dls_query(const uint8_t* in, size_t in_bytes, dls_params* p_out,
+                     double* eps_out, int32_t eps_cap, int64_t* nblocks);
+
+/* Alg. 2: inflate every batch, rebuild the lattice values of every block,
+ * apply the escapes and assemble the field (Eq. (7)) into d_field_out, a
+ * caller-allocated device buffer of nvars*nt*nz*ny*nx elements of the
+ * stream's dtype.  DLS_ECORRUPT on a truncated or inconsistent stream. */
+dls_status dls_decompress(const uint8_t* in, size_t in_bytes, void* d_field_out,
+                          void* stream);
+
+/* Summary of a stream, computed on the host (no device work). */
+typedef struct dls_stream_stats {
+  int64_t nblocks, nbatches, nraw, nescapes;
+  int64_t rank_hist[33];     /* rank_hist[r] = blocks with rank r           */
+  int64_t payload_bytes;     /* uncompressed payload                        */
+  int64_t stream_bytes;      /* whole stream                                */
+} dls_stream_stats;
+dls_status dls_stats(const uint8_t* in, size_t in_bytes, dls_stream_stats* s);
+
+/* Release a buffer returned by dls_finalize / dls_compress. */
+void dls_free(void* p);
+
+/* Thread-local description of the last error; valid until the next call. */
+const char* dls_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DLS_H */

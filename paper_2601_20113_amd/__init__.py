@@ -1,0 +1,264 @@
+"""Python binding of libdls (the MI355X DLS encoder / decoder).
+
+Argument marshalling only: every step of compression and decompression runs
+in the library's HIP kernels and host code.  PyTorch supplies device memory
+and streams.  Importing torch first makes the library share torch's HIP
+runtime.
+
+    import paper_2601_20113_amd as dls
+    p = dls.Params(nx=64, ny=64, nz=1, nt=32, nvars=1, dtype="f64",
+                   px=8, py=8, pz=1, window=16, eps=[1e-3])
+    buf = dls.compress(field_cuda_tensor, p)       # bytes
+    out = dls.decompress(buf)                      # cuda tensor
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field as dc_field
+from typing import Optional, Sequence
+
+import torch  # noqa: F401  (load torch's HIP runtime before libdls)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdls.so")
+
+DLS_OK, DLS_EINVAL, DLS_ENOMEM, DLS_EDEVICE, DLS_ECORRUPT, DLS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+DLS_F32, DLS_F64 = 0, 1
+DLS_PREC_FP32, DLS_PREC_BF16 = 0, 1
+DLS_ADAPTIVE = 1
+
+EXPORTS = ["dls_ctx_create", "dls_ctx_destroy", "dls_encode", "dls_encode_info_get",
+           "dls_finalize", "dls_compress", "dls_query", "dls_decompress", "dls_stats",
+           "dls_free", "dls_last_error"]
+
+
+class DlsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("dls status %d: %s" % (status, msg))
+        self.status = status
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("nvars", ctypes.c_int32),
+                ("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64),
+                ("nt", ctypes.c_int64), ("dtype", ctypes.c_int32),
+                ("px", ctypes.c_int32), ("py", ctypes.c_int32), ("pz", ctypes.c_int32),
+                ("pmin", ctypes.c_int32), ("window", ctypes.c_int32), ("r_max", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("abs_eps", ctypes.POINTER(ctypes.c_double))]
+
+
+class _EncodeInfo(ctypes.Structure):
+    _fields_ = [("nblocks", ctypes.c_int64), ("nescapes", ctypes.c_int64), ("nraw", ctypes.c_int64),
+                ("wpad", ctypes.c_int64), ("d_rank", ctypes.c_void_p), ("d_lam", ctypes.c_void_p),
+                ("d_basis", ctypes.c_void_p), ("d_desc", ctypes.c_void_p),
+                ("qa_bytes", ctypes.c_int64), ("codes_bytes", ctypes.c_int64),
+                ("d_qa", ctypes.c_void_p), ("d_codes", ctypes.c_void_p),
+                ("d_qa_off", ctypes.c_void_p), ("d_code_off", ctypes.c_void_p),
+                ("d_coef", ctypes.c_void_p), ("gpu_ms", ctypes.c_double),
+                ("stage_ms", ctypes.c_double * 4)]
+
+
+class _StreamStats(ctypes.Structure):
+    _fields_ = [("nblocks", ctypes.c_int64), ("nbatches", ctypes.c_int64), ("nraw", ctypes.c_int64),
+                ("nescapes", ctypes.c_int64), ("rank_hist", ctypes.c_int64 * 33),
+                ("payload_bytes", ctypes.c_int64), ("stream_bytes", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libdls; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libdls.so is not built (run __graft_entry__.build() or "
+                              "python -m paper_2601_20113_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        c_void_pp = ctypes.POINTER(ctypes.c_void_p)
+        L.dls_ctx_create.argtypes = [ctypes.c_int, c_void_pp]
+        L.dls_ctx_destroy.argtypes = [ctypes.c_void_p]
+        L.dls_ctx_destroy.restype = None
+        L.dls_encode.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Params),
+                                 ctypes.c_void_p, ctypes.c_int]
+        L.dls_encode_info_get.argtypes = [ctypes.c_void_p, ctypes.POINTER(_EncodeInfo)]
+        L.dls_finalize.argtypes = [ctypes.c_void_p, c_void_pp, ctypes.POINTER(ctypes.c_size_t)]
+        L.dls_compress.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Params), ctypes.c_void_p,
+                                   c_void_pp, ctypes.POINTER(ctypes.c_size_t)]
+        L.dls_query.argtypes = [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(_Params),
+                                ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                ctypes.POINTER(ctypes.c_int64)]
+        L.dls_decompress.argtypes = [ctypes.c_char_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]
+        L.dls_stats.argtypes = [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(_StreamStats)]
+        L.dls_free.argtypes = [ctypes.c_void_p]
+        L.dls_free.restype = None
+        L.dls_last_error.restype = ctypes.c_char_p
+        for name in ("dls_ctx_create", "dls_encode", "dls_encode_info_get", "dls_finalize",
+                     "dls_compress", "dls_query", "dls_decompress", "dls_stats"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != DLS_OK:
+        raise DlsError(status, lib().dls_last_error().decode(errors="replace"))
+
+
+@dataclass
+class Params:
+    """Problem statement: grid, patch and window sizes, absolute bounds."""
+    nx: int
+    ny: int
+    nz: int
+    nt: int
+    nvars: int
+    dtype: str            # "f32" | "f64"
+    px: int
+    py: int
+    pz: int
+    window: int
+    eps: Sequence[float]
+    pmin: int = 0
+    r_max: int = 0
+    precision: str = "fp32"   # "fp32" | "bf16"
+    adaptive: bool = False
+    _keep: list = dc_field(default_factory=list, repr=False)
+
+    def to_c(self) -> _Params:
+        arr = (ctypes.c_double * len(self.eps))(*[float(e) for e in self.eps])
+        self._keep = [arr]
+        return _Params(ctypes.sizeof(_Params), self.nvars, self.nx, self.ny, self.nz, self.nt,
+                       DLS_F32 if self.dtype == "f32" else DLS_F64, self.px, self.py, self.pz,
+                       self.pmin, self.window, self.r_max,
+                       DLS_PREC_BF16 if self.precision == "bf16" else DLS_PREC_FP32,
+                       DLS_ADAPTIVE if self.adaptive else 0,
+                       ctypes.cast(arr, ctypes.POINTER(ctypes.c_double)))
+
+    @property
+    def torch_dtype(self):
+        return torch.float32 if self.dtype == "f32" else torch.float64
+
+    @property
+    def shape(self):
+        return (self.nvars, self.nt, self.nz, self.ny, self.nx)
+
+
+def _stream_handle(stream) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_field(t: torch.Tensor, p: Params):
+    if not t.is_cuda:
+        raise ValueError("field must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("field must be contiguous")
+    if t.dtype != p.torch_dtype or tuple(t.shape) != p.shape:
+        raise ValueError("field dtype/shape %s %s does not match params %s %s"
+                         % (t.dtype, tuple(t.shape), p.torch_dtype, p.shape))
+
+
+class Encoder:
+    """A reusable encoder context (device workspace lives here)."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().dls_ctx_create(device, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if self._h:
+            lib().dls_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def encode(self, field: torch.Tensor, p: Params, stream=None, keep_coef: bool = False):
+        _check_field(field, p)
+        cp = p.to_c()
+        _check(lib().dls_encode(self._h, ctypes.c_void_p(field.data_ptr()), ctypes.byref(cp),
+                                _stream_handle(stream), 1 if keep_coef else 0))
+
+    def info(self) -> _EncodeInfo:
+        inf = _EncodeInfo()
+        _check(lib().dls_encode_info_get(self._h, ctypes.byref(inf)))
+        return inf
+
+    def finalize(self) -> bytes:
+        out = ctypes.c_void_p()
+        n = ctypes.c_size_t()
+        _check(lib().dls_finalize(self._h, ctypes.byref(out), ctypes.byref(n)))
+        try:
+            return ctypes.string_at(out.value, n.value)
+        finally:
+            lib().dls_free(out)
+
+
+def compress(field: torch.Tensor, p: Params, stream=None) -> bytes:
+    _check_field(field, p)
+    cp = p.to_c()
+    out = ctypes.c_void_p()
+    n = ctypes.c_size_t()
+    _check(lib().dls_compress(ctypes.c_void_p(field.data_ptr()), ctypes.byref(cp),
+                              _stream_handle(stream), ctypes.byref(out), ctypes.byref(n)))
+    try:
+        return ctypes.string_at(out.value, n.value)
+    finally:
+        lib().dls_free(out)
+
+
+def query(buf: bytes):
+    """(Params, nblocks) from a stream header."""
+    cp = _Params()
+    eps = (ctypes.c_double * 65536)()
+    nb = ctypes.c_int64()
+    _check(lib().dls_query(buf, len(buf), ctypes.byref(cp), eps, 65536, ctypes.byref(nb)))
+    p = Params(nx=cp.nx, ny=cp.ny, nz=cp.nz, nt=cp.nt, nvars=cp.nvars,
+               dtype="f32" if cp.dtype == DLS_F32 else "f64", px=cp.px, py=cp.py, pz=cp.pz,
+               window=cp.window, eps=[eps[i] for i in range(cp.nvars)], pmin=cp.pmin,
+               r_max=cp.r_max, adaptive=bool(cp.flags & DLS_ADAPTIVE))
+    return p, nb.value
+
+
+def stats(buf: bytes) -> dict:
+    s = _StreamStats()
+    _check(lib().dls_stats(buf, len(buf), ctypes.byref(s)))
+    return {"nblocks": s.nblocks, "nbatches": s.nbatches, "nraw": s.nraw, "nescapes": s.nescapes,
+            "rank_hist": list(s.rank_hist), "payload_bytes": s.payload_bytes,
+            "stream_bytes": s.stream_bytes}
+
+
+def decompress(buf: bytes, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    p, _ = query(buf)
+    if out is None:
+        out = torch.empty(p.shape, dtype=p.torch_dtype, device="cuda")
+    _check_field(out, p)
+    _check(lib().dls_decompress(buf, len(buf), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return out
+
+
+_hiplib = None
+
+
+def d2h(ptr: int, nbytes: int):
+    """Copy device memory (a pointer from Encoder.info()) to a host uint8 numpy array."""
+    import numpy as np
+    global _hiplib
+    if _hiplib is None:
+        # the runtime torch already loaded, so both sides share one HIP instance
+        _hiplib = ctypes.CDLL(os.path.join(os.path.dirname(torch.__file__), "lib", "libamdhip64.so"))
+        _hiplib.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        _hiplib.hipMemcpy.restype = ctypes.c_int
+    out = np.empty(max(int(nbytes), 1), dtype=np.uint8)
+    if nbytes:
+        st = _hiplib.hipMemcpy(out.ctypes.data, ctypes.c_void_p(ptr), int(nbytes), 2)
+        if st != 0:
+            raise RuntimeError("hipMemcpy failed: %d" % st)
+    return out[:int(nbytes)]

@@ -1,0 +1,732 @@
+// libdls: the C ABI declared in include/dls.h.
+//
+// Compression is split in a device half (dls_encode: plan upload, Gram,
+// eigensolve + rank, offset scan, projection / quantization / residual codes)
+// and a host half (dls_finalize: copy the packed payload to host, sort the
+// escapes, deflate each batch of 1000 blocks on host threads, write the
+// header and batch table, Sec. 2.7.2).  Decompression (Alg. 2) inflates on
+// host threads and rebuilds the field on the device.
+#include <hip/hip_runtime.h>
+#include <zlib.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/dls.h"
+#include "dls_internal.h"
+#include "dls_kernels.h"
+
+using namespace dls;
+
+namespace {
+
+thread_local std::string g_err;
+
+dls_status fail(dls_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(e_ == hipErrorOutOfMemory ? DLS_ENOMEM : DLS_EDEVICE,            \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));              \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  hipError_t ensure(size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (bytes <= n) return hipSuccess;
+    release();
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e == hipSuccess) n = bytes;
+    else p = nullptr;
+    return e;
+  }
+  template <typename T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+int worker_count() {
+  unsigned n = std::thread::hardware_concurrency();
+  if (const char* s = std::getenv("DLS_HOST_THREADS")) n = unsigned(std::max(1, atoi(s)));
+  return int(std::max(1u, std::min(n, 64u)));
+}
+
+template <typename F>
+void parallel_for(int64_t n, F&& fn) {
+  const int nw = int(std::min<int64_t>(worker_count(), std::max<int64_t>(n, 1)));
+  std::atomic<int64_t> next{0};
+  auto body = [&]() {
+    for (int64_t i = next++; i < n; i = next++) fn(i);
+  };
+  std::vector<std::thread> th;
+  for (int w = 1; w < nw; ++w) th.emplace_back(body);
+  body();
+  for (auto& t : th) t.join();
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+dls_status validate(const dls_params* in, Problem& p) {
+  if (in == nullptr) return fail(DLS_EINVAL, "params is NULL");
+  if (in->struct_size != sizeof(dls_params)) return fail(DLS_EINVAL, "params.struct_size mismatch");
+  p.nvars = in->nvars;
+  p.nx = in->nx; p.ny = in->ny; p.nz = in->nz; p.nt = in->nt;
+  p.dtype = in->dtype;
+  p.px = in->px; p.py = in->py; p.pz = in->pz; p.pmin = in->pmin;
+  p.window = in->window;
+  p.precision = in->precision;
+  p.flags = in->flags;
+  if (p.nvars < 1 || p.nvars > 65536) return fail(DLS_EINVAL, "nvars out of range");
+  const int64_t lim = int64_t(1) << 31;
+  if (p.nx < 1 || p.ny < 1 || p.nz < 1 || p.nt < 1 || p.nx >= lim || p.ny >= lim || p.nz >= lim || p.nt >= lim)
+    return fail(DLS_EINVAL, "grid sizes must be in [1, 2^31)");
+  if (p.dtype != DLS_F32 && p.dtype != DLS_F64) return fail(DLS_EINVAL, "dtype must be DLS_F32 or DLS_F64");
+  if (p.window < 1 || p.window > 32) return fail(DLS_EINVAL, "window must be in [1, 32]");
+  if (p.px < 1 || p.px > 32 || p.py < 1 || p.py > 32 || p.pz < 1 || p.pz > 32)
+    return fail(DLS_EINVAL, "patch edges must be in [1, 32]");
+  if (p.nz == 1 && p.pz != 1) return fail(DLS_EINVAL, "pz must be 1 for a 2D field");
+  if (in->r_max < 0 || in->r_max > 32) return fail(DLS_EINVAL, "r_max must be in [0, 32]");
+  p.r_max = in->r_max > 0 ? in->r_max : std::min(p.window, 32);
+  if (p.flags & ~uint32_t(DLS_ADAPTIVE)) return fail(DLS_EINVAL, "unknown flags");
+  if (p.precision != DLS_PREC_FP32 && p.precision != DLS_PREC_BF16)
+    return fail(DLS_EINVAL, "unknown precision");
+  if (p.flags & DLS_ADAPTIVE) {
+    if (!is_pow2(p.px) || p.py != p.px || p.pz != (p.nz > 1 ? p.px : 1))
+      return fail(DLS_EINVAL, "adaptive plan needs px = py (= pz in 3D), a power of two");
+    if (!is_pow2(p.pmin) || p.pmin > p.px) return fail(DLS_EINVAL, "pmin must be a power of two <= px");
+  }
+  if (in->abs_eps == nullptr) return fail(DLS_EINVAL, "abs_eps is NULL");
+  p.eps.assign(in->abs_eps, in->abs_eps + p.nvars);
+  for (double e : p.eps)
+    if (!(e > 0.0) || !std::isfinite(e)) return fail(DLS_EINVAL, "abs_eps must be finite and > 0");
+  return DLS_OK;
+}
+
+VarConst var_const(double eps) {
+  VarConst k;
+  k.eps = eps;
+  k.c = std::ldexp(eps, -kBasisBits);
+  k.inv_eps = 1.0 / eps;
+  k.inv2eps = 1.0 / (2.0 * eps);
+  k.inv_eps_f = float(k.inv_eps);
+  k.pad = 0.f;
+  return k;
+}
+
+int slice_points(const Problem& p) {
+  return (p.dtype == DLS_F32 && p.wpad() == 16) ? 1024 : 512;
+}
+
+bool same_layout(const Problem& a, const Problem& b) {
+  return a.nvars == b.nvars && a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.nt == b.nt &&
+         a.dtype == b.dtype && a.px == b.px && a.py == b.py && a.pz == b.pz &&
+         a.window == b.window && a.flags == b.flags && a.pmin == b.pmin;
+}
+
+}  // namespace
+
+struct dls_ctx {
+  int device = 0;
+  Problem prob;
+  bool plan_valid = false;
+  Plan plan;
+  DevBuf desc, items, item_start, code_off, gram, rank, lam, basis;
+  DevBuf qv_size, qa_size, qv_off, qa_off, scan_tmp, qv, qa, codes, coef;
+  DevBuf esc_key, esc_val, counters, vconst, eps_v;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t evs[4] = {nullptr, nullptr, nullptr, nullptr};  // gram, eigen, scan ends; encode start
+  double stage_ms[4] = {0, 0, 0, 0};
+  uint64_t esc_cap = 0;
+  // results of the last dls_encode
+  bool have_result = false;
+  bool keep_coef = false;
+  int64_t nesc = 0, nraw = 0, qv_bytes = 0, qa_bytes = 0;
+  double gpu_ms = 0.0;
+  ~dls_ctx() {
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    for (auto& e : evs)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+extern "C" {
+
+const char* dls_last_error(void) { return g_err.c_str(); }
+
+void dls_free(void* p) { std::free(p); }
+
+dls_status dls_ctx_create(int device, dls_ctx** out) {
+  if (out == nullptr) return fail(DLS_EINVAL, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  HIP_TRY(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(DLS_EINVAL, "no such device");
+  std::unique_ptr<dls_ctx> c(new (std::nothrow) dls_ctx());
+  if (!c) return fail(DLS_ENOMEM, "context allocation");
+  c->device = device;
+  HIP_TRY(hipSetDevice(device));
+  HIP_TRY(hipEventCreate(&c->ev0));
+  HIP_TRY(hipEventCreate(&c->ev1));
+  for (auto& e : c->evs) HIP_TRY(hipEventCreate(&e));
+  *out = c.release();
+  return DLS_OK;
+}
+
+void dls_ctx_destroy(dls_ctx* ctx) {
+  if (ctx == nullptr) return;
+  (void)hipSetDevice(ctx->device);
+  delete ctx;
+}
+
+dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* params, void* stream,
+                      int keep_coef) {
+  if (ctx == nullptr) return fail(DLS_EINVAL, "ctx is NULL");
+  if (d_field == nullptr) return fail(DLS_EINVAL, "field is NULL");
+  Problem p;
+  if (dls_status s = validate(params, p)) return s;
+  if (p.precision != DLS_PREC_FP32) return fail(DLS_EUNSUPPORTED, "BF16 contractions are not built yet");
+  if (p.flags & DLS_ADAPTIVE) return fail(DLS_EUNSUPPORTED, "adaptive plan is not built yet");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipSetDevice(ctx->device));
+  ctx->have_result = false;
+
+  // plan: uniform tiling depends on the problem statement only, so it is cached
+  if (!ctx->plan_valid || !same_layout(ctx->prob, p)) {
+    ctx->plan_valid = false;
+    ctx->plan = Plan();
+    ctx->plan.leaves.assign(p.nvars, uniform_leaves(p));
+    ctx->plan.bits.assign(p.nvars, {});
+    build_blocks(p, ctx->plan, slice_points(p));
+    if (ctx->plan.blocks.size() >= (size_t(1) << 31)) return fail(DLS_EINVAL, "too many blocks");
+    const Plan& pl = ctx->plan;
+    HIP_TRY(ctx->desc.ensure(pl.blocks.size() * sizeof(BlockDesc)));
+    HIP_TRY(ctx->items.ensure(pl.items.size() * sizeof(Item)));
+    HIP_TRY(ctx->item_start.ensure(pl.item_start.size() * sizeof(int32_t)));
+    HIP_TRY(ctx->code_off.ensure(pl.code_off.size() * sizeof(int64_t)));
+    HIP_TRY(hipMemcpy(ctx->desc.p, pl.blocks.data(), pl.blocks.size() * sizeof(BlockDesc), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(ctx->items.p, pl.items.data(), pl.items.size() * sizeof(Item), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(ctx->item_start.p, pl.item_start.data(), pl.item_start.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(ctx->code_off.p, pl.code_off.data(), pl.code_off.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    ctx->plan_valid = true;
+  }
+  ctx->prob = p;
+  const Plan& pl = ctx->plan;
+  const int64_t nb = int64_t(pl.blocks.size());
+  const int64_t ni = int64_t(pl.items.size());
+  const int wp = p.wpad();
+
+  HIP_TRY(ctx->gram.ensure(size_t(ni) * wp * wp * sizeof(double)));
+  HIP_TRY(ctx->rank.ensure(size_t(nb)));
+  HIP_TRY(ctx->lam.ensure(size_t(nb) * wp * sizeof(double)));
+  HIP_TRY(ctx->basis.ensure(size_t(nb) * wp * wp * sizeof(double)));
+  HIP_TRY(ctx->qv_size.ensure(size_t(nb) * sizeof(int64_t)));
+  HIP_TRY(ctx->qa_size.ensure(size_t(nb) * sizeof(int64_t)));
+  HIP_TRY(ctx->qv_off.ensure(size_t(nb) * sizeof(int64_t)));
+  HIP_TRY(ctx->qa_off.ensure(size_t(nb) * sizeof(int64_t)));
+  HIP_TRY(ctx->scan_tmp.ensure(size_t(4 * (nb / 1024 + 4)) * sizeof(int64_t)));
+  HIP_TRY(ctx->codes.ensure(size_t(pl.codes_bytes)));
+  HIP_TRY(ctx->counters.ensure(2 * sizeof(unsigned long long)));
+  if (ctx->esc_cap == 0) {
+    ctx->esc_cap = std::max<uint64_t>(uint64_t(1) << 20, uint64_t(p.values() / 256));
+    HIP_TRY(ctx->esc_key.ensure(ctx->esc_cap * 8));
+    HIP_TRY(ctx->esc_val.ensure(ctx->esc_cap * 8));
+  }
+  std::vector<VarConst> vc(p.nvars);
+  for (int v = 0; v < p.nvars; ++v) vc[v] = var_const(p.eps[v]);
+  HIP_TRY(ctx->vconst.ensure(vc.size() * sizeof(VarConst)));
+  HIP_TRY(ctx->eps_v.ensure(p.eps.size() * sizeof(double)));
+  HIP_TRY(hipMemcpyAsync(ctx->vconst.p, vc.data(), vc.size() * sizeof(VarConst), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(ctx->eps_v.p, p.eps.data(), p.eps.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(ctx->counters.p, 0, 2 * sizeof(unsigned long long), s));
+
+  const Dims dims{p.nx, p.ny, p.nz, p.nt};
+  unsigned long long* cnt = ctx->counters.as<unsigned long long>();
+  HIP_TRY(hipEventRecord(ctx->ev0, s));
+  HIP_TRY(launch_gram(wp, p.dtype, d_field, dims, ctx->desc.as<BlockDesc>(), ctx->items.as<Item>(), ni,
+                      ctx->gram.as<double>(), s));
+  HIP_TRY(hipEventRecord(ctx->evs[0], s));
+  HIP_TRY(launch_eigen(wp, ctx->gram.as<double>(), ctx->item_start.as<int32_t>(), ctx->desc.as<BlockDesc>(),
+                       nb, ctx->eps_v.as<double>(), p.r_max, ctx->rank.as<uint8_t>(), ctx->lam.as<double>(),
+                       ctx->basis.as<double>(), ctx->qv_size.as<int64_t>(), ctx->qa_size.as<int64_t>(),
+                       cnt + 1, s));
+  HIP_TRY(hipEventRecord(ctx->evs[1], s));
+  HIP_TRY(launch_scan(ctx->qv_size.as<int64_t>(), nb, ctx->qv_off.as<int64_t>(), ctx->scan_tmp.as<int64_t>(), s));
+  HIP_TRY(launch_scan(ctx->qa_size.as<int64_t>(), nb, ctx->qa_off.as<int64_t>(), ctx->scan_tmp.as<int64_t>(), s));
+  HIP_TRY(hipEventRecord(ctx->evs[2], s));
+  int64_t tail[4];
+  HIP_TRY(hipMemcpyAsync(&tail[0], ctx->qv_off.as<int64_t>() + nb - 1, 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&tail[1], ctx->qv_size.as<int64_t>() + nb - 1, 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&tail[2], ctx->qa_off.as<int64_t>() + nb - 1, 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&tail[3], ctx->qa_size.as<int64_t>() + nb - 1, 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  ctx->qv_bytes = tail[0] + tail[1];
+  ctx->qa_bytes = tail[2] + tail[3];
+  HIP_TRY(ctx->qv.ensure(size_t(ctx->qv_bytes)));
+  HIP_TRY(ctx->qa.ensure(size_t(ctx->qa_bytes)));
+  ctx->keep_coef = keep_coef != 0;
+  if (ctx->keep_coef) HIP_TRY(ctx->coef.ensure(size_t(ctx->qa_bytes)));
+
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    EscOut esc{cnt, ctx->esc_key.as<uint64_t>(), ctx->esc_val.as<uint64_t>(), ctx->esc_cap};
+    HIP_TRY(hipEventRecord(ctx->evs[3], s));
+    HIP_TRY(launch_encode(wp, p.dtype, d_field, dims, ctx->desc.as<BlockDesc>(), ctx->items.as<Item>(), ni,
+                          ctx->rank.as<uint8_t>(), ctx->basis.as<double>(), ctx->qv_off.as<int64_t>(),
+                          ctx->qa_off.as<int64_t>(), ctx->code_off.as<int64_t>(), ctx->vconst.as<VarConst>(),
+                          ctx->qv.as<uint8_t>(), ctx->qa.as<uint8_t>(), ctx->codes.as<uint8_t>(),
+                          ctx->keep_coef ? ctx->coef.as<float>() : nullptr, esc, s));
+    HIP_TRY(hipEventRecord(ctx->ev1, s));
+    unsigned long long hc[2];
+    HIP_TRY(hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    ctx->nesc = int64_t(hc[0]);
+    ctx->nraw = int64_t(hc[1]);
+    if (hc[0] <= ctx->esc_cap) break;
+    // more escapes than room: grow and run the encode kernel again (it rewrites
+    // every output, so the result is identical apart from the escape list)
+    ctx->esc_cap = hc[0] + (hc[0] >> 3) + 1024;
+    HIP_TRY(ctx->esc_key.ensure(ctx->esc_cap * 8));
+    HIP_TRY(ctx->esc_val.ensure(ctx->esc_cap * 8));
+    HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s));
+  }
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  ctx->gpu_ms = ms;
+  const hipEvent_t marks[5][2] = {{ctx->ev0, ctx->evs[0]}, {ctx->evs[0], ctx->evs[1]},
+                                  {ctx->evs[1], ctx->evs[2]}, {ctx->evs[3], ctx->ev1}, {nullptr, nullptr}};
+  for (int i = 0; i < 4; ++i) {
+    HIP_TRY(hipEventElapsedTime(&ms, marks[i][0], marks[i][1]));
+    ctx->stage_ms[i] = ms;
+  }
+  ctx->have_result = true;
+  return DLS_OK;
+}
+
+dls_status dls_encode_info_get(const dls_ctx* ctx, dls_encode_info* info) {
+  if (ctx == nullptr || info == nullptr) return fail(DLS_EINVAL, "NULL argument");
+  if (!ctx->have_result) return fail(DLS_EINVAL, "no encode result in this context");
+  info->nblocks = int64_t(ctx->plan.blocks.size());
+  info->nescapes = ctx->nesc;
+  info->nraw = ctx->nraw;
+  info->wpad = ctx->prob.wpad();
+  info->d_rank = ctx->rank.as<uint8_t>();
+  info->d_lam = ctx->lam.as<double>();
+  info->d_basis = ctx->basis.as<double>();
+  info->d_desc = ctx->desc.as<int32_t>();
+  info->qa_bytes = ctx->qa_bytes;
+  info->codes_bytes = ctx->plan.codes_bytes;
+  info->d_qa = ctx->qa.as<uint8_t>();
+  info->d_codes = ctx->codes.as<uint8_t>();
+  info->d_qa_off = ctx->qa_off.as<int64_t>();
+  info->d_code_off = ctx->code_off.as<int64_t>();
+  info->d_coef = ctx->keep_coef ? ctx->coef.as<float>() : nullptr;
+  info->gpu_ms = ctx->gpu_ms;
+  for (int i = 0; i < 4; ++i) info->stage_ms[i] = ctx->stage_ms[i];
+  return DLS_OK;
+}
+
+dls_status dls_finalize(dls_ctx* ctx, uint8_t** out, size_t* out_bytes) {
+  if (ctx == nullptr || out == nullptr || out_bytes == nullptr) return fail(DLS_EINVAL, "NULL argument");
+  if (!ctx->have_result) return fail(DLS_EINVAL, "no encode result in this context");
+  *out = nullptr;
+  *out_bytes = 0;
+  HIP_TRY(hipSetDevice(ctx->device));
+  const Problem& p = ctx->prob;
+  const Plan& pl = ctx->plan;
+  const int64_t nb = int64_t(pl.blocks.size());
+  std::vector<uint8_t> rank(nb), qv(ctx->qv_bytes), qa(ctx->qa_bytes), codes(pl.codes_bytes);
+  std::vector<int64_t> qv_off(nb), qa_off(nb);
+  std::vector<uint64_t> ekey(ctx->nesc), eval(ctx->nesc);
+  HIP_TRY(hipMemcpy(rank.data(), ctx->rank.p, nb, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(qv_off.data(), ctx->qv_off.p, nb * 8, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(qa_off.data(), ctx->qa_off.p, nb * 8, hipMemcpyDeviceToHost));
+  if (ctx->qv_bytes) HIP_TRY(hipMemcpy(qv.data(), ctx->qv.p, ctx->qv_bytes, hipMemcpyDeviceToHost));
+  if (ctx->qa_bytes) HIP_TRY(hipMemcpy(qa.data(), ctx->qa.p, ctx->qa_bytes, hipMemcpyDeviceToHost));
+  if (pl.codes_bytes) HIP_TRY(hipMemcpy(codes.data(), ctx->codes.p, pl.codes_bytes, hipMemcpyDeviceToHost));
+  if (ctx->nesc) {
+    HIP_TRY(hipMemcpy(ekey.data(), ctx->esc_key.p, ctx->nesc * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(eval.data(), ctx->esc_val.p, ctx->nesc * 8, hipMemcpyDeviceToHost));
+  }
+  // escapes in block, then (t, p) order
+  std::vector<int64_t> order(ctx->nesc);
+  for (int64_t i = 0; i < ctx->nesc; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return ekey[a] < ekey[b]; });
+  std::vector<int64_t> esc_start(nb + 1, 0);
+  for (int64_t i = 0; i < ctx->nesc; ++i) esc_start[(ekey[i] >> 32) + 1]++;
+  for (int64_t b = 0; b < nb; ++b) esc_start[b + 1] += esc_start[b];
+
+  const int64_t nbatch = (nb + kBatchBlocks - 1) / kBatchBlocks;
+  const int es = p.esize();
+  std::vector<std::vector<uint8_t>> zs(nbatch);
+  std::vector<uint64_t> usz(nbatch);
+  std::atomic<bool> zfail{false};
+  parallel_for(nbatch, [&](int64_t bi) {
+    const int64_t b0 = bi * kBatchBlocks, b1 = std::min(nb, b0 + kBatchBlocks);
+    std::vector<uint8_t> raw;
+    size_t need = (b1 - b0) * 5;
+    for (int64_t b = b0; b < b1; ++b) {
+      const BlockDesc& d = pl.blocks[b];
+      need += size_t(4) * rank[b] * (d.w() + d.m) + size_t(2) * d.w() * d.m + size_t(es) * (esc_start[b + 1] - esc_start[b]);
+    }
+    raw.reserve(need);
+    raw.insert(raw.end(), rank.begin() + b0, rank.begin() + b1);
+    for (int64_t b = b0; b < b1; ++b) {
+      uint32_t c = uint32_t(esc_start[b + 1] - esc_start[b]);
+      uint8_t tmp[4];
+      std::memcpy(tmp, &c, 4);
+      raw.insert(raw.end(), tmp, tmp + 4);
+    }
+    for (int64_t b = b0; b < b1; ++b) {
+      const int64_t n = int64_t(pl.blocks[b].w()) * rank[b], pad = pad16(n);
+      for (int j = 0; j < 4; ++j) {
+        const uint8_t* src = qv.data() + qv_off[b] + j * pad;
+        raw.insert(raw.end(), src, src + n);
+      }
+    }
+    for (int64_t b = b0; b < b1; ++b) {
+      const int64_t n = int64_t(pl.blocks[b].m) * rank[b], pad = pad16(n);
+      for (int j = 0; j < 4; ++j) {
+        const uint8_t* src = qa.data() + qa_off[b] + j * pad;
+        raw.insert(raw.end(), src, src + n);
+      }
+    }
+    for (int64_t b = b0; b < b1; ++b) {
+      const int64_t n = int64_t(pl.blocks[b].w()) * pl.blocks[b].m, pad = pad16(n);
+      for (int j = 0; j < 2; ++j) {
+        const uint8_t* src = codes.data() + pl.code_off[b] + j * pad;
+        raw.insert(raw.end(), src, src + n);
+      }
+    }
+    for (int64_t i = esc_start[b0]; i < esc_start[b1]; ++i) {
+      uint8_t tmp[8];
+      std::memcpy(tmp, &eval[order[i]], 8);
+      raw.insert(raw.end(), tmp, tmp + es);
+    }
+    uLongf zn = compressBound(uLong(raw.size()));
+    std::vector<uint8_t> z(zn);
+    if (compress2(z.data(), &zn, raw.data(), uLong(raw.size()), kZlibLevel) != Z_OK) {
+      zfail = true;
+      return;
+    }
+    z.resize(zn);
+    zs[bi] = std::move(z);
+    usz[bi] = raw.size();
+  });
+  if (zfail) return fail(DLS_ENOMEM, "zlib compress2 failed");
+  std::vector<StreamHeader::Batch> table(nbatch);
+  uint64_t off = 0;
+  for (int64_t i = 0; i < nbatch; ++i) {
+    table[i] = StreamHeader::Batch{off, zs[i].size(), usz[i]};
+    off += zs[i].size();
+  }
+  std::vector<uint8_t> hdr = write_header(p, nb, pl.bits, table);
+  const size_t total = hdr.size() + off;
+  uint8_t* buf = static_cast<uint8_t*>(std::malloc(total ? total : 1));
+  if (buf == nullptr) return fail(DLS_ENOMEM, "output allocation");
+  std::memcpy(buf, hdr.data(), hdr.size());
+  size_t pos = hdr.size();
+  for (auto& z : zs) {
+    std::memcpy(buf + pos, z.data(), z.size());
+    pos += z.size();
+  }
+  *out = buf;
+  *out_bytes = total;
+  return DLS_OK;
+}
+
+dls_status dls_compress(const void* d_field, const dls_params* p, void* stream, uint8_t** out,
+                        size_t* out_bytes) {
+  if (out == nullptr || out_bytes == nullptr) return fail(DLS_EINVAL, "NULL output argument");
+  if (d_field == nullptr) return fail(DLS_EINVAL, "field is NULL");
+  Problem chk;
+  if (dls_status s = validate(p, chk)) return s;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  dls_ctx* ctx = nullptr;
+  if (dls_status s = dls_ctx_create(dev, &ctx)) return s;
+  dls_status s = dls_encode(ctx, d_field, p, stream, 0);
+  if (s == DLS_OK) s = dls_finalize(ctx, out, out_bytes);
+  dls_ctx_destroy(ctx);
+  return s;
+}
+
+dls_status dls_query(const uint8_t* in, size_t in_bytes, dls_params* p_out, double* eps_out,
+                     int32_t eps_cap, int64_t* nblocks) {
+  if (p_out == nullptr) return fail(DLS_EINVAL, "p_out is NULL");
+  StreamHeader h;
+  std::string err = parse_header(in, in_bytes, h);
+  if (!err.empty()) return fail(DLS_ECORRUPT, err);
+  const Problem& p = h.prob;
+  std::memset(p_out, 0, sizeof(*p_out));
+  p_out->struct_size = sizeof(dls_params);
+  p_out->nvars = p.nvars;
+  p_out->nx = p.nx; p_out->ny = p.ny; p_out->nz = p.nz; p_out->nt = p.nt;
+  p_out->dtype = p.dtype;
+  p_out->px = p.px; p_out->py = p.py; p_out->pz = p.pz; p_out->pmin = p.pmin;
+  p_out->window = p.window;
+  p_out->r_max = p.r_max;
+  p_out->precision = 0;
+  p_out->flags = p.flags;
+  p_out->abs_eps = nullptr;
+  if (eps_out != nullptr)
+    for (int v = 0; v < std::min<int>(p.nvars, std::max(0, eps_cap)); ++v) eps_out[v] = p.eps[v];
+  if (nblocks != nullptr) *nblocks = h.nblocks;
+  return DLS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Host view of one inflated batch, split into its sections.
+struct BatchView {
+  std::vector<uint8_t> raw;
+  size_t ranks = 0, esc = 0, qv = 0, qa = 0, codes = 0, vals = 0;
+};
+
+// Rebuild the plan of a parsed header; "" on success.
+std::string plan_from_header(const StreamHeader& h, Plan& pl, int slice) {
+  const Problem& p = h.prob;
+  pl.leaves.assign(p.nvars, {});
+  pl.bits = h.bits;
+  for (int v = 0; v < p.nvars; ++v) {
+    if (p.flags & DLS_ADAPTIVE) {
+      bool ok = true;
+      pl.leaves[v] = leaves_from_bits(p, h.bits[v], &ok);
+      if (!ok) return "split bits inconsistent with the grid";
+    } else {
+      if (!h.bits[v].empty()) return "split bits in a uniform stream";
+      pl.leaves[v] = uniform_leaves(p);
+    }
+  }
+  int64_t nb = 0;
+  for (int v = 0; v < p.nvars; ++v) nb += int64_t(pl.leaves[v].size()) * ((p.nt + p.window - 1) / p.window);
+  if (nb != h.nblocks) return "block count mismatch";
+  build_blocks(p, pl, slice);
+  return "";
+}
+
+// Inflate batch bi and locate its sections; "" on success.
+std::string inflate_batch(const uint8_t* in, const StreamHeader& h, const Plan& pl, int64_t bi, BatchView& bv) {
+  const auto& e = h.batches[bi];
+  if (e.usize > (uint64_t(1) << 40)) return "batch too large";
+  bv.raw.resize(e.usize);
+  uLongf n = uLongf(e.usize);
+  if (uncompress(bv.raw.data(), &n, in + h.header_bytes + e.off, uLong(e.csize)) != Z_OK || n != e.usize)
+    return "zlib stream of a batch is corrupt";
+  const int64_t nb = int64_t(pl.blocks.size());
+  const int64_t b0 = bi * kBatchBlocks, b1 = std::min(nb, b0 + kBatchBlocks);
+  const int64_t cnt = b1 - b0;
+  size_t pos = 0;
+  auto need = [&](size_t k) { return pos + k <= bv.raw.size(); };
+  if (!need(5 * cnt)) return "batch payload truncated";
+  bv.ranks = 0;
+  bv.esc = cnt;
+  pos = 5 * cnt;
+  bv.qv = pos;
+  for (int64_t b = b0; b < b1; ++b) {
+    const int r = bv.raw[b - b0];
+    const BlockDesc& d = pl.blocks[b];
+    if (r > std::min({h.prob.r_max, d.w(), d.m})) return "rank out of range";
+    pos += size_t(4) * d.w() * r;
+  }
+  bv.qa = pos;
+  for (int64_t b = b0; b < b1; ++b) pos += size_t(4) * pl.blocks[b].m * bv.raw[b - b0];
+  bv.codes = pos;
+  for (int64_t b = b0; b < b1; ++b) pos += size_t(2) * pl.blocks[b].w() * pl.blocks[b].m;
+  bv.vals = pos;
+  int64_t nesc = 0;
+  for (int64_t j = 0; j < cnt; ++j) {
+    uint32_t c;
+    std::memcpy(&c, bv.raw.data() + cnt + 4 * j, 4);
+    nesc += c;
+  }
+  pos += size_t(h.prob.esize()) * size_t(nesc);
+  if (pos != bv.raw.size()) return "batch payload size mismatch";
+  return "";
+}
+
+}  // namespace
+
+extern "C" {
+
+dls_status dls_stats(const uint8_t* in, size_t in_bytes, dls_stream_stats* s) {
+  if (s == nullptr) return fail(DLS_EINVAL, "s is NULL");
+  StreamHeader h;
+  std::string err = parse_header(in, in_bytes, h);
+  if (!err.empty()) return fail(DLS_ECORRUPT, err);
+  Plan pl;
+  err = plan_from_header(h, pl, 1024);
+  if (!err.empty()) return fail(DLS_ECORRUPT, err);
+  std::memset(s, 0, sizeof(*s));
+  s->nblocks = h.nblocks;
+  s->nbatches = int64_t(h.batches.size());
+  s->stream_bytes = int64_t(in_bytes);
+  for (int64_t bi = 0; bi < s->nbatches; ++bi) {
+    BatchView bv;
+    err = inflate_batch(in, h, pl, bi, bv);
+    if (!err.empty()) return fail(DLS_ECORRUPT, err);
+    const int64_t cnt = int64_t(bv.esc);
+    for (int64_t j = 0; j < cnt; ++j) {
+      const int r = bv.raw[j];
+      s->rank_hist[r]++;
+      if (r == 0) s->nraw++;
+      uint32_t c;
+      std::memcpy(&c, bv.raw.data() + cnt + 4 * j, 4);
+      s->nescapes += c;
+    }
+    s->payload_bytes += int64_t(bv.raw.size());
+  }
+  return DLS_OK;
+}
+
+dls_status dls_decompress(const uint8_t* in, size_t in_bytes, void* d_out, void* stream) {
+  if (d_out == nullptr) return fail(DLS_EINVAL, "output is NULL");
+  StreamHeader h;
+  std::string err = parse_header(in, in_bytes, h);
+  if (!err.empty()) return fail(DLS_ECORRUPT, err);
+  const Problem& p = h.prob;
+  Plan pl;
+  err = plan_from_header(h, pl, 1024);
+  if (!err.empty()) return fail(DLS_ECORRUPT, err);
+  const int64_t nb = h.nblocks, nbatch = int64_t(h.batches.size());
+  std::vector<BatchView> views(nbatch);
+  std::vector<std::string> errs(nbatch);
+  parallel_for(nbatch, [&](int64_t bi) { errs[bi] = inflate_batch(in, h, pl, bi, views[bi]); });
+  for (auto& e : errs)
+    if (!e.empty()) return fail(DLS_ECORRUPT, e);
+
+  // device layout of the payload (same padding rules as the encoder)
+  std::vector<uint8_t> rank(nb);
+  std::vector<int64_t> qv_off(nb), qa_off(nb);
+  int64_t qv_bytes = 0, qa_bytes = 0;
+  for (int64_t b = 0; b < nb; ++b) {
+    const BlockDesc& d = pl.blocks[b];
+    const int r = views[b / kBatchBlocks].raw[b % kBatchBlocks];
+    rank[b] = uint8_t(r);
+    qv_off[b] = qv_bytes;
+    qa_off[b] = qa_bytes;
+    qv_bytes += 4 * pad16(int64_t(d.w()) * r);
+    qa_bytes += 4 * pad16(int64_t(d.m) * r);
+  }
+  std::vector<uint8_t> qv(std::max<int64_t>(qv_bytes, 1)), qa(std::max<int64_t>(qa_bytes, 1)),
+      codes(std::max<int64_t>(pl.codes_bytes, 1));
+  std::vector<std::vector<int64_t>> eidx(nbatch);
+  std::vector<std::vector<uint64_t>> ebits(nbatch);
+  const int es = p.esize();
+  const Dims dims{p.nx, p.ny, p.nz, p.nt};
+  parallel_for(nbatch, [&](int64_t bi) {
+    BatchView& bv = views[bi];
+    const int64_t b0 = bi * kBatchBlocks, b1 = std::min(nb, b0 + kBatchBlocks);
+    const int64_t cnt = b1 - b0;
+    size_t pv = bv.qv, pa = bv.qa, pc = bv.codes, pe = bv.vals;
+    for (int64_t b = b0; b < b1; ++b) {
+      const int64_t n = int64_t(pl.blocks[b].w()) * rank[b], pad = pad16(n);
+      for (int j = 0; j < 4; ++j, pv += n) std::memcpy(qv.data() + qv_off[b] + j * pad, bv.raw.data() + pv, n);
+    }
+    for (int64_t b = b0; b < b1; ++b) {
+      const int64_t n = int64_t(pl.blocks[b].m) * rank[b], pad = pad16(n);
+      for (int j = 0; j < 4; ++j, pa += n) std::memcpy(qa.data() + qa_off[b] + j * pad, bv.raw.data() + pa, n);
+    }
+    for (int64_t b = b0; b < b1; ++b) {
+      const BlockDesc& d = pl.blocks[b];
+      const int64_t n = int64_t(d.w()) * d.m, pad = pad16(n);
+      const uint8_t* lo = bv.raw.data() + pc;
+      const uint8_t* hi = lo + n;
+      std::memcpy(codes.data() + pl.code_off[b], lo, n);
+      std::memcpy(codes.data() + pl.code_off[b] + pad, hi, n);
+      uint32_t want;
+      std::memcpy(&want, bv.raw.data() + cnt + 4 * (b - b0), 4);
+      uint32_t got = 0;
+      for (int64_t i = 0; i < n; ++i) {
+        if (lo[i] == 0xFF && hi[i] == 0xFF) {
+          const int t = int(i / d.m), pt = int(i % d.m);
+          const int ii = pt % d.px(), rho = pt / d.px(), jj = rho % d.py(), kk = rho / d.py();
+          const int64_t fi = (((int64_t(d.var) * dims.nt + d.t0 + t) * dims.nz + d.z0 + kk) * dims.ny + d.y0 + jj) *
+                                 dims.nx + d.x0 + ii;
+          uint64_t v = 0;
+          if (pe + es <= bv.raw.size()) std::memcpy(&v, bv.raw.data() + pe, es);
+          pe += es;
+          eidx[bi].push_back(fi);
+          ebits[bi].push_back(v);
+          ++got;
+        }
+      }
+      if (got != want) {
+        errs[bi] = "escape count mismatch";
+        return;
+      }
+      pc += 2 * n;
+    }
+  });
+  for (auto& e : errs)
+    if (!e.empty()) return fail(DLS_ECORRUPT, e);
+  std::vector<int64_t> all_idx;
+  std::vector<uint64_t> all_bits;
+  for (int64_t bi = 0; bi < nbatch; ++bi) {
+    all_idx.insert(all_idx.end(), eidx[bi].begin(), eidx[bi].end());
+    all_bits.insert(all_bits.end(), ebits[bi].begin(), ebits[bi].end());
+  }
+  std::vector<VarConst> vc(p.nvars);
+  for (int v = 0; v < p.nvars; ++v) vc[v] = var_const(p.eps[v]);
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevBuf d_desc, d_items, d_rank, d_qvo, d_qao, d_codeo, d_vc, d_qv, d_qa, d_codes, d_eidx, d_ebits;
+  HIP_TRY(d_desc.ensure(pl.blocks.size() * sizeof(BlockDesc)));
+  HIP_TRY(d_items.ensure(pl.items.size() * sizeof(Item)));
+  HIP_TRY(d_rank.ensure(nb));
+  HIP_TRY(d_qvo.ensure(nb * 8));
+  HIP_TRY(d_qao.ensure(nb * 8));
+  HIP_TRY(d_codeo.ensure(nb * 8));
+  HIP_TRY(d_vc.ensure(vc.size() * sizeof(VarConst)));
+  HIP_TRY(d_qv.ensure(qv.size()));
+  HIP_TRY(d_qa.ensure(qa.size()));
+  HIP_TRY(d_codes.ensure(codes.size()));
+  HIP_TRY(d_eidx.ensure(all_idx.size() * 8));
+  HIP_TRY(d_ebits.ensure(all_bits.size() * 8));
+  HIP_TRY(hipMemcpyAsync(d_desc.p, pl.blocks.data(), pl.blocks.size() * sizeof(BlockDesc), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_items.p, pl.items.data(), pl.items.size() * sizeof(Item), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_rank.p, rank.data(), nb, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_qvo.p, qv_off.data(), nb * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_qao.p, qa_off.data(), nb * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_codeo.p, pl.code_off.data(), nb * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_vc.p, vc.data(), vc.size() * sizeof(VarConst), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_qv.p, qv.data(), qv.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_qa.p, qa.data(), qa.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_codes.p, codes.data(), codes.size(), hipMemcpyHostToDevice, s));
+  if (!all_idx.empty()) {
+    HIP_TRY(hipMemcpyAsync(d_eidx.p, all_idx.data(), all_idx.size() * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_ebits.p, all_bits.data(), all_bits.size() * 8, hipMemcpyHostToDevice, s));
+  }
+  HIP_TRY(launch_decode(p.wpad(), p.dtype, d_out, dims, d_desc.as<BlockDesc>(), d_items.as<Item>(),
+                        int64_t(pl.items.size()), d_rank.as<uint8_t>(), d_qvo.as<int64_t>(), d_qao.as<int64_t>(),
+                        d_codeo.as<int64_t>(), d_vc.as<VarConst>(), d_qv.as<uint8_t>(), d_qa.as<uint8_t>(),
+                        d_codes.as<uint8_t>(), s));
+  HIP_TRY(launch_scatter(p.dtype, d_out, d_eidx.as<int64_t>(), d_ebits.as<uint64_t>(), int64_t(all_idx.size()), s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return DLS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,46 @@
+// Launch wrappers of the gfx950 kernels (see dls_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "dls_internal.h"
+
+namespace dls {
+
+// Per-variable constants of the quantizers, computed once on the host so the
+// device and any other decoder use identical values.
+struct VarConst {
+  double eps;       // absolute bound
+  double c;         // eps * 2^-16, the lattice step
+  double inv_eps;   // 1 / eps
+  double inv2eps;   // 1 / (2 eps), the residual quantizer
+  float inv_eps_f;  // float(1 / eps), coefficient quantizer
+  float pad;
+};
+
+struct EscOut {
+  unsigned long long* count;  // appended entries (may exceed cap)
+  uint64_t* key;              // block << 32 | (t * M_b + p)
+  uint64_t* val;              // input value bits
+  unsigned long long cap;
+};
+
+hipError_t launch_gram(int wp, int dtype, const void* F, const Dims& dims, const BlockDesc* desc,
+                       const Item* items, int64_t nitems, double* gpart, hipStream_t s);
+hipError_t launch_eigen(int wp, const double* gpart, const int32_t* item_start, const BlockDesc* desc,
+                        int64_t nblocks, const double* eps_v, int r_max, uint8_t* rank, double* lam,
+                        double* basis, int64_t* qv_size, int64_t* qa_size, unsigned long long* nraw,
+                        hipStream_t s);
+hipError_t launch_scan(const int64_t* in, int64_t n, int64_t* out, int64_t* tmp, hipStream_t s);
+hipError_t launch_encode(int wp, int dtype, const void* F, const Dims& dims, const BlockDesc* desc,
+                         const Item* items, int64_t nitems, const uint8_t* rank, const double* basis,
+                         const int64_t* qv_off, const int64_t* qa_off, const int64_t* code_off,
+                         const VarConst* vc, uint8_t* qv, uint8_t* qa, uint8_t* codes, float* coef,
+                         EscOut esc, hipStream_t s);
+hipError_t launch_decode(int wp, int dtype, void* F, const Dims& dims, const BlockDesc* desc,
+                         const Item* items, int64_t nitems, const uint8_t* rank, const int64_t* qv_off,
+                         const int64_t* qa_off, const int64_t* code_off, const VarConst* vc,
+                         const uint8_t* qv, const uint8_t* qa, const uint8_t* codes, hipStream_t s);
+hipError_t launch_scatter(int dtype, void* F, const int64_t* idx, const uint64_t* bits, int64_t n,
+                          hipStream_t s);
+
+}  // namespace dls

@@ -1,0 +1,779 @@
+// gfx950 kernels of the DLS block encoder / decoder.
+//
+//   k_gram    Gram product G = X X^T of every block slice on the matrix cores
+//             (v_mfma_f32_16x16x4f32, FP32 products; every 64-point chunk is
+//             flushed into FP64 accumulators), Sec. 2.7.1 cross-product SVD.
+//   k_eigen   one wavefront per block: sum of the slice Grams in FP64,
+//             cyclic Jacobi in FP64 with a parallel (round-robin) ordering,
+//             Rayleigh quotients, descending sort, canonical signs, and the
+//             rank rule of Sec. 2.4 Eq. (4) / Alg. 1 step 3.
+//   k_scan_*  exclusive scan of the per-block payload sizes (the offset scan
+//             the paper does with MPI_Scan, Sec. 2.7.2).
+//   k_encode  projection A = X^T V_r (Eq. (5)), coefficient and basis
+//             quantization, exact integer-lattice reconstruction in FP64 and
+//             the residual codes that enforce the absolute bound, with escapes.
+//   k_decode  Alg. 2: lattice values from (qV, qA, codes) and scatter, Eq. (7).
+//
+// The file is compiled with -ffp-contract=off: the lattice arithmetic must
+// round exactly as written so that the decoder reproduces the encoder bit
+// for bit.  Fused multiply-adds are written explicitly where wanted.
+#include <hip/hip_runtime.h>
+
+#include "dls_kernels.h"
+
+namespace dls {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int64_t fidx(const Dims& d, int var, int t, int z, int y, int x) {
+  return (((int64_t(var) * d.nt + t) * d.nz + z) * d.ny + y) * d.nx + x;
+}
+
+// Offset of slice point p (row-major over the patch, x fastest) from the
+// patch origin in the field.
+__device__ __forceinline__ int64_t point_off(int p, int px, int py, int64_t nx, int64_t nxy) {
+  int rho = p / px;
+  int i = p - rho * px;
+  int k = rho / py;
+  int j = rho - k * py;
+  return int64_t(k) * nxy + int64_t(j) * nx + i;
+}
+
+template <typename T>
+__device__ __forceinline__ void load4(const T* __restrict__ row, int64_t off, float* v);
+
+template <>
+__device__ __forceinline__ void load4<float>(const float* __restrict__ row, int64_t off, float* v) {
+  float4 a = *reinterpret_cast<const float4*>(row + off);
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+}
+
+template <>
+__device__ __forceinline__ void load4<double>(const double* __restrict__ row, int64_t off, float* v) {
+  double2 a = *reinterpret_cast<const double2*>(row + off);
+  double2 b = *reinterpret_cast<const double2*>(row + off + 2);
+  v[0] = float(a.x); v[1] = float(a.y); v[2] = float(b.x); v[3] = float(b.y);
+}
+
+// Load the 16 values one lane feeds to 16 MFMA steps of a 64-point chunk:
+// lane quarter q holds points 16 j + 4 q + e (j, e < 4) of time row `row`.
+template <typename T>
+__device__ __forceinline__ void load_chunk(const T* __restrict__ row, const Item& it, const BlockDesc& d,
+                                           int chunk, int q, int64_t nx, int64_t nxy, float* v) {
+#pragma unroll
+  for (int s = 0; s < 16; ++s) v[s] = 0.f;
+  if (row == nullptr) return;
+  const int px = d.px(), py = d.py();
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    int ps = chunk * 64 + 16 * j + 4 * q;
+    if (d.vec) {
+      if (ps < it.np) load4<T>(row, point_off(it.p0 + ps, px, py, nx, nxy), v + 4 * j);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (ps + e < it.np) v[4 * j + e] = float(row[point_off(it.p0 + ps + e, px, py, nx, nxy)]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Gram: one workgroup (4 waves) per item; output gpart[item][WP][WP] (FP64).
+// ---------------------------------------------------------------------------
+template <int WP, typename T>
+__global__ __launch_bounds__(256) void k_gram(const T* __restrict__ F, Dims dims,
+                                              const BlockDesc* __restrict__ desc,
+                                              const Item* __restrict__ items,
+                                              double* __restrict__ gpart) {
+  constexpr int NT = (WP == 16) ? 1 : 3;  // 16x16 tiles: 00 (and 01, 11 when WP = 32)
+  const Item it = items[blockIdx.x];
+  const BlockDesc d = desc[it.block];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tl = lane & 15, q = lane >> 4;
+  const int W = d.w();
+  const int64_t nxy = dims.nx * dims.ny;
+  const T* row0 = (tl < W) ? F + fidx(dims, d.var, d.t0 + tl, d.z0, d.y0, d.x0) : nullptr;
+  const T* row1 = (WP == 32 && tl + 16 < W) ? F + fidx(dims, d.var, d.t0 + tl + 16, d.z0, d.y0, d.x0) : nullptr;
+
+  double acc[NT][4];
+#pragma unroll
+  for (int a = 0; a < NT; ++a)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[a][v] = 0.0;
+
+  for (int c = wave; c * 64 < it.np; c += 4) {
+    float v0[16], v1[16];
+    load_chunk<T>(row0, it, d, c, q, dims.nx, nxy, v0);
+    if (WP == 32) load_chunk<T>(row1, it, d, c, q, dims.nx, nxy, v1);
+    f32x4 a00 = {0.f, 0.f, 0.f, 0.f}, a01 = a00, a11 = a00;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      a00 = __builtin_amdgcn_mfma_f32_16x16x4f32(v0[s], v0[s], a00, 0, 0, 0);
+      if (WP == 32) {
+        a01 = __builtin_amdgcn_mfma_f32_16x16x4f32(v0[s], v1[s], a01, 0, 0, 0);
+        a11 = __builtin_amdgcn_mfma_f32_16x16x4f32(v1[s], v1[s], a11, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      acc[0][v] += double(a00[v]);
+      if (WP == 32) {
+        acc[1][v] += double(a01[v]);
+        acc[2][v] += double(a11[v]);
+      }
+    }
+  }
+
+  __shared__ double red[4][NT * 4][64];
+#pragma unroll
+  for (int a = 0; a < NT; ++a)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[wave][a * 4 + v][lane] = acc[a][v];
+  __syncthreads();
+  if (wave != 0) return;
+  double* out = gpart + int64_t(blockIdx.x) * WP * WP;
+#pragma unroll
+  for (int a = 0; a < NT; ++a)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int s = a * 4 + v;
+      double g = ((red[0][s][lane] + red[1][s][lane]) + red[2][s][lane]) + red[3][s][lane];
+      // MFMA 16x16 output: lane l, register v holds row 4 (l / 16) + v, column l % 16
+      const int i = 4 * q + v, j = tl;
+      if (a == 0) {
+        out[i * WP + j] = g;
+      } else if (a == 1) {
+        out[i * WP + 16 + j] = g;
+        out[(16 + j) * WP + i] = g;
+      } else {
+        out[(16 + i) * WP + 16 + j] = g;
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Eigensolve + rank: one 64-lane workgroup per block.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int rr_player(int pos, int step, int n) {
+  return pos == 0 ? 0 : ((pos - 1 + step) % (n - 1)) + 1;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int WP>
+__global__ __launch_bounds__(64) void k_eigen(const double* __restrict__ gpart,
+                                              const int32_t* __restrict__ item_start,
+                                              const BlockDesc* __restrict__ desc,
+                                              const double* __restrict__ eps_v, int r_max,
+                                              uint8_t* __restrict__ rank_out,
+                                              double* __restrict__ lam_out,
+                                              double* __restrict__ basis_out,
+                                              int64_t* __restrict__ qv_size,
+                                              int64_t* __restrict__ qa_size,
+                                              unsigned long long* __restrict__ nraw) {
+  constexpr int EPT = WP * WP / 64;
+  constexpr int LD = WP + 1;
+  __shared__ double G[WP * LD], A[WP * LD], V[WP * LD];
+  __shared__ double alpha[WP], beta[WP], lam_s[WP], tail_s[WP + 1];
+  __shared__ int partner[WP], perm[WP];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const BlockDesc d = desc[b];
+  const int W = d.w(), M = d.m;
+
+  const int i0 = item_start[b], i1 = item_start[b + 1];
+  double gv[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int idx = tid + 64 * e;
+    double s = 0.0;
+    for (int it = i0; it < i1; ++it) s += gpart[int64_t(it) * WP * WP + idx];
+    gv[e] = s;
+    G[(idx / WP) * LD + idx % WP] = s;
+  }
+  __syncthreads();
+  bool fin = true;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int idx = tid + 64 * e, i = idx / WP, j = idx % WP;
+    const double s = 0.5 * (gv[e] + G[j * LD + i]);
+    fin = fin && isfinite(s);
+    gv[e] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int idx = tid + 64 * e, i = idx / WP, j = idx % WP;
+    G[i * LD + j] = gv[e];
+    A[i * LD + j] = gv[e];
+    V[i * LD + j] = (i == j) ? 1.0 : 0.0;
+  }
+  fin = __syncthreads_and(fin);
+  if (!fin) {  // non-finite input: raw block, every point becomes an escape
+    if (tid == 0) {
+      rank_out[b] = 0;
+      qv_size[b] = 0;
+      qa_size[b] = 0;
+      atomicAdd(nraw, 1ULL);
+    }
+    if (tid < WP) lam_out[int64_t(b) * WP + tid] = 0.0;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int idx = tid + 64 * e;
+      basis_out[int64_t(b) * WP * WP + idx] = (idx / WP == idx % WP) ? 1.0 : 0.0;
+    }
+    return;
+  }
+
+  // cyclic Jacobi, parallel round-robin ordering (WP / 2 rotations per step)
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    double off = 0.0, tot = 0.0;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int idx = tid + 64 * e, i = idx / WP, j = idx % WP;
+      const double a = A[i * LD + j];
+      tot += a * a;
+      if (i != j) off += a * a;
+    }
+    off = wave_sum(off);
+    tot = wave_sum(tot);
+    if (!(off > 1e-26 * tot)) break;
+    for (int step = 0; step < WP - 1; ++step) {
+      if (tid < WP / 2) {
+        int p = rr_player(tid, step, WP), q = rr_player(WP - 1 - tid, step, WP);
+        if (p > q) { int t = p; p = q; q = t; }
+        const double app = A[p * LD + p], aqq = A[q * LD + q], apq = A[p * LD + q];
+        double c = 1.0, s = 0.0;
+        if (apq != 0.0) {
+          const double theta = (aqq - app) / (2.0 * apq);
+          double t = 1.0 / (fabs(theta) + sqrt(1.0 + theta * theta));
+          if (theta < 0.0) t = -t;
+          c = 1.0 / sqrt(1.0 + t * t);
+          s = t * c;
+        }
+        partner[p] = q; partner[q] = p;
+        alpha[p] = c; beta[p] = -s;
+        alpha[q] = c; beta[q] = s;
+      }
+      __syncthreads();
+      double na[EPT], nv[EPT];
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int idx = tid + 64 * e, i = idx / WP, j = idx % WP;
+        const int mi = partner[i], mj = partner[j];
+        const double ai = alpha[i], bi = beta[i], aj = alpha[j], bj = beta[j];
+        const double ri = fma(aj, A[i * LD + j], bj * A[i * LD + mj]);
+        const double rm = fma(aj, A[mi * LD + j], bj * A[mi * LD + mj]);
+        na[e] = fma(ai, ri, bi * rm);
+        nv[e] = fma(aj, V[i * LD + j], bj * V[i * LD + mj]);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int idx = tid + 64 * e, i = idx / WP, j = idx % WP;
+        A[i * LD + j] = na[e];
+        V[i * LD + j] = nv[e];
+      }
+      __syncthreads();
+    }
+  }
+
+  // descending order of the Jacobi eigenvalues (stable by index).  Padded
+  // indices t >= W_b have exactly zero Gram rows, so every rotation touching
+  // them is the identity and their columns stay unit vectors on the padded
+  // rows: they sort last, after every real mode.
+  if (tid < WP) perm[tid] = tid;
+  __syncthreads();
+  if (tid < WP) {
+    const double dk = tid < W ? A[tid * LD + tid] : -INFINITY;
+    int pos = 0;
+    for (int j = 0; j < WP; ++j) {
+      const double dj = j < W ? A[j * LD + j] : -INFINITY;
+      pos += (dj > dk || (dj == dk && j < tid)) ? 1 : 0;
+    }
+    perm[pos] = tid;
+  }
+  __syncthreads();
+  // Rayleigh quotient and canonical sign of sorted column `tid`
+  double sgn = 1.0;
+  int col = 0;
+  if (tid < WP) {
+    col = perm[tid];
+    col = (col >= 0 && col < WP) ? col : tid;
+    double lam = 0.0;
+    for (int i = 0; i < WP; ++i) {
+      double gi = 0.0;
+      for (int j = 0; j < WP; ++j) gi = fma(G[i * LD + j], V[j * LD + col], gi);
+      lam = fma(V[i * LD + col], gi, lam);
+    }
+    lam_s[tid] = lam > 0.0 ? lam : 0.0;
+    double best = -1.0;
+    for (int i = 0; i < WP; ++i) {
+      const double a = fabs(V[i * LD + col]);
+      if (a > best) { best = a; sgn = V[i * LD + col] < 0.0 ? -1.0 : 1.0; }
+    }
+  }
+  __syncthreads();
+  if (tid < WP) {
+    lam_out[int64_t(b) * WP + tid] = lam_s[tid];
+    double* bo = basis_out + (int64_t(b) * WP + tid) * WP;
+    for (int t = 0; t < WP; ++t) bo[t] = sgn * V[t * LD + col];
+  }
+  if (tid == 0) {
+    const double eps = eps_v[d.var];
+    const double tau = kKappa * eps * eps * double(M) * double(W);
+    int rcap = r_max < W ? r_max : W;
+    rcap = rcap < M ? rcap : M;
+    tail_s[WP] = 0.0;
+    for (int k = WP - 1; k >= 0; --k) tail_s[k] = tail_s[k + 1] + lam_s[k];
+    int r = rcap;
+    for (int k = 1; k <= rcap; ++k)
+      if (tail_s[k] <= tau) { r = k; break; }
+    rank_out[b] = uint8_t(r);
+    qv_size[b] = 4 * pad16(int64_t(W) * r);
+    qa_size[b] = 4 * pad16(int64_t(M) * r);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of int64 sizes (n <= 1024 * 1024 * 4 per level).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_scan_local(const int64_t* __restrict__ in, int64_t n,
+                                                    int64_t* __restrict__ out, int64_t* __restrict__ tops) {
+  __shared__ int64_t s[256];
+  const int64_t base = int64_t(blockIdx.x) * 1024;
+  int64_t v[4], sum = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t i = base + threadIdx.x * 4 + e;
+    v[e] = i < n ? in[i] : 0;
+    sum += v[e];
+  }
+  s[threadIdx.x] = sum;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    const int64_t add = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
+    __syncthreads();
+    s[threadIdx.x] += add;
+    __syncthreads();
+  }
+  int64_t run = s[threadIdx.x] - sum;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t i = base + threadIdx.x * 4 + e;
+    if (i < n) out[i] = run;
+    run += v[e];
+  }
+  if (threadIdx.x == 255) tops[blockIdx.x] = s[255];
+}
+
+__global__ __launch_bounds__(256) void k_scan_add(int64_t* __restrict__ out, int64_t n,
+                                                  const int64_t* __restrict__ tops_scanned) {
+  const int64_t i = int64_t(blockIdx.x) * 1024 + threadIdx.x;
+  const int64_t add = tops_scanned[blockIdx.x];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (i + 256 * e < n) out[i + 256 * e] += add;
+}
+
+// ---------------------------------------------------------------------------
+// Encode: projection, quantization, lattice reconstruction, residual codes.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t zigzag32(int32_t v) {
+  return (uint32_t(v) << 1) ^ uint32_t(v >> 31);
+}
+__device__ __forceinline__ int32_t unzigzag32(uint32_t z) {
+  return int32_t(z >> 1) ^ -int32_t(z & 1);
+}
+
+template <typename T>
+__device__ __forceinline__ uint64_t bits_of(T v);
+template <>
+__device__ __forceinline__ uint64_t bits_of<float>(float v) { return uint64_t(__float_as_uint(v)); }
+template <>
+__device__ __forceinline__ uint64_t bits_of<double>(double v) { return uint64_t(__double_as_longlong(v)); }
+
+template <int PPT>
+__device__ __forceinline__ void store_bytes(uint8_t* __restrict__ dst, const uint32_t* bytes, int valid, bool vec) {
+  if (vec && valid == PPT) {
+    if (PPT == 4) {
+      *reinterpret_cast<uint32_t*>(dst) = bytes[0] | (bytes[1] << 8) | (bytes[2] << 16) | (bytes[3] << 24);
+    } else if (PPT == 2) {
+      *reinterpret_cast<uint16_t*>(dst) = uint16_t(bytes[0] | (bytes[1] << 8));
+    } else {
+      dst[0] = uint8_t(bytes[0]);
+    }
+  } else {
+    for (int e = 0; e < valid; ++e) dst[e] = uint8_t(bytes[e]);
+  }
+}
+
+template <int WP, typename T, int PPT>
+__global__ __launch_bounds__(256) void k_encode(const T* __restrict__ F, Dims dims,
+                                                const BlockDesc* __restrict__ desc,
+                                                const Item* __restrict__ items,
+                                                const uint8_t* __restrict__ rank,
+                                                const double* __restrict__ basis,
+                                                const int64_t* __restrict__ qv_off,
+                                                const int64_t* __restrict__ qa_off,
+                                                const int64_t* __restrict__ code_off,
+                                                const VarConst* __restrict__ vc,
+                                                uint8_t* __restrict__ qv_buf,
+                                                uint8_t* __restrict__ qa_buf,
+                                                uint8_t* __restrict__ codes,
+                                                float* __restrict__ coef,
+                                                EscOut esc) {
+  constexpr int RMAX = WP;
+  __shared__ float Vf[WP][WP];    // [k][t]
+  __shared__ double Qv[WP][WP];   // [t][k], integer valued
+  const Item it = items[blockIdx.x];
+  const int b = it.block;
+  const BlockDesc d = desc[b];
+  const int W = d.w(), M = d.m, r = rank[b];
+  const VarConst K = vc[d.var];
+  const int64_t wm_pad = pad16(int64_t(W) * M);
+
+  for (int idx = threadIdx.x; idx < WP * WP; idx += blockDim.x) {
+    const int k = idx / WP, t = idx % WP;
+    const double v = basis[int64_t(b) * WP * WP + idx];
+    const double qv = rint(v * 65536.0);
+    Vf[k][t] = float(v);
+    Qv[t][k] = qv;
+    if (it.first && k < r && t < W) {
+      const uint32_t z = zigzag32(int32_t(qv));
+      const int64_t plane = pad16(int64_t(W) * r);
+      uint8_t* dst = qv_buf + qv_off[b] + k * W + t;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) dst[j * plane] = uint8_t(z >> (8 * j));
+    }
+  }
+  __syncthreads();
+
+  const int ps0 = threadIdx.x * PPT;
+  if (ps0 >= it.np) return;
+  const int valid = (it.np - ps0) < PPT ? (it.np - ps0) : PPT;
+  const int p = it.p0 + ps0;
+  const int px = d.px(), py = d.py();
+  const int64_t nxy = dims.nx * dims.ny;
+  const T* base = F + fidx(dims, d.var, d.t0, d.z0, d.y0, d.x0);
+  const int64_t tstride = dims.nz * nxy;
+  int64_t poff[PPT];
+#pragma unroll
+  for (int e = 0; e < PPT; ++e) poff[e] = point_off(p + (e < valid ? e : 0), px, py, dims.nx, nxy);
+  const bool vec = d.vec != 0;
+
+  T x[WP][PPT];
+#pragma unroll
+  for (int t = 0; t < WP; ++t) {
+    if (t < W) {
+      const T* row = base + int64_t(t) * tstride;
+      if (vec && valid == PPT) {
+        if constexpr (sizeof(T) == 4 && PPT == 4) {
+          float4 a = *reinterpret_cast<const float4*>(row + poff[0]);
+          x[t][0] = a.x; x[t][1] = a.y; x[t][2] = a.z; x[t][3] = a.w;
+        } else if constexpr (sizeof(T) == 4 && PPT == 2) {
+          float2 a = *reinterpret_cast<const float2*>(row + poff[0]);
+          x[t][0] = a.x; x[t][1] = a.y;
+        } else {
+#pragma unroll
+          for (int e = 0; e < PPT; e += 2) {
+            double2 a = *reinterpret_cast<const double2*>(row + poff[0] + e);
+            x[t][e] = T(a.x); x[t][e + 1] = T(a.y);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < PPT; ++e) x[t][e] = (e < valid) ? row[poff[e]] : T(0);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) x[t][e] = T(0);
+    }
+  }
+
+  const int64_t code_lo = code_off[b] + int64_t(p);
+  const int64_t code_hi = code_lo + wm_pad;
+
+  if (r == 0) {  // raw block: every point is an escape
+#pragma unroll
+    for (int t = 0; t < WP; ++t) {
+      if (t >= W) continue;
+      uint32_t ff[PPT];
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) ff[e] = 0xFF;
+      store_bytes<PPT>(codes + code_lo + int64_t(t) * M, ff, valid, vec);
+      store_bytes<PPT>(codes + code_hi + int64_t(t) * M, ff, valid, vec);
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) {
+        if (e >= valid) continue;
+        const unsigned long long slot = atomicAdd(esc.count, 1ULL);
+        if (slot < esc.cap) {
+          esc.key[slot] = (uint64_t(b) << 32) | uint64_t(uint32_t(t * M + p + e));
+          esc.val[slot] = bits_of<T>(x[t][e]);
+        }
+      }
+    }
+    return;
+  }
+
+  // projection and coefficient quantization (FP32), row-wise overflow guard
+  int32_t qa[RMAX][PPT];
+  bool ovf[PPT];
+#pragma unroll
+  for (int e = 0; e < PPT; ++e) ovf[e] = false;
+  const int64_t qa_plane = pad16(int64_t(M) * r);
+#pragma unroll
+  for (int k = 0; k < RMAX; ++k) {
+    if (k >= r) continue;
+    float a[PPT];
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) a[e] = 0.f;
+#pragma unroll
+    for (int t = 0; t < WP; ++t) {
+      if (t < W) {
+        const float v = Vf[k][t];
+#pragma unroll
+        for (int e = 0; e < PPT; ++e) a[e] = fmaf(float(x[t][e]), v, a[e]);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) {
+      const float qf = rintf(a[e] * K.inv_eps_f);
+      const bool ok = fabsf(qf) < 2147483648.0f;
+      ovf[e] = ovf[e] || !ok;
+      qa[k][e] = ok ? int32_t(qf) : 0;
+    }
+    if (coef != nullptr) {
+#pragma unroll
+      for (int e = 0; e < PPT; ++e)
+        if (e < valid) coef[qa_off[b] / 4 + int64_t(k) * M + p + e] = a[e];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < RMAX; ++k) {
+    if (k >= r) continue;
+    uint32_t z[PPT];
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) {
+      if (ovf[e]) qa[k][e] = 0;
+      z[e] = zigzag32(qa[k][e]);
+    }
+    uint8_t* dst = qa_buf + qa_off[b] + int64_t(k) * M + p;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      uint32_t by[PPT];
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) by[e] = (z[e] >> (8 * j)) & 0xFF;
+      store_bytes<PPT>(dst + j * qa_plane, by, valid, vec);
+    }
+  }
+
+  // lattice reconstruction (exact in FP64) and residual codes
+#pragma unroll
+  for (int t = 0; t < WP; ++t) {
+    if (t >= W) continue;
+    uint32_t lo[PPT], hi[PPT];
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) {
+      double S = 0.0;
+#pragma unroll
+      for (int k = 0; k < RMAX; ++k)
+        if (k < r) S = fma(Qv[t][k], double(qa[k][e]), S);
+      const double xv = double(x[t][e]);
+      const double xhat = S * K.c;
+      const double dlt = xv - xhat;
+      double q = rint(dlt * K.inv2eps);
+      bool esc_pt = fabs(q) > 32767.0;
+      if (esc_pt) q = 0.0;
+      const double n = S + q * 131072.0;
+      const T outv = T(n * K.c);
+      esc_pt = esc_pt || (fabs(xv - double(outv)) > K.eps);
+      uint32_t code = 0xFFFF;
+      if (!esc_pt) {
+        const int32_t qi = int32_t(q);
+        code = uint32_t(uint16_t((qi << 1) ^ (qi >> 31)));
+      } else if (e < valid) {
+        const unsigned long long slot = atomicAdd(esc.count, 1ULL);
+        if (slot < esc.cap) {
+          esc.key[slot] = (uint64_t(b) << 32) | uint64_t(uint32_t(t * M + p + e));
+          esc.val[slot] = bits_of<T>(x[t][e]);
+        }
+      }
+      lo[e] = code & 0xFF;
+      hi[e] = code >> 8;
+    }
+    store_bytes<PPT>(codes + code_lo + int64_t(t) * M, lo, valid, vec);
+    store_bytes<PPT>(codes + code_hi + int64_t(t) * M, hi, valid, vec);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Decode (Alg. 2): lattice values of every non-escaped point, scattered into
+// the field (Eq. (7)).  Escapes are written afterwards by k_scatter.
+// ---------------------------------------------------------------------------
+template <int WP, typename T>
+__global__ __launch_bounds__(256) void k_decode(T* __restrict__ F, Dims dims,
+                                                const BlockDesc* __restrict__ desc,
+                                                const Item* __restrict__ items,
+                                                const uint8_t* __restrict__ rank,
+                                                const int64_t* __restrict__ qv_off,
+                                                const int64_t* __restrict__ qa_off,
+                                                const int64_t* __restrict__ code_off,
+                                                const VarConst* __restrict__ vc,
+                                                const uint8_t* __restrict__ qv_buf,
+                                                const uint8_t* __restrict__ qa_buf,
+                                                const uint8_t* __restrict__ codes) {
+  __shared__ double Qv[WP][WP];  // [t][k]
+  const Item it = items[blockIdx.x];
+  const int b = it.block;
+  const BlockDesc d = desc[b];
+  const int W = d.w(), M = d.m, r = rank[b];
+  const VarConst K = vc[d.var];
+  const int64_t vplane = pad16(int64_t(W) * r);
+  for (int idx = threadIdx.x; idx < WP * WP; idx += blockDim.x) {
+    const int k = idx / WP, t = idx % WP;
+    double v = 0.0;
+    if (k < r && t < W) {
+      const uint8_t* src = qv_buf + qv_off[b] + k * W + t;
+      const uint32_t z = uint32_t(src[0]) | (uint32_t(src[vplane]) << 8) |
+                         (uint32_t(src[2 * vplane]) << 16) | (uint32_t(src[3 * vplane]) << 24);
+      v = double(unzigzag32(z));
+    }
+    Qv[t][k] = v;
+  }
+  __syncthreads();
+  const int64_t aplane = pad16(int64_t(M) * r);
+  const int64_t wm_pad = pad16(int64_t(W) * M);
+  const int64_t nxy = dims.nx * dims.ny;
+  T* base = F + fidx(dims, d.var, d.t0, d.z0, d.y0, d.x0);
+  const int64_t tstride = dims.nz * nxy;
+  for (int ps = threadIdx.x; ps < it.np; ps += blockDim.x) {
+    const int p = it.p0 + ps;
+    double qa[WP];
+#pragma unroll
+    for (int k = 0; k < WP; ++k) {
+      qa[k] = 0.0;
+      if (k < r) {
+        const uint8_t* src = qa_buf + qa_off[b] + int64_t(k) * M + p;
+        const uint32_t z = uint32_t(src[0]) | (uint32_t(src[aplane]) << 8) |
+                           (uint32_t(src[2 * aplane]) << 16) | (uint32_t(src[3 * aplane]) << 24);
+        qa[k] = double(unzigzag32(z));
+      }
+    }
+    const int64_t off = point_off(p, d.px(), d.py(), dims.nx, nxy);
+    for (int t = 0; t < W; ++t) {
+      const int64_t ci = code_off[b] + int64_t(t) * M + p;
+      const uint32_t code = uint32_t(codes[ci]) | (uint32_t(codes[ci + wm_pad]) << 8);
+      if (code == 0xFFFF) continue;
+      double S = 0.0;
+#pragma unroll
+      for (int k = 0; k < WP; ++k)
+        if (k < r) S = fma(Qv[t][k], qa[k], S);
+      const int32_t q = int32_t(code >> 1) ^ -int32_t(code & 1);
+      const double n = S + double(q) * 131072.0;
+      base[int64_t(t) * tstride + off] = T(n * K.c);
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_scatter(T* __restrict__ F, const int64_t* __restrict__ idx,
+                                                 const uint64_t* __restrict__ bits, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= n) return;
+  if (sizeof(T) == 4) {
+    reinterpret_cast<uint32_t*>(F)[idx[i]] = uint32_t(bits[i]);
+  } else {
+    reinterpret_cast<uint64_t*>(F)[idx[i]] = bits[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launch wrappers
+// ---------------------------------------------------------------------------
+hipError_t launch_gram(int wp, int dtype, const void* F, const Dims& dims, const BlockDesc* desc,
+                       const Item* items, int64_t nitems, double* gpart, hipStream_t s) {
+  if (nitems == 0) return hipSuccess;
+  const dim3 g{unsigned(nitems)}, bl{256};
+  if (wp == 16 && dtype == 0) hipLaunchKernelGGL((k_gram<16, float>), g, bl, 0, s, (const float*)F, dims, desc, items, gpart);
+  else if (wp == 16) hipLaunchKernelGGL((k_gram<16, double>), g, bl, 0, s, (const double*)F, dims, desc, items, gpart);
+  else if (dtype == 0) hipLaunchKernelGGL((k_gram<32, float>), g, bl, 0, s, (const float*)F, dims, desc, items, gpart);
+  else hipLaunchKernelGGL((k_gram<32, double>), g, bl, 0, s, (const double*)F, dims, desc, items, gpart);
+  return hipGetLastError();
+}
+
+hipError_t launch_eigen(int wp, const double* gpart, const int32_t* item_start, const BlockDesc* desc,
+                        int64_t nblocks, const double* eps_v, int r_max, uint8_t* rank, double* lam,
+                        double* basis, int64_t* qv_size, int64_t* qa_size, unsigned long long* nraw,
+                        hipStream_t s) {
+  if (nblocks == 0) return hipSuccess;
+  const dim3 g{unsigned(nblocks)}, bl{64};
+  if (wp == 16)
+    hipLaunchKernelGGL(k_eigen<16>, g, bl, 0, s, gpart, item_start, desc, eps_v, r_max, rank, lam, basis, qv_size, qa_size, nraw);
+  else
+    hipLaunchKernelGGL(k_eigen<32>, g, bl, 0, s, gpart, item_start, desc, eps_v, r_max, rank, lam, basis, qv_size, qa_size, nraw);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const int64_t* in, int64_t n, int64_t* out, int64_t* tmp, hipStream_t s) {
+  // tmp holds 2 * ceil(n / 1024) + 2 * ceil(n / 2^20) + 2 entries
+  if (n == 0) return hipSuccess;
+  const int64_t nb = (n + 1023) / 1024;
+  int64_t* tops = tmp;
+  int64_t* tops_scan = tmp + nb;
+  hipLaunchKernelGGL(k_scan_local, dim3(unsigned(nb)), dim3(256), 0, s, in, n, out, tops);
+  if (nb > 1) {
+    hipError_t e = launch_scan(tops, nb, tops_scan, tmp + 2 * nb, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_add, dim3(unsigned(nb)), dim3(256), 0, s, out, n, (const int64_t*)tops_scan);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_encode(int wp, int dtype, const void* F, const Dims& dims, const BlockDesc* desc,
+                         const Item* items, int64_t nitems, const uint8_t* rank, const double* basis,
+                         const int64_t* qv_off, const int64_t* qa_off, const int64_t* code_off,
+                         const VarConst* vc, uint8_t* qv, uint8_t* qa, uint8_t* codes, float* coef,
+                         EscOut esc, hipStream_t s) {
+  if (nitems == 0) return hipSuccess;
+  const dim3 g{unsigned(nitems)}, bl{256};
+  if (wp == 16 && dtype == 0)
+    hipLaunchKernelGGL((k_encode<16, float, 4>), g, bl, 0, s, (const float*)F, dims, desc, items, rank, basis, qv_off, qa_off, code_off, vc, qv, qa, codes, coef, esc);
+  else if (wp == 16)
+    hipLaunchKernelGGL((k_encode<16, double, 2>), g, bl, 0, s, (const double*)F, dims, desc, items, rank, basis, qv_off, qa_off, code_off, vc, qv, qa, codes, coef, esc);
+  else if (dtype == 0)
+    hipLaunchKernelGGL((k_encode<32, float, 2>), g, bl, 0, s, (const float*)F, dims, desc, items, rank, basis, qv_off, qa_off, code_off, vc, qv, qa, codes, coef, esc);
+  else
+    hipLaunchKernelGGL((k_encode<32, double, 2>), g, bl, 0, s, (const double*)F, dims, desc, items, rank, basis, qv_off, qa_off, code_off, vc, qv, qa, codes, coef, esc);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode(int wp, int dtype, void* F, const Dims& dims, const BlockDesc* desc,
+                         const Item* items, int64_t nitems, const uint8_t* rank, const int64_t* qv_off,
+                         const int64_t* qa_off, const int64_t* code_off, const VarConst* vc,
+                         const uint8_t* qv, const uint8_t* qa, const uint8_t* codes, hipStream_t s) {
+  if (nitems == 0) return hipSuccess;
+  const dim3 g{unsigned(nitems)}, bl{256};
+  if (wp == 16 && dtype == 0)
+    hipLaunchKernelGGL((k_decode<16, float>), g, bl, 0, s, (float*)F, dims, desc, items, rank, qv_off, qa_off, code_off, vc, qv, qa, codes);
+  else if (wp == 16)
+    hipLaunchKernelGGL((k_decode<16, double>), g, bl, 0, s, (double*)F, dims, desc, items, rank, qv_off, qa_off, code_off, vc, qv, qa, codes);
+  else if (dtype == 0)
+    hipLaunchKernelGGL((k_decode<32, float>), g, bl, 0, s, (float*)F, dims, desc, items, rank, qv_off, qa_off, code_off, vc, qv, qa, codes);
+  else
+    hipLaunchKernelGGL((k_decode<32, double>), g, bl, 0, s, (double*)F, dims, desc, items, rank, qv_off, qa_off, code_off, vc, qv, qa, codes);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(int dtype, void* F, const int64_t* idx, const uint64_t* bits, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const dim3 g{unsigned((n + 255) / 256)}, bl{256};
+  if (dtype == 0) hipLaunchKernelGGL(k_scatter<float>, g, bl, 0, s, (float*)F, idx, bits, n);
+  else hipLaunchKernelGGL(k_scatter<double>, g, bl, 0, s, (double*)F, idx, bits, n);
+  return hipGetLastError();
+}
+
+}  // namespace dls

@@ -34,6 +34,18 @@ CONFIGS = {
                     "k^-5/3, exp(-0.02 t) decay, 16^3 patches x 32-step windows, eps = 1e-3*range",
                kind="spectrum", nx=256, ny=256, nz=256, nt=64, nvars=3, dtype="f32", px=16, py=16,
                pz=16, window=32, seeds=[11, 12, 13], rel_eps=1e-3),
+    "c3": dict(desc="2D FP32 4096x2048 x 100 steps, 8192 moving Gaussian blobs (4 per 64^2) + "
+                    "N(0,1e-4) counter-based noise, quadtree 32^2..4^2 split where the mean "
+                    "|grad| of snapshot 0 exceeds its 80th percentile, 16-step windows "
+                    "(last one 4), eps = 1e-3*range",
+               kind="blobs_gpu", nx=4096, ny=2048, nz=1, nt=100, nvars=1, dtype="f32", px=32, py=32,
+               pz=1, pmin=4, adaptive=True, window=16, seeds=[31], nblobs=8192, rel_eps=1e-3),
+    "c5": dict(desc="3D FP32 512^3 x 48 steps, 2 variables (u, v), 64 random-phase modes k^-5/3, "
+                    "exp(-0.02 t) decay, octree 32^3..8^3 split where the mean |grad| of "
+                    "snapshot 0 exceeds its 80th percentile, 16-step windows, eps = 1e-3*range "
+                    "(51.5 GB resident in HBM)",
+               kind="spectrum", nx=512, ny=512, nz=512, nt=48, nvars=2, dtype="f32", px=32, py=32,
+               pz=32, pmin=8, adaptive=True, window=16, seeds=[11, 12], rel_eps=1e-3),
 }
 
 
@@ -51,15 +63,18 @@ def make_field(cfg):
         f = synth.blobs2d(nx=cfg["nx"], ny=cfg["ny"], nt=cfg["nt"], seed=cfg["seeds"][0],
                           dtype=np.float32 if cfg["dtype"] == "f32" else np.float64)
         t = torch.from_numpy(f).cuda()
+    elif cfg["kind"] == "blobs_gpu":
+        from synth import gpu as sg
+        t = torch.empty(shape, dtype=dt, device="cuda")
+        sg.blobs_into(t[0], nblobs=cfg["nblobs"], seed=cfg["seeds"][0])
     else:
         from synth import gpu as sg
         t = torch.empty(shape, dtype=dt, device="cuda")
         for v, seed in enumerate(cfg["seeds"]):
             sg.spectrum_into(t[v], seed=seed, nmodes=64, drift=cfg.get("drift", False))
-    eps = []
-    for v in range(cfg["nvars"]):
-        lo, hi = torch.aminmax(t[v])
-        eps.append(cfg["rel_eps"] * (float(hi.double()) - float(lo.double())))
+    import paper_2601_20113_amd as dls
+    lo, hi = dls.value_range(t)
+    eps = [cfg["rel_eps"] * (h - l) for l, h in zip(lo, hi)]
     torch.cuda.synchronize()
     return t, eps
 
@@ -74,11 +89,11 @@ def cpu_baseline(field, cfg, eps, seconds):
     sub = field[0:1, 0:W, 0:min(cfg["pz"], cfg["nz"])].cpu().numpy()
     p = odls.Params(nx=cfg["nx"], ny=cfg["ny"], nz=sub.shape[2], nt=W, nvars=1, dtype=cfg["dtype"],
                     px=cfg["px"], py=cfg["py"], pz=cfg["pz"] if cfg["nz"] > 1 else 1, window=W,
-                    eps=[eps[0]])
-    blocks, _ = odls.plan(sub, p)
+                    eps=[eps[0]], pmin=cfg.get("pmin", 0), adaptive=cfg.get("adaptive", False))
     done, nbytes = 0, 0
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
+        blocks, _ = odls.plan(sub, p)
         for b in blocks:
             xb = odls.gather(sub, b)
             odls.encode_block(xb, eps[0], p.resolved_rmax(), p.np_dtype)
@@ -88,7 +103,8 @@ def cpu_baseline(field, cfg, eps, seconds):
                 break
         dt = time.perf_counter() - t0
     return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": "%d of %d blocks (variable 0, window 0, first z-slab), %.1f MB in %.1f s"
+            "sample": "%d of %d blocks of variable 0, window 0, first z-slab (the oracle's own "
+                      "plan of that slab included), %.1f MB in %.1f s"
                       % (done, len(blocks), nbytes / 1e6, dt)}
 
 
@@ -115,21 +131,22 @@ def main():
     in_bytes = field.numel() * field.element_size()
     p = dls.Params(nx=cfg["nx"], ny=cfg["ny"], nz=cfg["nz"], nt=cfg["nt"], nvars=cfg["nvars"],
                    dtype=cfg["dtype"], px=cfg["px"], py=cfg["py"], pz=cfg["pz"],
-                   window=cfg["window"], eps=eps)
+                   window=cfg["window"], eps=eps, pmin=cfg.get("pmin", 0),
+                   adaptive=cfg.get("adaptive", False))
     enc = dls.Encoder()
     stream = torch.cuda.current_stream()
     log("warmup %d" % args.warmup)
     for _ in range(args.warmup):
         enc.encode(field, p, stream=stream)
     torch.cuda.synchronize()
-    stage = [0.0] * 4
+    stage = [0.0] * 5
     log("timing %d steps" % args.steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         enc.encode(field, p, stream=stream)
         inf = enc.info()
-        for i in range(4):
+        for i in range(5):
             stage[i] += inf.stage_ms[i]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -141,8 +158,8 @@ def main():
     # roofline of the dominant kernel, from algorithmic bytes per launch
     es = field.element_size()
     nvals = field.numel()
-    names = ["gram", "eigen", "scan", "encode"]
-    dom = max(range(4), key=lambda i: stage[i])
+    names = ["plan", "gram", "eigen", "scan", "encode"]
+    dom = max(range(5), key=lambda i: stage[i])
     if names[dom] == "encode":
         traffic_alg = nvals * (es + 2) + inf.qa_bytes
     elif names[dom] == "gram":

@@ -62,8 +62,10 @@ typedef enum { DLS_PREC_FP32 = 0, DLS_PREC_BF16 = 1 } dls_precision;
 /* dls_params.flags */
 enum {
   DLS_ADAPTIVE = 1   /* quadtree (2D) / octree (3D) patches between pmin and
-                        px, split where the mean gradient magnitude of
-                        snapshot 0 exceeds its 80th percentile             */
+                        px, computed per variable from snapshot 0: a node
+                        of edge e > pmin splits into its half-edge children
+                        while its mean gradient magnitude exceeds the 80th
+                        percentile sorted(g)[floor(0.8 (n-1))]             */
 };
 
 typedef struct dls_params {
@@ -106,8 +108,10 @@ typedef struct dls_encode_info {
   const float* d_coef;      /* [sum M_b r_b] FP32 coefficients A[k][p] at
                                d_qa_off[b]/4 when requested, else NULL      */
   double gpu_ms;            /* device time of the whole encode (HIP events) */
-  double stage_ms[4];       /* HIP-event time of each stage on the caller's
-                               stream: Gram, eigensolve + rank, offset scan,
+  double stage_ms[5];       /* HIP-event time of each stage on the caller's
+                               stream: plan (adaptive: gradient, percentile,
+                               node sums, tree walk, upload), Gram,
+                               eigensolve + rank, offset scan + rank classes,
                                projection / quantization / residual codes   */
 } dls_encode_info;
 
@@ -127,6 +131,15 @@ void dls_ctx_destroy(dls_ctx* ctx);
  * Errors: DLS_EINVAL (params), DLS_ENOMEM, DLS_EDEVICE. */
 dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* p,
                       void* stream, int keep_coef);
+
+/* Per-variable value range of a device field (layout above; nvars variables
+ * of values_per_var = nt*nz*ny*nx elements each), computed on the device in
+ * FP64 with non-finite values skipped.  The absolute bound of the benchmark
+ * configurations is eps_v = c * (max_v - min_v).  min_out / max_out: host
+ * arrays of nvars doubles (+inf / -inf for a variable with no finite value).
+ * Errors: DLS_EINVAL, DLS_ENOMEM, DLS_EDEVICE. */
+dls_status dls_range(const void* d_field, int32_t nvars, int64_t values_per_var, int32_t dtype,
+                     void* stream, double* min_out, double* max_out);
 
 /* Diagnostics of the last dls_encode on ctx (pointers into ctx memory). */
 dls_status dls_encode_info_get(const dls_ctx* ctx, dls_encode_info* info);

@@ -28,7 +28,7 @@ DLS_F32, DLS_F64 = 0, 1
 DLS_PREC_FP32, DLS_PREC_BF16 = 0, 1
 DLS_ADAPTIVE = 1
 
-EXPORTS = ["dls_ctx_create", "dls_ctx_destroy", "dls_encode", "dls_encode_info_get",
+EXPORTS = ["dls_ctx_create", "dls_ctx_destroy", "dls_encode", "dls_encode_info_get", "dls_range",
            "dls_finalize", "dls_compress", "dls_query", "dls_decompress", "dls_stats",
            "dls_free", "dls_last_error"]
 
@@ -57,7 +57,7 @@ class _EncodeInfo(ctypes.Structure):
                 ("d_qa", ctypes.c_void_p), ("d_codes", ctypes.c_void_p),
                 ("d_qa_off", ctypes.c_void_p), ("d_code_off", ctypes.c_void_p),
                 ("d_coef", ctypes.c_void_p), ("gpu_ms", ctypes.c_double),
-                ("stage_ms", ctypes.c_double * 4)]
+                ("stage_ms", ctypes.c_double * 5)]
 
 
 class _StreamStats(ctypes.Structure):
@@ -92,10 +92,12 @@ def lib():
                                 ctypes.POINTER(ctypes.c_int64)]
         L.dls_decompress.argtypes = [ctypes.c_char_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]
         L.dls_stats.argtypes = [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(_StreamStats)]
+        L.dls_range.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.dls_free.argtypes = [ctypes.c_void_p]
         L.dls_free.restype = None
         L.dls_last_error.restype = ctypes.c_char_p
-        for name in ("dls_ctx_create", "dls_encode", "dls_encode_info_get", "dls_finalize",
+        for name in ("dls_ctx_create", "dls_encode", "dls_encode_info_get", "dls_finalize", "dls_range",
                      "dls_compress", "dls_query", "dls_decompress", "dls_stats"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -199,6 +201,19 @@ class Encoder:
             return ctypes.string_at(out.value, n.value)
         finally:
             lib().dls_free(out)
+
+
+def value_range(field: torch.Tensor, stream=None):
+    """Per-variable (min, max) of a (nvars, ...) device field, computed on the device."""
+    if not field.is_cuda or not field.is_contiguous() or field.dtype not in (torch.float32, torch.float64):
+        raise ValueError("field must be a contiguous float32/float64 device tensor")
+    nv = field.shape[0]
+    lo = (ctypes.c_double * nv)()
+    hi = (ctypes.c_double * nv)()
+    _check(lib().dls_range(ctypes.c_void_p(field.data_ptr()), nv, field.numel() // nv,
+                           DLS_F32 if field.dtype == torch.float32 else DLS_F64,
+                           _stream_handle(stream), lo, hi))
+    return [lo[i] for i in range(nv)], [hi[i] for i in range(nv)]
 
 
 def compress(field: torch.Tensor, p: Params, stream=None) -> bytes:

@@ -154,10 +154,11 @@ struct dls_ctx {
   Plan plan;
   DevBuf desc, items, item_start, code_off, gram, rank, lam, basis;
   DevBuf qv_size, qa_size, qv_off, qa_off, scan_tmp, qv, qa, codes, coef;
-  DevBuf esc_key, esc_val, counters, vconst, eps_v;
+  DevBuf esc_key, esc_val, counters, vconst, eps_v, cls_lists;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  hipEvent_t evs[4] = {nullptr, nullptr, nullptr, nullptr};  // gram, eigen, scan ends; encode start
-  double stage_ms[4] = {0, 0, 0, 0};
+  hipEvent_t evs[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // gram, eigen, scan ends; encode start; plan start
+  double stage_ms[5] = {0, 0, 0, 0, 0};
+  PlanScratch* plan_scratch = nullptr;
   uint64_t esc_cap = 0;
   // results of the last dls_encode
   bool have_result = false;
@@ -169,6 +170,7 @@ struct dls_ctx {
     if (ev1) (void)hipEventDestroy(ev1);
     for (auto& e : evs)
       if (e) (void)hipEventDestroy(e);
+    plan_scratch_delete(plan_scratch);
   }
 };
 
@@ -191,6 +193,7 @@ dls_status dls_ctx_create(int device, dls_ctx** out) {
   HIP_TRY(hipEventCreate(&c->ev0));
   HIP_TRY(hipEventCreate(&c->ev1));
   for (auto& e : c->evs) HIP_TRY(hipEventCreate(&e));
+  c->plan_scratch = plan_scratch_new();
   *out = c.release();
   return DLS_OK;
 }
@@ -208,17 +211,28 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
   Problem p;
   if (dls_status s = validate(params, p)) return s;
   if (p.precision != DLS_PREC_FP32) return fail(DLS_EUNSUPPORTED, "BF16 contractions are not built yet");
-  if (p.flags & DLS_ADAPTIVE) return fail(DLS_EUNSUPPORTED, "adaptive plan is not built yet");
   hipStream_t s = static_cast<hipStream_t>(stream);
   HIP_TRY(hipSetDevice(ctx->device));
   ctx->have_result = false;
+  HIP_TRY(hipEventRecord(ctx->evs[4], s));
+  const bool adaptive = (p.flags & DLS_ADAPTIVE) != 0;
+  if (adaptive) {
+    // the adaptive plan depends on snapshot 0, so it is rebuilt on every call
+    ctx->plan_valid = false;
+    ctx->plan = Plan();
+    std::string err;
+    hipError_t he = adaptive_plan(p, d_field, s, *ctx->plan_scratch, ctx->plan, err);
+    if (he != hipSuccess) return fail(he == hipErrorOutOfMemory ? DLS_ENOMEM : DLS_EDEVICE, "adaptive plan: " + err);
+  }
 
   // plan: uniform tiling depends on the problem statement only, so it is cached
   if (!ctx->plan_valid || !same_layout(ctx->prob, p)) {
     ctx->plan_valid = false;
-    ctx->plan = Plan();
-    ctx->plan.leaves.assign(p.nvars, uniform_leaves(p));
-    ctx->plan.bits.assign(p.nvars, {});
+    if (!adaptive) {
+      ctx->plan = Plan();
+      ctx->plan.leaves.assign(p.nvars, uniform_leaves(p));
+      ctx->plan.bits.assign(p.nvars, {});
+    }
     build_blocks(p, ctx->plan, slice_points(p));
     if (ctx->plan.blocks.size() >= (size_t(1) << 31)) return fail(DLS_EINVAL, "too many blocks");
     const Plan& pl = ctx->plan;
@@ -248,7 +262,8 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
   HIP_TRY(ctx->qa_off.ensure(size_t(nb) * sizeof(int64_t)));
   HIP_TRY(ctx->scan_tmp.ensure(size_t(4 * (nb / 1024 + 4)) * sizeof(int64_t)));
   HIP_TRY(ctx->codes.ensure(size_t(pl.codes_bytes)));
-  HIP_TRY(ctx->counters.ensure(2 * sizeof(unsigned long long)));
+  HIP_TRY(ctx->counters.ensure(2 * sizeof(unsigned long long) + kRankClasses * sizeof(unsigned int)));
+  HIP_TRY(ctx->cls_lists.ensure(size_t(ni) * kRankClasses * sizeof(int32_t)));
   if (ctx->esc_cap == 0) {
     ctx->esc_cap = std::max<uint64_t>(uint64_t(1) << 20, uint64_t(p.values() / 256));
     HIP_TRY(ctx->esc_key.ensure(ctx->esc_cap * 8));
@@ -260,7 +275,7 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
   HIP_TRY(ctx->eps_v.ensure(p.eps.size() * sizeof(double)));
   HIP_TRY(hipMemcpyAsync(ctx->vconst.p, vc.data(), vc.size() * sizeof(VarConst), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(ctx->eps_v.p, p.eps.data(), p.eps.size() * sizeof(double), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemsetAsync(ctx->counters.p, 0, 2 * sizeof(unsigned long long), s));
+  HIP_TRY(hipMemsetAsync(ctx->counters.p, 0, 2 * sizeof(unsigned long long) + kRankClasses * sizeof(unsigned int), s));
 
   const Dims dims{p.nx, p.ny, p.nz, p.nt};
   unsigned long long* cnt = ctx->counters.as<unsigned long long>();
@@ -275,7 +290,12 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
   HIP_TRY(hipEventRecord(ctx->evs[1], s));
   HIP_TRY(launch_scan(ctx->qv_size.as<int64_t>(), nb, ctx->qv_off.as<int64_t>(), ctx->scan_tmp.as<int64_t>(), s));
   HIP_TRY(launch_scan(ctx->qa_size.as<int64_t>(), nb, ctx->qa_off.as<int64_t>(), ctx->scan_tmp.as<int64_t>(), s));
+  unsigned int* cls_count = reinterpret_cast<unsigned int*>(cnt + 2);
+  HIP_TRY(launch_classify(ctx->items.as<Item>(), ni, ctx->rank.as<uint8_t>(), cls_count,
+                          ctx->cls_lists.as<int32_t>(), s));
   HIP_TRY(hipEventRecord(ctx->evs[2], s));
+  unsigned int hcls[kRankClasses];
+  HIP_TRY(hipMemcpyAsync(hcls, cls_count, sizeof(hcls), hipMemcpyDeviceToHost, s));
   int64_t tail[4];
   HIP_TRY(hipMemcpyAsync(&tail[0], ctx->qv_off.as<int64_t>() + nb - 1, 8, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(&tail[1], ctx->qv_size.as<int64_t>() + nb - 1, 8, hipMemcpyDeviceToHost, s));
@@ -292,11 +312,13 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
   for (int attempt = 0; attempt < 2; ++attempt) {
     EscOut esc{cnt, ctx->esc_key.as<uint64_t>(), ctx->esc_val.as<uint64_t>(), ctx->esc_cap};
     HIP_TRY(hipEventRecord(ctx->evs[3], s));
-    HIP_TRY(launch_encode(wp, p.dtype, d_field, dims, ctx->desc.as<BlockDesc>(), ctx->items.as<Item>(), ni,
-                          ctx->rank.as<uint8_t>(), ctx->basis.as<double>(), ctx->qv_off.as<int64_t>(),
-                          ctx->qa_off.as<int64_t>(), ctx->code_off.as<int64_t>(), ctx->vconst.as<VarConst>(),
-                          ctx->qv.as<uint8_t>(), ctx->qa.as<uint8_t>(), ctx->codes.as<uint8_t>(),
-                          ctx->keep_coef ? ctx->coef.as<float>() : nullptr, esc, s));
+    for (int c = 0; c < kRankClasses; ++c)
+      HIP_TRY(launch_encode(wp, p.dtype, c, d_field, dims, ctx->desc.as<BlockDesc>(), ctx->items.as<Item>(),
+                            ctx->cls_lists.as<int32_t>() + int64_t(c) * ni, hcls[c], ctx->rank.as<uint8_t>(),
+                            ctx->basis.as<double>(), ctx->qv_off.as<int64_t>(), ctx->qa_off.as<int64_t>(),
+                            ctx->code_off.as<int64_t>(), ctx->vconst.as<VarConst>(), ctx->qv.as<uint8_t>(),
+                            ctx->qa.as<uint8_t>(), ctx->codes.as<uint8_t>(),
+                            ctx->keep_coef ? ctx->coef.as<float>() : nullptr, esc, s));
     HIP_TRY(hipEventRecord(ctx->ev1, s));
     unsigned long long hc[2];
     HIP_TRY(hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, s));
@@ -314,13 +336,34 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
   ctx->gpu_ms = ms;
-  const hipEvent_t marks[5][2] = {{ctx->ev0, ctx->evs[0]}, {ctx->evs[0], ctx->evs[1]},
-                                  {ctx->evs[1], ctx->evs[2]}, {ctx->evs[3], ctx->ev1}, {nullptr, nullptr}};
-  for (int i = 0; i < 4; ++i) {
+  const hipEvent_t marks[5][2] = {{ctx->evs[4], ctx->ev0}, {ctx->ev0, ctx->evs[0]}, {ctx->evs[0], ctx->evs[1]},
+                                  {ctx->evs[1], ctx->evs[2]}, {ctx->evs[3], ctx->ev1}};
+  for (int i = 0; i < 5; ++i) {
     HIP_TRY(hipEventElapsedTime(&ms, marks[i][0], marks[i][1]));
     ctx->stage_ms[i] = ms;
   }
   ctx->have_result = true;
+  return DLS_OK;
+}
+
+dls_status dls_range(const void* d_field, int32_t nvars, int64_t values_per_var, int32_t dtype,
+                     void* stream, double* min_out, double* max_out) {
+  if (d_field == nullptr || min_out == nullptr || max_out == nullptr) return fail(DLS_EINVAL, "NULL argument");
+  if (nvars < 1 || values_per_var < 1) return fail(DLS_EINVAL, "empty field");
+  if (dtype != DLS_F32 && dtype != DLS_F64) return fail(DLS_EINVAL, "bad dtype");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int nparts = int(std::min<int64_t>(1024, (values_per_var + 255) / 256));
+  DevBuf part, out;
+  HIP_TRY(part.ensure(size_t(nvars) * nparts * 2 * sizeof(double)));
+  HIP_TRY(out.ensure(size_t(nvars) * 2 * sizeof(double)));
+  HIP_TRY(launch_range(dtype, d_field, nvars, values_per_var, part.as<double>(), nparts, out.as<double>(), s));
+  std::vector<double> h(2 * size_t(nvars));
+  HIP_TRY(hipMemcpyAsync(h.data(), out.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int v = 0; v < nvars; ++v) {
+    min_out[v] = h[2 * v];
+    max_out[v] = h[2 * v + 1];
+  }
   return DLS_OK;
 }
 
@@ -343,7 +386,7 @@ dls_status dls_encode_info_get(const dls_ctx* ctx, dls_encode_info* info) {
   info->d_code_off = ctx->code_off.as<int64_t>();
   info->d_coef = ctx->keep_coef ? ctx->coef.as<float>() : nullptr;
   info->gpu_ms = ctx->gpu_ms;
-  for (int i = 0; i < 4; ++i) info->stage_ms[i] = ctx->stage_ms[i];
+  for (int i = 0; i < 5; ++i) info->stage_ms[i] = ctx->stage_ms[i];
   return DLS_OK;
 }
 

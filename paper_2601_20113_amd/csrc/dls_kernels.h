@@ -31,16 +31,28 @@ hipError_t launch_eigen(int wp, const double* gpart, const int32_t* item_start, 
                         double* basis, int64_t* qv_size, int64_t* qa_size, unsigned long long* nraw,
                         hipStream_t s);
 hipError_t launch_scan(const int64_t* in, int64_t n, int64_t* out, int64_t* tmp, hipStream_t s);
-hipError_t launch_encode(int wp, int dtype, const void* F, const Dims& dims, const BlockDesc* desc,
-                         const Item* items, int64_t nitems, const uint8_t* rank, const double* basis,
-                         const int64_t* qv_off, const int64_t* qa_off, const int64_t* code_off,
-                         const VarConst* vc, uint8_t* qv, uint8_t* qa, uint8_t* codes, float* coef,
-                         EscOut esc, hipStream_t s);
+hipError_t launch_range(int dtype, const void* F, int nvars, int64_t n_per_var, double* part, int nparts,
+                        double* out, hipStream_t s);
+constexpr int kRankClasses = 6;  // r <= 1, 2, 4, 8, 16, 32
+hipError_t launch_classify(const Item* items, int64_t nitems, const uint8_t* rank, unsigned int* counts,
+                           int32_t* lists, hipStream_t s);
+hipError_t launch_encode(int wp, int dtype, int cls, const void* F, const Dims& dims, const BlockDesc* desc,
+                         const Item* items, const int32_t* list, int64_t count, const uint8_t* rank,
+                         const double* basis, const int64_t* qv_off, const int64_t* qa_off,
+                         const int64_t* code_off, const VarConst* vc, uint8_t* qv, uint8_t* qa,
+                         uint8_t* codes, float* coef, EscOut esc, hipStream_t s);
 hipError_t launch_decode(int wp, int dtype, void* F, const Dims& dims, const BlockDesc* desc,
                          const Item* items, int64_t nitems, const uint8_t* rank, const int64_t* qv_off,
                          const int64_t* qa_off, const int64_t* code_off, const VarConst* vc,
                          const uint8_t* qv, const uint8_t* qa, const uint8_t* codes, hipStream_t s);
 hipError_t launch_scatter(int dtype, void* F, const int64_t* idx, const uint64_t* bits, int64_t n,
                           hipStream_t s);
+
+struct PlanScratch;
+PlanScratch* plan_scratch_new();
+void plan_scratch_delete(PlanScratch* s);
+// Adaptive leaves and split bits of every variable (see dls_plan.hip).
+hipError_t adaptive_plan(const Problem& p, const void* F, hipStream_t s, PlanScratch& scratch, Plan& plan,
+                         std::string& err);
 
 }  // namespace dls

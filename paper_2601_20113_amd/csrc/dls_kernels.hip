@@ -411,10 +411,13 @@ __device__ __forceinline__ void store_bytes(uint8_t* __restrict__ dst, const uin
   }
 }
 
-template <int WP, typename T, int PPT>
+// RMAX is the rank class of the launch (every block in it has r <= RMAX), so
+// the per-point coefficient registers are sized for the class, not for W.
+template <int WP, typename T, int PPT, int RMAX>
 __global__ __launch_bounds__(256) void k_encode(const T* __restrict__ F, Dims dims,
                                                 const BlockDesc* __restrict__ desc,
                                                 const Item* __restrict__ items,
+                                                const int32_t* __restrict__ item_list,
                                                 const uint8_t* __restrict__ rank,
                                                 const double* __restrict__ basis,
                                                 const int64_t* __restrict__ qv_off,
@@ -426,17 +429,16 @@ __global__ __launch_bounds__(256) void k_encode(const T* __restrict__ F, Dims di
                                                 uint8_t* __restrict__ codes,
                                                 float* __restrict__ coef,
                                                 EscOut esc) {
-  constexpr int RMAX = WP;
-  __shared__ float Vf[WP][WP];    // [k][t]
-  __shared__ double Qv[WP][WP];   // [t][k], integer valued
-  const Item it = items[blockIdx.x];
+  __shared__ float Vf[RMAX][WP];    // [k][t]
+  __shared__ double Qv[WP][RMAX];   // [t][k], integer valued
+  const Item it = items[item_list[blockIdx.x]];
   const int b = it.block;
   const BlockDesc d = desc[b];
   const int W = d.w(), M = d.m, r = rank[b];
   const VarConst K = vc[d.var];
   const int64_t wm_pad = pad16(int64_t(W) * M);
 
-  for (int idx = threadIdx.x; idx < WP * WP; idx += blockDim.x) {
+  for (int idx = threadIdx.x; idx < RMAX * WP; idx += blockDim.x) {
     const int k = idx / WP, t = idx % WP;
     const double v = basis[int64_t(b) * WP * WP + idx];
     const double qv = rint(v * 65536.0);
@@ -692,6 +694,101 @@ __global__ __launch_bounds__(256) void k_scatter(T* __restrict__ F, const int64_
 }
 
 // ---------------------------------------------------------------------------
+// Per-variable value range (min, max) in FP64: grid-stride partials, then one
+// workgroup folds the partials.  Non-finite values are skipped.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_range_partial(const T* __restrict__ F, int64_t n_per_var,
+                                                       double* __restrict__ part) {
+  const int v = blockIdx.y;
+  const T* base = F + int64_t(v) * n_per_var;
+  double lo = INFINITY, hi = -INFINITY;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n_per_var; i += int64_t(gridDim.x) * 256) {
+    const double x = double(base[i]);
+    if (isfinite(x)) {
+      lo = fmin(lo, x);
+      hi = fmax(hi, x);
+    }
+  }
+  __shared__ double slo[256], shi[256];
+  slo[threadIdx.x] = lo;
+  shi[threadIdx.x] = hi;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      slo[threadIdx.x] = fmin(slo[threadIdx.x], slo[threadIdx.x + o]);
+      shi[threadIdx.x] = fmax(shi[threadIdx.x], shi[threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * (int64_t(v) * gridDim.x + blockIdx.x)] = slo[0];
+    part[2 * (int64_t(v) * gridDim.x + blockIdx.x) + 1] = shi[0];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_range_final(const double* __restrict__ part, int nparts,
+                                                     double* __restrict__ out) {
+  const int v = blockIdx.x;
+  double lo = INFINITY, hi = -INFINITY;
+  for (int i = threadIdx.x; i < nparts; i += 256) {
+    lo = fmin(lo, part[2 * (int64_t(v) * nparts + i)]);
+    hi = fmax(hi, part[2 * (int64_t(v) * nparts + i) + 1]);
+  }
+  __shared__ double slo[256], shi[256];
+  slo[threadIdx.x] = lo;
+  shi[threadIdx.x] = hi;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      slo[threadIdx.x] = fmin(slo[threadIdx.x], slo[threadIdx.x + o]);
+      shi[threadIdx.x] = fmax(shi[threadIdx.x], shi[threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * v] = slo[0];
+    out[2 * v + 1] = shi[0];
+  }
+}
+
+hipError_t launch_range(int dtype, const void* F, int nvars, int64_t n_per_var, double* part, int nparts,
+                        double* out, hipStream_t s) {
+  const dim3 g{unsigned(nparts), unsigned(nvars)}, bl{256};
+  if (dtype == 0) hipLaunchKernelGGL(k_range_partial<float>, g, bl, 0, s, (const float*)F, n_per_var, part);
+  else hipLaunchKernelGGL(k_range_partial<double>, g, bl, 0, s, (const double*)F, n_per_var, part);
+  hipLaunchKernelGGL(k_range_final, dim3{unsigned(nvars)}, bl, 0, s, (const double*)part, nparts, out);
+  return hipGetLastError();
+}
+
+// Bucket the work items by the rank class of their block (one list per class,
+// order within a list is irrelevant: items write disjoint outputs).
+__device__ __forceinline__ int rank_class(int r) {
+  return r <= 1 ? 0 : r <= 2 ? 1 : r <= 4 ? 2 : r <= 8 ? 3 : r <= 16 ? 4 : 5;
+}
+
+__global__ __launch_bounds__(256) void k_classify(const Item* __restrict__ items, int64_t nitems,
+                                                  const uint8_t* __restrict__ rank,
+                                                  unsigned int* __restrict__ counts,
+                                                  int32_t* __restrict__ lists) {
+  // counts are aggregated per workgroup in LDS: one global atomic per class
+  __shared__ unsigned int lcount[8], lbase[8];
+  if (threadIdx.x < 8) lcount[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  int c = -1;
+  unsigned int lpos = 0;
+  if (i < nitems) {
+    c = rank_class(rank[items[i].block]);
+    lpos = atomicAdd(&lcount[c], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < 8 && lcount[threadIdx.x] > 0) lbase[threadIdx.x] = atomicAdd(counts + threadIdx.x, lcount[threadIdx.x]);
+  __syncthreads();
+  if (c >= 0) lists[int64_t(c) * nitems + lbase[c] + lpos] = int32_t(i);
+}
+
+// ---------------------------------------------------------------------------
 // Launch wrappers
 // ---------------------------------------------------------------------------
 hipError_t launch_gram(int wp, int dtype, const void* F, const Dims& dims, const BlockDesc* desc,
@@ -733,21 +830,52 @@ hipError_t launch_scan(const int64_t* in, int64_t n, int64_t* out, int64_t* tmp,
   return hipGetLastError();
 }
 
-hipError_t launch_encode(int wp, int dtype, const void* F, const Dims& dims, const BlockDesc* desc,
-                         const Item* items, int64_t nitems, const uint8_t* rank, const double* basis,
-                         const int64_t* qv_off, const int64_t* qa_off, const int64_t* code_off,
-                         const VarConst* vc, uint8_t* qv, uint8_t* qa, uint8_t* codes, float* coef,
-                         EscOut esc, hipStream_t s) {
+hipError_t launch_classify(const Item* items, int64_t nitems, const uint8_t* rank, unsigned int* counts,
+                           int32_t* lists, hipStream_t s) {
   if (nitems == 0) return hipSuccess;
-  const dim3 g{unsigned(nitems)}, bl{256};
+  const dim3 g{unsigned((nitems + 255) / 256)}, bl{256};
+  hipLaunchKernelGGL(k_classify, g, bl, 0, s, items, nitems, rank, counts, lists);
+  return hipGetLastError();
+}
+
+template <int WP, typename T, int PPT>
+static void encode_class(int cls, const dim3& g, hipStream_t s, const T* F, const Dims& dims,
+                         const BlockDesc* desc, const Item* items, const int32_t* list, const uint8_t* rank,
+                         const double* basis, const int64_t* qv_off, const int64_t* qa_off,
+                         const int64_t* code_off, const VarConst* vc, uint8_t* qv, uint8_t* qa,
+                         uint8_t* codes, float* coef, EscOut esc) {
+  const dim3 bl{256};
+#define DLS_ENC(R)                                                                                       \
+  hipLaunchKernelGGL((k_encode<WP, T, PPT, R>), g, bl, 0, s, F, dims, desc, items, list, rank, basis,  \
+                     qv_off, qa_off, code_off, vc, qv, qa, codes, coef, esc)
+  switch (cls) {
+    case 0: DLS_ENC(1); break;
+    case 1: DLS_ENC(2); break;
+    case 2: DLS_ENC(4); break;
+    case 3: DLS_ENC(8); break;
+    case 4: DLS_ENC(16); break;
+    default:
+      if constexpr (WP == 32) DLS_ENC(32);
+      break;
+  }
+#undef DLS_ENC
+}
+
+hipError_t launch_encode(int wp, int dtype, int cls, const void* F, const Dims& dims, const BlockDesc* desc,
+                         const Item* items, const int32_t* list, int64_t count, const uint8_t* rank,
+                         const double* basis, const int64_t* qv_off, const int64_t* qa_off,
+                         const int64_t* code_off, const VarConst* vc, uint8_t* qv, uint8_t* qa,
+                         uint8_t* codes, float* coef, EscOut esc, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  const dim3 g{unsigned(count)};
   if (wp == 16 && dtype == 0)
-    hipLaunchKernelGGL((k_encode<16, float, 4>), g, bl, 0, s, (const float*)F, dims, desc, items, rank, basis, qv_off, qa_off, code_off, vc, qv, qa, codes, coef, esc);
+    encode_class<16, float, 4>(cls, g, s, (const float*)F, dims, desc, items, list, rank, basis, qv_off, qa_off, code_off, vc, qv, qa, codes, coef, esc);
   else if (wp == 16)
-    hipLaunchKernelGGL((k_encode<16, double, 2>), g, bl, 0, s, (const double*)F, dims, desc, items, rank, basis, qv_off, qa_off, code_off, vc, qv, qa, codes, coef, esc);
+    encode_class<16, double, 2>(cls, g, s, (const double*)F, dims, desc, items, list, rank, basis, qv_off, qa_off, code_off, vc, qv, qa, codes, coef, esc);
   else if (dtype == 0)
-    hipLaunchKernelGGL((k_encode<32, float, 2>), g, bl, 0, s, (const float*)F, dims, desc, items, rank, basis, qv_off, qa_off, code_off, vc, qv, qa, codes, coef, esc);
+    encode_class<32, float, 2>(cls, g, s, (const float*)F, dims, desc, items, list, rank, basis, qv_off, qa_off, code_off, vc, qv, qa, codes, coef, esc);
   else
-    hipLaunchKernelGGL((k_encode<32, double, 2>), g, bl, 0, s, (const double*)F, dims, desc, items, rank, basis, qv_off, qa_off, code_off, vc, qv, qa, codes, coef, esc);
+    encode_class<32, double, 2>(cls, g, s, (const double*)F, dims, desc, items, list, rank, basis, qv_off, qa_off, code_off, vc, qv, qa, codes, coef, esc);
   return hipGetLastError();
 }
 

@@ -57,11 +57,38 @@ def _case(name):
         e = 1e-4 * synth.range_of(f)
         return f, odls.Params(nx=24, ny=20, nz=16, nt=30, nvars=1, dtype="f64", px=8, py=8, pz=8,
                               window=12, eps=list(e))
+    if name == "adaptive_quad_f32_96x80x20":
+        f = synth.blobs2d(nx=96, ny=80, nt=20, seed=6, nblobs=12, dtype=np.float32)
+        e = 1e-3 * synth.range_of(f)
+        return f, odls.Params(nx=96, ny=80, nz=1, nt=20, nvars=1, dtype="f32", px=32, py=32, pz=1,
+                              window=16, eps=list(e), pmin=4, adaptive=True)
+    if name == "adaptive_oct_f64_2var":
+        f = np.concatenate([_bumps3d(36, 28, 20, 12, seed=s) for s in (1, 2)])
+        e = [1e-3 * r for r in synth.range_of(f)]
+        return f, odls.Params(nx=36, ny=28, nz=20, nt=12, nvars=2, dtype="f64", px=16, py=16, pz=16,
+                              window=8, eps=e, pmin=4, adaptive=True)
     raise KeyError(name)
 
 
+def _bumps3d(nx, ny, nz, nt, seed):
+    """Smooth background plus three narrow moving 3D bumps (refines locally)."""
+    rng = np.random.default_rng(seed)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    c = rng.uniform(0, 1, (3, 3)) * [nx, ny, nz]
+    w = rng.uniform(1.5, 3.0, 3)
+    out = np.zeros((1, nt, nz, ny, nx))
+    for t in range(nt):
+        f = 0.05 * np.sin(0.05 * x + 0.03 * y + 0.02 * z + 0.1 * t)
+        for b in range(3):
+            d2 = (x - c[b, 0] - 0.3 * t) ** 2 + (y - c[b, 1]) ** 2 + (z - c[b, 2]) ** 2
+            f = f + np.exp(-d2 / (2 * w[b] ** 2))
+        out[0, t] = f
+    return out + 1e-4 * rng.normal(size=out.shape)
+
+
 CASES = ["c1_64x64x32_f64", "ragged_70x45x37_f64", "blobs_f32_96x64x20",
-         "spec3d_f32_w32_2var", "spec3d_f64_w12"]
+         "spec3d_f32_w32_2var", "spec3d_f64_w12", "adaptive_quad_f32_96x80x20",
+         "adaptive_oct_f64_2var"]
 
 
 @pytest.mark.parametrize("name", CASES)
@@ -149,3 +176,31 @@ def test_tiny_bound_escapes_exact():
     out = dls.decompress(g.stream).cpu().numpy()
     assert np.all(np.abs(out.astype(np.float64) - f.astype(np.float64)) <= 1e-5)
     assert np.array_equal(odls.decompress(g.stream).view(np.uint8), out.view(np.uint8))
+
+
+def test_value_range_matches_numpy():
+    f = synth.blobs2d(nx=50, ny=30, nt=9, seed=8, dtype=np.float32)
+    g = np.concatenate([f, 3 * f - 1.0])
+    g[1, 2, 0, 3, 4] = np.nan
+    lo, hi = dls.value_range(torch.from_numpy(g).cuda())
+    for v in range(2):
+        x = g[v][np.isfinite(g[v])].astype(np.float64)
+        assert lo[v] == x.min() and hi[v] == x.max()
+
+
+@pytest.mark.parametrize("name", ["adaptive_quad_f32_96x80x20", "adaptive_oct_f64_2var"])
+def test_adaptive_plan_matches_oracle(name):
+    """Split bits and the block list (origins, extents, windows) are identical."""
+    f, p = _case(name)
+    enc = odls.encode(f, p)
+    g = H.GpuRun(f, p)
+    _, bits, nb, _, _ = container.parse_header(g.stream)
+    assert bits == enc.split_bits
+    assert sum(enc.split_bits[0]) > 0
+    inf = g.enc.info()
+    desc = dls.d2h(inf.d_desc, nb * 32).view(np.int32).reshape(nb, 8)
+    for b, blk in enumerate(enc.blocks):
+        ext = desc[b, 4]
+        got = (desc[b, 0], desc[b, 1], desc[b, 2], desc[b, 3], ext & 255, (ext >> 8) & 255,
+               (ext >> 16) & 255, (ext >> 24) & 255, desc[b, 5])
+        assert got == (blk.x0, blk.y0, blk.z0, blk.t0, blk.px, blk.py, blk.pz, blk.w, blk.var)

@@ -20,3 +20,11 @@ def test_gpu_spectrum_matches_numpy(drift):
     sg.spectrum_into(t32, seed=11, nmodes=16, drift=drift)
     ref32 = synth.spectrum(24, 20, 12, 5, nmodes=16, seed=11, drift=drift, dtype=np.float32)[0]
     assert np.mean(t32.cpu().numpy() == ref32) > 0.999
+
+
+def test_gpu_blobs_match_numpy():
+    from synth import gpu as sg
+    ref = synth.blobs2d_truncated(150, 90, 4, nblobs=30, seed=3, dtype=np.float64)[0]
+    t = torch.empty((4, 1, 90, 150), dtype=torch.float64, device="cuda")
+    sg.blobs_into(t, nblobs=30, seed=3)
+    assert np.abs(t.cpu().numpy() - ref).max() <= 1e-12

@@ -61,11 +61,14 @@ typedef enum { DLS_PREC_FP32 = 0, DLS_PREC_BF16 = 1 } dls_precision;
 
 /* dls_params.flags */
 enum {
-  DLS_ADAPTIVE = 1   /* quadtree (2D) / octree (3D) patches between pmin and
+  DLS_ADAPTIVE = 1,  /* quadtree (2D) / octree (3D) patches between pmin and
                         px, computed per variable from snapshot 0: a node
                         of edge e > pmin splits into its half-edge children
                         while its mean gradient magnitude exceeds the 80th
                         percentile sorted(g)[floor(0.8 (n-1))]             */
+  DLS_LEARNED = 2    /* warm-started eigensolve with the model attached by
+                        dls_ctx_set_model (window <= 16); blocks whose
+                        prediction fails the rank test fall back to Jacobi */
 };
 
 typedef struct dls_params {
@@ -107,6 +110,8 @@ typedef struct dls_encode_info {
   const int64_t* d_code_off;/* [nblocks]                                    */
   const float* d_coef;      /* [sum M_b r_b] FP32 coefficients A[k][p] at
                                d_qa_off[b]/4 when requested, else NULL      */
+  int64_t nwarm_accept;     /* DLS_LEARNED: blocks solved by the warm start  */
+  int64_t nwarm_reject;     /* DLS_LEARNED: blocks that fell back to Jacobi   */
   double gpu_ms;            /* device time of the whole encode (HIP events) */
   double stage_ms[5];       /* HIP-event time of each stage on the caller's
                                stream: plan (adaptive: gradient, percentile,
@@ -176,6 +181,60 @@ typedef struct dls_stream_stats {
   int64_t stream_bytes;      /* whole stream                                */
 } dls_stream_stats;
 dls_status dls_stats(const uint8_t* in, size_t in_bytes, dls_stream_stats* s);
+
+/* ---- learned warm start ------------------------------------------------
+ * A small network (80 inputs -> 128 -> 128 -> 272 outputs, ReLU) maps the
+ * statistics of one block (dls_features) to 16 rank logits and a 16 x 16
+ * starting basis (outputs 16 + 16 k + t = V0[t][k]).  The encode path with
+ * DLS_LEARNED runs `iters` steps of subspace iteration from the first rhat
+ * predicted columns, a Rayleigh-Ritz step, and keeps the smallest rank whose
+ * discarded energy meets the local tolerance (Sec. 2.4 Eq. (4)); otherwise
+ * the block falls back to the Jacobi eigensolve.  Training runs on the GPU:
+ * forward and backward products on the matrix cores (bf16 operands, FP32
+ * accumulation), loss = cross entropy of the rank + masked squared error of
+ * the basis columns k < r, t < W_b, Adam (lr, 0.9, 0.999, 1e-8).
+ *
+ * Parameters are one FP32 vector of DLS_MODEL_NPARAM values, row-major:
+ * W1 (80 x 128), b1 (128), W2 (128 x 128), b2 (128), W3 (128 x 272), b3 (272);
+ * the normalisation is 32 values: mean and standard deviation of the 16
+ * statistics (the 64 pooled inputs are already normalised). */
+#define DLS_MODEL_NPARAM 61968
+#define DLS_NFEAT 80
+#define DLS_NOUT 272
+typedef struct dls_model dls_model;
+/* Create a model on `device` with all parameters zero and identity
+ * normalisation; set them with dls_model_set. */
+dls_status dls_model_create(int device, dls_model** out);
+void dls_model_destroy(dls_model* m);
+/* Copy parameters (and, if norm != NULL, the 32 normalisation values) from
+ * host arrays; resets the Adam state.  DLS_EINVAL on NULL params. */
+dls_status dls_model_set(dls_model* m, const float* params, const float* norm);
+/* Copy parameters and normalisation to host arrays (either may be NULL). */
+dls_status dls_model_get(const dls_model* m, float* params, float* norm);
+/* Outputs (n x 272, device) of raw features (n x 80, device, as written by
+ * dls_features).  bf16 != 0: products with bfloat16 operands. */
+dls_status dls_model_forward(dls_model* m, const float* d_feat, int64_t n, int bf16, float* d_out,
+                             void* stream);
+/* Gradient (device, DLS_MODEL_NPARAM floats) and mean loss of one batch
+ * without updating: d_rank (n, 1..16), d_basis (n x 256, target V[k][t]),
+ * d_wb (n, window lengths).  *loss_out is written (host). */
+dls_status dls_model_grad(dls_model* m, const float* d_feat, const int32_t* d_rank, const float* d_basis,
+                          const int32_t* d_wb, int64_t n, int bf16, float* d_grad, float* loss_out,
+                          void* stream);
+/* One Adam step on one batch (same inputs as dls_model_grad). */
+dls_status dls_model_train_step(dls_model* m, const float* d_feat, const int32_t* d_rank,
+                                const float* d_basis, const int32_t* d_wb, int64_t n, float lr, int bf16,
+                                float* loss_out, void* stream);
+/* Raw features (nblocks x 80, device) of every block of the last dls_encode
+ * on ctx, computed from d_field (the same field):  16 statistics (mean,
+ * std, min, max, skewness, excess kurtosis, mean|dt|/std, std(dt)/std,
+ * mean|dx|/std, mean|dy|/std, lag-1 and lag-2 temporal autocorrelation,
+ * log10(mean x^2 / eps^2), log10(std / eps), time-mean energy fraction,
+ * log2 M) then the 8 x 8 pooled time-mean image (normalised). */
+dls_status dls_features(dls_ctx* ctx, const void* d_field, float* d_out, void* stream);
+/* Attach a model (NULL detaches) and the number of subspace iterations
+ * (>= 0) used by encodes with DLS_LEARNED on this context. */
+dls_status dls_ctx_set_model(dls_ctx* ctx, dls_model* m, int iters);
 
 /* Release a buffer returned by dls_finalize / dls_compress. */
 void dls_free(void* p);

@@ -354,7 +354,16 @@ def encode_block(xs: np.ndarray, eps: float, rcap: int, dtype) -> BlockCode:
     lam, V = eig_desc(G)                                          # step 4
     tau = KAPPA * eps * eps * m * wb
     r = choose_rank(lam, tau, min(rcap, wb, m))                   # step 5
-    Vr = V[:, :r]
+    code = encode_with_basis(xs, eps, V[:, :r], lam, tau, dtype)
+    code.V = V
+    return code
+
+
+def encode_with_basis(xs: np.ndarray, eps: float, Vr: np.ndarray, lam: np.ndarray, tau: float,
+                      dtype) -> BlockCode:
+    """Steps 6-9 for a chosen orthonormal basis V_r (W_b x r)."""
+    x = xs.astype(np.float64)
+    r = Vr.shape[1]
     A = x.T @ Vr                                                  # step 6 (M x r)
     qV = np.rint(Vr * float(1 << BASIS_BITS)).astype(np.int64)    # step 7
     qa_f = np.rint(A * (1.0 / eps))
@@ -373,7 +382,7 @@ def encode_block(xs: np.ndarray, eps: float, rcap: int, dtype) -> BlockCode:
     codes = zigzag16(qi)
     codes[esc] = ESC_CODE
     out = np.where(esc, xs, out)
-    return BlockCode(r, qV, qA, codes, xs[esc].copy(), lam=lam, V=V, A=A,
+    return BlockCode(r, qV, qA, codes, xs[esc].copy(), lam=lam, V=Vr, A=A,
                      tau=tau, out=out)
 
 

@@ -27,10 +27,14 @@ DLS_OK, DLS_EINVAL, DLS_ENOMEM, DLS_EDEVICE, DLS_ECORRUPT, DLS_EUNSUPPORTED = 0,
 DLS_F32, DLS_F64 = 0, 1
 DLS_PREC_FP32, DLS_PREC_BF16 = 0, 1
 DLS_ADAPTIVE = 1
+DLS_LEARNED = 2
+NPARAM = 61968
 
 EXPORTS = ["dls_ctx_create", "dls_ctx_destroy", "dls_encode", "dls_encode_info_get", "dls_range",
            "dls_finalize", "dls_compress", "dls_query", "dls_decompress", "dls_stats",
-           "dls_free", "dls_last_error"]
+           "dls_free", "dls_last_error", "dls_model_create", "dls_model_destroy", "dls_model_set",
+           "dls_model_get", "dls_model_forward", "dls_model_grad", "dls_model_train_step",
+           "dls_features", "dls_ctx_set_model"]
 
 
 class DlsError(RuntimeError):
@@ -56,7 +60,8 @@ class _EncodeInfo(ctypes.Structure):
                 ("qa_bytes", ctypes.c_int64), ("codes_bytes", ctypes.c_int64),
                 ("d_qa", ctypes.c_void_p), ("d_codes", ctypes.c_void_p),
                 ("d_qa_off", ctypes.c_void_p), ("d_code_off", ctypes.c_void_p),
-                ("d_coef", ctypes.c_void_p), ("gpu_ms", ctypes.c_double),
+                ("d_coef", ctypes.c_void_p), ("nwarm_accept", ctypes.c_int64),
+                ("nwarm_reject", ctypes.c_int64), ("gpu_ms", ctypes.c_double),
                 ("stage_ms", ctypes.c_double * 5)]
 
 
@@ -94,10 +99,25 @@ def lib():
         L.dls_stats.argtypes = [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(_StreamStats)]
         L.dls_range.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
                                 ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        vp = ctypes.c_void_p
+        L.dls_model_create.argtypes = [ctypes.c_int, c_void_pp]
+        L.dls_model_destroy.argtypes = [vp]
+        L.dls_model_destroy.restype = None
+        L.dls_model_set.argtypes = [vp, vp, vp]
+        L.dls_model_get.argtypes = [vp, vp, vp]
+        L.dls_model_forward.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int, vp, vp]
+        L.dls_model_grad.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int64, ctypes.c_int, vp,
+                                     ctypes.POINTER(ctypes.c_float), vp]
+        L.dls_model_train_step.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int64, ctypes.c_float, ctypes.c_int,
+                                           ctypes.POINTER(ctypes.c_float), vp]
+        L.dls_features.argtypes = [vp, vp, vp, vp]
+        L.dls_ctx_set_model.argtypes = [vp, vp, ctypes.c_int]
         L.dls_free.argtypes = [ctypes.c_void_p]
         L.dls_free.restype = None
         L.dls_last_error.restype = ctypes.c_char_p
-        for name in ("dls_ctx_create", "dls_encode", "dls_encode_info_get", "dls_finalize", "dls_range",
+        for name in ("dls_model_create", "dls_model_set", "dls_model_get", "dls_model_forward", "dls_model_grad",
+                     "dls_model_train_step", "dls_features", "dls_ctx_set_model",
+                     "dls_ctx_create", "dls_encode", "dls_encode_info_get", "dls_finalize", "dls_range",
                      "dls_compress", "dls_query", "dls_decompress", "dls_stats"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -127,6 +147,7 @@ class Params:
     r_max: int = 0
     precision: str = "fp32"   # "fp32" | "bf16"
     adaptive: bool = False
+    learned: bool = False
     _keep: list = dc_field(default_factory=list, repr=False)
 
     def to_c(self) -> _Params:
@@ -136,7 +157,7 @@ class Params:
                        DLS_F32 if self.dtype == "f32" else DLS_F64, self.px, self.py, self.pz,
                        self.pmin, self.window, self.r_max,
                        DLS_PREC_BF16 if self.precision == "bf16" else DLS_PREC_FP32,
-                       DLS_ADAPTIVE if self.adaptive else 0,
+                       (DLS_ADAPTIVE if self.adaptive else 0) | (DLS_LEARNED if self.learned else 0),
                        ctypes.cast(arr, ctypes.POINTER(ctypes.c_double)))
 
     @property
@@ -187,6 +208,19 @@ class Encoder:
         cp = p.to_c()
         _check(lib().dls_encode(self._h, ctypes.c_void_p(field.data_ptr()), ctypes.byref(cp),
                                 _stream_handle(stream), 1 if keep_coef else 0))
+
+    def set_model(self, model: "Model", iters: int = 2):
+        """Attach a model for encodes with learned=True (None detaches)."""
+        self._model = model
+        _check(lib().dls_ctx_set_model(self._h, model._h if model is not None else None, iters))
+
+    def features(self, field: torch.Tensor, stream=None) -> torch.Tensor:
+        """Raw features (nblocks x 80) of the blocks of the last encode."""
+        nb = self.info().nblocks
+        out = torch.empty((nb, 80), dtype=torch.float32, device=field.device)
+        _check(lib().dls_features(self._h, ctypes.c_void_p(field.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                  _stream_handle(stream)))
+        return out
 
     def info(self) -> _EncodeInfo:
         inf = _EncodeInfo()
@@ -277,3 +311,72 @@ def d2h(ptr: int, nbytes: int):
         if st != 0:
             raise RuntimeError("hipMemcpy failed: %d" % st)
     return out[:int(nbytes)]
+
+
+def d2d(dst: torch.Tensor, ptr: int, nbytes: int):
+    """Copy nbytes of device memory at ptr (from Encoder.info()) into dst."""
+    d2h(0, 0)  # loads the runtime handle
+    st = _hiplib.hipMemcpy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(ptr), int(nbytes), 3)
+    if st != 0:
+        raise RuntimeError("hipMemcpy failed: %d" % st)
+    return dst
+
+
+class Model:
+    """The warm-start network on a device (parameters, Adam state)."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().dls_model_create(device, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if self._h:
+            lib().dls_model_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set(self, params, norm=None):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == NPARAM
+        n = None if norm is None else np.ascontiguousarray(norm, dtype=np.float32)
+        _check(lib().dls_model_set(self._h, ctypes.c_void_p(p.ctypes.data),
+                                   None if n is None else ctypes.c_void_p(n.ctypes.data)))
+
+    def get(self):
+        import numpy as np
+        p = np.empty(NPARAM, np.float32)
+        n = np.empty(32, np.float32)
+        _check(lib().dls_model_get(self._h, ctypes.c_void_p(p.ctypes.data), ctypes.c_void_p(n.ctypes.data)))
+        return p, n
+
+    def forward(self, feat: torch.Tensor, bf16: bool = True, stream=None) -> torch.Tensor:
+        feat = feat.contiguous()
+        out = torch.empty((feat.shape[0], 272), dtype=torch.float32, device=feat.device)
+        _check(lib().dls_model_forward(self._h, ctypes.c_void_p(feat.data_ptr()), feat.shape[0], int(bf16),
+                                       ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+        return out
+
+    def grad(self, feat, rank, basis, wb, bf16: bool = False, stream=None):
+        g = torch.empty(NPARAM, dtype=torch.float32, device=feat.device)
+        loss = ctypes.c_float()
+        _check(lib().dls_model_grad(self._h, ctypes.c_void_p(feat.data_ptr()), ctypes.c_void_p(rank.data_ptr()),
+                                    ctypes.c_void_p(basis.data_ptr()), ctypes.c_void_p(wb.data_ptr()),
+                                    feat.shape[0], int(bf16), ctypes.c_void_p(g.data_ptr()), ctypes.byref(loss),
+                                    _stream_handle(stream)))
+        return g, loss.value
+
+    def train_step(self, feat, rank, basis, wb, lr: float = 1e-3, bf16: bool = True, want_loss: bool = True,
+                   stream=None):
+        loss = ctypes.c_float()
+        _check(lib().dls_model_train_step(self._h, ctypes.c_void_p(feat.data_ptr()),
+                                          ctypes.c_void_p(rank.data_ptr()), ctypes.c_void_p(basis.data_ptr()),
+                                          ctypes.c_void_p(wb.data_ptr()), feat.shape[0], lr, int(bf16),
+                                          ctypes.byref(loss) if want_loss else None, _stream_handle(stream)))
+        return loss.value if want_loss else None

@@ -18,7 +18,7 @@ HIP_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-pass-failed",
 ]
-HIP_SOURCES = ["dls_kernels.hip", "dls_plan.hip", "dls_api.hip"]
+HIP_SOURCES = ["dls_kernels.hip", "dls_plan.hip", "dls_learned.hip", "dls_api.hip"]
 CXX_SOURCES = ["dls_format.cpp"]
 
 

@@ -11,6 +11,8 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
+#include <cstdio>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -109,7 +111,8 @@ dls_status validate(const dls_params* in, Problem& p) {
   if (p.nz == 1 && p.pz != 1) return fail(DLS_EINVAL, "pz must be 1 for a 2D field");
   if (in->r_max < 0 || in->r_max > 32) return fail(DLS_EINVAL, "r_max must be in [0, 32]");
   p.r_max = in->r_max > 0 ? in->r_max : std::min(p.window, 32);
-  if (p.flags & ~uint32_t(DLS_ADAPTIVE)) return fail(DLS_EINVAL, "unknown flags");
+  if (p.flags & ~uint32_t(DLS_ADAPTIVE | DLS_LEARNED)) return fail(DLS_EINVAL, "unknown flags");
+  if ((p.flags & DLS_LEARNED) && p.window > 16) return fail(DLS_EINVAL, "DLS_LEARNED needs window <= 16");
   if (p.precision != DLS_PREC_FP32 && p.precision != DLS_PREC_BF16)
     return fail(DLS_EINVAL, "unknown precision");
   if (p.flags & DLS_ADAPTIVE) {
@@ -147,6 +150,83 @@ bool same_layout(const Problem& a, const Problem& b) {
 
 }  // namespace
 
+struct dls_model {
+  int device = 0;
+  DevBuf params, norm, m, v, grad;
+  int64_t step = 0;
+  DevBuf z, h1, h2, out, gout, dh2, dh1, loss;  // workspace for a batch
+  int64_t ws_n = 0;
+};
+
+namespace {
+constexpr int kNF = 80, kH = 128, kNO = 272;
+constexpr int64_t kOffW1 = 0, kOffb1 = 80 * 128, kOffW2 = kOffb1 + 128, kOffb2 = kOffW2 + 128 * 128,
+                  kOffW3 = kOffb2 + 128, kOffb3 = kOffW3 + 128 * 272, kNParam = kOffb3 + 272;
+static_assert(kNParam == DLS_MODEL_NPARAM, "parameter count");
+
+dls_status model_workspace(dls_model* m, int64_t n) {
+  if (n <= m->ws_n) return DLS_OK;
+  HIP_TRY(m->z.ensure(size_t(n) * kNF * 4));
+  HIP_TRY(m->h1.ensure(size_t(n) * kH * 4));
+  HIP_TRY(m->h2.ensure(size_t(n) * kH * 4));
+  HIP_TRY(m->out.ensure(size_t(n) * kNO * 4));
+  HIP_TRY(m->gout.ensure(size_t(n) * kNO * 4));
+  HIP_TRY(m->dh2.ensure(size_t(n) * kH * 4));
+  HIP_TRY(m->dh1.ensure(size_t(n) * kH * 4));
+  HIP_TRY(m->loss.ensure(size_t(n) * 4));
+  m->ws_n = n;
+  return DLS_OK;
+}
+
+// forward pass into m->z, h1, h2, and `out` (n x 272)
+dls_status model_forward(dls_model* m, const float* feat, int64_t n, bool bf16, float* out, hipStream_t s) {
+  const float* P = m->params.as<float>();
+  HIP_TRY(launch_normalize(feat, n, m->norm.as<float>(), m->z.as<float>(), s));
+  HIP_TRY(launch_gemm(false, false, bf16, m->z.as<float>(), kNF, P + kOffW1, kH, m->h1.as<float>(), kH, int(n), kH,
+                      kNF, P + kOffb1, 1, s));
+  HIP_TRY(launch_gemm(false, false, bf16, m->h1.as<float>(), kH, P + kOffW2, kH, m->h2.as<float>(), kH, int(n), kH,
+                      kH, P + kOffb2, 1, s));
+  HIP_TRY(launch_gemm(false, false, bf16, m->h2.as<float>(), kH, P + kOffW3, kNO, out, kNO, int(n), kNO, kH,
+                      P + kOffb3, 0, s));
+  return DLS_OK;
+}
+
+// forward + loss + backward into m->grad; *loss_out = batch mean loss
+dls_status model_backprop(dls_model* m, const float* feat, const int32_t* rank, const float* basis, const int32_t* wb,
+                          int64_t n, bool bf16, float* loss_out, hipStream_t s) {
+  if (dls_status st = model_workspace(m, n)) return st;
+  if (dls_status st = model_forward(m, feat, n, bf16, m->out.as<float>(), s)) return st;
+  const float* P = m->params.as<float>();
+  float* G = m->grad.as<float>();
+  HIP_TRY(launch_loss(m->out.as<float>(), rank, basis, wb, n, m->gout.as<float>(), m->loss.as<float>(), s));
+  // dW3 = h2^T gout, db3 = colsum(gout), dh2 = gout W3^T * relu'(h2)
+  HIP_TRY(launch_gemm(true, false, bf16, m->h2.as<float>(), kH, m->gout.as<float>(), kNO, G + kOffW3, kNO, kH, kNO,
+                      int(n), nullptr, 0, s));
+  HIP_TRY(launch_colsum(m->gout.as<float>(), n, kNO, G + kOffb3, s));
+  HIP_TRY(launch_gemm(false, true, bf16, m->gout.as<float>(), kNO, P + kOffW3, kNO, m->dh2.as<float>(), kH, int(n), kH,
+                      kNO, nullptr, 0, s));
+  HIP_TRY(launch_relu_mask(m->dh2.as<float>(), m->h2.as<float>(), n * kH, s));
+  HIP_TRY(launch_gemm(true, false, bf16, m->h1.as<float>(), kH, m->dh2.as<float>(), kH, G + kOffW2, kH, kH, kH, int(n),
+                      nullptr, 0, s));
+  HIP_TRY(launch_colsum(m->dh2.as<float>(), n, kH, G + kOffb2, s));
+  HIP_TRY(launch_gemm(false, true, bf16, m->dh2.as<float>(), kH, P + kOffW2, kH, m->dh1.as<float>(), kH, int(n), kH,
+                      kH, nullptr, 0, s));
+  HIP_TRY(launch_relu_mask(m->dh1.as<float>(), m->h1.as<float>(), n * kH, s));
+  HIP_TRY(launch_gemm(true, false, bf16, m->z.as<float>(), kNF, m->dh1.as<float>(), kH, G + kOffW1, kH, kNF, kH, int(n),
+                      nullptr, 0, s));
+  HIP_TRY(launch_colsum(m->dh1.as<float>(), n, kH, G + kOffb1, s));
+  if (loss_out != nullptr) {
+    std::vector<float> l(n);
+    HIP_TRY(hipMemcpyAsync(l.data(), m->loss.p, size_t(n) * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double sum = 0.0;
+    for (float v : l) sum += v;
+    *loss_out = float(sum / double(n));
+  }
+  return DLS_OK;
+}
+}  // namespace
+
 struct dls_ctx {
   int device = 0;
   Problem prob;
@@ -159,6 +239,12 @@ struct dls_ctx {
   hipEvent_t evs[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // gram, eigen, scan ends; encode start; plan start
   double stage_ms[5] = {0, 0, 0, 0, 0};
   PlanScratch* plan_scratch = nullptr;
+  dls_model* model = nullptr;  // DLS_LEARNED
+  int warm_iters = 2;
+  DevBuf feat, zfeat, mlp_h1, mlp_h2, mlp_out, reject;
+  int64_t nwarm_accept = 0, nwarm_reject = 0;
+  void* pinned = nullptr;      // host staging for plan uploads
+  size_t pinned_bytes = 0;
   uint64_t esc_cap = 0;
   // results of the last dls_encode
   bool have_result = false;
@@ -171,8 +257,38 @@ struct dls_ctx {
     for (auto& e : evs)
       if (e) (void)hipEventDestroy(e);
     plan_scratch_delete(plan_scratch);
+    if (pinned) (void)hipHostFree(pinned);
   }
 };
+
+namespace {
+// Eigen stage of a DLS_LEARNED encode: features, network forward (bf16),
+// warm-started eigensolve, Jacobi on the rejected blocks.
+dls_status learned_eigen(dls_ctx* ctx, const void* d_field, const Problem& p, const Dims& dims, hipStream_t s) {
+  dls_model* m = ctx->model;
+  if (m == nullptr) return fail(DLS_EINVAL, "DLS_LEARNED without a model (dls_ctx_set_model)");
+  if (m->device != ctx->device) return fail(DLS_EINVAL, "model lives on another device");
+  const int64_t nb = int64_t(ctx->plan.blocks.size());
+  unsigned long long* cnt = ctx->counters.as<unsigned long long>();
+  HIP_TRY(ctx->feat.ensure(size_t(nb) * kNF * 4));
+  HIP_TRY(ctx->mlp_out.ensure(size_t(nb) * kNO * 4));
+  HIP_TRY(ctx->reject.ensure(size_t(nb)));
+  if (dls_status st = model_workspace(m, nb)) return st;
+  HIP_TRY(launch_features(p.dtype, d_field, dims, ctx->desc.as<BlockDesc>(), nb, ctx->eps_v.as<double>(),
+                          ctx->feat.as<float>(), s));
+  if (dls_status st = model_forward(m, ctx->feat.as<float>(), nb, true, ctx->mlp_out.as<float>(), s)) return st;
+  HIP_TRY(launch_warmstart(ctx->gram.as<double>(), ctx->item_start.as<int32_t>(), ctx->desc.as<BlockDesc>(), nb,
+                           ctx->eps_v.as<double>(), p.r_max, ctx->mlp_out.as<float>(), ctx->warm_iters,
+                           ctx->rank.as<uint8_t>(), ctx->lam.as<double>(), ctx->basis.as<double>(),
+                           ctx->qv_size.as<int64_t>(), ctx->qa_size.as<int64_t>(), ctx->reject.as<uint8_t>(),
+                           cnt + 2, s));
+  HIP_TRY(launch_eigen(16, ctx->gram.as<double>(), ctx->item_start.as<int32_t>(), ctx->desc.as<BlockDesc>(), nb,
+                       ctx->eps_v.as<double>(), p.r_max, ctx->rank.as<uint8_t>(), ctx->lam.as<double>(),
+                       ctx->basis.as<double>(), ctx->qv_size.as<int64_t>(), ctx->qa_size.as<int64_t>(), cnt + 1,
+                       ctx->reject.as<uint8_t>(), s));
+  return DLS_OK;
+}
+}  // namespace
 
 extern "C" {
 
@@ -217,15 +333,21 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
   HIP_TRY(hipEventRecord(ctx->evs[4], s));
   const bool adaptive = (p.flags & DLS_ADAPTIVE) != 0;
   if (adaptive) {
-    // the adaptive plan depends on snapshot 0, so it is rebuilt on every call
-    ctx->plan_valid = false;
-    ctx->plan = Plan();
+    // the adaptive plan depends on snapshot 0, so it is recomputed on every
+    // call; the block list is expanded and uploaded again only when the new
+    // split bits differ from those of the resident plan
+    Plan fresh;
     std::string err;
-    hipError_t he = adaptive_plan(p, d_field, s, *ctx->plan_scratch, ctx->plan, err);
+    hipError_t he = adaptive_plan(p, d_field, s, *ctx->plan_scratch, fresh, err);
     if (he != hipSuccess) return fail(he == hipErrorOutOfMemory ? DLS_ENOMEM : DLS_EDEVICE, "adaptive plan: " + err);
+    if (!(ctx->plan_valid && same_layout(ctx->prob, p) && fresh.bits == ctx->plan.bits)) {
+      ctx->plan_valid = false;
+      ctx->plan = std::move(fresh);
+    }
   }
 
   // plan: uniform tiling depends on the problem statement only, so it is cached
+  const auto th0 = std::chrono::steady_clock::now();
   if (!ctx->plan_valid || !same_layout(ctx->prob, p)) {
     ctx->plan_valid = false;
     if (!adaptive) {
@@ -240,11 +362,32 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
     HIP_TRY(ctx->items.ensure(pl.items.size() * sizeof(Item)));
     HIP_TRY(ctx->item_start.ensure(pl.item_start.size() * sizeof(int32_t)));
     HIP_TRY(ctx->code_off.ensure(pl.code_off.size() * sizeof(int64_t)));
-    HIP_TRY(hipMemcpy(ctx->desc.p, pl.blocks.data(), pl.blocks.size() * sizeof(BlockDesc), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(ctx->items.p, pl.items.data(), pl.items.size() * sizeof(Item), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(ctx->item_start.p, pl.item_start.data(), pl.item_start.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(ctx->code_off.p, pl.code_off.data(), pl.code_off.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    // one pinned staging buffer for the four plan arrays, then async copies
+    const size_t sz[4] = {pl.blocks.size() * sizeof(BlockDesc), pl.items.size() * sizeof(Item),
+                          pl.item_start.size() * sizeof(int32_t), pl.code_off.size() * sizeof(int64_t)};
+    const void* src[4] = {pl.blocks.data(), pl.items.data(), pl.item_start.data(), pl.code_off.data()};
+    void* dst[4] = {ctx->desc.p, ctx->items.p, ctx->item_start.p, ctx->code_off.p};
+    const size_t total = sz[0] + sz[1] + sz[2] + sz[3] + 64;
+    if (ctx->pinned_bytes < total) {
+      HIP_TRY(hipStreamSynchronize(s));
+      if (ctx->pinned) HIP_TRY(hipHostFree(ctx->pinned));
+      ctx->pinned = nullptr;
+      ctx->pinned_bytes = 0;
+      HIP_TRY(hipHostMalloc(&ctx->pinned, total, hipHostMallocDefault));
+      ctx->pinned_bytes = total;
+    }
+    HIP_TRY(hipStreamSynchronize(s));  // the staging buffer may still feed the previous call's copies
+    size_t o = 0;
+    for (int i = 0; i < 4; ++i) {
+      std::memcpy(static_cast<uint8_t*>(ctx->pinned) + o, src[i], sz[i]);
+      HIP_TRY(hipMemcpyAsync(dst[i], static_cast<uint8_t*>(ctx->pinned) + o, sz[i], hipMemcpyHostToDevice, s));
+      o += (sz[i] + 15) & ~size_t(15);
+    }
     ctx->plan_valid = true;
+    if (std::getenv("DLS_TIMING"))
+      std::fprintf(stderr, "[dls] blocks + upload %.3f ms (%zu blocks, %zu items)\n",
+                   std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - th0).count(),
+                   ctx->plan.blocks.size(), ctx->plan.items.size());
   }
   ctx->prob = p;
   const Plan& pl = ctx->plan;
@@ -262,7 +405,7 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
   HIP_TRY(ctx->qa_off.ensure(size_t(nb) * sizeof(int64_t)));
   HIP_TRY(ctx->scan_tmp.ensure(size_t(4 * (nb / 1024 + 4)) * sizeof(int64_t)));
   HIP_TRY(ctx->codes.ensure(size_t(pl.codes_bytes)));
-  HIP_TRY(ctx->counters.ensure(2 * sizeof(unsigned long long) + kRankClasses * sizeof(unsigned int)));
+  HIP_TRY(ctx->counters.ensure(4 * sizeof(unsigned long long) + kRankClasses * sizeof(unsigned int)));
   HIP_TRY(ctx->cls_lists.ensure(size_t(ni) * kRankClasses * sizeof(int32_t)));
   if (ctx->esc_cap == 0) {
     ctx->esc_cap = std::max<uint64_t>(uint64_t(1) << 20, uint64_t(p.values() / 256));
@@ -275,7 +418,7 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
   HIP_TRY(ctx->eps_v.ensure(p.eps.size() * sizeof(double)));
   HIP_TRY(hipMemcpyAsync(ctx->vconst.p, vc.data(), vc.size() * sizeof(VarConst), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(ctx->eps_v.p, p.eps.data(), p.eps.size() * sizeof(double), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemsetAsync(ctx->counters.p, 0, 2 * sizeof(unsigned long long) + kRankClasses * sizeof(unsigned int), s));
+  HIP_TRY(hipMemsetAsync(ctx->counters.p, 0, 4 * sizeof(unsigned long long) + kRankClasses * sizeof(unsigned int), s));
 
   const Dims dims{p.nx, p.ny, p.nz, p.nt};
   unsigned long long* cnt = ctx->counters.as<unsigned long long>();
@@ -283,14 +426,19 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
   HIP_TRY(launch_gram(wp, p.dtype, d_field, dims, ctx->desc.as<BlockDesc>(), ctx->items.as<Item>(), ni,
                       ctx->gram.as<double>(), s));
   HIP_TRY(hipEventRecord(ctx->evs[0], s));
-  HIP_TRY(launch_eigen(wp, ctx->gram.as<double>(), ctx->item_start.as<int32_t>(), ctx->desc.as<BlockDesc>(),
-                       nb, ctx->eps_v.as<double>(), p.r_max, ctx->rank.as<uint8_t>(), ctx->lam.as<double>(),
-                       ctx->basis.as<double>(), ctx->qv_size.as<int64_t>(), ctx->qa_size.as<int64_t>(),
-                       cnt + 1, s));
+  const bool learned = (p.flags & DLS_LEARNED) != 0;
+  if (learned) {
+    if (dls_status st = learned_eigen(ctx, d_field, p, dims, s)) return st;
+  } else {
+    HIP_TRY(launch_eigen(wp, ctx->gram.as<double>(), ctx->item_start.as<int32_t>(), ctx->desc.as<BlockDesc>(),
+                         nb, ctx->eps_v.as<double>(), p.r_max, ctx->rank.as<uint8_t>(), ctx->lam.as<double>(),
+                         ctx->basis.as<double>(), ctx->qv_size.as<int64_t>(), ctx->qa_size.as<int64_t>(),
+                         cnt + 1, nullptr, s));
+  }
   HIP_TRY(hipEventRecord(ctx->evs[1], s));
   HIP_TRY(launch_scan(ctx->qv_size.as<int64_t>(), nb, ctx->qv_off.as<int64_t>(), ctx->scan_tmp.as<int64_t>(), s));
   HIP_TRY(launch_scan(ctx->qa_size.as<int64_t>(), nb, ctx->qa_off.as<int64_t>(), ctx->scan_tmp.as<int64_t>(), s));
-  unsigned int* cls_count = reinterpret_cast<unsigned int*>(cnt + 2);
+  unsigned int* cls_count = reinterpret_cast<unsigned int*>(cnt + 4);
   HIP_TRY(launch_classify(ctx->items.as<Item>(), ni, ctx->rank.as<uint8_t>(), cls_count,
                           ctx->cls_lists.as<int32_t>(), s));
   HIP_TRY(hipEventRecord(ctx->evs[2], s));
@@ -320,11 +468,13 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
                             ctx->qa.as<uint8_t>(), ctx->codes.as<uint8_t>(),
                             ctx->keep_coef ? ctx->coef.as<float>() : nullptr, esc, s));
     HIP_TRY(hipEventRecord(ctx->ev1, s));
-    unsigned long long hc[2];
+    unsigned long long hc[4];
     HIP_TRY(hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     ctx->nesc = int64_t(hc[0]);
     ctx->nraw = int64_t(hc[1]);
+    ctx->nwarm_accept = learned ? int64_t(hc[2]) : 0;
+    ctx->nwarm_reject = learned ? int64_t(hc[3]) : 0;
     if (hc[0] <= ctx->esc_cap) break;
     // more escapes than room: grow and run the encode kernel again (it rewrites
     // every output, so the result is identical apart from the escape list)
@@ -343,6 +493,121 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
     ctx->stage_ms[i] = ms;
   }
   ctx->have_result = true;
+  return DLS_OK;
+}
+
+dls_status dls_model_create(int device, dls_model** out) {
+  if (out == nullptr) return fail(DLS_EINVAL, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  HIP_TRY(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(DLS_EINVAL, "no such device");
+  HIP_TRY(hipSetDevice(device));
+  std::unique_ptr<dls_model> m(new (std::nothrow) dls_model());
+  if (!m) return fail(DLS_ENOMEM, "model allocation");
+  m->device = device;
+  HIP_TRY(m->params.ensure(kNParam * 4));
+  HIP_TRY(m->grad.ensure(kNParam * 4));
+  HIP_TRY(m->m.ensure(kNParam * 4));
+  HIP_TRY(m->v.ensure(kNParam * 4));
+  HIP_TRY(m->norm.ensure(32 * 4));
+  HIP_TRY(hipMemset(m->params.p, 0, kNParam * 4));
+  HIP_TRY(hipMemset(m->grad.p, 0, kNParam * 4));
+  HIP_TRY(hipMemset(m->m.p, 0, kNParam * 4));
+  HIP_TRY(hipMemset(m->v.p, 0, kNParam * 4));
+  std::vector<float> norm(32, 0.f);
+  for (int i = 16; i < 32; ++i) norm[i] = 1.f;
+  HIP_TRY(hipMemcpy(m->norm.p, norm.data(), 32 * 4, hipMemcpyHostToDevice));
+  *out = m.release();
+  return DLS_OK;
+}
+
+void dls_model_destroy(dls_model* m) {
+  if (m == nullptr) return;
+  (void)hipSetDevice(m->device);
+  delete m;
+}
+
+dls_status dls_model_set(dls_model* m, const float* params, const float* norm) {
+  if (m == nullptr || params == nullptr) return fail(DLS_EINVAL, "NULL argument");
+  HIP_TRY(hipSetDevice(m->device));
+  if (norm != nullptr)
+    for (int i = 16; i < 32; ++i)
+      if (!(norm[i] > 0.f)) return fail(DLS_EINVAL, "normalisation scales must be > 0");
+  HIP_TRY(hipMemcpy(m->params.p, params, kNParam * 4, hipMemcpyHostToDevice));
+  if (norm != nullptr) HIP_TRY(hipMemcpy(m->norm.p, norm, 32 * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemset(m->m.p, 0, kNParam * 4));
+  HIP_TRY(hipMemset(m->v.p, 0, kNParam * 4));
+  m->step = 0;
+  return DLS_OK;
+}
+
+dls_status dls_model_get(const dls_model* m, float* params, float* norm) {
+  if (m == nullptr) return fail(DLS_EINVAL, "NULL model");
+  HIP_TRY(hipSetDevice(m->device));
+  if (params != nullptr) HIP_TRY(hipMemcpy(params, m->params.p, kNParam * 4, hipMemcpyDeviceToHost));
+  if (norm != nullptr) HIP_TRY(hipMemcpy(norm, m->norm.p, 32 * 4, hipMemcpyDeviceToHost));
+  return DLS_OK;
+}
+
+dls_status dls_model_forward(dls_model* m, const float* d_feat, int64_t n, int bf16, float* d_out, void* stream) {
+  if (m == nullptr || d_feat == nullptr || d_out == nullptr || n < 1) return fail(DLS_EINVAL, "bad argument");
+  HIP_TRY(hipSetDevice(m->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (dls_status st = model_workspace(m, n)) return st;
+  if (dls_status st = model_forward(m, d_feat, n, bf16 != 0, d_out, s)) return st;
+  HIP_TRY(hipStreamSynchronize(s));
+  return DLS_OK;
+}
+
+dls_status dls_model_grad(dls_model* m, const float* d_feat, const int32_t* d_rank, const float* d_basis,
+                          const int32_t* d_wb, int64_t n, int bf16, float* d_grad, float* loss_out, void* stream) {
+  if (m == nullptr || d_feat == nullptr || d_rank == nullptr || d_basis == nullptr || d_wb == nullptr ||
+      d_grad == nullptr || n < 1)
+    return fail(DLS_EINVAL, "bad argument");
+  HIP_TRY(hipSetDevice(m->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (dls_status st = model_backprop(m, d_feat, d_rank, d_basis, d_wb, n, bf16 != 0, loss_out, s)) return st;
+  HIP_TRY(hipMemcpyAsync(d_grad, m->grad.p, kNParam * 4, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return DLS_OK;
+}
+
+dls_status dls_model_train_step(dls_model* m, const float* d_feat, const int32_t* d_rank, const float* d_basis,
+                                const int32_t* d_wb, int64_t n, float lr, int bf16, float* loss_out,
+                                void* stream) {
+  if (m == nullptr || d_feat == nullptr || d_rank == nullptr || d_basis == nullptr || d_wb == nullptr || n < 1 ||
+      !(lr > 0.f))
+    return fail(DLS_EINVAL, "bad argument");
+  HIP_TRY(hipSetDevice(m->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (dls_status st = model_backprop(m, d_feat, d_rank, d_basis, d_wb, n, bf16 != 0, loss_out, s)) return st;
+  m->step += 1;
+  const float c1 = float(1.0 - std::pow(0.9, double(m->step)));
+  const float c2 = float(1.0 - std::pow(0.999, double(m->step)));
+  HIP_TRY(launch_adam(m->params.as<float>(), m->grad.as<float>(), m->m.as<float>(), m->v.as<float>(), kNParam, lr, c1,
+                      c2, s));
+  if (loss_out == nullptr) HIP_TRY(hipStreamSynchronize(s));
+  return DLS_OK;
+}
+
+dls_status dls_features(dls_ctx* ctx, const void* d_field, float* d_out, void* stream) {
+  if (ctx == nullptr || d_field == nullptr || d_out == nullptr) return fail(DLS_EINVAL, "NULL argument");
+  if (!ctx->have_result) return fail(DLS_EINVAL, "no encode result in this context");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Problem& p = ctx->prob;
+  const Dims dims{p.nx, p.ny, p.nz, p.nt};
+  HIP_TRY(launch_features(p.dtype, d_field, dims, ctx->desc.as<BlockDesc>(), int64_t(ctx->plan.blocks.size()),
+                          ctx->eps_v.as<double>(), d_out, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return DLS_OK;
+}
+
+dls_status dls_ctx_set_model(dls_ctx* ctx, dls_model* m, int iters) {
+  if (ctx == nullptr || iters < 0 || iters > 64) return fail(DLS_EINVAL, "bad argument");
+  ctx->model = m;
+  ctx->warm_iters = iters;
   return DLS_OK;
 }
 
@@ -385,6 +650,8 @@ dls_status dls_encode_info_get(const dls_ctx* ctx, dls_encode_info* info) {
   info->d_qa_off = ctx->qa_off.as<int64_t>();
   info->d_code_off = ctx->code_off.as<int64_t>();
   info->d_coef = ctx->keep_coef ? ctx->coef.as<float>() : nullptr;
+  info->nwarm_accept = ctx->nwarm_accept;
+  info->nwarm_reject = ctx->nwarm_reject;
   info->gpu_ms = ctx->gpu_ms;
   for (int i = 0; i < 5; ++i) info->stage_ms[i] = ctx->stage_ms[i];
   return DLS_OK;

@@ -114,6 +114,13 @@ void build_blocks(const Problem& p, Plan& plan, int slice_points) {
   plan.items.clear();
   plan.item_start.clear();
   plan.code_off.clear();
+  size_t nleaves = 0;
+  for (int v = 0; v < p.nvars; ++v) nleaves += plan.leaves[v].size();
+  const size_t nb_est = nleaves * size_t((p.nt + p.window - 1) / p.window);
+  plan.blocks.reserve(nb_est);
+  plan.code_off.reserve(nb_est);
+  plan.item_start.reserve(nb_est + 1);
+  plan.items.reserve(nb_est);
   int64_t off = 0;
   for (int v = 0; v < p.nvars; ++v) {
     for (int64_t t0 = 0; t0 < p.nt; t0 += p.window) {

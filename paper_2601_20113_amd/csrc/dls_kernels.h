@@ -26,10 +26,27 @@ struct EscOut {
 
 hipError_t launch_gram(int wp, int dtype, const void* F, const Dims& dims, const BlockDesc* desc,
                        const Item* items, int64_t nitems, double* gpart, hipStream_t s);
+// `only` (may be NULL): solve only the blocks b with only[b] != 0
 hipError_t launch_eigen(int wp, const double* gpart, const int32_t* item_start, const BlockDesc* desc,
                         int64_t nblocks, const double* eps_v, int r_max, uint8_t* rank, double* lam,
                         double* basis, int64_t* qv_size, int64_t* qa_size, unsigned long long* nraw,
-                        hipStream_t s);
+                        const uint8_t* only, hipStream_t s);
+// learned warm start (dls_learned.hip)
+hipError_t launch_features(int dtype, const void* F, const Dims& dims, const BlockDesc* desc, int64_t nblocks,
+                           const double* eps_v, float* feat, hipStream_t s);
+hipError_t launch_normalize(const float* raw, int64_t n, const float* norm, float* z, hipStream_t s);
+hipError_t launch_gemm(bool ta, bool tb, bool bf16, const float* A, int lda, const float* B, int ldb, float* C,
+                       int ldc, int M, int N, int K, const float* bias, int relu, hipStream_t s);
+hipError_t launch_loss(const float* out, const int32_t* rank, const float* basis, const int32_t* wb, int64_t n,
+                       float* gout, float* loss, hipStream_t s);
+hipError_t launch_colsum(const float* G, int64_t n, int cols, float* out, hipStream_t s);
+hipError_t launch_relu_mask(float* dh, const float* h, int64_t n, hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float c1, float c2,
+                       hipStream_t s);
+hipError_t launch_warmstart(const double* gpart, const int32_t* item_start, const BlockDesc* desc, int64_t nblocks,
+                            const double* eps_v, int r_max, const float* mlp_out, int iters, uint8_t* rank,
+                            double* lam, double* basis, int64_t* qv_size, int64_t* qa_size, uint8_t* reject,
+                            unsigned long long* counters, hipStream_t s);
 hipError_t launch_scan(const int64_t* in, int64_t n, int64_t* out, int64_t* tmp, hipStream_t s);
 hipError_t launch_range(int dtype, const void* F, int nvars, int64_t n_per_var, double* part, int nparts,
                         double* out, hipStream_t s);

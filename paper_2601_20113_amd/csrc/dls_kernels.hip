@@ -19,6 +19,7 @@
 // for bit.  Fused multiply-adds are written explicitly where wanted.
 #include <hip/hip_runtime.h>
 
+#include "dls_device.h"
 #include "dls_kernels.h"
 
 namespace dls {
@@ -154,16 +155,6 @@ __global__ __launch_bounds__(256) void k_gram(const T* __restrict__ F, Dims dims
 // ---------------------------------------------------------------------------
 // Eigensolve + rank: one 64-lane workgroup per block.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int rr_player(int pos, int step, int n) {
-  return pos == 0 ? 0 : ((pos - 1 + step) % (n - 1)) + 1;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
 template <int WP>
 __global__ __launch_bounds__(64) void k_eigen(const double* __restrict__ gpart,
                                               const int32_t* __restrict__ item_start,
@@ -174,7 +165,9 @@ __global__ __launch_bounds__(64) void k_eigen(const double* __restrict__ gpart,
                                               double* __restrict__ basis_out,
                                               int64_t* __restrict__ qv_size,
                                               int64_t* __restrict__ qa_size,
-                                              unsigned long long* __restrict__ nraw) {
+                                              unsigned long long* __restrict__ nraw,
+                                              const uint8_t* __restrict__ only) {
+  if (only != nullptr && only[blockIdx.x] == 0) return;
   constexpr int EPT = WP * WP / 64;
   constexpr int LD = WP + 1;
   __shared__ double G[WP * LD], A[WP * LD], V[WP * LD];
@@ -228,58 +221,7 @@ __global__ __launch_bounds__(64) void k_eigen(const double* __restrict__ gpart,
     return;
   }
 
-  // cyclic Jacobi, parallel round-robin ordering (WP / 2 rotations per step)
-  for (int sweep = 0; sweep < 12; ++sweep) {
-    double off = 0.0, tot = 0.0;
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int idx = tid + 64 * e, i = idx / WP, j = idx % WP;
-      const double a = A[i * LD + j];
-      tot += a * a;
-      if (i != j) off += a * a;
-    }
-    off = wave_sum(off);
-    tot = wave_sum(tot);
-    if (!(off > 1e-26 * tot)) break;
-    for (int step = 0; step < WP - 1; ++step) {
-      if (tid < WP / 2) {
-        int p = rr_player(tid, step, WP), q = rr_player(WP - 1 - tid, step, WP);
-        if (p > q) { int t = p; p = q; q = t; }
-        const double app = A[p * LD + p], aqq = A[q * LD + q], apq = A[p * LD + q];
-        double c = 1.0, s = 0.0;
-        if (apq != 0.0) {
-          const double theta = (aqq - app) / (2.0 * apq);
-          double t = 1.0 / (fabs(theta) + sqrt(1.0 + theta * theta));
-          if (theta < 0.0) t = -t;
-          c = 1.0 / sqrt(1.0 + t * t);
-          s = t * c;
-        }
-        partner[p] = q; partner[q] = p;
-        alpha[p] = c; beta[p] = -s;
-        alpha[q] = c; beta[q] = s;
-      }
-      __syncthreads();
-      double na[EPT], nv[EPT];
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        const int idx = tid + 64 * e, i = idx / WP, j = idx % WP;
-        const int mi = partner[i], mj = partner[j];
-        const double ai = alpha[i], bi = beta[i], aj = alpha[j], bj = beta[j];
-        const double ri = fma(aj, A[i * LD + j], bj * A[i * LD + mj]);
-        const double rm = fma(aj, A[mi * LD + j], bj * A[mi * LD + mj]);
-        na[e] = fma(ai, ri, bi * rm);
-        nv[e] = fma(aj, V[i * LD + j], bj * V[i * LD + mj]);
-      }
-      __syncthreads();
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        const int idx = tid + 64 * e, i = idx / WP, j = idx % WP;
-        A[i * LD + j] = na[e];
-        V[i * LD + j] = nv[e];
-      }
-      __syncthreads();
-    }
-  }
+  jacobi_lds<WP>(A, V, alpha, beta, partner, tid);
 
   // descending order of the Jacobi eigenvalues (stable by index).  Padded
   // indices t >= W_b have exactly zero Gram rows, so every rotation touching
@@ -805,13 +747,13 @@ hipError_t launch_gram(int wp, int dtype, const void* F, const Dims& dims, const
 hipError_t launch_eigen(int wp, const double* gpart, const int32_t* item_start, const BlockDesc* desc,
                         int64_t nblocks, const double* eps_v, int r_max, uint8_t* rank, double* lam,
                         double* basis, int64_t* qv_size, int64_t* qa_size, unsigned long long* nraw,
-                        hipStream_t s) {
+                        const uint8_t* only, hipStream_t s) {
   if (nblocks == 0) return hipSuccess;
   const dim3 g{unsigned(nblocks)}, bl{64};
   if (wp == 16)
-    hipLaunchKernelGGL(k_eigen<16>, g, bl, 0, s, gpart, item_start, desc, eps_v, r_max, rank, lam, basis, qv_size, qa_size, nraw);
+    hipLaunchKernelGGL(k_eigen<16>, g, bl, 0, s, gpart, item_start, desc, eps_v, r_max, rank, lam, basis, qv_size, qa_size, nraw, only);
   else
-    hipLaunchKernelGGL(k_eigen<32>, g, bl, 0, s, gpart, item_start, desc, eps_v, r_max, rank, lam, basis, qv_size, qa_size, nraw);
+    hipLaunchKernelGGL(k_eigen<32>, g, bl, 0, s, gpart, item_start, desc, eps_v, r_max, rank, lam, basis, qv_size, qa_size, nraw, only);
   return hipGetLastError();
 }
 

@@ -5,16 +5,21 @@
 // exceeds the 80th percentile of the snapshot's gradient magnitude.
 //
 // Device side: gradient magnitude in FP64 (central differences inside,
-// one-sided at the ends), the exact order statistic sorted(g)[floor(0.8 (n-1))]
-// by radix selection over the FP64 bit patterns (11-bit digits, 6 passes),
-// and per-level node sums.  Host side: the depth-first walk that emits the
-// split bits and the leaves in (z0, y0, x0) order.
+// one-sided at the ends), recomputed from the snapshot in every pass rather
+// than stored; the exact order statistic sorted(g)[floor(0.8 (n-1))] by radix
+// selection over the FP64 bit patterns (two 11-bit digit passes, then the few
+// points sharing the 22-bit prefix are gathered and selected on the host);
+// per-level node sums.  Host side: the depth-first walk that emits the split
+// bits and the leaves in (z0, y0, x0) order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "dls_internal.h"
@@ -24,13 +29,10 @@ namespace dls {
 
 namespace {
 
+// |grad f| at (x, y, z) of one snapshot, FP64; the same arithmetic everywhere
 template <typename T>
-__global__ __launch_bounds__(256) void k_gradient(const T* __restrict__ f0, int64_t nx, int64_t ny, int64_t nz,
-                                                  double* __restrict__ g) {
-  const int64_t n = nx * ny * nz;
-  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (i >= n) return;
-  const int64_t x = i % nx, y = (i / nx) % ny, z = i / (nx * ny);
+__device__ __forceinline__ double grad_mag(const T* __restrict__ f0, int64_t nx, int64_t ny, int64_t nz, int64_t x,
+                                           int64_t y, int64_t z) {
   auto at = [&](int64_t zz, int64_t yy, int64_t xx) { return double(f0[(zz * ny + yy) * nx + xx]); };
   double dx = 0.0, dy = 0.0, dz = 0.0;
   if (nx > 1) {
@@ -48,42 +50,135 @@ __global__ __launch_bounds__(256) void k_gradient(const T* __restrict__ f0, int6
     else if (z == nz - 1) dz = at(nz - 1, y, x) - at(nz - 2, y, x);
     else dz = (at(z + 1, y, x) - at(z - 1, y, x)) * 0.5;
   }
-  g[i] = sqrt(dx * dx + dy * dy + dz * dz);
+  return sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+// g = |grad f| of one snapshot, stored once in FP64 (rows over workgroups,
+// x over threads: no index divisions)
+template <typename T>
+__global__ __launch_bounds__(256) void k_gradient(const T* __restrict__ f0, int64_t nx, int64_t ny, int64_t nz,
+                                                  double* __restrict__ g) {
+  const int64_t rows = ny * nz;
+  for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+    const int64_t y = row % ny, z = row / ny;
+    for (int64_t x = threadIdx.x; x < nx; x += 256) g[row * nx + x] = grad_mag(f0, nx, ny, nz, x, y, z);
+  }
 }
 
 // histogram of digit (bits >> shift) & dmask among elements whose bits match
-// `prefix` under `pmask`
+// `prefix` under `pmask`.  With `aggregate`, lanes holding the same digit are
+// merged with a ballot first (the exponent pass, where a wave holds few
+// distinct digits and LDS atomics on one address would serialise).
 __global__ __launch_bounds__(256) void k_radix_hist(const double* __restrict__ g, int64_t n, uint64_t prefix,
-                                                    uint64_t pmask, int shift, uint32_t dmask,
+                                                    uint64_t pmask, int shift, uint32_t dmask, int aggregate,
                                                     unsigned int* __restrict__ hist) {
   __shared__ unsigned int h[2048];
   for (int j = threadIdx.x; j < 2048; j += 256) h[j] = 0;
   __syncthreads();
-  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
-    const uint64_t b = uint64_t(__double_as_longlong(g[i]));
-    if ((b & pmask) == prefix) atomicAdd(&h[(b >> shift) & dmask], 1u);
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = int64_t(gridDim.x) * 256;
+  const int64_t nround = (n + stride - 1) / stride;
+  for (int64_t it = 0; it < nround; ++it) {   // uniform trip count: every lane joins the ballots
+    const int64_t i = it * stride + int64_t(blockIdx.x) * 256 + threadIdx.x;
+    bool act = false;
+    uint32_t d = 0;
+    if (i < n) {
+      const uint64_t b = uint64_t(__double_as_longlong(g[i]));
+      act = (b & pmask) == prefix;
+      d = uint32_t(b >> shift) & dmask;
+    }
+    if (!aggregate) {
+      if (act) atomicAdd(&h[d], 1u);
+      continue;
+    }
+    uint64_t pending = __ballot(act);
+    while (pending) {
+      const int leader = __ffsll((unsigned long long)pending) - 1;
+      const uint32_t d0 = __shfl(d, leader, 64);
+      const uint64_t same = __ballot(act && d == d0);
+      if (lane == leader) atomicAdd(&h[d0], unsigned(__popcll(same)));
+      if (d == d0) act = false;
+      pending &= ~same;
+    }
   }
   __syncthreads();
   for (int j = threadIdx.x; j <= int(dmask); j += 256)
     if (h[j]) atomicAdd(hist + j, h[j]);
 }
 
-// finest-level node sums and counts of g (node edge e, node grid NX x NY x NZ)
+// append the bit patterns of g that match `prefix` under `pmask`; one global
+// atomic per wavefront (lanes take consecutive slots by their rank in the
+// ballot)
+__global__ __launch_bounds__(256) void k_radix_compact(const double* __restrict__ g, int64_t n, uint64_t prefix,
+                                                       uint64_t pmask, unsigned long long* __restrict__ count,
+                                                       uint64_t* __restrict__ out, unsigned long long cap) {
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = int64_t(gridDim.x) * 256;
+  const int64_t nround = (n + stride - 1) / stride;
+  for (int64_t it = 0; it < nround; ++it) {
+    const int64_t i = it * stride + int64_t(blockIdx.x) * 256 + threadIdx.x;
+    uint64_t b = 0;
+    bool hit = false;
+    if (i < n) {
+      b = uint64_t(__double_as_longlong(g[i]));
+      hit = (b & pmask) == prefix;
+    }
+    const uint64_t mask = __ballot(hit);
+    if (mask == 0) continue;
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(count, (unsigned long long)__popcll(mask));
+    base = __shfl(base, leader, 64);
+    if (hit) {
+      const unsigned long long slot = base + __popcll(mask & ((1ULL << lane) - 1ULL));
+      if (slot < cap) out[slot] = b;
+    }
+  }
+}
+
+// finest-level node sums and counts of g.  Nodes of at most 64 points: one
+// thread per node; larger nodes: one wavefront per node with a fixed-order
+// reduction.  Points are summed in (z, y, x) order within each lane.
 __global__ __launch_bounds__(256) void k_node_sums(const double* __restrict__ g, int64_t nx, int64_t ny, int64_t nz,
-                                                   int e, int ez, int64_t NX, int64_t NY, int64_t NZ,
+                                                   int e, int ez, int64_t NX, int64_t NY, int64_t NZ, int per_wave,
                                                    double* __restrict__ sum, int64_t* __restrict__ cnt) {
   const int64_t nn = NX * NY * NZ;
-  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (i >= nn) return;
-  const int64_t ix = i % NX, iy = (i / NX) % NY, iz = i / (NX * NY);
+  const int lane = threadIdx.x & 63;
+  const int64_t node = per_wave ? int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6) : int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (node >= nn) return;
+  const int64_t ix = node % NX, iy = (node / NX) % NY, iz = node / (NX * NY);
   const int64_t x0 = ix * e, y0 = iy * e, z0 = iz * ez;
-  const int64_t x1 = x0 + e < nx ? x0 + e : nx, y1 = y0 + e < ny ? y0 + e : ny, z1 = z0 + ez < nz ? z0 + ez : nz;
+  const int ex = int((x0 + e < nx ? x0 + e : nx) - x0), ey = int((y0 + e < ny ? y0 + e : ny) - y0),
+            ezz = int((z0 + ez < nz ? z0 + ez : nz) - z0);
   double s = 0.0;
-  for (int64_t z = z0; z < z1; ++z)
-    for (int64_t y = y0; y < y1; ++y)
-      for (int64_t x = x0; x < x1; ++x) s += g[(z * ny + y) * nx + x];
-  sum[i] = s;
-  cnt[i] = (x1 - x0) * (y1 - y0) * (z1 - z0);
+  if (!per_wave) {
+    for (int zz = 0; zz < ezz; ++zz)
+      for (int yy = 0; yy < ey; ++yy) {
+        const double* row = g + ((z0 + zz) * ny + y0 + yy) * nx + x0;
+        for (int xx = 0; xx < ex; ++xx) s += row[xx];
+      }
+    sum[node] = s;
+    cnt[node] = int64_t(ex) * ey * ezz;
+    return;
+  }
+  const int np = ex * ey * ezz;
+  for (int q = lane; q < np; q += 64) {
+    const int xx = q % ex, rest = q / ex, yy = rest % ey, zz = rest / ey;
+    s += g[((z0 + zz) * ny + y0 + yy) * nx + x0 + xx];
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) {
+    sum[node] = s;
+    cnt[node] = np;
+  }
+}
+
+// split flag of every node: mean of g over the node > thr
+__global__ __launch_bounds__(256) void k_split_flags(const double* __restrict__ sum, const int64_t* __restrict__ cnt,
+                                                     int64_t n, double thr, uint8_t* __restrict__ flag) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i < n) flag[i] = (sum[i] / double(cnt[i]) > thr) ? 1 : 0;
 }
 
 // parent level from the child level (children in (z, y, x) order)
@@ -131,7 +226,7 @@ struct DevMem {
 }  // namespace
 
 struct PlanScratch {
-  DevMem g, hist, sums, cnts;
+  DevMem g, cand, hist, sums, cnts, count, flags;
 };
 
 PlanScratch* plan_scratch_new() { return new PlanScratch(); }
@@ -154,6 +249,9 @@ hipError_t adaptive_plan(const Problem& p, const void* F, hipStream_t s, PlanScr
   const bool is3d = p.nz > 1;
   PLAN_TRY(S.g.ensure(size_t(n) * sizeof(double)));
   PLAN_TRY(S.hist.ensure(2048 * sizeof(unsigned int)));
+  PLAN_TRY(S.count.ensure(sizeof(unsigned long long)));
+  const unsigned long long cand_cap = 1ULL << 22;
+  PLAN_TRY(S.cand.ensure(size_t(cand_cap) * sizeof(uint64_t)));
   // node grids, coarsest (edge px) to finest (edge pmin)
   std::vector<int> edges;
   for (int e = p.px; e >= p.pmin; e /= 2) edges.push_back(e);
@@ -167,35 +265,49 @@ hipError_t adaptive_plan(const Problem& p, const void* F, hipStream_t s, PlanScr
   }
   PLAN_TRY(S.sums.ensure(size_t(off[L]) * sizeof(double)));
   PLAN_TRY(S.cnts.ensure(size_t(off[L]) * sizeof(int64_t)));
+  PLAN_TRY(S.flags.ensure(size_t(off[L])));
   double* dsum = static_cast<double*>(S.sums.p);
   int64_t* dcnt = static_cast<int64_t*>(S.cnts.p);
   unsigned int* dhist = static_cast<unsigned int*>(S.hist.p);
+  unsigned long long* dcount = static_cast<unsigned long long*>(S.count.p);
+  uint64_t* dcand = static_cast<uint64_t*>(S.cand.p);
   double* g = static_cast<double*>(S.g.p);
-  std::vector<double> hsum(off[L]);
-  std::vector<int64_t> hcnt(off[L]);
+  uint8_t* dflag = static_cast<uint8_t*>(S.flags.p);
+  std::vector<uint8_t> hflag(off[L]);
   plan.leaves.assign(p.nvars, {});
   plan.bits.assign(p.nvars, {});
   const int es = p.esize();
+  const bool timing = std::getenv("DLS_TIMING") != nullptr;
+  auto now = [] { return std::chrono::steady_clock::now(); };
+  auto ms = [](std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+  };
   for (int v = 0; v < p.nvars; ++v) {
+    const auto t0 = now();
     const uint8_t* f0 = static_cast<const uint8_t*>(F) + size_t(v) * size_t(p.nt) * size_t(n) * es;
-    const dim3 gn{unsigned((n + 255) / 256)}, bl{256};
+    const dim3 bl{256};
+    const unsigned nrowblk = unsigned(std::min<int64_t>(8192, p.ny * p.nz));
     if (p.dtype == 0)
-      hipLaunchKernelGGL(k_gradient<float>, gn, bl, 0, s, (const float*)f0, p.nx, p.ny, p.nz, g);
+      hipLaunchKernelGGL(k_gradient<float>, dim3{nrowblk}, bl, 0, s, (const float*)f0, p.nx, p.ny, p.nz, g);
     else
-      hipLaunchKernelGGL(k_gradient<double>, gn, bl, 0, s, (const double*)f0, p.nx, p.ny, p.nz, g);
+      hipLaunchKernelGGL(k_gradient<double>, dim3{nrowblk}, bl, 0, s, (const double*)f0, p.nx, p.ny, p.nz, g);
     PLAN_TRY(hipGetLastError());
-    // exact order statistic k = floor(0.8 (n - 1)) by radix selection
+    auto hist_pass = [&](uint64_t prefix, uint64_t pmask, int shift, uint32_t dmask, unsigned nblk) {
+      hipLaunchKernelGGL(k_radix_hist, dim3{nblk}, bl, 0, s, (const double*)g, n, prefix, pmask, shift, dmask,
+                         shift == 53 ? 1 : 0, dhist);
+    };
+    // exact order statistic k = floor(0.8 (n - 1)): three 11-bit radix passes
+    // over g, then the points sharing the 33-bit prefix are gathered and the
+    // rest of the selection runs on the host
     int64_t k = int64_t(std::floor(0.8 * double(n - 1)));
     uint64_t prefix = 0, pmask = 0;
-    const int shifts[6] = {53, 42, 31, 20, 9, 0};
-    const int widths[6] = {11, 11, 11, 11, 11, 9};
-    const unsigned nblk = unsigned(std::min<int64_t>(2048, (n + 255) / 256));
+    const unsigned nblk = unsigned(std::min<int64_t>(4096, (n + 255) / 256));
     std::vector<unsigned int> h(2048);
-    for (int pass = 0; pass < 6; ++pass) {
-      const uint32_t dmask = (1u << widths[pass]) - 1u;
+    for (int pass = 0; pass < 3; ++pass) {
+      const int shift = 53 - 11 * pass;
+      const uint32_t dmask = 2047u;
       PLAN_TRY(hipMemsetAsync(dhist, 0, 2048 * sizeof(unsigned int), s));
-      hipLaunchKernelGGL(k_radix_hist, dim3{nblk}, bl, 0, s, (const double*)g, n, prefix, pmask, shifts[pass],
-                         dmask, dhist);
+      hist_pass(prefix, pmask, shift, dmask, nblk);
       PLAN_TRY(hipGetLastError());
       PLAN_TRY(hipMemcpyAsync(h.data(), dhist, 2048 * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
       PLAN_TRY(hipStreamSynchronize(s));
@@ -208,17 +320,63 @@ hipError_t adaptive_plan(const Problem& p, const void* F, hipStream_t s, PlanScr
         err = "radix selection lost its element";
         return hipErrorUnknown;
       }
-      prefix |= uint64_t(d) << shifts[pass];
-      pmask |= uint64_t(dmask) << shifts[pass];
+      prefix |= uint64_t(d) << shift;
+      pmask |= uint64_t(dmask) << shift;
+    }
+    PLAN_TRY(hipMemsetAsync(dcount, 0, sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(k_radix_compact, dim3{nblk}, bl, 0, s, (const double*)g, n, prefix, pmask, dcount, dcand,
+                       cand_cap);
+    PLAN_TRY(hipGetLastError());
+    unsigned long long ncand = 0;
+    PLAN_TRY(hipMemcpyAsync(&ncand, dcount, sizeof(ncand), hipMemcpyDeviceToHost, s));
+    PLAN_TRY(hipStreamSynchronize(s));
+    uint64_t thr_bits = 0;
+    if (ncand <= cand_cap) {
+      std::vector<uint64_t> cand(ncand);
+      PLAN_TRY(hipMemcpy(cand.data(), dcand, size_t(ncand) * sizeof(uint64_t), hipMemcpyDeviceToHost));
+      if (k >= int64_t(ncand)) {
+        err = "radix selection lost its element";
+        return hipErrorUnknown;
+      }
+      std::nth_element(cand.begin(), cand.begin() + k, cand.end());
+      thr_bits = cand[k];
+    } else {
+      // too many ties on the prefix: finish with device passes (3 more digits)
+      const int shifts[3] = {20, 9, 0};
+      const int widths[3] = {11, 11, 9};
+      for (int pass = 0; pass < 3; ++pass) {
+        const uint32_t dmask = (1u << widths[pass]) - 1u;
+        PLAN_TRY(hipMemsetAsync(dhist, 0, 2048 * sizeof(unsigned int), s));
+        hist_pass(prefix, pmask, shifts[pass], dmask, nblk);
+        PLAN_TRY(hipGetLastError());
+        PLAN_TRY(hipMemcpyAsync(h.data(), dhist, 2048 * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+        PLAN_TRY(hipStreamSynchronize(s));
+        uint32_t d = 0;
+        for (; d <= dmask; ++d) {
+          if (k < int64_t(h[d])) break;
+          k -= h[d];
+        }
+        if (d > dmask) {
+          err = "radix selection lost its element";
+          return hipErrorUnknown;
+        }
+        prefix |= uint64_t(d) << shifts[pass];
+        pmask |= uint64_t(dmask) << shifts[pass];
+      }
+      thr_bits = prefix;
     }
     double thr;
-    std::memcpy(&thr, &prefix, 8);
+    std::memcpy(&thr, &thr_bits, 8);
+    const auto t1 = now();
     // node sums: finest level directly, coarser levels from their children
     {
       const int l = L - 1;
       const int64_t nn = NX[l] * NY[l] * NZ[l];
-      hipLaunchKernelGGL(k_node_sums, dim3{unsigned((nn + 255) / 256)}, bl, 0, s, (const double*)g, p.nx, p.ny,
-                         p.nz, edges[l], is3d ? edges[l] : 1, NX[l], NY[l], NZ[l], dsum + off[l], dcnt + off[l]);
+      const int64_t node_pts = int64_t(edges[l]) * edges[l] * (is3d ? edges[l] : 1);
+      const int per_wave = node_pts > 64 ? 1 : 0;
+      const dim3 gs{unsigned(per_wave ? (nn + 3) / 4 : (nn + 255) / 256)};
+      hipLaunchKernelGGL(k_node_sums, gs, bl, 0, s, (const double*)g, p.nx, p.ny, p.nz, edges[l], is3d ? edges[l] : 1,
+                         NX[l], NY[l], NZ[l], per_wave, dsum + off[l], dcnt + off[l]);
       PLAN_TRY(hipGetLastError());
     }
     for (int l = L - 2; l >= 0; --l) {
@@ -228,9 +386,12 @@ hipError_t adaptive_plan(const Problem& p, const void* F, hipStream_t s, PlanScr
                          NY[l], NZ[l], dsum + off[l], dcnt + off[l]);
       PLAN_TRY(hipGetLastError());
     }
-    PLAN_TRY(hipMemcpyAsync(hsum.data(), dsum, size_t(off[L]) * sizeof(double), hipMemcpyDeviceToHost, s));
-    PLAN_TRY(hipMemcpyAsync(hcnt.data(), dcnt, size_t(off[L]) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    hipLaunchKernelGGL(k_split_flags, dim3{unsigned((off[L] + 255) / 256)}, bl, 0, s, (const double*)dsum,
+                       (const int64_t*)dcnt, off[L], thr, dflag);
+    PLAN_TRY(hipGetLastError());
+    PLAN_TRY(hipMemcpyAsync(hflag.data(), dflag, size_t(off[L]), hipMemcpyDeviceToHost, s));
     PLAN_TRY(hipStreamSynchronize(s));
+    const auto t2 = now();
     // depth-first walk: roots in (z, y, x) order, children in (z, y, x) order
     std::vector<Leaf>& leaves = plan.leaves[v];
     std::vector<uint8_t>& bits = plan.bits[v];
@@ -246,7 +407,7 @@ hipError_t adaptive_plan(const Problem& p, const void* F, hipStream_t s, PlanScr
             const int e = edges[nd.l];
             const int64_t j = off[nd.l] + (nd.iz * NY[nd.l] + nd.iy) * NX[nd.l] + nd.ix;
             if (e > p.pmin) {
-              const bool split = hsum[j] / double(hcnt[j]) > thr;
+              const bool split = hflag[j] != 0;
               bits.push_back(split ? 1 : 0);
               if (split) {
                 const int c = nd.l + 1;
@@ -273,6 +434,9 @@ hipError_t adaptive_plan(const Problem& p, const void* F, hipStream_t s, PlanScr
       if (a.y0 != b.y0) return a.y0 < b.y0;
       return a.x0 < b.x0;
     });
+    if (timing)
+      std::fprintf(stderr, "[dls] plan var %d: percentile %.3f ms, node sums %.3f ms, tree %.3f ms, %zu leaves\n", v,
+                   ms(t0, t1), ms(t1, t2), ms(t2, now()), leaves.size());
   }
   return hipSuccess;
 }

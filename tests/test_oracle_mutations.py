@@ -19,10 +19,12 @@ from oracle import dls  # noqa: E402
 MUTATIONS = [
     ("tail_energies", "t[r] = t[r + 1] + lam[r]", "t[r] = t[r + 1] + lam[min(r + 1, lam.size - 1)]"),
     ("choose_rank", "if tail[r] <= tau:", "if tail[r - 1] <= tau:"),
-    ("encode_block", "A = x.T @ Vr", "A = x.T @ V[:, 1:r + 1] if V.shape[1] > r else x.T @ Vr"),
-    ("encode_block", "q = np.rint((x - xhat) * (1.0 / (2.0 * eps)))", "q = np.rint((x - xhat) * (1.0 / eps))"),
-    ("encode_block", "xhat = S.astype(np.float64) * c", "xhat = -S.astype(np.float64) * c"),
-    ("encode_block", "qV = np.rint(Vr * float(1 << BASIS_BITS)).astype(np.int64)",
+    ("encode_block", "code = encode_with_basis(xs, eps, V[:, :r], lam, tau, dtype)",
+     "code = encode_with_basis(xs, eps, V[:, 1:r + 1] if V.shape[1] > r else V[:, :r], lam, tau, dtype)"),
+    ("encode_with_basis", "A = x.T @ Vr", "A = x @ Vr[:x.shape[1]] if False else x.T @ Vr[::-1]"),
+    ("encode_with_basis", "q = np.rint((x - xhat) * (1.0 / (2.0 * eps)))", "q = np.rint((x - xhat) * (1.0 / eps))"),
+    ("encode_with_basis", "xhat = S.astype(np.float64) * c", "xhat = -S.astype(np.float64) * c"),
+    ("encode_with_basis", "qV = np.rint(Vr * float(1 << BASIS_BITS)).astype(np.int64)",
      "qV = np.rint(Vr * float(1 << (BASIS_BITS - 1))).astype(np.int64)"),
     ("encode_block", "tau = KAPPA * eps * eps * m * wb", "tau = KAPPA * eps * m * wb"),
     ("encode_block", "G = x @ x.T", "G = x @ x.T - np.diag(np.diag(x @ x.T)) * 0.5"),

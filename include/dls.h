@@ -232,9 +232,11 @@ dls_status dls_model_train_step(dls_model* m, const float* d_feat, const int32_t
  * log10(mean x^2 / eps^2), log10(std / eps), time-mean energy fraction,
  * log2 M) then the 8 x 8 pooled time-mean image (normalised). */
 dls_status dls_features(dls_ctx* ctx, const void* d_field, float* d_out, void* stream);
-/* Attach a model (NULL detaches) and the number of subspace iterations
- * (>= 0) used by encodes with DLS_LEARNED on this context. */
-dls_status dls_ctx_set_model(dls_ctx* ctx, dls_model* m, int iters);
+/* Attach a model (NULL detaches), the number of subspace iterations
+ * (0..64) and a rank margin (0..16: the warm start uses rhat + margin
+ * columns, the acceptance test then keeps the smallest sufficient rank) for
+ * encodes with DLS_LEARNED on this context. */
+dls_status dls_ctx_set_model(dls_ctx* ctx, dls_model* m, int iters, int rank_margin);
 
 /* Release a buffer returned by dls_finalize / dls_compress. */
 void dls_free(void* p);

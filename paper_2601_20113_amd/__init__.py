@@ -111,7 +111,7 @@ def lib():
         L.dls_model_train_step.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int64, ctypes.c_float, ctypes.c_int,
                                            ctypes.POINTER(ctypes.c_float), vp]
         L.dls_features.argtypes = [vp, vp, vp, vp]
-        L.dls_ctx_set_model.argtypes = [vp, vp, ctypes.c_int]
+        L.dls_ctx_set_model.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int]
         L.dls_free.argtypes = [ctypes.c_void_p]
         L.dls_free.restype = None
         L.dls_last_error.restype = ctypes.c_char_p
@@ -209,10 +209,10 @@ class Encoder:
         _check(lib().dls_encode(self._h, ctypes.c_void_p(field.data_ptr()), ctypes.byref(cp),
                                 _stream_handle(stream), 1 if keep_coef else 0))
 
-    def set_model(self, model: "Model", iters: int = 2):
+    def set_model(self, model: "Model", iters: int = 2, margin: int = 1):
         """Attach a model for encodes with learned=True (None detaches)."""
         self._model = model
-        _check(lib().dls_ctx_set_model(self._h, model._h if model is not None else None, iters))
+        _check(lib().dls_ctx_set_model(self._h, model._h if model is not None else None, iters, margin))
 
     def features(self, field: torch.Tensor, stream=None) -> torch.Tensor:
         """Raw features (nblocks x 80) of the blocks of the last encode."""

@@ -241,6 +241,7 @@ struct dls_ctx {
   PlanScratch* plan_scratch = nullptr;
   dls_model* model = nullptr;  // DLS_LEARNED
   int warm_iters = 2;
+  int warm_margin = 1;
   DevBuf feat, zfeat, mlp_h1, mlp_h2, mlp_out, reject;
   int64_t nwarm_accept = 0, nwarm_reject = 0;
   void* pinned = nullptr;      // host staging for plan uploads
@@ -279,7 +280,7 @@ dls_status learned_eigen(dls_ctx* ctx, const void* d_field, const Problem& p, co
   if (dls_status st = model_forward(m, ctx->feat.as<float>(), nb, true, ctx->mlp_out.as<float>(), s)) return st;
   HIP_TRY(launch_warmstart(ctx->gram.as<double>(), ctx->item_start.as<int32_t>(), ctx->desc.as<BlockDesc>(), nb,
                            ctx->eps_v.as<double>(), p.r_max, ctx->mlp_out.as<float>(), ctx->warm_iters,
-                           ctx->rank.as<uint8_t>(), ctx->lam.as<double>(), ctx->basis.as<double>(),
+                           ctx->warm_margin, ctx->rank.as<uint8_t>(), ctx->lam.as<double>(), ctx->basis.as<double>(),
                            ctx->qv_size.as<int64_t>(), ctx->qa_size.as<int64_t>(), ctx->reject.as<uint8_t>(),
                            cnt + 2, s));
   HIP_TRY(launch_eigen(16, ctx->gram.as<double>(), ctx->item_start.as<int32_t>(), ctx->desc.as<BlockDesc>(), nb,
@@ -604,10 +605,12 @@ dls_status dls_features(dls_ctx* ctx, const void* d_field, float* d_out, void* s
   return DLS_OK;
 }
 
-dls_status dls_ctx_set_model(dls_ctx* ctx, dls_model* m, int iters) {
-  if (ctx == nullptr || iters < 0 || iters > 64) return fail(DLS_EINVAL, "bad argument");
+dls_status dls_ctx_set_model(dls_ctx* ctx, dls_model* m, int iters, int rank_margin) {
+  if (ctx == nullptr || iters < 0 || iters > 64 || rank_margin < 0 || rank_margin > 16)
+    return fail(DLS_EINVAL, "bad argument");
   ctx->model = m;
   ctx->warm_iters = iters;
+  ctx->warm_margin = rank_margin;
   return DLS_OK;
 }
 

@@ -44,9 +44,9 @@ hipError_t launch_relu_mask(float* dh, const float* h, int64_t n, hipStream_t s)
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float c1, float c2,
                        hipStream_t s);
 hipError_t launch_warmstart(const double* gpart, const int32_t* item_start, const BlockDesc* desc, int64_t nblocks,
-                            const double* eps_v, int r_max, const float* mlp_out, int iters, uint8_t* rank,
-                            double* lam, double* basis, int64_t* qv_size, int64_t* qa_size, uint8_t* reject,
-                            unsigned long long* counters, hipStream_t s);
+                            const double* eps_v, int r_max, const float* mlp_out, int iters, int margin,
+                            uint8_t* rank, double* lam, double* basis, int64_t* qv_size, int64_t* qa_size,
+                            uint8_t* reject, unsigned long long* counters, hipStream_t s);
 hipError_t launch_scan(const int64_t* in, int64_t n, int64_t* out, int64_t* tmp, hipStream_t s);
 hipError_t launch_range(int dtype, const void* F, int nvars, int64_t n_per_var, double* part, int nparts,
                         double* out, hipStream_t s);

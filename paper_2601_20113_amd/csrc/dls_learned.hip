@@ -27,48 +27,26 @@ __device__ __forceinline__ short to_bf16(float f) {
 
 // ---------------------------------------------------------------------------
 // Per-block features: 16 statistics then the 8 x 8 pooled time-mean image
-// (normalised by the block mean and standard deviation).  One 256-thread
-// workgroup per block, FP64 sums reduced in a fixed order.
+// (normalised by the block mean and standard deviation).  One wavefront per
+// block (four per workgroup): lanes stride the block's points, FP64 sums are
+// reduced with a fixed xor-shuffle tree; lane c computes pooled cell c.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double block_sum(double v, double* red) {
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
-  const double r = red[0];
-  __syncthreads();
-  return r;
-}
-
-__device__ __forceinline__ double block_min(double v, double* red) {
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + o]);
-    __syncthreads();
-  }
-  const double r = red[0];
-  __syncthreads();
-  return r;
-}
-
 template <typename T>
 __global__ __launch_bounds__(256) void k_features(const T* __restrict__ F, Dims dims,
-                                                  const BlockDesc* __restrict__ desc,
+                                                  const BlockDesc* __restrict__ desc, int64_t nblocks,
                                                   const double* __restrict__ eps_v, float* __restrict__ feat) {
-  __shared__ double red[256];
-  __shared__ double cell[64];
-  const int b = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t b = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (b >= nblocks) return;
   const BlockDesc d = desc[b];
   const int W = d.w(), M = d.m, px = d.px(), py = d.py(), pz = d.pz();
   const int64_t nxy = dims.nx * dims.ny, tstride = dims.nz * nxy;
   const T* base = F + (((int64_t(d.var) * dims.nt + d.t0) * dims.nz + d.z0) * dims.ny + d.y0) * dims.nx + d.x0;
-  auto at = [&](int t, int i, int j, int k) { return double(base[int64_t(t) * tstride + int64_t(k) * nxy + int64_t(j) * dims.nx + i]); };
-
+  auto at = [&](int t, int i, int j, int k) {
+    return double(base[int64_t(t) * tstride + int64_t(k) * nxy + int64_t(j) * dims.nx + i]);
+  };
   double s1 = 0, s2 = 0, mn = INFINITY, mx = -INFINITY, adt = 0, sdt = 0, sdt2 = 0, adx = 0, ady = 0, tme = 0;
-  for (int p = threadIdx.x; p < M; p += 256) {
+  for (int p = lane; p < M; p += 64) {
     const int i = p % px, rho = p / px, j = rho % py, k = rho / py;
     double prev = 0.0, ts = 0.0;
     for (int t = 0; t < W; ++t) {
@@ -90,21 +68,16 @@ __global__ __launch_bounds__(256) void k_features(const T* __restrict__ F, Dims 
     }
     tme += ts * ts;
   }
+  s1 = wave_sum(s1); s2 = wave_sum(s2); adt = wave_sum(adt); sdt = wave_sum(sdt); sdt2 = wave_sum(sdt2);
+  adx = wave_sum(adx); ady = wave_sum(ady); tme = wave_sum(tme);
+  for (int o = 32; o >= 1; o >>= 1) {
+    mn = fmin(mn, __shfl_xor(mn, o, 64));
+    mx = fmax(mx, __shfl_xor(mx, o, 64));
+  }
   const double n = double(W) * M;
-  s1 = block_sum(s1, red);
-  s2 = block_sum(s2, red);
-  mn = block_min(mn, red);
-  mx = -block_min(-mx, red);
-  adt = block_sum(adt, red);
-  sdt = block_sum(sdt, red);
-  sdt2 = block_sum(sdt2, red);
-  adx = block_sum(adx, red);
-  ady = block_sum(ady, red);
-  tme = block_sum(tme, red);
   const double mu = s1 / n;
-
   double c3 = 0, c4 = 0, l1 = 0, l2 = 0, cvar = 0;
-  for (int p = threadIdx.x; p < M; p += 256) {
+  for (int p = lane; p < M; p += 64) {
     const int i = p % px, rho = p / px, j = rho % py, k = rho / py;
     double x1 = 0, x2 = 0;
     for (int t = 0; t < W; ++t) {
@@ -119,42 +92,29 @@ __global__ __launch_bounds__(256) void k_features(const T* __restrict__ F, Dims 
       x1 = y;
     }
   }
-  cvar = block_sum(cvar, red);
-  c3 = block_sum(c3, red);
-  c4 = block_sum(c4, red);
-  l1 = block_sum(l1, red);
-  l2 = block_sum(l2, red);
+  cvar = wave_sum(cvar); c3 = wave_sum(c3); c4 = wave_sum(c4); l1 = wave_sum(l1); l2 = wave_sum(l2);
   const double var = cvar / n;
   const double sd = sqrt(var);
   const double inv = sd > 0.0 ? 1.0 / sd : 0.0;
-
-  // pooled time-mean: cell c = (row group bb, column group aa), 4 threads per cell
+  // pooled time-mean: lane c owns cell (row group c / 8, column group c % 8)
+  double cellv;
   {
-    const int c = threadIdx.x >> 2, sub = threadIdx.x & 3;
-    const int bb = c >> 3, aa = c & 7;
+    const int bb = lane >> 3, aa = lane & 7;
     int j0 = (bb * py + 7) / 8, j1 = ((bb + 1) * py + 7) / 8;
     int i0 = (aa * px + 7) / 8, i1 = ((aa + 1) * px + 7) / 8;
     if (j1 <= j0) { j0 = (bb * py) / 8; j1 = j0 + 1; }
     if (i1 <= i0) { i0 = (aa * px) / 8; i1 = i0 + 1; }
-    const int ci = i1 - i0, cj = j1 - j0;
-    const int npix = ci * cj * pz * W;
     double s = 0.0;
-    for (int q = sub; q < npix; q += 4) {
-      const int ii = q % ci, r1 = q / ci, jj = r1 % cj, r2 = r1 / cj, kk = r2 % pz, t = r2 / pz;
-      s += at(t, i0 + ii, j0 + jj, kk);
-    }
-    red[threadIdx.x] = s;
-    __syncthreads();
-    if (sub == 0) {
-      const double tot = ((red[threadIdx.x] + red[threadIdx.x + 1]) + red[threadIdx.x + 2]) + red[threadIdx.x + 3];
-      cell[c] = tot / double(npix);
-    }
-    __syncthreads();
+    for (int t = 0; t < W; ++t)
+      for (int kk = 0; kk < pz; ++kk)
+        for (int jj = j0; jj < j1; ++jj)
+          for (int ii = i0; ii < i1; ++ii) s += at(t, ii, jj, kk);
+    cellv = s / double((i1 - i0) * (j1 - j0) * pz * W);
   }
-
-  if (threadIdx.x == 0) {
+  float* o = feat + b * 80;
+  o[16 + lane] = float(sd > 0.0 ? (cellv - mu) / sd : 0.0);
+  if (lane == 0) {
     const double eps = eps_v[d.var];
-    float* o = feat + int64_t(b) * 80;
     double f[16];
     f[0] = mu;
     f[1] = sd;
@@ -175,7 +135,6 @@ __global__ __launch_bounds__(256) void k_features(const T* __restrict__ F, Dims 
     f[14] = s2 > 0.0 ? tme / (double(W) * s2) : 0.0;
     f[15] = log2(double(M));
     for (int q = 0; q < 16; ++q) o[q] = float(f[q]);
-    for (int q = 0; q < 64; ++q) o[16 + q] = float(sd > 0.0 ? (cell[q] - mu) / sd : 0.0);
   }
 }
 
@@ -275,13 +234,17 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ out, con
   loss[s] = float(l + mse / cnt);
 }
 
+// column sums, one wavefront per column, lanes stride the rows, fixed-order
+// shuffle reduction
 __global__ __launch_bounds__(256) void k_colsum(const float* __restrict__ G, int64_t n, int cols,
                                                 float* __restrict__ out) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (j >= cols) return;
   double s = 0.0;
-  for (int64_t i = 0; i < n; ++i) s += G[i * cols + j];
-  out[j] = float(s);
+  for (int64_t i = lane; i < n; i += 64) s += G[i * cols + j];
+  s = wave_sum(s);
+  if (lane == 0) out[j] = float(s);
 }
 
 __global__ __launch_bounds__(256) void k_relu_mask(float* __restrict__ dh, const float* __restrict__ h, int64_t n) {
@@ -303,206 +266,321 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
 }
 
 // ---------------------------------------------------------------------------
-// Warm-started eigensolve of one block (W <= 16): one 64-lane workgroup.
+// Warm-started eigensolve: 16 lanes per block, four blocks per wavefront,
+// sixteen per workgroup.  Lane t owns row t of G and of the iterate Q
+// (registers); sums over the 16 rows use DPP row operations, so every lane
+// of a group holds bitwise the same sum and all lanes take the same
+// decisions.  LDS carries the broadcasts of Q and the small Rayleigh-Ritz
+// matrix.  A group touches only its own LDS and its own DPP row, and the
+// 16 lanes of a group are always active together, so within the group no
+// workgroup barrier is needed: wave_sync() only keeps the compiler from
+// moving LDS accesses across it (a wavefront's LDS accesses complete in
+// issue order).  Predictions of more than kWarmMax columns go to the
+// Jacobi fallback.
 // ---------------------------------------------------------------------------
-// Modified Gram-Schmidt (twice) of the first r columns of Q (LDS, [t][k],
-// leading dimension 17) over rows t < W; a collapsing column is replaced by
-// the first unit vector e_j that stays independent.  Lanes t < 16 own row t.
-__device__ void mgs16(double* Q, int r, int W, int tid) {
-  const int t = tid & 15;
-  const bool own = tid < 16;
-  auto dot16 = [&](double v) {
-    for (int o = 8; o >= 1; o >>= 1) v += __shfl_xor(v, o, 16);
-    return v;
-  };
-  for (int k = 0; k < r; ++k) {
-    double y = (t < W) ? Q[t * 17 + k] : 0.0;
-    const double n0 = sqrt(dot16(y * y));
-    for (int pass = 0; pass < 2; ++pass)
-      for (int j = 0; j < k; ++j) {
-        const double qj = (t < W) ? Q[t * 17 + j] : 0.0;
-        const double c = dot16(qj * y);
-        y -= c * qj;
+constexpr int kWarmMax = 8;
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t u = uint64_t(__double_as_longlong(v));
+  const int lo = __builtin_amdgcn_update_dpp(0, int(uint32_t(u)), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(uint32_t(u >> 32)), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)((uint64_t(uint32_t(hi)) << 32) | uint64_t(uint32_t(lo))));
+}
+
+// Sum over the 16 lanes of a DPP row.  Each step adds a lane's value to its
+// partner's (x + y in one lane, y + x in the other: the same bits), so all
+// 16 lanes end with the same result.
+__device__ __forceinline__ double row_sum(double v) {
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
+  return v;
+}
+
+// Orthonormalise the first r columns of Q (row t in q[]), classical
+// Gram-Schmidt applied twice per column; a column that collapses is
+// replaced by the first unit vector e_j (j < W) that stays independent.
+__device__ __forceinline__ void orth_rows(double (&q)[kWarmMax], int r, int W, int t) {
+#pragma unroll
+  for (int k = 0; k < kWarmMax; ++k) {
+    if (k < r) {
+      auto project_out = [&](double y) {
+#pragma unroll
+        for (int pass = 0; pass < 2; ++pass) {
+          double c[kWarmMax];
+#pragma unroll
+          for (int j = 0; j < k; ++j) c[j] = row_sum(q[j] * y);
+#pragma unroll
+          for (int j = 0; j < k; ++j) y -= c[j] * q[j];
+        }
+        return y;
+      };
+      double y = q[k];
+      const double n0 = sqrt(row_sum(y * y));
+      y = project_out(y);
+      double nrm = sqrt(row_sum(y * y));
+      if (!(nrm > 1e-12 * n0) || n0 == 0.0) {
+        for (int e = 0; e < W; ++e) {
+          y = project_out(t == e ? 1.0 : 0.0);
+          nrm = sqrt(row_sum(y * y));
+          if (nrm > 0.5) break;
+        }
       }
-    double nrm = sqrt(dot16(y * y));
-    if (!(nrm > 1e-12 * n0) || n0 == 0.0) {
-      for (int e = 0; e < W; ++e) {
-        y = (t == e) ? 1.0 : 0.0;
-        for (int pass = 0; pass < 2; ++pass)
-          for (int j = 0; j < k; ++j) {
-            const double qj = (t < W) ? Q[t * 17 + j] : 0.0;
-            const double c = dot16(qj * y);
-            y -= c * qj;
-          }
-        nrm = sqrt(dot16(y * y));
-        if (nrm > 0.5) break;
-      }
+      q[k] = (t < W) ? y / nrm : 0.0;
     }
-    __syncthreads();
-    if (own) Q[t * 17 + k] = (t < W) ? y / nrm : 0.0;
-    __syncthreads();
   }
 }
 
-__global__ __launch_bounds__(64) void k_warmstart(const double* __restrict__ gpart, const int32_t* __restrict__ item_start,
-                                                  const BlockDesc* __restrict__ desc, const double* __restrict__ eps_v,
-                                                  int r_max, const float* __restrict__ mlp_out, int iters,
-                                                  uint8_t* __restrict__ rank_out, double* __restrict__ lam_out,
-                                                  double* __restrict__ basis_out, int64_t* __restrict__ qv_size,
-                                                  int64_t* __restrict__ qa_size, uint8_t* __restrict__ reject,
-                                                  unsigned long long* __restrict__ counters) {
-  constexpr int LD = 17;
-  __shared__ double G[16 * LD], Q[16 * LD], Y[16 * LD], H[16 * LD], U[16 * LD];
-  __shared__ double alpha[16], beta[16], th[16];
-  __shared__ int partner[16], perm[16];
-  const int b = blockIdx.x, tid = threadIdx.x;
-  const BlockDesc d = desc[b];
-  const int W = d.w(), M = d.m;
-  const int i0 = item_start[b], i1 = item_start[b + 1];
-  bool fin = true;
-  for (int e = 0; e < 4; ++e) {
-    const int idx = tid + 64 * e;
-    double s = 0.0;
-    for (int it = i0; it < i1; ++it) s += gpart[int64_t(it) * 256 + idx];
-    G[(idx >> 4) * LD + (idx & 15)] = s;
-  }
-  __syncthreads();
-  double gs[4];
-  for (int e = 0; e < 4; ++e) {
-    const int idx = tid + 64 * e, i = idx >> 4, j = idx & 15;
-    gs[e] = 0.5 * (G[i * LD + j] + G[j * LD + i]);
-    fin = fin && isfinite(gs[e]);
-  }
-  __syncthreads();
-  for (int e = 0; e < 4; ++e) {
-    const int idx = tid + 64 * e;
-    G[(idx >> 4) * LD + (idx & 15)] = gs[e];
-  }
-  fin = __syncthreads_and(fin);
-  if (!fin) {  // non-finite block: the plain path makes it a raw block
-    if (tid == 0) reject[b] = 1;
-    return;
-  }
-  int rcap = r_max < W ? r_max : W;
-  rcap = rcap < M ? rcap : M;
-  const float* o = mlp_out + int64_t(b) * 272;
-  int rhat = 0;
-  float best = o[0];
-  for (int k = 1; k < 16; ++k)
-    if (o[k] > best) { best = o[k]; rhat = k; }
-  rhat = rhat + 1;
-  rhat = rhat < rcap ? rhat : rcap;
-  for (int e = 0; e < 4; ++e) {
-    const int idx = tid + 64 * e, t = idx >> 4, k = idx & 15;
-    Q[t * LD + k] = (t < W && k < rhat) ? double(o[16 + k * 16 + t]) : 0.0;
-  }
-  __syncthreads();
-  mgs16(Q, rhat, W, tid);
-  for (int s = 0; s < iters; ++s) {
-    for (int e = 0; e < 4; ++e) {  // Y = G Q
-      const int idx = tid + 64 * e, t = idx >> 4, k = idx & 15;
-      double y = 0.0;
-      if (k < rhat)
-        for (int j = 0; j < 16; ++j) y = fma(G[t * LD + j], Q[j * LD + k], y);
-      Y[t * LD + k] = y;
-    }
-    __syncthreads();
+// Cyclic Jacobi with the round-robin ordering on the leading n x n block of
+// H (LDS, leading dimension kWarmMax + 1), n <= kWarmMax, rotations
+// accumulated into U.  The 16 lanes of one group call it together.
+__device__ void jacobi_group(double* H, double* U, double* alpha, double* beta, int* partner, int n, int t) {
+  constexpr int LD = kWarmMax + 1;
+  if (n <= 1) return;
+  const int ne = n + (n & 1);
+  const int nn = ne * ne;
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    double off = 0.0, tot = 0.0;
+#pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int idx = tid + 64 * e, t = idx >> 4, k = idx & 15;
-      Q[t * LD + k] = Y[t * LD + k];
+      const int idx = t + 16 * e;
+      if (idx < nn) {
+        const int i = idx / ne, j = idx % ne;
+        const double a = (i < n && j < n) ? H[i * LD + j] : 0.0;
+        tot += a * a;
+        if (i != j) off += a * a;
+      }
     }
-    __syncthreads();
-    mgs16(Q, rhat, W, tid);
+    off = row_sum(off);
+    tot = row_sum(tot);
+    if (!(off > 1e-26 * tot)) break;
+    for (int step = 0; step < ne - 1; ++step) {
+      if (t < ne / 2) {
+        int p = rr_player(t, step, ne), q = rr_player(ne - 1 - t, step, ne);
+        if (p > q) { const int x = p; p = q; q = x; }
+        double c = 1.0, s = 0.0;
+        if (q < n) {
+          const double app = H[p * LD + p], aqq = H[q * LD + q], apq = H[p * LD + q];
+          if (apq != 0.0) {
+            const double theta = (aqq - app) / (2.0 * apq);
+            double tt = 1.0 / (fabs(theta) + sqrt(1.0 + theta * theta));
+            if (theta < 0.0) tt = -tt;
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            s = tt * c;
+          }
+        }
+        partner[p] = q; partner[q] = p;
+        alpha[p] = c; beta[p] = -s;
+        alpha[q] = c; beta[q] = s;
+      }
+      wave_sync();
+      double na[4], nu[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int idx = t + 16 * e;
+        na[e] = nu[e] = 0.0;
+        if (idx < nn) {
+          const int i = idx / ne, j = idx % ne;
+          if (i < n && j < n) {
+            const int mi = partner[i], mj = partner[j];
+            const double ai = alpha[i], bi = beta[i], aj = alpha[j], bj = beta[j];
+            const double amj = mj < n ? H[i * LD + mj] : 0.0;
+            const double ami = mi < n ? H[mi * LD + j] : 0.0;
+            const double amm = (mi < n && mj < n) ? H[mi * LD + mj] : 0.0;
+            const double ri = fma(aj, H[i * LD + j], bj * amj);
+            const double rm = fma(aj, ami, bj * amm);
+            na[e] = fma(ai, ri, bi * rm);
+            const double umj = mj < n ? U[i * LD + mj] : 0.0;
+            nu[e] = fma(aj, U[i * LD + j], bj * umj);
+          }
+        }
+      }
+      wave_sync();
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int idx = t + 16 * e;
+        if (idx < nn) {
+          const int i = idx / ne, j = idx % ne;
+          if (i < n && j < n) {
+            H[i * LD + j] = na[e];
+            U[i * LD + j] = nu[e];
+          }
+        }
+      }
+      wave_sync();
+    }
   }
-  // Rayleigh-Ritz: H = Q^T (G Q), padded to 16 with zeros; Jacobi; sort
-  for (int e = 0; e < 4; ++e) {
-    const int idx = tid + 64 * e, t = idx >> 4, k = idx & 15;
-    double y = 0.0;
-    if (k < rhat)
-      for (int j = 0; j < 16; ++j) y = fma(G[t * LD + j], Q[j * LD + k], y);
-    Y[t * LD + k] = y;
-  }
+}
+
+__global__ __launch_bounds__(256) void k_warmstart(const double* __restrict__ gpart, const int32_t* __restrict__ item_start,
+                                                   const BlockDesc* __restrict__ desc, int64_t nblocks,
+                                                   const double* __restrict__ eps_v, int r_max,
+                                                   const float* __restrict__ mlp_out, int iters, int margin,
+                                                   uint8_t* __restrict__ rank_out, double* __restrict__ lam_out,
+                                                   double* __restrict__ basis_out, int64_t* __restrict__ qv_size,
+                                                   int64_t* __restrict__ qa_size, uint8_t* __restrict__ reject,
+                                                   unsigned long long* __restrict__ counters) {
+  constexpr int RH = kWarmMax, LQ = RH, LH = RH + 1;
+  __shared__ double sQ[16][16 * LQ];
+  __shared__ double sH[16][RH * LH], sU[16][RH * LH];
+  __shared__ double sAl[16][RH], sBe[16][RH], sTh[16][RH], sSg[16][RH];
+  __shared__ int sPa[16][RH], sPe[16][RH];
+  __shared__ unsigned int n_acc, n_rej;
+  const int grp = threadIdx.x >> 4, t = threadIdx.x & 15;
+  if (threadIdx.x == 0) { n_acc = 0; n_rej = 0; }
   __syncthreads();
-  for (int e = 0; e < 4; ++e) {
-    const int idx = tid + 64 * e, i = idx >> 4, j = idx & 15;
-    double h = 0.0;
-    if (i < rhat && j < rhat)
-      for (int t = 0; t < 16; ++t) h = fma(Q[t * LD + i], Y[t * LD + j], h);
-    H[i * LD + j] = h;
-    U[i * LD + j] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  for (int e = 0; e < 4; ++e) {  // symmetrise
-    const int idx = tid + 64 * e, i = idx >> 4, j = idx & 15;
-    gs[e] = 0.5 * (H[i * LD + j] + H[j * LD + i]);
-  }
-  __syncthreads();
-  for (int e = 0; e < 4; ++e) {
-    const int idx = tid + 64 * e;
-    H[(idx >> 4) * LD + (idx & 15)] = gs[e];
-  }
-  __syncthreads();
-  jacobi_lds<16>(H, U, alpha, beta, partner, tid);
-  if (tid < 16) perm[tid] = tid;
-  __syncthreads();
-  if (tid < 16) {
-    const double dk = tid < rhat ? H[tid * LD + tid] : -INFINITY;
-    int pos = 0;
+  const int64_t b = int64_t(blockIdx.x) * 16 + grp;
+  double* Q = sQ[grp];
+  double* H = sH[grp];
+  double* U = sU[grp];
+  int verdict = 0;  // 0: no block, 1: accepted, 2: rejected
+  if (b < nblocks) {
+    const BlockDesc d = desc[b];
+    const int W = d.w(), M = d.m;
+    const int i0 = item_start[b], i1 = item_start[b + 1];
+    double g[16];
+    bool fin = true;
+#pragma unroll
     for (int j = 0; j < 16; ++j) {
-      const double dj = j < rhat ? H[j * LD + j] : -INFINITY;
-      pos += (dj > dk || (dj == dk && j < tid)) ? 1 : 0;
+      double s1 = 0.0, s2 = 0.0;
+      for (int it = i0; it < i1; ++it) {
+        s1 += gpart[int64_t(it) * 256 + t * 16 + j];
+        s2 += gpart[int64_t(it) * 256 + j * 16 + t];
+      }
+      g[j] = 0.5 * (s1 + s2);
+      fin = fin && isfinite(g[j]);
     }
-    perm[pos] = tid;
-  }
-  __syncthreads();
-  // Ritz vectors Z[:, c] = Q U[:, perm[c]], canonical signs
-  if (tid < 16) {
-    const int c = tid;
-    int col = perm[c];
-    col = (col >= 0 && col < 16) ? col : c;
-    th[c] = c < rhat ? H[col * LD + col] : 0.0;
-    double best_a = -1.0, sgn = 1.0;
-    for (int t = 0; t < 16; ++t) {
-      double z = 0.0;
-      if (c < rhat)
-        for (int j = 0; j < 16; ++j) z = fma(Q[t * LD + j], U[j * LD + col], z);
-      Y[t * LD + c] = z;
-      if (fabs(z) > best_a) { best_a = fabs(z); sgn = z < 0.0 ? -1.0 : 1.0; }
-    }
-    for (int t = 0; t < 16; ++t) Y[t * LD + c] *= sgn;
-  }
-  __syncthreads();
-  __shared__ int acc_r;
-  if (tid == 0) {
-    double tr = 0.0;
-    for (int t = 0; t < 16; ++t) tr += G[t * LD + t];
-    const double eps = eps_v[d.var];
-    const double tau = kKappa * eps * eps * double(M) * double(W);
+    fin = row_sum(fin ? 0.0 : 1.0) == 0.0;
+    int rcap = r_max < W ? r_max : W;
+    rcap = rcap < M ? rcap : M;
+    const float* o = mlp_out + b * 272;
+    int rhat = 0;
+    float best = o[0];
+    for (int k = 1; k < 16; ++k)
+      if (o[k] > best) { best = o[k]; rhat = k; }
+    rhat = rhat + 1 + margin;
+    rhat = rhat < rcap ? rhat : rcap;
     int r = 0;
-    double cum = 0.0;
-    for (int k = 1; k <= rhat; ++k) {
-      cum += th[k - 1];
-      if (tr - cum <= tau) { r = k; break; }
+    double z[RH];
+    if (fin && rhat <= RH) {
+      double q[RH];
+#pragma unroll
+      for (int k = 0; k < RH; ++k) q[k] = (t < W && k < rhat) ? double(o[16 + k * 16 + t]) : 0.0;
+      orth_rows(q, rhat, W, t);
+      double y[RH];
+      auto times_g = [&]() {  // y = G Q, row t
+#pragma unroll
+        for (int k = 0; k < RH; ++k) Q[t * LQ + k] = q[k];
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < RH; ++k) y[k] = 0.0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+#pragma unroll
+          for (int k = 0; k < RH; ++k) y[k] = fma(g[j], Q[j * LQ + k], y[k]);
+        wave_sync();
+      };
+      for (int s = 0; s < iters; ++s) {
+        times_g();
+#pragma unroll
+        for (int k = 0; k < RH; ++k) q[k] = y[k];
+        orth_rows(q, rhat, W, t);
+      }
+      // Rayleigh-Ritz: H = Q^T G Q (upper triangle, mirrored), U = I
+      times_g();
+#pragma unroll
+      for (int a = 0; a < RH; ++a)
+#pragma unroll
+        for (int c = a; c < RH; ++c) {
+          const double h = row_sum(q[a] * y[c]);
+          if (t == 0) {
+            H[a * LH + c] = (a < rhat && c < rhat) ? h : 0.0;
+            H[c * LH + a] = (a < rhat && c < rhat) ? h : 0.0;
+            U[a * LH + c] = a == c ? 1.0 : 0.0;
+            U[c * LH + a] = a == c ? 1.0 : 0.0;
+          }
+        }
+      wave_sync();
+      jacobi_group(H, U, sAl[grp], sBe[grp], sPa[grp], rhat, t);
+      // descending order of the Ritz values (stable by index)
+      if (t < rhat) {
+        const double dk = H[t * LH + t];
+        int pos = 0;
+        for (int j = 0; j < rhat; ++j) {
+          const double dj = H[j * LH + j];
+          pos += (dj > dk || (dj == dk && j < t)) ? 1 : 0;
+        }
+        sPe[grp][pos] = t;
+        sTh[grp][pos] = dk;
+      }
+      wave_sync();
+      // Ritz vectors Z[:, c] = Q U[:, perm[c]], then canonical signs
+#pragma unroll
+      for (int c = 0; c < RH; ++c) {
+        double v = 0.0;
+        if (c < rhat) {
+          const int col = sPe[grp][c];
+#pragma unroll
+          for (int j = 0; j < RH; ++j) v = fma(q[j], U[j * LH + col], v);
+        }
+        z[c] = v;
+        Q[t * LQ + c] = v;
+      }
+      wave_sync();
+      if (t < rhat) {
+        double besta = -1.0, sg = 1.0;
+        for (int i = 0; i < 16; ++i) {
+          const double v = Q[i * LQ + t];
+          if (fabs(v) > besta) { besta = fabs(v); sg = v < 0.0 ? -1.0 : 1.0; }
+        }
+        sSg[grp][t] = sg;
+      }
+      wave_sync();
+#pragma unroll
+      for (int c = 0; c < RH; ++c) z[c] = c < rhat ? z[c] * sSg[grp][c] : 0.0;
+      // acceptance: smallest r <= rhat whose discarded energy meets tau
+      double diag = 0.0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) diag = (j == t) ? g[j] : diag;
+      const double tr = row_sum(diag);
+      const double eps = eps_v[d.var];
+      const double tau = kKappa * eps * eps * double(M) * double(W);
+      double cum = 0.0;
+      for (int k = 1; k <= rhat; ++k) {
+        cum += sTh[grp][k - 1];
+        if (tr - cum <= tau) { r = k; break; }
+      }
     }
-    acc_r = r;
     if (r == 0) {
-      reject[b] = 1;
-      atomicAdd(counters + 1, 1ULL);
+      verdict = 2;
+      if (t == 0) reject[b] = 1;
     } else {
-      reject[b] = 0;
-      atomicAdd(counters, 1ULL);
-      rank_out[b] = uint8_t(r);
-      qv_size[b] = 4 * pad16(int64_t(W) * r);
-      qa_size[b] = 4 * pad16(int64_t(M) * r);
+      verdict = 1;
+      if (t == 0) {
+        reject[b] = 0;
+        rank_out[b] = uint8_t(r);
+        qv_size[b] = 4 * pad16(int64_t(W) * r);
+        qa_size[b] = 4 * pad16(int64_t(M) * r);
+      }
+      lam_out[b * 16 + t] = t < r ? fmax(sTh[grp][t < RH ? t : 0], 0.0) : 0.0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) basis_out[b * 256 + k * 16 + t] = (k < r && k < RH) ? z[k < RH ? k : 0] : 0.0;
     }
   }
+  if (t == 0 && verdict == 1) atomicAdd(&n_acc, 1u);
+  if (t == 0 && verdict == 2) atomicAdd(&n_rej, 1u);
   __syncthreads();
-  const int r = acc_r;
-  if (r == 0) return;
-  if (tid < 16) lam_out[int64_t(b) * 16 + tid] = tid < r ? fmax(th[tid], 0.0) : 0.0;
-  for (int e = 0; e < 4; ++e) {
-    const int idx = tid + 64 * e, k = idx >> 4, t = idx & 15;
-    basis_out[int64_t(b) * 256 + idx] = (k < r) ? Y[t * LD + k] : 0.0;
+  if (threadIdx.x == 0) {
+    if (n_acc) atomicAdd(counters, (unsigned long long)n_acc);
+    if (n_rej) atomicAdd(counters + 1, (unsigned long long)n_rej);
   }
 }
 
@@ -512,9 +590,9 @@ __global__ __launch_bounds__(64) void k_warmstart(const double* __restrict__ gpa
 hipError_t launch_features(int dtype, const void* F, const Dims& dims, const BlockDesc* desc, int64_t nblocks,
                            const double* eps_v, float* feat, hipStream_t s) {
   if (nblocks == 0) return hipSuccess;
-  const dim3 g{unsigned(nblocks)}, bl{256};
-  if (dtype == 0) hipLaunchKernelGGL(k_features<float>, g, bl, 0, s, (const float*)F, dims, desc, eps_v, feat);
-  else hipLaunchKernelGGL(k_features<double>, g, bl, 0, s, (const double*)F, dims, desc, eps_v, feat);
+  const dim3 g{unsigned((nblocks + 3) / 4)}, bl{256};
+  if (dtype == 0) hipLaunchKernelGGL(k_features<float>, g, bl, 0, s, (const float*)F, dims, desc, nblocks, eps_v, feat);
+  else hipLaunchKernelGGL(k_features<double>, g, bl, 0, s, (const double*)F, dims, desc, nblocks, eps_v, feat);
   return hipGetLastError();
 }
 
@@ -547,7 +625,7 @@ hipError_t launch_loss(const float* out, const int32_t* rank, const float* basis
 }
 
 hipError_t launch_colsum(const float* G, int64_t n, int cols, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_colsum, dim3{unsigned((cols + 255) / 256)}, dim3{256}, 0, s, G, n, cols, out);
+  hipLaunchKernelGGL(k_colsum, dim3{unsigned((cols + 3) / 4)}, dim3{256}, 0, s, G, n, cols, out);
   return hipGetLastError();
 }
 
@@ -564,12 +642,13 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
 }
 
 hipError_t launch_warmstart(const double* gpart, const int32_t* item_start, const BlockDesc* desc, int64_t nblocks,
-                            const double* eps_v, int r_max, const float* mlp_out, int iters, uint8_t* rank,
-                            double* lam, double* basis, int64_t* qv_size, int64_t* qa_size, uint8_t* reject,
-                            unsigned long long* counters, hipStream_t s) {
+                            const double* eps_v, int r_max, const float* mlp_out, int iters, int margin,
+                            uint8_t* rank, double* lam, double* basis, int64_t* qv_size, int64_t* qa_size,
+                            uint8_t* reject, unsigned long long* counters, hipStream_t s) {
   if (nblocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_warmstart, dim3{unsigned(nblocks)}, dim3{64}, 0, s, gpart, item_start, desc, eps_v, r_max,
-                     mlp_out, iters, rank, lam, basis, qv_size, qa_size, reject, counters);
+  hipLaunchKernelGGL(k_warmstart, dim3{unsigned((nblocks + 15) / 16)}, dim3{256}, 0, s, gpart, item_start, desc,
+                     nblocks, eps_v, r_max, mlp_out, iters, margin, rank, lam, basis, qv_size, qa_size, reject,
+                     counters);
   return hipGetLastError();
 }
 

@@ -148,7 +148,7 @@ def test_warm_start_parity(case):
     rhat, iters = 4, 2
     m = _fixed_guess_model(rhat)
     enc = dls.Encoder()
-    enc.set_model(m, iters)
+    enc.set_model(m, iters, margin=0)
     lp = H.to_lib_params(p)
     lp.learned = True
     t = torch.from_numpy(f).cuda()

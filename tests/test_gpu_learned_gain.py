@@ -1,0 +1,68 @@
+"""What the trained network gains over the method without it.
+
+Train on config-1 fields of seeds A (labels from the plain GPU method),
+evaluate on unseen seeds B.  Against the plain path (full Jacobi on every
+block) and against a non-learned warm start (a fixed guess: rank 3, the
+first unit vectors), the learned path must keep the bound at every point,
+stay within 1 % of the plain compression ratio, keep the plain ranks on the
+large majority of blocks, accept the warm start on most blocks, and spend
+less device time in the eigensolve stage.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+import paper_2601_20113_amd as dls  # noqa: E402
+from paper_2601_20113_amd import train as T  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _encode(enc, t, p, reps=3):
+    """Encode `reps` times, return (stage eigen ms of the last, info, ranks, stream)."""
+    for _ in range(reps):
+        enc.encode(t, p)
+    inf = enc.info()
+    ranks = dls.d2h(inf.d_rank, inf.nblocks).copy()
+    return inf.stage_ms[2], inf, ranks, enc.finalize()
+
+
+def test_learned_warm_start_gain():
+    print("training", flush=True)
+    model, data, losses = T.fit(np.arange(100000, 100160), epochs=12, batch=512, lr=2e-3, seed=1)
+    print("losses", ["%.3f" % l for l in losses], flush=True)
+    assert losses[-1] < 0.5 * losses[0]
+    f, eps = T.c1_fields(np.arange(200000, 200256))
+    nv, nt, nz, ny, nx = f.shape
+    t = torch.from_numpy(f).cuda()
+    base = dict(nx=nx, ny=ny, nz=nz, nt=nt, nvars=nv, dtype="f64", px=8, py=8, pz=1, window=16, eps=eps)
+    enc = dls.Encoder()
+    ms_plain, inf_p, r_plain, s_plain = _encode(enc, t, dls.Params(**base))
+    enc.set_model(model, 2, margin=1)
+    ms_learn, inf_l, r_learn, s_learn = _encode(enc, t, dls.Params(**base, learned=True))
+    fixed = dls.Model()
+    P = np.zeros(dls.NPARAM, np.float32)
+    ob3 = 80 * 128 + 128 + 128 * 128 + 128 + 128 * 272
+    P[ob3 + 2] = 10.0
+    for k in range(16):
+        P[ob3 + 16 + 17 * k] = 1.0
+    fixed.set(P, np.concatenate([np.zeros(16), np.ones(16)]).astype(np.float32))
+    enc.set_model(fixed, 2, margin=0)
+    ms_fix, inf_f, r_fix, s_fix = _encode(enc, t, dls.Params(**base, learned=True))
+    nb = inf_p.nblocks
+    agree = float(np.mean(r_plain == r_learn))
+    print("eigen stage ms: plain %.3f learned %.3f fixed-guess %.3f" % (ms_plain, ms_learn, ms_fix), flush=True)
+    print("accept learned %d/%d fixed %d/%d; rank agreement %.4f; CR plain %.3f learned %.3f fixed %.3f"
+          % (inf_l.nwarm_accept, nb, inf_f.nwarm_accept, nb, agree, f.nbytes / len(s_plain),
+             f.nbytes / len(s_learn), f.nbytes / len(s_fix)), flush=True)
+    out = dls.decompress(s_learn).cpu().numpy()
+    assert np.all(np.abs(out - f) <= np.array(eps)[:, None, None, None, None])
+    assert abs(len(s_learn) / len(s_plain) - 1.0) <= 0.01
+    assert agree >= 0.95
+    assert inf_l.nwarm_accept >= 0.9 * nb
+    assert inf_l.nwarm_accept >= inf_f.nwarm_accept
+    assert ms_learn < ms_plain

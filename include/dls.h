@@ -212,7 +212,10 @@ dls_status dls_model_set(dls_model* m, const float* params, const float* norm);
 /* Copy parameters and normalisation to host arrays (either may be NULL). */
 dls_status dls_model_get(const dls_model* m, float* params, float* norm);
 /* Outputs (n x 272, device) of raw features (n x 80, device, as written by
- * dls_features).  bf16 != 0: products with bfloat16 operands. */
+ * dls_features).  bf16 = 0: FP32 products; 1: bfloat16 operands, FP32
+ * accumulation, the three layers in one fused kernel (the path encodes
+ * use); 2: the same arithmetic layer by layer (bitwise equal to 1, kept as
+ * its reference).  Other values: DLS_EINVAL. */
 dls_status dls_model_forward(dls_model* m, const float* d_feat, int64_t n, int bf16, float* d_out,
                              void* stream);
 /* Gradient (device, DLS_MODEL_NPARAM floats) and mean loss of one batch

@@ -292,18 +292,38 @@ def warm_start_eig(G: np.ndarray, V0: np.ndarray, tau: float, iters: int = 2):
     return False, rhat, th, Z
 
 
+WARM_MAX = 8      # most columns the warm start iterates; larger predictions fall back
+RETRY_EXTRA = 4   # columns added by the second attempt
+RETRY_ITERS = 2   # subspace iterations added by the second attempt
+
+
 def encode_block_learned(xs: np.ndarray, eps: float, rcap: int, dtype, rhat: int, V0: np.ndarray,
                          iters: int = 2):
-    """encode_block with the warm-started eigensolve; falls back to the plain
-    eigensolve when the warm start is rejected.  Returns (BlockCode, accepted)."""
+    """encode_block with the warm-started eigensolve.
+
+    V0 holds the network's starting columns (W x 16, or at least as many
+    columns as an attempt uses).  Attempt 1 iterates the first rhat columns
+    `iters` times; if it is rejected, attempt 2 iterates the first
+    min(rhat + RETRY_EXTRA, WARM_MAX, cap) columns `iters + RETRY_ITERS`
+    times (only when that is more columns).  An attempt with more than
+    WARM_MAX columns is not made.  If no attempt is accepted the block takes
+    the plain eigensolve.  Returns (BlockCode, accepted)."""
     wb, m = xs.shape
     x = xs.astype(np.float64)
     if not np.all(np.isfinite(x)):
         return dls._raw_block(xs), False
     G = x @ x.T
     tau = dls.KAPPA * eps * eps * m * wb
-    rhat = max(1, min(rhat, rcap, wb, m))
-    ok, r, th, Z = warm_start_eig(G, V0[:wb, :rhat], tau, iters)
-    if not ok:
-        return dls.encode_block(xs, eps, rcap, dtype), False
-    return dls.encode_with_basis(xs, eps, Z[:, :r], np.maximum(th[:r], 0.0), tau, dtype), True
+    cap = min(rcap, wb, m)
+    rhat = max(1, min(rhat, cap))
+    attempts = [(rhat, iters)]
+    r2 = min(rhat + RETRY_EXTRA, WARM_MAX, cap)
+    if r2 > rhat:
+        attempts.append((r2, iters + RETRY_ITERS))
+    for k, it in attempts:
+        if k > WARM_MAX:
+            break
+        ok, r, th, Z = warm_start_eig(G, V0[:wb, :k], tau, it)
+        if ok:
+            return dls.encode_with_basis(xs, eps, Z[:, :r], np.maximum(th[:r], 0.0), tau, dtype), True
+    return dls.encode_block(xs, eps, rcap, dtype), False

@@ -356,7 +356,8 @@ class Model:
         _check(lib().dls_model_get(self._h, ctypes.c_void_p(p.ctypes.data), ctypes.c_void_p(n.ctypes.data)))
         return p, n
 
-    def forward(self, feat: torch.Tensor, bf16: bool = True, stream=None) -> torch.Tensor:
+    def forward(self, feat: torch.Tensor, bf16=True, stream=None) -> torch.Tensor:
+        """bf16: False (FP32 products), True (bf16, fused kernel) or 2 (bf16, layer by layer)."""
         feat = feat.contiguous()
         out = torch.empty((feat.shape[0], 272), dtype=torch.float32, device=feat.device)
         _check(lib().dls_model_forward(self._h, ctypes.c_void_p(feat.data_ptr()), feat.shape[0], int(bf16),

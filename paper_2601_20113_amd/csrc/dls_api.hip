@@ -153,16 +153,26 @@ bool same_layout(const Problem& a, const Problem& b) {
 struct dls_model {
   int device = 0;
   DevBuf params, norm, m, v, grad;
+  DevBuf packed;           // bf16 weights in the fused forward's LDS layout
+  bool packed_valid = false;
   int64_t step = 0;
   DevBuf z, h1, h2, out, gout, dh2, dh1, loss;  // workspace for a batch
   int64_t ws_n = 0;
 };
 
 namespace {
-constexpr int kNF = 80, kH = 128, kNO = 272;
-constexpr int64_t kOffW1 = 0, kOffb1 = 80 * 128, kOffW2 = kOffb1 + 128, kOffb2 = kOffW2 + 128 * 128,
-                  kOffW3 = kOffb2 + 128, kOffb3 = kOffW3 + 128 * 272, kNParam = kOffb3 + 272;
 static_assert(kNParam == DLS_MODEL_NPARAM, "parameter count");
+
+// inference forward (fused kernel); packs the bf16 weights after a change
+dls_status model_infer(dls_model* m, const float* feat, int64_t n, float* out, hipStream_t s) {
+  if (!m->packed_valid) {
+    HIP_TRY(m->packed.ensure(kPackedWeightBytes));
+    HIP_TRY(launch_pack_weights(m->params.as<float>(), m->packed.as<short>(), s));
+    m->packed_valid = true;
+  }
+  HIP_TRY(launch_mlp_forward(feat, n, m->norm.as<float>(), m->params.as<float>(), m->packed.as<short>(), out, s));
+  return DLS_OK;
+}
 
 dls_status model_workspace(dls_model* m, int64_t n) {
   if (n <= m->ws_n) return DLS_OK;
@@ -274,10 +284,9 @@ dls_status learned_eigen(dls_ctx* ctx, const void* d_field, const Problem& p, co
   HIP_TRY(ctx->feat.ensure(size_t(nb) * kNF * 4));
   HIP_TRY(ctx->mlp_out.ensure(size_t(nb) * kNO * 4));
   HIP_TRY(ctx->reject.ensure(size_t(nb)));
-  if (dls_status st = model_workspace(m, nb)) return st;
   HIP_TRY(launch_features(p.dtype, d_field, dims, ctx->desc.as<BlockDesc>(), nb, ctx->eps_v.as<double>(),
                           ctx->feat.as<float>(), s));
-  if (dls_status st = model_forward(m, ctx->feat.as<float>(), nb, true, ctx->mlp_out.as<float>(), s)) return st;
+  if (dls_status st = model_infer(m, ctx->feat.as<float>(), nb, ctx->mlp_out.as<float>(), s)) return st;
   HIP_TRY(launch_warmstart(ctx->gram.as<double>(), ctx->item_start.as<int32_t>(), ctx->desc.as<BlockDesc>(), nb,
                            ctx->eps_v.as<double>(), p.r_max, ctx->mlp_out.as<float>(), ctx->warm_iters,
                            ctx->warm_margin, ctx->rank.as<uint8_t>(), ctx->lam.as<double>(), ctx->basis.as<double>(),
@@ -536,6 +545,7 @@ dls_status dls_model_set(dls_model* m, const float* params, const float* norm) {
     for (int i = 16; i < 32; ++i)
       if (!(norm[i] > 0.f)) return fail(DLS_EINVAL, "normalisation scales must be > 0");
   HIP_TRY(hipMemcpy(m->params.p, params, kNParam * 4, hipMemcpyHostToDevice));
+  m->packed_valid = false;
   if (norm != nullptr) HIP_TRY(hipMemcpy(m->norm.p, norm, 32 * 4, hipMemcpyHostToDevice));
   HIP_TRY(hipMemset(m->m.p, 0, kNParam * 4));
   HIP_TRY(hipMemset(m->v.p, 0, kNParam * 4));
@@ -552,11 +562,16 @@ dls_status dls_model_get(const dls_model* m, float* params, float* norm) {
 }
 
 dls_status dls_model_forward(dls_model* m, const float* d_feat, int64_t n, int bf16, float* d_out, void* stream) {
-  if (m == nullptr || d_feat == nullptr || d_out == nullptr || n < 1) return fail(DLS_EINVAL, "bad argument");
+  if (m == nullptr || d_feat == nullptr || d_out == nullptr || n < 1 || bf16 < 0 || bf16 > 2)
+    return fail(DLS_EINVAL, "bad argument");
   HIP_TRY(hipSetDevice(m->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (dls_status st = model_workspace(m, n)) return st;
-  if (dls_status st = model_forward(m, d_feat, n, bf16 != 0, d_out, s)) return st;
+  if (bf16 == 1) {
+    if (dls_status st = model_infer(m, d_feat, n, d_out, s)) return st;
+  } else {
+    if (dls_status st = model_workspace(m, n)) return st;
+    if (dls_status st = model_forward(m, d_feat, n, bf16 != 0, d_out, s)) return st;
+  }
   HIP_TRY(hipStreamSynchronize(s));
   return DLS_OK;
 }
@@ -586,6 +601,7 @@ dls_status dls_model_train_step(dls_model* m, const float* d_feat, const int32_t
   m->step += 1;
   const float c1 = float(1.0 - std::pow(0.9, double(m->step)));
   const float c2 = float(1.0 - std::pow(0.999, double(m->step)));
+  m->packed_valid = false;
   HIP_TRY(launch_adam(m->params.as<float>(), m->grad.as<float>(), m->m.as<float>(), m->v.as<float>(), kNParam, lr, c1,
                       c2, s));
   if (loss_out == nullptr) HIP_TRY(hipStreamSynchronize(s));
@@ -598,6 +614,7 @@ dls_status dls_features(dls_ctx* ctx, const void* d_field, float* d_out, void* s
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Problem& p = ctx->prob;
+  if (p.window > 16) return fail(DLS_EINVAL, "features need window <= 16");
   const Dims dims{p.nx, p.ny, p.nz, p.nt};
   HIP_TRY(launch_features(p.dtype, d_field, dims, ctx->desc.as<BlockDesc>(), int64_t(ctx->plan.blocks.size()),
                           ctx->eps_v.as<double>(), d_out, s));

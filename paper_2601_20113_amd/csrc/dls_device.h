@@ -1,6 +1,7 @@
 // Device helpers shared by the gfx950 kernel files.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <stdint.h>
 
 namespace dls {
 
@@ -14,69 +15,76 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Cyclic Jacobi on the symmetric WP x WP matrix A (LDS, leading dimension
-// WP + 1), accumulating the rotations into V, with the parallel round-robin
-// ordering (WP / 2 disjoint rotations per step, WP - 1 steps per sweep).
-// Called by all 64 lanes of a one-wave workgroup.  Stops when the
-// off-diagonal norm falls below 1e-13 of the Frobenius norm, or after 12
-// sweeps.  Indices whose rows and columns are exactly zero are never
-// rotated (their (p, q) entry is 0).
-template <int WP>
-__device__ inline void jacobi_lds(double* A, double* V, double* alpha, double* beta, int* partner, int tid) {
-  constexpr int EPT = WP * WP / 64;
-  constexpr int LD = WP + 1;
-  for (int sweep = 0; sweep < 12; ++sweep) {
-    double off = 0.0, tot = 0.0;
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int idx = tid + 64 * e, i = idx / WP, j = idx % WP;
-      const double a = A[i * LD + j];
-      tot += a * a;
-      if (i != j) off += a * a;
-    }
-    off = wave_sum(off);
-    tot = wave_sum(tot);
-    if (!(off > 1e-26 * tot)) break;
-    for (int step = 0; step < WP - 1; ++step) {
-      if (tid < WP / 2) {
-        int p = rr_player(tid, step, WP), q = rr_player(WP - 1 - tid, step, WP);
-        if (p > q) { int t = p; p = q; q = t; }
-        const double app = A[p * LD + p], aqq = A[q * LD + q], apq = A[p * LD + q];
-        double c = 1.0, s = 0.0;
-        if (apq != 0.0) {
-          const double theta = (aqq - app) / (2.0 * apq);
-          double t = 1.0 / (fabs(theta) + sqrt(1.0 + theta * theta));
-          if (theta < 0.0) t = -t;
-          c = 1.0 / sqrt(1.0 + t * t);
-          s = t * c;
-        }
-        partner[p] = q; partner[q] = p;
-        alpha[p] = c; beta[p] = -s;
-        alpha[q] = c; beta[q] = s;
-      }
-      __syncthreads();
-      double na[EPT], nv[EPT];
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        const int idx = tid + 64 * e, i = idx / WP, j = idx % WP;
-        const int mi = partner[i], mj = partner[j];
-        const double ai = alpha[i], bi = beta[i], aj = alpha[j], bj = beta[j];
-        const double ri = fma(aj, A[i * LD + j], bj * A[i * LD + mj]);
-        const double rm = fma(aj, A[mi * LD + j], bj * A[mi * LD + mj]);
-        na[e] = fma(ai, ri, bi * rm);
-        nv[e] = fma(aj, V[i * LD + j], bj * V[i * LD + mj]);
-      }
-      __syncthreads();
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        const int idx = tid + 64 * e, i = idx / WP, j = idx % WP;
-        A[i * LD + j] = na[e];
-        V[i * LD + j] = nv[e];
-      }
-      __syncthreads();
-    }
-  }
+// Player at position pos of step `step` of the round-robin ordering on n
+// players (player 0 fixed, the others rotate), and the inverse map.
+__device__ __forceinline__ int rr_slot(int j, int step, int n) {
+  return j == 0 ? 0 : ((j - 1 - step) % (n - 1) + (n - 1)) % (n - 1) + 1;
+}
 
+// Keeps the compiler from moving LDS accesses across this point.  Lanes of
+// one wavefront see each other's earlier LDS writes (a wavefront's LDS
+// accesses complete in issue order), so this is all the ordering needed
+// between lanes of the same wavefront.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t u = uint64_t(__double_as_longlong(v));
+  const int lo = __builtin_amdgcn_update_dpp(0, int(uint32_t(u)), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(uint32_t(u >> 32)), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)((uint64_t(uint32_t(hi)) << 32) | uint64_t(uint32_t(lo))));
+}
+
+// Sum over the 16 lanes of a DPP row.  Each step adds a lane's value to its
+// partner's (x + y in one lane, y + x in the other: the same bits), so all
+// 16 lanes end with the same result.
+__device__ __forceinline__ double row_sum(double v) {
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
+  return v;
+}
+
+// Sum over an aligned group of G lanes (16 or 32), bitwise equal in every
+// lane of the group.
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+  v = row_sum(v);
+  if constexpr (G == 32) v += __shfl_xor(v, 16, 64);
+  return v;
+}
+
+// Parameters of the Jacobi rotation that annihilates apq (Golub & Van Loan,
+// symmetric Schur 2x2): t = sign(theta) / (|theta| + sqrt(1 + theta^2)),
+// theta = (aqq - app) / (2 apq), c = 1 / sqrt(1 + t^2), s = t c.  Any t
+// gives an exactly orthogonal rotation as long as c and s agree, so t comes
+// from the hardware reciprocal and square-root estimates; c is then refined
+// to full precision by two Newton steps on 1 / sqrt(1 + t^2).
+__device__ __forceinline__ void jacobi_rotation(double app, double aqq, double apq, double& c, double& s) {
+  c = 1.0;
+  s = 0.0;
+  if (!(fabs(apq) > 1e-300)) return;
+  const double theta = (aqq - app) * __builtin_amdgcn_rcp(2.0 * apq);
+  const double at = fabs(theta);
+  double t;
+  if (at > 1e150) {
+    t = 0.5 * __builtin_amdgcn_rcp(at);
+  } else {
+    const double u = fma(theta, theta, 1.0);
+    t = __builtin_amdgcn_rcp(at + u * __builtin_amdgcn_rsq(u));
+  }
+  if (theta < 0.0) t = -t;
+  const double u = fma(t, t, 1.0);
+  double y = __builtin_amdgcn_rsq(u);
+  y = y * fma(-0.5 * u * y, y, 1.5);
+  y = y * fma(-0.5 * u * y, y, 1.5);
+  c = y;
+  s = t * y;
 }
 
 }  // namespace dls

@@ -43,6 +43,20 @@ hipError_t launch_colsum(const float* G, int64_t n, int cols, float* out, hipStr
 hipError_t launch_relu_mask(float* dh, const float* h, int64_t n, hipStream_t s);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float c1, float c2,
                        hipStream_t s);
+// Warm-start network 80 -> 128 -> 128 -> 272 (ReLU), flat FP32 parameters
+// W1 (80 x 128, row-major [in][out]), b1, W2, b2, W3, b3.
+constexpr int kNF = 80, kH = 128, kNO = 272;
+constexpr int64_t kOffW1 = 0, kOffb1 = 80 * 128, kOffW2 = kOffb1 + 128, kOffb2 = kOffW2 + 128 * 128,
+                  kOffW3 = kOffb2 + 128, kOffb3 = kOffW3 + 128 * 272, kNParam = kOffb3 + 272;
+
+// Inference forward of the network, the three layers fused (bf16 products,
+// FP32 accumulation, bit-identical to the layer-by-layer path).  `packed`
+// holds the weights as written by launch_pack_weights.
+constexpr int kPackLd = kH + 4;  // bf16 leading dimension of a packed layer ([out][in])
+constexpr int64_t kPackedWeightBytes = int64_t(2) * kPackLd * (kH + kH + kNO);
+hipError_t launch_pack_weights(const float* P, short* packed, hipStream_t s);
+hipError_t launch_mlp_forward(const float* raw, int64_t n, const float* norm, const float* P, const short* packed,
+                              float* out, hipStream_t s);
 hipError_t launch_warmstart(const double* gpart, const int32_t* item_start, const BlockDesc* desc, int64_t nblocks,
                             const double* eps_v, int r_max, const float* mlp_out, int iters, int margin,
                             uint8_t* rank, double* lam, double* basis, int64_t* qv_size, int64_t* qa_size,

@@ -3,10 +3,10 @@
 //   k_gram    Gram product G = X X^T of every block slice on the matrix cores
 //             (v_mfma_f32_16x16x4f32, FP32 products; every 64-point chunk is
 //             flushed into FP64 accumulators), Sec. 2.7.1 cross-product SVD.
-//   k_eigen   one wavefront per block: sum of the slice Grams in FP64,
-//             cyclic Jacobi in FP64 with a parallel (round-robin) ordering,
-//             Rayleigh quotients, descending sort, canonical signs, and the
-//             rank rule of Sec. 2.4 Eq. (4) / Alg. 1 step 3.
+//   k_eigen   W lanes per block: sum of the slice Grams in FP64, cyclic
+//             Jacobi in FP64 with a parallel (round-robin) ordering,
+//             descending sort, canonical signs, and the rank rule of
+//             Sec. 2.4 Eq. (4) / Alg. 1 step 3.
 //   k_scan_*  exclusive scan of the per-block payload sizes (the offset scan
 //             the paper does with MPI_Scan, Sec. 2.7.2).
 //   k_encode  projection A = X^T V_r (Eq. (5)), coefficient and basis
@@ -21,6 +21,12 @@
 
 #include "dls_device.h"
 #include "dls_kernels.h"
+
+// steps of a Jacobi sweep unrolled per loop iteration (1: position
+// rotation by register moves; more trades registers for fewer moves)
+#ifndef DLS_JACOBI_UNROLL
+#define DLS_JACOBI_UNROLL 1
+#endif
 
 namespace dls {
 
@@ -153,127 +159,187 @@ __global__ __launch_bounds__(256) void k_gram(const T* __restrict__ F, Dims dims
 }
 
 // ---------------------------------------------------------------------------
-// Eigensolve + rank: one 64-lane workgroup per block.
+// Eigensolve + rank.  WP lanes per block (lane i owns row i of the Gram
+// matrix A and row i of the accumulated rotations V, in registers), 256 / WP
+// blocks per workgroup.  Cyclic Jacobi in FP64 with the parallel round-robin
+// ordering: at each step the WP / 2 disjoint pairs sit at positions
+// (k, WP-1-k); the columns are held in position order and rotated by one
+// position after every step, so the partner of register k is always register
+// WP-1-k.  Each step: every lane publishes its row in LDS, the lower lane of
+// each pair computes the rotation, then every lane forms its new row from
+// its own row and its partner's.  A group only touches its own LDS and its
+// lanes are active together, so no workgroup barrier is used.
 // ---------------------------------------------------------------------------
 template <int WP>
-__global__ __launch_bounds__(64) void k_eigen(const double* __restrict__ gpart,
-                                              const int32_t* __restrict__ item_start,
-                                              const BlockDesc* __restrict__ desc,
-                                              const double* __restrict__ eps_v, int r_max,
-                                              uint8_t* __restrict__ rank_out,
-                                              double* __restrict__ lam_out,
-                                              double* __restrict__ basis_out,
-                                              int64_t* __restrict__ qv_size,
-                                              int64_t* __restrict__ qa_size,
-                                              unsigned long long* __restrict__ nraw,
-                                              const uint8_t* __restrict__ only) {
-  if (only != nullptr && only[blockIdx.x] == 0) return;
-  constexpr int EPT = WP * WP / 64;
+__global__ __launch_bounds__(256) void k_eigen(const double* __restrict__ gpart,
+                                               const int32_t* __restrict__ item_start,
+                                               const BlockDesc* __restrict__ desc, int64_t nblocks,
+                                               const double* __restrict__ eps_v, int r_max,
+                                               uint8_t* __restrict__ rank_out,
+                                               double* __restrict__ lam_out,
+                                               double* __restrict__ basis_out,
+                                               int64_t* __restrict__ qv_size,
+                                               int64_t* __restrict__ qa_size,
+                                               unsigned long long* __restrict__ nraw,
+                                               const uint8_t* __restrict__ only) {
+  constexpr int GPW = 256 / WP;
   constexpr int LD = WP + 1;
-  __shared__ double G[WP * LD], A[WP * LD], V[WP * LD];
-  __shared__ double alpha[WP], beta[WP], lam_s[WP], tail_s[WP + 1];
-  __shared__ int partner[WP], perm[WP];
-  const int b = blockIdx.x, tid = threadIdx.x;
+  __shared__ double sA[GPW][WP * LD];
+  __shared__ double2 sCS[GPW][WP];
+  __shared__ double sLam[GPW][WP], sSg[GPW][WP];
+  __shared__ int sPerm[GPW][WP];
+  const int grp = threadIdx.x / WP, i = threadIdx.x % WP;
+  const int64_t b = int64_t(blockIdx.x) * GPW + grp;
+  if (b >= nblocks) return;
+  if (only != nullptr && only[b] == 0) return;
+  double* A = sA[grp];
+  double2* CS = sCS[grp];
   const BlockDesc d = desc[b];
   const int W = d.w(), M = d.m;
-
   const int i0 = item_start[b], i1 = item_start[b + 1];
-  double gv[EPT];
+
+  // Gram row i = sum of the slice Grams, symmetrised through LDS
+  double a[WP], v[WP];
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int idx = tid + 64 * e;
+  for (int j = 0; j < WP; ++j) {
     double s = 0.0;
-    for (int it = i0; it < i1; ++it) s += gpart[int64_t(it) * WP * WP + idx];
-    gv[e] = s;
-    G[(idx / WP) * LD + idx % WP] = s;
+    for (int it = i0; it < i1; ++it) s += gpart[int64_t(it) * WP * WP + i * WP + j];
+    a[j] = s;
+    A[i * LD + j] = s;
   }
-  __syncthreads();
+  wave_sync();
   bool fin = true;
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int idx = tid + 64 * e, i = idx / WP, j = idx % WP;
-    const double s = 0.5 * (gv[e] + G[j * LD + i]);
-    fin = fin && isfinite(s);
-    gv[e] = s;
+  for (int j = 0; j < WP; ++j) {
+    a[j] = 0.5 * (a[j] + A[j * LD + i]);
+    fin = fin && isfinite(a[j]);
+    v[j] = (j == i) ? 1.0 : 0.0;
   }
-  __syncthreads();
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int idx = tid + 64 * e, i = idx / WP, j = idx % WP;
-    G[i * LD + j] = gv[e];
-    A[i * LD + j] = gv[e];
-    V[i * LD + j] = (i == j) ? 1.0 : 0.0;
-  }
-  fin = __syncthreads_and(fin);
-  if (!fin) {  // non-finite input: raw block, every point becomes an escape
-    if (tid == 0) {
+  wave_sync();
+  if (group_sum<WP>(fin ? 0.0 : 1.0) != 0.0) {  // non-finite input: raw block
+    if (i == 0) {
       rank_out[b] = 0;
       qv_size[b] = 0;
       qa_size[b] = 0;
       atomicAdd(nraw, 1ULL);
     }
-    if (tid < WP) lam_out[int64_t(b) * WP + tid] = 0.0;
+    lam_out[b * WP + i] = 0.0;
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int idx = tid + 64 * e;
-      basis_out[int64_t(b) * WP * WP + idx] = (idx / WP == idx % WP) ? 1.0 : 0.0;
-    }
+    for (int k = 0; k < WP; ++k) basis_out[(b * WP + k) * WP + i] = (k == i) ? 1.0 : 0.0;
     return;
   }
 
-  jacobi_lds<WP>(A, V, alpha, beta, partner, tid);
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    // positions are in natural order at a sweep boundary
+    double off = 0.0, tot = 0.0;
+#pragma unroll
+    for (int j = 0; j < WP; ++j) {
+      const double x = a[j] * a[j];
+      tot += x;
+      off += (j == i) ? 0.0 : x;
+    }
+    off = group_sum<WP>(off);
+    tot = group_sum<WP>(tot);
+    if (!(off > 1e-26 * tot)) break;
+#pragma unroll DLS_JACOBI_UNROLL
+    for (int step = 0; step < WP - 1; ++step) {
+#pragma unroll
+      for (int k = 0; k < WP; ++k) A[i * LD + k] = a[k];
+      wave_sync();
+      const int pos = rr_slot(i, step, WP);
+      const int mpos = WP - 1 - pos;
+      const int m = rr_player(mpos, step, WP);
+      if (i < m) {
+        double c, s;
+        jacobi_rotation(A[i * LD + pos], A[m * LD + mpos], A[i * LD + mpos], c, s);
+        CS[pos] = make_double2(c, -s);
+        CS[mpos] = make_double2(c, s);
+      }
+      wave_sync();
+      const double2 ci = CS[pos];
+      double pm[WP];
+#pragma unroll
+      for (int k = 0; k < WP; ++k) pm[k] = A[m * LD + k];
+#pragma unroll
+      for (int k = 0; k < WP / 2; ++k) {
+        const int mk = WP - 1 - k;
+        const double2 ck = CS[k], cm = CS[mk];
+        // row rotation (own row with the partner's), then column rotation
+        const double rk = fma(ci.x, a[k], ci.y * pm[k]);
+        const double rm = fma(ci.x, a[mk], ci.y * pm[mk]);
+        a[k] = fma(ck.x, rk, ck.y * rm);
+        a[mk] = fma(cm.x, rm, cm.y * rk);
+        const double vk = fma(ck.x, v[k], ck.y * v[mk]);
+        const double vm = fma(cm.x, v[mk], cm.y * v[k]);
+        v[k] = vk;
+        v[mk] = vm;
+      }
+      // next step: position k takes the column of position k + 1, the last
+      // position takes the column of position 1, position 0 stays
+      const double a1 = a[1], v1 = v[1];
+#pragma unroll
+      for (int k = 1; k < WP - 1; ++k) {
+        a[k] = a[k + 1];
+        v[k] = v[k + 1];
+      }
+      a[WP - 1] = a1;
+      v[WP - 1] = v1;
+      wave_sync();
+    }
+  }
 
-  // descending order of the Jacobi eigenvalues (stable by index).  Padded
-  // indices t >= W_b have exactly zero Gram rows, so every rotation touching
-  // them is the identity and their columns stay unit vectors on the padded
-  // rows: they sort last, after every real mode.
-  if (tid < WP) perm[tid] = tid;
-  __syncthreads();
-  if (tid < WP) {
-    const double dk = tid < W ? A[tid * LD + tid] : -INFINITY;
+  // V rows and the diagonal to LDS; descending order of the eigenvalue
+  // estimates diag(A) (stable by index).  Padded indices i >= W_b have zero
+  // Gram rows, are never rotated, and sort last.
+  double di = 0.0;
+#pragma unroll
+  for (int j = 0; j < WP; ++j) {
+    A[i * LD + j] = v[j];
+    di = (j == i) ? a[j] : di;
+  }
+  sLam[grp][i] = i < W ? di : -INFINITY;
+  wave_sync();
+  {
+    const double dk = sLam[grp][i];
     int pos = 0;
     for (int j = 0; j < WP; ++j) {
-      const double dj = j < W ? A[j * LD + j] : -INFINITY;
-      pos += (dj > dk || (dj == dk && j < tid)) ? 1 : 0;
+      const double dj = sLam[grp][j];
+      pos += (dj > dk || (dj == dk && j < i)) ? 1 : 0;
     }
-    perm[pos] = tid;
+    sPerm[grp][pos] = i;
   }
-  __syncthreads();
-  // Rayleigh quotient and canonical sign of sorted column `tid`
-  double sgn = 1.0;
-  int col = 0;
-  if (tid < WP) {
-    col = perm[tid];
-    col = (col >= 0 && col < WP) ? col : tid;
-    double lam = 0.0;
-    for (int i = 0; i < WP; ++i) {
-      double gi = 0.0;
-      for (int j = 0; j < WP; ++j) gi = fma(G[i * LD + j], V[j * LD + col], gi);
-      lam = fma(V[i * LD + col], gi, lam);
+  wave_sync();
+  // sorted column i: its eigenvalue and canonical sign (largest |component|
+  // positive, lowest row on a tie)
+  const int col = sPerm[grp][i];
+  const double lam = fmax(i < W ? sLam[grp][col] : 0.0, 0.0);
+  {
+    double best = -1.0, sg = 1.0;
+    for (int t = 0; t < WP; ++t) {
+      const double x = A[t * LD + col];
+      if (fabs(x) > best) { best = fabs(x); sg = x < 0.0 ? -1.0 : 1.0; }
     }
-    lam_s[tid] = lam > 0.0 ? lam : 0.0;
-    double best = -1.0;
-    for (int i = 0; i < WP; ++i) {
-      const double a = fabs(V[i * LD + col]);
-      if (a > best) { best = a; sgn = V[i * LD + col] < 0.0 ? -1.0 : 1.0; }
-    }
+    sSg[grp][i] = sg;
   }
-  __syncthreads();
-  if (tid < WP) {
-    lam_out[int64_t(b) * WP + tid] = lam_s[tid];
-    double* bo = basis_out + (int64_t(b) * WP + tid) * WP;
-    for (int t = 0; t < WP; ++t) bo[t] = sgn * V[t * LD + col];
-  }
-  if (tid == 0) {
+  wave_sync();
+  sLam[grp][i] = lam;
+  lam_out[b * WP + i] = lam;
+#pragma unroll 4
+  for (int k = 0; k < WP; ++k) basis_out[(b * WP + k) * WP + i] = sSg[grp][k] * A[i * LD + sPerm[grp][k]];
+  wave_sync();
+  if (i == 0) {
     const double eps = eps_v[d.var];
     const double tau = kKappa * eps * eps * double(M) * double(W);
     int rcap = r_max < W ? r_max : W;
     rcap = rcap < M ? rcap : M;
-    tail_s[WP] = 0.0;
-    for (int k = WP - 1; k >= 0; --k) tail_s[k] = tail_s[k + 1] + lam_s[k];
+    // suffix sums tail_k = sum_{j >= k} lambda_j; r = the smallest k <= rcap
+    // with tail_k <= tau, else rcap
+    double tail = 0.0;
     int r = rcap;
-    for (int k = 1; k <= rcap; ++k)
-      if (tail_s[k] <= tau) { r = k; break; }
+    for (int k = WP - 1; k >= 1; --k) {
+      tail += sLam[grp][k];
+      if (k <= rcap && tail <= tau) r = k;
+    }
     rank_out[b] = uint8_t(r);
     qv_size[b] = 4 * pad16(int64_t(W) * r);
     qa_size[b] = 4 * pad16(int64_t(M) * r);
@@ -749,11 +815,13 @@ hipError_t launch_eigen(int wp, const double* gpart, const int32_t* item_start, 
                         double* basis, int64_t* qv_size, int64_t* qa_size, unsigned long long* nraw,
                         const uint8_t* only, hipStream_t s) {
   if (nblocks == 0) return hipSuccess;
-  const dim3 g{unsigned(nblocks)}, bl{64};
+  const dim3 bl{256};
   if (wp == 16)
-    hipLaunchKernelGGL(k_eigen<16>, g, bl, 0, s, gpart, item_start, desc, eps_v, r_max, rank, lam, basis, qv_size, qa_size, nraw, only);
+    hipLaunchKernelGGL(k_eigen<16>, dim3{unsigned((nblocks + 15) / 16)}, bl, 0, s, gpart, item_start, desc, nblocks,
+                       eps_v, r_max, rank, lam, basis, qv_size, qa_size, nraw, only);
   else
-    hipLaunchKernelGGL(k_eigen<32>, g, bl, 0, s, gpart, item_start, desc, eps_v, r_max, rank, lam, basis, qv_size, qa_size, nraw, only);
+    hipLaunchKernelGGL(k_eigen<32>, dim3{unsigned((nblocks + 7) / 8)}, bl, 0, s, gpart, item_start, desc, nblocks,
+                       eps_v, r_max, rank, lam, basis, qv_size, qa_size, nraw, only);
   return hipGetLastError();
 }
 

@@ -35,38 +35,93 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_features(const T* __restrict__ F, Dims dims,
                                                   const BlockDesc* __restrict__ desc, int64_t nblocks,
                                                   const double* __restrict__ eps_v, float* __restrict__ feat) {
-  const int lane = threadIdx.x & 63;
-  const int64_t b = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  constexpr int kStage = 1024;  // blocks up to this many points keep their time sums in LDS
+  __shared__ double sts[4][kStage];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t b = int64_t(blockIdx.x) * 4 + wv;
   if (b >= nblocks) return;
   const BlockDesc d = desc[b];
   const int W = d.w(), M = d.m, px = d.px(), py = d.py(), pz = d.pz();
   const int64_t nxy = dims.nx * dims.ny, tstride = dims.nz * nxy;
   const T* base = F + (((int64_t(d.var) * dims.nt + d.t0) * dims.nz + d.z0) * dims.ny + d.y0) * dims.nx + d.x0;
-  auto at = [&](int t, int i, int j, int k) {
-    return double(base[int64_t(t) * tstride + int64_t(k) * nxy + int64_t(j) * dims.nx + i]);
+  const bool stage = M <= kStage;
+  // the W values of point p (W <= 16), all loads issued before any use
+  auto load_point = [&](int p, int64_t shift, double* x) {
+    const int i = p % px, rho = p / px, j = rho % py, k = rho / py;
+    const T* pt = base + int64_t(k) * nxy + int64_t(j) * dims.nx + i + shift;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) x[t] = (t < W) ? double(pt[int64_t(t) * tstride]) : 0.0;
   };
   double s1 = 0, s2 = 0, mn = INFINITY, mx = -INFINITY, adt = 0, sdt = 0, sdt2 = 0, adx = 0, ady = 0, tme = 0;
-  for (int p = lane; p < M; p += 64) {
-    const int i = p % px, rho = p / px, j = rho % py, k = rho / py;
-    double prev = 0.0, ts = 0.0;
-    for (int t = 0; t < W; ++t) {
-      const double x = at(t, i, j, k);
-      s1 += x;
-      s2 += x * x;
-      mn = fmin(mn, x);
-      mx = fmax(mx, x);
-      ts += x;
-      if (t > 0) {
-        const double dt = x - prev;
-        adt += fabs(dt);
-        sdt += dt;
-        sdt2 += dt * dt;
+  // first-pass sums of point p from its values x and, where they exist, its
+  // +x and +y neighbours xr, xd
+  auto accumulate = [&](int p, const double* x, const double* xr, const double* xd) {
+    const int i = p % px, j = (p / px) % py;
+    double ts = 0.0;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      if (t < W) {
+        const double v = x[t];
+        s1 += v;
+        s2 += v * v;
+        mn = fmin(mn, v);
+        mx = fmax(mx, v);
+        ts += v;
+        if (t > 0) {
+          const double dt = v - x[t - 1];
+          adt += fabs(dt);
+          sdt += dt;
+          sdt2 += dt * dt;
+        }
+        if (i + 1 < px) adx += fabs(xr[t] - v);
+        if (j + 1 < py) ady += fabs(xd[t] - v);
       }
-      if (i + 1 < px) adx += fabs(at(t, i + 1, j, k) - x);
-      if (j + 1 < py) ady += fabs(at(t, i, j + 1, k) - x);
-      prev = x;
     }
     tme += ts * ts;
+    if (stage) sts[wv][p] = ts;
+  };
+  // second-pass (central) sums of point p
+  double c3 = 0, c4 = 0, l1 = 0, l2 = 0, cvar = 0;
+  auto central = [&](const double* x, double mu) {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      if (t < W) {
+        const double y = x[t] - mu;
+        const double y2 = y * y;
+        cvar += y2;
+        c3 += y2 * y;
+        c4 += y2 * y2;
+        if (t >= 1) l1 += y * (x[t - 1] - mu);
+        if (t >= 2) l2 += y * (x[t - 2] - mu);
+      }
+    }
+  };
+  const bool one = M <= 64;  // one point per lane: neighbours come from other lanes, values stay in registers
+  double x1[16];
+  if (one) {
+    const bool act = lane < M;
+    if (act) {
+      load_point(lane, 0, x1);
+    } else {
+#pragma unroll
+      for (int t = 0; t < 16; ++t) x1[t] = 0.0;
+    }
+    double xr[16], xd[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      xr[t] = __shfl(x1[t], lane + 1, 64);
+      xd[t] = __shfl(x1[t], lane + px, 64);
+    }
+    if (act) accumulate(lane, x1, xr, xd);
+  } else {
+    for (int p = lane; p < M; p += 64) {
+      const int i = p % px, j = (p / px) % py;
+      double x[16], xr[16], xd[16];
+      load_point(p, 0, x);
+      if (i + 1 < px) load_point(p, 1, xr);
+      if (j + 1 < py) load_point(p, dims.nx, xd);
+      accumulate(p, x, xr, xd);
+    }
   }
   s1 = wave_sum(s1); s2 = wave_sum(s2); adt = wave_sum(adt); sdt = wave_sum(sdt); sdt2 = wave_sum(sdt2);
   adx = wave_sum(adx); ady = wave_sum(ady); tme = wave_sum(tme);
@@ -76,26 +131,20 @@ __global__ __launch_bounds__(256) void k_features(const T* __restrict__ F, Dims 
   }
   const double n = double(W) * M;
   const double mu = s1 / n;
-  double c3 = 0, c4 = 0, l1 = 0, l2 = 0, cvar = 0;
-  for (int p = lane; p < M; p += 64) {
-    const int i = p % px, rho = p / px, j = rho % py, k = rho / py;
-    double x1 = 0, x2 = 0;
-    for (int t = 0; t < W; ++t) {
-      const double y = at(t, i, j, k) - mu;
-      const double y2 = y * y;
-      cvar += y2;
-      c3 += y2 * y;
-      c4 += y2 * y2;
-      if (t >= 1) l1 += y * x1;
-      if (t >= 2) l2 += y * x2;
-      x2 = x1;
-      x1 = y;
+  if (one) {
+    if (lane < M) central(x1, mu);
+  } else {
+    for (int p = lane; p < M; p += 64) {
+      double x[16];
+      load_point(p, 0, x);
+      central(x, mu);
     }
   }
   cvar = wave_sum(cvar); c3 = wave_sum(c3); c4 = wave_sum(c4); l1 = wave_sum(l1); l2 = wave_sum(l2);
   const double var = cvar / n;
   const double sd = sqrt(var);
   const double inv = sd > 0.0 ? 1.0 / sd : 0.0;
+  wave_sync();
   // pooled time-mean: lane c owns cell (row group c / 8, column group c % 8)
   double cellv;
   {
@@ -105,10 +154,17 @@ __global__ __launch_bounds__(256) void k_features(const T* __restrict__ F, Dims 
     if (j1 <= j0) { j0 = (bb * py) / 8; j1 = j0 + 1; }
     if (i1 <= i0) { i0 = (aa * px) / 8; i1 = i0 + 1; }
     double s = 0.0;
-    for (int t = 0; t < W; ++t)
+    if (stage) {
       for (int kk = 0; kk < pz; ++kk)
         for (int jj = j0; jj < j1; ++jj)
-          for (int ii = i0; ii < i1; ++ii) s += at(t, ii, jj, kk);
+          for (int ii = i0; ii < i1; ++ii) s += sts[wv][(kk * py + jj) * px + ii];
+    } else {
+      for (int t = 0; t < W; ++t)
+        for (int kk = 0; kk < pz; ++kk)
+          for (int jj = j0; jj < j1; ++jj)
+            for (int ii = i0; ii < i1; ++ii)
+              s += double(base[int64_t(t) * tstride + int64_t(kk) * nxy + int64_t(jj) * dims.nx + ii]);
+    }
     cellv = s / double((i1 - i0) * (j1 - j0) * pz * W);
   }
   float* o = feat + b * 80;
@@ -198,6 +254,114 @@ __global__ __launch_bounds__(256) void k_gemm(const float* __restrict__ A, int l
   }
 }
 
+// ---------------------------------------------------------------------------
+// Inference forward, three layers fused: 64 rows per workgroup (16 per
+// wave).  Each layer's weights are staged in LDS as bf16, transposed to
+// [out][in] so a lane's four k values are contiguous; the hidden
+// activations pass through LDS (bf16) to change from the MFMA output layout
+// (lane = column) to the operand layout (lane = row).  Products, the k order
+// of the accumulation and every rounding are those of k_gemm with BF16.
+// ---------------------------------------------------------------------------
+// bf16 copies of W1, W2, W3, each transposed to [out][in] with leading
+// dimension kPackLd (inputs beyond K are zero): the LDS image the fused
+// forward stages with plain 16-byte copies.
+__global__ __launch_bounds__(256) void k_pack_weights(const float* __restrict__ P, short* __restrict__ packed) {
+  const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t rows = kH + kH + kNO;
+  if (idx >= rows * kPackLd) return;
+  int j = int(idx / kPackLd);
+  const int k = int(idx % kPackLd);
+  const float* Wg;
+  int K, N;
+  if (j < kH) {
+    Wg = P + kOffW1; K = kNF; N = kH;
+  } else if (j < 2 * kH) {
+    Wg = P + kOffW2; K = kH; N = kH; j -= kH;
+  } else {
+    Wg = P + kOffW3; K = kH; N = kNO; j -= 2 * kH;
+  }
+  packed[idx] = k < K ? to_bf16(Wg[int64_t(k) * N + j]) : short(0);
+}
+
+__global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ raw, int64_t n,
+                                                     const float* __restrict__ norm, const float* __restrict__ P,
+                                                     const short* __restrict__ packed, float* __restrict__ out) {
+  constexpr int LW = kPackLd;
+  __shared__ __align__(16) short sW[kNO * LW];
+  __shared__ __align__(16) short sH[4][16 * LW];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, r = lane & 15, q = lane >> 4;
+  const int64_t row0 = int64_t(blockIdx.x) * 64 + wave * 16;
+  const bool row_ok = row0 + r < n;
+  short* H = sH[wave];
+  // layer `l` (0, 1, 2) of N outputs: copy its packed image into LDS
+  auto stage = [&](int l, int N) {
+    const uint4* src = reinterpret_cast<const uint4*>(packed + int64_t(l) * kH * LW);
+    uint4* dst = reinterpret_cast<uint4*>(sW);
+    const int n16 = N * LW * 2 / 16;
+    for (int i = threadIdx.x; i < n16; i += 256) dst[i] = src[i];
+  };
+  // one layer: A fragments from `afrag(ks)`, K = 16 * KS inputs, N outputs;
+  // epilogue(nt, acc) consumes each 16 x 16 output tile
+  auto layer = [&](auto afrag, int KS, int N, auto epilogue) {
+    for (int nt = 0; nt < N / 16; ++nt) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      for (int ks = 0; ks < KS; ++ks) {
+        const bf16x4 bv = *reinterpret_cast<const bf16x4*>(&sW[(nt * 16 + r) * LW + ks * 16 + 4 * q]);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(afrag(ks), bv, acc, 0, 0, 0);
+      }
+      epilogue(nt, acc);
+    }
+  };
+  auto hidden_out = [&](const float* bias) {
+    return [=](int nt, f32x4 acc) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        float c = acc[v] + bias[nt * 16 + r];
+        c = c > 0.f ? c : 0.f;
+        H[(4 * q + v) * LW + nt * 16 + r] = to_bf16(c);
+      }
+    };
+  };
+  auto from_h = [&](int ks) { return *reinterpret_cast<const bf16x4*>(&H[r * LW + ks * 16 + 4 * q]); };
+
+  // layer 1: z = (raw - mean) / std on the 16 statistics, raw on the rest
+  bf16x4 z[5];
+#pragma unroll
+  for (int ks = 0; ks < 5; ++ks)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = ks * 16 + 4 * q + e;
+      float v = row_ok ? raw[(row0 + r) * kNF + k] : 0.f;
+      if (row_ok && k < 16) v = (v - norm[k]) / norm[16 + k];
+      z[ks][e] = to_bf16(v);
+    }
+  stage(0, kH);
+  __syncthreads();
+  layer([&](int ks) { return z[ks]; }, 5, kH, hidden_out(P + kOffb1));
+  __syncthreads();
+  stage(1, kH);
+  __syncthreads();
+  // h1 is read from H and h2 written back into it: read all fragments first
+  bf16x4 h[8];
+#pragma unroll
+  for (int ks = 0; ks < 8; ++ks) h[ks] = from_h(ks);
+  __syncthreads();
+  layer([&](int ks) { return h[ks]; }, 8, kH, hidden_out(P + kOffb2));
+  __syncthreads();
+  stage(2, kNO);
+  __syncthreads();
+#pragma unroll
+  for (int ks = 0; ks < 8; ++ks) h[ks] = from_h(ks);
+  const float* b3 = P + kOffb3;
+  layer([&](int ks) { return h[ks]; }, 8, kNO, [&](int nt, f32x4 acc) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t i = row0 + 4 * q + v;
+      if (i < n) out[i * kNO + nt * 16 + r] = acc[v] + b3[nt * 16 + r];
+    }
+  });
+}
+
 // Loss CE(logits, r - 1) + masked MSE of the basis, per sample; gout = dL/dout
 // of the batch-mean loss.
 __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ out, const int32_t* __restrict__ rank,
@@ -278,32 +442,9 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
 // issue order).  Predictions of more than kWarmMax columns go to the
 // Jacobi fallback.
 // ---------------------------------------------------------------------------
-constexpr int kWarmMax = 8;
-
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const uint64_t u = uint64_t(__double_as_longlong(v));
-  const int lo = __builtin_amdgcn_update_dpp(0, int(uint32_t(u)), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, int(uint32_t(u >> 32)), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double((long long)((uint64_t(uint32_t(hi)) << 32) | uint64_t(uint32_t(lo))));
-}
-
-// Sum over the 16 lanes of a DPP row.  Each step adds a lane's value to its
-// partner's (x + y in one lane, y + x in the other: the same bits), so all
-// 16 lanes end with the same result.
-__device__ __forceinline__ double row_sum(double v) {
-  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
-  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dpp_f64<0x141>(v);  // row_half_mirror
-  v += dpp_f64<0x140>(v);  // row_mirror
-  return v;
-}
+constexpr int kWarmMax = 8;      // most columns an attempt iterates
+constexpr int kRetryExtra = 4;   // columns the second attempt adds
+constexpr int kRetryIters = 2;   // iterations the second attempt adds
 
 // Orthonormalise the first r columns of Q (row t in q[]), classical
 // Gram-Schmidt applied twice per column; a column that collapses is
@@ -367,16 +508,7 @@ __device__ void jacobi_group(double* H, double* U, double* alpha, double* beta, 
         int p = rr_player(t, step, ne), q = rr_player(ne - 1 - t, step, ne);
         if (p > q) { const int x = p; p = q; q = x; }
         double c = 1.0, s = 0.0;
-        if (q < n) {
-          const double app = H[p * LD + p], aqq = H[q * LD + q], apq = H[p * LD + q];
-          if (apq != 0.0) {
-            const double theta = (aqq - app) / (2.0 * apq);
-            double tt = 1.0 / (fabs(theta) + sqrt(1.0 + theta * theta));
-            if (theta < 0.0) tt = -tt;
-            c = 1.0 / sqrt(1.0 + tt * tt);
-            s = tt * c;
-          }
-        }
+        if (q < n) jacobi_rotation(H[p * LD + p], H[q * LD + q], H[p * LD + q], c, s);
         partner[p] = q; partner[q] = p;
         alpha[p] = c; beta[p] = -s;
         alpha[q] = c; beta[q] = s;
@@ -424,6 +556,7 @@ __global__ __launch_bounds__(256) void k_warmstart(const double* __restrict__ gp
                                                    const BlockDesc* __restrict__ desc, int64_t nblocks,
                                                    const double* __restrict__ eps_v, int r_max,
                                                    const float* __restrict__ mlp_out, int iters, int margin,
+                                                   int retry,
                                                    uint8_t* __restrict__ rank_out, double* __restrict__ lam_out,
                                                    double* __restrict__ basis_out, int64_t* __restrict__ qv_size,
                                                    int64_t* __restrict__ qa_size, uint8_t* __restrict__ reject,
@@ -442,7 +575,9 @@ __global__ __launch_bounds__(256) void k_warmstart(const double* __restrict__ gp
   double* H = sH[grp];
   double* U = sU[grp];
   int verdict = 0;  // 0: no block, 1: accepted, 2: rejected
-  if (b < nblocks) {
+  if (retry && b < nblocks && reject[b] == 0) {
+    verdict = 1;  // accepted by attempt 1
+  } else if (b < nblocks) {
     const BlockDesc d = desc[b];
     const int W = d.w(), M = d.m;
     const int i0 = item_start[b], i1 = item_start[b + 1];
@@ -468,14 +603,21 @@ __global__ __launch_bounds__(256) void k_warmstart(const double* __restrict__ gp
       if (o[k] > best) { best = o[k]; rhat = k; }
     rhat = rhat + 1 + margin;
     rhat = rhat < rcap ? rhat : rcap;
+    // attempt 1: the predicted rhat columns and `iters` iterations; attempt 2
+    // (a second launch, blocks rejected by attempt 1 only): kRetryExtra more
+    // columns, kRetryIters more iterations
+    int rhat2 = rhat + kRetryExtra;
+    rhat2 = rhat2 < RH ? rhat2 : RH;
+    rhat2 = rhat2 < rcap ? rhat2 : rcap;
+    const int nc = retry ? rhat2 : rhat;
+    const int nit = retry ? iters + kRetryIters : iters;
     int r = 0;
-    double z[RH];
-    if (fin && rhat <= RH) {
+    if (fin && nc <= RH && (!retry || rhat2 > rhat)) {
       double q[RH];
 #pragma unroll
-      for (int k = 0; k < RH; ++k) q[k] = (t < W && k < rhat) ? double(o[16 + k * 16 + t]) : 0.0;
-      orth_rows(q, rhat, W, t);
-      double y[RH];
+      for (int k = 0; k < RH; ++k) q[k] = (t < W && k < nc) ? double(o[16 + k * 16 + t]) : 0.0;
+      orth_rows(q, nc, W, t);
+      double y[RH], z[RH];
       auto times_g = [&]() {  // y = G Q, row t
 #pragma unroll
         for (int k = 0; k < RH; ++k) Q[t * LQ + k] = q[k];
@@ -488,11 +630,11 @@ __global__ __launch_bounds__(256) void k_warmstart(const double* __restrict__ gp
           for (int k = 0; k < RH; ++k) y[k] = fma(g[j], Q[j * LQ + k], y[k]);
         wave_sync();
       };
-      for (int s = 0; s < iters; ++s) {
+      for (int s = 0; s < nit; ++s) {
         times_g();
 #pragma unroll
         for (int k = 0; k < RH; ++k) q[k] = y[k];
-        orth_rows(q, rhat, W, t);
+        orth_rows(q, nc, W, t);
       }
       // Rayleigh-Ritz: H = Q^T G Q (upper triangle, mirrored), U = I
       times_g();
@@ -502,19 +644,19 @@ __global__ __launch_bounds__(256) void k_warmstart(const double* __restrict__ gp
         for (int c = a; c < RH; ++c) {
           const double h = row_sum(q[a] * y[c]);
           if (t == 0) {
-            H[a * LH + c] = (a < rhat && c < rhat) ? h : 0.0;
-            H[c * LH + a] = (a < rhat && c < rhat) ? h : 0.0;
+            H[a * LH + c] = (a < nc && c < nc) ? h : 0.0;
+            H[c * LH + a] = (a < nc && c < nc) ? h : 0.0;
             U[a * LH + c] = a == c ? 1.0 : 0.0;
             U[c * LH + a] = a == c ? 1.0 : 0.0;
           }
         }
       wave_sync();
-      jacobi_group(H, U, sAl[grp], sBe[grp], sPa[grp], rhat, t);
+      jacobi_group(H, U, sAl[grp], sBe[grp], sPa[grp], nc, t);
       // descending order of the Ritz values (stable by index)
-      if (t < rhat) {
+      if (t < nc) {
         const double dk = H[t * LH + t];
         int pos = 0;
-        for (int j = 0; j < rhat; ++j) {
+        for (int j = 0; j < nc; ++j) {
           const double dj = H[j * LH + j];
           pos += (dj > dk || (dj == dk && j < t)) ? 1 : 0;
         }
@@ -526,7 +668,7 @@ __global__ __launch_bounds__(256) void k_warmstart(const double* __restrict__ gp
 #pragma unroll
       for (int c = 0; c < RH; ++c) {
         double v = 0.0;
-        if (c < rhat) {
+        if (c < nc) {
           const int col = sPe[grp][c];
 #pragma unroll
           for (int j = 0; j < RH; ++j) v = fma(q[j], U[j * LH + col], v);
@@ -535,7 +677,7 @@ __global__ __launch_bounds__(256) void k_warmstart(const double* __restrict__ gp
         Q[t * LQ + c] = v;
       }
       wave_sync();
-      if (t < rhat) {
+      if (t < nc) {
         double besta = -1.0, sg = 1.0;
         for (int i = 0; i < 16; ++i) {
           const double v = Q[i * LQ + t];
@@ -545,8 +687,8 @@ __global__ __launch_bounds__(256) void k_warmstart(const double* __restrict__ gp
       }
       wave_sync();
 #pragma unroll
-      for (int c = 0; c < RH; ++c) z[c] = c < rhat ? z[c] * sSg[grp][c] : 0.0;
-      // acceptance: smallest r <= rhat whose discarded energy meets tau
+      for (int c = 0; c < RH; ++c) z[c] = c < nc ? z[c] * sSg[grp][c] : 0.0;
+      // acceptance: smallest r <= nc whose discarded energy meets tau
       double diag = 0.0;
 #pragma unroll
       for (int j = 0; j < 16; ++j) diag = (j == t) ? g[j] : diag;
@@ -554,9 +696,14 @@ __global__ __launch_bounds__(256) void k_warmstart(const double* __restrict__ gp
       const double eps = eps_v[d.var];
       const double tau = kKappa * eps * eps * double(M) * double(W);
       double cum = 0.0;
-      for (int k = 1; k <= rhat; ++k) {
+      for (int k = 1; k <= nc; ++k) {
         cum += sTh[grp][k - 1];
         if (tr - cum <= tau) { r = k; break; }
+      }
+      if (r > 0) {
+        lam_out[b * 16 + t] = t < r ? fmax(sTh[grp][t < RH ? t : 0], 0.0) : 0.0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) basis_out[b * 256 + k * 16 + t] = (k < r && k < RH) ? z[k < RH ? k : 0] : 0.0;
       }
     }
     if (r == 0) {
@@ -570,15 +717,12 @@ __global__ __launch_bounds__(256) void k_warmstart(const double* __restrict__ gp
         qv_size[b] = 4 * pad16(int64_t(W) * r);
         qa_size[b] = 4 * pad16(int64_t(M) * r);
       }
-      lam_out[b * 16 + t] = t < r ? fmax(sTh[grp][t < RH ? t : 0], 0.0) : 0.0;
-#pragma unroll
-      for (int k = 0; k < 16; ++k) basis_out[b * 256 + k * 16 + t] = (k < r && k < RH) ? z[k < RH ? k : 0] : 0.0;
     }
   }
   if (t == 0 && verdict == 1) atomicAdd(&n_acc, 1u);
   if (t == 0 && verdict == 2) atomicAdd(&n_rej, 1u);
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && retry) {  // final counts after both attempts
     if (n_acc) atomicAdd(counters, (unsigned long long)n_acc);
     if (n_rej) atomicAdd(counters + 1, (unsigned long long)n_rej);
   }
@@ -617,6 +761,19 @@ hipError_t launch_gemm(bool ta, bool tb, bool bf16, const float* A, int lda, con
   return hipGetLastError();
 }
 
+hipError_t launch_pack_weights(const float* P, short* packed, hipStream_t s) {
+  const int64_t total = int64_t(kH + kH + kNO) * kPackLd;
+  hipLaunchKernelGGL(k_pack_weights, dim3{unsigned((total + 255) / 256)}, dim3{256}, 0, s, P, packed);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const float* raw, int64_t n, const float* norm, const float* P, const short* packed,
+                              float* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mlp_forward, dim3{unsigned((n + 63) / 64)}, dim3{256}, 0, s, raw, n, norm, P, packed, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_loss(const float* out, const int32_t* rank, const float* basis, const int32_t* wb, int64_t n,
                        float* gout, float* loss, hipStream_t s) {
   if (n == 0) return hipSuccess;
@@ -646,9 +803,10 @@ hipError_t launch_warmstart(const double* gpart, const int32_t* item_start, cons
                             uint8_t* rank, double* lam, double* basis, int64_t* qv_size, int64_t* qa_size,
                             uint8_t* reject, unsigned long long* counters, hipStream_t s) {
   if (nblocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_warmstart, dim3{unsigned((nblocks + 15) / 16)}, dim3{256}, 0, s, gpart, item_start, desc,
-                     nblocks, eps_v, r_max, mlp_out, iters, margin, rank, lam, basis, qv_size, qa_size, reject,
-                     counters);
+  for (int retry = 0; retry < 2; ++retry)
+    hipLaunchKernelGGL(k_warmstart, dim3{unsigned((nblocks + 15) / 16)}, dim3{256}, 0, s, gpart, item_start, desc,
+                       nblocks, eps_v, r_max, mlp_out, iters, margin, retry, rank, lam, basis, qv_size, qa_size,
+                       reject, counters);
   return hipGetLastError();
 }
 

@@ -5,8 +5,8 @@
   bf16 products vs the oracle with the same bf16 rounding (<= 2e-2);
 * training on the GPU lowers the loss;
 * warm-started eigensolve: with a model whose output ignores its input
-  (fixed rank guess 4, V0 = the first four unit vectors) the GPU and the
-  oracle start from identical V0; accepted/rejected blocks, ranks,
+  (fixed rank guess 4, V0 = the unit vectors) the GPU and the oracle start
+  from identical V0 (both attempts); accepted/rejected blocks, ranks,
   coefficients (1e-5 on gap-qualified blocks), the bound and bit-identical
   decoding are compared.
 """
@@ -111,6 +111,29 @@ def test_gradients_match_oracle(bf16):
         assert rel <= tol, name
 
 
+def test_fused_forward_matches_layers_and_oracle():
+    """The fused inference kernel reproduces the layer-by-layer bf16 forward
+    bit for bit, and the FP64 oracle with the same bf16 roundings."""
+    net = _net_for_test(9)
+    P, N = _flat(net)
+    m = dls.Model()
+    m.set(P, N)
+    rng = np.random.default_rng(10)
+    feat = rng.normal(size=(1000, 80)).astype(np.float32)   # not a multiple of 64 rows
+    tf = torch.from_numpy(feat).cuda()
+    fused = m.forward(tf, bf16=True).cpu().numpy()
+    layers = m.forward(tf, bf16=2).cpu().numpy()
+    assert np.array_equal(fused.view(np.uint32), layers.view(np.uint32))
+    sizes = [a.size for a in net.params()]
+    parts = np.split(P.astype(np.float64), np.cumsum(sizes)[:-1])
+    net32 = L.Net(*[q.reshape(a.shape) for q, a in zip(parts, net.params())],
+                  N[:16].astype(np.float64), N[16:].astype(np.float64))
+    ref = L.forward(net32, L.normalise(net32, feat.astype(np.float64)), round_bf16=True)[2]
+    rel = np.linalg.norm(fused - ref) / np.linalg.norm(ref)
+    print("fused forward vs oracle rel %.2e" % rel, flush=True)
+    assert rel <= 1e-4
+
+
 def test_training_lowers_the_loss():
     rng = np.random.default_rng(5)
     n = 512
@@ -161,7 +184,7 @@ def test_warm_start_parity(case):
     coef = dls.d2h(inf.d_coef, inf.qa_bytes).view(np.float32)
     stream = enc.finalize()
     blocks, _ = odls.plan(f, p)
-    V0 = np.eye(16)[:, :rhat]
+    V0 = np.eye(16)   # the model's 16 starting columns (a retry uses more than rhat)
     n_acc, mism, errs = 0, 0, []
     for b, blk in enumerate(blocks):
         code, acc = L.encode_block_learned(odls.gather(f, blk), p.eps[blk.var], p.resolved_rmax(),

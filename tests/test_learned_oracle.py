@@ -190,7 +190,28 @@ def test_learned_encode_keeps_the_bound():
     rng = np.random.default_rng(3)
     for b in blocks:
         xb = dls.gather(f, b)
-        V0 = rng.normal(size=(16, 2))
+        V0 = rng.normal(size=(16, 16))
         code, acc = L.encode_block_learned(xb, eps, 16, np.float64, 2, V0)
         out = dls.decode_block(code.r, code.qV, code.qA, code.codes, code.esc_values, eps, np.float64)
         assert np.all(np.abs(out - xb) <= eps)
+
+
+def test_learned_retry_and_limits():
+    """A rank-6 block: rhat 1 is rejected, the retry with 5 columns is
+    rejected too (tail of mode 6 > tau), so the plain eigensolve decides; a
+    prediction above WARM_MAX columns falls back at once; rhat 3 is rejected
+    and its retry with 7 columns accepted, returning the plain rank."""
+    rng = np.random.default_rng(12)
+    a, _ = np.linalg.qr(rng.normal(size=(16, 6)))
+    bvec, _ = np.linalg.qr(rng.normal(size=(64, 6)))
+    x = (a * np.array([50.0, 30, 20, 10, 5, 2])) @ bvec.T
+    eps = 1e-3
+    V0 = rng.normal(size=(16, 16))
+    plain = dls.encode_block(x, eps, 16, np.float64)
+    assert plain.r == 6
+    code, acc = L.encode_block_learned(x, eps, 16, np.float64, 1, V0)
+    assert not acc and code.r == plain.r
+    code, acc = L.encode_block_learned(x, eps, 16, np.float64, L.WARM_MAX + 1, V0)
+    assert not acc and code.r == plain.r
+    code, acc = L.encode_block_learned(x, eps, 16, np.float64, 3, V0)
+    assert acc and code.r == plain.r

@@ -54,9 +54,12 @@ typedef enum {
 
 typedef enum { DLS_F32 = 0, DLS_F64 = 1 } dls_dtype;
 
-/* Input precision of the Gram and projection contractions (both accumulate
- * in FP32 on the matrix cores; the eigensolve, the lattice reconstruction
- * and the bound check are FP64 in every mode). */
+/* Operand precision of the Gram contraction (Sec. 2.2's eigenbasis).
+ * DLS_PREC_BF16 rounds the snapshots to bfloat16 as the matrix cores take
+ * them (FP32 accumulation per 64-point chunk, FP64 across chunks); the
+ * eigenbasis then carries bfloat16-level error.  The projection, the
+ * eigensolve, the lattice reconstruction and the bound check use the
+ * stored values in every mode, so the bound holds exactly either way. */
 typedef enum { DLS_PREC_FP32 = 0, DLS_PREC_BF16 = 1 } dls_precision;
 
 /* dls_params.flags */

@@ -80,6 +80,7 @@ class Params:
     pmin: int = 0               # adaptive: smallest leaf edge
     r_max: int = 0              # 0 -> min(window, 32)
     adaptive: bool = False
+    precision: str = "fp32"     # 'bf16': the Gram contraction takes bfloat16 operands
 
     @property
     def ndim(self) -> int:
@@ -344,13 +345,24 @@ def lattice_values(S: np.ndarray, q: np.ndarray, eps: float, dtype) -> np.ndarra
     return (n.astype(np.float64) * c).astype(dtype)
 
 
-def encode_block(xs: np.ndarray, eps: float, rcap: int, dtype) -> BlockCode:
-    """Encode one block X_b (storage dtype, W_b x M_b) under the bound eps."""
+def round_bf16(a: np.ndarray) -> np.ndarray:
+    """Values rounded to bfloat16 (8 significant bits, round half to even),
+    after a first rounding to float32; normal range only."""
+    f = np.asarray(a, dtype=np.float64).astype(np.float32).astype(np.float64)
+    m, e = np.frexp(f)                       # f = m 2^e, 0.5 <= |m| < 1
+    return np.where(f == 0.0, f, np.ldexp(np.rint(np.ldexp(m, 8)), e - 8))
+
+
+def encode_block(xs: np.ndarray, eps: float, rcap: int, dtype, bf16_gram: bool = False) -> BlockCode:
+    """Encode one block X_b (storage dtype, W_b x M_b) under the bound eps.
+    With bf16_gram the Gram matrix is formed from the bfloat16-rounded
+    snapshots (mixed precision); every later step uses the exact values."""
     wb, m = xs.shape
     x = xs.astype(np.float64)
     if not np.all(np.isfinite(x)):
         return _raw_block(xs)
-    G = x @ x.T                                                   # step 3
+    xg = round_bf16(x) if bf16_gram else x
+    G = xg @ xg.T                                                 # step 3
     lam, V = eig_desc(G)                                          # step 4
     tau = KAPPA * eps * eps * m * wb
     r = choose_rank(lam, tau, min(rcap, wb, m))                   # step 5
@@ -426,7 +438,7 @@ def encode(field: np.ndarray, p: Params) -> Encoded:
     assert field.dtype == p.np_dtype
     blocks, bits = plan(field, p)
     rmax = p.resolved_rmax()
-    codes = [encode_block(gather(field, b), float(p.eps[b.var]), rmax, p.np_dtype)
+    codes = [encode_block(gather(field, b), float(p.eps[b.var]), rmax, p.np_dtype, p.precision == "bf16")
              for b in blocks]
     return Encoded(p, blocks, codes, bits)
 

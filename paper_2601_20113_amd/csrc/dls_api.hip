@@ -336,7 +336,6 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
   if (d_field == nullptr) return fail(DLS_EINVAL, "field is NULL");
   Problem p;
   if (dls_status s = validate(params, p)) return s;
-  if (p.precision != DLS_PREC_FP32) return fail(DLS_EUNSUPPORTED, "BF16 contractions are not built yet");
   hipStream_t s = static_cast<hipStream_t>(stream);
   HIP_TRY(hipSetDevice(ctx->device));
   ctx->have_result = false;
@@ -433,7 +432,7 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
   const Dims dims{p.nx, p.ny, p.nz, p.nt};
   unsigned long long* cnt = ctx->counters.as<unsigned long long>();
   HIP_TRY(hipEventRecord(ctx->ev0, s));
-  HIP_TRY(launch_gram(wp, p.dtype, d_field, dims, ctx->desc.as<BlockDesc>(), ctx->items.as<Item>(), ni,
+  HIP_TRY(launch_gram(wp, p.dtype, p.precision == DLS_PREC_BF16, d_field, dims, ctx->desc.as<BlockDesc>(), ctx->items.as<Item>(), ni,
                       ctx->gram.as<double>(), s));
   HIP_TRY(hipEventRecord(ctx->evs[0], s));
   const bool learned = (p.flags & DLS_LEARNED) != 0;

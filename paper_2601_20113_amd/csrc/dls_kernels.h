@@ -24,7 +24,7 @@ struct EscOut {
   unsigned long long cap;
 };
 
-hipError_t launch_gram(int wp, int dtype, const void* F, const Dims& dims, const BlockDesc* desc,
+hipError_t launch_gram(int wp, int dtype, bool bf16, const void* F, const Dims& dims, const BlockDesc* desc,
                        const Item* items, int64_t nitems, double* gpart, hipStream_t s);
 // `only` (may be NULL): solve only the blocks b with only[b] != 0
 hipError_t launch_eigen(int wp, const double* gpart, const int32_t* item_start, const BlockDesc* desc,

@@ -31,6 +31,7 @@
 namespace dls {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int64_t fidx(const Dims& d, int var, int t, int z, int y, int x) {
   return (((int64_t(var) * d.nt + t) * d.nz + z) * d.ny + y) * d.nx + x;
@@ -87,7 +88,18 @@ __device__ __forceinline__ void load_chunk(const T* __restrict__ row, const Item
 // ---------------------------------------------------------------------------
 // Gram: one workgroup (4 waves) per item; output gpart[item][WP][WP] (FP64).
 // ---------------------------------------------------------------------------
-template <int WP, typename T>
+// bfloat16 of x, round to nearest even (normal range; NaN and infinity keep
+// their class, which the eigensolve's finiteness check needs)
+__device__ __forceinline__ short bf16_rne(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return short(uint16_t((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16));
+}
+
+// BF: bfloat16 operands (v_mfma_f32_16x16x16bf16_1k, one instruction per 16
+// points); otherwise FP32 operands (v_mfma_f32_16x16x4f32, one per 4 points).
+// Either way the lane feeds the same points, so the products are those of
+// X X^T with the operands rounded as the instruction takes them.
+template <int WP, typename T, bool BF>
 __global__ __launch_bounds__(256) void k_gram(const T* __restrict__ F, Dims dims,
                                               const BlockDesc* __restrict__ desc,
                                               const Item* __restrict__ items,
@@ -113,12 +125,30 @@ __global__ __launch_bounds__(256) void k_gram(const T* __restrict__ F, Dims dims
     load_chunk<T>(row0, it, d, c, q, dims.nx, nxy, v0);
     if (WP == 32) load_chunk<T>(row1, it, d, c, q, dims.nx, nxy, v1);
     f32x4 a00 = {0.f, 0.f, 0.f, 0.f}, a01 = a00, a11 = a00;
+    if constexpr (BF) {
+      // MFMA j takes points 16 j + 4 q + e (e < 4) as its k index 4 q + e
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      a00 = __builtin_amdgcn_mfma_f32_16x16x4f32(v0[s], v0[s], a00, 0, 0, 0);
-      if (WP == 32) {
-        a01 = __builtin_amdgcn_mfma_f32_16x16x4f32(v0[s], v1[s], a01, 0, 0, 0);
-        a11 = __builtin_amdgcn_mfma_f32_16x16x4f32(v1[s], v1[s], a11, 0, 0, 0);
+      for (int j = 0; j < 4; ++j) {
+        bf16x4 b0, b1;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          b0[e] = bf16_rne(v0[4 * j + e]);
+          if (WP == 32) b1[e] = bf16_rne(v1[4 * j + e]);
+        }
+        a00 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b0, b0, a00, 0, 0, 0);
+        if (WP == 32) {
+          a01 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b0, b1, a01, 0, 0, 0);
+          a11 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b1, b1, a11, 0, 0, 0);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        a00 = __builtin_amdgcn_mfma_f32_16x16x4f32(v0[s], v0[s], a00, 0, 0, 0);
+        if (WP == 32) {
+          a01 = __builtin_amdgcn_mfma_f32_16x16x4f32(v0[s], v1[s], a01, 0, 0, 0);
+          a11 = __builtin_amdgcn_mfma_f32_16x16x4f32(v1[s], v1[s], a11, 0, 0, 0);
+        }
       }
     }
 #pragma unroll
@@ -201,12 +231,14 @@ __global__ __launch_bounds__(256) void k_eigen(const double* __restrict__ gpart,
   // Gram row i = sum of the slice Grams, symmetrised through LDS
   double a[WP], v[WP];
 #pragma unroll
-  for (int j = 0; j < WP; ++j) {
-    double s = 0.0;
-    for (int it = i0; it < i1; ++it) s += gpart[int64_t(it) * WP * WP + i * WP + j];
-    a[j] = s;
-    A[i * LD + j] = s;
+  for (int j = 0; j < WP; ++j) a[j] = 0.0;
+  for (int it = i0; it < i1; ++it) {  // every entry's loads of an item issued together
+    const double* gp = gpart + int64_t(it) * WP * WP + i * WP;
+#pragma unroll
+    for (int j = 0; j < WP; ++j) a[j] += gp[j];
   }
+#pragma unroll
+  for (int j = 0; j < WP; ++j) A[i * LD + j] = a[j];
   wave_sync();
   bool fin = true;
 #pragma unroll
@@ -799,14 +831,20 @@ __global__ __launch_bounds__(256) void k_classify(const Item* __restrict__ items
 // ---------------------------------------------------------------------------
 // Launch wrappers
 // ---------------------------------------------------------------------------
-hipError_t launch_gram(int wp, int dtype, const void* F, const Dims& dims, const BlockDesc* desc,
+hipError_t launch_gram(int wp, int dtype, bool bf16, const void* F, const Dims& dims, const BlockDesc* desc,
                        const Item* items, int64_t nitems, double* gpart, hipStream_t s) {
   if (nitems == 0) return hipSuccess;
   const dim3 g{unsigned(nitems)}, bl{256};
-  if (wp == 16 && dtype == 0) hipLaunchKernelGGL((k_gram<16, float>), g, bl, 0, s, (const float*)F, dims, desc, items, gpart);
-  else if (wp == 16) hipLaunchKernelGGL((k_gram<16, double>), g, bl, 0, s, (const double*)F, dims, desc, items, gpart);
-  else if (dtype == 0) hipLaunchKernelGGL((k_gram<32, float>), g, bl, 0, s, (const float*)F, dims, desc, items, gpart);
-  else hipLaunchKernelGGL((k_gram<32, double>), g, bl, 0, s, (const double*)F, dims, desc, items, gpart);
+#define DLS_GRAM(WPV, TV, BFV) \
+  hipLaunchKernelGGL((k_gram<WPV, TV, BFV>), g, bl, 0, s, (const TV*)F, dims, desc, items, gpart)
+  if (wp == 16) {
+    if (dtype == 0) { if (bf16) DLS_GRAM(16, float, true); else DLS_GRAM(16, float, false); }
+    else { if (bf16) DLS_GRAM(16, double, true); else DLS_GRAM(16, double, false); }
+  } else {
+    if (dtype == 0) { if (bf16) DLS_GRAM(32, float, true); else DLS_GRAM(32, float, false); }
+    else { if (bf16) DLS_GRAM(32, double, true); else DLS_GRAM(32, double, false); }
+  }
+#undef DLS_GRAM
   return hipGetLastError();
 }
 

@@ -581,16 +581,21 @@ __global__ __launch_bounds__(256) void k_warmstart(const double* __restrict__ gp
     const BlockDesc d = desc[b];
     const int W = d.w(), M = d.m;
     const int i0 = item_start[b], i1 = item_start[b + 1];
-    double g[16];
+    double g[16], gc[16];
     bool fin = true;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      double s1 = 0.0, s2 = 0.0;
-      for (int it = i0; it < i1; ++it) {
-        s1 += gpart[int64_t(it) * 256 + t * 16 + j];
-        s2 += gpart[int64_t(it) * 256 + j * 16 + t];
+    for (int j = 0; j < 16; ++j) g[j] = gc[j] = 0.0;
+    for (int it = i0; it < i1; ++it) {  // every entry's loads of an item issued together
+      const double* gp = gpart + int64_t(it) * 256;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        g[j] += gp[t * 16 + j];
+        gc[j] += gp[j * 16 + t];
       }
-      g[j] = 0.5 * (s1 + s2);
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      g[j] = 0.5 * (g[j] + gc[j]);
       fin = fin && isfinite(g[j]);
     }
     fin = row_sum(fin ? 0.0 : 1.0) == 0.0;

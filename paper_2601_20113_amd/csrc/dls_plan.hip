@@ -54,12 +54,20 @@ __device__ __forceinline__ double grad_mag(const T* __restrict__ f0, int64_t nx,
 }
 
 // g = |grad f| of one snapshot, stored once in FP64 (rows over workgroups,
-// x over threads: no index divisions)
+// x over threads: no index divisions).  Workgroups are dealt to the 8 XCDs
+// round-robin, so workgroup b runs on XCD b % 8; each XCD is given one
+// contiguous eighth of the rows, which its workgroups sweep together, so the
+// y and z neighbours of a row are read through the same L2.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gradient(const T* __restrict__ f0, int64_t nx, int64_t ny, int64_t nz,
                                                   double* __restrict__ g) {
   const int64_t rows = ny * nz;
-  for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+  const int64_t per_xcd = (rows + 7) / 8;
+  const int xcd = int(blockIdx.x % 8);
+  const int64_t lo = int64_t(xcd) * per_xcd;
+  const int64_t hi = lo + per_xcd < rows ? lo + per_xcd : rows;
+  const int64_t step = gridDim.x / 8;
+  for (int64_t row = lo + blockIdx.x / 8; row < hi; row += step) {
     const int64_t y = row % ny, z = row / ny;
     for (int64_t x = threadIdx.x; x < nx; x += 256) g[row * nx + x] = grad_mag(f0, nx, ny, nz, x, y, z);
   }
@@ -286,7 +294,7 @@ hipError_t adaptive_plan(const Problem& p, const void* F, hipStream_t s, PlanScr
     const auto t0 = now();
     const uint8_t* f0 = static_cast<const uint8_t*>(F) + size_t(v) * size_t(p.nt) * size_t(n) * es;
     const dim3 bl{256};
-    const unsigned nrowblk = unsigned(std::min<int64_t>(8192, p.ny * p.nz));
+    const unsigned nrowblk = 8 * unsigned(std::min<int64_t>(1024, (p.ny * p.nz + 7) / 8));  // a multiple of 8
     if (p.dtype == 0)
       hipLaunchKernelGGL(k_gradient<float>, dim3{nrowblk}, bl, 0, s, (const float*)f0, p.nx, p.ny, p.nz, g);
     else

@@ -323,10 +323,35 @@ def pin_container_round_trip():
             assert np.abs(out.astype(np.float64) - f.astype(np.float64)).max() <= p.eps[0]
 
 
+
+
+def pin_round_bf16():
+    """The oracle's bfloat16 rounding (mantissa arithmetic) agrees with the
+    float32 bit rule (add 0x7FFF plus the lowest kept bit, truncate) on
+    random normal values, and with hand-worked cases."""
+    from oracle import learned
+    rng = np.random.default_rng(4)
+    x = rng.normal(size=20000) * np.exp(rng.uniform(-30, 30, 20000))
+    assert np.array_equal(dls.round_bf16(x), learned.bf16(x))
+    # 1 + 2^-8 is a tie between 1 and 1 + 2^-7: even mantissa (1) wins;
+    # 1 + 3 * 2^-8 ties between 1 + 2^-7 and 1 + 2^-6: even (1 + 2^-6) wins
+    assert dls.round_bf16(np.array([1 + 2.0 ** -8]))[0] == 1.0
+    assert dls.round_bf16(np.array([1 + 3 * 2.0 ** -8]))[0] == 1 + 2.0 ** -6
+    assert dls.round_bf16(np.array([-(1 + 2.0 ** -8 + 2.0 ** -20)]))[0] == -(1 + 2.0 ** -7)
+    assert dls.round_bf16(np.array([0.0, 3.0]))[1] == 3.0
+
+    # the bf16-Gram mode forms G from the rounded values: a 1 x 2 block
+    # [1 + 2^-8, 3] has G = 1 + 9 = 10 exactly (the full-precision G is larger)
+    x = np.array([[1 + 2.0 ** -8, 3.0]])
+    c = dls.encode_block(x, 1e-3, 1, np.float64, bf16_gram=True)
+    assert c.lam[0] == 10.0
+    assert dls.encode_block(x, 1e-3, 1, np.float64).lam[0] > 10.0
+
+
 ALL_PINS = [
     pin_eigenvalues_vs_svd, pin_eigenvectors_orthonormal_and_residual,
     pin_eigenvalues_vs_jacobi, pin_rank_bruteforce, pin_exact_rank_data,
     pin_pointwise_bound, pin_escapes_rare_on_smooth_data, pin_lattice_one_rounding,
     pin_hand_worked_rank_one, pin_special_blocks, pin_gradient_and_percentile,
-    pin_adaptive_plan, pin_container_round_trip,
+    pin_adaptive_plan, pin_container_round_trip, pin_round_bf16,
 ]

@@ -204,3 +204,57 @@ def test_adaptive_plan_matches_oracle(name):
         got = (desc[b, 0], desc[b, 1], desc[b, 2], desc[b, 3], ext & 255, (ext >> 8) & 255,
                (ext >> 16) & 255, (ext >> 24) & 255, desc[b, 5])
         assert got == (blk.x0, blk.y0, blk.z0, blk.t0, blk.px, blk.py, blk.pz, blk.w, blk.var)
+
+
+@pytest.mark.parametrize("name", ["c1_64x64x32_f64", "blobs_f32_96x64x20", "spec3d_f32_w32_2var"])
+def test_bf16_gram_parity(name):
+    """Mixed precision (DLS_PREC_BF16): the Gram matrix from bfloat16 snapshots.
+
+    * Against the oracle in the same mode (Gram of the bf16-rounded values,
+      FP64): the bf16 products are exact in FP32, so ranks agree on >= 95 % of
+      blocks and coefficients to 1e-5 on gap-qualified equal-rank blocks;
+      the ratio is within 1 % of that oracle's.
+    * Against the full-precision oracle: coefficients within 1e-2 on blocks
+      whose eigengaps keep the first-order effect of that block's actual
+      bf16 Gram perturbation below 1e-2.
+    * The bound holds at every point and decoding is bit-identical, as in
+      every mode (only the eigenbasis sees bfloat16).
+    """
+    print("case", name, flush=True)
+    f, p = _case(name)
+    pb = odls.Params(**{**p.__dict__, "precision": "bf16"})
+    enc_bf = odls.encode(f, pb)
+    enc_fp = odls.encode(f, p)
+    g = H.GpuRun(f, p, precision="bf16")
+    ranks_bf = np.array([c.r for c in enc_bf.codes])
+    mism = int(np.sum(ranks_bf != g.rank))
+    e_same, e_full = [], []
+    for b, blk in enumerate(enc_bf.blocks):
+        w, r = blk.w, int(g.rank[b])
+        V = g.basis_of(b, w)[:, :w]
+        assert np.abs(V.T @ V - np.eye(w)).max() <= 1e-12
+        A = g.coef_of(b, blk.m)
+        c = enc_bf.codes[b]
+        if c.r == r and r > 0 and H.gap_qualified(c.lam, r):
+            e_same.append(H.coef_rel_err(A, V[:, :r], c.A, c.V[:, :r]))
+        c = enc_fp.codes[b]
+        if c.r == r and r > 0:
+            # first-order error from this block's actual bf16 Gram perturbation
+            x = odls.gather(f, blk).astype(np.float64)
+            xb = odls.round_bf16(x)
+            eta = np.linalg.norm(xb @ xb.T - x @ x.T, 2) / max(c.lam[0], 1e-300)
+            if H.predicted_coef_err(c.lam, r, eta=eta) <= 1e-2:
+                e_full.append(H.coef_rel_err(A, V[:, :r], c.A, c.V[:, :r]))
+    print("bf16: rank mismatches %d / %d; coef vs bf16 oracle: %d blocks max %.3g; vs full oracle: %d blocks max %.3g"
+          % (mism, g.nb, len(e_same), max(e_same, default=0), len(e_full), max(e_full, default=0)), flush=True)
+    assert mism <= 0.05 * g.nb
+    assert len(e_same) >= 0.1 * g.nb and max(e_same) <= 1e-5
+    assert len(e_full) >= 0.1 * g.nb and max(e_full) <= 1e-2
+    out_gpu = dls.decompress(g.stream).cpu().numpy()
+    err = np.abs(out_gpu.astype(np.float64) - f.astype(np.float64))
+    assert np.all(err <= np.array(p.eps)[:, None, None, None, None])
+    assert np.array_equal(odls.decompress(g.stream).view(np.uint8), out_gpu.view(np.uint8))
+    cr_g, cr_bf = f.nbytes / len(g.stream), f.nbytes / len(container.pack(enc_bf))
+    cr_fp = f.nbytes / len(container.pack(enc_fp))
+    print("CR gpu-bf16 %.4f oracle-bf16 %.4f oracle-full %.4f" % (cr_g, cr_bf, cr_fp), flush=True)
+    assert abs(cr_g / cr_bf - 1.0) <= 0.01

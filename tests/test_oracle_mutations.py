@@ -27,7 +27,8 @@ MUTATIONS = [
     ("encode_with_basis", "qV = np.rint(Vr * float(1 << BASIS_BITS)).astype(np.int64)",
      "qV = np.rint(Vr * float(1 << (BASIS_BITS - 1))).astype(np.int64)"),
     ("encode_block", "tau = KAPPA * eps * eps * m * wb", "tau = KAPPA * eps * m * wb"),
-    ("encode_block", "G = x @ x.T", "G = x @ x.T - np.diag(np.diag(x @ x.T)) * 0.5"),
+    ("encode_block", "G = xg @ xg.T", "G = xg @ xg.T - np.diag(np.diag(xg @ xg.T)) * 0.5"),
+    ("round_bf16", "np.ldexp(m, 8)", "np.ldexp(m, 9)"),
     ("eig_desc", "order = np.argsort(-lam, kind=\"stable\")", "order = np.argsort(lam, kind=\"stable\")"),
     ("canonical_signs", "if V[i, k] < 0:", "if V[i, k] > 0:"),
     ("gradient_magnitude", "d[s(1, n - 1)] = (f[s(2, n)] - f[s(0, n - 2)]) * 0.5",

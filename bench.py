@@ -3,12 +3,14 @@
 
 One step = one dls_encode over the whole synthetic field (plan, Gram,
 eigensolve + rank, offset scan, projection / quantization / lattice
-reconstruction / residual codes), input already resident in HBM.  Prints one
-JSON line with the throughput, the roofline of the dominant kernel (measured
-with HIP events on the stream the kernels run on), and the FP64 CPU oracle
-timed on a bounded sample of the same workload.
+reconstruction / residual codes), input already resident in HBM.  Two forms
+are timed on the same field: the plain GPU form and the full form (learned
+warm start, bf16 Gram, device-driven launch).  Prints one JSON line with the
+full form's throughput, the plain form's and their ratio, the roofline of the
+dominant kernel (measured with HIP events on the stream the kernels run on),
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c5]
 """
 from __future__ import annotations
 
@@ -23,7 +25,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-METRIC = "compress GB/s at abs bound 1e-3·range, learned+mixed vs plain GPU; ratio"
+METRIC = ("device compress GB/s at abs bound 1e-3*range (learned + mixed + batched form; "
+          "ratio_vs_plain = its GB/s over the plain GPU form)")
 
 CONFIGS = {
     "c1": dict(desc="2D FP64 64x64 x 32 steps, 4 moving Gaussian blobs + N(0,1e-4) noise, "
@@ -108,15 +111,118 @@ def cpu_baseline(field, cfg, eps, seconds):
                       % (done, len(blocks), nbytes / 1e6, dt)}
 
 
+FORMS = {
+    "plain": "FP32 Gram, full Jacobi eigensolve, host-driven launches",
+    "full": "learned warm start (windows <= 16) + bf16 Gram + device-driven launch",
+}
+
+
+def params_for(cfg, eps, form):
+    import paper_2601_20113_amd as dls
+    full = form == "full"
+    return dls.Params(nx=cfg["nx"], ny=cfg["ny"], nz=cfg["nz"], nt=cfg["nt"], nvars=cfg["nvars"],
+                      dtype=cfg["dtype"], px=cfg["px"], py=cfg["py"], pz=cfg["pz"],
+                      window=cfg["window"], eps=eps, pmin=cfg.get("pmin", 0),
+                      adaptive=cfg.get("adaptive", False),
+                      precision="bf16" if full else "fp32",
+                      learned=full and cfg["window"] <= 16, persistent=full)
+
+
+def train_model(cfg, log):
+    """The warm-start network for this workload: fields of the same generator
+    and block shape with seeds disjoint from the timed field's, labelled by
+    the plain method, trained on the device."""
+    import numpy as np
+    import torch
+    import paper_2601_20113_amd as dls
+    from paper_2601_20113_amd import train as T
+    from synth import gpu as sg
+    t0 = time.perf_counter()
+    enc = dls.Encoder()
+    parts = []
+    if cfg["kind"] == "blobs":
+        data = T.collect(np.arange(100000, 100160))
+    else:
+        for i in range(4):
+            if cfg["kind"] == "blobs_gpu":
+                shape = (1, min(cfg["nt"], 48), 1, 1024, 1024)
+                f = torch.empty(shape, dtype=torch.float32, device="cuda")
+                sg.blobs_into(f[0], nblobs=cfg["nblobs"] * 1024 * 1024 // (cfg["nx"] * cfg["ny"]), seed=5000 + i)
+            else:
+                shape = (1, cfg["nt"], cfg["nz"] // 2, cfg["ny"] // 2, cfg["nx"] // 2)
+                f = torch.empty(shape, dtype=torch.float32, device="cuda")
+                sg.spectrum_into(f[0], seed=5000 + i, nmodes=64)
+            lo, hi = dls.value_range(f)
+            c = dict(cfg, nt=shape[1], nz=shape[2], ny=shape[3], nx=shape[4], nvars=1)
+            parts.append(T.label_blocks(enc, f, params_for(c, [cfg["rel_eps"] * (hi[0] - lo[0])], "plain")))
+            del f
+        data = T.merge(parts)
+    model, losses = T.fit_data(data, epochs=12, batch=512, lr=2e-3, seed=1)
+    log("model: %d labelled blocks, loss %.3f -> %.3f, %.1f s"
+        % (data["feat"].shape[0], losses[0], losses[-1], time.perf_counter() - t0))
+    return model
+
+
+def run_form(field, cfg, eps, form, steps, warmup, model, log):
+    """Time `steps` encodes (after `warmup`); returns the measurements."""
+    import torch
+    import paper_2601_20113_amd as dls
+    p = params_for(cfg, eps, form)
+    enc = dls.Encoder()
+    if p.learned:
+        enc.set_model(model, 2, margin=1)
+    stream = torch.cuda.current_stream()
+    log("%s: warmup %d" % (form, warmup))
+    for _ in range(warmup):
+        enc.encode(field, p, stream=stream)
+    torch.cuda.synchronize()
+    stage = [0.0] * 5
+    log("%s: timing %d steps" % (form, steps))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        enc.encode(field, p, stream=stream)
+        inf = enc.info()
+        for i in range(5):
+            stage[i] += inf.stage_ms[i]
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    return {"enc": enc, "ms": ms, "stage": [s / steps for s in stage], "info": enc.info(), "params": p}
+
+
+def source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("dls_kernels.hip", "dls_device.h", "dls_kernels.h"):
+        with open(os.path.join(ROOT, "paper_2601_20113_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 counter summary, or None when the kernel sources changed
+    since the counters were taken (or there is no entry)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        tab = json.load(fh)
+    e = tab.get("%s/%s" % (kernel, workload))
+    if not e or e.get("source_sha") != source_sha():
+        return None
+    return int(e["fetch_bytes"] + e["write_bytes"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c5", choices=sorted(CONFIGS))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-ratio", action="store_true")
+    ap.add_argument("--no-ratio", action="store_true", help="skip the compression ratios (host zlib)")
+    ap.add_argument("--forms", default="plain,full")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -124,66 +230,53 @@ def main():
         sys.exit(2)
 
     import torch
-    import paper_2601_20113_amd as dls
     cfg = CONFIGS[args.config]
+    forms = [f for f in args.forms.split(",") if f]
+    model = None
+    if "full" in forms and cfg["window"] <= 16:
+        log("training the warm-start network")
+        model = train_model(cfg, log)
+        torch.cuda.empty_cache()
     log("generating %s" % args.config)
     field, eps = make_field(cfg)
     in_bytes = field.numel() * field.element_size()
-    p = dls.Params(nx=cfg["nx"], ny=cfg["ny"], nz=cfg["nz"], nt=cfg["nt"], nvars=cfg["nvars"],
-                   dtype=cfg["dtype"], px=cfg["px"], py=cfg["py"], pz=cfg["pz"],
-                   window=cfg["window"], eps=eps, pmin=cfg.get("pmin", 0),
-                   adaptive=cfg.get("adaptive", False))
-    enc = dls.Encoder()
-    stream = torch.cuda.current_stream()
-    log("warmup %d" % args.warmup)
-    for _ in range(args.warmup):
-        enc.encode(field, p, stream=stream)
-    torch.cuda.synchronize()
-    stage = [0.0] * 5
-    log("timing %d steps" % args.steps)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        enc.encode(field, p, stream=stream)
-        inf = enc.info()
-        for i in range(5):
-            stage[i] += inf.stage_ms[i]
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms = dt * 1e3 / args.steps
-    stage = [s / args.steps for s in stage]
-    inf = enc.info()
-    gbs = in_bytes / (ms * 1e-3) / 1e9
+    res = {}
+    for form in forms:
+        r = run_form(field, cfg, eps, form, args.steps, args.warmup, model, log)
+        r["gbs"] = in_bytes / (r["ms"] * 1e-3) / 1e9
+        if not args.no_ratio:
+            log("%s: finalize for the compression ratio" % form)
+            t1 = time.perf_counter()
+            r["cr"] = in_bytes / len(r["enc"].finalize())
+            log("%s: finalize %.1f s" % (form, time.perf_counter() - t1))
+        res[form] = r
+        log("%s: %.3f ms/step, %.1f GB/s, stages %s" % (form, r["ms"], r["gbs"], [round(s, 3) for s in r["stage"]]))
+    head = res["full"] if "full" in res else res[forms[0]]
+    head_form = "full" if "full" in res else forms[0]
 
-    # roofline of the dominant kernel, from algorithmic bytes per launch
+    # roofline of the headline form's dominant kernel: algorithmic bytes per
+    # launch over the launch time measured with HIP events on the encode stream
     es = field.element_size()
     nvals = field.numel()
     names = ["plan", "gram", "eigen", "scan", "encode"]
+    stage = head["stage"]
+    inf = head["info"]
     dom = max(range(5), key=lambda i: stage[i])
     if names[dom] == "encode":
-        traffic_alg = nvals * (es + 2) + inf.qa_bytes
+        alg = nvals * (es + 2) + inf.qa_bytes + (inf.qv_bytes if hasattr(inf, "qv_bytes") else 0)
+        kern = "k_encode"
     elif names[dom] == "gram":
-        traffic_alg = nvals * es
+        alg, kern = nvals * es, "k_gram"
     else:
-        traffic_alg = None
-    roof = None
-    if traffic_alg is not None:
-        ach = traffic_alg / (stage[dom] * 1e-3) / 1e9
-        roof = {"kernel": "k_" + names[dom], "bound": "hbm", "achieved": round(ach, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                "traffic": None, "alg_bytes_per_launch": int(traffic_alg),
-                "launch_ms": round(stage[dom], 4)}
+        alg, kern = None, "k_" + names[dom]
+    if alg is not None:
+        ach = alg / (stage[dom] * 1e-3) / 1e9
+        roof = {"kernel": kern, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kern, args.config),
+                "alg_bytes_per_launch": int(alg), "launch_ms": round(stage[dom], 4)}
     else:
-        roof = {"kernel": "k_" + names[dom], "bound": "alu", "achieved": None, "peak": None,
-                "unit": "TFLOP/s", "frac": None, "traffic": None, "launch_ms": round(stage[dom], 4)}
-
-    ratio = None
-    if not args.no_ratio:
-        log("finalize for the compression ratio")
-        t1 = time.perf_counter()
-        buf = enc.finalize()
-        ratio = in_bytes / len(buf)
-        log("finalize %.1f s" % (time.perf_counter() - t1))
+        roof = {"kernel": kern, "bound": "alu", "achieved": None, "peak": None, "unit": "TFLOP/s",
+                "frac": None, "traffic": None, "launch_ms": round(stage[dom], 4)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -191,18 +284,25 @@ def main():
         cpu = cpu_baseline(field, cfg, eps, args.cpu_seconds)
 
     out = {
-        "metric": METRIC, "value": round(gbs, 2), "unit": "GB/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "metric": METRIC, "value": round(head["gbs"], 2), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(head["ms"], 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": cfg["dtype"], "data": "synthetic",
-        "config": {"workload": args.config + ": " + cfg["desc"], "form": "plain",
+        "config": {"workload": args.config + ": " + cfg["desc"], "form": head_form + ": " + FORMS[head_form],
                    "input_bytes": in_bytes, "blocks": int(inf.nblocks)},
         "stage_ms": {n: round(s, 4) for n, s in zip(names, stage)},
-        "compression_ratio": None if ratio is None else round(ratio, 3),
+        "compression_ratio": None if "cr" not in head else round(head["cr"], 3),
         "escapes": int(inf.nescapes),
+        "warm_start_accepted": int(inf.nwarm_accept) if head["params"].learned else None,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if "plain" in res and head_form != "plain":
+        pl = res["plain"]
+        out["plain"] = {"value": round(pl["gbs"], 2), "ms_per_step": round(pl["ms"], 3),
+                        "stage_ms": {n: round(s, 4) for n, s in zip(names, pl["stage"])},
+                        "compression_ratio": None if "cr" not in pl else round(pl["cr"], 3)}
+        out["ratio_vs_plain"] = round(head["gbs"] / pl["gbs"], 4)
     print(json.dumps(out), flush=True)
 
 

@@ -69,9 +69,18 @@ enum {
                         of edge e > pmin splits into its half-edge children
                         while its mean gradient magnitude exceeds the 80th
                         percentile sorted(g)[floor(0.8 (n-1))]             */
-  DLS_LEARNED = 2    /* warm-started eigensolve with the model attached by
+  DLS_LEARNED = 2,   /* warm-started eigensolve with the model attached by
                         dls_ctx_set_model (window <= 16); blocks whose
                         prediction fails the rank test fall back to Jacobi */
+  DLS_PERSISTENT = 4 /* batched launch: no host round trip between the
+                        eigensolve and the encode.  The encode kernels walk
+                        the device-written rank-class lists with a fixed
+                        grid, into qV/qA buffers sized by earlier calls;
+                        when they do not fit, the library grows them and
+                        encodes again host-driven.  Applied to plans of up
+                        to 65536 slices (launch-bound sizes; larger plans
+                        keep the host-driven launch, faster there).  Output
+                        identical to the host-driven launch. */
 };
 
 typedef struct dls_params {
@@ -236,7 +245,9 @@ dls_status dls_model_train_step(dls_model* m, const float* d_feat, const int32_t
  * std, min, max, skewness, excess kurtosis, mean|dt|/std, std(dt)/std,
  * mean|dx|/std, mean|dy|/std, lag-1 and lag-2 temporal autocorrelation,
  * log10(mean x^2 / eps^2), log10(std / eps), time-mean energy fraction,
- * log2 M) then the 8 x 8 pooled time-mean image (normalised). */
+ * log2 M) then the 8 x 8 pooled time-mean image (normalised).  Blocks of
+ * more than 256 points (which never take the warm start) get zeros;
+ * windows above 16 steps: DLS_EINVAL. */
 dls_status dls_features(dls_ctx* ctx, const void* d_field, float* d_out, void* stream);
 /* Attach a model (NULL detaches), the number of subspace iterations
  * (0..64) and a rank margin (0..16: the warm start uses rhat + margin

@@ -293,6 +293,7 @@ def warm_start_eig(G: np.ndarray, V0: np.ndarray, tau: float, iters: int = 2):
 
 
 WARM_MAX = 8      # most columns the warm start iterates; larger predictions fall back
+WARM_MAX_POINTS = 256    # larger blocks take the plain eigensolve directly
 RETRY_EXTRA = 4   # columns added by the second attempt
 RETRY_ITERS = 2   # subspace iterations added by the second attempt
 
@@ -312,6 +313,8 @@ def encode_block_learned(xs: np.ndarray, eps: float, rcap: int, dtype, rhat: int
     x = xs.astype(np.float64)
     if not np.all(np.isfinite(x)):
         return dls._raw_block(xs), False
+    if m > WARM_MAX_POINTS:
+        return dls.encode_block(xs, eps, rcap, dtype), False
     G = x @ x.T
     tau = dls.KAPPA * eps * eps * m * wb
     cap = min(rcap, wb, m)

@@ -26,6 +26,7 @@ LIB_PATH = os.path.join(_HERE, "libdls.so")
 DLS_OK, DLS_EINVAL, DLS_ENOMEM, DLS_EDEVICE, DLS_ECORRUPT, DLS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 DLS_F32, DLS_F64 = 0, 1
 DLS_PREC_FP32, DLS_PREC_BF16 = 0, 1
+DLS_PERSISTENT = 4
 DLS_ADAPTIVE = 1
 DLS_LEARNED = 2
 NPARAM = 61968
@@ -148,6 +149,7 @@ class Params:
     precision: str = "fp32"   # "fp32" | "bf16"
     adaptive: bool = False
     learned: bool = False
+    persistent: bool = False  # device-driven (batched) encode launch
     _keep: list = dc_field(default_factory=list, repr=False)
 
     def to_c(self) -> _Params:
@@ -157,7 +159,8 @@ class Params:
                        DLS_F32 if self.dtype == "f32" else DLS_F64, self.px, self.py, self.pz,
                        self.pmin, self.window, self.r_max,
                        DLS_PREC_BF16 if self.precision == "bf16" else DLS_PREC_FP32,
-                       (DLS_ADAPTIVE if self.adaptive else 0) | (DLS_LEARNED if self.learned else 0),
+                       (DLS_ADAPTIVE if self.adaptive else 0) | (DLS_LEARNED if self.learned else 0)
+                       | (DLS_PERSISTENT if self.persistent else 0),
                        ctypes.cast(arr, ctypes.POINTER(ctypes.c_double)))
 
     @property

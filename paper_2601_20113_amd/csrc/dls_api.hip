@@ -65,6 +65,8 @@ struct DevBuf {
     else p = nullptr;
     return e;
   }
+  // at least `bytes`, contents not kept
+  hipError_t grow(size_t bytes) { return ensure(bytes); }
   template <typename T>
   T* as() const { return static_cast<T*>(p); }
 };
@@ -111,7 +113,7 @@ dls_status validate(const dls_params* in, Problem& p) {
   if (p.nz == 1 && p.pz != 1) return fail(DLS_EINVAL, "pz must be 1 for a 2D field");
   if (in->r_max < 0 || in->r_max > 32) return fail(DLS_EINVAL, "r_max must be in [0, 32]");
   p.r_max = in->r_max > 0 ? in->r_max : std::min(p.window, 32);
-  if (p.flags & ~uint32_t(DLS_ADAPTIVE | DLS_LEARNED)) return fail(DLS_EINVAL, "unknown flags");
+  if (p.flags & ~uint32_t(DLS_ADAPTIVE | DLS_LEARNED | DLS_PERSISTENT)) return fail(DLS_EINVAL, "unknown flags");
   if ((p.flags & DLS_LEARNED) && p.window > 16) return fail(DLS_EINVAL, "DLS_LEARNED needs window <= 16");
   if (p.precision != DLS_PREC_FP32 && p.precision != DLS_PREC_BF16)
     return fail(DLS_EINVAL, "unknown precision");
@@ -300,6 +302,25 @@ dls_status learned_eigen(dls_ctx* ctx, const void* d_field, const Problem& p, co
 }
 }  // namespace
 
+namespace {
+constexpr int64_t kDeviceDrivenMaxItems = 65536;
+
+// device time of the whole encode and of its five stages, from the events
+dls_status finish_encode(dls_ctx* ctx) {
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  ctx->gpu_ms = ms;
+  const hipEvent_t marks[5][2] = {{ctx->evs[4], ctx->ev0}, {ctx->ev0, ctx->evs[0]}, {ctx->evs[0], ctx->evs[1]},
+                                  {ctx->evs[1], ctx->evs[2]}, {ctx->evs[3], ctx->ev1}};
+  for (int i = 0; i < 5; ++i) {
+    HIP_TRY(hipEventElapsedTime(&ms, marks[i][0], marks[i][1]));
+    ctx->stage_ms[i] = ms;
+  }
+  ctx->have_result = true;
+  return DLS_OK;
+}
+}  // namespace
+
 extern "C" {
 
 const char* dls_last_error(void) { return g_err.c_str(); }
@@ -414,7 +435,7 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
   HIP_TRY(ctx->qa_off.ensure(size_t(nb) * sizeof(int64_t)));
   HIP_TRY(ctx->scan_tmp.ensure(size_t(4 * (nb / 1024 + 4)) * sizeof(int64_t)));
   HIP_TRY(ctx->codes.ensure(size_t(pl.codes_bytes)));
-  HIP_TRY(ctx->counters.ensure(4 * sizeof(unsigned long long) + kRankClasses * sizeof(unsigned int)));
+  HIP_TRY(ctx->counters.ensure(kCounterBytes));
   HIP_TRY(ctx->cls_lists.ensure(size_t(ni) * kRankClasses * sizeof(int32_t)));
   if (ctx->esc_cap == 0) {
     ctx->esc_cap = std::max<uint64_t>(uint64_t(1) << 20, uint64_t(p.values() / 256));
@@ -427,7 +448,7 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
   HIP_TRY(ctx->eps_v.ensure(p.eps.size() * sizeof(double)));
   HIP_TRY(hipMemcpyAsync(ctx->vconst.p, vc.data(), vc.size() * sizeof(VarConst), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(ctx->eps_v.p, p.eps.data(), p.eps.size() * sizeof(double), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemsetAsync(ctx->counters.p, 0, 4 * sizeof(unsigned long long) + kRankClasses * sizeof(unsigned int), s));
+  HIP_TRY(launch_zero(ctx->counters.p, kCounterBytes, s));
 
   const Dims dims{p.nx, p.ny, p.nz, p.nt};
   unsigned long long* cnt = ctx->counters.as<unsigned long long>();
@@ -451,6 +472,60 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
   HIP_TRY(launch_classify(ctx->items.as<Item>(), ni, ctx->rank.as<uint8_t>(), cls_count,
                           ctx->cls_lists.as<int32_t>(), s));
   HIP_TRY(hipEventRecord(ctx->evs[2], s));
+  unsigned int* overflow = reinterpret_cast<unsigned int*>(reinterpret_cast<uint8_t*>(cnt) + kOverflowAt);
+  int64_t* totals = reinterpret_cast<int64_t*>(reinterpret_cast<uint8_t*>(cnt) + kTotalsAt);
+  ctx->keep_coef = keep_coef != 0;
+  // the device-driven launch saves the host round trip (~0.1-0.2 ms) but its
+  // looping workgroups encode large lists more slowly than one workgroup per
+  // item; measured on the synthetic workloads the crossover lies between
+  // ~10^4 and ~2 x 10^5 items, so larger plans keep the host-driven launch
+  if ((p.flags & DLS_PERSISTENT) && ni <= kDeviceDrivenMaxItems) {
+    // device-driven encode into the buffers as they are; one readback at the end
+    HIP_TRY(ctx->qv.ensure(16));
+    HIP_TRY(ctx->qa.ensure(16));
+    if (ctx->keep_coef) HIP_TRY(ctx->coef.ensure(ctx->qa.n));
+    HIP_TRY(launch_totals(ctx->qv_off.as<int64_t>(), ctx->qv_size.as<int64_t>(), ctx->qa_off.as<int64_t>(),
+                          ctx->qa_size.as<int64_t>(), nb, totals, s));
+    EscOut esc{cnt, ctx->esc_key.as<uint64_t>(), ctx->esc_val.as<uint64_t>(), ctx->esc_cap};
+    HIP_TRY(hipEventRecord(ctx->evs[3], s));
+    for (int c = 0; c < kRankClasses; ++c) {
+      const EncodeWork work{cls_count + c, ni, int64_t(ctx->qv.n), int64_t(ctx->qa.n), overflow};
+      HIP_TRY(launch_encode(wp, p.dtype, c, d_field, dims, ctx->desc.as<BlockDesc>(), ctx->items.as<Item>(),
+                            ctx->cls_lists.as<int32_t>() + int64_t(c) * ni, work, ctx->rank.as<uint8_t>(),
+                            ctx->basis.as<double>(), ctx->qv_off.as<int64_t>(), ctx->qa_off.as<int64_t>(),
+                            ctx->code_off.as<int64_t>(), ctx->vconst.as<VarConst>(), ctx->qv.as<uint8_t>(),
+                            ctx->qa.as<uint8_t>(), ctx->codes.as<uint8_t>(),
+                            ctx->keep_coef ? ctx->coef.as<float>() : nullptr, esc, s));
+    }
+    HIP_TRY(hipEventRecord(ctx->ev1, s));
+    uint8_t hbuf[kCounterBytes];
+    HIP_TRY(hipMemcpyAsync(hbuf, cnt, kCounterBytes, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    unsigned long long hc[4];
+    unsigned int hov;
+    int64_t ht[2];
+    std::memcpy(hc, hbuf, sizeof(hc));
+    std::memcpy(&hov, hbuf + kOverflowAt, 4);
+    std::memcpy(ht, hbuf + kTotalsAt, sizeof(ht));
+    ctx->qv_bytes = ht[0];
+    ctx->qa_bytes = ht[1];
+    ctx->nesc = int64_t(hc[0]);
+    ctx->nraw = int64_t(hc[1]);
+    ctx->nwarm_accept = learned ? int64_t(hc[2]) : 0;
+    ctx->nwarm_reject = learned ? int64_t(hc[3]) : 0;
+    if (hov == 0 && hc[0] <= ctx->esc_cap) return finish_encode(ctx);
+    // did not fit: grow with headroom for later calls, then the host-driven
+    // encode below rewrites every output
+    HIP_TRY(ctx->qv.grow(size_t(ht[0] + ht[0] / 4 + 16)));
+    HIP_TRY(ctx->qa.grow(size_t(ht[1] + ht[1] / 4 + 16)));
+    if (ctx->keep_coef) HIP_TRY(ctx->coef.grow(ctx->qa.n));
+    if (hc[0] > ctx->esc_cap) {
+      ctx->esc_cap = hc[0] + (hc[0] >> 3) + 1024;
+      HIP_TRY(ctx->esc_key.ensure(ctx->esc_cap * 8));
+      HIP_TRY(ctx->esc_val.ensure(ctx->esc_cap * 8));
+    }
+    HIP_TRY(launch_zero(cnt, sizeof(unsigned long long), s));
+  }
   unsigned int hcls[kRankClasses];
   HIP_TRY(hipMemcpyAsync(hcls, cls_count, sizeof(hcls), hipMemcpyDeviceToHost, s));
   int64_t tail[4];
@@ -463,7 +538,6 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
   ctx->qa_bytes = tail[2] + tail[3];
   HIP_TRY(ctx->qv.ensure(size_t(ctx->qv_bytes)));
   HIP_TRY(ctx->qa.ensure(size_t(ctx->qa_bytes)));
-  ctx->keep_coef = keep_coef != 0;
   if (ctx->keep_coef) HIP_TRY(ctx->coef.ensure(size_t(ctx->qa_bytes)));
 
   for (int attempt = 0; attempt < 2; ++attempt) {
@@ -471,7 +545,9 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
     HIP_TRY(hipEventRecord(ctx->evs[3], s));
     for (int c = 0; c < kRankClasses; ++c)
       HIP_TRY(launch_encode(wp, p.dtype, c, d_field, dims, ctx->desc.as<BlockDesc>(), ctx->items.as<Item>(),
-                            ctx->cls_lists.as<int32_t>() + int64_t(c) * ni, hcls[c], ctx->rank.as<uint8_t>(),
+                            ctx->cls_lists.as<int32_t>() + int64_t(c) * ni,
+                            EncodeWork{nullptr, int64_t(hcls[c]), int64_t(ctx->qv.n), int64_t(ctx->qa.n), overflow},
+                            ctx->rank.as<uint8_t>(),
                             ctx->basis.as<double>(), ctx->qv_off.as<int64_t>(), ctx->qa_off.as<int64_t>(),
                             ctx->code_off.as<int64_t>(), ctx->vconst.as<VarConst>(), ctx->qv.as<uint8_t>(),
                             ctx->qa.as<uint8_t>(), ctx->codes.as<uint8_t>(),
@@ -490,19 +566,9 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
     ctx->esc_cap = hc[0] + (hc[0] >> 3) + 1024;
     HIP_TRY(ctx->esc_key.ensure(ctx->esc_cap * 8));
     HIP_TRY(ctx->esc_val.ensure(ctx->esc_cap * 8));
-    HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s));
+    HIP_TRY(launch_zero(cnt, sizeof(unsigned long long), s));
   }
-  float ms = 0.f;
-  HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-  ctx->gpu_ms = ms;
-  const hipEvent_t marks[5][2] = {{ctx->evs[4], ctx->ev0}, {ctx->ev0, ctx->evs[0]}, {ctx->evs[0], ctx->evs[1]},
-                                  {ctx->evs[1], ctx->evs[2]}, {ctx->evs[3], ctx->ev1}};
-  for (int i = 0; i < 5; ++i) {
-    HIP_TRY(hipEventElapsedTime(&ms, marks[i][0], marks[i][1]));
-    ctx->stage_ms[i] = ms;
-  }
-  ctx->have_result = true;
-  return DLS_OK;
+  return finish_encode(ctx);
 }
 
 dls_status dls_model_create(int device, dls_model** out) {

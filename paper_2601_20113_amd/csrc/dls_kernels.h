@@ -24,6 +24,33 @@ struct EscOut {
   unsigned long long cap;
 };
 
+// How an encode launch finds its work.  Host-driven: `count` items of the
+// class list, one workgroup each.  Device-driven (dcount != NULL): a fixed
+// grid walks the *dcount items the classifier wrote, so no host round trip
+// is needed between the eigensolve and the encode.  An item whose qV or qA
+// region would end beyond qv_cap / qa_cap writes nothing and sets
+// *overflow (the host then grows the buffers and encodes again).
+struct EncodeWork {
+  const unsigned int* dcount;
+  int64_t count;
+  int64_t qv_cap, qa_cap;
+  unsigned int* overflow;
+};
+
+// Layout of the per-encode counter block: four u64 (escapes, raw blocks,
+// warm starts accepted, rejected), kRankClasses u32 class counts, the u32
+// overflow flag of a device-driven encode, and the two i64 payload totals
+// (qV bytes, qA bytes).
+constexpr int kRankClasses = 6;  // r <= 1, 2, 4, 8, 16, 32
+constexpr size_t kOverflowAt = 4 * 8 + kRankClasses * 4;
+constexpr size_t kTotalsAt = 64;
+constexpr size_t kCounterBytes = kTotalsAt + 16;
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+// totals[0] = qv_off[n-1] + qv_size[n-1], totals[1] likewise for qA
+hipError_t launch_totals(const int64_t* qv_off, const int64_t* qv_size, const int64_t* qa_off,
+                         const int64_t* qa_size, int64_t n, int64_t* totals, hipStream_t s);
+
 hipError_t launch_gram(int wp, int dtype, bool bf16, const void* F, const Dims& dims, const BlockDesc* desc,
                        const Item* items, int64_t nitems, double* gpart, hipStream_t s);
 // `only` (may be NULL): solve only the blocks b with only[b] != 0
@@ -43,6 +70,11 @@ hipError_t launch_colsum(const float* G, int64_t n, int cols, float* out, hipStr
 hipError_t launch_relu_mask(float* dh, const float* h, int64_t n, hipStream_t s);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float c1, float c2,
                        hipStream_t s);
+// Blocks of more points than this take the plain eigensolve: the warm start
+// pays for one extra read of the block (its features), which outweighs the
+// Jacobi work it saves beyond about this size at W = 16.
+constexpr int kWarmMaxPoints = 256;
+
 // Warm-start network 80 -> 128 -> 128 -> 272 (ReLU), flat FP32 parameters
 // W1 (80 x 128, row-major [in][out]), b1, W2, b2, W3, b3.
 constexpr int kNF = 80, kH = 128, kNO = 272;
@@ -64,11 +96,10 @@ hipError_t launch_warmstart(const double* gpart, const int32_t* item_start, cons
 hipError_t launch_scan(const int64_t* in, int64_t n, int64_t* out, int64_t* tmp, hipStream_t s);
 hipError_t launch_range(int dtype, const void* F, int nvars, int64_t n_per_var, double* part, int nparts,
                         double* out, hipStream_t s);
-constexpr int kRankClasses = 6;  // r <= 1, 2, 4, 8, 16, 32
 hipError_t launch_classify(const Item* items, int64_t nitems, const uint8_t* rank, unsigned int* counts,
                            int32_t* lists, hipStream_t s);
 hipError_t launch_encode(int wp, int dtype, int cls, const void* F, const Dims& dims, const BlockDesc* desc,
-                         const Item* items, const int32_t* list, int64_t count, const uint8_t* rank,
+                         const Item* items, const int32_t* list, const EncodeWork& work, const uint8_t* rank,
                          const double* basis, const int64_t* qv_off, const int64_t* qa_off,
                          const int64_t* code_off, const VarConst* vc, uint8_t* qv, uint8_t* qa,
                          uint8_t* codes, float* coef, EscOut esc, hipStream_t s);

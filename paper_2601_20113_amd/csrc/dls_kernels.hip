@@ -19,6 +19,8 @@
 // for bit.  Fused multiply-adds are written explicitly where wanted.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "dls_device.h"
 #include "dls_kernels.h"
 
@@ -453,30 +455,35 @@ __device__ __forceinline__ void store_bytes(uint8_t* __restrict__ dst, const uin
 
 // RMAX is the rank class of the launch (every block in it has r <= RMAX), so
 // the per-point coefficient registers are sized for the class, not for W.
-template <int WP, typename T, int PPT, int RMAX>
-__global__ __launch_bounds__(256) void k_encode(const T* __restrict__ F, Dims dims,
-                                                const BlockDesc* __restrict__ desc,
-                                                const Item* __restrict__ items,
-                                                const int32_t* __restrict__ item_list,
-                                                const uint8_t* __restrict__ rank,
-                                                const double* __restrict__ basis,
-                                                const int64_t* __restrict__ qv_off,
-                                                const int64_t* __restrict__ qa_off,
-                                                const int64_t* __restrict__ code_off,
-                                                const VarConst* __restrict__ vc,
-                                                uint8_t* __restrict__ qv_buf,
-                                                uint8_t* __restrict__ qa_buf,
-                                                uint8_t* __restrict__ codes,
-                                                float* __restrict__ coef,
-                                                EscOut esc) {
-  __shared__ float Vf[RMAX][WP];    // [k][t]
-  __shared__ double Qv[WP][RMAX];   // [t][k], integer valued
-  const Item it = items[item_list[blockIdx.x]];
+template <int WP, typename T, int PPT, int RMAX, bool DEV>
+__device__ __forceinline__ void encode_item(int64_t li, float (&Vf)[RMAX][WP], double (&Qv)[WP][RMAX],
+                                            const T* __restrict__ F, const Dims& dims,
+                                            const BlockDesc* __restrict__ desc,
+                                            const Item* __restrict__ items,
+                                            const int32_t* __restrict__ item_list,
+                                            const uint8_t* __restrict__ rank,
+                                            const double* __restrict__ basis,
+                                            const int64_t* __restrict__ qv_off,
+                                            const int64_t* __restrict__ qa_off,
+                                            const int64_t* __restrict__ code_off,
+                                            const VarConst* __restrict__ vc,
+                                            uint8_t* __restrict__ qv_buf,
+                                            uint8_t* __restrict__ qa_buf,
+                                            uint8_t* __restrict__ codes,
+                                            float* __restrict__ coef,
+                                            const EscOut& esc, const EncodeWork& work) {
+  const Item it = items[item_list[li]];
   const int b = it.block;
   const BlockDesc d = desc[b];
   const int W = d.w(), M = d.m, r = rank[b];
   const VarConst K = vc[d.var];
   const int64_t wm_pad = pad16(int64_t(W) * M);
+  if constexpr (DEV) {  // host-driven launches size the buffers exactly
+    if (qv_off[b] + 4 * pad16(int64_t(W) * r) > work.qv_cap || qa_off[b] + 4 * pad16(int64_t(M) * r) > work.qa_cap) {
+      if (threadIdx.x == 0) atomicOr(work.overflow, 1u);
+      return;
+    }
+  }
 
   for (int idx = threadIdx.x; idx < RMAX * WP; idx += blockDim.x) {
     const int k = idx / WP, t = idx % WP;
@@ -649,6 +656,39 @@ __global__ __launch_bounds__(256) void k_encode(const T* __restrict__ F, Dims di
     }
     store_bytes<PPT>(codes + code_lo + int64_t(t) * M, lo, valid, vec);
     store_bytes<PPT>(codes + code_hi + int64_t(t) * M, hi, valid, vec);
+  }
+}
+
+// DEV = false: host-driven, one item per workgroup; DEV = true:
+// device-driven, the grid walks the *work.dcount items of the list
+template <int WP, typename T, int PPT, int RMAX, bool DEV>
+__global__ __launch_bounds__(256) void k_encode(const T* __restrict__ F, Dims dims,
+                                                const BlockDesc* __restrict__ desc,
+                                                const Item* __restrict__ items,
+                                                const int32_t* __restrict__ item_list,
+                                                const uint8_t* __restrict__ rank,
+                                                const double* __restrict__ basis,
+                                                const int64_t* __restrict__ qv_off,
+                                                const int64_t* __restrict__ qa_off,
+                                                const int64_t* __restrict__ code_off,
+                                                const VarConst* __restrict__ vc,
+                                                uint8_t* __restrict__ qv_buf,
+                                                uint8_t* __restrict__ qa_buf,
+                                                uint8_t* __restrict__ codes,
+                                                float* __restrict__ coef,
+                                                EscOut esc, EncodeWork work) {
+  __shared__ float Vf[RMAX][WP];    // [k][t]
+  __shared__ double Qv[WP][RMAX];   // [t][k], integer valued
+  if constexpr (!DEV) {
+    encode_item<WP, T, PPT, RMAX, false>(blockIdx.x, Vf, Qv, F, dims, desc, items, item_list, rank, basis, qv_off,
+                                  qa_off, code_off, vc, qv_buf, qa_buf, codes, coef, esc, work);
+    return;
+  }
+  const int64_t nwork = int64_t(*work.dcount);
+  for (int64_t li = blockIdx.x; li < nwork; li += gridDim.x) {
+    if (li != blockIdx.x) __syncthreads();  // the previous item's LDS reads are done
+    encode_item<WP, T, PPT, RMAX, true>(li, Vf, Qv, F, dims, desc, items, item_list, rank, basis, qv_off, qa_off,
+                                  code_off, vc, qv_buf, qa_buf, codes, coef, esc, work);
   }
 }
 
@@ -831,6 +871,33 @@ __global__ __launch_bounds__(256) void k_classify(const Item* __restrict__ items
 // ---------------------------------------------------------------------------
 // Launch wrappers
 // ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_zero(uint32_t* __restrict__ p, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+__global__ void k_totals(const int64_t* __restrict__ qv_off, const int64_t* __restrict__ qv_size,
+                         const int64_t* __restrict__ qa_off, const int64_t* __restrict__ qa_size, int64_t n,
+                         int64_t* __restrict__ totals) {
+  if (threadIdx.x == 0) {
+    totals[0] = n ? qv_off[n - 1] + qv_size[n - 1] : 0;
+    totals[1] = n ? qa_off[n - 1] + qa_size[n - 1] : 0;
+  }
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+  const int64_t n = int64_t(bytes / 4);  // whole words; every user passes a multiple of 4
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero, dim3{unsigned((n + 255) / 256)}, dim3{256}, 0, s, static_cast<uint32_t*>(p), n);
+  return hipGetLastError();
+}
+
+hipError_t launch_totals(const int64_t* qv_off, const int64_t* qv_size, const int64_t* qa_off,
+                         const int64_t* qa_size, int64_t n, int64_t* totals, hipStream_t s) {
+  hipLaunchKernelGGL(k_totals, dim3{1}, dim3{64}, 0, s, qv_off, qv_size, qa_off, qa_size, n, totals);
+  return hipGetLastError();
+}
+
 hipError_t launch_gram(int wp, int dtype, bool bf16, const void* F, const Dims& dims, const BlockDesc* desc,
                        const Item* items, int64_t nitems, double* gpart, hipStream_t s) {
   if (nitems == 0) return hipSuccess;
@@ -891,11 +958,17 @@ static void encode_class(int cls, const dim3& g, hipStream_t s, const T* F, cons
                          const BlockDesc* desc, const Item* items, const int32_t* list, const uint8_t* rank,
                          const double* basis, const int64_t* qv_off, const int64_t* qa_off,
                          const int64_t* code_off, const VarConst* vc, uint8_t* qv, uint8_t* qa,
-                         uint8_t* codes, float* coef, EscOut esc) {
+                         uint8_t* codes, float* coef, EscOut esc, const EncodeWork& work) {
   const dim3 bl{256};
-#define DLS_ENC(R)                                                                                       \
-  hipLaunchKernelGGL((k_encode<WP, T, PPT, R>), g, bl, 0, s, F, dims, desc, items, list, rank, basis,  \
-                     qv_off, qa_off, code_off, vc, qv, qa, codes, coef, esc)
+#define DLS_ENC(R)                                                                                         \
+  do {                                                                                                     \
+    if (work.dcount)                                                                                       \
+      hipLaunchKernelGGL((k_encode<WP, T, PPT, R, true>), g, bl, 0, s, F, dims, desc, items, list, rank,  \
+                         basis, qv_off, qa_off, code_off, vc, qv, qa, codes, coef, esc, work);             \
+    else                                                                                                   \
+      hipLaunchKernelGGL((k_encode<WP, T, PPT, R, false>), g, bl, 0, s, F, dims, desc, items, list, rank, \
+                         basis, qv_off, qa_off, code_off, vc, qv, qa, codes, coef, esc, work);             \
+  } while (0)
   switch (cls) {
     case 0: DLS_ENC(1); break;
     case 1: DLS_ENC(2); break;
@@ -910,20 +983,23 @@ static void encode_class(int cls, const dim3& g, hipStream_t s, const T* F, cons
 }
 
 hipError_t launch_encode(int wp, int dtype, int cls, const void* F, const Dims& dims, const BlockDesc* desc,
-                         const Item* items, const int32_t* list, int64_t count, const uint8_t* rank,
+                         const Item* items, const int32_t* list, const EncodeWork& work, const uint8_t* rank,
                          const double* basis, const int64_t* qv_off, const int64_t* qa_off,
                          const int64_t* code_off, const VarConst* vc, uint8_t* qv, uint8_t* qa,
                          uint8_t* codes, float* coef, EscOut esc, hipStream_t s) {
-  if (count == 0) return hipSuccess;
-  const dim3 g{unsigned(count)};
-  if (wp == 16 && dtype == 0)
-    encode_class<16, float, 4>(cls, g, s, (const float*)F, dims, desc, items, list, rank, basis, qv_off, qa_off, code_off, vc, qv, qa, codes, coef, esc);
-  else if (wp == 16)
-    encode_class<16, double, 2>(cls, g, s, (const double*)F, dims, desc, items, list, rank, basis, qv_off, qa_off, code_off, vc, qv, qa, codes, coef, esc);
-  else if (dtype == 0)
-    encode_class<32, float, 2>(cls, g, s, (const float*)F, dims, desc, items, list, rank, basis, qv_off, qa_off, code_off, vc, qv, qa, codes, coef, esc);
-  else
-    encode_class<32, double, 2>(cls, g, s, (const double*)F, dims, desc, items, list, rank, basis, qv_off, qa_off, code_off, vc, qv, qa, codes, coef, esc);
+  // host-driven: one workgroup per item; device-driven: a grid that fills
+  // the chip a few times over and walks the list
+  const int64_t grid = work.dcount ? std::min<int64_t>(work.count, 4096) : work.count;
+  if (grid == 0) return hipSuccess;
+  const dim3 g{unsigned(grid)};
+#define DLS_ENC_CLASS(WPV, TV, PPTV) \
+  encode_class<WPV, TV, PPTV>(cls, g, s, (const TV*)F, dims, desc, items, list, rank, basis, qv_off, qa_off, \
+                              code_off, vc, qv, qa, codes, coef, esc, work)
+  if (wp == 16 && dtype == 0) DLS_ENC_CLASS(16, float, 4);
+  else if (wp == 16) DLS_ENC_CLASS(16, double, 2);
+  else if (dtype == 0) DLS_ENC_CLASS(32, float, 2);
+  else DLS_ENC_CLASS(32, double, 2);
+#undef DLS_ENC_CLASS
   return hipGetLastError();
 }
 

@@ -35,16 +35,21 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_features(const T* __restrict__ F, Dims dims,
                                                   const BlockDesc* __restrict__ desc, int64_t nblocks,
                                                   const double* __restrict__ eps_v, float* __restrict__ feat) {
-  constexpr int kStage = 1024;  // blocks up to this many points keep their time sums in LDS
+  constexpr int kStage = kWarmMaxPoints;  // the block's per-point time sums live in LDS
   __shared__ double sts[4][kStage];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t b = int64_t(blockIdx.x) * 4 + wv;
   if (b >= nblocks) return;
   const BlockDesc d = desc[b];
   const int W = d.w(), M = d.m, px = d.px(), py = d.py(), pz = d.pz();
+  if (M > kWarmMaxPoints) {  // no warm start for this block: no features either
+    feat[b * 80 + lane] = 0.f;
+    if (lane < 16) feat[b * 80 + 64 + lane] = 0.f;
+    return;
+  }
   const int64_t nxy = dims.nx * dims.ny, tstride = dims.nz * nxy;
   const T* base = F + (((int64_t(d.var) * dims.nt + d.t0) * dims.nz + d.z0) * dims.ny + d.y0) * dims.nx + d.x0;
-  const bool stage = M <= kStage;
+  const bool stage = true;  // M <= kWarmMaxPoints = kStage
   // the W values of point p (W <= 16), all loads issued before any use
   auto load_point = [&](int p, int64_t shift, double* x) {
     const int i = p % px, rho = p / px, j = rho % py, k = rho / py;
@@ -617,7 +622,7 @@ __global__ __launch_bounds__(256) void k_warmstart(const double* __restrict__ gp
     const int nc = retry ? rhat2 : rhat;
     const int nit = retry ? iters + kRetryIters : iters;
     int r = 0;
-    if (fin && nc <= RH && (!retry || rhat2 > rhat)) {
+    if (fin && M <= kWarmMaxPoints && nc <= RH && (!retry || rhat2 > rhat)) {
       double q[RH];
 #pragma unroll
       for (int k = 0; k < RH; ++k) q[k] = (t < W && k < nc) ? double(o[16 + k * 16 + t]) : 0.0;

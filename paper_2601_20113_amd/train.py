@@ -39,34 +39,41 @@ def c1_fields(seeds, nx=64, ny=64, nt=32):
     return f, eps
 
 
+def label_blocks(enc: "dls.Encoder", field: torch.Tensor, p: "dls.Params") -> dict:
+    """Encode `field` with the plain method and return its labelled blocks
+    (raw blocks dropped): device tensors feat (n x 80), rank (n,),
+    basis (n x 256, [k][t]) and wb (n,)."""
+    enc.encode(field, p)
+    inf = enc.info()
+    nb = inf.nblocks
+    rank = torch.empty(nb, dtype=torch.uint8, device=field.device)
+    dls.d2d(rank, inf.d_rank, nb)
+    basis = torch.empty((nb, 16, 16), dtype=torch.float64, device=field.device)
+    dls.d2d(basis, inf.d_basis, nb * 256 * 8)
+    desc = torch.empty((nb, 8), dtype=torch.int32, device=field.device)
+    dls.d2d(desc, inf.d_desc, nb * 32)
+    feat = enc.features(field)
+    keep = rank > 0
+    return {"feat": feat[keep], "rank": rank[keep].to(torch.int32),
+            "basis": basis[keep].reshape(-1, 256).to(torch.float32),
+            "wb": ((desc[keep, 4] >> 24) & 255).to(torch.int32)}
+
+
+def merge(parts) -> dict:
+    return {k: torch.cat([q[k] for q in parts]) for k in ("feat", "rank", "basis", "wb")}
+
+
 def collect(seeds, chunk: int = 64, px: int = 8, window: int = 16):
-    """Labelled blocks of config-1 fields: dict of device tensors
-    feat (n x 80), rank (n,), basis (n x 256, [k][t]), wb (n,)."""
+    """Labelled blocks of config-1 fields (see label_blocks)."""
     enc = dls.Encoder()
-    feats, ranks, bases, wbs = [], [], [], []
+    parts = []
     for i in range(0, len(seeds), chunk):
         f, eps = c1_fields(seeds[i:i + chunk])
         nv, nt, nz, ny, nx = f.shape
         p = dls.Params(nx=nx, ny=ny, nz=nz, nt=nt, nvars=nv, dtype="f64", px=px, py=px, pz=1,
                        window=window, eps=eps)
-        t = torch.from_numpy(f).cuda()
-        enc.encode(t, p)
-        inf = enc.info()
-        nb = inf.nblocks
-        rank = torch.empty(nb, dtype=torch.uint8, device="cuda")
-        dls.d2d(rank, inf.d_rank, nb)
-        basis = torch.empty((nb, 16, 16), dtype=torch.float64, device="cuda")
-        dls.d2d(basis, inf.d_basis, nb * 256 * 8)
-        desc = torch.empty((nb, 8), dtype=torch.int32, device="cuda")
-        dls.d2d(desc, inf.d_desc, nb * 32)
-        feat = enc.features(t)
-        keep = rank > 0
-        feats.append(feat[keep])
-        ranks.append(rank[keep].to(torch.int32))
-        bases.append(basis[keep].reshape(-1, 256).to(torch.float32))
-        wbs.append(((desc[keep, 4] >> 24) & 255).to(torch.int32))
-    return {"feat": torch.cat(feats), "rank": torch.cat(ranks), "basis": torch.cat(bases),
-            "wb": torch.cat(wbs)}
+        parts.append(label_blocks(enc, torch.from_numpy(f).cuda(), p))
+    return merge(parts)
 
 
 def zscore(feat: torch.Tensor) -> np.ndarray:
@@ -101,15 +108,22 @@ def train(model: "dls.Model", data: dict, epochs: int = 10, batch: int = 1024, l
     return losses
 
 
+def fit_data(data: dict, epochs=10, batch=1024, lr=1e-3, seed=0, log=None):
+    """Set the z-scoring from `data`, train from He initialisation; returns (model, losses)."""
+    model = dls.Model()
+    model.set(he_init(seed), zscore(data["feat"]))
+    batch = max(1, min(batch, int(data["feat"].shape[0])))
+    losses = train(model, data, epochs, batch, lr, seed, log)
+    return model, losses
+
+
 def fit(train_seeds, epochs=10, batch=1024, lr=1e-3, seed=0, log=None):
     """Collect labels, set the z-scoring, train; returns (model, data, losses)."""
     t0 = time.perf_counter()
     data = collect(train_seeds)
     if log:
         log("collected %d blocks in %.1f s" % (data["feat"].shape[0], time.perf_counter() - t0))
-    model = dls.Model()
-    model.set(he_init(seed), zscore(data["feat"]))
-    losses = train(model, data, epochs, batch, lr, seed, log)
+    model, losses = fit_data(data, epochs, batch, lr, seed, log)
     return model, data, losses
 
 

@@ -258,3 +258,25 @@ def test_bf16_gram_parity(name):
     cr_fp = f.nbytes / len(container.pack(enc_fp))
     print("CR gpu-bf16 %.4f oracle-bf16 %.4f oracle-full %.4f" % (cr_g, cr_bf, cr_fp), flush=True)
     assert abs(cr_g / cr_bf - 1.0) <= 0.01
+
+
+def test_persistent_launch_matches_host_driven():
+    """DLS_PERSISTENT (device-driven encode launch) writes the same stream as
+    the host-driven launch: on a first call (buffers too small: it grows them
+    and encodes again), on a repeat call (fits), and after switching to a
+    field that needs more room, with escapes and a raw block present."""
+    enc = dls.Encoder()
+    for name in ["blobs_f32_96x64x20", "blobs_f32_96x64x20", "c1_64x64x32_f64", "spec3d_f32_w32_2var"]:
+        f, p = _case(name)
+        f = f.copy()
+        f.reshape(-1)[7] = np.nan
+        f.reshape(-1)[f.size // 2] = 1e9
+        ref = H.GpuRun(f, p).stream
+        lp = H.to_lib_params(p)
+        lp.persistent = True
+        t = torch.from_numpy(f).cuda()
+        enc.encode(t, lp)
+        got = enc.finalize()
+        print(name, "persistent stream", len(got), "host-driven", len(ref), "escapes", enc.info().nescapes,
+              flush=True)
+        assert got == ref

@@ -215,3 +215,14 @@ def test_learned_retry_and_limits():
     assert not acc and code.r == plain.r
     code, acc = L.encode_block_learned(x, eps, 16, np.float64, 3, V0)
     assert acc and code.r == plain.r
+
+
+def test_large_blocks_take_the_plain_eigensolve():
+    """Blocks above WARM_MAX_POINTS points are not warm-started: the result
+    is the plain encode, reported as not accepted."""
+    rng = np.random.default_rng(21)
+    x = rng.normal(size=(16, L.WARM_MAX_POINTS + 1))
+    V0 = np.eye(16)
+    code, acc = L.encode_block_learned(x, 1e-2, 16, np.float64, 2, V0)
+    plain = dls.encode_block(x, 1e-2, 16, np.float64)
+    assert not acc and code.r == plain.r and np.array_equal(code.qA, plain.qA)

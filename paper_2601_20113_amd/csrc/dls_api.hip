@@ -244,6 +244,7 @@ struct dls_ctx {
   Problem prob;
   bool plan_valid = false;
   Plan plan;
+  int64_t plan_warm_blocks = 0;  // blocks small enough for the warm start
   DevBuf desc, items, item_start, code_off, gram, rank, lam, basis;
   DevBuf qv_size, qa_size, qv_off, qa_off, scan_tmp, qv, qa, codes, coef;
   DevBuf esc_key, esc_val, counters, vconst, eps_v, cls_lists;
@@ -386,6 +387,8 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
       ctx->plan.bits.assign(p.nvars, {});
     }
     build_blocks(p, ctx->plan, slice_points(p));
+    ctx->plan_warm_blocks = 0;
+    for (const BlockDesc& d : ctx->plan.blocks) ctx->plan_warm_blocks += d.m <= kWarmMaxPoints ? 1 : 0;
     if (ctx->plan.blocks.size() >= (size_t(1) << 31)) return fail(DLS_EINVAL, "too many blocks");
     const Plan& pl = ctx->plan;
     HIP_TRY(ctx->desc.ensure(pl.blocks.size() * sizeof(BlockDesc)));
@@ -457,7 +460,10 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
                       ctx->gram.as<double>(), s));
   HIP_TRY(hipEventRecord(ctx->evs[0], s));
   const bool learned = (p.flags & DLS_LEARNED) != 0;
-  if (learned) {
+  // the warm start applies to blocks of at most kWarmMaxPoints points; a plan
+  // without any takes the plain eigensolve directly
+  const bool warm_any = ctx->plan_warm_blocks > 0;
+  if (learned && warm_any) {
     if (dls_status st = learned_eigen(ctx, d_field, p, dims, s)) return st;
   } else {
     HIP_TRY(launch_eigen(wp, ctx->gram.as<double>(), ctx->item_start.as<int32_t>(), ctx->desc.as<BlockDesc>(),
@@ -512,7 +518,7 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
     ctx->nesc = int64_t(hc[0]);
     ctx->nraw = int64_t(hc[1]);
     ctx->nwarm_accept = learned ? int64_t(hc[2]) : 0;
-    ctx->nwarm_reject = learned ? int64_t(hc[3]) : 0;
+    ctx->nwarm_reject = learned ? (warm_any ? int64_t(hc[3]) : nb) : 0;
     if (hov == 0 && hc[0] <= ctx->esc_cap) return finish_encode(ctx);
     // did not fit: grow with headroom for later calls, then the host-driven
     // encode below rewrites every output
@@ -559,7 +565,7 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
     ctx->nesc = int64_t(hc[0]);
     ctx->nraw = int64_t(hc[1]);
     ctx->nwarm_accept = learned ? int64_t(hc[2]) : 0;
-    ctx->nwarm_reject = learned ? int64_t(hc[3]) : 0;
+    ctx->nwarm_reject = learned ? (warm_any ? int64_t(hc[3]) : nb) : 0;
     if (hc[0] <= ctx->esc_cap) break;
     // more escapes than room: grow and run the encode kernel again (it rewrites
     // every output, so the result is identical apart from the escape list)

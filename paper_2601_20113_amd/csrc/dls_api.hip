@@ -245,6 +245,9 @@ struct dls_ctx {
   bool plan_valid = false;
   Plan plan;
   int64_t plan_warm_blocks = 0;  // blocks small enough for the warm start
+  bool split_valid = false;       // large / small slice lists of the plan
+  int64_t split_nlarge = 0, split_nsmall = 0;
+  DevBuf split_lists;
   DevBuf desc, items, item_start, code_off, gram, rank, lam, basis;
   DevBuf qv_size, qa_size, qv_off, qa_off, scan_tmp, qv, qa, codes, coef;
   DevBuf esc_key, esc_val, counters, vconst, eps_v, cls_lists;
@@ -387,6 +390,7 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
       ctx->plan.bits.assign(p.nvars, {});
     }
     build_blocks(p, ctx->plan, slice_points(p));
+    ctx->split_valid = false;
     ctx->plan_warm_blocks = 0;
     for (const BlockDesc& d : ctx->plan.blocks) ctx->plan_warm_blocks += d.m <= kWarmMaxPoints ? 1 : 0;
     if (ctx->plan.blocks.size() >= (size_t(1) << 31)) return fail(DLS_EINVAL, "too many blocks");
@@ -439,7 +443,7 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
   HIP_TRY(ctx->scan_tmp.ensure(size_t(4 * (nb / 1024 + 4)) * sizeof(int64_t)));
   HIP_TRY(ctx->codes.ensure(size_t(pl.codes_bytes)));
   HIP_TRY(ctx->counters.ensure(kCounterBytes));
-  HIP_TRY(ctx->cls_lists.ensure(size_t(ni) * kRankClasses * sizeof(int32_t)));
+  HIP_TRY(ctx->cls_lists.ensure(size_t(ni) * kEncodeClasses * sizeof(int32_t)));
   if (ctx->esc_cap == 0) {
     ctx->esc_cap = std::max<uint64_t>(uint64_t(1) << 20, uint64_t(p.values() / 256));
     HIP_TRY(ctx->esc_key.ensure(ctx->esc_cap * 8));
@@ -456,8 +460,33 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
   const Dims dims{p.nx, p.ny, p.nz, p.nt};
   unsigned long long* cnt = ctx->counters.as<unsigned long long>();
   HIP_TRY(hipEventRecord(ctx->ev0, s));
-  HIP_TRY(launch_gram(wp, p.dtype, p.precision == DLS_PREC_BF16, d_field, dims, ctx->desc.as<BlockDesc>(), ctx->items.as<Item>(), ni,
-                      ctx->gram.as<double>(), s));
+  // batched: slices of at most kSmallSlice points share workgroups (the split
+  // depends on the plan only and is uploaded once per plan)
+  const bool batched = (p.flags & DLS_PERSISTENT) != 0;
+  if (batched && !ctx->split_valid) {
+    std::vector<int32_t> lists[2];
+    for (int64_t i = 0; i < ni; ++i) lists[pl.items[i].np <= kSmallSlice ? 1 : 0].push_back(int32_t(i));
+    ctx->split_nlarge = int64_t(lists[0].size());
+    ctx->split_nsmall = int64_t(lists[1].size());
+    HIP_TRY(ctx->split_lists.ensure(size_t(ni) * sizeof(int32_t)));
+    HIP_TRY(hipStreamSynchronize(s));  // the pinned staging buffer is reused below
+    if (ctx->pinned_bytes < size_t(ni) * sizeof(int32_t)) {
+      if (ctx->pinned) HIP_TRY(hipHostFree(ctx->pinned));
+      ctx->pinned = nullptr;
+      ctx->pinned_bytes = 0;
+      HIP_TRY(hipHostMalloc(&ctx->pinned, size_t(ni) * sizeof(int32_t), hipHostMallocDefault));
+      ctx->pinned_bytes = size_t(ni) * sizeof(int32_t);
+    }
+    int32_t* st = static_cast<int32_t*>(ctx->pinned);
+    std::copy(lists[0].begin(), lists[0].end(), st);
+    std::copy(lists[1].begin(), lists[1].end(), st + lists[0].size());
+    HIP_TRY(hipMemcpyAsync(ctx->split_lists.p, st, size_t(ni) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    ctx->split_valid = true;
+  }
+  const GramSplit split{ctx->split_lists.as<int32_t>(), ctx->split_nlarge,
+                        ctx->split_lists.as<int32_t>() + ctx->split_nlarge, ctx->split_nsmall};
+  HIP_TRY(launch_gram(wp, p.dtype, p.precision == DLS_PREC_BF16, d_field, dims, ctx->desc.as<BlockDesc>(),
+                      ctx->items.as<Item>(), ni, batched ? &split : nullptr, ctx->gram.as<double>(), s));
   HIP_TRY(hipEventRecord(ctx->evs[0], s));
   const bool learned = (p.flags & DLS_LEARNED) != 0;
   // the warm start applies to blocks of at most kWarmMaxPoints points; a plan
@@ -475,7 +504,8 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
   HIP_TRY(launch_scan(ctx->qv_size.as<int64_t>(), nb, ctx->qv_off.as<int64_t>(), ctx->scan_tmp.as<int64_t>(), s));
   HIP_TRY(launch_scan(ctx->qa_size.as<int64_t>(), nb, ctx->qa_off.as<int64_t>(), ctx->scan_tmp.as<int64_t>(), s));
   unsigned int* cls_count = reinterpret_cast<unsigned int*>(cnt + 4);
-  HIP_TRY(launch_classify(ctx->items.as<Item>(), ni, ctx->rank.as<uint8_t>(), cls_count,
+  HIP_TRY(launch_classify(ctx->items.as<Item>(), ni, ctx->rank.as<uint8_t>(),
+                          batched ? encode_small_limit(wp, p.dtype) : 0, cls_count,
                           ctx->cls_lists.as<int32_t>(), s));
   HIP_TRY(hipEventRecord(ctx->evs[2], s));
   unsigned int* overflow = reinterpret_cast<unsigned int*>(reinterpret_cast<uint8_t*>(cnt) + kOverflowAt);
@@ -494,7 +524,7 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
                           ctx->qa_size.as<int64_t>(), nb, totals, s));
     EscOut esc{cnt, ctx->esc_key.as<uint64_t>(), ctx->esc_val.as<uint64_t>(), ctx->esc_cap};
     HIP_TRY(hipEventRecord(ctx->evs[3], s));
-    for (int c = 0; c < kRankClasses; ++c) {
+    for (int c = 0; c < kEncodeClasses; ++c) {
       const EncodeWork work{cls_count + c, ni, int64_t(ctx->qv.n), int64_t(ctx->qa.n), overflow};
       HIP_TRY(launch_encode(wp, p.dtype, c, d_field, dims, ctx->desc.as<BlockDesc>(), ctx->items.as<Item>(),
                             ctx->cls_lists.as<int32_t>() + int64_t(c) * ni, work, ctx->rank.as<uint8_t>(),
@@ -532,7 +562,7 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
     }
     HIP_TRY(launch_zero(cnt, sizeof(unsigned long long), s));
   }
-  unsigned int hcls[kRankClasses];
+  unsigned int hcls[kEncodeClasses];
   HIP_TRY(hipMemcpyAsync(hcls, cls_count, sizeof(hcls), hipMemcpyDeviceToHost, s));
   int64_t tail[4];
   HIP_TRY(hipMemcpyAsync(&tail[0], ctx->qv_off.as<int64_t>() + nb - 1, 8, hipMemcpyDeviceToHost, s));
@@ -549,7 +579,7 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
   for (int attempt = 0; attempt < 2; ++attempt) {
     EscOut esc{cnt, ctx->esc_key.as<uint64_t>(), ctx->esc_val.as<uint64_t>(), ctx->esc_cap};
     HIP_TRY(hipEventRecord(ctx->evs[3], s));
-    for (int c = 0; c < kRankClasses; ++c)
+    for (int c = 0; c < kEncodeClasses; ++c)
       HIP_TRY(launch_encode(wp, p.dtype, c, d_field, dims, ctx->desc.as<BlockDesc>(), ctx->items.as<Item>(),
                             ctx->cls_lists.as<int32_t>() + int64_t(c) * ni,
                             EncodeWork{nullptr, int64_t(hcls[c]), int64_t(ctx->qv.n), int64_t(ctx->qa.n), overflow},

@@ -38,21 +38,33 @@ struct EncodeWork {
 };
 
 // Layout of the per-encode counter block: four u64 (escapes, raw blocks,
-// warm starts accepted, rejected), kRankClasses u32 class counts, the u32
+// warm starts accepted, rejected), kEncodeClasses u32 class counts, the u32
 // overflow flag of a device-driven encode, and the two i64 payload totals
 // (qV bytes, qA bytes).
 constexpr int kRankClasses = 6;  // r <= 1, 2, 4, 8, 16, 32
-constexpr size_t kOverflowAt = 4 * 8 + kRankClasses * 4;
-constexpr size_t kTotalsAt = 64;
+constexpr int kEncodeClasses = 2 * kRankClasses;  // then the same for small slices
+constexpr size_t kOverflowAt = 4 * 8 + kEncodeClasses * 4;
+constexpr size_t kTotalsAt = 88;
 constexpr size_t kCounterBytes = kTotalsAt + 16;
+// largest slice (points) the small-slice encode takes: one wavefront x PPT
+int encode_small_limit(int wp, int dtype);
 
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // totals[0] = qv_off[n-1] + qv_size[n-1], totals[1] likewise for qA
 hipError_t launch_totals(const int64_t* qv_off, const int64_t* qv_size, const int64_t* qa_off,
                          const int64_t* qa_size, int64_t n, int64_t* totals, hipStream_t s);
 
+// Slices of at most kSmallSlice points may share workgroups (one wave each)
+// when the plan is split into these two lists of slice indices.
+constexpr int kSmallSlice = 256;
+struct GramSplit {
+  const int32_t* large;
+  int64_t nlarge;
+  const int32_t* small;
+  int64_t nsmall;
+};
 hipError_t launch_gram(int wp, int dtype, bool bf16, const void* F, const Dims& dims, const BlockDesc* desc,
-                       const Item* items, int64_t nitems, double* gpart, hipStream_t s);
+                       const Item* items, int64_t nitems, const GramSplit* split, double* gpart, hipStream_t s);
 // `only` (may be NULL): solve only the blocks b with only[b] != 0
 hipError_t launch_eigen(int wp, const double* gpart, const int32_t* item_start, const BlockDesc* desc,
                         int64_t nblocks, const double* eps_v, int r_max, uint8_t* rank, double* lam,
@@ -96,8 +108,8 @@ hipError_t launch_warmstart(const double* gpart, const int32_t* item_start, cons
 hipError_t launch_scan(const int64_t* in, int64_t n, int64_t* out, int64_t* tmp, hipStream_t s);
 hipError_t launch_range(int dtype, const void* F, int nvars, int64_t n_per_var, double* part, int nparts,
                         double* out, hipStream_t s);
-hipError_t launch_classify(const Item* items, int64_t nitems, const uint8_t* rank, unsigned int* counts,
-                           int32_t* lists, hipStream_t s);
+hipError_t launch_classify(const Item* items, int64_t nitems, const uint8_t* rank, int small_limit,
+                           unsigned int* counts, int32_t* lists, hipStream_t s);
 hipError_t launch_encode(int wp, int dtype, int cls, const void* F, const Dims& dims, const BlockDesc* desc,
                          const Item* items, const int32_t* list, const EncodeWork& work, const uint8_t* rank,
                          const double* basis, const int64_t* qv_off, const int64_t* qa_off,

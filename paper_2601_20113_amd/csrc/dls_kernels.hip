@@ -90,11 +90,12 @@ __device__ __forceinline__ void load_chunk(const T* __restrict__ row, const Item
 // ---------------------------------------------------------------------------
 // Gram: one workgroup (4 waves) per item; output gpart[item][WP][WP] (FP64).
 // ---------------------------------------------------------------------------
-// bfloat16 of x, round to nearest even (normal range; NaN and infinity keep
-// their class, which the eigensolve's finiteness check needs)
-__device__ __forceinline__ short bf16_rne(float x) {
-  const uint32_t u = __float_as_uint(x);
-  return short(uint16_t((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16));
+// four bfloat16 values, each rounded to nearest even (v_cvt_pk_bf16_f32;
+// infinity stays infinity, so the eigensolve's finiteness check still sees it)
+__device__ __forceinline__ bf16x4 to_bf16x4(const float* v) {
+  typedef __bf16 bfv4 __attribute__((ext_vector_type(4)));
+  const bfv4 r = {(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
+  return __builtin_bit_cast(bf16x4, r);
 }
 
 // BF: bfloat16 operands (v_mfma_f32_16x16x16bf16_1k, one instruction per 16
@@ -105,9 +106,15 @@ template <int WP, typename T, bool BF>
 __global__ __launch_bounds__(256) void k_gram(const T* __restrict__ F, Dims dims,
                                               const BlockDesc* __restrict__ desc,
                                               const Item* __restrict__ items,
+                                              const int32_t* __restrict__ list,
                                               double* __restrict__ gpart) {
   constexpr int NT = (WP == 16) ? 1 : 3;  // 16x16 tiles: 00 (and 01, 11 when WP = 32)
-  const Item it = items[blockIdx.x];
+  constexpr int LDR = 68;                 // staged row: 64 points + 4 floats of padding
+  constexpr size_t kStage = size_t(4) * WP * LDR * sizeof(float);
+  constexpr size_t kRed = size_t(4) * NT * 4 * 64 * sizeof(double);
+  __shared__ __align__(16) char smem[kStage > kRed ? kStage : kRed];
+  const int64_t item = list ? int64_t(list[blockIdx.x]) : int64_t(blockIdx.x);
+  const Item it = items[item];
   const BlockDesc d = desc[it.block];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tl = lane & 15, q = lane >> 4;
@@ -122,21 +129,181 @@ __global__ __launch_bounds__(256) void k_gram(const T* __restrict__ F, Dims dims
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[a][v] = 0.0;
 
-  for (int c = wave; c * 64 < it.np; c += 4) {
-    float v0[16], v1[16];
-    load_chunk<T>(row0, it, d, c, q, dims.nx, nxy, v0);
-    if (WP == 32) load_chunk<T>(row1, it, d, c, q, dims.nx, nxy, v1);
+  // G += X X^T of one 64-point chunk held as the MFMA operands v0 (rows
+  // 0..15) and v1 (rows 16..31): lane (t, q) holds points 16 j + 4 q + e
+  auto mfma_chunk = [&](const float* v0, const float* v1) {
     f32x4 a00 = {0.f, 0.f, 0.f, 0.f}, a01 = a00, a11 = a00;
     if constexpr (BF) {
       // MFMA j takes points 16 j + 4 q + e (e < 4) as its k index 4 q + e
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        bf16x4 b0, b1;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          b0[e] = bf16_rne(v0[4 * j + e]);
-          if (WP == 32) b1[e] = bf16_rne(v1[4 * j + e]);
+        const bf16x4 b0 = to_bf16x4(v0 + 4 * j);
+        bf16x4 b1 = b0;
+        if (WP == 32) b1 = to_bf16x4(v1 + 4 * j);
+        a00 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b0, b0, a00, 0, 0, 0);
+        if (WP == 32) {
+          a01 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b0, b1, a01, 0, 0, 0);
+          a11 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b1, b1, a11, 0, 0, 0);
         }
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        a00 = __builtin_amdgcn_mfma_f32_16x16x4f32(v0[s], v0[s], a00, 0, 0, 0);
+        if (WP == 32) {
+          a01 = __builtin_amdgcn_mfma_f32_16x16x4f32(v0[s], v1[s], a01, 0, 0, 0);
+          a11 = __builtin_amdgcn_mfma_f32_16x16x4f32(v1[s], v1[s], a11, 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      acc[0][v] += double(a00[v]);
+      if (WP == 32) {
+        acc[1][v] += double(a01[v]);
+        acc[2][v] += double(a11[v]);
+      }
+    }
+  };
+
+  // the wave's chunks c = wave, wave + 4, ... are taken CPW at a time, with
+  // every load of the group issued before the first MFMA
+  constexpr int CPW = (WP == 16) ? 4 : 2;
+  bool staged = false;
+  if constexpr (sizeof(T) == 4) staged = d.vec != 0;
+  if (staged) {
+    // FP32 rows of 4-aligned points: each load instruction covers 4 time rows
+    // x 64 consecutive chunk points (full cache lines); the chunk goes through
+    // LDS into the MFMA operand layout
+    float* stage = reinterpret_cast<float*>(smem) + wave * WP * LDR;
+    const int lr = lane >> 4, lp = 4 * (lane & 15);
+    const int px = d.px(), py = d.py();
+    for (int c0 = wave; c0 * 64 < it.np; c0 += 4 * CPW) {
+      float4 raw[CPW][WP / 4];
+#pragma unroll
+      for (int u = 0; u < CPW; ++u) {
+        const int ps = (c0 + 4 * u) * 64 + lp;
+        const bool okp = ps < it.np;
+        const int64_t off = point_off(it.p0 + (okp ? ps : 0), px, py, dims.nx, nxy);
+#pragma unroll
+        for (int i = 0; i < WP / 4; ++i) {
+          const int t = 4 * i + lr;
+          raw[u][i] = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (okp && t < W)
+            raw[u][i] = *reinterpret_cast<const float4*>(
+                reinterpret_cast<const float*>(F) + fidx(dims, d.var, d.t0 + t, d.z0, d.y0, d.x0) + off);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < CPW; ++u) {
+        if ((c0 + 4 * u) * 64 >= it.np) continue;
+#pragma unroll
+        for (int i = 0; i < WP / 4; ++i)
+          *reinterpret_cast<float4*>(stage + (4 * i + lr) * LDR + lp) = raw[u][i];
+        wave_sync();
+        float v0[16], v1[16];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float4 a = *reinterpret_cast<const float4*>(stage + tl * LDR + 16 * j + 4 * q);
+          v0[4 * j] = a.x; v0[4 * j + 1] = a.y; v0[4 * j + 2] = a.z; v0[4 * j + 3] = a.w;
+          if (WP == 32) {
+            const float4 b = *reinterpret_cast<const float4*>(stage + (16 + tl) * LDR + 16 * j + 4 * q);
+            v1[4 * j] = b.x; v1[4 * j + 1] = b.y; v1[4 * j + 2] = b.z; v1[4 * j + 3] = b.w;
+          }
+        }
+        wave_sync();
+        mfma_chunk(v0, v1);
+      }
+    }
+  } else {
+    for (int c0 = wave; c0 * 64 < it.np; c0 += 4 * CPW) {
+      float vv0[CPW][16], vv1[CPW][16];
+#pragma unroll
+      for (int u = 0; u < CPW; ++u) {
+        load_chunk<T>(row0, it, d, c0 + 4 * u, q, dims.nx, nxy, vv0[u]);
+        if (WP == 32) load_chunk<T>(row1, it, d, c0 + 4 * u, q, dims.nx, nxy, vv1[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < CPW; ++u) {
+        if ((c0 + 4 * u) * 64 >= it.np) continue;
+        mfma_chunk(vv0[u], vv1[u]);
+      }
+    }
+  }
+
+  __syncthreads();  // every wave is done with its staging area before it becomes `red`
+  double (*red)[NT * 4][64] = reinterpret_cast<double (*)[NT * 4][64]>(smem);
+#pragma unroll
+  for (int a = 0; a < NT; ++a)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[wave][a * 4 + v][lane] = acc[a][v];
+  __syncthreads();
+  if (wave != 0) return;
+  double* out = gpart + item * WP * WP;
+#pragma unroll
+  for (int a = 0; a < NT; ++a)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int s = a * 4 + v;
+      double g = ((red[0][s][lane] + red[1][s][lane]) + red[2][s][lane]) + red[3][s][lane];
+      // MFMA 16x16 output: lane l, register v holds row 4 (l / 16) + v, column l % 16
+      const int i = 4 * q + v, j = tl;
+      if (a == 0) {
+        out[i * WP + j] = g;
+      } else if (a == 1) {
+        out[i * WP + 16 + j] = g;
+        out[(16 + j) * WP + i] = g;
+      } else {
+        out[(16 + i) * WP + 16 + j] = g;
+      }
+    }
+}
+
+// Gram of small slices (<= 256 points): one wavefront per slice, four
+// slices per workgroup, no cross-wave reduction.  The chunk order and the
+// FP64 flush per chunk are those of k_gram's wave 0 over the same slice, so
+// the partial Gram is bitwise the same.
+template <int WP, typename T, bool BF>
+__global__ __launch_bounds__(256) void k_gram_wave(const T* __restrict__ F, Dims dims,
+                                                   const BlockDesc* __restrict__ desc,
+                                                   const Item* __restrict__ items,
+                                                   const int32_t* __restrict__ list, int64_t nlist,
+                                                   double* __restrict__ gpart) {
+  constexpr int NT = (WP == 16) ? 1 : 3;
+  const int lane = threadIdx.x & 63;
+  const int64_t li = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (li >= nlist) return;
+  const int64_t item = list[li];
+  const Item it = items[item];
+  const BlockDesc d = desc[it.block];
+  const int tl = lane & 15, q = lane >> 4;
+  const int W = d.w();
+  const int64_t nxy = dims.nx * dims.ny;
+  const T* row0 = (tl < W) ? F + fidx(dims, d.var, d.t0 + tl, d.z0, d.y0, d.x0) : nullptr;
+  const T* row1 = (WP == 32 && tl + 16 < W) ? F + fidx(dims, d.var, d.t0 + tl + 16, d.z0, d.y0, d.x0) : nullptr;
+  double acc[NT][4];
+#pragma unroll
+  for (int a = 0; a < NT; ++a)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[a][v] = 0.0;
+  float vv0[4][16], vv1[4][16];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    load_chunk<T>(row0, it, d, c, q, dims.nx, nxy, vv0[c]);
+    if (WP == 32) load_chunk<T>(row1, it, d, c, q, dims.nx, nxy, vv1[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (c * 64 >= it.np) continue;
+    const float* v0 = vv0[c];
+    const float* v1 = vv1[c];
+    f32x4 a00 = {0.f, 0.f, 0.f, 0.f}, a01 = a00, a11 = a00;
+    if constexpr (BF) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bf16x4 b0 = to_bf16x4(v0 + 4 * j);
+        bf16x4 b1 = b0;
+        if (WP == 32) b1 = to_bf16x4(v1 + 4 * j);
         a00 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b0, b0, a00, 0, 0, 0);
         if (WP == 32) {
           a01 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b0, b1, a01, 0, 0, 0);
@@ -162,22 +329,12 @@ __global__ __launch_bounds__(256) void k_gram(const T* __restrict__ F, Dims dims
       }
     }
   }
-
-  __shared__ double red[4][NT * 4][64];
-#pragma unroll
-  for (int a = 0; a < NT; ++a)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) red[wave][a * 4 + v][lane] = acc[a][v];
-  __syncthreads();
-  if (wave != 0) return;
-  double* out = gpart + int64_t(blockIdx.x) * WP * WP;
+  double* out = gpart + item * WP * WP;
 #pragma unroll
   for (int a = 0; a < NT; ++a)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int s = a * 4 + v;
-      double g = ((red[0][s][lane] + red[1][s][lane]) + red[2][s][lane]) + red[3][s][lane];
-      // MFMA 16x16 output: lane l, register v holds row 4 (l / 16) + v, column l % 16
+      const double g = acc[a][v];
       const int i = 4 * q + v, j = tl;
       if (a == 0) {
         out[i * WP + j] = g;
@@ -455,8 +612,16 @@ __device__ __forceinline__ void store_bytes(uint8_t* __restrict__ dst, const uin
 
 // RMAX is the rank class of the launch (every block in it has r <= RMAX), so
 // the per-point coefficient registers are sized for the class, not for W.
-template <int WP, typename T, int PPT, int RMAX, bool DEV>
-__device__ __forceinline__ void encode_item(int64_t li, float (&Vf)[RMAX][WP], double (&Qv)[WP][RMAX],
+// One slice, encoded by a team of TEAM threads (the workgroup, 256, or one
+// wavefront, 64, for slices of at most 64 * PPT points); `tid` < TEAM.
+template <int TEAM>
+__device__ __forceinline__ void team_sync() {
+  if constexpr (TEAM == 64) wave_sync();
+  else __syncthreads();
+}
+
+template <int WP, typename T, int PPT, int RMAX, bool DEV, int TEAM>
+__device__ __forceinline__ void encode_item(int64_t li, int tid, float (&Vf)[RMAX][WP], double (&Qv)[WP][RMAX],
                                             const T* __restrict__ F, const Dims& dims,
                                             const BlockDesc* __restrict__ desc,
                                             const Item* __restrict__ items,
@@ -480,12 +645,12 @@ __device__ __forceinline__ void encode_item(int64_t li, float (&Vf)[RMAX][WP], d
   const int64_t wm_pad = pad16(int64_t(W) * M);
   if constexpr (DEV) {  // host-driven launches size the buffers exactly
     if (qv_off[b] + 4 * pad16(int64_t(W) * r) > work.qv_cap || qa_off[b] + 4 * pad16(int64_t(M) * r) > work.qa_cap) {
-      if (threadIdx.x == 0) atomicOr(work.overflow, 1u);
+      if (tid == 0) atomicOr(work.overflow, 1u);
       return;
     }
   }
 
-  for (int idx = threadIdx.x; idx < RMAX * WP; idx += blockDim.x) {
+  for (int idx = tid; idx < RMAX * WP; idx += TEAM) {
     const int k = idx / WP, t = idx % WP;
     const double v = basis[int64_t(b) * WP * WP + idx];
     const double qv = rint(v * 65536.0);
@@ -499,9 +664,9 @@ __device__ __forceinline__ void encode_item(int64_t li, float (&Vf)[RMAX][WP], d
       for (int j = 0; j < 4; ++j) dst[j * plane] = uint8_t(z >> (8 * j));
     }
   }
-  __syncthreads();
+  team_sync<TEAM>();
 
-  const int ps0 = threadIdx.x * PPT;
+  const int ps0 = tid * PPT;
   if (ps0 >= it.np) return;
   const int valid = (it.np - ps0) < PPT ? (it.np - ps0) : PPT;
   const int p = it.p0 + ps0;
@@ -661,7 +826,9 @@ __device__ __forceinline__ void encode_item(int64_t li, float (&Vf)[RMAX][WP], d
 
 // DEV = false: host-driven, one item per workgroup; DEV = true:
 // device-driven, the grid walks the *work.dcount items of the list
-template <int WP, typename T, int PPT, int RMAX, bool DEV>
+// SMALL: four slices per workgroup, one wavefront each (slices of at most
+// 64 * PPT points); otherwise one slice per workgroup.
+template <int WP, typename T, int PPT, int RMAX, bool DEV, bool SMALL>
 __global__ __launch_bounds__(256) void k_encode(const T* __restrict__ F, Dims dims,
                                                 const BlockDesc* __restrict__ desc,
                                                 const Item* __restrict__ items,
@@ -677,18 +844,26 @@ __global__ __launch_bounds__(256) void k_encode(const T* __restrict__ F, Dims di
                                                 uint8_t* __restrict__ codes,
                                                 float* __restrict__ coef,
                                                 EscOut esc, EncodeWork work) {
-  __shared__ float Vf[RMAX][WP];    // [k][t]
-  __shared__ double Qv[WP][RMAX];   // [t][k], integer valued
+  constexpr int NTEAM = SMALL ? 4 : 1;
+  constexpr int TEAM = SMALL ? 64 : 256;
+  __shared__ float Vf[NTEAM][RMAX][WP];    // [k][t]
+  __shared__ double Qv[NTEAM][WP][RMAX];   // [t][k], integer valued
+  const int team = SMALL ? int(threadIdx.x >> 6) : 0;
+  const int tid = SMALL ? int(threadIdx.x & 63) : int(threadIdx.x);
+  const int64_t first = int64_t(blockIdx.x) * NTEAM + team;
   if constexpr (!DEV) {
-    encode_item<WP, T, PPT, RMAX, false>(blockIdx.x, Vf, Qv, F, dims, desc, items, item_list, rank, basis, qv_off,
-                                  qa_off, code_off, vc, qv_buf, qa_buf, codes, coef, esc, work);
+    if (SMALL && first >= work.count) return;  // a whole wavefront leaves together
+    encode_item<WP, T, PPT, RMAX, false, TEAM>(first, tid, Vf[team], Qv[team], F, dims, desc, items, item_list,
+                                               rank, basis, qv_off, qa_off, code_off, vc, qv_buf, qa_buf, codes,
+                                               coef, esc, work);
     return;
   }
   const int64_t nwork = int64_t(*work.dcount);
-  for (int64_t li = blockIdx.x; li < nwork; li += gridDim.x) {
-    if (li != blockIdx.x) __syncthreads();  // the previous item's LDS reads are done
-    encode_item<WP, T, PPT, RMAX, true>(li, Vf, Qv, F, dims, desc, items, item_list, rank, basis, qv_off, qa_off,
-                                  code_off, vc, qv_buf, qa_buf, codes, coef, esc, work);
+  for (int64_t li = first; li < nwork; li += int64_t(gridDim.x) * NTEAM) {
+    if (li != first) team_sync<TEAM>();  // the previous slice's LDS reads are done
+    encode_item<WP, T, PPT, RMAX, true, TEAM>(li, tid, Vf[team], Qv[team], F, dims, desc, items, item_list, rank,
+                                              basis, qv_off, qa_off, code_off, vc, qv_buf, qa_buf, codes, coef, esc,
+                                              work);
   }
 }
 
@@ -847,23 +1022,28 @@ __device__ __forceinline__ int rank_class(int r) {
   return r <= 1 ? 0 : r <= 2 ? 1 : r <= 4 ? 2 : r <= 8 ? 3 : r <= 16 ? 4 : 5;
 }
 
+// Rank class of every slice (and, when small_limit > 0, slices of at most
+// small_limit points go to the small-slice classes kRankClasses + c).
 __global__ __launch_bounds__(256) void k_classify(const Item* __restrict__ items, int64_t nitems,
-                                                  const uint8_t* __restrict__ rank,
+                                                  const uint8_t* __restrict__ rank, int small_limit,
                                                   unsigned int* __restrict__ counts,
                                                   int32_t* __restrict__ lists) {
   // counts are aggregated per workgroup in LDS: one global atomic per class
-  __shared__ unsigned int lcount[8], lbase[8];
-  if (threadIdx.x < 8) lcount[threadIdx.x] = 0;
+  constexpr int NC = 2 * kRankClasses;
+  __shared__ unsigned int lcount[NC], lbase[NC];
+  if (threadIdx.x < NC) lcount[threadIdx.x] = 0;
   __syncthreads();
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
   int c = -1;
   unsigned int lpos = 0;
   if (i < nitems) {
-    c = rank_class(rank[items[i].block]);
+    const Item it = items[i];
+    c = rank_class(rank[it.block]) + (it.np <= small_limit ? kRankClasses : 0);
     lpos = atomicAdd(&lcount[c], 1u);
   }
   __syncthreads();
-  if (threadIdx.x < 8 && lcount[threadIdx.x] > 0) lbase[threadIdx.x] = atomicAdd(counts + threadIdx.x, lcount[threadIdx.x]);
+  if (threadIdx.x < NC && lcount[threadIdx.x] > 0)
+    lbase[threadIdx.x] = atomicAdd(counts + threadIdx.x, lcount[threadIdx.x]);
   __syncthreads();
   if (c >= 0) lists[int64_t(c) * nitems + lbase[c] + lpos] = int32_t(i);
 }
@@ -899,11 +1079,22 @@ hipError_t launch_totals(const int64_t* qv_off, const int64_t* qv_size, const in
 }
 
 hipError_t launch_gram(int wp, int dtype, bool bf16, const void* F, const Dims& dims, const BlockDesc* desc,
-                       const Item* items, int64_t nitems, double* gpart, hipStream_t s) {
+                       const Item* items, int64_t nitems, const GramSplit* split, double* gpart, hipStream_t s) {
   if (nitems == 0) return hipSuccess;
-  const dim3 g{unsigned(nitems)}, bl{256};
-#define DLS_GRAM(WPV, TV, BFV) \
-  hipLaunchKernelGGL((k_gram<WPV, TV, BFV>), g, bl, 0, s, (const TV*)F, dims, desc, items, gpart)
+  const dim3 bl{256};
+  // without a split every slice takes a 4-wave workgroup; with one, the large
+  // slices do and the small ones share workgroups, one wave each
+  const int32_t* list = split ? split->large : nullptr;
+  const int64_t nlarge = split ? split->nlarge : nitems;
+  const dim3 g{unsigned(nlarge)}, gs{unsigned(split ? (split->nsmall + 3) / 4 : 0)};
+#define DLS_GRAM(WPV, TV, BFV)                                                                              \
+  do {                                                                                                      \
+    if (nlarge)                                                                                             \
+      hipLaunchKernelGGL((k_gram<WPV, TV, BFV>), g, bl, 0, s, (const TV*)F, dims, desc, items, list, gpart); \
+    if (split && split->nsmall)                                                                             \
+      hipLaunchKernelGGL((k_gram_wave<WPV, TV, BFV>), gs, bl, 0, s, (const TV*)F, dims, desc, items,        \
+                         split->small, split->nsmall, gpart);                                               \
+  } while (0)
   if (wp == 16) {
     if (dtype == 0) { if (bf16) DLS_GRAM(16, float, true); else DLS_GRAM(16, float, false); }
     else { if (bf16) DLS_GRAM(16, double, true); else DLS_GRAM(16, double, false); }
@@ -945,31 +1136,31 @@ hipError_t launch_scan(const int64_t* in, int64_t n, int64_t* out, int64_t* tmp,
   return hipGetLastError();
 }
 
-hipError_t launch_classify(const Item* items, int64_t nitems, const uint8_t* rank, unsigned int* counts,
-                           int32_t* lists, hipStream_t s) {
+hipError_t launch_classify(const Item* items, int64_t nitems, const uint8_t* rank, int small_limit,
+                           unsigned int* counts, int32_t* lists, hipStream_t s) {
   if (nitems == 0) return hipSuccess;
   const dim3 g{unsigned((nitems + 255) / 256)}, bl{256};
-  hipLaunchKernelGGL(k_classify, g, bl, 0, s, items, nitems, rank, counts, lists);
+  hipLaunchKernelGGL(k_classify, g, bl, 0, s, items, nitems, rank, small_limit, counts, lists);
   return hipGetLastError();
 }
 
-template <int WP, typename T, int PPT>
-static void encode_class(int cls, const dim3& g, hipStream_t s, const T* F, const Dims& dims,
+template <int WP, typename T, int PPT, bool SMALL>
+static void encode_class(int rc, const dim3& g, hipStream_t s, const T* F, const Dims& dims,
                          const BlockDesc* desc, const Item* items, const int32_t* list, const uint8_t* rank,
                          const double* basis, const int64_t* qv_off, const int64_t* qa_off,
                          const int64_t* code_off, const VarConst* vc, uint8_t* qv, uint8_t* qa,
                          uint8_t* codes, float* coef, EscOut esc, const EncodeWork& work) {
   const dim3 bl{256};
-#define DLS_ENC(R)                                                                                         \
-  do {                                                                                                     \
-    if (work.dcount)                                                                                       \
-      hipLaunchKernelGGL((k_encode<WP, T, PPT, R, true>), g, bl, 0, s, F, dims, desc, items, list, rank,  \
-                         basis, qv_off, qa_off, code_off, vc, qv, qa, codes, coef, esc, work);             \
-    else                                                                                                   \
-      hipLaunchKernelGGL((k_encode<WP, T, PPT, R, false>), g, bl, 0, s, F, dims, desc, items, list, rank, \
-                         basis, qv_off, qa_off, code_off, vc, qv, qa, codes, coef, esc, work);             \
+#define DLS_ENC(R)                                                                                          \
+  do {                                                                                                      \
+    if (work.dcount)                                                                                        \
+      hipLaunchKernelGGL((k_encode<WP, T, PPT, R, true, SMALL>), g, bl, 0, s, F, dims, desc, items, list,  \
+                         rank, basis, qv_off, qa_off, code_off, vc, qv, qa, codes, coef, esc, work);        \
+    else                                                                                                    \
+      hipLaunchKernelGGL((k_encode<WP, T, PPT, R, false, SMALL>), g, bl, 0, s, F, dims, desc, items, list, \
+                         rank, basis, qv_off, qa_off, code_off, vc, qv, qa, codes, coef, esc, work);        \
   } while (0)
-  switch (cls) {
+  switch (rc) {
     case 0: DLS_ENC(1); break;
     case 1: DLS_ENC(2); break;
     case 2: DLS_ENC(4); break;
@@ -982,19 +1173,32 @@ static void encode_class(int cls, const dim3& g, hipStream_t s, const T* F, cons
 #undef DLS_ENC
 }
 
+int encode_small_limit(int wp, int dtype) { return 64 * ((wp == 16 && dtype == 0) ? 4 : 2); }
+
 hipError_t launch_encode(int wp, int dtype, int cls, const void* F, const Dims& dims, const BlockDesc* desc,
                          const Item* items, const int32_t* list, const EncodeWork& work, const uint8_t* rank,
                          const double* basis, const int64_t* qv_off, const int64_t* qa_off,
                          const int64_t* code_off, const VarConst* vc, uint8_t* qv, uint8_t* qa,
                          uint8_t* codes, float* coef, EscOut esc, hipStream_t s) {
-  // host-driven: one workgroup per item; device-driven: a grid that fills
-  // the chip a few times over and walks the list
-  const int64_t grid = work.dcount ? std::min<int64_t>(work.count, 4096) : work.count;
+  // classes kRankClasses.. hold small slices: four per workgroup.  Host-driven:
+  // one team per slice; device-driven: a grid that fills the chip a few times
+  // over and walks the list
+  const bool small = cls >= kRankClasses;
+  const int rc = cls % kRankClasses;
+  const int64_t per = small ? 4 : 1;
+  const int64_t need = (work.count + per - 1) / per;
+  const int64_t grid = work.dcount ? std::min<int64_t>(need, 4096) : need;
   if (grid == 0) return hipSuccess;
   const dim3 g{unsigned(grid)};
-#define DLS_ENC_CLASS(WPV, TV, PPTV) \
-  encode_class<WPV, TV, PPTV>(cls, g, s, (const TV*)F, dims, desc, items, list, rank, basis, qv_off, qa_off, \
-                              code_off, vc, qv, qa, codes, coef, esc, work)
+#define DLS_ENC_CLASS(WPV, TV, PPTV)                                                                          \
+  do {                                                                                                        \
+    if (small)                                                                                                \
+      encode_class<WPV, TV, PPTV, true>(rc, g, s, (const TV*)F, dims, desc, items, list, rank, basis, qv_off, \
+                                        qa_off, code_off, vc, qv, qa, codes, coef, esc, work);                \
+    else                                                                                                      \
+      encode_class<WPV, TV, PPTV, false>(rc, g, s, (const TV*)F, dims, desc, items, list, rank, basis,        \
+                                         qv_off, qa_off, code_off, vc, qv, qa, codes, coef, esc, work);       \
+  } while (0)
   if (wp == 16 && dtype == 0) DLS_ENC_CLASS(16, float, 4);
   else if (wp == 16) DLS_ENC_CLASS(16, double, 2);
   else if (dtype == 0) DLS_ENC_CLASS(32, float, 2);

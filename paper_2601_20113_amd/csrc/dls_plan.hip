@@ -294,7 +294,8 @@ hipError_t adaptive_plan(const Problem& p, const void* F, hipStream_t s, PlanScr
     const auto t0 = now();
     const uint8_t* f0 = static_cast<const uint8_t*>(F) + size_t(v) * size_t(p.nt) * size_t(n) * es;
     const dim3 bl{256};
-    const unsigned nrowblk = 8 * unsigned(std::min<int64_t>(1024, (p.ny * p.nz + 7) / 8));  // a multiple of 8
+    // one row per workgroup up to 2^19 rows (latency-bound rows in flight), a multiple of 8
+    const unsigned nrowblk = 8 * unsigned(std::min<int64_t>(65536, (p.ny * p.nz + 7) / 8));
     if (p.dtype == 0)
       hipLaunchKernelGGL(k_gradient<float>, dim3{nrowblk}, bl, 0, s, (const float*)f0, p.nx, p.ny, p.nz, g);
     else

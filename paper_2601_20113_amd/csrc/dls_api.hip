@@ -262,6 +262,14 @@ struct dls_ctx {
   int64_t nwarm_accept = 0, nwarm_reject = 0;
   void* pinned = nullptr;      // host staging for plan uploads
   size_t pinned_bytes = 0;
+  uint8_t* hcnt = nullptr;     // pinned host copy of the counter block
+  hipError_t host_counters() {
+    if (hcnt) return hipSuccess;
+    void* q = nullptr;
+    hipError_t e = hipHostMalloc(&q, kCounterBytes, hipHostMallocDefault);
+    if (e == hipSuccess) hcnt = static_cast<uint8_t*>(q);
+    return e;
+  }
   uint64_t esc_cap = 0;
   // results of the last dls_encode
   bool have_result = false;
@@ -275,6 +283,7 @@ struct dls_ctx {
       if (e) (void)hipEventDestroy(e);
     plan_scratch_delete(plan_scratch);
     if (pinned) (void)hipHostFree(pinned);
+    if (hcnt) (void)hipHostFree(hcnt);
   }
 };
 
@@ -534,9 +543,10 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
                             ctx->keep_coef ? ctx->coef.as<float>() : nullptr, esc, s));
     }
     HIP_TRY(hipEventRecord(ctx->ev1, s));
-    uint8_t hbuf[kCounterBytes];
-    HIP_TRY(hipMemcpyAsync(hbuf, cnt, kCounterBytes, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx->host_counters());
+    HIP_TRY(hipMemcpyAsync(ctx->hcnt, cnt, kCounterBytes, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    const uint8_t* hbuf = ctx->hcnt;
     unsigned long long hc[4];
     unsigned int hov;
     int64_t ht[2];
@@ -562,16 +572,18 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
     }
     HIP_TRY(launch_zero(cnt, sizeof(unsigned long long), s));
   }
-  unsigned int hcls[kEncodeClasses];
-  HIP_TRY(hipMemcpyAsync(hcls, cls_count, sizeof(hcls), hipMemcpyDeviceToHost, s));
-  int64_t tail[4];
-  HIP_TRY(hipMemcpyAsync(&tail[0], ctx->qv_off.as<int64_t>() + nb - 1, 8, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(&tail[1], ctx->qv_size.as<int64_t>() + nb - 1, 8, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(&tail[2], ctx->qa_off.as<int64_t>() + nb - 1, 8, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(&tail[3], ctx->qa_size.as<int64_t>() + nb - 1, 8, hipMemcpyDeviceToHost, s));
+  // class counts and payload totals in one readback into pinned memory
+  HIP_TRY(launch_totals(ctx->qv_off.as<int64_t>(), ctx->qv_size.as<int64_t>(), ctx->qa_off.as<int64_t>(),
+                        ctx->qa_size.as<int64_t>(), nb, totals, s));
+  HIP_TRY(ctx->host_counters());
+  HIP_TRY(hipMemcpyAsync(ctx->hcnt, cnt, kCounterBytes, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  ctx->qv_bytes = tail[0] + tail[1];
-  ctx->qa_bytes = tail[2] + tail[3];
+  unsigned int hcls[kEncodeClasses];
+  int64_t htot[2];
+  std::memcpy(hcls, ctx->hcnt + 4 * sizeof(unsigned long long), sizeof(hcls));
+  std::memcpy(htot, ctx->hcnt + kTotalsAt, sizeof(htot));
+  ctx->qv_bytes = htot[0];
+  ctx->qa_bytes = htot[1];
   HIP_TRY(ctx->qv.ensure(size_t(ctx->qv_bytes)));
   HIP_TRY(ctx->qa.ensure(size_t(ctx->qa_bytes)));
   if (ctx->keep_coef) HIP_TRY(ctx->coef.ensure(size_t(ctx->qa_bytes)));
@@ -590,8 +602,9 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
                             ctx->keep_coef ? ctx->coef.as<float>() : nullptr, esc, s));
     HIP_TRY(hipEventRecord(ctx->ev1, s));
     unsigned long long hc[4];
-    HIP_TRY(hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(ctx->hcnt, cnt, sizeof(hc), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    std::memcpy(hc, ctx->hcnt, sizeof(hc));
     ctx->nesc = int64_t(hc[0]);
     ctx->nraw = int64_t(hc[1]);
     ctx->nwarm_accept = learned ? int64_t(hc[2]) : 0;

@@ -13,6 +13,8 @@
 // bits and the leaves in (z0, y0, x0) order.
 #include <hip/hip_runtime.h>
 
+#include <array>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -70,6 +72,69 @@ __global__ __launch_bounds__(256) void k_gradient(const T* __restrict__ f0, int6
   for (int64_t row = lo + blockIdx.x / 8; row < hi; row += step) {
     const int64_t y = row % ny, z = row / ny;
     for (int64_t x = threadIdx.x; x < nx; x += 256) g[row * nx + x] = grad_mag(f0, nx, ny, nz, x, y, z);
+  }
+}
+
+// The same gradient for FP32 rows of a multiple of 4 points: each thread
+// takes 4 consecutive points (16-byte loads of the row and of its four
+// neighbour rows, two scalar loads for the x neighbours), one row per 128
+// threads, two rows per workgroup.  Same arithmetic as grad_mag, so the
+// values are bitwise equal.
+__global__ __launch_bounds__(256) void k_gradient4(const float* __restrict__ f0, int64_t nx, int64_t ny, int64_t nz,
+                                                   double* __restrict__ g) {
+  const int64_t rows = ny * nz;
+  const int64_t nq = nx / 4;  // float4 per row
+  const int64_t row = int64_t(blockIdx.x) * 2 + (threadIdx.x >> 7);
+  if (row >= rows) return;
+  const int64_t y = row % ny, z = row / ny;
+  const float* rp = f0 + row * nx;
+  for (int64_t qi = threadIdx.x & 127; qi < nq; qi += 128) {
+    const int64_t x = 4 * qi;
+    const float4 c = *reinterpret_cast<const float4*>(rp + x);
+    double v[4] = {c.x, c.y, c.z, c.w};
+    double dx[4] = {0.0, 0.0, 0.0, 0.0}, dy[4] = {0.0, 0.0, 0.0, 0.0}, dz[4] = {0.0, 0.0, 0.0, 0.0};
+    if (nx > 1) {
+      const double l = x > 0 ? double(rp[x - 1]) : 0.0;
+      const double r = x + 4 < nx ? double(rp[x + 4]) : 0.0;
+      dx[0] = x == 0 ? v[1] - v[0] : (v[1] - l) * 0.5;
+      dx[1] = (v[2] - v[0]) * 0.5;
+      dx[2] = (v[3] - v[1]) * 0.5;
+      dx[3] = x + 4 == nx ? v[3] - v[2] : (r - v[2]) * 0.5;
+    }
+    auto row4 = [&](int64_t zz, int64_t yy, double* o) {
+      const float4 a = *reinterpret_cast<const float4*>(f0 + (zz * ny + yy) * nx + x);
+      o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
+    };
+    if (ny > 1) {
+      double a[4], b[4];
+      if (y == 0) {
+        row4(z, 1, a);
+        for (int e = 0; e < 4; ++e) dy[e] = a[e] - v[e];
+      } else if (y == ny - 1) {
+        row4(z, ny - 2, b);
+        for (int e = 0; e < 4; ++e) dy[e] = v[e] - b[e];
+      } else {
+        row4(z, y + 1, a);
+        row4(z, y - 1, b);
+        for (int e = 0; e < 4; ++e) dy[e] = (a[e] - b[e]) * 0.5;
+      }
+    }
+    if (nz > 1) {
+      double a[4], b[4];
+      if (z == 0) {
+        row4(1, y, a);
+        for (int e = 0; e < 4; ++e) dz[e] = a[e] - v[e];
+      } else if (z == nz - 1) {
+        row4(nz - 2, y, b);
+        for (int e = 0; e < 4; ++e) dz[e] = v[e] - b[e];
+      } else {
+        row4(z + 1, y, a);
+        row4(z - 1, y, b);
+        for (int e = 0; e < 4; ++e) dz[e] = (a[e] - b[e]) * 0.5;
+      }
+    }
+    double* out = g + row * nx + x;
+    for (int e = 0; e < 4; ++e) out[e] = sqrt(dx[e] * dx[e] + dy[e] * dy[e] + dz[e] * dz[e]);
   }
 }
 
@@ -235,6 +300,17 @@ struct DevMem {
 
 struct PlanScratch {
   DevMem g, cand, hist, sums, cnts, count, flags;
+  // the split flags of the previous call per variable, with the leaves and
+  // bits they produced: equal flags give the same tree, so its walk is skipped
+  std::vector<std::vector<uint8_t>> prev_flags, prev_bits;
+  std::vector<std::vector<Leaf>> prev_leaves;
+  std::vector<std::array<int64_t, 5>> prev_key;  // nx, ny, nz, px, pmin
+  unsigned int* hhist = nullptr;                  // pinned host copies of the histogram / count
+  unsigned long long* hcount = nullptr;
+  ~PlanScratch() {
+    if (hhist) (void)hipHostFree(hhist);
+    if (hcount) (void)hipHostFree(hcount);
+  }
 };
 
 PlanScratch* plan_scratch_new() { return new PlanScratch(); }
@@ -296,7 +372,10 @@ hipError_t adaptive_plan(const Problem& p, const void* F, hipStream_t s, PlanScr
     const dim3 bl{256};
     // one row per workgroup up to 2^19 rows (latency-bound rows in flight), a multiple of 8
     const unsigned nrowblk = 8 * unsigned(std::min<int64_t>(65536, (p.ny * p.nz + 7) / 8));
-    if (p.dtype == 0)
+    if (p.dtype == 0 && p.nx % 4 == 0 && (reinterpret_cast<uintptr_t>(f0) & 15) == 0)
+      hipLaunchKernelGGL(k_gradient4, dim3{unsigned((p.ny * p.nz + 1) / 2)}, bl, 0, s, (const float*)f0, p.nx, p.ny,
+                         p.nz, g);
+    else if (p.dtype == 0)
       hipLaunchKernelGGL(k_gradient<float>, dim3{nrowblk}, bl, 0, s, (const float*)f0, p.nx, p.ny, p.nz, g);
     else
       hipLaunchKernelGGL(k_gradient<double>, dim3{nrowblk}, bl, 0, s, (const double*)f0, p.nx, p.ny, p.nz, g);
@@ -311,14 +390,21 @@ hipError_t adaptive_plan(const Problem& p, const void* F, hipStream_t s, PlanScr
     int64_t k = int64_t(std::floor(0.8 * double(n - 1)));
     uint64_t prefix = 0, pmask = 0;
     const unsigned nblk = unsigned(std::min<int64_t>(4096, (n + 255) / 256));
-    std::vector<unsigned int> h(2048);
+    if (S.hhist == nullptr) {
+      void* q = nullptr;
+      PLAN_TRY(hipHostMalloc(&q, 2048 * sizeof(unsigned int), hipHostMallocDefault));
+      S.hhist = static_cast<unsigned int*>(q);
+      PLAN_TRY(hipHostMalloc(&q, sizeof(unsigned long long), hipHostMallocDefault));
+      S.hcount = static_cast<unsigned long long*>(q);
+    }
+    unsigned int* h = S.hhist;
     for (int pass = 0; pass < 3; ++pass) {
       const int shift = 53 - 11 * pass;
       const uint32_t dmask = 2047u;
       PLAN_TRY(hipMemsetAsync(dhist, 0, 2048 * sizeof(unsigned int), s));
       hist_pass(prefix, pmask, shift, dmask, nblk);
       PLAN_TRY(hipGetLastError());
-      PLAN_TRY(hipMemcpyAsync(h.data(), dhist, 2048 * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+      PLAN_TRY(hipMemcpyAsync(h, dhist, 2048 * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
       PLAN_TRY(hipStreamSynchronize(s));
       uint32_t d = 0;
       for (; d <= dmask; ++d) {
@@ -336,9 +422,9 @@ hipError_t adaptive_plan(const Problem& p, const void* F, hipStream_t s, PlanScr
     hipLaunchKernelGGL(k_radix_compact, dim3{nblk}, bl, 0, s, (const double*)g, n, prefix, pmask, dcount, dcand,
                        cand_cap);
     PLAN_TRY(hipGetLastError());
-    unsigned long long ncand = 0;
-    PLAN_TRY(hipMemcpyAsync(&ncand, dcount, sizeof(ncand), hipMemcpyDeviceToHost, s));
+    PLAN_TRY(hipMemcpyAsync(S.hcount, dcount, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     PLAN_TRY(hipStreamSynchronize(s));
+    const unsigned long long ncand = *S.hcount;
     uint64_t thr_bits = 0;
     if (ncand <= cand_cap) {
       std::vector<uint64_t> cand(ncand);
@@ -358,7 +444,7 @@ hipError_t adaptive_plan(const Problem& p, const void* F, hipStream_t s, PlanScr
         PLAN_TRY(hipMemsetAsync(dhist, 0, 2048 * sizeof(unsigned int), s));
         hist_pass(prefix, pmask, shifts[pass], dmask, nblk);
         PLAN_TRY(hipGetLastError());
-        PLAN_TRY(hipMemcpyAsync(h.data(), dhist, 2048 * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+        PLAN_TRY(hipMemcpyAsync(h, dhist, 2048 * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
         PLAN_TRY(hipStreamSynchronize(s));
         uint32_t d = 0;
         for (; d <= dmask; ++d) {
@@ -401,6 +487,19 @@ hipError_t adaptive_plan(const Problem& p, const void* F, hipStream_t s, PlanScr
     PLAN_TRY(hipMemcpyAsync(hflag.data(), dflag, size_t(off[L]), hipMemcpyDeviceToHost, s));
     PLAN_TRY(hipStreamSynchronize(s));
     const auto t2 = now();
+    // the tree depends only on the flags and the grid: reuse the previous walk
+    const std::array<int64_t, 5> key{p.nx, p.ny, p.nz, int64_t(p.px), int64_t(p.pmin)};
+    if (S.prev_flags.size() < size_t(p.nvars)) {
+      S.prev_flags.resize(p.nvars);
+      S.prev_bits.resize(p.nvars);
+      S.prev_leaves.resize(p.nvars);
+      S.prev_key.resize(p.nvars, std::array<int64_t, 5>{-1, -1, -1, -1, -1});
+    }
+    if (S.prev_key[v] == key && S.prev_flags[v] == hflag) {
+      plan.leaves[v] = S.prev_leaves[v];
+      plan.bits[v] = S.prev_bits[v];
+      continue;
+    }
     // depth-first walk: roots in (z, y, x) order, children in (z, y, x) order
     std::vector<Leaf>& leaves = plan.leaves[v];
     std::vector<uint8_t>& bits = plan.bits[v];
@@ -443,6 +542,10 @@ hipError_t adaptive_plan(const Problem& p, const void* F, hipStream_t s, PlanScr
       if (a.y0 != b.y0) return a.y0 < b.y0;
       return a.x0 < b.x0;
     });
+    S.prev_key[v] = key;
+    S.prev_flags[v] = hflag;
+    S.prev_leaves[v] = leaves;
+    S.prev_bits[v] = bits;
     if (timing)
       std::fprintf(stderr, "[dls] plan var %d: percentile %.3f ms, node sums %.3f ms, tree %.3f ms, %zu leaves\n", v,
                    ms(t0, t1), ms(t1, t2), ms(t2, now()), leaves.size());

@@ -250,7 +250,7 @@ struct dls_ctx {
   DevBuf split_lists;
   DevBuf desc, items, item_start, code_off, gram, rank, lam, basis;
   DevBuf qv_size, qa_size, qv_off, qa_off, scan_tmp, qv, qa, codes, coef;
-  DevBuf esc_key, esc_val, counters, vconst, eps_v, cls_lists;
+  DevBuf esc_key, esc_val, counters, vconst, eps_v, cls_lists, reject_list;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t evs[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // gram, eigen, scan ends; encode start; plan start
   double stage_ms[5] = {0, 0, 0, 0, 0};
@@ -307,10 +307,15 @@ dls_status learned_eigen(dls_ctx* ctx, const void* d_field, const Problem& p, co
                            ctx->warm_margin, ctx->rank.as<uint8_t>(), ctx->lam.as<double>(), ctx->basis.as<double>(),
                            ctx->qv_size.as<int64_t>(), ctx->qa_size.as<int64_t>(), ctx->reject.as<uint8_t>(),
                            cnt + 2, s));
+  // the fallback Jacobi takes a compacted list of the rejected blocks, so its
+  // workgroups are full of real work
+  unsigned int* nrej = reinterpret_cast<unsigned int*>(reinterpret_cast<uint8_t*>(cnt) + kRejectCountAt);
+  HIP_TRY(ctx->reject_list.ensure(size_t(nb) * sizeof(int32_t)));
+  HIP_TRY(launch_compact_flags(ctx->reject.as<uint8_t>(), nb, ctx->reject_list.as<int32_t>(), nrej, s));
   HIP_TRY(launch_eigen(16, ctx->gram.as<double>(), ctx->item_start.as<int32_t>(), ctx->desc.as<BlockDesc>(), nb,
                        ctx->eps_v.as<double>(), p.r_max, ctx->rank.as<uint8_t>(), ctx->lam.as<double>(),
                        ctx->basis.as<double>(), ctx->qv_size.as<int64_t>(), ctx->qa_size.as<int64_t>(), cnt + 1,
-                       ctx->reject.as<uint8_t>(), s));
+                       ctx->reject_list.as<int32_t>(), nrej, s));
   return DLS_OK;
 }
 }  // namespace
@@ -507,7 +512,7 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
     HIP_TRY(launch_eigen(wp, ctx->gram.as<double>(), ctx->item_start.as<int32_t>(), ctx->desc.as<BlockDesc>(),
                          nb, ctx->eps_v.as<double>(), p.r_max, ctx->rank.as<uint8_t>(), ctx->lam.as<double>(),
                          ctx->basis.as<double>(), ctx->qv_size.as<int64_t>(), ctx->qa_size.as<int64_t>(),
-                         cnt + 1, nullptr, s));
+                         cnt + 1, nullptr, nullptr, s));
   }
   HIP_TRY(hipEventRecord(ctx->evs[1], s));
   HIP_TRY(launch_scan(ctx->qv_size.as<int64_t>(), nb, ctx->qv_off.as<int64_t>(), ctx->scan_tmp.as<int64_t>(), s));

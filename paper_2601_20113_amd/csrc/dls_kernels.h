@@ -39,11 +39,12 @@ struct EncodeWork {
 
 // Layout of the per-encode counter block: four u64 (escapes, raw blocks,
 // warm starts accepted, rejected), kEncodeClasses u32 class counts, the u32
-// overflow flag of a device-driven encode, and the two i64 payload totals
-// (qV bytes, qA bytes).
+// overflow flag of a device-driven encode, the u32 count of the fallback
+// list, and the two i64 payload totals (qV bytes, qA bytes).
 constexpr int kRankClasses = 6;  // r <= 1, 2, 4, 8, 16, 32
 constexpr int kEncodeClasses = 2 * kRankClasses;  // then the same for small slices
 constexpr size_t kOverflowAt = 4 * 8 + kEncodeClasses * 4;
+constexpr size_t kRejectCountAt = kOverflowAt + 4;  // u32: blocks the warm start left to Jacobi
 constexpr size_t kTotalsAt = 88;
 constexpr size_t kCounterBytes = kTotalsAt + 16;
 // largest slice (points) the small-slice encode takes: one wavefront x PPT
@@ -65,11 +66,14 @@ struct GramSplit {
 };
 hipError_t launch_gram(int wp, int dtype, bool bf16, const void* F, const Dims& dims, const BlockDesc* desc,
                        const Item* items, int64_t nitems, const GramSplit* split, double* gpart, hipStream_t s);
-// `only` (may be NULL): solve only the blocks b with only[b] != 0
+// list (may be NULL): solve only the *list_count blocks list[0..) (a
+// device-written list; the grid covers nblocks, the rest exits at once)
 hipError_t launch_eigen(int wp, const double* gpart, const int32_t* item_start, const BlockDesc* desc,
                         int64_t nblocks, const double* eps_v, int r_max, uint8_t* rank, double* lam,
                         double* basis, int64_t* qv_size, int64_t* qa_size, unsigned long long* nraw,
-                        const uint8_t* only, hipStream_t s);
+                        const int32_t* list, const unsigned int* list_count, hipStream_t s);
+// list of the blocks b < n with flag[b] != 0, in any order; *count is added to
+hipError_t launch_compact_flags(const uint8_t* flag, int64_t n, int32_t* list, unsigned int* count, hipStream_t s);
 // learned warm start (dls_learned.hip)
 hipError_t launch_features(int dtype, const void* F, const Dims& dims, const BlockDesc* desc, int64_t nblocks,
                            const double* eps_v, float* feat, hipStream_t s);

@@ -370,7 +370,8 @@ __global__ __launch_bounds__(256) void k_eigen(const double* __restrict__ gpart,
                                                int64_t* __restrict__ qv_size,
                                                int64_t* __restrict__ qa_size,
                                                unsigned long long* __restrict__ nraw,
-                                               const uint8_t* __restrict__ only) {
+                                               const int32_t* __restrict__ list,
+                                               const unsigned int* __restrict__ list_count) {
   constexpr int GPW = 256 / WP;
   constexpr int LD = WP + 1;
   __shared__ double sA[GPW][WP * LD];
@@ -378,9 +379,10 @@ __global__ __launch_bounds__(256) void k_eigen(const double* __restrict__ gpart,
   __shared__ double sLam[GPW][WP], sSg[GPW][WP];
   __shared__ int sPerm[GPW][WP];
   const int grp = threadIdx.x / WP, i = threadIdx.x % WP;
-  const int64_t b = int64_t(blockIdx.x) * GPW + grp;
-  if (b >= nblocks) return;
-  if (only != nullptr && only[b] == 0) return;
+  // every block, or (list != NULL) the blocks of the device-written list
+  const int64_t li = int64_t(blockIdx.x) * GPW + grp;
+  if (li >= (list ? int64_t(*list_count) : nblocks)) return;
+  const int64_t b = list ? int64_t(list[li]) : li;
   double* A = sA[grp];
   double2* CS = sCS[grp];
   const BlockDesc d = desc[b];
@@ -1065,6 +1067,25 @@ __global__ void k_totals(const int64_t* __restrict__ qv_off, const int64_t* __re
   }
 }
 
+// wave-aggregated compaction: one atomic per wavefront
+__global__ __launch_bounds__(256) void k_compact_flags(const uint8_t* __restrict__ flag, int64_t n,
+                                                       int32_t* __restrict__ list, unsigned int* __restrict__ count) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const bool on = i < n && flag[i] != 0;
+  const uint64_t m = __ballot(on);
+  const int lane = threadIdx.x & 63;
+  unsigned int base = 0;
+  if (lane == 0 && m) base = atomicAdd(count, unsigned(__popcll(m)));
+  base = __shfl(base, 0, 64);
+  if (on) list[base + __popcll(m & ((1ULL << lane) - 1ULL))] = int32_t(i);
+}
+
+hipError_t launch_compact_flags(const uint8_t* flag, int64_t n, int32_t* list, unsigned int* count, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_compact_flags, dim3{unsigned((n + 255) / 256)}, dim3{256}, 0, s, flag, n, list, count);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
   const int64_t n = int64_t(bytes / 4);  // whole words; every user passes a multiple of 4
   if (n == 0) return hipSuccess;
@@ -1109,15 +1130,15 @@ hipError_t launch_gram(int wp, int dtype, bool bf16, const void* F, const Dims& 
 hipError_t launch_eigen(int wp, const double* gpart, const int32_t* item_start, const BlockDesc* desc,
                         int64_t nblocks, const double* eps_v, int r_max, uint8_t* rank, double* lam,
                         double* basis, int64_t* qv_size, int64_t* qa_size, unsigned long long* nraw,
-                        const uint8_t* only, hipStream_t s) {
+                        const int32_t* list, const unsigned int* list_count, hipStream_t s) {
   if (nblocks == 0) return hipSuccess;
   const dim3 bl{256};
   if (wp == 16)
     hipLaunchKernelGGL(k_eigen<16>, dim3{unsigned((nblocks + 15) / 16)}, bl, 0, s, gpart, item_start, desc, nblocks,
-                       eps_v, r_max, rank, lam, basis, qv_size, qa_size, nraw, only);
+                       eps_v, r_max, rank, lam, basis, qv_size, qa_size, nraw, list, list_count);
   else
     hipLaunchKernelGGL(k_eigen<32>, dim3{unsigned((nblocks + 7) / 8)}, bl, 0, s, gpart, item_start, desc, nblocks,
-                       eps_v, r_max, rank, lam, basis, qv_size, qa_size, nraw, only);
+                       eps_v, r_max, rank, lam, basis, qv_size, qa_size, nraw, list, list_count);
   return hipGetLastError();
 }
 

@@ -102,8 +102,58 @@ __global__ __launch_bounds__(256) void k_features(const T* __restrict__ F, Dims 
     }
   };
   const bool one = M <= 64;  // one point per lane: neighbours come from other lanes, values stay in registers
+  // FP32 blocks of 65..256 points: four points per lane (p = lane + 64 r),
+  // kept in registers as loaded; neighbours come from other lanes
+  const bool regs4 = sizeof(T) == 4 && !one;
   double x1[16];
-  if (one) {
+  float xf[4][16];
+  if (regs4) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int p = lane + 64 * r;
+      const int i = p % px, rho = p / px, j = rho % py, k = rho / py;
+      const T* pt = base + int64_t(k) * nxy + int64_t(j) * dims.nx + i;
+#pragma unroll
+      for (int t = 0; t < 16; ++t) xf[r][t] = (p < M && t < W) ? float(pt[int64_t(t) * tstride]) : 0.f;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int p = lane + 64 * r;
+      const int i = p % px, j = (p / px) % py;
+      const bool hr = i + 1 < px && p < M, hd = j + 1 < py && p < M;
+      const int lr = (lane + 1) & 63, ld = (lane + px) & 63;
+      const bool rr_next = lane + 1 >= 64, rd_next = lane + px >= 64;
+      double ts = 0.0, prev = 0.0;
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        // every lane takes part in the shuffles
+        const float ar = __shfl(xf[r][t], lr, 64), ad = __shfl(xf[r][t], ld, 64);
+        const float br = r < 3 ? __shfl(xf[r < 3 ? r + 1 : r][t], lr, 64) : 0.f;
+        const float bd = r < 3 ? __shfl(xf[r < 3 ? r + 1 : r][t], ld, 64) : 0.f;
+        if (p < M && t < W) {
+          const double v = xf[r][t];
+          s1 += v;
+          s2 += v * v;
+          mn = fmin(mn, v);
+          mx = fmax(mx, v);
+          ts += v;
+          if (t > 0) {
+            const double dt = v - prev;
+            adt += fabs(dt);
+            sdt += dt;
+            sdt2 += dt * dt;
+          }
+          if (hr) adx += fabs(double(rr_next ? br : ar) - v);
+          if (hd) ady += fabs(double(rd_next ? bd : ad) - v);
+          prev = v;
+        }
+      }
+      if (p < M) {
+        tme += ts * ts;
+        sts[wv][p] = ts;
+      }
+    }
+  } else if (one) {
     const bool act = lane < M;
     if (act) {
       load_point(lane, 0, x1);
@@ -136,7 +186,17 @@ __global__ __launch_bounds__(256) void k_features(const T* __restrict__ F, Dims 
   }
   const double n = double(W) * M;
   const double mu = s1 / n;
-  if (one) {
+  if (regs4) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (lane + 64 * r < M) {
+        double x[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) x[t] = xf[r][t];
+        central(x, mu);
+      }
+    }
+  } else if (one) {
     if (lane < M) central(x1, mu);
   } else {
     for (int p = lane; p < M; p += 64) {

@@ -285,7 +285,7 @@ def main():
     inf = head["info"]
     dom = max(range(5), key=lambda i: stage[i])
     if names[dom] == "encode":
-        alg = nvals * (es + 2) + inf.qa_bytes + (inf.qv_bytes if hasattr(inf, "qv_bytes") else 0)
+        alg = nvals * (es + 1) + inf.qa_bytes + (inf.qv_bytes if hasattr(inf, "qv_bytes") else 0)
         kern = "k_encode"
     elif names[dom] == "gram":
         alg, kern = nvals * es, "k_gram"

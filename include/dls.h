@@ -117,7 +117,8 @@ typedef struct dls_encode_info {
                                pz<<16 | w<<24), var, M_b, vector flag      */
   int64_t qa_bytes, codes_bytes;
   const uint8_t* d_qa;      /* qA planes, per block at d_qa_off[b]          */
-  const uint8_t* d_codes;   /* residual code planes, per block at d_code_off */
+  const uint8_t* d_codes;   /* residual codes, one byte per value (zigzag  */
+                            /* int8, 0xFF = escape), per block at d_code_off */
   const int64_t* d_qa_off;  /* [nblocks]                                    */
   const int64_t* d_code_off;/* [nblocks]                                    */
   const float* d_coef;      /* [sum M_b r_b] FP32 coefficients A[k][p] at

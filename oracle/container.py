@@ -9,7 +9,7 @@ decodable zlib stream (deflate, level 6 -- gzip's algorithm, Sec. 2.5) per
 batch.
 
 Header (little-endian):
-    char[4] "DLS1"; u32 version=1; u32 header_bytes; u32 flags (bit0 adaptive)
+    char[4] "DLS1"; u32 version=2; u32 header_bytes; u32 flags (bit0 adaptive)
     i32 ndim, nvars, dtype (0 f32, 1 f64), r_max
     i64 nx, ny, nz, nt
     i32 px, py, pz, pmin, window, batch_blocks
@@ -25,7 +25,7 @@ Uncompressed batch payload for blocks [b0, b0 + nb):
     qV         per block, zigzag(int32) of qV[k][t] (k < r, t < W_b), as 4
                byte planes (all low bytes, then the next bytes, ...)
     qA         per block, zigzag(int32) of qA[k][p] (k < r, p < M_b), 4 planes
-    codes      per block, u16 codes[t][p] as 2 planes (low bytes, high bytes)
+    codes      per block, u8 codes[t][p] (one plane)
     escapes    escaped input values of the batch, block then (t, p) order,
                in the storage dtype
 """
@@ -39,7 +39,7 @@ import numpy as np
 from . import dls
 
 MAGIC = b"DLS1"
-VERSION = 1
+VERSION = 2
 ZLIB_LEVEL = 6
 _FIXED = struct.Struct("<4sIII iiii qqqq iiiiii QII")
 
@@ -78,7 +78,7 @@ def batch_payload(codes) -> bytes:
     for c in codes:
         parts.append(planes(zigzag32(c.qA.T.ravel()), 4))
     for c in codes:
-        parts.append(planes(c.codes.ravel(), 2))
+        parts.append(planes(c.codes.ravel(), 1))
     for c in codes:
         parts.append(c.esc_values.astype(c.esc_values.dtype.newbyteorder("<")).tobytes())
     return b"".join(parts)
@@ -210,7 +210,7 @@ def unpack(buf: bytes) -> "dls.Encoded":
                        .reshape(int(r), b.m).T)
         for b in bl:
             n = b.w * b.m
-            cds.append(unplanes(take(2 * n), n, 2, np.uint16).reshape(b.w, b.m))
+            cds.append(unplanes(take(n), n, 1, np.uint8).reshape(b.w, b.m))
         for j, b in enumerate(bl):
             ne = int(nesc[j])
             if ne != int(np.count_nonzero(cds[j] == dls.ESC_CODE)):

@@ -28,7 +28,7 @@ What is computed, per variable v, per spatial block x time window b:
  8. lattice -- S = qV qA^T in exact integers; xhat = float64(S) * c with
                c = eps 2^-16 (reconstruction sum of Sec. 2.6 / Alg. 2).
  9. residual-- q = rint((x - xhat) * (1/(2 eps))); out = dtype(float64(S +
-               2^17 q) * c); a point with |q| > 32767 or |x - out| > eps
+               2^17 q) * c); a point with |q| > 127 or |x - out| > eps
                (checked in FP64 on the returned dtype value) is an escape and
                is stored verbatim.  This enforces an absolute pointwise bound,
                a reading beyond the paper's L2 control.
@@ -51,8 +51,8 @@ KAPPA = 1.0            # tau = KAPPA * eps^2 * M_b * W_b
 BASIS_BITS = 16        # qV = rint(V * 2^16)
 RES_SHIFT = 17         # 2 eps = 2^17 * c
 QA_LIMIT = 2.0 ** 31   # |rint(A/eps)| must stay below this, else the row is zeroed
-Q_LIMIT = 32767        # residual codes are int16; larger |q| -> escape
-ESC_CODE = 0xFFFF      # zigzag code value reserved for escapes
+Q_LIMIT = 127          # residual codes are one byte (zigzag int8); larger |q| -> escape
+ESC_CODE = 0xFF        # zigzag code value reserved for escapes
 BATCH_BLOCKS = 1000    # Sec. 2.7.2: patches are processed in batches of 1000
 
 
@@ -283,7 +283,7 @@ class BlockCode:
     r: int                       # 0 = raw block
     qV: np.ndarray               # int64 (W_b, r)
     qA: np.ndarray               # int64 (M_b, r)
-    codes: np.ndarray            # uint16 (W_b, M_b), zigzag residual codes / ESC_CODE
+    codes: np.ndarray            # uint8 (W_b, M_b), zigzag residual codes / ESC_CODE
     esc_values: np.ndarray       # storage dtype, escaped x in (t, p) order
     # diagnostics (not stored in the stream)
     lam: Optional[np.ndarray] = None
@@ -328,12 +328,13 @@ def choose_rank(lam: np.ndarray, tau: float, rcap: int) -> int:
     return rcap
 
 
-def zigzag16(q: np.ndarray) -> np.ndarray:
+def zigzag8(q: np.ndarray) -> np.ndarray:
+    """Residual code of q, |q| <= Q_LIMIT: 0, -1, 1, -2, ... -> 0, 1, 2, 3, ..."""
     q = q.astype(np.int64)
-    return np.where(q >= 0, 2 * q, -2 * q - 1).astype(np.uint16)
+    return np.where(q >= 0, 2 * q, -2 * q - 1).astype(np.uint8)
 
 
-def unzigzag16(z: np.ndarray) -> np.ndarray:
+def unzigzag8(z: np.ndarray) -> np.ndarray:
     z = z.astype(np.int64)
     return np.where(z % 2 == 0, z // 2, -(z + 1) // 2)
 
@@ -391,7 +392,7 @@ def encode_with_basis(xs: np.ndarray, eps: float, Vr: np.ndarray, lam: np.ndarra
     qi = q.astype(np.int64)
     out = lattice_values(S, qi, eps, dtype)
     esc = big | (np.abs(x - out.astype(np.float64)) > eps)
-    codes = zigzag16(qi)
+    codes = zigzag8(qi)
     codes[esc] = ESC_CODE
     out = np.where(esc, xs, out)
     return BlockCode(r, qV, qA, codes, xs[esc].copy(), lam=lam, V=Vr, A=A,
@@ -401,7 +402,7 @@ def encode_with_basis(xs: np.ndarray, eps: float, Vr: np.ndarray, lam: np.ndarra
 def _raw_block(xs: np.ndarray) -> BlockCode:
     wb, m = xs.shape
     return BlockCode(0, np.zeros((wb, 0), np.int64), np.zeros((m, 0), np.int64),
-                     np.full((wb, m), ESC_CODE, np.uint16), xs.ravel().copy(),
+                     np.full((wb, m), ESC_CODE, np.uint8), xs.ravel().copy(),
                      out=xs.copy())
 
 
@@ -414,7 +415,7 @@ def decode_block(r: int, qV: np.ndarray, qA: np.ndarray, codes: np.ndarray,
     else:
         S = qV.astype(np.int64) @ qA.astype(np.int64).T
     esc = codes == ESC_CODE
-    q = unzigzag16(np.where(esc, 0, codes))
+    q = unzigzag8(np.where(esc, 0, codes))
     out = lattice_values(S, q, eps, dtype)
     if esc.any():
         out[esc] = esc_values

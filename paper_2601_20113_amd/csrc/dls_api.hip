@@ -862,11 +862,9 @@ dls_status dls_finalize(dls_ctx* ctx, uint8_t** out, size_t* out_bytes) {
       }
     }
     for (int64_t b = b0; b < b1; ++b) {
-      const int64_t n = int64_t(pl.blocks[b].w()) * pl.blocks[b].m, pad = pad16(n);
-      for (int j = 0; j < 2; ++j) {
-        const uint8_t* src = codes.data() + pl.code_off[b] + j * pad;
-        raw.insert(raw.end(), src, src + n);
-      }
+      const int64_t n = int64_t(pl.blocks[b].w()) * pl.blocks[b].m;
+      const uint8_t* src = codes.data() + pl.code_off[b];
+      raw.insert(raw.end(), src, src + n);
     }
     for (int64_t i = esc_start[b0]; i < esc_start[b1]; ++i) {
       uint8_t tmp[8];
@@ -1004,7 +1002,7 @@ std::string inflate_batch(const uint8_t* in, const StreamHeader& h, const Plan& 
   bv.qa = pos;
   for (int64_t b = b0; b < b1; ++b) pos += size_t(4) * pl.blocks[b].m * bv.raw[b - b0];
   bv.codes = pos;
-  for (int64_t b = b0; b < b1; ++b) pos += size_t(2) * pl.blocks[b].w() * pl.blocks[b].m;
+  for (int64_t b = b0; b < b1; ++b) pos += size_t(pl.blocks[b].w()) * pl.blocks[b].m;
   bv.vals = pos;
   int64_t nesc = 0;
   for (int64_t j = 0; j < cnt; ++j) {
@@ -1101,16 +1099,14 @@ dls_status dls_decompress(const uint8_t* in, size_t in_bytes, void* d_out, void*
     }
     for (int64_t b = b0; b < b1; ++b) {
       const BlockDesc& d = pl.blocks[b];
-      const int64_t n = int64_t(d.w()) * d.m, pad = pad16(n);
-      const uint8_t* lo = bv.raw.data() + pc;
-      const uint8_t* hi = lo + n;
-      std::memcpy(codes.data() + pl.code_off[b], lo, n);
-      std::memcpy(codes.data() + pl.code_off[b] + pad, hi, n);
+      const int64_t n = int64_t(d.w()) * d.m;
+      const uint8_t* cd = bv.raw.data() + pc;
+      std::memcpy(codes.data() + pl.code_off[b], cd, n);
       uint32_t want;
       std::memcpy(&want, bv.raw.data() + cnt + 4 * (b - b0), 4);
       uint32_t got = 0;
       for (int64_t i = 0; i < n; ++i) {
-        if (lo[i] == 0xFF && hi[i] == 0xFF) {
+        if (cd[i] == kEscCode) {
           const int t = int(i / d.m), pt = int(i % d.m);
           const int ii = pt % d.px(), rho = pt / d.px(), jj = rho % d.py(), kk = rho / d.py();
           const int64_t fi = (((int64_t(d.var) * dims.nt + d.t0 + t) * dims.nz + d.z0 + kk) * dims.ny + d.y0 + jj) *
@@ -1127,7 +1123,7 @@ dls_status dls_decompress(const uint8_t* in, size_t in_bytes, void* d_out, void*
         errs[bi] = "escape count mismatch";
         return;
       }
-      pc += 2 * n;
+      pc += n;
     }
   });
   for (auto& e : errs)

@@ -5,7 +5,7 @@
 // how long it is, followed by the packed, independently decodable batches.
 //
 // Header, little-endian:
-//   char[4] "DLS1"; u32 version = 1; u32 header_bytes; u32 flags (bit0 adaptive)
+//   char[4] "DLS1"; u32 version = 2; u32 header_bytes; u32 flags (bit0 adaptive)
 //   i32 ndim, nvars, dtype (0 f32, 1 f64), r_max
 //   i64 nx, ny, nz, nt
 //   i32 px, py, pz, pmin, window, batch_blocks (= 1000)
@@ -22,7 +22,7 @@
 namespace dls {
 
 namespace {
-constexpr uint32_t kVersion = 1;
+constexpr uint32_t kVersion = 2;
 constexpr size_t kFixed = 104;
 
 template <typename T>
@@ -140,7 +140,7 @@ void build_blocks(const Problem& p, Plan& plan, int slice_points) {
           plan.items.push_back(Item{int32_t(plan.blocks.size()), r0 * L.ex, nr * L.ex, r0 == 0});
         }
         plan.code_off.push_back(off);
-        off += 2 * pad16(int64_t(w) * d.m);
+        off += pad16(int64_t(w) * d.m);
         plan.blocks.push_back(d);
       }
     }

@@ -4,9 +4,9 @@
 //   desc[b]        BlockDesc, blocks ordered variable, window, patch (z, y, x)
 //   items[i]       a slice of one block's points, the unit of work of the
 //                  Gram and encode kernels; a block's items are contiguous
-//   codes          per block: low-byte plane then high-byte plane of the
-//                  zigzag int16 residual codes, [t][p] order, each plane
-//                  padded to 16 bytes; block regions start 16-byte aligned
+//   codes          per block: one byte per value, the zigzag int8 residual
+//                  codes (0xFF = escape), [t][p] order, padded to 16 bytes;
+//                  block regions start 16-byte aligned
 //   qv / qa        per block: 4 byte planes of zigzag int32 codes of the
 //                  quantized basis qV[k][t] / coefficients qA[k][p], each
 //                  plane padded to 16 bytes
@@ -28,7 +28,8 @@ namespace dls {
 
 constexpr int kBasisBits = 16;       // qV = rint(V * 2^16)
 constexpr int kResShift = 17;        // 2 eps = 2^17 * (eps * 2^-16)
-constexpr uint16_t kEscCode = 0xFFFF;
+constexpr uint8_t kEscCode = 0xFF;  // residual code of an escaped point
+constexpr int kQLimit = 127;         // |q| above this is an escape
 constexpr int kBatchBlocks = 1000;   // Sec. 2.7.2: batches of 1000 patches
 constexpr double kKappa = 1.0;       // tau = kappa eps^2 M_b W_b
 constexpr int kZlibLevel = 6;

@@ -644,7 +644,6 @@ __device__ __forceinline__ void encode_item(int64_t li, int tid, float (&Vf)[RMA
   const BlockDesc d = desc[b];
   const int W = d.w(), M = d.m, r = rank[b];
   const VarConst K = vc[d.var];
-  const int64_t wm_pad = pad16(int64_t(W) * M);
   if constexpr (DEV) {  // host-driven launches size the buffers exactly
     if (qv_off[b] + 4 * pad16(int64_t(W) * r) > work.qv_cap || qa_off[b] + 4 * pad16(int64_t(M) * r) > work.qa_cap) {
       if (tid == 0) atomicOr(work.overflow, 1u);
@@ -652,25 +651,10 @@ __device__ __forceinline__ void encode_item(int64_t li, int tid, float (&Vf)[RMA
     }
   }
 
-  for (int idx = tid; idx < RMAX * WP; idx += TEAM) {
-    const int k = idx / WP, t = idx % WP;
-    const double v = basis[int64_t(b) * WP * WP + idx];
-    const double qv = rint(v * 65536.0);
-    Vf[k][t] = float(v);
-    Qv[t][k] = qv;
-    if (it.first && k < r && t < W) {
-      const uint32_t z = zigzag32(int32_t(qv));
-      const int64_t plane = pad16(int64_t(W) * r);
-      uint8_t* dst = qv_buf + qv_off[b] + k * W + t;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) dst[j * plane] = uint8_t(z >> (8 * j));
-    }
-  }
-  team_sync<TEAM>();
-
+  // the slice's values are loaded first, so that their latency overlaps the
+  // basis staging below
   const int ps0 = tid * PPT;
-  if (ps0 >= it.np) return;
-  const int valid = (it.np - ps0) < PPT ? (it.np - ps0) : PPT;
+  const int valid = ps0 >= it.np ? 0 : ((it.np - ps0) < PPT ? (it.np - ps0) : PPT);
   const int p = it.p0 + ps0;
   const int px = d.px(), py = d.py();
   const int64_t nxy = dims.nx * dims.ny;
@@ -710,8 +694,24 @@ __device__ __forceinline__ void encode_item(int64_t li, int tid, float (&Vf)[RMA
     }
   }
 
-  const int64_t code_lo = code_off[b] + int64_t(p);
-  const int64_t code_hi = code_lo + wm_pad;
+  for (int idx = tid; idx < RMAX * WP; idx += TEAM) {
+    const int k = idx / WP, t = idx % WP;
+    const double v = basis[int64_t(b) * WP * WP + idx];
+    const double qv = rint(v * 65536.0);
+    Vf[k][t] = float(v);
+    Qv[t][k] = qv;
+    if (it.first && k < r && t < W) {
+      const uint32_t z = zigzag32(int32_t(qv));
+      const int64_t plane = pad16(int64_t(W) * r);
+      uint8_t* dst = qv_buf + qv_off[b] + k * W + t;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) dst[j * plane] = uint8_t(z >> (8 * j));
+    }
+  }
+  team_sync<TEAM>();
+  if (valid == 0) return;
+
+  const int64_t code_at = code_off[b] + int64_t(p);
 
   if (r == 0) {  // raw block: every point is an escape
 #pragma unroll
@@ -719,9 +719,8 @@ __device__ __forceinline__ void encode_item(int64_t li, int tid, float (&Vf)[RMA
       if (t >= W) continue;
       uint32_t ff[PPT];
 #pragma unroll
-      for (int e = 0; e < PPT; ++e) ff[e] = 0xFF;
-      store_bytes<PPT>(codes + code_lo + int64_t(t) * M, ff, valid, vec);
-      store_bytes<PPT>(codes + code_hi + int64_t(t) * M, ff, valid, vec);
+      for (int e = 0; e < PPT; ++e) ff[e] = kEscCode;
+      store_bytes<PPT>(codes + code_at + int64_t(t) * M, ff, valid, vec);
 #pragma unroll
       for (int e = 0; e < PPT; ++e) {
         if (e >= valid) continue;
@@ -791,7 +790,7 @@ __device__ __forceinline__ void encode_item(int64_t li, int tid, float (&Vf)[RMA
 #pragma unroll
   for (int t = 0; t < WP; ++t) {
     if (t >= W) continue;
-    uint32_t lo[PPT], hi[PPT];
+    uint32_t cd[PPT];
 #pragma unroll
     for (int e = 0; e < PPT; ++e) {
       double S = 0.0;
@@ -802,15 +801,15 @@ __device__ __forceinline__ void encode_item(int64_t li, int tid, float (&Vf)[RMA
       const double xhat = S * K.c;
       const double dlt = xv - xhat;
       double q = rint(dlt * K.inv2eps);
-      bool esc_pt = fabs(q) > 32767.0;
+      bool esc_pt = fabs(q) > double(kQLimit);
       if (esc_pt) q = 0.0;
       const double n = S + q * 131072.0;
       const T outv = T(n * K.c);
       esc_pt = esc_pt || (fabs(xv - double(outv)) > K.eps);
-      uint32_t code = 0xFFFF;
+      uint32_t code = kEscCode;
       if (!esc_pt) {
         const int32_t qi = int32_t(q);
-        code = uint32_t(uint16_t((qi << 1) ^ (qi >> 31)));
+        code = uint32_t((qi << 1) ^ (qi >> 31));  // zigzag, <= 254
       } else if (e < valid) {
         const unsigned long long slot = atomicAdd(esc.count, 1ULL);
         if (slot < esc.cap) {
@@ -818,11 +817,9 @@ __device__ __forceinline__ void encode_item(int64_t li, int tid, float (&Vf)[RMA
           esc.val[slot] = bits_of<T>(x[t][e]);
         }
       }
-      lo[e] = code & 0xFF;
-      hi[e] = code >> 8;
+      cd[e] = code;
     }
-    store_bytes<PPT>(codes + code_lo + int64_t(t) * M, lo, valid, vec);
-    store_bytes<PPT>(codes + code_hi + int64_t(t) * M, hi, valid, vec);
+    store_bytes<PPT>(codes + code_at + int64_t(t) * M, cd, valid, vec);
   }
 }
 
@@ -905,7 +902,6 @@ __global__ __launch_bounds__(256) void k_decode(T* __restrict__ F, Dims dims,
   }
   __syncthreads();
   const int64_t aplane = pad16(int64_t(M) * r);
-  const int64_t wm_pad = pad16(int64_t(W) * M);
   const int64_t nxy = dims.nx * dims.ny;
   T* base = F + fidx(dims, d.var, d.t0, d.z0, d.y0, d.x0);
   const int64_t tstride = dims.nz * nxy;
@@ -925,8 +921,8 @@ __global__ __launch_bounds__(256) void k_decode(T* __restrict__ F, Dims dims,
     const int64_t off = point_off(p, d.px(), d.py(), dims.nx, nxy);
     for (int t = 0; t < W; ++t) {
       const int64_t ci = code_off[b] + int64_t(t) * M + p;
-      const uint32_t code = uint32_t(codes[ci]) | (uint32_t(codes[ci + wm_pad]) << 8);
-      if (code == 0xFFFF) continue;
+      const uint32_t code = codes[ci];
+      if (code == kEscCode) continue;
       double S = 0.0;
 #pragma unroll
       for (int k = 0; k < WP; ++k)

@@ -158,8 +158,35 @@ def pin_escapes_rare_on_smooth_data():
         x = _rand_block(rng, w, m)
         c = dls.encode_block(x, 1e-3 * float(np.ptp(x)), 32, np.float64)
         assert c.esc_values.size == 0
-        q = dls.unzigzag16(c.codes)
+        q = dls.unzigzag8(c.codes)
         assert np.abs(q).max() <= 4
+
+
+def pin_escape_threshold():
+    """Residual codes are one byte: |q| <= 127 is coded, |q| >= 128 escapes.
+
+    X = [[100, 0], [0, v]], eps = 0.1, rank capped at 1: lam = (10^4, v^2),
+    V_1 = e_1, A = (100, 0), qA = (1000, 0), S = [[65536000, 0], [0, 0]], so
+    the point (1, 1) keeps its whole value as residual, q = rint(v / 0.2).
+    v = 25.4 gives q = 127 (code 254); v = 25.6 gives q = 128, an escape that
+    stores v verbatim; the decoder returns it exactly.
+    """
+    for v, q_want in ((25.4, 127), (-25.4, -127), (25.6, None), (-30.0, None)):
+        x = np.array([[100.0, 0.0], [0.0, v]])
+        c = dls.encode_block(x, 0.1, 1, np.float64)
+        assert c.r == 1 and c.qA[:, 0].tolist() == [1000, 0]
+        assert c.codes[0, 0] == 0 and c.codes[0, 1] == 0 and c.codes[1, 0] == 0
+        if q_want is None:
+            assert c.codes[1, 1] == dls.ESC_CODE
+            assert c.esc_values.tolist() == [v]
+        else:
+            assert c.esc_values.size == 0
+            assert int(c.codes[1, 1]) == (2 * q_want if q_want >= 0 else -2 * q_want - 1)
+        out = dls.decode_block(c.r, c.qV, c.qA, c.codes, c.esc_values, 0.1, np.float64)
+        assert np.array_equal(out, c.out)
+        assert np.abs(out - x).max() <= 0.1
+        if q_want is None:
+            assert out[1, 1] == v
 
 
 def pin_lattice_one_rounding():
@@ -176,7 +203,7 @@ def pin_lattice_one_rounding():
         c = dls.encode_block(x, eps, rcap, np.float64)
         qV = [[int(v) for v in row] for row in c.qV]
         qA = [[int(v) for v in row] for row in c.qA]
-        q = dls.unzigzag16(c.codes)
+        q = dls.unzigzag8(c.codes)
         if rcap == 1:
             assert np.abs(q).max() >= 1
         cf = Fraction(eps) / (1 << 16)
@@ -208,7 +235,7 @@ def pin_hand_worked_rank_one():
     S = np.array([[29309 * 4, 29309 * 9], [58617 * 4, 58617 * 9]])
     xhat = S * (0.5 / 65536.0)
     q = np.rint((x - xhat) / 1.0)
-    assert np.array_equal(dls.unzigzag16(c.codes), q)
+    assert np.array_equal(dls.unzigzag8(c.codes), q)
 
 
 def pin_special_blocks():
@@ -351,7 +378,7 @@ def pin_round_bf16():
 ALL_PINS = [
     pin_eigenvalues_vs_svd, pin_eigenvectors_orthonormal_and_residual,
     pin_eigenvalues_vs_jacobi, pin_rank_bruteforce, pin_exact_rank_data,
-    pin_pointwise_bound, pin_escapes_rare_on_smooth_data, pin_lattice_one_rounding,
+    pin_pointwise_bound, pin_escapes_rare_on_smooth_data, pin_escape_threshold, pin_lattice_one_rounding,
     pin_hand_worked_rank_one, pin_special_blocks, pin_gradient_and_percentile,
     pin_adaptive_plan, pin_container_round_trip, pin_round_bf16,
 ]

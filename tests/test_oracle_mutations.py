@@ -35,7 +35,8 @@ MUTATIONS = [
      "d[s(1, n - 1)] = (f[s(2, n)] - f[s(0, n - 2)])"),
     ("percentile80", "int(math.floor(0.8 * (v.size - 1)))", "int(math.ceil(0.8 * (v.size - 1)))"),
     ("lattice_values", "n = S + q * (1 << RES_SHIFT)", "n = S + q * (1 << (RES_SHIFT - 1))"),
-    ("zigzag16", "-2 * q - 1", "-2 * q + 1"),
+    ("zigzag8", "-2 * q - 1", "-2 * q + 1"),
+    ("encode_with_basis", "big = np.abs(q) > Q_LIMIT", "big = np.abs(q) > 2 * Q_LIMIT"),
 ]
 
 

@@ -248,6 +248,9 @@ struct dls_ctx {
   bool split_valid = false;       // large / small slice lists of the plan
   int64_t split_nlarge = 0, split_nsmall = 0;
   DevBuf split_lists;
+  bool feat_valid = false;        // the plan's block lists of the feature kernels
+  int64_t feat_n[3] = {0, 0, 0};
+  DevBuf feat_lists;
   DevBuf desc, items, item_start, code_off, gram, rank, lam, basis;
   DevBuf qv_size, qa_size, qv_off, qa_off, scan_tmp, qv, qa, codes, coef;
   DevBuf esc_key, esc_val, counters, vconst, eps_v, cls_lists, reject_list;
@@ -288,6 +291,31 @@ struct dls_ctx {
 };
 
 namespace {
+// The plan's blocks split by size for the feature kernels (uploaded once per
+// plan): at most kFeatSmall points, at most kWarmMaxPoints, larger.
+dls_status feature_lists(dls_ctx* ctx, FeatureLists& L) {
+  if (!ctx->feat_valid) {
+    const auto& blocks = ctx->plan.blocks;
+    std::vector<int32_t> l[3];
+    for (size_t b = 0; b < blocks.size(); ++b)
+      l[blocks[b].m <= kFeatSmall ? 0 : (blocks[b].m <= kWarmMaxPoints ? 1 : 2)].push_back(int32_t(b));
+    std::vector<int32_t> all;
+    all.reserve(blocks.size());
+    for (int c = 0; c < 3; ++c) {
+      ctx->feat_n[c] = int64_t(l[c].size());
+      all.insert(all.end(), l[c].begin(), l[c].end());
+    }
+    HIP_TRY(ctx->feat_lists.ensure(std::max<size_t>(all.size(), 1) * sizeof(int32_t)));
+    if (!all.empty())
+      HIP_TRY(hipMemcpy(ctx->feat_lists.p, all.data(), all.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    ctx->feat_valid = true;
+  }
+  const int32_t* base = ctx->feat_lists.as<int32_t>();
+  L = FeatureLists{base, ctx->feat_n[0], base + ctx->feat_n[0], ctx->feat_n[1],
+                   base + ctx->feat_n[0] + ctx->feat_n[1], ctx->feat_n[2]};
+  return DLS_OK;
+}
+
 // Eigen stage of a DLS_LEARNED encode: features, network forward (bf16),
 // warm-started eigensolve, Jacobi on the rejected blocks.
 dls_status learned_eigen(dls_ctx* ctx, const void* d_field, const Problem& p, const Dims& dims, hipStream_t s) {
@@ -299,7 +327,9 @@ dls_status learned_eigen(dls_ctx* ctx, const void* d_field, const Problem& p, co
   HIP_TRY(ctx->feat.ensure(size_t(nb) * kNF * 4));
   HIP_TRY(ctx->mlp_out.ensure(size_t(nb) * kNO * 4));
   HIP_TRY(ctx->reject.ensure(size_t(nb)));
-  HIP_TRY(launch_features(p.dtype, d_field, dims, ctx->desc.as<BlockDesc>(), nb, ctx->eps_v.as<double>(),
+  FeatureLists fl;
+  if (dls_status st = feature_lists(ctx, fl)) return st;
+  HIP_TRY(launch_features(p.dtype, d_field, dims, ctx->desc.as<BlockDesc>(), fl, ctx->eps_v.as<double>(),
                           ctx->feat.as<float>(), s));
   if (dls_status st = model_infer(m, ctx->feat.as<float>(), nb, ctx->mlp_out.as<float>(), s)) return st;
   HIP_TRY(launch_warmstart(ctx->gram.as<double>(), ctx->item_start.as<int32_t>(), ctx->desc.as<BlockDesc>(), nb,
@@ -405,6 +435,7 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
     }
     build_blocks(p, ctx->plan, slice_points(p));
     ctx->split_valid = false;
+    ctx->feat_valid = false;
     ctx->plan_warm_blocks = 0;
     for (const BlockDesc& d : ctx->plan.blocks) ctx->plan_warm_blocks += d.m <= kWarmMaxPoints ? 1 : 0;
     if (ctx->plan.blocks.size() >= (size_t(1) << 31)) return fail(DLS_EINVAL, "too many blocks");
@@ -735,8 +766,9 @@ dls_status dls_features(dls_ctx* ctx, const void* d_field, float* d_out, void* s
   const Problem& p = ctx->prob;
   if (p.window > 16) return fail(DLS_EINVAL, "features need window <= 16");
   const Dims dims{p.nx, p.ny, p.nz, p.nt};
-  HIP_TRY(launch_features(p.dtype, d_field, dims, ctx->desc.as<BlockDesc>(), int64_t(ctx->plan.blocks.size()),
-                          ctx->eps_v.as<double>(), d_out, s));
+  FeatureLists fl;
+  if (dls_status st = feature_lists(ctx, fl)) return st;
+  HIP_TRY(launch_features(p.dtype, d_field, dims, ctx->desc.as<BlockDesc>(), fl, ctx->eps_v.as<double>(), d_out, s));
   HIP_TRY(hipStreamSynchronize(s));
   return DLS_OK;
 }

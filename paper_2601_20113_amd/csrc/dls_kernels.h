@@ -75,8 +75,20 @@ hipError_t launch_eigen(int wp, const double* gpart, const int32_t* item_start, 
 // list of the blocks b < n with flag[b] != 0, in any order; *count is added to
 hipError_t launch_compact_flags(const uint8_t* flag, int64_t n, int32_t* list, unsigned int* count, hipStream_t s);
 // learned warm start (dls_learned.hip)
-hipError_t launch_features(int dtype, const void* F, const Dims& dims, const BlockDesc* desc, int64_t nblocks,
-                           const double* eps_v, float* feat, hipStream_t s);
+// Feature rows are computed per list: blocks of at most kFeatSmall points
+// (16 lanes each), the other blocks of at most kWarmMaxPoints points (one
+// wavefront each), and the rest (zero rows).
+constexpr int kFeatSmall = 16;
+struct FeatureLists {
+  const int32_t* small;
+  int64_t nsmall;
+  const int32_t* wave;
+  int64_t nwave;
+  const int32_t* zero;
+  int64_t nzero;
+};
+hipError_t launch_features(int dtype, const void* F, const Dims& dims, const BlockDesc* desc,
+                           const FeatureLists& lists, const double* eps_v, float* feat, hipStream_t s);
 hipError_t launch_normalize(const float* raw, int64_t n, const float* norm, float* z, hipStream_t s);
 hipError_t launch_gemm(bool ta, bool tb, bool bf16, const float* A, int lda, const float* B, int ldb, float* C,
                        int ldc, int M, int N, int K, const float* bias, int relu, hipStream_t s);

@@ -27,236 +27,305 @@ __device__ __forceinline__ short to_bf16(float f) {
 
 // ---------------------------------------------------------------------------
 // Per-block features: 16 statistics then the 8 x 8 pooled time-mean image
-// (normalised by the block mean and standard deviation).  One wavefront per
-// block (four per workgroup): lanes stride the block's points, FP64 sums are
-// reduced with a fixed xor-shuffle tree; lane c computes pooled cell c.
+// (normalised by the block mean and standard deviation), FP64 sums.  Blocks
+// of more than kWarmMaxPoints points get zeros (they take no warm start).
+// Blocks of at most 16 points: 16 lanes each, four per wavefront (sums by
+// DPP row reductions).  Other blocks: one wavefront each, points in chunks
+// of 64 lanes.  Neighbours in x and y come from other lanes where they hold
+// them, else from memory; the central moments take a second pass over the
+// values (kept in registers for the last chunk, reloaded for the others).
+// The 16 statistics are computed one per lane.
 // ---------------------------------------------------------------------------
+template <int CTRL, bool MAX>
+__device__ __forceinline__ double dpp_minmax(double v) {
+  const double o = dpp_f64<CTRL>(v);
+  return MAX ? fmax(v, o) : fmin(v, o);
+}
+template <bool MAX>
+__device__ __forceinline__ double row_minmax(double v) {
+  v = dpp_minmax<0xB1, MAX>(v);
+  v = dpp_minmax<0x4E, MAX>(v);
+  v = dpp_minmax<0x141, MAX>(v);
+  return dpp_minmax<0x140, MAX>(v);
+}
+// G = 16: over the lane's DPP row; G = 64: over the wavefront
+template <int G>
+__device__ __forceinline__ double fsum(double v) {
+  v = row_sum(v);
+  if constexpr (G == 64) {
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+  }
+  return v;
+}
+template <int G, bool MAX>
+__device__ __forceinline__ double fminmax(double v) {
+  v = row_minmax<MAX>(v);
+  if constexpr (G == 64) {
+    const double a = __shfl_xor(v, 16, 64);
+    v = MAX ? fmax(v, a) : fmin(v, a);
+    const double b = __shfl_xor(v, 32, 64);
+    v = MAX ? fmax(v, b) : fmin(v, b);
+  }
+  return v;
+}
+
+// Block sums of one block's values (first pass) and central sums (second).
+struct FeatSums {
+  double s1 = 0, s2 = 0, mn = INFINITY, mx = -INFINITY, adt = 0, sdt = 0, sdt2 = 0, adx = 0, ady = 0, tme = 0;
+  double cvar = 0, c3 = 0, c4 = 0, l1 = 0, l2 = 0;
+};
+
+// first-pass sums of one point: x its W values, xr / xd the values of its
+// +x / +y neighbour (used when hr / hd); returns the point's time sum
 template <typename T>
-__global__ __launch_bounds__(256) void k_features(const T* __restrict__ F, Dims dims,
-                                                  const BlockDesc* __restrict__ desc, int64_t nblocks,
-                                                  const double* __restrict__ eps_v, float* __restrict__ feat) {
-  constexpr int kStage = kWarmMaxPoints;  // the block's per-point time sums live in LDS
-  __shared__ double sts[4][kStage];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t b = int64_t(blockIdx.x) * 4 + wv;
-  if (b >= nblocks) return;
+__device__ __forceinline__ double feat_point(FeatSums& S, const T* x, const T* xr, const T* xd, int W, bool hr,
+                                             bool hd) {
+  double ts = 0.0, prev = 0.0;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    if (t < W) {
+      const double v = double(x[t]);
+      S.s1 += v;
+      S.s2 += v * v;
+      S.mn = fmin(S.mn, v);
+      S.mx = fmax(S.mx, v);
+      ts += v;
+      if (t > 0) {
+        const double dt = v - prev;
+        S.adt += fabs(dt);
+        S.sdt += dt;
+        S.sdt2 += dt * dt;
+      }
+      if (hr) S.adx += fabs(double(xr[t]) - v);
+      if (hd) S.ady += fabs(double(xd[t]) - v);
+      prev = v;
+    }
+  }
+  S.tme += ts * ts;
+  return ts;
+}
+
+template <typename T>
+__device__ __forceinline__ void feat_central(FeatSums& S, const T* x, int W, double mu) {
+  double ym1 = 0.0, ym2 = 0.0;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    if (t < W) {
+      const double y = double(x[t]) - mu;
+      const double y2 = y * y;
+      S.cvar += y2;
+      S.c3 += y2 * y;
+      S.c4 += y2 * y2;
+      if (t >= 1) S.l1 += y * ym1;
+      if (t >= 2) S.l2 += y * ym2;
+      ym2 = ym1;
+      ym1 = y;
+    }
+  }
+}
+
+// statistic q (0..15) of a block from its reduced sums (same value in every
+// lane that asks for the same q): one division, and one log10 for the lanes
+// that need it
+__device__ __forceinline__ float moment_feature(int q, const FeatSums& S, int W, int M, int px, int py, int pz,
+                                                double eps) {
+  const double n = double(W) * M, nd = double(W - 1) * M;
+  const double mu = S.s1 / n, var = S.cvar / n, sd = sqrt(var);
+  const double inv = sd > 0.0 ? 1.0 / sd : 0.0;
+  double a = 0.0, b = 1.0, lo = 0.0, scale = 1.0;
+  int post = 0;  // 1: -3, 2: std of dt, 3: log10, 4: times inv
+  bool on = true;
+  switch (q) {
+    case 0: a = S.s1; b = n; break;
+    case 1: a = sd; break;
+    case 2: a = S.mn; break;
+    case 3: a = S.mx; break;
+    case 4: on = sd > 0.0; a = S.c3; b = n * (sd * sd * sd); break;
+    case 5: on = sd > 0.0; a = S.c4; b = n * (var * var); post = 1; break;
+    case 6: on = W > 1; a = S.adt; b = nd; post = 4; break;
+    case 7: on = W > 1; a = S.sdt2; b = nd; post = 2; break;
+    case 8: on = px > 1; a = S.adx; b = double(W) * (px - 1) * py * pz; post = 4; break;
+    case 9: on = py > 1; a = S.ady; b = double(W) * px * (py - 1) * pz; post = 4; break;
+    case 10: on = W > 1 && sd > 0.0; a = S.l1; b = nd * var; break;
+    case 11: on = W > 2 && sd > 0.0; a = S.l2; b = double(W - 2) * M * var; break;
+    case 12: a = S.s2; b = n * (eps * eps); post = 3; lo = 1e-30; break;
+    case 13: a = sd; b = eps; post = 3; lo = 1e-15; break;
+    case 14: on = S.s2 > 0.0; a = S.tme; b = double(W) * S.s2; break;
+    default: a = double(M); post = 3; scale = 3.321928094887362; break;  // log2 M = log10 M / log10 2
+  }
+  if (!on) return 0.f;
+  double v = a / b;
+  if (post == 1) {
+    v -= 3.0;
+  } else if (post == 2) {
+    const double mdt = S.sdt / nd;
+    v = sqrt(fmax(v - mdt * mdt, 0.0)) * inv;
+  } else if (post == 3) {
+    v = log10(fmax(v, lo)) * scale;
+  } else if (post == 4) {
+    v *= inv;
+  }
+  return float(v);
+}
+
+// pooled cell c = 8 b + a: mean over t and z of the rows / columns that fall
+// in the cell (or the single nearest one), from the per-point time sums ts
+__device__ __forceinline__ float pooled_cell(int c, const double* ts, int W, int px, int py, int pz, double mu,
+                                             double sd) {
+  const int bb = c >> 3, aa = c & 7;
+  int j0 = (bb * py + 7) / 8, j1 = ((bb + 1) * py + 7) / 8;
+  int i0 = (aa * px + 7) / 8, i1 = ((aa + 1) * px + 7) / 8;
+  if (j1 <= j0) { j0 = (bb * py) / 8; j1 = j0 + 1; }
+  if (i1 <= i0) { i0 = (aa * px) / 8; i1 = i0 + 1; }
+  double s = 0.0;
+  for (int kk = 0; kk < pz; ++kk)
+    for (int jj = j0; jj < j1; ++jj)
+      for (int ii = i0; ii < i1; ++ii) s += ts[(kk * py + jj) * px + ii];
+  const double cellv = s / double((i1 - i0) * (j1 - j0) * pz * W);
+  return float(sd > 0.0 ? (cellv - mu) / sd : 0.0);
+}
+
+// Blocks of at most 16 points: 16 lanes per block (lane = point), four blocks
+// per wavefront, sixteen per workgroup.  Every lane of a DPP row takes part in
+// the reductions; a lane past the list end computes on a copy of the last
+// listed block and writes nothing.
+template <typename T>
+__global__ __launch_bounds__(256) void k_features_small(const T* __restrict__ F, Dims dims,
+                                                       const BlockDesc* __restrict__ desc,
+                                                       const int32_t* __restrict__ list, int64_t nlist,
+                                                       const double* __restrict__ eps_v, float* __restrict__ feat) {
+  __shared__ double sts[16][16];
+  const int lane = threadIdx.x & 63, g = lane & 15, grp = threadIdx.x >> 4;
+  const int64_t li = int64_t(blockIdx.x) * 16 + grp;
+  const bool have = li < nlist;
+  const int64_t b = list[have ? li : nlist - 1];
   const BlockDesc d = desc[b];
   const int W = d.w(), M = d.m, px = d.px(), py = d.py(), pz = d.pz();
-  if (M > kWarmMaxPoints) {  // no warm start for this block: no features either
-    feat[b * 80 + lane] = 0.f;
-    if (lane < 16) feat[b * 80 + 64 + lane] = 0.f;
-    return;
+  const int64_t nxy = dims.nx * dims.ny, tstride = dims.nz * nxy;
+  const int p = g;
+  const bool act = p < M;
+  const int i = p % px, rho = p / px, j = rho % py, k = rho / py;
+  T x[16];
+  {
+    const T* pt = F + (((int64_t(d.var) * dims.nt + d.t0) * dims.nz + d.z0 + k) * dims.ny + d.y0 + j) * dims.nx +
+                  d.x0 + i;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) x[t] = (act && t < W) ? pt[int64_t(t) * tstride] : T(0);
   }
+  // the +x and +y neighbours of a point of the block are points of the block,
+  // so they sit in this lane's 16-lane group
+  T xr[16], xd[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    xr[t] = __shfl(x[t], (lane + 1) & 63, 64);
+    xd[t] = __shfl(x[t], (lane + px) & 63, 64);
+  }
+  FeatSums S;
+  if (act) sts[grp][p] = feat_point<T>(S, x, xr, xd, W, i + 1 < px, j + 1 < py);
+  S.s1 = fsum<16>(S.s1); S.s2 = fsum<16>(S.s2); S.adt = fsum<16>(S.adt); S.sdt = fsum<16>(S.sdt);
+  S.sdt2 = fsum<16>(S.sdt2); S.adx = fsum<16>(S.adx); S.ady = fsum<16>(S.ady); S.tme = fsum<16>(S.tme);
+  S.mn = fminmax<16, false>(S.mn);
+  S.mx = fminmax<16, true>(S.mx);
+  const double n = double(W) * M, mu = S.s1 / n;
+  if (act) feat_central<T>(S, x, W, mu);
+  S.cvar = fsum<16>(S.cvar); S.c3 = fsum<16>(S.c3); S.c4 = fsum<16>(S.c4); S.l1 = fsum<16>(S.l1);
+  S.l2 = fsum<16>(S.l2);
+  const float fq = moment_feature(g, S, W, M, px, py, pz, eps_v[d.var]);
+  const double sd = sqrt(S.cvar / n);
+  wave_sync();
+  float cells[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) cells[u] = pooled_cell(g + 16 * u, sts[grp], W, px, py, pz, mu, sd);
+  if (!have) return;
+  float* o = feat + b * 80;
+  o[g] = fq;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) o[16 + g + 16 * u] = cells[u];
+}
+
+// Blocks of 17..kWarmMaxPoints points: one wavefront per block, four per
+// workgroup; point p = 64 c + lane in chunk c.
+template <typename T>
+__global__ __launch_bounds__(256) void k_features_wave(const T* __restrict__ F, Dims dims,
+                                                      const BlockDesc* __restrict__ desc,
+                                                      const int32_t* __restrict__ list, int64_t nlist,
+                                                      const double* __restrict__ eps_v, float* __restrict__ feat) {
+  __shared__ double sts[4][kWarmMaxPoints];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t li = int64_t(blockIdx.x) * 4 + wv;
+  if (li >= nlist) return;
+  const int64_t b = list[li];
+  const BlockDesc d = desc[b];
+  const int W = d.w(), M = d.m, px = d.px(), py = d.py(), pz = d.pz();
   const int64_t nxy = dims.nx * dims.ny, tstride = dims.nz * nxy;
   const T* base = F + (((int64_t(d.var) * dims.nt + d.t0) * dims.nz + d.z0) * dims.ny + d.y0) * dims.nx + d.x0;
-  const bool stage = true;  // M <= kWarmMaxPoints = kStage
-  // the W values of point p (W <= 16), all loads issued before any use
-  auto load_point = [&](int p, int64_t shift, double* x) {
+  const int nchunk = (M + 63) >> 6;
+  auto point_ptr = [&](int p) {
     const int i = p % px, rho = p / px, j = rho % py, k = rho / py;
-    const T* pt = base + int64_t(k) * nxy + int64_t(j) * dims.nx + i + shift;
-#pragma unroll
-    for (int t = 0; t < 16; ++t) x[t] = (t < W) ? double(pt[int64_t(t) * tstride]) : 0.0;
+    return base + int64_t(k) * nxy + int64_t(j) * dims.nx + i;
   };
-  double s1 = 0, s2 = 0, mn = INFINITY, mx = -INFINITY, adt = 0, sdt = 0, sdt2 = 0, adx = 0, ady = 0, tme = 0;
-  // first-pass sums of point p from its values x and, where they exist, its
-  // +x and +y neighbours xr, xd
-  auto accumulate = [&](int p, const double* x, const double* xr, const double* xd) {
+  auto load = [&](int p, T* x) {
+    const T* pt = point_ptr(p < M ? p : 0);
+#pragma unroll
+    for (int t = 0; t < 16; ++t) x[t] = (p < M && t < W) ? pt[int64_t(t) * tstride] : T(0);
+  };
+  FeatSums S;
+  T x[16];
+  for (int c = 0; c < nchunk; ++c) {
+    const int p = 64 * c + lane;
+    load(p, x);
+    const bool act = p < M;
     const int i = p % px, j = (p / px) % py;
-    double ts = 0.0;
+    const bool hr = act && i + 1 < px, hd = act && j + 1 < py;
+    // a neighbour outside this chunk's lanes is read from memory
+    const bool mr = hr && lane == 63, md = hd && lane + px >= 64;
+    T xr[16], xd[16];
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
-      if (t < W) {
-        const double v = x[t];
-        s1 += v;
-        s2 += v * v;
-        mn = fmin(mn, v);
-        mx = fmax(mx, v);
-        ts += v;
-        if (t > 0) {
-          const double dt = v - x[t - 1];
-          adt += fabs(dt);
-          sdt += dt;
-          sdt2 += dt * dt;
-        }
-        if (i + 1 < px) adx += fabs(xr[t] - v);
-        if (j + 1 < py) ady += fabs(xd[t] - v);
-      }
+      xr[t] = __shfl(x[t], (lane + 1) & 63, 64);
+      xd[t] = __shfl(x[t], (lane + px) & 63, 64);
     }
-    tme += ts * ts;
-    if (stage) sts[wv][p] = ts;
-  };
-  // second-pass (central) sums of point p
-  double c3 = 0, c4 = 0, l1 = 0, l2 = 0, cvar = 0;
-  auto central = [&](const double* x, double mu) {
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      if (t < W) {
-        const double y = x[t] - mu;
-        const double y2 = y * y;
-        cvar += y2;
-        c3 += y2 * y;
-        c4 += y2 * y2;
-        if (t >= 1) l1 += y * (x[t - 1] - mu);
-        if (t >= 2) l2 += y * (x[t - 2] - mu);
-      }
-    }
-  };
-  const bool one = M <= 64;  // one point per lane: neighbours come from other lanes, values stay in registers
-  // FP32 blocks of 65..256 points: four points per lane (p = lane + 64 r),
-  // kept in registers as loaded; neighbours come from other lanes
-  const bool regs4 = sizeof(T) == 4 && !one;
-  double x1[16];
-  float xf[4][16];
-  if (regs4) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int p = lane + 64 * r;
-      const int i = p % px, rho = p / px, j = rho % py, k = rho / py;
-      const T* pt = base + int64_t(k) * nxy + int64_t(j) * dims.nx + i;
-#pragma unroll
-      for (int t = 0; t < 16; ++t) xf[r][t] = (p < M && t < W) ? float(pt[int64_t(t) * tstride]) : 0.f;
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int p = lane + 64 * r;
-      const int i = p % px, j = (p / px) % py;
-      const bool hr = i + 1 < px && p < M, hd = j + 1 < py && p < M;
-      const int lr = (lane + 1) & 63, ld = (lane + px) & 63;
-      const bool rr_next = lane + 1 >= 64, rd_next = lane + px >= 64;
-      double ts = 0.0, prev = 0.0;
+    if (mr || md) {
+      const T* pt = point_ptr(p);
 #pragma unroll
       for (int t = 0; t < 16; ++t) {
-        // every lane takes part in the shuffles
-        const float ar = __shfl(xf[r][t], lr, 64), ad = __shfl(xf[r][t], ld, 64);
-        const float br = r < 3 ? __shfl(xf[r < 3 ? r + 1 : r][t], lr, 64) : 0.f;
-        const float bd = r < 3 ? __shfl(xf[r < 3 ? r + 1 : r][t], ld, 64) : 0.f;
-        if (p < M && t < W) {
-          const double v = xf[r][t];
-          s1 += v;
-          s2 += v * v;
-          mn = fmin(mn, v);
-          mx = fmax(mx, v);
-          ts += v;
-          if (t > 0) {
-            const double dt = v - prev;
-            adt += fabs(dt);
-            sdt += dt;
-            sdt2 += dt * dt;
-          }
-          if (hr) adx += fabs(double(rr_next ? br : ar) - v);
-          if (hd) ady += fabs(double(rd_next ? bd : ad) - v);
-          prev = v;
+        if (t < W) {
+          if (mr) xr[t] = pt[int64_t(t) * tstride + 1];
+          if (md) xd[t] = pt[int64_t(t) * tstride + dims.nx];
         }
       }
-      if (p < M) {
-        tme += ts * ts;
-        sts[wv][p] = ts;
-      }
     }
-  } else if (one) {
-    const bool act = lane < M;
-    if (act) {
-      load_point(lane, 0, x1);
-    } else {
-#pragma unroll
-      for (int t = 0; t < 16; ++t) x1[t] = 0.0;
-    }
-    double xr[16], xd[16];
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      xr[t] = __shfl(x1[t], lane + 1, 64);
-      xd[t] = __shfl(x1[t], lane + px, 64);
-    }
-    if (act) accumulate(lane, x1, xr, xd);
-  } else {
-    for (int p = lane; p < M; p += 64) {
-      const int i = p % px, j = (p / px) % py;
-      double x[16], xr[16], xd[16];
-      load_point(p, 0, x);
-      if (i + 1 < px) load_point(p, 1, xr);
-      if (j + 1 < py) load_point(p, dims.nx, xd);
-      accumulate(p, x, xr, xd);
-    }
+    if (act) sts[wv][p] = feat_point<T>(S, x, xr, xd, W, hr, hd);
   }
-  s1 = wave_sum(s1); s2 = wave_sum(s2); adt = wave_sum(adt); sdt = wave_sum(sdt); sdt2 = wave_sum(sdt2);
-  adx = wave_sum(adx); ady = wave_sum(ady); tme = wave_sum(tme);
-  for (int o = 32; o >= 1; o >>= 1) {
-    mn = fmin(mn, __shfl_xor(mn, o, 64));
-    mx = fmax(mx, __shfl_xor(mx, o, 64));
+  S.s1 = fsum<64>(S.s1); S.s2 = fsum<64>(S.s2); S.adt = fsum<64>(S.adt); S.sdt = fsum<64>(S.sdt);
+  S.sdt2 = fsum<64>(S.sdt2); S.adx = fsum<64>(S.adx); S.ady = fsum<64>(S.ady); S.tme = fsum<64>(S.tme);
+  S.mn = fminmax<64, false>(S.mn);
+  S.mx = fminmax<64, true>(S.mx);
+  const double n = double(W) * M, mu = S.s1 / n;
+  // second pass, last chunk first: its values are still in registers
+  for (int c = nchunk - 1; c >= 0; --c) {
+    const int p = 64 * c + lane;
+    if (c != nchunk - 1) load(p, x);
+    if (p < M) feat_central<T>(S, x, W, mu);
   }
-  const double n = double(W) * M;
-  const double mu = s1 / n;
-  if (regs4) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      if (lane + 64 * r < M) {
-        double x[16];
-#pragma unroll
-        for (int t = 0; t < 16; ++t) x[t] = xf[r][t];
-        central(x, mu);
-      }
-    }
-  } else if (one) {
-    if (lane < M) central(x1, mu);
-  } else {
-    for (int p = lane; p < M; p += 64) {
-      double x[16];
-      load_point(p, 0, x);
-      central(x, mu);
-    }
-  }
-  cvar = wave_sum(cvar); c3 = wave_sum(c3); c4 = wave_sum(c4); l1 = wave_sum(l1); l2 = wave_sum(l2);
-  const double var = cvar / n;
-  const double sd = sqrt(var);
-  const double inv = sd > 0.0 ? 1.0 / sd : 0.0;
+  S.cvar = fsum<64>(S.cvar); S.c3 = fsum<64>(S.c3); S.c4 = fsum<64>(S.c4); S.l1 = fsum<64>(S.l1);
+  S.l2 = fsum<64>(S.l2);
+  const float fq = moment_feature(lane & 15, S, W, M, px, py, pz, eps_v[d.var]);
+  const double sd = sqrt(S.cvar / n);
   wave_sync();
-  // pooled time-mean: lane c owns cell (row group c / 8, column group c % 8)
-  double cellv;
-  {
-    const int bb = lane >> 3, aa = lane & 7;
-    int j0 = (bb * py + 7) / 8, j1 = ((bb + 1) * py + 7) / 8;
-    int i0 = (aa * px + 7) / 8, i1 = ((aa + 1) * px + 7) / 8;
-    if (j1 <= j0) { j0 = (bb * py) / 8; j1 = j0 + 1; }
-    if (i1 <= i0) { i0 = (aa * px) / 8; i1 = i0 + 1; }
-    double s = 0.0;
-    if (stage) {
-      for (int kk = 0; kk < pz; ++kk)
-        for (int jj = j0; jj < j1; ++jj)
-          for (int ii = i0; ii < i1; ++ii) s += sts[wv][(kk * py + jj) * px + ii];
-    } else {
-      for (int t = 0; t < W; ++t)
-        for (int kk = 0; kk < pz; ++kk)
-          for (int jj = j0; jj < j1; ++jj)
-            for (int ii = i0; ii < i1; ++ii)
-              s += double(base[int64_t(t) * tstride + int64_t(kk) * nxy + int64_t(jj) * dims.nx + ii]);
-    }
-    cellv = s / double((i1 - i0) * (j1 - j0) * pz * W);
-  }
+  const float cell = pooled_cell(lane, sts[wv], W, px, py, pz, mu, sd);
   float* o = feat + b * 80;
-  o[16 + lane] = float(sd > 0.0 ? (cellv - mu) / sd : 0.0);
-  if (lane == 0) {
-    const double eps = eps_v[d.var];
-    double f[16];
-    f[0] = mu;
-    f[1] = sd;
-    f[2] = mn;
-    f[3] = mx;
-    f[4] = sd > 0.0 ? (c3 / n) / (sd * sd * sd) : 0.0;
-    f[5] = sd > 0.0 ? (c4 / n) / (var * var) - 3.0 : 0.0;
-    const double nd = double(W - 1) * M;
-    f[6] = W > 1 ? (adt / nd) * inv : 0.0;
-    const double mdt = W > 1 ? sdt / nd : 0.0;
-    f[7] = W > 1 ? sqrt(fmax(sdt2 / nd - mdt * mdt, 0.0)) * inv : 0.0;
-    f[8] = px > 1 ? (adx / (double(W) * (px - 1) * py * pz)) * inv : 0.0;
-    f[9] = py > 1 ? (ady / (double(W) * px * (py - 1) * pz)) * inv : 0.0;
-    f[10] = (W > 1 && sd > 0.0) ? (l1 / (double(W - 1) * M)) / var : 0.0;
-    f[11] = (W > 2 && sd > 0.0) ? (l2 / (double(W - 2) * M)) / var : 0.0;
-    f[12] = log10(fmax((s2 / n) / (eps * eps), 1e-30));
-    f[13] = log10(fmax(sd / eps, 1e-15));
-    f[14] = s2 > 0.0 ? tme / (double(W) * s2) : 0.0;
-    f[15] = log2(double(M));
-    for (int q = 0; q < 16; ++q) o[q] = float(f[q]);
-  }
+  if (lane < 16) o[lane] = fq;
+  o[16 + lane] = cell;
+}
+
+// zero feature rows (blocks that take no warm start)
+__global__ __launch_bounds__(256) void k_features_zero(const int32_t* __restrict__ list, int64_t nlist,
+                                                       float* __restrict__ feat) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= nlist * 80) return;
+  feat[int64_t(list[i / 80]) * 80 + i % 80] = 0.f;
 }
 
 // z-score the 16 statistics with the model's training statistics
@@ -801,13 +870,34 @@ __global__ __launch_bounds__(256) void k_warmstart(const double* __restrict__ gp
 // ---------------------------------------------------------------------------
 // Launch wrappers
 // ---------------------------------------------------------------------------
-hipError_t launch_features(int dtype, const void* F, const Dims& dims, const BlockDesc* desc, int64_t nblocks,
-                           const double* eps_v, float* feat, hipStream_t s) {
-  if (nblocks == 0) return hipSuccess;
-  const dim3 g{unsigned((nblocks + 3) / 4)}, bl{256};
-  if (dtype == 0) hipLaunchKernelGGL(k_features<float>, g, bl, 0, s, (const float*)F, dims, desc, nblocks, eps_v, feat);
-  else hipLaunchKernelGGL(k_features<double>, g, bl, 0, s, (const double*)F, dims, desc, nblocks, eps_v, feat);
-  return hipGetLastError();
+hipError_t launch_features(int dtype, const void* F, const Dims& dims, const BlockDesc* desc,
+                           const FeatureLists& L, const double* eps_v, float* feat, hipStream_t s) {
+  const dim3 bl{256};
+  if (L.nsmall > 0) {
+    const dim3 g{unsigned((L.nsmall + 15) / 16)};
+    if (dtype == 0)
+      hipLaunchKernelGGL(k_features_small<float>, g, bl, 0, s, (const float*)F, dims, desc, L.small, L.nsmall, eps_v,
+                         feat);
+    else
+      hipLaunchKernelGGL(k_features_small<double>, g, bl, 0, s, (const double*)F, dims, desc, L.small, L.nsmall,
+                         eps_v, feat);
+    if (hipError_t e = hipGetLastError()) return e;
+  }
+  if (L.nwave > 0) {
+    const dim3 g{unsigned((L.nwave + 3) / 4)};
+    if (dtype == 0)
+      hipLaunchKernelGGL(k_features_wave<float>, g, bl, 0, s, (const float*)F, dims, desc, L.wave, L.nwave, eps_v,
+                         feat);
+    else
+      hipLaunchKernelGGL(k_features_wave<double>, g, bl, 0, s, (const double*)F, dims, desc, L.wave, L.nwave,
+                         eps_v, feat);
+    if (hipError_t e = hipGetLastError()) return e;
+  }
+  if (L.nzero > 0) {
+    hipLaunchKernelGGL(k_features_zero, dim3{unsigned((L.nzero * 80 + 255) / 256)}, bl, 0, s, L.zero, L.nzero, feat);
+    if (hipError_t e = hipGetLastError()) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_normalize(const float* raw, int64_t n, const float* norm, float* z, hipStream_t s) {

@@ -36,10 +36,19 @@ def _fields():
     f3 = synth.spectrum(20, 18, 12, 10, nmodes=8, seed=5, drift=True, dtype=np.float64)
     p3 = odls.Params(nx=20, ny=18, nz=12, nt=10, nvars=1, dtype="f64", px=8, py=8, pz=4, window=10,
                      eps=list(1e-3 * synth.range_of(f3)))
-    return [(f1, p1), (f2, p2), (f3, p3)]
+    # blocks of at most 16 points (16 lanes per block): 4 x 4 patches with
+    # truncated edges (4 x 3, 1 x 4, 1 x 3) and a short last window; 3 x 2 x 2
+    # patches of a 3D field with 1 x 2 x 2 edges
+    f4 = synth.blobs2d(nx=29, ny=27, nt=19, seed=7, nblobs=5, dtype=np.float32)
+    p4 = odls.Params(nx=29, ny=27, nz=1, nt=19, nvars=1, dtype="f32", px=4, py=4, pz=1, window=16,
+                     eps=list(1e-3 * synth.range_of(f4)))
+    f5 = synth.spectrum(10, 6, 8, 7, nmodes=6, seed=9, drift=True, dtype=np.float64)
+    p5 = odls.Params(nx=10, ny=6, nz=8, nt=7, nvars=1, dtype="f64", px=3, py=2, pz=2, window=7,
+                     eps=list(1e-3 * synth.range_of(f5)))
+    return [(f1, p1), (f2, p2), (f3, p3), (f4, p4), (f5, p5)]
 
 
-@pytest.mark.parametrize("case", [0, 1, 2])
+@pytest.mark.parametrize("case", [0, 1, 2, 3, 4])
 def test_features_match_oracle(case):
     f, p = _fields()[case]
     print("features case", case, flush=True)

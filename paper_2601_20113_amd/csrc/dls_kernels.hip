@@ -375,7 +375,8 @@ __global__ __launch_bounds__(256) void k_eigen(const double* __restrict__ gpart,
   constexpr int GPW = 256 / WP;
   constexpr int LD = WP + 1;
   __shared__ double sA[GPW][WP * LD];
-  __shared__ double2 sCS[GPW][WP];
+  // one (c, s) per position pair, kept at its lower position k < WP / 2
+  __shared__ double2 sCS[GPW][WP / 2];
   __shared__ double sLam[GPW][WP], sSg[GPW][WP];
   __shared__ int sPerm[GPW][WP];
   const int grp = threadIdx.x / WP, i = threadIdx.x % WP;
@@ -445,18 +446,20 @@ __global__ __launch_bounds__(256) void k_eigen(const double* __restrict__ gpart,
       if (i < m) {
         double c, s;
         jacobi_rotation(A[i * LD + pos], A[m * LD + mpos], A[i * LD + mpos], c, s);
-        CS[pos] = make_double2(c, -s);
-        CS[mpos] = make_double2(c, s);
+        // seen from position pos the pair rotates by (c, -s), from mpos by (c, s)
+        if (pos < mpos) CS[pos] = make_double2(c, -s);
+        else CS[mpos] = make_double2(c, s);
       }
       wave_sync();
-      const double2 ci = CS[pos];
+      double2 ci = CS[pos < mpos ? pos : mpos];
+      if (pos > mpos) ci.y = -ci.y;
       double pm[WP];
 #pragma unroll
       for (int k = 0; k < WP; ++k) pm[k] = A[m * LD + k];
 #pragma unroll
       for (int k = 0; k < WP / 2; ++k) {
         const int mk = WP - 1 - k;
-        const double2 ck = CS[k], cm = CS[mk];
+        const double2 ck = CS[k], cm = make_double2(ck.x, -ck.y);
         // row rotation (own row with the partner's), then column rotation
         const double rk = fma(ci.x, a[k], ci.y * pm[k]);
         const double rm = fma(ci.x, a[mk], ci.y * pm[mk]);

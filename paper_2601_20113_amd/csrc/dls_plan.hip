@@ -5,11 +5,10 @@
 // exceeds the 80th percentile of the snapshot's gradient magnitude.
 //
 // Device side: gradient magnitude in FP64 (central differences inside,
-// one-sided at the ends), recomputed from the snapshot in every pass rather
-// than stored; the exact order statistic sorted(g)[floor(0.8 (n-1))] by radix
-// selection over the FP64 bit patterns (two 11-bit digit passes, then the few
-// points sharing the 22-bit prefix are gathered and selected on the host);
-// per-level node sums.  Host side: the depth-first walk that emits the split
+// one-sided at the ends), stored once; the exact order statistic
+// sorted(g)[floor(0.8 (n-1))] by radix selection over the FP64 bit patterns
+// (three 11-bit digit passes, then the few points sharing the 33-bit prefix
+// are gathered and selected on the host); per-level node sums.  Host side: the depth-first walk that emits the split
 // bits and the leaves in (z0, y0, x0) order.
 #include <hip/hip_runtime.h>
 

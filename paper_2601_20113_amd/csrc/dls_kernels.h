@@ -47,7 +47,7 @@ constexpr size_t kOverflowAt = 4 * 8 + kEncodeClasses * 4;
 constexpr size_t kRejectCountAt = kOverflowAt + 4;  // u32: blocks the warm start left to Jacobi
 constexpr size_t kTotalsAt = 88;
 constexpr size_t kCounterBytes = kTotalsAt + 16;
-// largest slice (points) the small-slice encode takes: one wavefront x PPT
+// largest slice (points) the small-slice encode takes: its team of lanes x PPT
 int encode_small_limit(int wp, int dtype);
 
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);

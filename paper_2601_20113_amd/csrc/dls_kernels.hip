@@ -617,11 +617,15 @@ __device__ __forceinline__ void store_bytes(uint8_t* __restrict__ dst, const uin
 
 // RMAX is the rank class of the launch (every block in it has r <= RMAX), so
 // the per-point coefficient registers are sized for the class, not for W.
-// One slice, encoded by a team of TEAM threads (the workgroup, 256, or one
-// wavefront, 64, for slices of at most 64 * PPT points); `tid` < TEAM.
+// One slice, encoded by a team of TEAM threads (the workgroup, 256, or, for
+// small slices, part of one wavefront: SmallTeam lanes, at most
+// SmallTeam * PPT points); `tid` < TEAM.
+template <int WP, typename T>
+constexpr int SmallTeam = (WP == 16 && sizeof(T) == 4) ? 16 : 64;
+
 template <int TEAM>
 __device__ __forceinline__ void team_sync() {
-  if constexpr (TEAM == 64) wave_sync();
+  if constexpr (TEAM <= 64) wave_sync();  // the team's lanes are in one wavefront
   else __syncthreads();
 }
 
@@ -846,15 +850,15 @@ __global__ __launch_bounds__(256) void k_encode(const T* __restrict__ F, Dims di
                                                 uint8_t* __restrict__ codes,
                                                 float* __restrict__ coef,
                                                 EscOut esc, EncodeWork work) {
-  constexpr int NTEAM = SMALL ? 4 : 1;
-  constexpr int TEAM = SMALL ? 64 : 256;
+  constexpr int TEAM = SMALL ? SmallTeam<WP, T> : 256;
+  constexpr int NTEAM = 256 / TEAM;
   __shared__ float Vf[NTEAM][RMAX][WP];    // [k][t]
   __shared__ double Qv[NTEAM][WP][RMAX];   // [t][k], integer valued
-  const int team = SMALL ? int(threadIdx.x >> 6) : 0;
-  const int tid = SMALL ? int(threadIdx.x & 63) : int(threadIdx.x);
+  const int team = int(threadIdx.x) / TEAM;
+  const int tid = int(threadIdx.x) % TEAM;
   const int64_t first = int64_t(blockIdx.x) * NTEAM + team;
   if constexpr (!DEV) {
-    if (SMALL && first >= work.count) return;  // a whole wavefront leaves together
+    if (SMALL && first >= work.count) return;  // a whole team leaves together
     encode_item<WP, T, PPT, RMAX, false, TEAM>(first, tid, Vf[team], Qv[team], F, dims, desc, items, item_list,
                                                rank, basis, qv_off, qa_off, code_off, vc, qv_buf, qa_buf, codes,
                                                coef, esc, work);
@@ -1193,19 +1197,19 @@ static void encode_class(int rc, const dim3& g, hipStream_t s, const T* F, const
 #undef DLS_ENC
 }
 
-int encode_small_limit(int wp, int dtype) { return 64 * ((wp == 16 && dtype == 0) ? 4 : 2); }
+int encode_small_limit(int wp, int dtype) { return (wp == 16 && dtype == 0) ? 16 * 4 : 64 * 2; }
 
 hipError_t launch_encode(int wp, int dtype, int cls, const void* F, const Dims& dims, const BlockDesc* desc,
                          const Item* items, const int32_t* list, const EncodeWork& work, const uint8_t* rank,
                          const double* basis, const int64_t* qv_off, const int64_t* qa_off,
                          const int64_t* code_off, const VarConst* vc, uint8_t* qv, uint8_t* qa,
                          uint8_t* codes, float* coef, EscOut esc, hipStream_t s) {
-  // classes kRankClasses.. hold small slices: four per workgroup.  Host-driven:
-  // one team per slice; device-driven: a grid that fills the chip a few times
-  // over and walks the list
+  // classes kRankClasses.. hold small slices: 16 per workgroup (FP32, W <= 16)
+  // or 4.  Host-driven: one team per slice; device-driven: a grid that fills
+  // the chip a few times over and walks the list
   const bool small = cls >= kRankClasses;
   const int rc = cls % kRankClasses;
-  const int64_t per = small ? 4 : 1;
+  const int64_t per = small ? ((wp == 16 && dtype == 0) ? 16 : 4) : 1;
   const int64_t need = (work.count + per - 1) / per;
   const int64_t grid = work.dcount ? std::min<int64_t>(need, 4096) : need;
   if (grid == 0) return hipSuccess;

@@ -421,15 +421,18 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ r
                                                      const float* __restrict__ norm, const float* __restrict__ P,
                                                      const short* __restrict__ packed, float* __restrict__ out) {
   constexpr int LW = kPackLd;
-  __shared__ __align__(16) short sW[kNO * LW];
+  // one layer's weights at a time, the output layer in parts of at most kH
+  // rows, so that three workgroups fit in a CU's LDS
+  __shared__ __align__(16) short sW[kH * LW];
   __shared__ __align__(16) short sH[4][16 * LW];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, r = lane & 15, q = lane >> 4;
   const int64_t row0 = int64_t(blockIdx.x) * 64 + wave * 16;
   const bool row_ok = row0 + r < n;
   short* H = sH[wave];
-  // layer `l` (0, 1, 2) of N outputs: copy its packed image into LDS
-  auto stage = [&](int l, int N) {
-    const uint4* src = reinterpret_cast<const uint4*>(packed + int64_t(l) * kH * LW);
+  // N packed rows (outputs) from row `first` of the packed image (layers 1, 2
+  // and 3 start at rows 0, kH and 2 kH) into LDS
+  auto stage = [&](int first, int N) {
+    const uint4* src = reinterpret_cast<const uint4*>(packed + int64_t(first) * LW);
     uint4* dst = reinterpret_cast<uint4*>(sW);
     const int n16 = N * LW * 2 / 16;
     for (int i = threadIdx.x; i < n16; i += 256) dst[i] = src[i];
@@ -473,7 +476,7 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ r
   __syncthreads();
   layer([&](int ks) { return z[ks]; }, 5, kH, hidden_out(P + kOffb1));
   __syncthreads();
-  stage(1, kH);
+  stage(kH, kH);
   __syncthreads();
   // h1 is read from H and h2 written back into it: read all fragments first
   bf16x4 h[8];
@@ -482,18 +485,24 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ r
   __syncthreads();
   layer([&](int ks) { return h[ks]; }, 8, kH, hidden_out(P + kOffb2));
   __syncthreads();
-  stage(2, kNO);
-  __syncthreads();
 #pragma unroll
   for (int ks = 0; ks < 8; ++ks) h[ks] = from_h(ks);
   const float* b3 = P + kOffb3;
-  layer([&](int ks) { return h[ks]; }, 8, kNO, [&](int nt, f32x4 acc) {
+  // output layer in three parts of 96, 96 and 80 outputs
+  for (int part = 0; part < 3; ++part) {
+    const int c0 = 96 * part, N = part < 2 ? 96 : kNO - 192;
+    __syncthreads();  // the previous weights are no longer read
+    stage(2 * kH + c0, N);
+    __syncthreads();
+    layer([&](int ks) { return h[ks]; }, 8, N, [&](int nt, f32x4 acc) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t i = row0 + 4 * q + v;
-      if (i < n) out[i * kNO + nt * 16 + r] = acc[v] + b3[nt * 16 + r];
-    }
-  });
+      for (int v = 0; v < 4; ++v) {
+        const int64_t i = row0 + 4 * q + v;
+        const int c = c0 + nt * 16 + r;
+        if (i < n) out[i * kNO + c] = acc[v] + b3[c];
+      }
+    });
+  }
 }
 
 // Loss CE(logits, r - 1) + masked MSE of the basis, per sample; gout = dL/dout

@@ -232,6 +232,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ratio", action="store_true", help="skip the compression ratios (host zlib)")
     ap.add_argument("--forms", default="plain,full")
+    ap.add_argument("--no-decode", action="store_true", help="skip the device decode measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 4 GiB device-to-device copy twice (the reference the "
                          "HBM byte counters are scaled by) and exit")
@@ -300,6 +301,41 @@ def main():
         roof = {"kernel": kern, "bound": "alu", "achieved": None, "peak": None, "unit": "TFLOP/s",
                 "frac": None, "traffic": None, "launch_ms": round(stage[dom], 4)}
 
+    # device decode (the inverse, Alg. 2) of the headline form's last encode:
+    # the context's device payload back to a field, timed with events on the
+    # stream the kernels run on; every point checked against the bound
+    dec = None
+    if not args.no_decode:
+        log("device decode of the %s form" % head_form)
+        outbuf = torch.empty_like(field)
+        stream = torch.cuda.current_stream()
+        for _ in range(max(1, args.warmup)):
+            head["enc"].decode(outbuf, stream=stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            head["enc"].decode(outbuf, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        dms = e0.elapsed_time(e1) / args.steps
+        ok = True
+        for v in range(field.shape[0]):
+            for t in range(field.shape[1]):
+                d = (outbuf[v, t].double() - field[v, t].double()).abs().max().item()
+                ok = ok and d <= eps[v]
+        del outbuf
+        torch.cuda.empty_cache()
+        # algorithmic bytes: residual codes (1 B/value) and the coefficient
+        # payload read, the field written, escapes (16 B each)
+        dalg = nvals * (1 + es) + inf.qa_bytes + 16 * int(inf.nescapes)
+        dach = dalg / (dms * 1e-3) / 1e9
+        dec = {"value": round(in_bytes / (dms * 1e-3) / 1e9, 2), "unit": "GB/s (field bytes out)",
+               "ms": round(dms, 4), "bound_holds": bool(ok),
+               "roofline": {"kernel": "k_decode", "bound": "hbm", "achieved": round(dach, 1), "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": round(dach / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": int(dalg)}}
+        log("decode: %.3f ms, %.1f GB/s out, bound %s" % (dms, dec["value"], "holds" if ok else "VIOLATED"))
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline")
@@ -318,6 +354,7 @@ def main():
         "warm_start_accepted": int(inf.nwarm_accept) if head["params"].learned else None,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "decode": dec,
     }
     if "plain" in res and head_form != "plain":
         pl = res["plain"]

@@ -168,6 +168,18 @@ dls_status dls_encode_info_get(const dls_ctx* ctx, dls_encode_info* info);
  * library-owned host buffer; release it with dls_free. */
 dls_status dls_finalize(dls_ctx* ctx, uint8_t** out, size_t* out_bytes);
 
+/* Device half of decompression (Alg. 2, Eq. (7)) for the last dls_encode of
+ * this context: reconstructs every value from the context's device payload
+ * (quantized basis and coefficients, residual codes, escapes) into d_out, a
+ * caller-owned device buffer laid out like the encoded field
+ * ([var][t][z][y][x], the encode's dtype, nvars * nt * nz * ny * nx values).
+ * The result is bitwise the one dls_decompress gives for the stream
+ * dls_finalize writes.  Enqueued on `stream` (a hipStream_t, NULL = default
+ * stream); the call returns without waiting, and the context must not be
+ * encoded again before the stream has reached this point.  DLS_EINVAL when
+ * an argument is NULL or the context holds no encode result. */
+dls_status dls_decode(dls_ctx* ctx, void* d_out, void* stream);
+
 /* dls_encode + dls_finalize with a temporary context. */
 dls_status dls_compress(const void* d_field, const dls_params* p, void* stream,
                         uint8_t** out, size_t* out_bytes);

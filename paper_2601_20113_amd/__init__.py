@@ -35,7 +35,7 @@ EXPORTS = ["dls_ctx_create", "dls_ctx_destroy", "dls_encode", "dls_encode_info_g
            "dls_finalize", "dls_compress", "dls_query", "dls_decompress", "dls_stats",
            "dls_free", "dls_last_error", "dls_model_create", "dls_model_destroy", "dls_model_set",
            "dls_model_get", "dls_model_forward", "dls_model_grad", "dls_model_train_step",
-           "dls_features", "dls_ctx_set_model"]
+           "dls_features", "dls_ctx_set_model", "dls_decode"]
 
 
 class DlsError(RuntimeError):
@@ -112,12 +112,13 @@ def lib():
         L.dls_model_train_step.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int64, ctypes.c_float, ctypes.c_int,
                                            ctypes.POINTER(ctypes.c_float), vp]
         L.dls_features.argtypes = [vp, vp, vp, vp]
+        L.dls_decode.argtypes = [vp, vp, vp]
         L.dls_ctx_set_model.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int]
         L.dls_free.argtypes = [ctypes.c_void_p]
         L.dls_free.restype = None
         L.dls_last_error.restype = ctypes.c_char_p
         for name in ("dls_model_create", "dls_model_set", "dls_model_get", "dls_model_forward", "dls_model_grad",
-                     "dls_model_train_step", "dls_features", "dls_ctx_set_model",
+                     "dls_model_train_step", "dls_features", "dls_ctx_set_model", "dls_decode",
                      "dls_ctx_create", "dls_encode", "dls_encode_info_get", "dls_finalize", "dls_range",
                      "dls_compress", "dls_query", "dls_decompress", "dls_stats"):
             getattr(L, name).restype = ctypes.c_int
@@ -216,6 +217,12 @@ class Encoder:
         """Attach a model for encodes with learned=True (None detaches)."""
         self._model = model
         _check(lib().dls_ctx_set_model(self._h, model._h if model is not None else None, iters, margin))
+
+    def decode(self, out: torch.Tensor, stream=None) -> torch.Tensor:
+        """Reconstruct the last encode's field into `out` (device tensor of the
+        field's shape and dtype) on the device, enqueued on `stream`."""
+        _check(lib().dls_decode(self._h, ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+        return out
 
     def features(self, field: torch.Tensor, stream=None) -> torch.Tensor:
         """Raw features (nblocks x 80) of the blocks of the last encode."""

@@ -758,6 +758,29 @@ dls_status dls_model_train_step(dls_model* m, const float* d_feat, const int32_t
   return DLS_OK;
 }
 
+dls_status dls_decode(dls_ctx* ctx, void* d_out, void* stream) {
+  if (ctx == nullptr || d_out == nullptr) return fail(DLS_EINVAL, "NULL argument");
+  if (!ctx->have_result) return fail(DLS_EINVAL, "no encode result in this context");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Problem& p = ctx->prob;
+  const Dims dims{p.nx, p.ny, p.nz, p.nt};
+  // one launch per rank class, over the encode's class lists (their counts
+  // are in the host copy of the counter block the encode read back last)
+  const int64_t ni = int64_t(ctx->plan.items.size());
+  unsigned int hcls[kEncodeClasses];
+  std::memcpy(hcls, ctx->hcnt + 4 * sizeof(unsigned long long), sizeof(hcls));
+  for (int c = 0; c < kEncodeClasses; ++c)
+    HIP_TRY(launch_decode_class(p.wpad(), p.dtype, c % kRankClasses, ctx->cls_lists.as<int32_t>() + int64_t(c) * ni,
+                                int64_t(hcls[c]), d_out, dims, ctx->desc.as<BlockDesc>(), ctx->items.as<Item>(),
+                                ctx->rank.as<uint8_t>(), ctx->qv_off.as<int64_t>(), ctx->qa_off.as<int64_t>(),
+                                ctx->code_off.as<int64_t>(), ctx->vconst.as<VarConst>(), ctx->qv.as<uint8_t>(),
+                                ctx->qa.as<uint8_t>(), ctx->codes.as<uint8_t>(), s));
+  HIP_TRY(launch_scatter_keys(p.dtype, d_out, dims, ctx->desc.as<BlockDesc>(), ctx->esc_key.as<uint64_t>(),
+                              ctx->esc_val.as<uint64_t>(), ctx->nesc, s));
+  return DLS_OK;
+}
+
 dls_status dls_features(dls_ctx* ctx, const void* d_field, float* d_out, void* stream) {
   if (ctx == nullptr || d_field == nullptr || d_out == nullptr) return fail(DLS_EINVAL, "NULL argument");
   if (!ctx->have_result) return fail(DLS_EINVAL, "no encode result in this context");

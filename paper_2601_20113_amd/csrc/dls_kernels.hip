@@ -874,13 +874,16 @@ __global__ __launch_bounds__(256) void k_encode(const T* __restrict__ F, Dims di
 }
 
 // ---------------------------------------------------------------------------
-// Decode (Alg. 2): lattice values of every non-escaped point, scattered into
-// the field (Eq. (7)).  Escapes are written afterwards by k_scatter.
+// Decode (Alg. 2): lattice values of every point, scattered into the field
+// (Eq. (7)); an escaped point gets the value of q = 0 here and is overwritten
+// by the escape scatter (k_scatter or k_scatter_keys) that follows.
 // ---------------------------------------------------------------------------
-template <int WP, typename T>
+// RMAX bounds the rank of every block of the launch (a rank class, or WP).
+template <int WP, typename T, int RMAX>
 __global__ __launch_bounds__(256) void k_decode(T* __restrict__ F, Dims dims,
                                                 const BlockDesc* __restrict__ desc,
                                                 const Item* __restrict__ items,
+                                                const int32_t* __restrict__ list,
                                                 const uint8_t* __restrict__ rank,
                                                 const int64_t* __restrict__ qv_off,
                                                 const int64_t* __restrict__ qa_off,
@@ -889,14 +892,17 @@ __global__ __launch_bounds__(256) void k_decode(T* __restrict__ F, Dims dims,
                                                 const uint8_t* __restrict__ qv_buf,
                                                 const uint8_t* __restrict__ qa_buf,
                                                 const uint8_t* __restrict__ codes) {
-  __shared__ double Qv[WP][WP];  // [t][k]
-  const Item it = items[blockIdx.x];
+  // PPT consecutive points per thread: 4-byte code and coefficient-plane
+  // loads and 16-byte (FP32) stores for 4-aligned patch rows
+  constexpr int PPT = WP == 16 ? 4 : 2;
+  __shared__ double Qv[WP][RMAX];  // [t][k]
+  const Item it = items[list ? list[blockIdx.x] : int32_t(blockIdx.x)];
   const int b = it.block;
   const BlockDesc d = desc[b];
   const int W = d.w(), M = d.m, r = rank[b];
   const VarConst K = vc[d.var];
   const int64_t vplane = pad16(int64_t(W) * r);
-  for (int idx = threadIdx.x; idx < WP * WP; idx += blockDim.x) {
+  for (int idx = threadIdx.x; idx < WP * RMAX; idx += blockDim.x) {
     const int k = idx / WP, t = idx % WP;
     double v = 0.0;
     if (k < r && t < W) {
@@ -912,31 +918,91 @@ __global__ __launch_bounds__(256) void k_decode(T* __restrict__ F, Dims dims,
   const int64_t nxy = dims.nx * dims.ny;
   T* base = F + fidx(dims, d.var, d.t0, d.z0, d.y0, d.x0);
   const int64_t tstride = dims.nz * nxy;
-  for (int ps = threadIdx.x; ps < it.np; ps += blockDim.x) {
-    const int p = it.p0 + ps;
-    double qa[WP];
+  const bool vec = d.vec != 0;
+  for (int ps0 = threadIdx.x * PPT; ps0 < it.np; ps0 += blockDim.x * PPT) {
+    const int valid = (it.np - ps0) < PPT ? (it.np - ps0) : PPT;
+    const bool full = vec && valid == PPT;
+    const int p = it.p0 + ps0;
+    // coefficients of the PPT points: zigzag codes gathered one byte plane at
+    // a time, then decoded in place
+    int32_t qa[RMAX][PPT];
 #pragma unroll
-    for (int k = 0; k < WP; ++k) {
-      qa[k] = 0.0;
+    for (int k = 0; k < RMAX; ++k) {
+      uint32_t za[PPT];
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) za[e] = 0u;
       if (k < r) {
         const uint8_t* src = qa_buf + qa_off[b] + int64_t(k) * M + p;
-        const uint32_t z = uint32_t(src[0]) | (uint32_t(src[aplane]) << 8) |
-                           (uint32_t(src[2 * aplane]) << 16) | (uint32_t(src[3 * aplane]) << 24);
-        qa[k] = double(unzigzag32(z));
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          uint32_t by[PPT];
+          if (full && PPT == 4) {
+            const uint32_t w4 = *reinterpret_cast<const uint32_t*>(src + j * aplane);
+#pragma unroll
+            for (int e = 0; e < PPT; ++e) by[e] = (w4 >> (8 * e)) & 0xFFu;
+          } else {
+#pragma unroll
+            for (int e = 0; e < PPT; ++e) by[e] = e < valid ? uint32_t(src[j * aplane + e]) : 0u;
+          }
+#pragma unroll
+          for (int e = 0; e < PPT; ++e) za[e] |= by[e] << (8 * j);
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) qa[k][e] = unzigzag32(za[e]);
+    }
+    int64_t off[PPT];
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) off[e] = point_off(p + (e < valid ? e : 0), d.px(), d.py(), dims.nx, nxy);
+    // the residual codes of every step, all loads issued before any use:
+    // byte e of cw[t] is the code of point p + e at step t
+    uint32_t cw[WP];
+#pragma unroll
+    for (int t = 0; t < WP; ++t) {
+      cw[t] = 0xFFFFFFFFu;
+      if (t < W) {
+        const uint8_t* cp = codes + code_off[b] + int64_t(t) * M + p;
+        if (full && PPT == 4) {
+          cw[t] = *reinterpret_cast<const uint32_t*>(cp);
+        } else {
+#pragma unroll
+          for (int e = 0; e < PPT; ++e)
+            if (e < valid) cw[t] = (cw[t] & ~(0xFFu << (8 * e))) | (uint32_t(cp[e]) << (8 * e));
+        }
       }
     }
-    const int64_t off = point_off(p, d.px(), d.py(), dims.nx, nxy);
-    for (int t = 0; t < W; ++t) {
-      const int64_t ci = code_off[b] + int64_t(t) * M + p;
-      const uint32_t code = codes[ci];
-      if (code == kEscCode) continue;
-      double S = 0.0;
 #pragma unroll
-      for (int k = 0; k < WP; ++k)
-        if (k < r) S = fma(Qv[t][k], qa[k], S);
-      const int32_t q = int32_t(code >> 1) ^ -int32_t(code & 1);
-      const double n = S + double(q) * 131072.0;
-      base[int64_t(t) * tstride + off] = T(n * K.c);
+    for (int t = 0; t < WP; ++t) {
+      if (t >= W) continue;
+      uint32_t cd[PPT];
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) cd[e] = (cw[t] >> (8 * e)) & 0xFFu;
+      T outv[PPT];
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) {
+        double S = 0.0;
+#pragma unroll
+        for (int k = 0; k < RMAX; ++k)
+          if (k < r) S = fma(Qv[t][k], double(qa[k][e]), S);
+        // escaped points get the lattice value with q = 0 here; the escape
+        // scatter that follows overwrites them
+        const uint32_t code = cd[e] == kEscCode ? 0u : cd[e];
+        const int32_t q = int32_t(code >> 1) ^ -int32_t(code & 1);
+        outv[e] = T((S + double(q) * 131072.0) * K.c);
+      }
+      T* row = base + int64_t(t) * tstride;
+      if (full) {
+        if constexpr (sizeof(T) == 4 && PPT == 4) {
+          *reinterpret_cast<float4*>(row + off[0]) = make_float4(outv[0], outv[1], outv[2], outv[3]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < PPT; ++e) row[off[0] + e] = outv[e];
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < PPT; ++e)
+          if (e < valid) row[off[e]] = outv[e];
+      }
     }
   }
 }
@@ -1051,6 +1117,27 @@ __global__ __launch_bounds__(256) void k_classify(const Item* __restrict__ items
     lbase[threadIdx.x] = atomicAdd(counts + threadIdx.x, lcount[threadIdx.x]);
   __syncthreads();
   if (c >= 0) lists[int64_t(c) * nitems + lbase[c] + lpos] = int32_t(i);
+}
+
+// Escapes straight from the encoder's list: key = block << 32 | (t M_b + p)
+template <typename T>
+__global__ __launch_bounds__(256) void k_scatter_keys(T* __restrict__ F, Dims dims,
+                                                      const BlockDesc* __restrict__ desc,
+                                                      const uint64_t* __restrict__ key,
+                                                      const uint64_t* __restrict__ bits, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t kk = key[i];
+  const BlockDesc d = desc[kk >> 32];
+  const uint32_t tp = uint32_t(kk);
+  const int t = int(tp / uint32_t(d.m)), p = int(tp % uint32_t(d.m));
+  const int64_t at = fidx(dims, d.var, d.t0 + t, d.z0, d.y0, d.x0) +
+                     point_off(p, d.px(), d.py(), dims.nx, dims.nx * dims.ny);
+  if (sizeof(T) == 4) {
+    reinterpret_cast<uint32_t*>(F)[at] = uint32_t(bits[i]);
+  } else {
+    reinterpret_cast<uint64_t*>(F)[at] = bits[i];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1231,20 +1318,68 @@ hipError_t launch_encode(int wp, int dtype, int cls, const void* F, const Dims& 
   return hipGetLastError();
 }
 
+template <int WP, typename T, int RMAX>
+static void decode_launch(const dim3& g, hipStream_t s, void* F, const Dims& dims, const BlockDesc* desc,
+                          const Item* items, const int32_t* list, const uint8_t* rank, const int64_t* qv_off,
+                          const int64_t* qa_off, const int64_t* code_off, const VarConst* vc, const uint8_t* qv,
+                          const uint8_t* qa, const uint8_t* codes) {
+  hipLaunchKernelGGL((k_decode<WP, T, RMAX>), g, dim3{256}, 0, s, (T*)F, dims, desc, items, list, rank, qv_off,
+                     qa_off, code_off, vc, qv, qa, codes);
+}
+
+// rc < 0: every rank (RMAX = WP); else the rank class rc (r <= 1, 2, 4, ... 32)
+static hipError_t decode_dispatch(int wp, int dtype, int rc, const dim3& g, hipStream_t s, void* F,
+                                  const Dims& dims, const BlockDesc* desc, const Item* items, const int32_t* list,
+                                  const uint8_t* rank, const int64_t* qv_off, const int64_t* qa_off,
+                                  const int64_t* code_off, const VarConst* vc, const uint8_t* qv, const uint8_t* qa,
+                                  const uint8_t* codes) {
+#define DLS_DEC(WPV, TV, R) \
+  decode_launch<WPV, TV, R>(g, s, F, dims, desc, items, list, rank, qv_off, qa_off, code_off, vc, qv, qa, codes)
+#define DLS_DEC_RC(WPV, TV)                  \
+  do {                                       \
+    switch (rc) {                            \
+      case 0: DLS_DEC(WPV, TV, 1); break;    \
+      case 1: DLS_DEC(WPV, TV, 2); break;    \
+      case 2: DLS_DEC(WPV, TV, 4); break;    \
+      case 3: DLS_DEC(WPV, TV, 8); break;    \
+      case 4: DLS_DEC(WPV, TV, 16); break;   \
+      default: DLS_DEC(WPV, TV, WPV); break; \
+    }                                        \
+  } while (0)
+  if (wp == 16 && dtype == 0) DLS_DEC_RC(16, float);
+  else if (wp == 16) DLS_DEC_RC(16, double);
+  else if (dtype == 0) DLS_DEC_RC(32, float);
+  else DLS_DEC_RC(32, double);
+#undef DLS_DEC_RC
+#undef DLS_DEC
+  return hipGetLastError();
+}
+
 hipError_t launch_decode(int wp, int dtype, void* F, const Dims& dims, const BlockDesc* desc,
                          const Item* items, int64_t nitems, const uint8_t* rank, const int64_t* qv_off,
                          const int64_t* qa_off, const int64_t* code_off, const VarConst* vc,
                          const uint8_t* qv, const uint8_t* qa, const uint8_t* codes, hipStream_t s) {
   if (nitems == 0) return hipSuccess;
-  const dim3 g{unsigned(nitems)}, bl{256};
-  if (wp == 16 && dtype == 0)
-    hipLaunchKernelGGL((k_decode<16, float>), g, bl, 0, s, (float*)F, dims, desc, items, rank, qv_off, qa_off, code_off, vc, qv, qa, codes);
-  else if (wp == 16)
-    hipLaunchKernelGGL((k_decode<16, double>), g, bl, 0, s, (double*)F, dims, desc, items, rank, qv_off, qa_off, code_off, vc, qv, qa, codes);
-  else if (dtype == 0)
-    hipLaunchKernelGGL((k_decode<32, float>), g, bl, 0, s, (float*)F, dims, desc, items, rank, qv_off, qa_off, code_off, vc, qv, qa, codes);
-  else
-    hipLaunchKernelGGL((k_decode<32, double>), g, bl, 0, s, (double*)F, dims, desc, items, rank, qv_off, qa_off, code_off, vc, qv, qa, codes);
+  return decode_dispatch(wp, dtype, -1, dim3{unsigned(nitems)}, s, F, dims, desc, items, nullptr, rank, qv_off,
+                         qa_off, code_off, vc, qv, qa, codes);
+}
+
+hipError_t launch_decode_class(int wp, int dtype, int rc, const int32_t* list, int64_t count, void* F,
+                               const Dims& dims, const BlockDesc* desc, const Item* items, const uint8_t* rank,
+                               const int64_t* qv_off, const int64_t* qa_off, const int64_t* code_off,
+                               const VarConst* vc, const uint8_t* qv, const uint8_t* qa, const uint8_t* codes,
+                               hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  return decode_dispatch(wp, dtype, rc, dim3{unsigned(count)}, s, F, dims, desc, items, list, rank, qv_off, qa_off,
+                         code_off, vc, qv, qa, codes);
+}
+
+hipError_t launch_scatter_keys(int dtype, void* F, const Dims& dims, const BlockDesc* desc, const uint64_t* key,
+                              const uint64_t* bits, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const dim3 g{unsigned((n + 255) / 256)}, bl{256};
+  if (dtype == 0) hipLaunchKernelGGL(k_scatter_keys<float>, g, bl, 0, s, (float*)F, dims, desc, key, bits, n);
+  else hipLaunchKernelGGL(k_scatter_keys<double>, g, bl, 0, s, (double*)F, dims, desc, key, bits, n);
   return hipGetLastError();
 }
 

@@ -1,0 +1,72 @@
+"""The device-side decode (dls_decode) against the stream decoder.
+
+dls_decode reconstructs the last encode's field straight from the context's
+device payload.  On every parity case, on blocks with escapes and raw
+blocks, and with the escape-heavy tiny bound it must give bitwise the
+values dls_decompress gives for the stream dls_finalize writes (which the
+parity tests tie to the oracle's decoder), and hold the bound.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+import gpu_helpers as H  # noqa: E402
+import paper_2601_20113_amd as dls  # noqa: E402
+import synth  # noqa: E402
+from oracle import dls as odls  # noqa: E402
+from test_gpu_parity import CASES, _case  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _device_vs_stream(f, p):
+    lp = H.to_lib_params(p)
+    t = torch.from_numpy(f).cuda()
+    enc = dls.Encoder()
+    enc.encode(t, lp)
+    out = torch.full_like(t, float("nan"))
+    enc.decode(out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    ref = dls.decompress(enc.finalize()).cpu().numpy()
+    assert np.array_equal(got.view(np.uint8), ref.view(np.uint8))
+    return got
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_device_decode_matches_stream_decode(name):
+    print("device decode", name, flush=True)
+    f, p = _case(name)
+    got = _device_vs_stream(f, p)
+    for v in range(p.nvars):
+        assert np.all(np.abs(got[v].astype(np.float64) - f[v].astype(np.float64)) <= p.eps[v])
+
+
+def test_device_decode_raw_blocks_and_escapes():
+    print("device decode raw blocks and escapes", flush=True)
+    f, p = _case("c1_64x64x32_f64")
+    f = f.copy()
+    f[0, 3, 0, 10, 10] = np.nan
+    f[0, 20, 0, 40, 50] = 1e12
+    got = _device_vs_stream(f, p)
+    assert got[0, 20, 0, 40, 50] == 1e12
+    assert np.isnan(got[0, 3, 0, 10, 10])
+
+
+def test_device_decode_tiny_bound():
+    print("device decode tiny bound", flush=True)
+    f = synth.blobs2d(nx=32, ny=32, nt=16, seed=5, dtype=np.float32) * 1000.0
+    p = odls.Params(nx=32, ny=32, nz=1, nt=16, nvars=1, dtype="f32", px=8, py=8, pz=1, window=16, eps=[1e-5])
+    got = _device_vs_stream(f, p)
+    assert np.all(np.abs(got.astype(np.float64) - f.astype(np.float64)) <= 1e-5)
+
+
+def test_device_decode_requires_a_result():
+    enc = dls.Encoder()
+    out = torch.empty(16, device="cuda")
+    with pytest.raises(dls.DlsError):
+        enc.decode(out)

@@ -771,7 +771,8 @@ dls_status dls_decode(dls_ctx* ctx, void* d_out, void* stream) {
   unsigned int hcls[kEncodeClasses];
   std::memcpy(hcls, ctx->hcnt + 4 * sizeof(unsigned long long), sizeof(hcls));
   for (int c = 0; c < kEncodeClasses; ++c)
-    HIP_TRY(launch_decode_class(p.wpad(), p.dtype, c % kRankClasses, ctx->cls_lists.as<int32_t>() + int64_t(c) * ni,
+    HIP_TRY(launch_decode_class(p.wpad(), p.dtype, c % kRankClasses, c >= kRankClasses,
+                                ctx->cls_lists.as<int32_t>() + int64_t(c) * ni,
                                 int64_t(hcls[c]), d_out, dims, ctx->desc.as<BlockDesc>(), ctx->items.as<Item>(),
                                 ctx->rank.as<uint8_t>(), ctx->qv_off.as<int64_t>(), ctx->qa_off.as<int64_t>(),
                                 ctx->code_off.as<int64_t>(), ctx->vconst.as<VarConst>(), ctx->qv.as<uint8_t>(),

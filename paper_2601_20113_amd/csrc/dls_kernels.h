@@ -137,8 +137,9 @@ hipError_t launch_decode(int wp, int dtype, void* F, const Dims& dims, const Blo
                          const uint8_t* qv, const uint8_t* qa, const uint8_t* codes, hipStream_t s);
 hipError_t launch_scatter(int dtype, void* F, const int64_t* idx, const uint64_t* bits, int64_t n,
                           hipStream_t s);
-// decode of the `count` items of one rank class (the encode's class list)
-hipError_t launch_decode_class(int wp, int dtype, int rc, const int32_t* list, int64_t count, void* F,
+// decode of the `count` items of one rank class (the encode's class list;
+// small: a small-slice class, decoded by one wavefront per slice)
+hipError_t launch_decode_class(int wp, int dtype, int rc, bool small, const int32_t* list, int64_t count, void* F,
                                const Dims& dims, const BlockDesc* desc, const Item* items, const uint8_t* rank,
                                const int64_t* qv_off, const int64_t* qa_off, const int64_t* code_off,
                                const VarConst* vc, const uint8_t* qv, const uint8_t* qa, const uint8_t* codes,

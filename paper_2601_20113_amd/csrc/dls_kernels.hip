@@ -1318,23 +1318,24 @@ hipError_t launch_encode(int wp, int dtype, int cls, const void* F, const Dims& 
   return hipGetLastError();
 }
 
+// bl: threads per slice (one workgroup each); 64 for the small-slice classes
 template <int WP, typename T, int RMAX>
-static void decode_launch(const dim3& g, hipStream_t s, void* F, const Dims& dims, const BlockDesc* desc,
-                          const Item* items, const int32_t* list, const uint8_t* rank, const int64_t* qv_off,
-                          const int64_t* qa_off, const int64_t* code_off, const VarConst* vc, const uint8_t* qv,
-                          const uint8_t* qa, const uint8_t* codes) {
-  hipLaunchKernelGGL((k_decode<WP, T, RMAX>), g, dim3{256}, 0, s, (T*)F, dims, desc, items, list, rank, qv_off,
-                     qa_off, code_off, vc, qv, qa, codes);
+static void decode_launch(const dim3& g, const dim3& bl, hipStream_t s, void* F, const Dims& dims,
+                          const BlockDesc* desc, const Item* items, const int32_t* list, const uint8_t* rank,
+                          const int64_t* qv_off, const int64_t* qa_off, const int64_t* code_off, const VarConst* vc,
+                          const uint8_t* qv, const uint8_t* qa, const uint8_t* codes) {
+  hipLaunchKernelGGL((k_decode<WP, T, RMAX>), g, bl, 0, s, (T*)F, dims, desc, items, list, rank, qv_off, qa_off,
+                     code_off, vc, qv, qa, codes);
 }
 
 // rc < 0: every rank (RMAX = WP); else the rank class rc (r <= 1, 2, 4, ... 32)
-static hipError_t decode_dispatch(int wp, int dtype, int rc, const dim3& g, hipStream_t s, void* F,
+static hipError_t decode_dispatch(int wp, int dtype, int rc, const dim3& g, const dim3& bl, hipStream_t s, void* F,
                                   const Dims& dims, const BlockDesc* desc, const Item* items, const int32_t* list,
                                   const uint8_t* rank, const int64_t* qv_off, const int64_t* qa_off,
                                   const int64_t* code_off, const VarConst* vc, const uint8_t* qv, const uint8_t* qa,
                                   const uint8_t* codes) {
 #define DLS_DEC(WPV, TV, R) \
-  decode_launch<WPV, TV, R>(g, s, F, dims, desc, items, list, rank, qv_off, qa_off, code_off, vc, qv, qa, codes)
+  decode_launch<WPV, TV, R>(g, bl, s, F, dims, desc, items, list, rank, qv_off, qa_off, code_off, vc, qv, qa, codes)
 #define DLS_DEC_RC(WPV, TV)                  \
   do {                                       \
     switch (rc) {                            \
@@ -1360,18 +1361,18 @@ hipError_t launch_decode(int wp, int dtype, void* F, const Dims& dims, const Blo
                          const int64_t* qa_off, const int64_t* code_off, const VarConst* vc,
                          const uint8_t* qv, const uint8_t* qa, const uint8_t* codes, hipStream_t s) {
   if (nitems == 0) return hipSuccess;
-  return decode_dispatch(wp, dtype, -1, dim3{unsigned(nitems)}, s, F, dims, desc, items, nullptr, rank, qv_off,
-                         qa_off, code_off, vc, qv, qa, codes);
+  return decode_dispatch(wp, dtype, -1, dim3{unsigned(nitems)}, dim3{256}, s, F, dims, desc, items, nullptr, rank,
+                         qv_off, qa_off, code_off, vc, qv, qa, codes);
 }
 
-hipError_t launch_decode_class(int wp, int dtype, int rc, const int32_t* list, int64_t count, void* F,
+hipError_t launch_decode_class(int wp, int dtype, int rc, bool small, const int32_t* list, int64_t count, void* F,
                                const Dims& dims, const BlockDesc* desc, const Item* items, const uint8_t* rank,
                                const int64_t* qv_off, const int64_t* qa_off, const int64_t* code_off,
                                const VarConst* vc, const uint8_t* qv, const uint8_t* qa, const uint8_t* codes,
                                hipStream_t s) {
   if (count == 0) return hipSuccess;
-  return decode_dispatch(wp, dtype, rc, dim3{unsigned(count)}, s, F, dims, desc, items, list, rank, qv_off, qa_off,
-                         code_off, vc, qv, qa, codes);
+  return decode_dispatch(wp, dtype, rc, dim3{unsigned(count)}, dim3{small ? 64u : 256u}, s, F, dims, desc, items,
+                         list, rank, qv_off, qa_off, code_off, vc, qv, qa, codes);
 }
 
 hipError_t launch_scatter_keys(int dtype, void* F, const Dims& dims, const BlockDesc* desc, const uint64_t* key,

@@ -723,25 +723,6 @@ __global__ __launch_bounds__(256) void k_warmstart(const double* __restrict__ gp
   } else if (b < nblocks) {
     const BlockDesc d = desc[b];
     const int W = d.w(), M = d.m;
-    const int i0 = item_start[b], i1 = item_start[b + 1];
-    double g[16], gc[16];
-    bool fin = true;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) g[j] = gc[j] = 0.0;
-    for (int it = i0; it < i1; ++it) {  // every entry's loads of an item issued together
-      const double* gp = gpart + int64_t(it) * 256;
-#pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        g[j] += gp[t * 16 + j];
-        gc[j] += gp[j * 16 + t];
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      g[j] = 0.5 * (g[j] + gc[j]);
-      fin = fin && isfinite(g[j]);
-    }
-    fin = row_sum(fin ? 0.0 : 1.0) == 0.0;
     int rcap = r_max < W ? r_max : W;
     rcap = rcap < M ? rcap : M;
     const float* o = mlp_out + b * 272;
@@ -759,8 +740,32 @@ __global__ __launch_bounds__(256) void k_warmstart(const double* __restrict__ gp
     rhat2 = rhat2 < rcap ? rhat2 : rcap;
     const int nc = retry ? rhat2 : rhat;
     const int nit = retry ? iters + kRetryIters : iters;
+    // a block that takes no attempt here (too large, too many columns, or
+    // no wider retry) is left to the Jacobi fallback without reading its Gram
+    const bool attempt = M <= kWarmMaxPoints && nc <= RH && (!retry || rhat2 > rhat);
+    bool fin = true;
+    double g[16], gc[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) g[j] = gc[j] = 0.0;
+    if (attempt) {
+      const int i0 = item_start[b], i1 = item_start[b + 1];
+      for (int it = i0; it < i1; ++it) {  // every entry's loads of an item issued together
+        const double* gp = gpart + int64_t(it) * 256;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          g[j] += gp[t * 16 + j];
+          gc[j] += gp[j * 16 + t];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        g[j] = 0.5 * (g[j] + gc[j]);
+        fin = fin && isfinite(g[j]);
+      }
+      fin = row_sum(fin ? 0.0 : 1.0) == 0.0;
+    }
     int r = 0;
-    if (fin && M <= kWarmMaxPoints && nc <= RH && (!retry || rhat2 > rhat)) {
+    if (attempt && fin) {
       double q[RH];
 #pragma unroll
       for (int k = 0; k < RH; ++k) q[k] = (t < W && k < nc) ? double(o[16 + k * 16 + t]) : 0.0;

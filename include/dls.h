@@ -176,9 +176,11 @@ dls_status dls_finalize(dls_ctx* ctx, uint8_t** out, size_t* out_bytes);
  * The result is bitwise the one dls_decompress gives for the stream
  * dls_finalize writes.  Enqueued on `stream` (a hipStream_t, NULL = default
  * stream); the call returns without waiting, and the context must not be
- * encoded again before the stream has reached this point.  DLS_EINVAL when
- * an argument is NULL or the context holds no encode result. */
-dls_status dls_decode(dls_ctx* ctx, void* d_out, void* stream);
+ * encoded again before the stream has reached this point.  out_bytes is the
+ * size of d_out in bytes.  DLS_EINVAL (nothing written) when an argument is
+ * NULL, the context holds no encode result, or out_bytes is below
+ * nvars * nt * nz * ny * nx * element size of the last encode. */
+dls_status dls_decode(dls_ctx* ctx, void* d_out, size_t out_bytes, void* stream);
 
 /* dls_encode + dls_finalize with a temporary context. */
 dls_status dls_compress(const void* d_field, const dls_params* p, void* stream,
@@ -259,9 +261,13 @@ dls_status dls_model_train_step(dls_model* m, const float* d_feat, const int32_t
  * mean|dx|/std, mean|dy|/std, lag-1 and lag-2 temporal autocorrelation,
  * log10(mean x^2 / eps^2), log10(std / eps), time-mean energy fraction,
  * log2 M) then the 8 x 8 pooled time-mean image (normalised).  Blocks of
- * more than 256 points (which never take the warm start) get zeros;
- * windows above 16 steps: DLS_EINVAL. */
-dls_status dls_features(dls_ctx* ctx, const void* d_field, float* d_out, void* stream);
+ * more than 256 points (which never take the warm start) get zeros.
+ * field_bytes / out_bytes are the sizes of d_field and d_out in bytes.
+ * DLS_EINVAL (nothing written) for windows above 16 steps, a field buffer
+ * smaller than the last encode's field, or an output buffer smaller than
+ * nblocks * 80 floats. */
+dls_status dls_features(dls_ctx* ctx, const void* d_field, size_t field_bytes, float* d_out, size_t out_bytes,
+                        void* stream);
 /* Attach a model (NULL detaches), the number of subspace iterations
  * (0..64) and a rank margin (0..16: the warm start uses rhat + margin
  * columns, the acceptance test then keeps the smallest sufficient rank) for

@@ -225,15 +225,6 @@ def adam_step(params, grads, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         P -= lr * mh / (np.sqrt(vh) + eps)
 
 
-def predict(net: Net, z: np.ndarray, wb: int, rcap: int):
-    """(rhat, V0 (W x rhat)) from one normalised input row."""
-    _, _, out = forward(net, z[None, :])
-    rhat = int(np.argmax(out[0, :16])) + 1
-    rhat = max(1, min(rhat, rcap))
-    V0 = out[0, 16:].reshape(16, 16)[:rhat, :wb].T
-    return rhat, V0
-
-
 # --------------------------------------------------------------------------
 # Warm-started eigensolve
 # --------------------------------------------------------------------------

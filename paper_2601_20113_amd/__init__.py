@@ -111,8 +111,8 @@ def lib():
                                      ctypes.POINTER(ctypes.c_float), vp]
         L.dls_model_train_step.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int64, ctypes.c_float, ctypes.c_int,
                                            ctypes.POINTER(ctypes.c_float), vp]
-        L.dls_features.argtypes = [vp, vp, vp, vp]
-        L.dls_decode.argtypes = [vp, vp, vp]
+        L.dls_features.argtypes = [vp, vp, ctypes.c_size_t, vp, ctypes.c_size_t, vp]
+        L.dls_decode.argtypes = [vp, vp, ctypes.c_size_t, vp]
         L.dls_ctx_set_model.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int]
         L.dls_free.argtypes = [ctypes.c_void_p]
         L.dls_free.restype = None
@@ -210,26 +210,37 @@ class Encoder:
     def encode(self, field: torch.Tensor, p: Params, stream=None, keep_coef: bool = False):
         _check_field(field, p)
         cp = p.to_c()
+        self._last_params = None
         _check(lib().dls_encode(self._h, ctypes.c_void_p(field.data_ptr()), ctypes.byref(cp),
                                 _stream_handle(stream), 1 if keep_coef else 0))
+        self._last_params = p
 
     def set_model(self, model: "Model", iters: int = 2, margin: int = 1):
         """Attach a model for encodes with learned=True (None detaches)."""
         self._model = model
         _check(lib().dls_ctx_set_model(self._h, model._h if model is not None else None, iters, margin))
 
+    def _last(self) -> Params:
+        p = getattr(self, "_last_params", None)
+        if p is None:
+            raise DlsError(DLS_EINVAL, "no encode result in this context")
+        return p
+
     def decode(self, out: torch.Tensor, stream=None) -> torch.Tensor:
         """Reconstruct the last encode's field into `out` (device tensor of the
         field's shape and dtype) on the device, enqueued on `stream`."""
-        _check(lib().dls_decode(self._h, ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+        _check_field(out, self._last())
+        _check(lib().dls_decode(self._h, ctypes.c_void_p(out.data_ptr()), out.numel() * out.element_size(),
+                                _stream_handle(stream)))
         return out
 
     def features(self, field: torch.Tensor, stream=None) -> torch.Tensor:
         """Raw features (nblocks x 80) of the blocks of the last encode."""
+        _check_field(field, self._last())
         nb = self.info().nblocks
         out = torch.empty((nb, 80), dtype=torch.float32, device=field.device)
-        _check(lib().dls_features(self._h, ctypes.c_void_p(field.data_ptr()), ctypes.c_void_p(out.data_ptr()),
-                                  _stream_handle(stream)))
+        _check(lib().dls_features(self._h, ctypes.c_void_p(field.data_ptr()), field.numel() * field.element_size(),
+                                  ctypes.c_void_p(out.data_ptr()), out.numel() * 4, _stream_handle(stream)))
         return out
 
     def info(self) -> _EncodeInfo:

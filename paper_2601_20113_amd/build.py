@@ -4,6 +4,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -19,6 +20,12 @@ HIP_FLAGS = [
     "-Wno-pass-failed",
 ]
 HIP_SOURCES = ["dls_kernels.hip", "dls_plan.hip", "dls_learned.hip", "dls_api.hip"]
+# dls_codec.hip holds the encode / decode kernels; it is compiled once per
+# (padded window, element type, part) so that its rank-class instantiations
+# build in parallel: (tag, W, element type, points per thread)
+CODEC_TYPES = [("w16_f32", 16, "float", 4), ("w16_f64", 16, "double", 2), ("w32_f32", 32, "float", 2),
+               ("w32_f64", 32, "double", 2)]
+CODEC_PARTS = 3  # 0 large-slice encode, 1 small-slice encode, 2 decode
 CXX_SOURCES = ["dls_format.cpp"]
 
 
@@ -36,15 +43,25 @@ def _run(cmd, verbose):
 def build(verbose: bool = False) -> str:
     """Compile every HIP source for gfx950 and link libdls.so; returns its path."""
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
+    jobs = []
     for src in HIP_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        _run([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj], verbose)
-        objs.append(obj)
+        jobs.append((obj, [HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]))
+    for tag, wp, ty, ppt in CODEC_TYPES:
+        for part in range(CODEC_PARTS):
+            obj = os.path.join(BUILD, "dls_codec_%s_%d.o" % (tag, part))
+            defs = ["-DDLS_CODEC_TAG=" + tag, "-DDLS_CODEC_WP=%d" % wp, "-DDLS_CODEC_T=" + ty,
+                    "-DDLS_CODEC_PPT=%d" % ppt, "-DDLS_CODEC_PART=%d" % part]
+            jobs.append((obj, [HIPCC] + HIP_FLAGS + defs + ["-c", os.path.join(CSRC, "dls_codec.hip"), "-o", obj]))
     for src in CXX_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        _run(["g++", "-O2", "-std=c++17", "-fPIC", "-c", os.path.join(CSRC, src), "-o", obj], verbose)
-        objs.append(obj)
+        jobs.append((obj, ["g++", "-O2", "-std=c++17", "-fPIC", "-c", os.path.join(CSRC, src), "-o", obj]))
+    jobs.sort(key=lambda j: "dls_codec_w32" not in j[0])  # the longest units first
+    nproc = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(max_workers=nproc) as ex:
+        for f in [ex.submit(_run, cmd, verbose) for _, cmd in jobs]:
+            f.result()
+    objs = [obj for obj, _ in jobs]
     tmp = OUT + ".tmp"
     _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ["-lz", "-lpthread"], verbose)
     os.replace(tmp, OUT)

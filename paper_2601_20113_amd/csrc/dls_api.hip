@@ -758,12 +758,14 @@ dls_status dls_model_train_step(dls_model* m, const float* d_feat, const int32_t
   return DLS_OK;
 }
 
-dls_status dls_decode(dls_ctx* ctx, void* d_out, void* stream) {
+dls_status dls_decode(dls_ctx* ctx, void* d_out, size_t out_bytes, void* stream) {
   if (ctx == nullptr || d_out == nullptr) return fail(DLS_EINVAL, "NULL argument");
   if (!ctx->have_result) return fail(DLS_EINVAL, "no encode result in this context");
+  const Problem& p = ctx->prob;
+  if (out_bytes < size_t(p.values()) * size_t(p.esize()))
+    return fail(DLS_EINVAL, "output buffer smaller than the encoded field");
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const Problem& p = ctx->prob;
   const Dims dims{p.nx, p.ny, p.nz, p.nt};
   // one launch per rank class, over the encode's class lists (their counts
   // are in the host copy of the counter block the encode read back last)
@@ -782,12 +784,17 @@ dls_status dls_decode(dls_ctx* ctx, void* d_out, void* stream) {
   return DLS_OK;
 }
 
-dls_status dls_features(dls_ctx* ctx, const void* d_field, float* d_out, void* stream) {
+dls_status dls_features(dls_ctx* ctx, const void* d_field, size_t field_bytes, float* d_out, size_t out_bytes,
+                        void* stream) {
   if (ctx == nullptr || d_field == nullptr || d_out == nullptr) return fail(DLS_EINVAL, "NULL argument");
   if (!ctx->have_result) return fail(DLS_EINVAL, "no encode result in this context");
+  const Problem& p = ctx->prob;
+  if (field_bytes < size_t(p.values()) * size_t(p.esize()))
+    return fail(DLS_EINVAL, "field buffer smaller than the encoded field");
+  if (out_bytes < ctx->plan.blocks.size() * size_t(kNF) * sizeof(float))
+    return fail(DLS_EINVAL, "output buffer smaller than nblocks x 80 floats");
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const Problem& p = ctx->prob;
   if (p.window > 16) return fail(DLS_EINVAL, "features need window <= 16");
   const Dims dims{p.nx, p.ny, p.nz, p.nt};
   FeatureLists fl;

@@ -1,0 +1,547 @@
+// Encode and decode kernels of one (padded window, element type) pair.
+//
+// The build compiles this file once per pair and part, with
+//   DLS_CODEC_WP    16 or 32 (padded window)
+//   DLS_CODEC_T     float or double
+//   DLS_CODEC_PPT   points per thread of the large-slice encode
+//   DLS_CODEC_TAG   w16_f32, w16_f64, w32_f32 or w32_f64 (entry point names)
+//   DLS_CODEC_PART  0: large-slice encode, 1: small-slice encode, 2: decode
+// so that the rank-class instantiations compile in parallel.
+//
+//   k_encode  projection A = X^T V_r (Eq. (5)), coefficient and basis
+//             quantization, exact integer-lattice reconstruction in FP64 and
+//             the residual codes that enforce the absolute bound, with escapes.
+//   k_decode  Alg. 2: lattice values from (qV, qA, codes) and scatter, Eq. (7).
+//
+// Compiled with -ffp-contract=off: the lattice arithmetic must round exactly
+// as written so that the decoder reproduces the encoder bit for bit.
+#ifndef DLS_CODEC_TAG
+#define DLS_CODEC_WP 16
+#define DLS_CODEC_T float
+#define DLS_CODEC_PPT 4
+#define DLS_CODEC_TAG w16_f32
+#define DLS_CODEC_PART 0
+#endif
+#define DLS_CODEC_CAT2(a, b) a##_##b
+#define DLS_CODEC_CAT(a, b) DLS_CODEC_CAT2(a, b)
+#define DLS_CODEC_FN(name) DLS_CODEC_CAT(name, DLS_CODEC_TAG)
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "dls_device.h"
+#include "dls_kernels.h"
+
+namespace dls {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Encode: projection, quantization, lattice reconstruction, residual codes.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t zigzag32(int32_t v) {
+  return (uint32_t(v) << 1) ^ uint32_t(v >> 31);
+}
+__device__ __forceinline__ int32_t unzigzag32(uint32_t z) {
+  return int32_t(z >> 1) ^ -int32_t(z & 1);
+}
+
+template <typename T>
+__device__ __forceinline__ uint64_t bits_of(T v);
+template <>
+__device__ __forceinline__ uint64_t bits_of<float>(float v) { return uint64_t(__float_as_uint(v)); }
+template <>
+__device__ __forceinline__ uint64_t bits_of<double>(double v) { return uint64_t(__double_as_longlong(v)); }
+
+template <int PPT>
+__device__ __forceinline__ void store_bytes(uint8_t* __restrict__ dst, const uint32_t* bytes, int valid, bool vec) {
+  if (vec && valid == PPT) {
+    if (PPT == 4) {
+      *reinterpret_cast<uint32_t*>(dst) = bytes[0] | (bytes[1] << 8) | (bytes[2] << 16) | (bytes[3] << 24);
+    } else if (PPT == 2) {
+      *reinterpret_cast<uint16_t*>(dst) = uint16_t(bytes[0] | (bytes[1] << 8));
+    } else {
+      dst[0] = uint8_t(bytes[0]);
+    }
+  } else {
+    for (int e = 0; e < valid; ++e) dst[e] = uint8_t(bytes[e]);
+  }
+}
+
+// RMAX is the rank class of the launch (every block in it has r <= RMAX), so
+// the per-point coefficient registers are sized for the class, not for W.
+// One slice, encoded by a team of TEAM threads (the workgroup, 256, or, for
+// small slices, part of one wavefront: SmallTeam lanes, at most
+// SmallTeam * PPT points); `tid` < TEAM.
+template <int WP, typename T>
+constexpr int SmallTeam = (WP == 16 && sizeof(T) == 4) ? 16 : 64;
+
+template <int TEAM>
+__device__ __forceinline__ void team_sync() {
+  if constexpr (TEAM <= 64) wave_sync();  // the team's lanes are in one wavefront
+  else __syncthreads();
+}
+
+template <int WP, typename T, int PPT, int RMAX, bool DEV, int TEAM>
+__device__ __forceinline__ void encode_item(int64_t li, int tid, float (&Vf)[RMAX][WP], double (&Qv)[WP][RMAX],
+                                            const T* __restrict__ F, const Dims& dims,
+                                            const BlockDesc* __restrict__ desc,
+                                            const Item* __restrict__ items,
+                                            const int32_t* __restrict__ item_list,
+                                            const uint8_t* __restrict__ rank,
+                                            const double* __restrict__ basis,
+                                            const int64_t* __restrict__ qv_off,
+                                            const int64_t* __restrict__ qa_off,
+                                            const int64_t* __restrict__ code_off,
+                                            const VarConst* __restrict__ vc,
+                                            uint8_t* __restrict__ qv_buf,
+                                            uint8_t* __restrict__ qa_buf,
+                                            uint8_t* __restrict__ codes,
+                                            float* __restrict__ coef,
+                                            const EscOut& esc, const EncodeWork& work) {
+  const Item it = items[item_list[li]];
+  const int b = it.block;
+  const BlockDesc d = desc[b];
+  const int W = d.w(), M = d.m, r = rank[b];
+  const VarConst K = vc[d.var];
+  if constexpr (DEV) {  // host-driven launches size the buffers exactly
+    if (qv_off[b] + 4 * pad16(int64_t(W) * r) > work.qv_cap || qa_off[b] + 4 * pad16(int64_t(M) * r) > work.qa_cap) {
+      if (tid == 0) atomicOr(work.overflow, 1u);
+      return;
+    }
+  }
+
+  // the slice's values are loaded first, so that their latency overlaps the
+  // basis staging below
+  const int ps0 = tid * PPT;
+  const int valid = ps0 >= it.np ? 0 : ((it.np - ps0) < PPT ? (it.np - ps0) : PPT);
+  const int p = it.p0 + ps0;
+  const int px = d.px(), py = d.py();
+  const int64_t nxy = dims.nx * dims.ny;
+  const T* base = F + fidx(dims, d.var, d.t0, d.z0, d.y0, d.x0);
+  const int64_t tstride = dims.nz * nxy;
+  int64_t poff[PPT];
+#pragma unroll
+  for (int e = 0; e < PPT; ++e) poff[e] = point_off(p + (e < valid ? e : 0), px, py, dims.nx, nxy);
+  const bool vec = d.vec != 0;
+
+  T x[WP][PPT];
+#pragma unroll
+  for (int t = 0; t < WP; ++t) {
+    if (t < W) {
+      const T* row = base + int64_t(t) * tstride;
+      if (vec && valid == PPT) {
+        if constexpr (sizeof(T) == 4 && PPT == 4) {
+          float4 a = *reinterpret_cast<const float4*>(row + poff[0]);
+          x[t][0] = a.x; x[t][1] = a.y; x[t][2] = a.z; x[t][3] = a.w;
+        } else if constexpr (sizeof(T) == 4 && PPT == 2) {
+          float2 a = *reinterpret_cast<const float2*>(row + poff[0]);
+          x[t][0] = a.x; x[t][1] = a.y;
+        } else {
+#pragma unroll
+          for (int e = 0; e < PPT; e += 2) {
+            double2 a = *reinterpret_cast<const double2*>(row + poff[0] + e);
+            x[t][e] = T(a.x); x[t][e + 1] = T(a.y);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < PPT; ++e) x[t][e] = (e < valid) ? row[poff[e]] : T(0);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) x[t][e] = T(0);
+    }
+  }
+
+  for (int idx = tid; idx < RMAX * WP; idx += TEAM) {
+    const int k = idx / WP, t = idx % WP;
+    const double v = basis[int64_t(b) * WP * WP + idx];
+    const double qv = rint(v * 65536.0);
+    Vf[k][t] = float(v);
+    Qv[t][k] = qv;
+    if (it.first && k < r && t < W) {
+      const uint32_t z = zigzag32(int32_t(qv));
+      const int64_t plane = pad16(int64_t(W) * r);
+      uint8_t* dst = qv_buf + qv_off[b] + k * W + t;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) dst[j * plane] = uint8_t(z >> (8 * j));
+    }
+  }
+  team_sync<TEAM>();
+  if (valid == 0) return;
+
+  const int64_t code_at = code_off[b] + int64_t(p);
+
+  if (r == 0) {  // raw block: every point is an escape
+#pragma unroll
+    for (int t = 0; t < WP; ++t) {
+      if (t >= W) continue;
+      uint32_t ff[PPT];
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) ff[e] = kEscCode;
+      store_bytes<PPT>(codes + code_at + int64_t(t) * M, ff, valid, vec);
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) {
+        if (e >= valid) continue;
+        const unsigned long long slot = atomicAdd(esc.count, 1ULL);
+        if (slot < esc.cap) {
+          esc.key[slot] = (uint64_t(b) << 32) | uint64_t(uint32_t(t * M + p + e));
+          esc.val[slot] = bits_of<T>(x[t][e]);
+        }
+      }
+    }
+    return;
+  }
+
+  // projection and coefficient quantization (FP32), row-wise overflow guard
+  int32_t qa[RMAX][PPT];
+  bool ovf[PPT];
+#pragma unroll
+  for (int e = 0; e < PPT; ++e) ovf[e] = false;
+  const int64_t qa_plane = pad16(int64_t(M) * r);
+#pragma unroll
+  for (int k = 0; k < RMAX; ++k) {
+    if (k >= r) continue;
+    float a[PPT];
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) a[e] = 0.f;
+#pragma unroll
+    for (int t = 0; t < WP; ++t) {
+      if (t < W) {
+        const float v = Vf[k][t];
+#pragma unroll
+        for (int e = 0; e < PPT; ++e) a[e] = fmaf(float(x[t][e]), v, a[e]);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) {
+      const float qf = rintf(a[e] * K.inv_eps_f);
+      const bool ok = fabsf(qf) < 2147483648.0f;
+      ovf[e] = ovf[e] || !ok;
+      qa[k][e] = ok ? int32_t(qf) : 0;
+    }
+    if (coef != nullptr) {
+#pragma unroll
+      for (int e = 0; e < PPT; ++e)
+        if (e < valid) coef[qa_off[b] / 4 + int64_t(k) * M + p + e] = a[e];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < RMAX; ++k) {
+    if (k >= r) continue;
+    uint32_t z[PPT];
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) {
+      if (ovf[e]) qa[k][e] = 0;
+      z[e] = zigzag32(qa[k][e]);
+    }
+    uint8_t* dst = qa_buf + qa_off[b] + int64_t(k) * M + p;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      uint32_t by[PPT];
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) by[e] = (z[e] >> (8 * j)) & 0xFF;
+      store_bytes<PPT>(dst + j * qa_plane, by, valid, vec);
+    }
+  }
+
+  // lattice reconstruction (exact in FP64) and residual codes
+#pragma unroll
+  for (int t = 0; t < WP; ++t) {
+    if (t >= W) continue;
+    uint32_t cd[PPT];
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) {
+      double S = 0.0;
+#pragma unroll
+      for (int k = 0; k < RMAX; ++k)
+        if (k < r) S = fma(Qv[t][k], double(qa[k][e]), S);
+      const double xv = double(x[t][e]);
+      const double xhat = S * K.c;
+      const double dlt = xv - xhat;
+      double q = rint(dlt * K.inv2eps);
+      bool esc_pt = fabs(q) > double(kQLimit);
+      if (esc_pt) q = 0.0;
+      const double n = S + q * 131072.0;
+      const T outv = T(n * K.c);
+      esc_pt = esc_pt || (fabs(xv - double(outv)) > K.eps);
+      uint32_t code = kEscCode;
+      if (!esc_pt) {
+        const int32_t qi = int32_t(q);
+        code = uint32_t((qi << 1) ^ (qi >> 31));  // zigzag, <= 254
+      } else if (e < valid) {
+        const unsigned long long slot = atomicAdd(esc.count, 1ULL);
+        if (slot < esc.cap) {
+          esc.key[slot] = (uint64_t(b) << 32) | uint64_t(uint32_t(t * M + p + e));
+          esc.val[slot] = bits_of<T>(x[t][e]);
+        }
+      }
+      cd[e] = code;
+    }
+    store_bytes<PPT>(codes + code_at + int64_t(t) * M, cd, valid, vec);
+  }
+}
+
+// DEV = false: host-driven, one item per workgroup; DEV = true:
+// device-driven, the grid walks the *work.dcount items of the list
+// SMALL: four slices per workgroup, one wavefront each (slices of at most
+// 64 * PPT points); otherwise one slice per workgroup.
+template <int WP, typename T, int PPT, int RMAX, bool DEV, bool SMALL>
+__global__ __launch_bounds__(256) void k_encode(const T* __restrict__ F, Dims dims,
+                                                const BlockDesc* __restrict__ desc,
+                                                const Item* __restrict__ items,
+                                                const int32_t* __restrict__ item_list,
+                                                const uint8_t* __restrict__ rank,
+                                                const double* __restrict__ basis,
+                                                const int64_t* __restrict__ qv_off,
+                                                const int64_t* __restrict__ qa_off,
+                                                const int64_t* __restrict__ code_off,
+                                                const VarConst* __restrict__ vc,
+                                                uint8_t* __restrict__ qv_buf,
+                                                uint8_t* __restrict__ qa_buf,
+                                                uint8_t* __restrict__ codes,
+                                                float* __restrict__ coef,
+                                                EscOut esc, EncodeWork work) {
+  constexpr int TEAM = SMALL ? SmallTeam<WP, T> : 256;
+  constexpr int NTEAM = 256 / TEAM;
+  __shared__ float Vf[NTEAM][RMAX][WP];    // [k][t]
+  __shared__ double Qv[NTEAM][WP][RMAX];   // [t][k], integer valued
+  const int team = int(threadIdx.x) / TEAM;
+  const int tid = int(threadIdx.x) % TEAM;
+  const int64_t first = int64_t(blockIdx.x) * NTEAM + team;
+  if constexpr (!DEV) {
+    if (SMALL && first >= work.count) return;  // a whole team leaves together
+    encode_item<WP, T, PPT, RMAX, false, TEAM>(first, tid, Vf[team], Qv[team], F, dims, desc, items, item_list,
+                                               rank, basis, qv_off, qa_off, code_off, vc, qv_buf, qa_buf, codes,
+                                               coef, esc, work);
+    return;
+  }
+  const int64_t nwork = int64_t(*work.dcount);
+  for (int64_t li = first; li < nwork; li += int64_t(gridDim.x) * NTEAM) {
+    if (li != first) team_sync<TEAM>();  // the previous slice's LDS reads are done
+    encode_item<WP, T, PPT, RMAX, true, TEAM>(li, tid, Vf[team], Qv[team], F, dims, desc, items, item_list, rank,
+                                              basis, qv_off, qa_off, code_off, vc, qv_buf, qa_buf, codes, coef, esc,
+                                              work);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Decode (Alg. 2): lattice values of every point, scattered into the field
+// (Eq. (7)); an escaped point gets the value of q = 0 here and is overwritten
+// by the escape scatter (k_scatter or k_scatter_keys) that follows.
+// ---------------------------------------------------------------------------
+// RMAX bounds the rank of every block of the launch (a rank class, or WP).
+template <int WP, typename T, int RMAX>
+__global__ __launch_bounds__(256) void k_decode(T* __restrict__ F, Dims dims,
+                                                const BlockDesc* __restrict__ desc,
+                                                const Item* __restrict__ items,
+                                                const int32_t* __restrict__ list,
+                                                const uint8_t* __restrict__ rank,
+                                                const int64_t* __restrict__ qv_off,
+                                                const int64_t* __restrict__ qa_off,
+                                                const int64_t* __restrict__ code_off,
+                                                const VarConst* __restrict__ vc,
+                                                const uint8_t* __restrict__ qv_buf,
+                                                const uint8_t* __restrict__ qa_buf,
+                                                const uint8_t* __restrict__ codes) {
+  // PPT consecutive points per thread: 4-byte code and coefficient-plane
+  // loads and 16-byte (FP32) stores for 4-aligned patch rows
+  constexpr int PPT = WP == 16 ? 4 : 2;
+  __shared__ double Qv[WP][RMAX];  // [t][k]
+  const Item it = items[list ? list[blockIdx.x] : int32_t(blockIdx.x)];
+  const int b = it.block;
+  const BlockDesc d = desc[b];
+  const int W = d.w(), M = d.m, r = rank[b];
+  const VarConst K = vc[d.var];
+  const int64_t vplane = pad16(int64_t(W) * r);
+  for (int idx = threadIdx.x; idx < WP * RMAX; idx += blockDim.x) {
+    const int k = idx / WP, t = idx % WP;
+    double v = 0.0;
+    if (k < r && t < W) {
+      const uint8_t* src = qv_buf + qv_off[b] + k * W + t;
+      const uint32_t z = uint32_t(src[0]) | (uint32_t(src[vplane]) << 8) |
+                         (uint32_t(src[2 * vplane]) << 16) | (uint32_t(src[3 * vplane]) << 24);
+      v = double(unzigzag32(z));
+    }
+    Qv[t][k] = v;
+  }
+  __syncthreads();
+  const int64_t aplane = pad16(int64_t(M) * r);
+  const int64_t nxy = dims.nx * dims.ny;
+  T* base = F + fidx(dims, d.var, d.t0, d.z0, d.y0, d.x0);
+  const int64_t tstride = dims.nz * nxy;
+  const bool vec = d.vec != 0;
+  for (int ps0 = threadIdx.x * PPT; ps0 < it.np; ps0 += blockDim.x * PPT) {
+    const int valid = (it.np - ps0) < PPT ? (it.np - ps0) : PPT;
+    const bool full = vec && valid == PPT;
+    const int p = it.p0 + ps0;
+    // coefficients of the PPT points: zigzag codes gathered one byte plane at
+    // a time, then decoded in place
+    int32_t qa[RMAX][PPT];
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k) {
+      uint32_t za[PPT];
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) za[e] = 0u;
+      if (k < r) {
+        const uint8_t* src = qa_buf + qa_off[b] + int64_t(k) * M + p;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          uint32_t by[PPT];
+          if (full && PPT == 4) {
+            const uint32_t w4 = *reinterpret_cast<const uint32_t*>(src + j * aplane);
+#pragma unroll
+            for (int e = 0; e < PPT; ++e) by[e] = (w4 >> (8 * e)) & 0xFFu;
+          } else {
+#pragma unroll
+            for (int e = 0; e < PPT; ++e) by[e] = e < valid ? uint32_t(src[j * aplane + e]) : 0u;
+          }
+#pragma unroll
+          for (int e = 0; e < PPT; ++e) za[e] |= by[e] << (8 * j);
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) qa[k][e] = unzigzag32(za[e]);
+    }
+    int64_t off[PPT];
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) off[e] = point_off(p + (e < valid ? e : 0), d.px(), d.py(), dims.nx, nxy);
+    // the residual codes of every step, all loads issued before any use:
+    // byte e of cw[t] is the code of point p + e at step t
+    uint32_t cw[WP];
+#pragma unroll
+    for (int t = 0; t < WP; ++t) {
+      cw[t] = 0xFFFFFFFFu;
+      if (t < W) {
+        const uint8_t* cp = codes + code_off[b] + int64_t(t) * M + p;
+        if (full && PPT == 4) {
+          cw[t] = *reinterpret_cast<const uint32_t*>(cp);
+        } else {
+#pragma unroll
+          for (int e = 0; e < PPT; ++e)
+            if (e < valid) cw[t] = (cw[t] & ~(0xFFu << (8 * e))) | (uint32_t(cp[e]) << (8 * e));
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < WP; ++t) {
+      if (t >= W) continue;
+      uint32_t cd[PPT];
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) cd[e] = (cw[t] >> (8 * e)) & 0xFFu;
+      T outv[PPT];
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) {
+        double S = 0.0;
+#pragma unroll
+        for (int k = 0; k < RMAX; ++k)
+          if (k < r) S = fma(Qv[t][k], double(qa[k][e]), S);
+        // escaped points get the lattice value with q = 0 here; the escape
+        // scatter that follows overwrites them
+        const uint32_t code = cd[e] == kEscCode ? 0u : cd[e];
+        const int32_t q = int32_t(code >> 1) ^ -int32_t(code & 1);
+        outv[e] = T((S + double(q) * 131072.0) * K.c);
+      }
+      T* row = base + int64_t(t) * tstride;
+      if (full) {
+        if constexpr (sizeof(T) == 4 && PPT == 4) {
+          *reinterpret_cast<float4*>(row + off[0]) = make_float4(outv[0], outv[1], outv[2], outv[3]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < PPT; ++e) row[off[0] + e] = outv[e];
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < PPT; ++e)
+          if (e < valid) row[off[e]] = outv[e];
+      }
+    }
+  }
+}
+
+template <int WP, typename T, int PPT, bool SMALL>
+void encode_class(int rc, const dim3& g, hipStream_t s, const T* F, const Dims& dims,
+                         const BlockDesc* desc, const Item* items, const int32_t* list, const uint8_t* rank,
+                         const double* basis, const int64_t* qv_off, const int64_t* qa_off,
+                         const int64_t* code_off, const VarConst* vc, uint8_t* qv, uint8_t* qa,
+                         uint8_t* codes, float* coef, EscOut esc, const EncodeWork& work) {
+  const dim3 bl{256};
+#define DLS_ENC(R)                                                                                          \
+  do {                                                                                                      \
+    if (work.dcount)                                                                                        \
+      hipLaunchKernelGGL((k_encode<WP, T, PPT, R, true, SMALL>), g, bl, 0, s, F, dims, desc, items, list,  \
+                         rank, basis, qv_off, qa_off, code_off, vc, qv, qa, codes, coef, esc, work);        \
+    else                                                                                                    \
+      hipLaunchKernelGGL((k_encode<WP, T, PPT, R, false, SMALL>), g, bl, 0, s, F, dims, desc, items, list, \
+                         rank, basis, qv_off, qa_off, code_off, vc, qv, qa, codes, coef, esc, work);        \
+  } while (0)
+  switch (rc) {
+    case 0: DLS_ENC(1); break;
+    case 1: DLS_ENC(2); break;
+    case 2: DLS_ENC(4); break;
+    case 3: DLS_ENC(8); break;
+    case 4: DLS_ENC(16); break;
+    default:
+      if constexpr (WP == 32) DLS_ENC(32);
+      break;
+  }
+#undef DLS_ENC
+}
+
+// bl: threads per slice (one workgroup each); 64 for the small-slice classes
+template <int WP, typename T, int RMAX>
+void decode_launch(const dim3& g, const dim3& bl, hipStream_t s, void* F, const Dims& dims,
+                          const BlockDesc* desc, const Item* items, const int32_t* list, const uint8_t* rank,
+                          const int64_t* qv_off, const int64_t* qa_off, const int64_t* code_off, const VarConst* vc,
+                          const uint8_t* qv, const uint8_t* qa, const uint8_t* codes) {
+  hipLaunchKernelGGL((k_decode<WP, T, RMAX>), g, bl, 0, s, (T*)F, dims, desc, items, list, rank, qv_off, qa_off,
+                     code_off, vc, qv, qa, codes);
+}
+
+}  // namespace
+
+#if DLS_CODEC_PART == 0
+#define DLS_CODEC_SMALL false
+#define DLS_CODEC_ENTRY encode_large
+#elif DLS_CODEC_PART == 1
+#define DLS_CODEC_SMALL true
+#define DLS_CODEC_ENTRY encode_small
+#endif
+
+#if DLS_CODEC_PART == 0 || DLS_CODEC_PART == 1
+hipError_t DLS_CODEC_FN(DLS_CODEC_ENTRY)(int rc, const dim3& g, hipStream_t s, const void* F, const Dims& dims,
+                                         const BlockDesc* desc, const Item* items, const int32_t* list,
+                                         const uint8_t* rank, const double* basis, const int64_t* qv_off,
+                                         const int64_t* qa_off, const int64_t* code_off, const VarConst* vc,
+                                         uint8_t* qv, uint8_t* qa, uint8_t* codes, float* coef, EscOut esc,
+                                         const EncodeWork& work) {
+  using T = DLS_CODEC_T;
+  constexpr int WP = DLS_CODEC_WP, PPT = DLS_CODEC_PPT;
+  encode_class<WP, T, PPT, DLS_CODEC_SMALL>(rc, g, s, (const T*)F, dims, desc, items, list, rank, basis, qv_off,
+                                            qa_off, code_off, vc, qv, qa, codes, coef, esc, work);
+  return hipGetLastError();
+}
+#else
+hipError_t DLS_CODEC_FN(decode_part)(int rc, const dim3& g, const dim3& bl, hipStream_t s, void* F,
+                                     const Dims& dims, const BlockDesc* desc, const Item* items,
+                                     const int32_t* list, const uint8_t* rank, const int64_t* qv_off,
+                                     const int64_t* qa_off, const int64_t* code_off, const VarConst* vc,
+                                     const uint8_t* qv, const uint8_t* qa, const uint8_t* codes) {
+  using T = DLS_CODEC_T;
+  constexpr int WP = DLS_CODEC_WP;
+#define DLS_DEC(R) decode_launch<WP, T, R>(g, bl, s, F, dims, desc, items, list, rank, qv_off, qa_off, code_off, vc, qv, qa, codes)
+  switch (rc) {
+    case 0: DLS_DEC(1); break;
+    case 1: DLS_DEC(2); break;
+    case 2: DLS_DEC(4); break;
+    case 3: DLS_DEC(8); break;
+    case 4: DLS_DEC(16); break;
+    default: DLS_DEC(WP); break;  // rc < 0 (every rank) or the r <= 32 class
+  }
+#undef DLS_DEC
+  return hipGetLastError();
+}
+#endif
+
+}  // namespace dls

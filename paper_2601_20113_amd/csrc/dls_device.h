@@ -3,7 +3,23 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "dls_internal.h"
+
 namespace dls {
+
+__device__ __forceinline__ int64_t fidx(const Dims& d, int var, int t, int z, int y, int x) {
+  return (((int64_t(var) * d.nt + t) * d.nz + z) * d.ny + y) * d.nx + x;
+}
+
+// Offset of slice point p (row-major over the patch, x fastest) from the
+// patch origin in the field.
+__device__ __forceinline__ int64_t point_off(int p, int px, int py, int64_t nx, int64_t nxy) {
+  int rho = p / px;
+  int i = p - rho * px;
+  int k = rho / py;
+  int j = rho - k * py;
+  return int64_t(k) * nxy + int64_t(j) * nx + i;
+}
 
 __device__ __forceinline__ int rr_player(int pos, int step, int n) {
   return pos == 0 ? 0 : ((pos - 1 + step) % (n - 1)) + 1;

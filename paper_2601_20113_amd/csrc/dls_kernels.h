@@ -50,6 +50,29 @@ constexpr size_t kCounterBytes = kTotalsAt + 16;
 // largest slice (points) the small-slice encode takes: its team of lanes x PPT
 int encode_small_limit(int wp, int dtype);
 
+// Per-(padded window, element type) entry points of the encode / decode
+// kernels (dls_codec.hip, compiled once per pair and part): one rank class of
+// the large-slice or the small-slice encode, one rank class of the decode
+// (rc < 0: every rank).
+#define DLS_CODEC_ENC_DECL(NAME)                                                                                 \
+  hipError_t NAME(int rc, const dim3& g, hipStream_t s, const void* F, const Dims& dims, const BlockDesc* desc,  \
+                  const Item* items, const int32_t* list, const uint8_t* rank, const double* basis,            \
+                  const int64_t* qv_off, const int64_t* qa_off, const int64_t* code_off, const VarConst* vc,   \
+                  uint8_t* qv, uint8_t* qa, uint8_t* codes, float* coef, EscOut esc, const EncodeWork& work);
+#define DLS_CODEC_DECL(TAG)                                                                                       \
+  DLS_CODEC_ENC_DECL(encode_large_##TAG)                                                                          \
+  DLS_CODEC_ENC_DECL(encode_small_##TAG)                                                                          \
+  hipError_t decode_part_##TAG(int rc, const dim3& g, const dim3& bl, hipStream_t s, void* F, const Dims& dims,   \
+                               const BlockDesc* desc, const Item* items, const int32_t* list, const uint8_t* rank, \
+                               const int64_t* qv_off, const int64_t* qa_off, const int64_t* code_off,           \
+                               const VarConst* vc, const uint8_t* qv, const uint8_t* qa, const uint8_t* codes);
+DLS_CODEC_DECL(w16_f32)
+DLS_CODEC_DECL(w16_f64)
+DLS_CODEC_DECL(w32_f32)
+DLS_CODEC_DECL(w32_f64)
+#undef DLS_CODEC_DECL
+#undef DLS_CODEC_ENC_DECL
+
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // totals[0] = qv_off[n-1] + qv_size[n-1], totals[1] likewise for qA
 hipError_t launch_totals(const int64_t* qv_off, const int64_t* qv_size, const int64_t* qa_off,

@@ -375,10 +375,69 @@ def pin_round_bf16():
     assert dls.encode_block(x, 1e-3, 1, np.float64).lam[0] > 10.0
 
 
+# -- hand-worked fixtures: input statistics, NRMSE, sign ties ---------------
+def _golden(name):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)) as fh:
+        return json.load(fh)
+
+
+def pin_moments_hand_case():
+    """The 16 statistics of a 4 x 2 block against values worked by hand
+    (golden moments_4x2.json), and the temporal autocorrelations and
+    log10(std / eps) of a random block against explicit loops over the
+    definitions."""
+    from oracle import learned
+    g = _golden("moments_4x2.json")
+    i = g["inputs"]
+    f = learned.moments(np.array(i["x"]), i["px"], i["py"], i["pz"], i["eps"])
+    assert np.allclose(f, g["expected"]["f"], rtol=0, atol=1e-12), f
+    rng = np.random.default_rng(21)
+    w, m = 7, 12
+    x = rng.normal(size=(w, m)) + np.arange(w)[:, None] * 0.3
+    f = learned.moments(x, 4, 3, 1, 0.05)
+    vals = [float(v) for v in x.ravel()]
+    mu = sum(vals) / len(vals)
+    var = sum((v - mu) ** 2 for v in vals) / len(vals)
+    for lag, k in ((1, 10), (2, 11)):
+        acc, n = 0.0, 0
+        for t in range(w - lag):
+            for q in range(m):
+                acc += (x[t + lag, q] - mu) * (x[t, q] - mu)
+                n += 1
+        assert abs(f[k] - acc / n / var) <= 1e-12, (lag, f[k], acc / n / var)
+    assert abs(f[13] - math.log10(math.sqrt(var) / 0.05)) <= 1e-12
+
+
+def pin_nrmse_hand_case():
+    """NRMSE (Sec. 2.4) of the hand-worked 2 x 2 case (golden nrmse_2x2.json)
+    and of a field off by a constant fraction (closed form 100 * |s|)."""
+    g = _golden("nrmse_2x2.json")
+    got = dls.nrmse(np.array(g["inputs"]["u"]), np.array(g["inputs"]["u_hat"]))
+    assert abs(got - g["expected"]["nrmse"]) <= 1e-12, got
+    u = np.random.default_rng(3).normal(size=(2, 5, 1, 4, 3))
+    assert abs(dls.nrmse(u, u * (1 - 0.025)) - 2.5) <= 1e-12
+
+
+def pin_sign_tie():
+    """Canonical signs on an exact magnitude tie (golden sign_tie_2x2.json):
+    the lowest index among the largest magnitudes is made positive,
+    whichever sign the solver returned."""
+    g = _golden("sign_tie_2x2.json")
+    want = np.array(g["expected"]["V_sign"], dtype=float) / math.sqrt(2.0)
+    got = dls.canonical_signs(np.array(g["inputs"]["flipped"]))
+    assert np.array_equal(np.sign(got), np.sign(want)), got
+    lam, V = dls.eig_desc(np.array(g["inputs"]["G"]))
+    assert np.allclose(lam, g["expected"]["lam"], rtol=0, atol=1e-12)
+    assert np.array_equal(np.sign(V), np.array(g["expected"]["V_sign"])), V
+
+
 ALL_PINS = [
     pin_eigenvalues_vs_svd, pin_eigenvectors_orthonormal_and_residual,
     pin_eigenvalues_vs_jacobi, pin_rank_bruteforce, pin_exact_rank_data,
     pin_pointwise_bound, pin_escapes_rare_on_smooth_data, pin_escape_threshold, pin_lattice_one_rounding,
     pin_hand_worked_rank_one, pin_special_blocks, pin_gradient_and_percentile,
-    pin_adaptive_plan, pin_container_round_trip, pin_round_bf16,
+    pin_adaptive_plan, pin_container_round_trip, pin_round_bf16, pin_moments_hand_case,
+    pin_nrmse_hand_case, pin_sign_tie,
 ]

@@ -14,9 +14,23 @@ import pytest
 
 sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
 import oracle_pins as P  # noqa: E402
-from oracle import dls  # noqa: E402
+from oracle import dls, learned  # noqa: E402
 
+MODULES = {"dls": dls, "learned": learned}
+
+# (function, original text, planted mistake); functions of oracle.learned are
+# prefixed "learned."
 MUTATIONS = [
+    ("learned.moments", "f[11] = float(np.mean((x[2:] - mu) * (x[:-2] - mu))) / var",
+     "f[11] = float(np.mean((x[1:] - mu) * (x[:-1] - mu))) / var"),
+    ("learned.moments", "f[13] = math.log10(max(sd / eps, 1e-15))", "f[13] = math.log10(max(var / eps, 1e-15))"),
+    ("learned.moments", "f[10] = float(np.mean((x[1:] - mu) * (x[:-1] - mu))) / var",
+     "f[10] = float(np.mean((x[1:] - mu) * (x[:-1] - mu))) / sd"),
+    ("nrmse", "return 100.0 * float(np.sqrt(np.sum(d * d)) / np.sqrt(np.sum(a * a)))",
+     "return 100.0 * float(np.sum(d * d) / np.sum(a * a))"),
+    ("nrmse", "d = a - uh.astype(np.float64)", "d = a - uh.astype(np.float32)"),
+    ("canonical_signs", "i = int(np.argmax(np.abs(V[:, k])))",
+     "i = V.shape[0] - 1 - int(np.argmax(np.abs(V[::-1, k])))"),
     ("tail_energies", "t[r] = t[r + 1] + lam[r]", "t[r] = t[r + 1] + lam[min(r + 1, lam.size - 1)]"),
     ("choose_rank", "if tail[r] <= tau:", "if tail[r - 1] <= tau:"),
     ("encode_block", "code = encode_with_basis(xs, eps, V[:, :r], lam, tau, dtype)",
@@ -40,19 +54,21 @@ MUTATIONS = [
 ]
 
 
-def _mutate(name, old, new):
-    fn = getattr(dls, name)
+def _mutate(qual, old, new):
+    mod, name = qual.split(".") if "." in qual else ("dls", qual)
+    module = MODULES[mod]
+    fn = getattr(module, name)
     src = textwrap.dedent(inspect.getsource(fn))
-    assert old in src, (name, old)
-    ns = dict(vars(dls))
+    assert old in src, (qual, old)
+    ns = dict(vars(module))
     exec(compile(src.replace(old, new), "<mutant>", "exec"), ns)
-    return fn, ns[name]
+    return module, name, ns[name]
 
 
 @pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] + ":" + m[2][:30] for m in MUTATIONS])
 def test_mutation_is_caught(name, old, new, monkeypatch):
-    orig, mutant = _mutate(name, old, new)
-    monkeypatch.setattr(dls, name, mutant)
+    module, fname, mutant = _mutate(name, old, new)
+    monkeypatch.setattr(module, fname, mutant)
     # functions that call the mutated one resolve it through the module globals
     caught = []
     for pin in P.ALL_PINS:

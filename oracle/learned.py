@@ -290,7 +290,7 @@ RETRY_ITERS = 2   # subspace iterations added by the second attempt
 
 
 def encode_block_learned(xs: np.ndarray, eps: float, rcap: int, dtype, rhat: int, V0: np.ndarray,
-                         iters: int = 2):
+                         iters: int = 2, bf16_gram: bool = False):
     """encode_block with the warm-started eigensolve.
 
     V0 holds the network's starting columns (W x 16, or at least as many
@@ -299,14 +299,17 @@ def encode_block_learned(xs: np.ndarray, eps: float, rcap: int, dtype, rhat: int
     min(rhat + RETRY_EXTRA, WARM_MAX, cap) columns `iters + RETRY_ITERS`
     times (only when that is more columns).  An attempt with more than
     WARM_MAX columns is not made.  If no attempt is accepted the block takes
-    the plain eigensolve.  Returns (BlockCode, accepted)."""
+    the plain eigensolve.  With bf16_gram the Gram matrix is formed from the
+    bfloat16-rounded snapshots, as in dls.encode_block (mixed precision: the
+    acceptance test then sees that Gram).  Returns (BlockCode, accepted)."""
     wb, m = xs.shape
     x = xs.astype(np.float64)
     if not np.all(np.isfinite(x)):
         return dls._raw_block(xs), False
     if m > WARM_MAX_POINTS:
-        return dls.encode_block(xs, eps, rcap, dtype), False
-    G = x @ x.T
+        return dls.encode_block(xs, eps, rcap, dtype, bf16_gram), False
+    xg = dls.round_bf16(x) if bf16_gram else x
+    G = xg @ xg.T
     tau = dls.KAPPA * eps * eps * m * wb
     cap = min(rcap, wb, m)
     rhat = max(1, min(rhat, cap))
@@ -320,4 +323,4 @@ def encode_block_learned(xs: np.ndarray, eps: float, rcap: int, dtype, rhat: int
         ok, r, th, Z = warm_start_eig(G, V0[:wb, :k], tau, it)
         if ok:
             return dls.encode_with_basis(xs, eps, Z[:, :r], np.maximum(th[:r], 0.0), tau, dtype), True
-    return dls.encode_block(xs, eps, rcap, dtype), False
+    return dls.encode_block(xs, eps, rcap, dtype, bf16_gram), False

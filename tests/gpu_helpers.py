@@ -76,3 +76,21 @@ def coef_rel_err(A_gpu, V_gpu, A_or, V_or) -> float:
     s[s == 0] = 1.0
     d = A_gpu.astype(np.float64) * s[None, :] - A_or
     return float(np.linalg.norm(d) / max(np.linalg.norm(A_or), 1e-300))
+
+
+def projector_unique(lam: np.ndarray, r: int, limit: float = 1e-6) -> bool:
+    """Reading R5: the rank-r subspace (and with it V_r V_r^T X) is unique
+    when the relative gap (lam_r - lam_{r+1}) / lam_1 at r is at least 1e-6;
+    below that several results are correct and only the bound judges."""
+    lam = np.maximum(np.asarray(lam, dtype=np.float64), 0.0)
+    nxt = lam[r] if r < lam.size else 0.0
+    return (lam[r - 1] - nxt) >= limit * max(lam[0], 1e-300)
+
+
+def projector_rel_err(A_gpu, V_gpu, A_or, V_or) -> float:
+    """||V_g A_g^T - V_o A_o^T||_F / ||V_o A_o^T||_F: the rank-r reconstructions
+    before quantization (unique when the kept and discarded spectra are
+    separated, whatever the basis inside the kept subspace)."""
+    Pg = V_gpu.astype(np.float64) @ A_gpu.astype(np.float64).T
+    Po = V_or @ A_or.T
+    return float(np.linalg.norm(Pg - Po) / max(np.linalg.norm(Po), 1e-300))

@@ -1,11 +1,14 @@
-"""The device-side decode (dls_decode) against the stream decoder.
+"""The device-side decode (dls_decode) against the oracle's decoder.
 
 dls_decode reconstructs the last encode's field straight from the context's
 device payload.  On every parity case, on blocks with escapes and raw
 blocks, and with the escape-heavy tiny bound it must give bitwise the
-values dls_decompress gives for the stream dls_finalize writes (which the
-parity tests tie to the oracle's decoder), and hold the bound.
+values the FP64 oracle's decoder (Alg. 2, Eq. (7)) computes from the stream
+dls_finalize writes for the same encode, bitwise the values dls_decompress
+gives for that stream, and hold the bound.  It refuses an output buffer
+smaller than the encoded field.
 """
+import ctypes
 import os
 import sys
 
@@ -32,7 +35,10 @@ def _device_vs_stream(f, p):
     enc.decode(out)
     torch.cuda.synchronize()
     got = out.cpu().numpy()
-    ref = dls.decompress(enc.finalize()).cpu().numpy()
+    stream = enc.finalize()
+    ref_or = odls.decompress(stream)
+    assert np.array_equal(got.view(np.uint8), ref_or.view(np.uint8))
+    ref = dls.decompress(stream).cpu().numpy()
     assert np.array_equal(got.view(np.uint8), ref.view(np.uint8))
     return got
 
@@ -70,3 +76,17 @@ def test_device_decode_requires_a_result():
     out = torch.empty(16, device="cuda")
     with pytest.raises(dls.DlsError):
         enc.decode(out)
+
+
+def test_device_decode_refuses_a_short_buffer():
+    """Through the C ABI: an output byte count below the encoded field's size
+    is rejected with DLS_EINVAL before any device work."""
+    f, p = _case("c1_64x64x32_f64")
+    enc = dls.Encoder()
+    enc.encode(torch.from_numpy(f).cuda(), H.to_lib_params(p))
+    small = torch.zeros(f.size - 1, dtype=torch.float64, device="cuda")
+    st = dls.lib().dls_decode(enc._h, ctypes.c_void_p(small.data_ptr()), small.numel() * 8, None)
+    assert st == dls.DLS_EINVAL
+    assert bool((small == 0).all())
+    with pytest.raises(ValueError):
+        enc.decode(small)

@@ -226,3 +226,16 @@ def test_large_blocks_take_the_plain_eigensolve():
     code, acc = L.encode_block_learned(x, 1e-2, 16, np.float64, 2, V0)
     plain = dls.encode_block(x, 1e-2, 16, np.float64)
     assert not acc and code.r == plain.r and np.array_equal(code.qA, plain.qA)
+
+
+def test_bf16_gram_mode_forms_the_gram_from_rounded_values():
+    """With bf16_gram the warm start sees the Gram of the bfloat16-rounded
+    snapshots, as the plain oracle's mixed-precision mode does: for the
+    1 x 2 block [1 + 2^-8, 3] that Gram is 1 + 9 = 10 exactly (1 + 2^-8 is a
+    tie that rounds to the even 1), while the full-precision one is larger."""
+    x = np.array([[1 + 2.0 ** -8, 3.0]])
+    V0 = np.ones((1, 16))
+    code, acc = L.encode_block_learned(x, 1e-3, 1, np.float64, 1, V0, 2, bf16_gram=True)
+    assert acc and code.r == 1 and code.lam[0] == 10.0
+    code, acc = L.encode_block_learned(x, 1e-3, 1, np.float64, 1, V0, 2)
+    assert acc and code.lam[0] > 10.0

@@ -159,6 +159,19 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* p,
 dls_status dls_range(const void* d_field, int32_t nvars, int64_t values_per_var, int32_t dtype,
                      void* stream, double* min_out, double* max_out);
 
+/* dls_range without any device allocation, for callers that cannot
+ * allocate (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same arguments and results as dls_range, bitwise.
+ * Its partial minima / maxima live in a fixed device array of the library
+ * (about 1 MiB, one copy per GPU, held until the process ends) instead of
+ * buffers allocated per call; the device is the current one.  At most 64
+ * variables (DLS_EINVAL above that, nothing launched).  Calls on one GPU
+ * share that array: calls that overlap on one GPU (other host threads, or
+ * work still queued on another stream) race, so serialise them.  Errors:
+ * DLS_EINVAL, DLS_EDEVICE. */
+dls_status dls_range_noalloc(const void* d_field, int32_t nvars, int64_t values_per_var, int32_t dtype,
+                             void* stream, double* min_out, double* max_out);
+
 /* Diagnostics of the last dls_encode on ctx (pointers into ctx memory). */
 dls_status dls_encode_info_get(const dls_ctx* ctx, dls_encode_info* info);
 

@@ -35,7 +35,7 @@ EXPORTS = ["dls_ctx_create", "dls_ctx_destroy", "dls_encode", "dls_encode_info_g
            "dls_finalize", "dls_compress", "dls_query", "dls_decompress", "dls_stats",
            "dls_free", "dls_last_error", "dls_model_create", "dls_model_destroy", "dls_model_set",
            "dls_model_get", "dls_model_forward", "dls_model_grad", "dls_model_train_step",
-           "dls_features", "dls_ctx_set_model", "dls_decode"]
+           "dls_features", "dls_ctx_set_model", "dls_decode", "dls_range_noalloc"]
 
 
 class DlsError(RuntimeError):
@@ -100,6 +100,7 @@ def lib():
         L.dls_stats.argtypes = [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(_StreamStats)]
         L.dls_range.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
                                 ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        L.dls_range_noalloc.argtypes = L.dls_range.argtypes
         vp = ctypes.c_void_p
         L.dls_model_create.argtypes = [ctypes.c_int, c_void_pp]
         L.dls_model_destroy.argtypes = [vp]
@@ -120,7 +121,7 @@ def lib():
         for name in ("dls_model_create", "dls_model_set", "dls_model_get", "dls_model_forward", "dls_model_grad",
                      "dls_model_train_step", "dls_features", "dls_ctx_set_model", "dls_decode",
                      "dls_ctx_create", "dls_encode", "dls_encode_info_get", "dls_finalize", "dls_range",
-                     "dls_compress", "dls_query", "dls_decompress", "dls_stats"):
+                     "dls_compress", "dls_query", "dls_decompress", "dls_stats", "dls_range_noalloc"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib

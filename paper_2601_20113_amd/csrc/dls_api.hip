@@ -819,13 +819,36 @@ dls_status dls_range(const void* d_field, int32_t nvars, int64_t values_per_var,
   if (nvars < 1 || values_per_var < 1) return fail(DLS_EINVAL, "empty field");
   if (dtype != DLS_F32 && dtype != DLS_F64) return fail(DLS_EINVAL, "bad dtype");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int nparts = int(std::min<int64_t>(1024, (values_per_var + 255) / 256));
+  const int nparts = int(std::min<int64_t>(kRangeParts, (values_per_var + 255) / 256));
   DevBuf part, out;
   HIP_TRY(part.ensure(size_t(nvars) * nparts * 2 * sizeof(double)));
   HIP_TRY(out.ensure(size_t(nvars) * 2 * sizeof(double)));
   HIP_TRY(launch_range(dtype, d_field, nvars, values_per_var, part.as<double>(), nparts, out.as<double>(), s));
   std::vector<double> h(2 * size_t(nvars));
   HIP_TRY(hipMemcpyAsync(h.data(), out.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int v = 0; v < nvars; ++v) {
+    min_out[v] = h[2 * v];
+    max_out[v] = h[2 * v + 1];
+  }
+  return DLS_OK;
+}
+
+dls_status dls_range_noalloc(const void* d_field, int32_t nvars, int64_t values_per_var, int32_t dtype,
+                             void* stream, double* min_out, double* max_out) {
+  if (d_field == nullptr || min_out == nullptr || max_out == nullptr) return fail(DLS_EINVAL, "NULL argument");
+  if (nvars < 1 || values_per_var < 1) return fail(DLS_EINVAL, "empty field");
+  if (nvars > kRangeNoAllocVars) return fail(DLS_EINVAL, "dls_range_noalloc takes at most 64 variables");
+  if (dtype != DLS_F32 && dtype != DLS_F64) return fail(DLS_EINVAL, "bad dtype");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  double* sp = nullptr;  // this device's copy of the library's fixed range scratch
+  HIP_TRY(range_scratch(dev, &sp));
+  HIP_TRY(launch_range_noalloc(sp, dtype, d_field, nvars, values_per_var, s));
+  double h[2 * kRangeNoAllocVars];
+  HIP_TRY(hipMemcpyAsync(h, sp + int64_t(nvars) * 2 * kRangeParts, size_t(2 * nvars) * sizeof(double),
+                         hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   for (int v = 0; v < nvars; ++v) {
     min_out[v] = h[2 * v];

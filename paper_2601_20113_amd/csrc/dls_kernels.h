@@ -145,6 +145,14 @@ hipError_t launch_warmstart(const double* gpart, const int32_t* item_start, cons
                             uint8_t* rank, double* lam, double* basis, int64_t* qv_size, int64_t* qa_size,
                             uint8_t* reject, unsigned long long* counters, hipStream_t s);
 hipError_t launch_scan(const int64_t* in, int64_t n, int64_t* out, int64_t* tmp, hipStream_t s);
+// Allocation-free range: the partials live in a fixed device array (one per
+// GPU) whose address range_scratch() returns for the current device;
+// results at scratch_ptr + nvars * 2 * 1024 as (min, max) per variable.
+constexpr int kRangeNoAllocVars = 64;
+constexpr int kRangeParts = 1024;  // partials per variable (fewer for short fields)
+hipError_t range_scratch(int device, double** scratch_ptr);
+hipError_t launch_range_noalloc(double* scratch_ptr, int dtype, const void* F, int nvars, int64_t n_per_var,
+                                hipStream_t s);
 hipError_t launch_range(int dtype, const void* F, int nvars, int64_t n_per_var, double* part, int nparts,
                         double* out, hipStream_t s);
 hipError_t launch_classify(const Item* items, int64_t nitems, const uint8_t* rank, int small_limit,

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "dls_device.h"
 #include "dls_kernels.h"
@@ -651,6 +652,42 @@ hipError_t launch_range(int dtype, const void* F, int nvars, int64_t n_per_var, 
   else hipLaunchKernelGGL(k_range_partial<double>, g, bl, 0, s, (const double*)F, n_per_var, part);
   hipLaunchKernelGGL(k_range_final, dim3{unsigned(nvars)}, bl, 0, s, (const double*)part, nparts, out);
   return hipGetLastError();
+}
+
+// Fixed device scratch of the allocation-free range (dls_range_noalloc):
+// the per-variable partial minima / maxima (kRangeParts per variable) and
+// the folded results, for at most kRangeNoAllocVars variables.  One copy per
+// GPU, kept for the life of the process; every launch writes every slot it
+// later reads, so nothing needs clearing.  Host code uses the address
+// returned by range_scratch(), never this name.
+static __device__ __align__(256) double scratch[kRangeNoAllocVars * (2 * kRangeParts + 2)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t range_scratch(int device, double** ptr) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device] == nullptr) {
+    void* p = nullptr;
+    // the caller has made `device` current: this is its copy of the array
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<double*>(p);
+  }
+  *ptr = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
+hipError_t launch_range_noalloc(double* scratch_ptr, int dtype, const void* F, int nvars, int64_t n_per_var,
+                                hipStream_t s) {
+  const int nparts = int(std::min<int64_t>(kRangeParts, (n_per_var + 255) / 256));
+  double* part = scratch_ptr;
+  double* out = scratch_ptr + int64_t(nvars) * 2 * kRangeParts;
+  return launch_range(dtype, F, nvars, n_per_var, part, nparts, out, s);
 }
 
 // Bucket the work items by the rank class of their block (one list per class,

@@ -72,15 +72,25 @@ enum {
   DLS_LEARNED = 2,   /* warm-started eigensolve with the model attached by
                         dls_ctx_set_model (window <= 16); blocks whose
                         prediction fails the rank test fall back to Jacobi */
-  DLS_PERSISTENT = 4 /* batched launch: no host round trip between the
-                        eigensolve and the encode.  The encode kernels walk
-                        the device-written rank-class lists with a fixed
-                        grid, into qV/qA buffers sized by earlier calls;
-                        when they do not fit, the library grows them and
-                        encodes again host-driven.  Applied to plans of up
-                        to 65536 slices (launch-bound sizes; larger plans
-                        keep the host-driven launch, faster there).  Output
-                        identical to the host-driven launch. */
+  DLS_PERSISTENT = 4 /* batched launch.  Plans whose blocks all span at
+                        least 1024 points (FP32, window <= 16): one fused
+                        persistent launch reads every slice once into
+                        registers, forms its Gram, and the slice that
+                        completes a block solves it at rank 1 when the
+                        exact discarded energy of a power-iteration basis
+                        meets the tolerance (Sec. 2.4 Eq. (4)); the block
+                        is then encoded from registers, without a second
+                        read of the field.  Blocks that need a higher rank
+                        take the Jacobi eigensolve and a second read.
+                        Other plans of up to 65536 slices: no host round
+                        trip between the eigensolve and the encode (the
+                        encode kernels walk device-written rank-class
+                        lists); larger plans keep the host-driven launch.
+                        Payload buffers are sized by earlier calls; when
+                        they do not fit, the library grows them and encodes
+                        the call again two-pass.  The stream decodes to
+                        the same guarantees; its rank-1 bases come from the
+                        power iteration instead of Jacobi. */
 };
 
 typedef struct dls_params {
@@ -130,7 +140,16 @@ typedef struct dls_encode_info {
                                stream: plan (adaptive: gradient, percentile,
                                node sums, tree walk, upload), Gram,
                                eigensolve + rank, offset scan + rank classes,
-                               projection / quantization / residual codes   */
+                               projection / quantization / residual codes;
+                               in the fused single pass: the fused kernel,
+                               Jacobi of the deferred blocks, their payload
+                               regions and slice lists, their encode        */
+  int64_t nfast_accept;     /* fused single pass: blocks solved at rank 1 and
+                               encoded in the same pass                      */
+  int64_t ndeferred;        /* fused single pass: blocks left to the Jacobi
+                               eigensolve and a second read                 */
+  int32_t launch_mode;      /* 0 host-driven, 1 device-driven, 2 fused single
+                               pass (see DLS_PERSISTENT)                     */
 } dls_encode_info;
 
 typedef struct dls_ctx dls_ctx;

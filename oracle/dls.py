@@ -372,6 +372,74 @@ def encode_block(xs: np.ndarray, eps: float, rcap: int, dtype, bf16_gram: bool =
     return code
 
 
+FAST_ITERS = 6        # power steps of the rank-1 basis after its start column
+SKETCH_POINTS = 1024  # the sketch is the block's first whole x-rows, at most this many points
+
+
+def leading_vector(G: np.ndarray, iters: int = FAST_ITERS):
+    """The rank-1 basis of the single-pass form (reading R28): q starts as the
+    Gram column of the largest diagonal entry (the lowest index on ties;
+    e_i itself when that column is zero), normalised, and takes `iters`
+    power steps q = G q / ||G q||.  Returned with the canonical sign, or
+    None when G is not finite."""
+    w = G.shape[0]
+    if not np.all(np.isfinite(G)):
+        return None
+    i = int(np.argmax(np.diag(G)))
+    q = G[:, i].astype(np.float64).copy()
+    n = math.sqrt(float(q @ q))
+    if n > 0.0:
+        q = q / n
+    else:
+        q = np.zeros(w)
+        q[i] = 1.0
+    for _ in range(iters):
+        y = G @ q
+        n = math.sqrt(float(y @ y))
+        if n > 0.0:
+            q = y / n
+    return canonical_signs(q[:, None])[:, 0]
+
+
+def rank_one_verify(G: np.ndarray, q: np.ndarray, tau: float):
+    """Exact test of a unit vector q as the block's basis: theta = q^T G q is
+    the energy it keeps, so trace(G) - theta = ||X - q q^T X||_F^2 is its
+    discarded energy; accepted when that is <= tau (the local tolerance of
+    Sec. 2.4 Eq. (4), '<=' as in Alg. 1).  Since lambda_1 >= theta, an
+    accepted block has tail_1 <= tau too: rank 1 is what the rank rule
+    chooses.  Returns (accepted, theta)."""
+    if q is None or not np.all(np.isfinite(G)):
+        return False, 0.0
+    theta = float(q @ (G @ q))
+    return float(np.trace(G)) - theta <= tau, theta
+
+
+def sketch_points(m: int, px: int) -> int:
+    """Points of the sketch: the first floor(SKETCH_POINTS / px) x-rows of
+    the block (p order), all of it when smaller."""
+    return min(m, max(1, SKETCH_POINTS // px) * px)
+
+
+def encode_block_sketch(xs: np.ndarray, eps: float, rcap: int, dtype, px: int, bf16_gram: bool = False):
+    """encode_block as the single-pass form does it (reading R28): the rank-1
+    basis q of the sketch's Gram (the block's first x-rows), verified on the
+    whole block's Gram; a block it does not pass takes the plain eigensolve.
+    Returns (BlockCode, accepted)."""
+    wb, m = xs.shape
+    x = xs.astype(np.float64)
+    if not np.all(np.isfinite(x)):
+        return _raw_block(xs), False
+    xg = round_bf16(x) if bf16_gram else x
+    G = xg @ xg.T
+    s = sketch_points(m, px)
+    q = leading_vector(xg[:, :s] @ xg[:, :s].T)
+    tau = KAPPA * eps * eps * m * wb
+    ok, theta = rank_one_verify(G, q, tau)
+    if ok:
+        return encode_with_basis(xs, eps, q[:, None], np.array([max(theta, 0.0)]), tau, dtype), True
+    return encode_block(xs, eps, rcap, dtype, bf16_gram), False
+
+
 def encode_with_basis(xs: np.ndarray, eps: float, Vr: np.ndarray, lam: np.ndarray, tau: float,
                       dtype) -> BlockCode:
     """Steps 6-9 for a chosen orthonormal basis V_r (W_b x r)."""

@@ -63,7 +63,8 @@ class _EncodeInfo(ctypes.Structure):
                 ("d_qa_off", ctypes.c_void_p), ("d_code_off", ctypes.c_void_p),
                 ("d_coef", ctypes.c_void_p), ("nwarm_accept", ctypes.c_int64),
                 ("nwarm_reject", ctypes.c_int64), ("gpu_ms", ctypes.c_double),
-                ("stage_ms", ctypes.c_double * 5)]
+                ("stage_ms", ctypes.c_double * 5), ("nfast_accept", ctypes.c_int64),
+                ("ndeferred", ctypes.c_int64), ("launch_mode", ctypes.c_int32)]
 
 
 class _StreamStats(ctypes.Structure):

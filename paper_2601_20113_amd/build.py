@@ -26,6 +26,7 @@ HIP_SOURCES = ["dls_kernels.hip", "dls_plan.hip", "dls_learned.hip", "dls_api.hi
 CODEC_TYPES = [("w16_f32", 16, "float", 4), ("w16_f64", 16, "double", 2), ("w32_f32", 32, "float", 2),
                ("w32_f64", 32, "double", 2)]
 CODEC_PARTS = 3  # 0 large-slice encode, 1 small-slice encode, 2 decode
+FUSED_TAG = "w16_f32"  # part 3, the fused single-pass encode, exists for this pair only
 CXX_SOURCES = ["dls_format.cpp"]
 
 
@@ -48,7 +49,7 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(BUILD, src + ".o")
         jobs.append((obj, [HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]))
     for tag, wp, ty, ppt in CODEC_TYPES:
-        for part in range(CODEC_PARTS):
+        for part in range(CODEC_PARTS + (1 if tag == FUSED_TAG else 0)):
             obj = os.path.join(BUILD, "dls_codec_%s_%d.o" % (tag, part))
             defs = ["-DDLS_CODEC_TAG=" + tag, "-DDLS_CODEC_WP=%d" % wp, "-DDLS_CODEC_T=" + ty,
                     "-DDLS_CODEC_PPT=%d" % ppt, "-DDLS_CODEC_PART=%d" % part]

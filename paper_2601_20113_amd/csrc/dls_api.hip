@@ -245,6 +245,15 @@ struct dls_ctx {
   bool plan_valid = false;
   Plan plan;
   int64_t plan_warm_blocks = 0;  // blocks small enough for the warm start
+  int64_t plan_min_points = 0;   // smallest block of the plan (points)
+  int64_t plan_qv_r1 = 0, plan_qa_r1 = 0;  // payload bytes if every block had rank 1
+  bool r1_valid = false;         // r1_off holds the plan's static rank-1 payload offsets
+  DevBuf r1_off;                 // [nblocks] qV then [nblocks] qA offsets of the rank-1 payload
+  DevBuf fused;                  // fused-encode state: arrivals, verdicts, deferred list, counters
+  unsigned long long* hfused = nullptr;  // pinned host copy of the fused counters
+  int64_t nfast_accept = 0, ndeferred = 0;
+  int64_t nesc_slots = 0;        // escape list entries to read (dropped ones included)
+  int launch_mode = 0;           // 0 host-driven, 1 device-driven, 2 fused single pass
   bool split_valid = false;       // large / small slice lists of the plan
   int64_t split_nlarge = 0, split_nsmall = 0;
   DevBuf split_lists;
@@ -287,6 +296,7 @@ struct dls_ctx {
     plan_scratch_delete(plan_scratch);
     if (pinned) (void)hipHostFree(pinned);
     if (hcnt) (void)hipHostFree(hcnt);
+    if (hfused) (void)hipHostFree(hfused);
   }
 };
 
@@ -369,6 +379,145 @@ dls_status finish_encode(dls_ctx* ctx) {
 }
 }  // namespace
 
+namespace {
+// The single-pass encode (DLS_PERSISTENT on plans of large FP32 blocks,
+// W <= 16; reading R28): the Gram of every block's first slice gives a
+// rank-1 basis (k_sketch_basis); one launch (k_fused) reads every slice once,
+// encodes it with that basis, forms the slice's Gram partial, and the slice
+// that completes its block verifies the basis on the whole Gram.  Blocks it
+// does not verify take the Jacobi eigensolve and a device-driven encode that
+// reads them again.  On success *done is set; otherwise (payload buffers too
+// small, escape list full) the buffers are grown and the caller encodes the
+// call again two-pass.
+dls_status fused_encode(dls_ctx* ctx, const void* d_field, const Problem& p, const Dims& dims, hipStream_t s,
+                        bool* done) {
+  *done = false;
+  const Plan& pl = ctx->plan;
+  const int64_t nb = int64_t(pl.blocks.size()), ni = int64_t(pl.items.size());
+  unsigned long long* cnt = ctx->counters.as<unsigned long long>();
+  if (!ctx->r1_valid) {  // static rank-1 payload offsets of the plan
+    std::vector<int64_t> off(2 * size_t(nb));
+    int64_t v = 0, a = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+      off[b] = v;
+      off[nb + b] = a;
+      v += 4 * pad16(pl.blocks[b].w());
+      a += 4 * pad16(pl.blocks[b].m);
+    }
+    HIP_TRY(ctx->r1_off.ensure(off.size() * sizeof(int64_t)));
+    HIP_TRY(hipMemcpy(ctx->r1_off.p, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    ctx->r1_valid = true;
+  }
+  // state: state[nb], deferred[nb] (u32 each), ndeferred (u32, padded), counters (u64)
+  const size_t fbytes = 8 * size_t(nb) + 16 + kFusedNCounters * 8;
+  HIP_TRY(ctx->fused.ensure(fbytes));
+  uint8_t* fb = ctx->fused.as<uint8_t>();
+  FusedState fs{reinterpret_cast<unsigned int*>(fb), reinterpret_cast<int32_t*>(fb + 4 * nb),
+                reinterpret_cast<unsigned int*>(fb + 8 * nb), reinterpret_cast<unsigned long long*>(fb + 8 * nb + 16)};
+  if (ctx->hfused == nullptr) {
+    void* q = nullptr;
+    HIP_TRY(hipHostMalloc(&q, 16 + kFusedNCounters * 8, hipHostMallocDefault));
+    ctx->hfused = static_cast<unsigned long long*>(q);
+  }
+  // the rank-1 payload of every block is the least room needed
+  HIP_TRY(ctx->qv.ensure(size_t(ctx->plan_qv_r1) + 16));
+  HIP_TRY(ctx->qa.ensure(size_t(ctx->plan_qa_r1) + 16));
+  if (ctx->keep_coef) HIP_TRY(ctx->coef.ensure(ctx->qa.n));
+  HIP_TRY(launch_zero(fb, fbytes, s));
+  const int wp = p.wpad();
+  const bool bf16 = p.precision == DLS_PREC_BF16;
+  EscOut esc{cnt, ctx->esc_key.as<uint64_t>(), ctx->esc_val.as<uint64_t>(), ctx->esc_cap};
+  unsigned int* overflow = reinterpret_cast<unsigned int*>(reinterpret_cast<uint8_t*>(cnt) + kOverflowAt);
+  unsigned int* cls_count = reinterpret_cast<unsigned int*>(cnt + 4);
+  // the sketch: Gram partials of every block's first slice (item_start[b]
+  // is that slice), then its rank-1 basis
+  const GramSplit first{ctx->item_start.as<int32_t>(), nb, nullptr, 0};
+  HIP_TRY(launch_gram(wp, p.dtype, bf16, d_field, dims, ctx->desc.as<BlockDesc>(), ctx->items.as<Item>(), ni, &first,
+                      ctx->gram.as<double>(), s));
+  HIP_TRY(launch_sketch_basis(ctx->gram.as<double>(), ctx->item_start.as<int32_t>(), ctx->desc.as<BlockDesc>(), nb,
+                              ctx->r1_off.as<int64_t>(), ctx->rank.as<uint8_t>(), ctx->lam.as<double>(),
+                              ctx->basis.as<double>(), ctx->qv_size.as<int64_t>(), ctx->qa_size.as<int64_t>(),
+                              ctx->qv_off.as<int64_t>(), ctx->qa_off.as<int64_t>(), fs.state, s));
+  HIP_TRY(launch_fused(bf16, int(std::min<int64_t>(ni, INT32_MAX)), static_cast<const float*>(d_field), dims,
+                       ctx->desc.as<BlockDesc>(),
+                       ctx->items.as<Item>(), ni, ctx->vconst.as<VarConst>(), ctx->gram.as<double>(), fs.state,
+                       ctx->basis.as<double>(), ctx->qv_off.as<int64_t>(), ctx->qa_off.as<int64_t>(),
+                       ctx->code_off.as<int64_t>(), ctx->qv.as<uint8_t>(), ctx->qa.as<uint8_t>(),
+                       ctx->codes.as<uint8_t>(), ctx->keep_coef ? ctx->coef.as<float>() : nullptr, esc, s));
+  HIP_TRY(hipEventRecord(ctx->evs[0], s));
+  HIP_TRY(launch_verify(ctx->gram.as<double>(), ctx->item_start.as<int32_t>(), ctx->desc.as<BlockDesc>(), nb,
+                        ctx->eps_v.as<double>(), ctx->basis.as<double>(), ctx->lam.as<double>(), fs, s));
+  // deferred blocks: Jacobi, payload regions after the rank-1 ones, their
+  // slices encoded device-driven
+  HIP_TRY(launch_eigen(wp, ctx->gram.as<double>(), ctx->item_start.as<int32_t>(), ctx->desc.as<BlockDesc>(), nb,
+                       ctx->eps_v.as<double>(), p.r_max, ctx->rank.as<uint8_t>(), ctx->lam.as<double>(),
+                       ctx->basis.as<double>(), ctx->qv_size.as<int64_t>(), ctx->qa_size.as<int64_t>(), cnt + 1,
+                       fs.deferred, fs.ndeferred, s));
+  HIP_TRY(hipEventRecord(ctx->evs[1], s));
+  HIP_TRY(launch_alloc_deferred(fs.deferred, fs.ndeferred, nb, ctx->qv_size.as<int64_t>(), ctx->qa_size.as<int64_t>(),
+                                fs.counters, ctx->plan_qv_r1, ctx->plan_qa_r1, ctx->qv_off.as<int64_t>(),
+                                ctx->qa_off.as<int64_t>(), s));
+  HIP_TRY(launch_classify(ctx->items.as<Item>(), ni, ctx->rank.as<uint8_t>(), 0, cls_count,
+                          ctx->cls_lists.as<int32_t>(), s, fs.state));
+  HIP_TRY(hipEventRecord(ctx->evs[2], s));
+  HIP_TRY(hipEventRecord(ctx->evs[3], s));
+  for (int c = 0; c < kRankClasses; ++c) {
+    const EncodeWork work{cls_count + c, ni, int64_t(ctx->qv.n), int64_t(ctx->qa.n), overflow};
+    HIP_TRY(launch_encode(wp, p.dtype, c, d_field, dims, ctx->desc.as<BlockDesc>(), ctx->items.as<Item>(),
+                          ctx->cls_lists.as<int32_t>() + int64_t(c) * ni, work, ctx->rank.as<uint8_t>(),
+                          ctx->basis.as<double>(), ctx->qv_off.as<int64_t>(), ctx->qa_off.as<int64_t>(),
+                          ctx->code_off.as<int64_t>(), ctx->vconst.as<VarConst>(), ctx->qv.as<uint8_t>(),
+                          ctx->qa.as<uint8_t>(), ctx->codes.as<uint8_t>(),
+                          ctx->keep_coef ? ctx->coef.as<float>() : nullptr, esc, s));
+  }
+  HIP_TRY(launch_fix_escapes(ctx->esc_key.as<uint64_t>(), cnt, ctx->esc_cap, fs.state,
+                             fs.counters + kFusedDropped, s));
+  // rank-class lists of every slice, for the device decode of this result
+  HIP_TRY(launch_zero(cls_count, kEncodeClasses * sizeof(unsigned int), s));
+  HIP_TRY(launch_classify(ctx->items.as<Item>(), ni, ctx->rank.as<uint8_t>(), 0, cls_count,
+                          ctx->cls_lists.as<int32_t>(), s, nullptr));
+  HIP_TRY(hipEventRecord(ctx->ev1, s));
+  HIP_TRY(ctx->host_counters());
+  HIP_TRY(hipMemcpyAsync(ctx->hcnt, cnt, kCounterBytes, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(ctx->hfused, fb + 8 * nb, 16 + kFusedNCounters * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  unsigned long long hc[4];
+  unsigned int hov;
+  std::memcpy(hc, ctx->hcnt, sizeof(hc));
+  std::memcpy(&hov, ctx->hcnt + kOverflowAt, 4);
+  unsigned int ndef;
+  std::memcpy(&ndef, ctx->hfused, 4);
+  const unsigned long long* fc = ctx->hfused + 2;
+  ctx->nesc_slots = int64_t(hc[0]);
+  ctx->nesc = int64_t(hc[0] - fc[kFusedDropped]);
+  ctx->nraw = int64_t(hc[1]);
+  ctx->qv_bytes = ctx->plan_qv_r1 + int64_t(fc[kFusedQvCursor]);
+  ctx->qa_bytes = ctx->plan_qa_r1 + int64_t(fc[kFusedQaCursor]);
+  ctx->nfast_accept = int64_t(fc[kFusedAccepted]);
+  ctx->ndeferred = int64_t(ndef);
+  const bool fits = hov == 0 && hc[0] <= ctx->esc_cap && ctx->qv_bytes <= int64_t(ctx->qv.n) &&
+                    ctx->qa_bytes <= int64_t(ctx->qa.n);
+  if (fits) {
+    *done = true;
+    ctx->launch_mode = 2;
+    ctx->nwarm_accept = 0;  // no block of these plans is small enough for the warm start
+    ctx->nwarm_reject = (p.flags & DLS_LEARNED) ? nb : 0;
+    return DLS_OK;
+  }
+  // grow with headroom for later calls; the caller encodes this call two-pass
+  HIP_TRY(ctx->qv.grow(size_t(ctx->qv_bytes + ctx->qv_bytes / 4 + 16)));
+  HIP_TRY(ctx->qa.grow(size_t(ctx->qa_bytes + ctx->qa_bytes / 4 + 16)));
+  if (ctx->keep_coef) HIP_TRY(ctx->coef.grow(ctx->qa.n));
+  if (hc[0] > ctx->esc_cap) {
+    ctx->esc_cap = hc[0] + (hc[0] >> 3) + 1024;
+    HIP_TRY(ctx->esc_key.ensure(ctx->esc_cap * 8));
+    HIP_TRY(ctx->esc_val.ensure(ctx->esc_cap * 8));
+  }
+  HIP_TRY(launch_zero(cnt, kCounterBytes, s));
+  return DLS_OK;
+}
+}  // namespace
+
 extern "C" {
 
 const char* dls_last_error(void) { return g_err.c_str(); }
@@ -437,7 +586,15 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
     ctx->split_valid = false;
     ctx->feat_valid = false;
     ctx->plan_warm_blocks = 0;
-    for (const BlockDesc& d : ctx->plan.blocks) ctx->plan_warm_blocks += d.m <= kWarmMaxPoints ? 1 : 0;
+    ctx->r1_valid = false;
+    ctx->plan_min_points = ctx->plan.blocks.empty() ? 0 : INT64_MAX;
+    ctx->plan_qv_r1 = ctx->plan_qa_r1 = 0;
+    for (const BlockDesc& d : ctx->plan.blocks) {
+      ctx->plan_warm_blocks += d.m <= kWarmMaxPoints ? 1 : 0;
+      ctx->plan_min_points = std::min<int64_t>(ctx->plan_min_points, d.m);
+      ctx->plan_qv_r1 += 4 * pad16(d.w());
+      ctx->plan_qa_r1 += 4 * pad16(d.m);
+    }
     if (ctx->plan.blocks.size() >= (size_t(1) << 31)) return fail(DLS_EINVAL, "too many blocks");
     const Plan& pl = ctx->plan;
     HIP_TRY(ctx->desc.ensure(pl.blocks.size() * sizeof(BlockDesc)));
@@ -530,6 +687,17 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
   }
   const GramSplit split{ctx->split_lists.as<int32_t>(), ctx->split_nlarge,
                         ctx->split_lists.as<int32_t>() + ctx->split_nlarge, ctx->split_nsmall};
+  ctx->keep_coef = keep_coef != 0;
+  ctx->nfast_accept = ctx->ndeferred = 0;
+  ctx->launch_mode = 0;
+  // batched plans of large FP32 blocks (W <= 16): the fused single pass
+  if (batched && p.dtype == DLS_F32 && wp == 16 && ctx->plan_min_points >= kFusedMinPoints) {
+    bool done = false;
+    if (dls_status st = fused_encode(ctx, d_field, p, dims, s, &done)) return st;
+    if (done) return finish_encode(ctx);
+    ctx->nfast_accept = ctx->ndeferred = 0;  // this call is encoded again two-pass
+    HIP_TRY(hipEventRecord(ctx->ev0, s));
+  }
   HIP_TRY(launch_gram(wp, p.dtype, p.precision == DLS_PREC_BF16, d_field, dims, ctx->desc.as<BlockDesc>(),
                       ctx->items.as<Item>(), ni, batched ? &split : nullptr, ctx->gram.as<double>(), s));
   HIP_TRY(hipEventRecord(ctx->evs[0], s));
@@ -555,7 +723,6 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
   HIP_TRY(hipEventRecord(ctx->evs[2], s));
   unsigned int* overflow = reinterpret_cast<unsigned int*>(reinterpret_cast<uint8_t*>(cnt) + kOverflowAt);
   int64_t* totals = reinterpret_cast<int64_t*>(reinterpret_cast<uint8_t*>(cnt) + kTotalsAt);
-  ctx->keep_coef = keep_coef != 0;
   // the device-driven launch saves the host round trip (~0.1-0.2 ms) but its
   // looping workgroups encode large lists more slowly than one workgroup per
   // item; measured on the synthetic workloads the crossover lies between
@@ -591,11 +758,14 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
     std::memcpy(ht, hbuf + kTotalsAt, sizeof(ht));
     ctx->qv_bytes = ht[0];
     ctx->qa_bytes = ht[1];
-    ctx->nesc = int64_t(hc[0]);
+    ctx->nesc = ctx->nesc_slots = int64_t(hc[0]);
     ctx->nraw = int64_t(hc[1]);
     ctx->nwarm_accept = learned ? int64_t(hc[2]) : 0;
     ctx->nwarm_reject = learned ? (warm_any ? int64_t(hc[3]) : nb) : 0;
-    if (hov == 0 && hc[0] <= ctx->esc_cap) return finish_encode(ctx);
+    if (hov == 0 && hc[0] <= ctx->esc_cap) {
+      ctx->launch_mode = 1;
+      return finish_encode(ctx);
+    }
     // did not fit: grow with headroom for later calls, then the host-driven
     // encode below rewrites every output
     HIP_TRY(ctx->qv.grow(size_t(ht[0] + ht[0] / 4 + 16)));
@@ -641,7 +811,7 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
     HIP_TRY(hipMemcpyAsync(ctx->hcnt, cnt, sizeof(hc), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     std::memcpy(hc, ctx->hcnt, sizeof(hc));
-    ctx->nesc = int64_t(hc[0]);
+    ctx->nesc = ctx->nesc_slots = int64_t(hc[0]);
     ctx->nraw = int64_t(hc[1]);
     ctx->nwarm_accept = learned ? int64_t(hc[2]) : 0;
     ctx->nwarm_reject = learned ? (warm_any ? int64_t(hc[3]) : nb) : 0;
@@ -780,7 +950,7 @@ dls_status dls_decode(dls_ctx* ctx, void* d_out, size_t out_bytes, void* stream)
                                 ctx->code_off.as<int64_t>(), ctx->vconst.as<VarConst>(), ctx->qv.as<uint8_t>(),
                                 ctx->qa.as<uint8_t>(), ctx->codes.as<uint8_t>(), s));
   HIP_TRY(launch_scatter_keys(p.dtype, d_out, dims, ctx->desc.as<BlockDesc>(), ctx->esc_key.as<uint64_t>(),
-                              ctx->esc_val.as<uint64_t>(), ctx->nesc, s));
+                              ctx->esc_val.as<uint64_t>(), ctx->nesc_slots, s));
   return DLS_OK;
 }
 
@@ -877,6 +1047,9 @@ dls_status dls_encode_info_get(const dls_ctx* ctx, dls_encode_info* info) {
   info->d_coef = ctx->keep_coef ? ctx->coef.as<float>() : nullptr;
   info->nwarm_accept = ctx->nwarm_accept;
   info->nwarm_reject = ctx->nwarm_reject;
+  info->nfast_accept = ctx->nfast_accept;
+  info->ndeferred = ctx->ndeferred;
+  info->launch_mode = ctx->launch_mode;
   info->gpu_ms = ctx->gpu_ms;
   for (int i = 0; i < 5; ++i) info->stage_ms[i] = ctx->stage_ms[i];
   return DLS_OK;
@@ -893,23 +1066,25 @@ dls_status dls_finalize(dls_ctx* ctx, uint8_t** out, size_t* out_bytes) {
   const int64_t nb = int64_t(pl.blocks.size());
   std::vector<uint8_t> rank(nb), qv(ctx->qv_bytes), qa(ctx->qa_bytes), codes(pl.codes_bytes);
   std::vector<int64_t> qv_off(nb), qa_off(nb);
-  std::vector<uint64_t> ekey(ctx->nesc), eval(ctx->nesc);
+  std::vector<uint64_t> ekey(ctx->nesc_slots), eval(ctx->nesc_slots);
   HIP_TRY(hipMemcpy(rank.data(), ctx->rank.p, nb, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(qv_off.data(), ctx->qv_off.p, nb * 8, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(qa_off.data(), ctx->qa_off.p, nb * 8, hipMemcpyDeviceToHost));
   if (ctx->qv_bytes) HIP_TRY(hipMemcpy(qv.data(), ctx->qv.p, ctx->qv_bytes, hipMemcpyDeviceToHost));
   if (ctx->qa_bytes) HIP_TRY(hipMemcpy(qa.data(), ctx->qa.p, ctx->qa_bytes, hipMemcpyDeviceToHost));
   if (pl.codes_bytes) HIP_TRY(hipMemcpy(codes.data(), ctx->codes.p, pl.codes_bytes, hipMemcpyDeviceToHost));
-  if (ctx->nesc) {
-    HIP_TRY(hipMemcpy(ekey.data(), ctx->esc_key.p, ctx->nesc * 8, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(eval.data(), ctx->esc_val.p, ctx->nesc * 8, hipMemcpyDeviceToHost));
+  if (ctx->nesc_slots) {
+    HIP_TRY(hipMemcpy(ekey.data(), ctx->esc_key.p, ctx->nesc_slots * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(eval.data(), ctx->esc_val.p, ctx->nesc_slots * 8, hipMemcpyDeviceToHost));
   }
-  // escapes in block, then (t, p) order
-  std::vector<int64_t> order(ctx->nesc);
-  for (int64_t i = 0; i < ctx->nesc; ++i) order[i] = i;
+  // escapes in block, then (t, p) order; entries the single pass dropped
+  // (key ~0) sort last and are left out
+  std::vector<int64_t> order(ctx->nesc_slots);
+  for (int64_t i = 0; i < ctx->nesc_slots; ++i) order[i] = i;
   std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return ekey[a] < ekey[b]; });
+  order.resize(ctx->nesc);
   std::vector<int64_t> esc_start(nb + 1, 0);
-  for (int64_t i = 0; i < ctx->nesc; ++i) esc_start[(ekey[i] >> 32) + 1]++;
+  for (int64_t i = 0; i < ctx->nesc; ++i) esc_start[(ekey[order[i]] >> 32) + 1]++;
   for (int64_t b = 0; b < nb; ++b) esc_start[b + 1] += esc_start[b];
 
   const int64_t nbatch = (nb + kBatchBlocks - 1) / kBatchBlocks;

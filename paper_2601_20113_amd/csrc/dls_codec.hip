@@ -5,13 +5,19 @@
 //   DLS_CODEC_T     float or double
 //   DLS_CODEC_PPT   points per thread of the large-slice encode
 //   DLS_CODEC_TAG   w16_f32, w16_f64, w32_f32 or w32_f64 (entry point names)
-//   DLS_CODEC_PART  0: large-slice encode, 1: small-slice encode, 2: decode
+//   DLS_CODEC_PART  0: large-slice encode, 1: small-slice encode, 2: decode,
+//                   3: the fused single-pass encode (W <= 16, FP32 only)
 // so that the rank-class instantiations compile in parallel.
 //
 //   k_encode  projection A = X^T V_r (Eq. (5)), coefficient and basis
 //             quantization, exact integer-lattice reconstruction in FP64 and
 //             the residual codes that enforce the absolute bound, with escapes.
 //   k_decode  Alg. 2: lattice values from (qV, qA, codes) and scatter, Eq. (7).
+//   k_fused   one pass over the field for plans of large blocks: every
+//             slice is read once into registers, its Gram formed on the
+//             matrix cores, the block's eigenproblem solved by the slice that
+//             completes it (rank-1 power iteration with the exact acceptance
+//             test of the rank rule), and the slice encoded from registers.
 //
 // Compiled with -ffp-contract=off: the lattice arithmetic must round exactly
 // as written so that the decoder reproduces the encoder bit for bit.
@@ -82,39 +88,13 @@ __device__ __forceinline__ void team_sync() {
   else __syncthreads();
 }
 
-template <int WP, typename T, int PPT, int RMAX, bool DEV, int TEAM>
-__device__ __forceinline__ void encode_item(int64_t li, int tid, float (&Vf)[RMAX][WP], double (&Qv)[WP][RMAX],
-                                            const T* __restrict__ F, const Dims& dims,
-                                            const BlockDesc* __restrict__ desc,
-                                            const Item* __restrict__ items,
-                                            const int32_t* __restrict__ item_list,
-                                            const uint8_t* __restrict__ rank,
-                                            const double* __restrict__ basis,
-                                            const int64_t* __restrict__ qv_off,
-                                            const int64_t* __restrict__ qa_off,
-                                            const int64_t* __restrict__ code_off,
-                                            const VarConst* __restrict__ vc,
-                                            uint8_t* __restrict__ qv_buf,
-                                            uint8_t* __restrict__ qa_buf,
-                                            uint8_t* __restrict__ codes,
-                                            float* __restrict__ coef,
-                                            const EscOut& esc, const EncodeWork& work) {
-  const Item it = items[item_list[li]];
-  const int b = it.block;
-  const BlockDesc d = desc[b];
-  const int W = d.w(), M = d.m, r = rank[b];
-  const VarConst K = vc[d.var];
-  if constexpr (DEV) {  // host-driven launches size the buffers exactly
-    if (qv_off[b] + 4 * pad16(int64_t(W) * r) > work.qv_cap || qa_off[b] + 4 * pad16(int64_t(M) * r) > work.qa_cap) {
-      if (tid == 0) atomicOr(work.overflow, 1u);
-      return;
-    }
-  }
-
-  // the slice's values are loaded first, so that their latency overlaps the
-  // basis staging below
-  const int ps0 = tid * PPT;
-  const int valid = ps0 >= it.np ? 0 : ((it.np - ps0) < PPT ? (it.np - ps0) : PPT);
+// Loads the values of PPT consecutive slice points (slice-relative first
+// point ps0, `valid` of them in the slice) for every step of the window:
+// x[t][e], zero for t >= W_b and for invalid points.
+template <int WP, typename T, int PPT>
+__device__ __forceinline__ void load_slice_values(const T* __restrict__ F, const Dims& dims, const BlockDesc& d,
+                                                  const Item& it, int ps0, int valid, T (&x)[WP][PPT]) {
+  const int W = d.w();
   const int p = it.p0 + ps0;
   const int px = d.px(), py = d.py();
   const int64_t nxy = dims.nx * dims.ny;
@@ -124,8 +104,6 @@ __device__ __forceinline__ void encode_item(int64_t li, int tid, float (&Vf)[RMA
 #pragma unroll
   for (int e = 0; e < PPT; ++e) poff[e] = point_off(p + (e < valid ? e : 0), px, py, dims.nx, nxy);
   const bool vec = d.vec != 0;
-
-  T x[WP][PPT];
 #pragma unroll
   for (int t = 0; t < WP; ++t) {
     if (t < W) {
@@ -153,7 +131,19 @@ __device__ __forceinline__ void encode_item(int64_t li, int tid, float (&Vf)[RMA
       for (int e = 0; e < PPT; ++e) x[t][e] = T(0);
     }
   }
+}
 
+// Stages block b's basis (its first RMAX columns, rank r) in LDS for a team
+// of TEAM threads: FP32 values for the projection, the quantized codes
+// qV = rint(V 2^16) for the lattice; the block's first slice also writes the
+// qV codes to the payload.  A team barrier must follow before the values
+// are used.
+template <int WP, int RMAX, int TEAM>
+__device__ __forceinline__ void stage_basis(int tid, const Item& it, int b, const BlockDesc& d, int r,
+                                            float (&Vf)[RMAX][WP], double (&Qv)[WP][RMAX],
+                                            const double* __restrict__ basis, const int64_t* __restrict__ qv_off,
+                                            uint8_t* __restrict__ qv_buf) {
+  const int W = d.w();
   for (int idx = tid; idx < RMAX * WP; idx += TEAM) {
     const int k = idx / WP, t = idx % WP;
     const double v = basis[int64_t(b) * WP * WP + idx];
@@ -168,7 +158,33 @@ __device__ __forceinline__ void encode_item(int64_t li, int tid, float (&Vf)[RMA
       for (int j = 0; j < 4; ++j) dst[j * plane] = uint8_t(z >> (8 * j));
     }
   }
-  team_sync<TEAM>();
+}
+
+// Everything after the loads, for the PPT points of one thread of a team of
+// TEAM threads (`tid` < TEAM) encoding block b's slice `it` at rank r: the
+// basis is staged in LDS (and its quantized codes written by the block's
+// first slice), then projection, quantization, lattice reconstruction and
+// residual codes of x.
+template <int WP, typename T, int PPT, int RMAX, int TEAM, bool STAGED = false>
+__device__ __forceinline__ void encode_values(int tid, const Item& it, int b, const BlockDesc& d, int r,
+                                              const VarConst& K, int ps0, int valid, const T (&x)[WP][PPT],
+                                              float (&Vf)[RMAX][WP], double (&Qv)[WP][RMAX],
+                                              const double* __restrict__ basis,
+                                              const int64_t* __restrict__ qv_off,
+                                              const int64_t* __restrict__ qa_off,
+                                              const int64_t* __restrict__ code_off,
+                                              uint8_t* __restrict__ qv_buf,
+                                              uint8_t* __restrict__ qa_buf,
+                                              uint8_t* __restrict__ codes,
+                                              float* __restrict__ coef,
+                                              const EscOut& esc, uint64_t key_mark = 0) {
+  const int W = d.w(), M = d.m;
+  const int p = it.p0 + ps0;
+  const bool vec = d.vec != 0;
+  if constexpr (!STAGED) {
+    stage_basis<WP, RMAX, TEAM>(tid, it, b, d, r, Vf, Qv, basis, qv_off, qv_buf);
+    team_sync<TEAM>();
+  }
   if (valid == 0) return;
 
   const int64_t code_at = code_off[b] + int64_t(p);
@@ -186,7 +202,7 @@ __device__ __forceinline__ void encode_item(int64_t li, int tid, float (&Vf)[RMA
         if (e >= valid) continue;
         const unsigned long long slot = atomicAdd(esc.count, 1ULL);
         if (slot < esc.cap) {
-          esc.key[slot] = (uint64_t(b) << 32) | uint64_t(uint32_t(t * M + p + e));
+          esc.key[slot] = key_mark | (uint64_t(b) << 32) | uint64_t(uint32_t(t * M + p + e));
           esc.val[slot] = bits_of<T>(x[t][e]);
         }
       }
@@ -273,7 +289,7 @@ __device__ __forceinline__ void encode_item(int64_t li, int tid, float (&Vf)[RMA
       } else if (e < valid) {
         const unsigned long long slot = atomicAdd(esc.count, 1ULL);
         if (slot < esc.cap) {
-          esc.key[slot] = (uint64_t(b) << 32) | uint64_t(uint32_t(t * M + p + e));
+          esc.key[slot] = key_mark | (uint64_t(b) << 32) | uint64_t(uint32_t(t * M + p + e));
           esc.val[slot] = bits_of<T>(x[t][e]);
         }
       }
@@ -281,6 +297,46 @@ __device__ __forceinline__ void encode_item(int64_t li, int tid, float (&Vf)[RMA
     }
     store_bytes<PPT>(codes + code_at + int64_t(t) * M, cd, valid, vec);
   }
+}
+
+
+template <int WP, typename T, int PPT, int RMAX, bool DEV, int TEAM>
+__device__ __forceinline__ void encode_item(int64_t li, int tid, float (&Vf)[RMAX][WP], double (&Qv)[WP][RMAX],
+                                            const T* __restrict__ F, const Dims& dims,
+                                            const BlockDesc* __restrict__ desc,
+                                            const Item* __restrict__ items,
+                                            const int32_t* __restrict__ item_list,
+                                            const uint8_t* __restrict__ rank,
+                                            const double* __restrict__ basis,
+                                            const int64_t* __restrict__ qv_off,
+                                            const int64_t* __restrict__ qa_off,
+                                            const int64_t* __restrict__ code_off,
+                                            const VarConst* __restrict__ vc,
+                                            uint8_t* __restrict__ qv_buf,
+                                            uint8_t* __restrict__ qa_buf,
+                                            uint8_t* __restrict__ codes,
+                                            float* __restrict__ coef,
+                                            const EscOut& esc, const EncodeWork& work) {
+  const Item it = items[item_list[li]];
+  const int b = it.block;
+  const BlockDesc d = desc[b];
+  const int W = d.w(), M = d.m, r = rank[b];
+  const VarConst K = vc[d.var];
+  if constexpr (DEV) {  // host-driven launches size the buffers exactly
+    if (qv_off[b] + 4 * pad16(int64_t(W) * r) > work.qv_cap || qa_off[b] + 4 * pad16(int64_t(M) * r) > work.qa_cap) {
+      if (tid == 0) atomicOr(work.overflow, 1u);
+      return;
+    }
+  }
+
+  const int ps0 = tid * PPT;
+  const int valid = ps0 >= it.np ? 0 : ((it.np - ps0) < PPT ? (it.np - ps0) : PPT);
+  // the slice's values are loaded first, so that their latency overlaps the
+  // basis staging
+  T x[WP][PPT];
+  load_slice_values<WP, T, PPT>(F, dims, d, it, ps0, valid, x);
+  encode_values<WP, T, PPT, RMAX, TEAM>(tid, it, b, d, r, K, ps0, valid, x, Vf, Qv, basis, qv_off, qa_off, code_off,
+                                        qv_buf, qa_buf, codes, coef, esc);
 }
 
 // DEV = false: host-driven, one item per workgroup; DEV = true:
@@ -499,6 +555,279 @@ void decode_launch(const dim3& g, const dim3& bl, hipStream_t s, void* F, const 
                      code_off, vc, qv, qa, codes);
 }
 
+#if DLS_CODEC_PART == 3
+// ---------------------------------------------------------------------------
+// Single-pass encode (reading R28), two kernels:
+//
+// k_sketch_basis: per block, the rank-1 basis q of its sketch -- the Gram
+//   partial of its first slice (the first whole x-rows, at most 1024 points),
+//   formed beforehand by k_gram -- by power iteration from the column of the
+//   largest diagonal entry; q becomes column 0 of the block's basis, the
+//   block's payload regions are the rank-1 ones at their static offsets.
+// k_fused: slices i = blockIdx.x, + gridDim.x, ... (one workgroup per slice
+//   as launched: hardware dispatch keeps the slices in flight contiguous).
+//   Every slice is read once into registers, its Gram partial
+//   is formed on the matrix cores (FP32 or bf16 operands, FP64 across
+//   64-point chunks) and stored, and the slice is encoded at rank 1 with its
+//   block's q (the residual codes keep the pointwise bound for any
+//   orthonormal basis).  No workgroup waits for another.
+// k_verify: per block, the sum of its slices' partials in slice order (as
+//   k_eigen forms it) and the test of q on the whole Gram: trace(G) -
+//   q^T G q is the exact discarded energy of q, so when it is <= tau the
+//   rank rule of Sec. 2.4 Eq. (4) picks rank 1 and the encode stands;
+//   otherwise the block is deferred: the two-pass path solves it by Jacobi
+//   and encodes it again (its escapes from the single pass carry a mark and
+//   are dropped afterwards).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sketch_basis(const double* __restrict__ gpart,
+                                                      const int32_t* __restrict__ item_start,
+                                                      const BlockDesc* __restrict__ desc, int64_t nblocks,
+                                                      const int64_t* __restrict__ r1_off, uint8_t* __restrict__ rank,
+                                                      double* __restrict__ lam, double* __restrict__ basis,
+                                                      int64_t* __restrict__ qv_size, int64_t* __restrict__ qa_size,
+                                                      int64_t* __restrict__ qv_off, int64_t* __restrict__ qa_off,
+                                                      unsigned int* __restrict__ state) {
+  constexpr int WP = 16;
+  __shared__ double sG[16][WP][WP + 1];
+  __shared__ double sq[16][WP];
+  const int grp = int(threadIdx.x) / WP, row = int(threadIdx.x) % WP;
+  const int64_t b = int64_t(blockIdx.x) * 16 + grp;
+  if (b >= nblocks) return;  // the whole 16-lane group leaves together
+  const BlockDesc d = desc[b];
+  const double* gp = gpart + int64_t(item_start[b]) * WP * WP + row * WP;
+  double a[WP];
+#pragma unroll
+  for (int j = 0; j < WP; ++j) {
+    a[j] = gp[j];
+    sG[grp][row][j] = a[j];
+  }
+  wave_sync();
+  bool fin = true;
+#pragma unroll
+  for (int j = 0; j < WP; ++j) {
+    a[j] = 0.5 * (a[j] + sG[grp][j][row]);
+    fin = fin && isfinite(a[j]);
+  }
+  wave_sync();
+#pragma unroll
+  for (int j = 0; j < WP; ++j) sG[grp][row][j] = a[j];
+  wave_sync();
+  fin = row_sum(fin ? 0.0 : 1.0) == 0.0;
+  double qi = row == 0 ? 1.0 : 0.0;
+  if (fin) {
+    int istar = 0;
+    double best = sG[grp][0][0];
+    for (int j = 1; j < WP; ++j)
+      if (sG[grp][j][j] > best) { best = sG[grp][j][j]; istar = j; }
+    qi = sG[grp][row][istar];
+    double n2 = row_sum(qi * qi);
+    if (n2 > 0.0) qi = qi / sqrt(n2);
+    else qi = row == istar ? 1.0 : 0.0;
+    for (int k = 0; k < kFusedIters; ++k) {
+      sq[grp][row] = qi;
+      wave_sync();
+      double y = 0.0;
+#pragma unroll
+      for (int j = 0; j < WP; ++j) y = fma(a[j], sq[grp][j], y);
+      wave_sync();
+      n2 = row_sum(y * y);
+      if (n2 > 0.0) qi = y / sqrt(n2);
+    }
+    // canonical sign: the largest |q_t| positive, the lowest t on a tie
+    sq[grp][row] = qi;
+    wave_sync();
+    double bq = -1.0, sg = 1.0;
+    for (int j = 0; j < WP; ++j)
+      if (fabs(sq[grp][j]) > bq) { bq = fabs(sq[grp][j]); sg = sq[grp][j] < 0.0 ? -1.0 : 1.0; }
+    qi *= sg;
+  }
+  double* bb = basis + b * WP * WP;
+  bb[row] = qi;  // column 0 at [0][t]; the other columns are not formed
+#pragma unroll
+  for (int k = 1; k < WP; ++k) bb[k * WP + row] = 0.0;
+  lam[b * WP + row] = 0.0;
+  if (row == 0) {
+    rank[b] = 1;
+    qv_size[b] = 4 * pad16(int64_t(d.w()));
+    qa_size[b] = 4 * pad16(int64_t(d.m));
+    qv_off[b] = r1_off[b];
+    qa_off[b] = r1_off[nblocks + b];
+    state[b] = fin ? 0u : 3u;  // 3: no usable sketch, the block is left to the two-pass path
+  }
+}
+
+template <bool BF>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_fused(const float* __restrict__ F, Dims dims,
+                                               const BlockDesc* __restrict__ desc,
+                                               const Item* __restrict__ items, int64_t nitems,
+                                               const VarConst* __restrict__ vc, double* __restrict__ gpart,
+                                               const unsigned int* __restrict__ state,
+                                               const double* __restrict__ basis,
+                                               const int64_t* __restrict__ qv_off, const int64_t* __restrict__ qa_off,
+                                               const int64_t* __restrict__ code_off, uint8_t* __restrict__ qv_buf,
+                                               uint8_t* __restrict__ qa_buf, uint8_t* __restrict__ codes,
+                                               float* __restrict__ coef, EscOut esc) {
+  constexpr int WP = 16, PPT = 4, LDR = 68;
+  __shared__ __align__(16) float stage[4][WP * LDR];
+  __shared__ double red[4][4][64];
+  __shared__ float Vf[1][WP];
+  __shared__ double Qv[WP][1];
+  const int tid = int(threadIdx.x), lane = tid & 63, wave = tid >> 6;
+  const int tl = lane & 15, q = lane >> 4;
+  constexpr uint64_t kSpeculative = uint64_t(1) << 63;
+  for (int64_t i = blockIdx.x; i < nitems; i += gridDim.x) {
+    const Item it = items[i];
+    const int b = it.block;
+    const BlockDesc d = desc[b];
+    const unsigned st_b = state[b];  // from k_sketch_basis: 0 usable basis, 3 none
+    // thread tid: slice points 4 tid .. 4 tid + 3 (wavefront w: chunks of 64
+    // points 4 w .. 4 w + 3), so every step's codes are stored as 256
+    // contiguous bytes per wavefront
+    const int ps0 = PPT * tid;
+    const int valid = ps0 >= it.np ? 0 : ((it.np - ps0) < PPT ? (it.np - ps0) : PPT);
+    float x[WP][PPT];
+    load_slice_values<WP, float, PPT>(F, dims, d, it, ps0, valid, x);
+    // the block's sketch basis, staged while the field loads are in flight
+    // (the Gram's barriers below publish it)
+    if (st_b == 0u) stage_basis<WP, 1, 256>(tid, it, b, d, 1, Vf, Qv, basis, qv_off, qv_buf);
+
+    // Gram partial of the slice: per 64-point chunk one MFMA accumulation
+    // (operands staged through LDS), flushed to FP64 in chunk order
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    float* st = stage[wave];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if ((4 * wave + u) * 64 >= it.np) continue;
+      if (q == u) {
+#pragma unroll
+        for (int t = 0; t < WP; ++t)
+          *reinterpret_cast<float4*>(st + t * LDR + 4 * tl) = make_float4(x[t][0], x[t][1], x[t][2], x[t][3]);
+      }
+      wave_sync();
+      float v0[16];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float4 a = *reinterpret_cast<const float4*>(st + tl * LDR + 16 * j + 4 * q);
+        v0[4 * j] = a.x; v0[4 * j + 1] = a.y; v0[4 * j + 2] = a.z; v0[4 * j + 3] = a.w;
+      }
+      wave_sync();
+      f32x4 a00 = {0.f, 0.f, 0.f, 0.f};
+      if constexpr (BF) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const bf16x4 b0 = to_bf16x4(v0 + 4 * j);
+          a00 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b0, b0, a00, 0, 0, 0);
+        }
+      } else {
+#pragma unroll
+        for (int s2 = 0; s2 < 16; ++s2) a00 = __builtin_amdgcn_mfma_f32_16x16x4f32(v0[s2], v0[s2], a00, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[v] += double(a00[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[wave][v][lane] = acc[v];
+    __syncthreads();
+    if (wave == 0) {
+      double* out = gpart + i * WP * WP;
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        out[(4 * q + v) * WP + tl] = ((red[0][v][lane] + red[1][v][lane]) + red[2][v][lane]) + red[3][v][lane];
+    }
+    // the slice encoded at rank 1 with its block's sketch basis
+    if (st_b == 0u)
+      encode_values<WP, float, PPT, 1, 256, true>(tid, it, b, d, 1, vc[d.var], ps0, valid, x, Vf, Qv, basis, qv_off,
+                                                  qa_off, code_off, qv_buf, qa_buf, codes, coef, esc, kSpeculative);
+    __syncthreads();  // LDS of this slice is free again
+  }
+}
+
+// Verification of the sketch bases: 16 lanes per block (lane = row of the
+// Gram), 16 blocks per workgroup.
+__global__ __launch_bounds__(256) void k_verify(const double* __restrict__ gpart,
+                                                const int32_t* __restrict__ item_start,
+                                                const BlockDesc* __restrict__ desc, int64_t nblocks,
+                                                const double* __restrict__ eps_v, const double* __restrict__ basis,
+                                                double* __restrict__ lam, FusedState fs) {
+  constexpr int WP = 16;
+  __shared__ double sA[16][WP][WP + 1];
+  __shared__ double sq[16][WP];
+  const int grp = int(threadIdx.x) / WP, row = int(threadIdx.x) % WP;
+  const int64_t b = int64_t(blockIdx.x) * 16 + grp;
+  if (b >= nblocks) return;  // the whole 16-lane group leaves together
+  const BlockDesc d = desc[b];
+  const int i0 = item_start[b], i1 = item_start[b + 1];
+  double a[WP];
+#pragma unroll
+  for (int j = 0; j < WP; ++j) a[j] = 0.0;
+  for (int s2 = i0; s2 < i1; ++s2) {  // every entry's loads of a slice issued together
+    const double* gp = gpart + int64_t(s2) * WP * WP + row * WP;
+#pragma unroll
+    for (int j = 0; j < WP; ++j) a[j] += gp[j];
+  }
+#pragma unroll
+  for (int j = 0; j < WP; ++j) sA[grp][row][j] = a[j];
+  wave_sync();
+  bool fin = true;
+#pragma unroll
+  for (int j = 0; j < WP; ++j) {
+    a[j] = 0.5 * (a[j] + sA[grp][j][row]);
+    fin = fin && isfinite(a[j]);
+  }
+  fin = row_sum(fin ? 0.0 : 1.0) == 0.0;
+  const unsigned st_b = fs.state[b];
+  bool accept = false;
+  double theta = 0.0;
+  if (fin && st_b == 0u) {
+    const double qi = basis[b * WP * WP + row];
+    sq[grp][row] = qi;
+    wave_sync();
+    double y = 0.0, di = 0.0;
+#pragma unroll
+    for (int j = 0; j < WP; ++j) {
+      y = fma(a[j], sq[grp][j], y);
+      di = j == row ? a[j] : di;
+    }
+    theta = row_sum(qi * y);
+    const double tr = row_sum(di);
+    const double eps = eps_v[d.var];
+    const double tau = kKappa * eps * eps * double(d.m) * double(d.w());
+    accept = (tr - theta) <= tau;
+  }
+  if (row == 0) {
+    if (accept) {
+      lam[b * WP] = theta;
+      fs.state[b] = 1u;
+      atomicAdd(fs.counters + kFusedAccepted, 1ULL);
+    } else {
+      fs.state[b] = 2u;
+      const unsigned slot = atomicAdd(fs.ndeferred, 1u);
+      fs.deferred[slot] = int32_t(b);
+    }
+  }
+}
+
+// Escapes written by k_fused (marked) for blocks it deferred are dropped:
+// their keys become ~0 (sorted last, skipped by the scatter) and are
+// counted; the marks of the blocks it kept are cleared.
+__global__ __launch_bounds__(256) void k_fix_escapes(uint64_t* __restrict__ key, const unsigned long long* count,
+                                                     unsigned long long cap, const unsigned int* __restrict__ state,
+                                                     unsigned long long* __restrict__ ndropped) {
+  const unsigned long long n = *count < cap ? *count : cap;
+  for (unsigned long long i = uint64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += uint64_t(gridDim.x) * 256) {
+    const uint64_t k = key[i];
+    if (!(k >> 63)) continue;
+    const uint64_t b = (k >> 32) & 0x7FFFFFFFu;
+    if (state[b] == 1u) {
+      key[i] = k & ~(uint64_t(1) << 63);
+    } else {
+      key[i] = ~uint64_t(0);
+      atomicAdd(ndropped, 1ULL);
+    }
+  }
+}
+#endif
+
 }  // namespace
 
 #if DLS_CODEC_PART == 0
@@ -507,6 +836,47 @@ void decode_launch(const dim3& g, const dim3& bl, hipStream_t s, void* F, const 
 #elif DLS_CODEC_PART == 1
 #define DLS_CODEC_SMALL true
 #define DLS_CODEC_ENTRY encode_small
+#endif
+
+#if DLS_CODEC_PART == 3
+hipError_t launch_sketch_basis(const double* gpart, const int32_t* item_start, const BlockDesc* desc, int64_t nblocks,
+                               const int64_t* r1_off, uint8_t* rank, double* lam, double* basis, int64_t* qv_size,
+                               int64_t* qa_size, int64_t* qv_off, int64_t* qa_off, unsigned int* state, hipStream_t s) {
+  if (nblocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sketch_basis, dim3{unsigned((nblocks + 15) / 16)}, dim3{256}, 0, s, gpart, item_start, desc,
+                     nblocks, r1_off, rank, lam, basis, qv_size, qa_size, qv_off, qa_off, state);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused(bool bf16, int grid, const float* F, const Dims& dims, const BlockDesc* desc,
+                        const Item* items, int64_t nitems, const VarConst* vc, double* gpart,
+                        const unsigned int* state, const double* basis, const int64_t* qv_off, const int64_t* qa_off,
+                        const int64_t* code_off, uint8_t* qv, uint8_t* qa, uint8_t* codes, float* coef, EscOut esc,
+                        hipStream_t s) {
+  if (nitems == 0) return hipSuccess;
+  const dim3 g{unsigned(grid)}, bl{256};
+  if (bf16)
+    hipLaunchKernelGGL(k_fused<true>, g, bl, 0, s, F, dims, desc, items, nitems, vc, gpart, state, basis, qv_off,
+                       qa_off, code_off, qv, qa, codes, coef, esc);
+  else
+    hipLaunchKernelGGL(k_fused<false>, g, bl, 0, s, F, dims, desc, items, nitems, vc, gpart, state, basis, qv_off,
+                       qa_off, code_off, qv, qa, codes, coef, esc);
+  return hipGetLastError();
+}
+
+hipError_t launch_verify(const double* gpart, const int32_t* item_start, const BlockDesc* desc, int64_t nblocks,
+                         const double* eps_v, const double* basis, double* lam, const FusedState& fs, hipStream_t s) {
+  if (nblocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_verify, dim3{unsigned((nblocks + 15) / 16)}, dim3{256}, 0, s, gpart, item_start, desc, nblocks,
+                     eps_v, basis, lam, fs);
+  return hipGetLastError();
+}
+
+hipError_t launch_fix_escapes(uint64_t* key, const unsigned long long* count, unsigned long long cap,
+                              const unsigned int* state, unsigned long long* ndropped, hipStream_t s) {
+  hipLaunchKernelGGL(k_fix_escapes, dim3{256}, dim3{256}, 0, s, key, count, cap, state, ndropped);
+  return hipGetLastError();
+}
 #endif
 
 #if DLS_CODEC_PART == 0 || DLS_CODEC_PART == 1
@@ -522,7 +892,7 @@ hipError_t DLS_CODEC_FN(DLS_CODEC_ENTRY)(int rc, const dim3& g, hipStream_t s, c
                                             qa_off, code_off, vc, qv, qa, codes, coef, esc, work);
   return hipGetLastError();
 }
-#else
+#elif DLS_CODEC_PART == 2
 hipError_t DLS_CODEC_FN(decode_part)(int rc, const dim3& g, const dim3& bl, hipStream_t s, void* F,
                                      const Dims& dims, const BlockDesc* desc, const Item* items,
                                      const int32_t* list, const uint8_t* rank, const int64_t* qv_off,

@@ -7,6 +7,17 @@
 
 namespace dls {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+
+// four bfloat16 values, each rounded to nearest even (v_cvt_pk_bf16_f32;
+// infinity stays infinity, so the eigensolve's finiteness check still sees it)
+__device__ __forceinline__ bf16x4 to_bf16x4(const float* v) {
+  typedef __bf16 bfv4 __attribute__((ext_vector_type(4)));
+  const bfv4 r = {(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
+  return __builtin_bit_cast(bf16x4, r);
+}
+
 __device__ __forceinline__ int64_t fidx(const Dims& d, int var, int t, int z, int y, int x) {
   return (((int64_t(var) * d.nt + t) * d.nz + z) * d.ny + y) * d.nx + x;
 }

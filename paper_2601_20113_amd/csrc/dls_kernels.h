@@ -73,6 +73,40 @@ DLS_CODEC_DECL(w32_f64)
 #undef DLS_CODEC_DECL
 #undef DLS_CODEC_ENC_DECL
 
+// Single-pass encode (k_sketch_basis, k_fused, k_verify in dls_codec.hip)
+// for plans whose blocks all span at least one full slice, W <= 16, FP32.
+// Per-call state, cleared before the launch: per block a verdict (0 sketch
+// basis usable, 1 verified at rank 1, 2 deferred to the two-pass path, 3 no
+// usable sketch), the list of deferred blocks, and u64 counters: payload
+// cursors of the deferred blocks (after the rank-1 regions), blocks verified
+// at rank 1, escapes dropped.
+constexpr int kFusedIters = 6;          // power steps of the sketch's basis after its start column
+constexpr int kFusedMinPoints = 1024;   // every block of the plan at least this large
+constexpr int kFusedQvCursor = 0, kFusedQaCursor = 1, kFusedAccepted = 2, kFusedDropped = 3, kFusedNCounters = 4;
+struct FusedState {
+  unsigned int* state;            // [nblocks]
+  int32_t* deferred;              // [nblocks]
+  unsigned int* ndeferred;        // 1
+  unsigned long long* counters;   // kFusedNCounters
+};
+// r1_off: [nblocks] static qV offsets then [nblocks] static qA offsets of the rank-1 payload
+hipError_t launch_sketch_basis(const double* gpart, const int32_t* item_start, const BlockDesc* desc, int64_t nblocks,
+                               const int64_t* r1_off, uint8_t* rank, double* lam, double* basis, int64_t* qv_size,
+                               int64_t* qa_size, int64_t* qv_off, int64_t* qa_off, unsigned int* state, hipStream_t s);
+hipError_t launch_fused(bool bf16, int grid, const float* F, const Dims& dims, const BlockDesc* desc,
+                        const Item* items, int64_t nitems, const VarConst* vc, double* gpart,
+                        const unsigned int* state, const double* basis, const int64_t* qv_off, const int64_t* qa_off,
+                        const int64_t* code_off, uint8_t* qv, uint8_t* qa, uint8_t* codes, float* coef, EscOut esc,
+                        hipStream_t s);
+hipError_t launch_verify(const double* gpart, const int32_t* item_start, const BlockDesc* desc, int64_t nblocks,
+                         const double* eps_v, const double* basis, double* lam, const FusedState& fs, hipStream_t s);
+hipError_t launch_fix_escapes(uint64_t* key, const unsigned long long* count, unsigned long long cap,
+                              const unsigned int* state, unsigned long long* ndropped, hipStream_t s);
+// payload offsets of the deferred blocks: base + a bump cursor
+hipError_t launch_alloc_deferred(const int32_t* list, const unsigned int* count, int64_t nmax, const int64_t* qv_size,
+                                 const int64_t* qa_size, unsigned long long* counters, int64_t qv_base,
+                                 int64_t qa_base, int64_t* qv_off, int64_t* qa_off, hipStream_t s);
+
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // totals[0] = qv_off[n-1] + qv_size[n-1], totals[1] likewise for qA
 hipError_t launch_totals(const int64_t* qv_off, const int64_t* qv_size, const int64_t* qa_off,
@@ -155,8 +189,9 @@ hipError_t launch_range_noalloc(double* scratch_ptr, int dtype, const void* F, i
                                 hipStream_t s);
 hipError_t launch_range(int dtype, const void* F, int nvars, int64_t n_per_var, double* part, int nparts,
                         double* out, hipStream_t s);
+// skip (may be NULL): items of blocks with skip[block] == 1 are left out
 hipError_t launch_classify(const Item* items, int64_t nitems, const uint8_t* rank, int small_limit,
-                           unsigned int* counts, int32_t* lists, hipStream_t s);
+                           unsigned int* counts, int32_t* lists, hipStream_t s, const unsigned int* skip = nullptr);
 hipError_t launch_encode(int wp, int dtype, int cls, const void* F, const Dims& dims, const BlockDesc* desc,
                          const Item* items, const int32_t* list, const EncodeWork& work, const uint8_t* rank,
                          const double* basis, const int64_t* qv_off, const int64_t* qa_off,

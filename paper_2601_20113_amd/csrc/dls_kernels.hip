@@ -34,8 +34,6 @@
 
 namespace dls {
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
 
 template <typename T>
 __device__ __forceinline__ void load4(const T* __restrict__ row, int64_t off, float* v);
@@ -78,13 +76,6 @@ __device__ __forceinline__ void load_chunk(const T* __restrict__ row, const Item
 // ---------------------------------------------------------------------------
 // Gram: one workgroup (4 waves) per item; output gpart[item][WP][WP] (FP64).
 // ---------------------------------------------------------------------------
-// four bfloat16 values, each rounded to nearest even (v_cvt_pk_bf16_f32;
-// infinity stays infinity, so the eigensolve's finiteness check still sees it)
-__device__ __forceinline__ bf16x4 to_bf16x4(const float* v) {
-  typedef __bf16 bfv4 __attribute__((ext_vector_type(4)));
-  const bfv4 r = {(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
-  return __builtin_bit_cast(bf16x4, r);
-}
 
 // BF: bfloat16 operands (v_mfma_f32_16x16x16bf16_1k, one instruction per 16
 // points); otherwise FP32 operands (v_mfma_f32_16x16x4f32, one per 4 points).
@@ -701,7 +692,8 @@ __device__ __forceinline__ int rank_class(int r) {
 __global__ __launch_bounds__(256) void k_classify(const Item* __restrict__ items, int64_t nitems,
                                                   const uint8_t* __restrict__ rank, int small_limit,
                                                   unsigned int* __restrict__ counts,
-                                                  int32_t* __restrict__ lists) {
+                                                  int32_t* __restrict__ lists,
+                                                  const unsigned int* __restrict__ skip) {
   // counts are aggregated per workgroup in LDS: one global atomic per class
   constexpr int NC = 2 * kRankClasses;
   __shared__ unsigned int lcount[NC], lbase[NC];
@@ -712,8 +704,10 @@ __global__ __launch_bounds__(256) void k_classify(const Item* __restrict__ items
   unsigned int lpos = 0;
   if (i < nitems) {
     const Item it = items[i];
-    c = rank_class(rank[it.block]) + (it.np <= small_limit ? kRankClasses : 0);
-    lpos = atomicAdd(&lcount[c], 1u);
+    if (skip == nullptr || skip[it.block] != 1u) {
+      c = rank_class(rank[it.block]) + (it.np <= small_limit ? kRankClasses : 0);
+      lpos = atomicAdd(&lcount[c], 1u);
+    }
   }
   __syncthreads();
   if (threadIdx.x < NC && lcount[threadIdx.x] > 0)
@@ -731,6 +725,7 @@ __global__ __launch_bounds__(256) void k_scatter_keys(T* __restrict__ F, Dims di
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (i >= n) return;
   const uint64_t kk = key[i];
+  if (kk == ~uint64_t(0)) return;  // an escape the single pass dropped
   const BlockDesc d = desc[kk >> 32];
   const uint32_t tp = uint32_t(kk);
   const int t = int(tp / uint32_t(d.m)), p = int(tp % uint32_t(d.m));
@@ -851,10 +846,36 @@ hipError_t launch_scan(const int64_t* in, int64_t n, int64_t* out, int64_t* tmp,
 }
 
 hipError_t launch_classify(const Item* items, int64_t nitems, const uint8_t* rank, int small_limit,
-                           unsigned int* counts, int32_t* lists, hipStream_t s) {
+                           unsigned int* counts, int32_t* lists, hipStream_t s, const unsigned int* skip) {
   if (nitems == 0) return hipSuccess;
   const dim3 g{unsigned((nitems + 255) / 256)}, bl{256};
-  hipLaunchKernelGGL(k_classify, g, bl, 0, s, items, nitems, rank, small_limit, counts, lists);
+  hipLaunchKernelGGL(k_classify, g, bl, 0, s, items, nitems, rank, small_limit, counts, lists, skip);
+  return hipGetLastError();
+}
+
+// Payload regions of the blocks the fused kernel deferred, taken from the
+// same bump cursors (any order: the stream is written block by block from
+// the offsets, so the layout of the device payload does not matter).
+__global__ __launch_bounds__(256) void k_alloc_deferred(const int32_t* __restrict__ list,
+                                                        const unsigned int* __restrict__ count,
+                                                        const int64_t* __restrict__ qv_size,
+                                                        const int64_t* __restrict__ qa_size,
+                                                        unsigned long long* __restrict__ counters,
+                                                        int64_t qv_base, int64_t qa_base,
+                                                        int64_t* __restrict__ qv_off, int64_t* __restrict__ qa_off) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= int64_t(*count)) return;
+  const int b = list[i];
+  qv_off[b] = qv_base + int64_t(atomicAdd(counters + kFusedQvCursor, (unsigned long long)qv_size[b]));
+  qa_off[b] = qa_base + int64_t(atomicAdd(counters + kFusedQaCursor, (unsigned long long)qa_size[b]));
+}
+
+hipError_t launch_alloc_deferred(const int32_t* list, const unsigned int* count, int64_t nmax, const int64_t* qv_size,
+                                 const int64_t* qa_size, unsigned long long* counters, int64_t qv_base,
+                                 int64_t qa_base, int64_t* qv_off, int64_t* qa_off, hipStream_t s) {
+  if (nmax == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_alloc_deferred, dim3{unsigned((nmax + 255) / 256)}, dim3{256}, 0, s, list, count, qv_size,
+                     qa_size, counters, qv_base, qa_base, qv_off, qa_off);
   return hipGetLastError();
 }
 

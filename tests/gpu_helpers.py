@@ -78,13 +78,37 @@ def coef_rel_err(A_gpu, V_gpu, A_or, V_or) -> float:
     return float(np.linalg.norm(d) / max(np.linalg.norm(A_or), 1e-300))
 
 
-def projector_unique(lam: np.ndarray, r: int, limit: float = 1e-6) -> bool:
-    """Reading R5: the rank-r subspace (and with it V_r V_r^T X) is unique
-    when the relative gap (lam_r - lam_{r+1}) / lam_1 at r is at least 1e-6;
-    below that several results are correct and only the bound judges."""
+U32 = 2.0 ** -24
+GAMMA64 = 64 * U32 / (1 - 64 * U32)   # FP32 accumulation of a 64-point chunk
+
+
+def projector_tol(lam: np.ndarray, r: int, w: int, energy_ratio=None):
+    """Bound on ||P_gpu X - P_or X||_F / ||P_or X||_F for the rank-r
+    reconstruction P X = V_r V_r^T X when the Gram is formed from FP32 (or
+    bf16) products accumulated in FP32 over 64-point chunks; None when the
+    rank-r subspace is not determined (reading R5: several results correct).
+
+    Each Gram entry is off by at most GAMMA64 sqrt(G_aa G_bb) (Cauchy-Schwarz
+    on the chunk's products), so ||dG||_2 <= ||dG||_F <= GAMMA64 W trace(G).
+    Davis-Kahan: the sine of the angle between the exact and the perturbed
+    rank-r subspaces is at most ||dG|| / (lam_r - lam_{r+1} - ||dG||), and
+    ||(P_g - P_o) X||_F <= sqrt(2) sin(theta) ||X||_F.  Relative to ||P_o X||_F
+    = sqrt(sum_{k<=r} lam_k) (or sqrt(trace / energy_ratio) given), plus 1e-6
+    for the FP32 projection itself.  Unlike the coefficients, the projector
+    shows a rotation of even the dominant mode at full weight, which an FP32
+    Gram makes of order 1e-5."""
     lam = np.maximum(np.asarray(lam, dtype=np.float64), 0.0)
+    tr = float(np.sum(lam))
+    if not tr > 0.0:
+        return None
+    dg = GAMMA64 * w * tr
     nxt = lam[r] if r < lam.size else 0.0
-    return (lam[r - 1] - nxt) >= limit * max(lam[0], 1e-300)
+    gap = lam[r - 1] - nxt - dg
+    if not gap > 0.0:
+        return None
+    sin = dg / gap
+    ratio = energy_ratio if energy_ratio is not None else tr / max(float(np.sum(lam[:r])), 1e-300)
+    return float(np.sqrt(2.0) * sin * np.sqrt(ratio) + 1e-6)
 
 
 def projector_rel_err(A_gpu, V_gpu, A_or, V_or) -> float:

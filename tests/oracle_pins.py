@@ -433,11 +433,72 @@ def pin_sign_tie():
     assert np.array_equal(np.sign(V), np.array(g["expected"]["V_sign"])), V
 
 
+# -- the single-pass form: rank-1 basis, exact verification, sketch ---------
+def pin_rank_one_single_pass():
+    """The rank-1 basis and its verification (reading R28) against the
+    hand-worked 2 x 2 cases (golden rank1_attempt_2x2.json), an exactly
+    rank-1 Gram with a zero component, the energy identity checked by
+    explicit projection, convergence to the leading eigenvector, the rank
+    rule an accepted block implies, and the sketch: on exactly rank-1 data
+    the sketch's basis passes the whole block; a block whose later rows add
+    a second mode beyond tau fails."""
+    g = _golden("rank1_attempt_2x2.json")
+    x = np.array(g["inputs"]["x"])
+    e = g["expected"]
+    tau = g["inputs"]["eps"] ** 2 * x.size
+    q = dls.leading_vector(x @ x.T)
+    ok, th = dls.rank_one_verify(x @ x.T, q, tau)
+    assert ok == e["accepted"] and abs(th - e["theta"]) <= 1e-12 and np.allclose(q, e["q"], rtol=0, atol=1e-15)
+    ok, _ = dls.rank_one_verify(np.eye(2), dls.leading_vector(np.eye(2)), g["inputs"]["identity_tau"])
+    assert ok == e["identity_accepted"]
+    q = dls.leading_vector(np.zeros((3, 3)))
+    ok, th = dls.rank_one_verify(np.zeros((3, 3)), q, 0.0)
+    assert ok and th == 0.0 and q.tolist() == e["zero_q"] + [0.0]
+    a = np.array([0.0, 3.0, -4.0, 0.0, 12.0]) / 13.0
+    q = dls.leading_vector(49.0 * np.outer(a, a))
+    ok, th = dls.rank_one_verify(49.0 * np.outer(a, a), q, 1e-9)
+    assert ok and abs(th - 49.0) <= 1e-12 and np.allclose(q, a * np.sign(a[4]), rtol=0, atol=1e-15)
+    rng = np.random.default_rng(31)
+    for w, m in [(16, 64), (7, 40), (16, 1024)]:
+        xs = _rand_block(rng, w, m)
+        G = xs @ xs.T
+        q = dls.leading_vector(G)
+        _, th = dls.rank_one_verify(G, q, 0.0)
+        r_ = xs - np.outer(q, q @ xs)          # exact discarded energy, by projection
+        assert abs(np.sum(r_ * r_) - (np.trace(G) - th)) <= 1e-10 * np.trace(G)
+        lam, V = dls.eig_desc(G)
+        assert th <= lam[0] * (1 + 1e-14)
+        # power iteration from e_i (i = largest diagonal entry; the start
+        # column G e_i is its first step): tan of the angle to v_1 shrinks by
+        # lam_2 / lam_1 per step (Golub & Van Loan, Sec. 8.2.1)
+        i = int(np.argmax(np.diag(G)))
+        v1 = V[:, 0]
+        tan0 = math.sqrt(max(1.0 - v1[i] ** 2, 0.0)) / abs(v1[i])
+        bound = tan0 * (lam[1] / lam[0]) ** (dls.FAST_ITERS + 1)
+        assert np.linalg.norm(q - v1) <= bound + 1e-12, (np.linalg.norm(q - v1), bound)
+        tau = np.trace(G) - th                 # an accepted block: the rank rule picks 1 too
+        ok, _ = dls.rank_one_verify(G, q, tau)
+        assert ok and dls.choose_rank(lam, tau, w) == 1
+    # sketch: the first floor(1024 / px) rows of px points
+    assert dls.sketch_points(32768, 32) == 1024 and dls.sketch_points(640, 24) == 640
+    assert dls.sketch_points(4096, 24) == 42 * 24 and dls.sketch_points(50, 100) == 50
+    t = np.arange(16)[:, None]
+    prof = np.exp(-0.02 * t)
+    amp = rng.normal(size=(1, 2048))
+    xs = prof * amp                               # exactly rank 1 in time
+    code, ok = dls.encode_block_sketch(xs, 1e-6, 16, np.float64, 32)
+    assert ok and code.r == 1 and np.allclose(code.V[:, 0], prof[:, 0] / np.linalg.norm(prof), rtol=0, atol=1e-14)
+    xs2 = xs.copy()
+    xs2[:, 1024:] += np.cos(0.7 * t) * rng.normal(size=(1, 1024))   # a second mode outside the sketch
+    code, ok = dls.encode_block_sketch(xs2, 1e-6, 16, np.float64, 32)
+    assert not ok and code.r >= 2
+
+
 ALL_PINS = [
     pin_eigenvalues_vs_svd, pin_eigenvectors_orthonormal_and_residual,
     pin_eigenvalues_vs_jacobi, pin_rank_bruteforce, pin_exact_rank_data,
     pin_pointwise_bound, pin_escapes_rare_on_smooth_data, pin_escape_threshold, pin_lattice_one_rounding,
     pin_hand_worked_rank_one, pin_special_blocks, pin_gradient_and_percentile,
     pin_adaptive_plan, pin_container_round_trip, pin_round_bf16, pin_moments_hand_case,
-    pin_nrmse_hand_case, pin_sign_tie,
+    pin_nrmse_hand_case, pin_sign_tie, pin_rank_one_single_pass,
 ]

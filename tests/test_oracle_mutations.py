@@ -21,6 +21,14 @@ MODULES = {"dls": dls, "learned": learned}
 # (function, original text, planted mistake); functions of oracle.learned are
 # prefixed "learned."
 MUTATIONS = [
+    ("rank_one_verify", "return float(np.trace(G)) - theta <= tau, theta",
+     "return float(np.trace(G)) - theta < tau, theta"),
+    ("leading_vector", "i = int(np.argmax(np.diag(G)))", "i = int(np.argmin(np.diag(G)))"),
+    ("rank_one_verify", "theta = float(q @ (G @ q))", "theta = float(q @ q)"),
+    ("leading_vector", "for _ in range(iters):", "for _ in range(iters // 3):"),
+    ("sketch_points", "return min(m, max(1, SKETCH_POINTS // px) * px)", "return min(m, SKETCH_POINTS)"),
+    ("encode_block_sketch", "ok, theta = rank_one_verify(G, q, tau)",
+     "ok, theta = rank_one_verify(xg[:, :s] @ xg[:, :s].T, q, tau)"),
     ("learned.moments", "f[11] = float(np.mean((x[2:] - mu) * (x[:-2] - mu))) / var",
      "f[11] = float(np.mean((x[1:] - mu) * (x[:-1] - mu))) / var"),
     ("learned.moments", "f[13] = math.log10(max(sd / eps, 1e-15))", "f[13] = math.log10(max(var / eps, 1e-15))"),

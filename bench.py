@@ -4,11 +4,16 @@
 One step = one dls_encode over the whole synthetic field (plan, Gram,
 eigensolve + rank, offset scan, projection / quantization / lattice
 reconstruction / residual codes), input already resident in HBM.  Two forms
-are timed on the same field: the plain GPU form and the full form (learned
-warm start, bf16 Gram, device-driven launch).  Prints one JSON line with the
-full form's throughput, the plain form's and their ratio, the roofline of the
-dominant kernel (measured with HIP events on the stream the kernels run on),
-and the FP64 CPU oracle timed on a bounded sample of the same workload.
+are timed on the same field: the plain GPU form (FP32 Gram, Jacobi, one
+host-driven launch per class) and the full form (bf16 Gram, the batched
+launch -- on plans of large FP32 blocks the single pass --, the learned warm
+start where blocks are small enough for it).  Prints one JSON line with the
+full form's throughput, the plain form's and their ratio, the label of what
+actually ran, the roofline of the dominant kernel (its launch timed with HIP
+events on the stream the kernels run on), end-to-end throughput (+ device to
+host copy and host zlib), the decode, error statistics of the decoded field,
+and the FP64 CPU oracle timed on a bounded sample of the same workload on the
+host's cores.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c5]
 """
@@ -82,48 +87,111 @@ def make_field(cfg):
     return t, eps
 
 
-def cpu_baseline(field, cfg, eps, seconds):
-    """The FP64 oracle, as it stands, on variable 0: window by window and
-    z-slab by z-slab (each with the oracle's own plan), block by block in plan
-    order, until ~`seconds` of CPU time; BLAS pinned to one thread."""
-    import numpy as np
+def _oracle_piece(args):
+    """Worker: the FP64 oracle on one piece of variable 0 (its own plan),
+    block by block, until the shared deadline; BLAS pinned to one thread.
+    Returns (bytes encoded, blocks, busy seconds)."""
+    piece, pkw, eps0, deadline = args
     from threadpoolctl import threadpool_limits
     from oracle import dls as odls
+    t0 = time.time()
+    nbytes = nblk = 0
+    with threadpool_limits(limits=1):
+        if t0 < deadline:
+            p = odls.Params(eps=[eps0], **pkw)
+            blocks, _ = odls.plan(piece, p)
+            for b in blocks:
+                if time.time() >= deadline:
+                    break
+                xb = odls.gather(piece, b)
+                odls.encode_block(xb, eps0, p.resolved_rmax(), p.np_dtype)
+                nbytes += xb.nbytes
+                nblk += 1
+    return nbytes, nblk, time.time() - t0
+
+
+def host_cores():
+    """Cores this process may use, at most 16 (one GPU's share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_pool():
+    """Worker processes for the oracle timing, forked before the GPU is
+    touched (a child of a process that holds the device never uses it)."""
+    import multiprocessing as mp
+    n = host_cores()
+    return mp.get_context("fork").Pool(n), n
+
+
+def cpu_baseline(pool, ncores, field, cfg, eps, seconds):
+    """The FP64 oracle, as it stands, on `ncores` processes: pieces of
+    variable 0 (window x z-slab x a strip of py rows, each planned by the
+    oracle on its own), block by block, until ~`seconds` of wall time."""
     W = cfg["window"]
     pz = cfg["pz"] if cfg["nz"] > 1 else 1
-    slabs = [(t0, z0) for t0 in range(0, cfg["nt"], W) for z0 in range(0, cfg["nz"], pz)]
-    done, total, nbytes, nslab = 0, 0, 0, 0
-    with threadpool_limits(limits=1):
-        t0c = time.perf_counter()
-        for (t0, z0) in slabs:
-            w = min(W, cfg["nt"] - t0)
-            sub = field[0:1, t0:t0 + w, z0:z0 + pz].cpu().numpy()
-            p = odls.Params(nx=cfg["nx"], ny=cfg["ny"], nz=sub.shape[2], nt=w, nvars=1, dtype=cfg["dtype"],
-                            px=cfg["px"], py=cfg["py"], pz=pz, window=w, eps=[eps[0]], pmin=cfg.get("pmin", 0),
-                            adaptive=cfg.get("adaptive", False))
-            blocks, _ = odls.plan(sub, p)
-            total += len(blocks)
-            nslab += 1
-            for b in blocks:
-                xb = odls.gather(sub, b)
-                odls.encode_block(xb, eps[0], p.resolved_rmax(), p.np_dtype)
-                done += 1
-                nbytes += xb.nbytes
-                if time.perf_counter() - t0c > seconds:
-                    break
-            if time.perf_counter() - t0c > seconds:
-                break
-        dt = time.perf_counter() - t0c
-    return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": "variable 0, %d window x z-slab pieces in order (each with the oracle's own plan): %d "
-                      "blocks encoded, %.1f MB in %.1f s; full-workload time extrapolates at this rate"
-                      % (nslab, done, nbytes / 1e6, dt)}
+    py = cfg["py"]
+    keys = [(t0, z0, y0) for t0 in range(0, cfg["nt"], W) for z0 in range(0, cfg["nz"], pz)
+            for y0 in range(0, cfg["ny"], py)]
+    keys = keys[:8 * ncores]
+    tasks = []
+    for (t0, z0, y0) in keys:
+        w = min(W, cfg["nt"] - t0)
+        piece = field[0:1, t0:t0 + w, z0:z0 + pz, y0:y0 + py].cpu().numpy()
+        pkw = dict(nx=cfg["nx"], ny=piece.shape[3], nz=piece.shape[2], nt=w, nvars=1, dtype=cfg["dtype"],
+                   px=cfg["px"], py=py, pz=pz, window=w, pmin=cfg.get("pmin", 0),
+                   adaptive=cfg.get("adaptive", False))
+        tasks.append([piece, pkw, float(eps[0]), None])
+    t0w = time.time()
+    deadline = t0w + seconds
+    for t in tasks:
+        t[3] = deadline
+    res = pool.map(_oracle_piece, [tuple(t) for t in tasks], chunksize=1)
+    wall = time.time() - t0w
+    nbytes = sum(r[0] for r in res)
+    nblk = sum(r[1] for r in res)
+    busy = sum(r[2] for r in res)
+    return {"value": round(nbytes / wall / 1e9, 5), "unit": "GB/s", "cores": ncores, "kind": "oracle",
+            "value_per_core": round(nbytes / max(busy, 1e-9) / 1e9, 5),
+            "os_cpu_count": os.cpu_count(), "cpu_model": cpu_model(), "blas_threads_per_process": 1,
+            "sample": "variable 0: %d pieces (%d-step window x %d-deep z-slab x %d-row y strip, whole x), "
+                      "each planned by the oracle on its own, on %d processes; %d blocks encoded, %.1f MB in "
+                      "%.1f s wall; the full workload extrapolates at this rate"
+                      % (len(tasks), W, pz, py, ncores, nblk, nbytes / 1e6, wall)}
 
 
-FORMS = {
-    "plain": "FP32 Gram, full Jacobi eigensolve, host-driven launches",
-    "full": "learned warm start (windows <= 16) + bf16 Gram + device-driven launch",
-}
+def smallest_block_points(cfg):
+    """Points of the plan's smallest possible block: the finest leaf
+    (adaptive) or the patch, truncated where the grid ends mid-patch."""
+    pts = 1
+    for n, pk in ((cfg["nx"], "px"), (cfg["ny"], "py"), (cfg["nz"], "pz")):
+        if n == 1:
+            continue
+        ext = cfg.get("pmin", 0) if cfg.get("adaptive") else cfg[pk]
+        ext = ext or cfg[pk]
+        pts *= min(ext, n % ext) if n % ext else ext
+    return pts
+
+
+def learned_applies(cfg):
+    """The warm start serves windows of <= 16 steps and blocks of at most
+    WARM_MAX_POINTS points; on a plan without such blocks it never runs."""
+    import paper_2601_20113_amd as dls
+    return cfg["window"] <= 16 and smallest_block_points(cfg) <= dls.WARM_MAX_POINTS
 
 
 def params_for(cfg, eps, form):
@@ -134,7 +202,33 @@ def params_for(cfg, eps, form):
                       window=cfg["window"], eps=eps, pmin=cfg.get("pmin", 0),
                       adaptive=cfg.get("adaptive", False),
                       precision="bf16" if full else "fp32",
-                      learned=full and cfg["window"] <= 16, persistent=full)
+                      learned=full and learned_applies(cfg), persistent=full)
+
+
+LAUNCH = {0: "host-driven launches (one per rank class and slice class)",
+          1: "device-driven launch (device-written class lists, one readback)"}
+
+
+def form_label(form, cfg, p, inf):
+    """What the encode actually ran, from its own counters."""
+    parts = ["bf16 Gram operands (FP32 MFMA accumulate, FP64 across chunks)" if p.precision == "bf16"
+             else "FP32 Gram"]
+    if inf.launch_mode == 2:
+        parts.append("single pass: %d of %d blocks verified at rank 1 on the sketch basis and encoded in the "
+                     "same read, %d deferred to Jacobi and a second read" % (inf.nfast_accept, inf.nblocks,
+                                                                            inf.ndeferred))
+    else:
+        if inf.fused_declined:
+            parts.append("single pass declined: the first slices predict %d of %d blocks to fail rank 1 (%d "
+                         "proven), so two-pass" % (inf.npredicted_deferred, inf.nblocks, inf.npruned))
+        parts.append("Jacobi eigensolve; " + LAUNCH[inf.launch_mode])
+    if p.learned:
+        parts.append("learned warm start: %d blocks accepted, %d to Jacobi" % (inf.nwarm_accept, inf.nwarm_reject))
+    elif form == "full":
+        parts.append("no learned warm start (%s)" % (
+            "windows above 16 steps" if cfg["window"] > 16 else
+            "smallest block %d points > %d" % (smallest_block_points(cfg), 256)))
+    return form + ": " + "; ".join(parts)
 
 
 def train_model(cfg, log):
@@ -173,7 +267,9 @@ def train_model(cfg, log):
 
 
 def run_form(field, cfg, eps, form, steps, warmup, model, log):
-    """Time `steps` encodes (after `warmup`); returns the measurements."""
+    """Time `steps` encodes (after `warmup`) between device synchronizations;
+    returns the wall time per step and the averages of the library's own
+    HIP-event times (stages, the fused kernel, the Jacobi launch)."""
     import torch
     import paper_2601_20113_amd as dls
     p = params_for(cfg, eps, form)
@@ -186,6 +282,7 @@ def run_form(field, cfg, eps, form, steps, warmup, model, log):
         enc.encode(field, p, stream=stream)
     torch.cuda.synchronize()
     stage = [0.0] * 5
+    fused = jac = 0.0
     log("%s: timing %d steps" % (form, steps))
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -193,15 +290,25 @@ def run_form(field, cfg, eps, form, steps, warmup, model, log):
         inf = enc.info()
         for i in range(5):
             stage[i] += inf.stage_ms[i]
+        fused += inf.fused_ms
+        jac += inf.jacobi_ms
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
-    return {"enc": enc, "ms": ms, "stage": [s / steps for s in stage], "info": enc.info(), "params": p}
+    return {"enc": enc, "ms": ms, "stage": [s / steps for s in stage], "fused_ms": fused / steps,
+            "jacobi_ms": jac / steps, "info": enc.info(), "params": p,
+            "label": form_label(form, cfg, p, enc.info())}
 
 
-def source_sha():
+KERNEL_SOURCES = {"k_fused": "dls_codec.hip", "k_encode": "dls_codec.hip", "k_decode": "dls_codec.hip",
+                  "k_gram": "dls_kernels.hip", "k_eigen": "dls_kernels.hip"}
+
+
+def source_sha(kernel):
+    """Hash of the sources a kernel is compiled from (its file and the
+    shared device headers)."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("dls_kernels.hip", "dls_device.h", "dls_internal.h"):
+    for name in (KERNEL_SOURCES[kernel], "dls_kernels.h", "dls_device.h", "dls_internal.h"):
         with open(os.path.join(ROOT, "paper_2601_20113_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -217,9 +324,93 @@ def measured_traffic(kernel, workload):
     with open(path) as fh:
         tab = json.load(fh)
     e = tab.get("%s/%s" % (kernel, workload))
-    if not e or e.get("source_sha") != source_sha():
+    if not e or kernel not in KERNEL_SOURCES or e.get("source_sha") != source_sha(kernel):
         return None
     return int(e["fetch_bytes"] + e["write_bytes"])
+
+
+FP64_PEAK_TFLOPS = 78.6
+
+
+def block_shapes(inf):
+    """(points M_b, window W_b) of every block, from the device descriptors."""
+    import numpy as np
+    import paper_2601_20113_amd as dls
+    desc = dls.d2h(inf.d_desc, inf.nblocks * 32).view(np.int32).reshape(inf.nblocks, 8)
+    return desc[:, 6].astype(np.int64), ((desc[:, 4].astype(np.int64) >> 24) & 255)
+
+
+def pad16(x):
+    return (x + 15) // 16 * 16
+
+
+def jacobi_stats(r):
+    """Sweeps, unconverged blocks and the FP64 rate of the Jacobi launch
+    (9 wpad^2 (wpad - 1) flops per sweep of order wpad)."""
+    inf = r["info"]
+    wp = inf.wpad
+    flops = inf.jacobi_sweeps * 9 * wp * wp * (wp - 1)
+    ms = r["jacobi_ms"]
+    tf = flops / (ms * 1e-3) / 1e12 if ms > 0 else None
+    return {"sweeps": int(inf.jacobi_sweeps), "unconverged": int(inf.jacobi_unconverged),
+            "ms": round(ms, 4), "flops": int(flops), "achieved_tflops": None if tf is None else round(tf, 3),
+            "peak_tflops": FP64_PEAK_TFLOPS, "frac": None if tf is None else round(tf / FP64_PEAK_TFLOPS, 4)}
+
+
+def roofline(r, field, workload):
+    """Roofline of the form's dominant kernel: algorithmic bytes (or flops)
+    per launch over the launch's own HIP-event time on the encode stream."""
+    import numpy as np
+    import paper_2601_20113_amd as dls
+    inf, stage = r["info"], r["stage"]
+    es, nvals = field.element_size(), field.numel()
+    in_bytes = nvals * es
+    m, w = block_shapes(inf)
+    if inf.launch_mode == 2 and r["fused_ms"] > 0:
+        # the fused kernel reads the field once and writes every value's
+        # residual code and every block's rank-1 qA and qV
+        alg = in_bytes + nvals + int(np.sum(4 * pad16(m) + 4 * pad16(w)))
+        kern, ms = "k_fused", r["fused_ms"]
+        note = ("field read once + 1 B code per value + rank-1 qA (4 B per point) and qV of every block; "
+                "the 2 KiB FP64 Gram partial per slice is not counted")
+    else:
+        cand = {"k_gram": stage[1], "k_eigen": r["jacobi_ms"], "k_encode": stage[4]}
+        kern = max(cand, key=cand.get)
+        ms = cand[kern]
+        if kern == "k_eigen":
+            j = jacobi_stats(r)
+            return {"kernel": kern, "bound": "alu", "achieved": j["achieved_tflops"], "peak": FP64_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": j["frac"], "traffic": None, "alg_flops_per_launch": j["flops"],
+                    "launch_ms": j["ms"], "note": "FP64 vector peak; 9 wpad^2 (wpad-1) flops per sweep taken"}
+        if kern == "k_gram":
+            alg, note = in_bytes, "field read once"
+        else:
+            rank = dls.d2h(inf.d_rank, inf.nblocks).astype(np.int64)
+            alg = nvals * (es + 1) + inf.qa_bytes + int(np.sum(4 * pad16(w * rank)))
+            note = "field read + 1 B code per value + qA + qV (all rank-class launches of the stage)"
+    ach = alg / (ms * 1e-3) / 1e9
+    return {"kernel": kern, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kern, workload),
+            "alg_bytes_per_launch": int(alg), "launch_ms": round(ms, 4), "note": note}
+
+
+def error_stats(field, out, eps, rel_eps):
+    """Per variable, over every point: max |x - x_hat| / eps and the NRMSE
+    (root-mean-square error over the variable's range), on the device in FP64."""
+    res = []
+    for v in range(field.shape[0]):
+        mx, se, n = 0.0, 0.0, 0
+        for t in range(field.shape[1]):
+            d = out[v, t].double() - field[v, t].double()
+            fin = d.isfinite()
+            d = d.masked_fill(~fin, 0.0)
+            mx = max(mx, d.abs().max().item())
+            se += (d * d).sum().item()
+            n += int(fin.sum().item())
+        rng = eps[v] / rel_eps
+        res.append({"max_abs_err_over_eps": round(mx / eps[v], 6), "within_eps": bool(mx <= eps[v]),
+                    "nrmse": float("%.6g" % (math.sqrt(se / max(n, 1)) / rng))})
+    return res
 
 
 def main():
@@ -233,10 +424,16 @@ def main():
     ap.add_argument("--no-ratio", action="store_true", help="skip the compression ratios (host zlib)")
     ap.add_argument("--forms", default="plain,full")
     ap.add_argument("--no-decode", action="store_true", help="skip the device decode measurement")
+    ap.add_argument("--no-drift", action="store_true",
+                    help="skip the drift variant (modes with a per-step phase drift) of the spectrum workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 4 GiB device-to-device copy twice (the reference the "
                          "HBM byte counters are scaled by) and exit")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: there is no multi-GPU path (blocks are independent; "
+              "a multi-GPU run would give each GPU a contiguous range of windows or z-slabs)", file=sys.stderr)
+        sys.exit(2)
     if args.copy_calibration:
         import torch
         a = torch.empty(1 << 30, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -247,16 +444,16 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4, "copies": 2}))
         return
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(blocks are independent; sharding is described in DESIGN.md)", file=sys.stderr)
-        sys.exit(2)
 
+    # the oracle's worker processes start before anything touches the GPU
+    pool, ncores = (None, 0) if args.no_cpu_baseline else cpu_pool()
+    # host threads of the back-end (device-to-host copy, zlib per batch)
+    os.environ.setdefault("DLS_HOST_THREADS", str(host_cores()))
     import torch
     cfg = CONFIGS[args.config]
     forms = [f for f in args.forms.split(",") if f]
     model = None
-    if "full" in forms and cfg["window"] <= 16:
+    if "full" in forms and learned_applies(cfg):
         log("training the warm-start network")
         model = train_model(cfg, log)
         torch.cuda.empty_cache()
@@ -268,43 +465,25 @@ def main():
         r = run_form(field, cfg, eps, form, args.steps, args.warmup, model, log)
         r["gbs"] = in_bytes / (r["ms"] * 1e-3) / 1e9
         if not args.no_ratio:
-            log("%s: finalize for the compression ratio" % form)
+            log("%s: finalize (device-to-host copy + host zlib) for the compression ratio" % form)
             t1 = time.perf_counter()
             r["cr"] = in_bytes / len(r["enc"].finalize())
-            log("%s: finalize %.1f s" % (form, time.perf_counter() - t1))
+            r["finalize_s"] = time.perf_counter() - t1
+            log("%s: finalize %.2f s" % (form, r["finalize_s"]))
         res[form] = r
-        log("%s: %.3f ms/step, %.1f GB/s, stages %s" % (form, r["ms"], r["gbs"], [round(s, 3) for s in r["stage"]]))
-    head = res["full"] if "full" in res else res[forms[0]]
+        log("%s: %.3f ms/step, %.1f GB/s, stages %s, fused %.3f ms, jacobi %.3f ms; %s"
+            % (form, r["ms"], r["gbs"], [round(x, 3) for x in r["stage"]], r["fused_ms"], r["jacobi_ms"],
+               r["label"]))
     head_form = "full" if "full" in res else forms[0]
-
-    # roofline of the headline form's dominant kernel: algorithmic bytes per
-    # launch over the launch time measured with HIP events on the encode stream
-    es = field.element_size()
-    nvals = field.numel()
-    names = ["plan", "gram", "eigen", "scan", "encode"]
-    stage = head["stage"]
+    head = res[head_form]
     inf = head["info"]
-    dom = max(range(5), key=lambda i: stage[i])
-    if names[dom] == "encode":
-        alg = nvals * (es + 1) + inf.qa_bytes + (inf.qv_bytes if hasattr(inf, "qv_bytes") else 0)
-        kern = "k_encode"
-    elif names[dom] == "gram":
-        alg, kern = nvals * es, "k_gram"
-    else:
-        alg, kern = None, "k_" + names[dom]
-    if alg is not None:
-        ach = alg / (stage[dom] * 1e-3) / 1e9
-        roof = {"kernel": kern, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kern, args.config),
-                "alg_bytes_per_launch": int(alg), "launch_ms": round(stage[dom], 4)}
-    else:
-        roof = {"kernel": kern, "bound": "alu", "achieved": None, "peak": None, "unit": "TFLOP/s",
-                "frac": None, "traffic": None, "launch_ms": round(stage[dom], 4)}
+    roof = roofline(head, field, args.config)
+    names = ["plan", "gram", "eigen", "scan", "encode"]
 
     # device decode (the inverse, Alg. 2) of the headline form's last encode:
     # the context's device payload back to a field, timed with events on the
     # stream the kernels run on; every point checked against the bound
-    dec = None
+    dec, err = None, None
     if not args.no_decode:
         log("device decode of the %s form" % head_form)
         outbuf = torch.empty_like(field)
@@ -319,49 +498,88 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         dms = e0.elapsed_time(e1) / args.steps
-        ok = True
-        for v in range(field.shape[0]):
-            for t in range(field.shape[1]):
-                d = (outbuf[v, t].double() - field[v, t].double()).abs().max().item()
-                ok = ok and d <= eps[v]
+        err = error_stats(field, outbuf, eps, cfg["rel_eps"])
+        ok = all(e["within_eps"] for e in err)
         del outbuf
         torch.cuda.empty_cache()
         # algorithmic bytes: residual codes (1 B/value) and the coefficient
         # payload read, the field written, escapes (16 B each)
-        dalg = nvals * (1 + es) + inf.qa_bytes + 16 * int(inf.nescapes)
+        nvals = field.numel()
+        dalg = nvals * (1 + field.element_size()) + inf.qa_bytes + 16 * int(inf.nescapes)
         dach = dalg / (dms * 1e-3) / 1e9
         dec = {"value": round(in_bytes / (dms * 1e-3) / 1e9, 2), "unit": "GB/s (field bytes out)",
                "ms": round(dms, 4), "bound_holds": bool(ok),
                "roofline": {"kernel": "k_decode", "bound": "hbm", "achieved": round(dach, 1), "peak": HBM_PEAK_GBS,
-                            "unit": "GB/s", "frac": round(dach / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": int(dalg)}}
-        log("decode: %.3f ms, %.1f GB/s out, bound %s" % (dms, dec["value"], "holds" if ok else "VIOLATED"))
+                            "unit": "GB/s", "frac": round(dach / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": int(dalg),
+                            "traffic": measured_traffic("k_decode", args.config)}}
+        log("decode: %.3f ms, %.1f GB/s out, bound %s, error %s" % (dms, dec["value"], "holds" if ok else "VIOLATED",
+                                                                  err))
 
     cpu = None
-    if not args.no_cpu_baseline:
-        log("cpu baseline")
-        cpu = cpu_baseline(field, cfg, eps, args.cpu_seconds)
+    if pool is not None:
+        log("cpu baseline: the FP64 oracle on %d processes" % ncores)
+        cpu = cpu_baseline(pool, ncores, field, cfg, eps, args.cpu_seconds)
+        pool.close()
+        pool.join()
+        log("cpu baseline: %s" % cpu)
 
     out = {
         "metric": METRIC, "value": round(head["gbs"], 2), "unit": "GB/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(head["ms"], 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": cfg["dtype"], "data": "synthetic",
-        "config": {"workload": args.config + ": " + cfg["desc"], "form": head_form + ": " + FORMS[head_form],
+        "config": {"workload": args.config + ": " + cfg["desc"], "form": head["label"],
                    "input_bytes": in_bytes, "blocks": int(inf.nblocks)},
-        "stage_ms": {n: round(s, 4) for n, s in zip(names, stage)},
+        "stage_ms": {n: round(x, 4) for n, x in zip(names, head["stage"])},
+        "kernel_ms": {"k_fused": round(head["fused_ms"], 4), "k_eigen": round(head["jacobi_ms"], 4)},
         "compression_ratio": None if "cr" not in head else round(head["cr"], 3),
         "escapes": int(inf.nescapes),
         "warm_start_accepted": int(inf.nwarm_accept) if head["params"].learned else None,
         "roofline": roof,
-        "cpu_baseline": cpu,
+        "jacobi": jacobi_stats(head),
+        "end_to_end": None if "finalize_s" not in head else {
+            "value": round(in_bytes / (head["ms"] * 1e-3 + head["finalize_s"]) / 1e9, 3), "unit": "GB/s",
+            "finalize_s": round(head["finalize_s"], 3), "host_threads": int(os.environ["DLS_HOST_THREADS"]),
+            "what": "device encode + device-to-host copy of the payload + host zlib (level 6, 1000-block "
+                    "batches) + container"},
+        "error": err,
         "decode": dec,
+        "cpu_baseline": cpu,
     }
     if "plain" in res and head_form != "plain":
         pl = res["plain"]
-        out["plain"] = {"value": round(pl["gbs"], 2), "ms_per_step": round(pl["ms"], 3),
-                        "stage_ms": {n: round(s, 4) for n, s in zip(names, pl["stage"])},
+        out["plain"] = {"value": round(pl["gbs"], 2), "ms_per_step": round(pl["ms"], 3), "form": pl["label"],
+                        "stage_ms": {n: round(x, 4) for n, x in zip(names, pl["stage"])},
+                        "roofline": roofline(pl, field, args.config), "jacobi": jacobi_stats(pl),
                         "compression_ratio": None if "cr" not in pl else round(pl["cr"], 3)}
         out["ratio_vs_plain"] = round(head["gbs"] / pl["gbs"], 4)
+    for r in res.values():
+        r["enc"].close()
+    res.clear()
+
+    # the drift variant: every mode's phase advances per step, so windows
+    # have ranks above 1 (the literal generator is rank 1 in time)
+    if cfg["kind"] == "spectrum" and not args.no_drift:
+        del field
+        torch.cuda.empty_cache()
+        dcfg = dict(cfg, drift=True)
+        log("generating the drift variant of %s" % args.config)
+        field, deps = make_field(dcfg)
+        drift = {"workload": "the same with a per-step phase drift of every mode (U[0, 0.2] rad/step)"}
+        for form in forms:
+            r = run_form(field, dcfg, deps, form, args.steps, args.warmup, model, log)
+            r["gbs"] = in_bytes / (r["ms"] * 1e-3) / 1e9
+            e = {"value": round(r["gbs"], 2), "ms_per_step": round(r["ms"], 3), "form": r["label"],
+                 "stage_ms": {n: round(x, 4) for n, x in zip(names, r["stage"])},
+                 "roofline": roofline(r, field, args.config + "-drift"), "jacobi": jacobi_stats(r)}
+            if not args.no_ratio and form == head_form:
+                e["compression_ratio"] = round(in_bytes / len(r["enc"].finalize()), 3)
+            log("drift %s: %.3f ms/step, %.1f GB/s; %s" % (form, r["ms"], r["gbs"], r["label"]))
+            drift[form] = e
+            r["enc"].close()
+        if "plain" in drift and head_form in drift and head_form != "plain":
+            drift["ratio_vs_plain"] = round(drift[head_form]["value"] / drift["plain"]["value"], 4)
+        out["drift"] = drift
     print(json.dumps(out), flush=True)
 
 

@@ -81,7 +81,9 @@ enum {
                         meets the tolerance (Sec. 2.4 Eq. (4)); the block
                         is then encoded from registers, without a second
                         read of the field.  Blocks that need a higher rank
-                        take the Jacobi eigensolve and a second read.
+                        take the Jacobi eigensolve and a second read; when
+                        the first slice of more than half the blocks
+                        already predicts that, the call runs two-pass.
                         Other plans of up to 65536 slices: no host round
                         trip between the eigensolve and the encode (the
                         encode kernels walk device-written rank-class
@@ -150,6 +152,25 @@ typedef struct dls_encode_info {
                                eigensolve and a second read                 */
   int32_t launch_mode;      /* 0 host-driven, 1 device-driven, 2 fused single
                                pass (see DLS_PERSISTENT)                     */
+  int64_t jacobi_sweeps;    /* sweeps the plain eigensolve took, summed over
+                               the blocks it solved; one sweep of order wpad
+                               costs 9 wpad^2 (wpad - 1) FP64 flops          */
+  int64_t jacobi_unconverged; /* blocks (and warm-start Rayleigh-Ritz solves)
+                               that used every sweep of the cap without off(A)
+                               <= 1e-13 ||A|| before one of them: their basis
+                               is orthonormal, their eigenvalues (so their
+                               rank) may not be converged; the bound holds
+                               regardless                                   */
+  double jacobi_ms;         /* HIP-event time of the Jacobi launch alone      */
+  double fused_ms;          /* fused single pass: HIP-event time of the fused
+                               kernel alone (0 otherwise)                    */
+  int64_t npredicted_deferred; /* DLS_PERSISTENT plans of large FP32 blocks:
+                               blocks whose sketch predicts that the rank-1
+                               basis fails on the whole block               */
+  int64_t npruned;          /* of those, blocks where the sketch alone proves
+                               it (its discarded energy exceeds tau)         */
+  int32_t fused_declined;   /* 1: more than half the blocks were predicted to
+                               fail, so the call ran two-pass                */
 } dls_encode_info;
 
 typedef struct dls_ctx dls_ctx;
@@ -159,6 +180,16 @@ typedef struct dls_ctx dls_ctx;
  * ordinal the context's memory lives on. */
 dls_status dls_ctx_create(int device, dls_ctx** out);
 void dls_ctx_destroy(dls_ctx* ctx);
+
+/* Cap on the sweeps of the plain Jacobi eigensolve (Sec. 2.7.1: the basis
+ * is the eigenvector set of the block's Gram) for later encodes in this
+ * context; default 12, which the tested workloads never reach.  A lower cap
+ * trades eigenvalue accuracy (and with it the rank choice) for time; the
+ * pointwise bound still holds since the residual codes correct any
+ * orthonormal basis.  Blocks that stop at the cap are counted in
+ * dls_encode_info.jacobi_unconverged.  Errors: DLS_EINVAL (NULL context,
+ * max_sweeps outside [1, 64]). */
+dls_status dls_ctx_set_jacobi_sweeps(dls_ctx* ctx, int max_sweeps);
 
 /* Device half of compression (Alg. 1 step 3 for every block): plan, Gram,
  * eigensolve, rank, projection, quantization, lattice reconstruction,

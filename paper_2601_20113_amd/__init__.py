@@ -30,12 +30,14 @@ DLS_PERSISTENT = 4
 DLS_ADAPTIVE = 1
 DLS_LEARNED = 2
 NPARAM = 61968
+WARM_MAX_POINTS = 256   # the warm start applies to blocks of at most this many points
 
 EXPORTS = ["dls_ctx_create", "dls_ctx_destroy", "dls_encode", "dls_encode_info_get", "dls_range",
            "dls_finalize", "dls_compress", "dls_query", "dls_decompress", "dls_stats",
            "dls_free", "dls_last_error", "dls_model_create", "dls_model_destroy", "dls_model_set",
            "dls_model_get", "dls_model_forward", "dls_model_grad", "dls_model_train_step",
-           "dls_features", "dls_ctx_set_model", "dls_decode", "dls_range_noalloc"]
+           "dls_features", "dls_ctx_set_model", "dls_decode", "dls_range_noalloc",
+           "dls_ctx_set_jacobi_sweeps"]
 
 
 class DlsError(RuntimeError):
@@ -64,7 +66,11 @@ class _EncodeInfo(ctypes.Structure):
                 ("d_coef", ctypes.c_void_p), ("nwarm_accept", ctypes.c_int64),
                 ("nwarm_reject", ctypes.c_int64), ("gpu_ms", ctypes.c_double),
                 ("stage_ms", ctypes.c_double * 5), ("nfast_accept", ctypes.c_int64),
-                ("ndeferred", ctypes.c_int64), ("launch_mode", ctypes.c_int32)]
+                ("ndeferred", ctypes.c_int64), ("launch_mode", ctypes.c_int32),
+                ("jacobi_sweeps", ctypes.c_int64), ("jacobi_unconverged", ctypes.c_int64),
+                ("jacobi_ms", ctypes.c_double), ("fused_ms", ctypes.c_double),
+                ("npredicted_deferred", ctypes.c_int64), ("npruned", ctypes.c_int64),
+                ("fused_declined", ctypes.c_int32)]
 
 
 class _StreamStats(ctypes.Structure):
@@ -88,6 +94,7 @@ def lib():
         L.dls_ctx_create.argtypes = [ctypes.c_int, c_void_pp]
         L.dls_ctx_destroy.argtypes = [ctypes.c_void_p]
         L.dls_ctx_destroy.restype = None
+        L.dls_ctx_set_jacobi_sweeps.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.dls_encode.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Params),
                                  ctypes.c_void_p, ctypes.c_int]
         L.dls_encode_info_get.argtypes = [ctypes.c_void_p, ctypes.POINTER(_EncodeInfo)]
@@ -180,6 +187,15 @@ def _stream_handle(stream) -> ctypes.c_void_p:
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _take_bytes(out: ctypes.c_void_p, n: ctypes.c_size_t) -> bytes:
+    """Copy a library-allocated host buffer of n bytes into a bytes object
+    (ctypes.string_at takes a C int length, so streams of 2 GiB and more need
+    this route)."""
+    if n.value == 0:
+        return b""
+    return (ctypes.c_char * n.value).from_address(out.value).raw
+
+
 def _check_field(t: torch.Tensor, p: Params):
     if not t.is_cuda:
         raise ValueError("field must be a device tensor")
@@ -222,6 +238,10 @@ class Encoder:
         self._model = model
         _check(lib().dls_ctx_set_model(self._h, model._h if model is not None else None, iters, margin))
 
+    def set_jacobi_sweeps(self, max_sweeps: int):
+        """Cap the plain eigensolve's sweeps for later encodes (default 12)."""
+        _check(lib().dls_ctx_set_jacobi_sweeps(self._h, int(max_sweeps)))
+
     def _last(self) -> Params:
         p = getattr(self, "_last_params", None)
         if p is None:
@@ -255,7 +275,7 @@ class Encoder:
         n = ctypes.c_size_t()
         _check(lib().dls_finalize(self._h, ctypes.byref(out), ctypes.byref(n)))
         try:
-            return ctypes.string_at(out.value, n.value)
+            return _take_bytes(out, n)
         finally:
             lib().dls_free(out)
 
@@ -281,7 +301,7 @@ def compress(field: torch.Tensor, p: Params, stream=None) -> bytes:
     _check(lib().dls_compress(ctypes.c_void_p(field.data_ptr()), ctypes.byref(cp),
                               _stream_handle(stream), ctypes.byref(out), ctypes.byref(n)))
     try:
-        return ctypes.string_at(out.value, n.value)
+        return _take_bytes(out, n)
     finally:
         lib().dls_free(out)
 

@@ -254,6 +254,8 @@ struct dls_ctx {
   int64_t nfast_accept = 0, ndeferred = 0;
   int64_t nesc_slots = 0;        // escape list entries to read (dropped ones included)
   int launch_mode = 0;           // 0 host-driven, 1 device-driven, 2 fused single pass
+  bool fused_declined = false;   // the sketch predicted too many deferred blocks
+  int64_t npredicted = 0, npruned = 0;
   bool split_valid = false;       // large / small slice lists of the plan
   int64_t split_nlarge = 0, split_nsmall = 0;
   DevBuf split_lists;
@@ -266,6 +268,13 @@ struct dls_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t evs[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // gram, eigen, scan ends; encode start; plan start
   double stage_ms[5] = {0, 0, 0, 0, 0};
+  // around the fused kernel and around the Jacobi launch of the last encode
+  hipEvent_t evf[2] = {nullptr, nullptr}, evj[2] = {nullptr, nullptr};
+  bool fused_timed = false, jacobi_timed = false;
+  double fused_ms = 0.0, jacobi_ms = 0.0;
+  int max_sweeps = kJacobiMaxSweeps;
+  int64_t jacobi_sweeps = 0, jacobi_unconverged = 0;
+  unsigned long long* jstats() { return reinterpret_cast<unsigned long long*>(counters.as<uint8_t>() + kJacobiAt); }
   PlanScratch* plan_scratch = nullptr;
   dls_model* model = nullptr;  // DLS_LEARNED
   int warm_iters = 2;
@@ -293,6 +302,10 @@ struct dls_ctx {
     if (ev1) (void)hipEventDestroy(ev1);
     for (auto& e : evs)
       if (e) (void)hipEventDestroy(e);
+    for (int k = 0; k < 2; ++k) {
+      if (evf[k]) (void)hipEventDestroy(evf[k]);
+      if (evj[k]) (void)hipEventDestroy(evj[k]);
+    }
     plan_scratch_delete(plan_scratch);
     if (pinned) (void)hipHostFree(pinned);
     if (hcnt) (void)hipHostFree(hcnt);
@@ -346,16 +359,19 @@ dls_status learned_eigen(dls_ctx* ctx, const void* d_field, const Problem& p, co
                            ctx->eps_v.as<double>(), p.r_max, ctx->mlp_out.as<float>(), ctx->warm_iters,
                            ctx->warm_margin, ctx->rank.as<uint8_t>(), ctx->lam.as<double>(), ctx->basis.as<double>(),
                            ctx->qv_size.as<int64_t>(), ctx->qa_size.as<int64_t>(), ctx->reject.as<uint8_t>(),
-                           cnt + 2, s));
+                           cnt + 2, ctx->jstats(), s));
   // the fallback Jacobi takes a compacted list of the rejected blocks, so its
   // workgroups are full of real work
   unsigned int* nrej = reinterpret_cast<unsigned int*>(reinterpret_cast<uint8_t*>(cnt) + kRejectCountAt);
   HIP_TRY(ctx->reject_list.ensure(size_t(nb) * sizeof(int32_t)));
   HIP_TRY(launch_compact_flags(ctx->reject.as<uint8_t>(), nb, ctx->reject_list.as<int32_t>(), nrej, s));
+  HIP_TRY(hipEventRecord(ctx->evj[0], s));
   HIP_TRY(launch_eigen(16, ctx->gram.as<double>(), ctx->item_start.as<int32_t>(), ctx->desc.as<BlockDesc>(), nb,
                        ctx->eps_v.as<double>(), p.r_max, ctx->rank.as<uint8_t>(), ctx->lam.as<double>(),
                        ctx->basis.as<double>(), ctx->qv_size.as<int64_t>(), ctx->qa_size.as<int64_t>(), cnt + 1,
-                       ctx->reject_list.as<int32_t>(), nrej, s));
+                       ctx->reject_list.as<int32_t>(), nrej, ctx->jstats(), ctx->max_sweeps, s));
+  HIP_TRY(hipEventRecord(ctx->evj[1], s));
+  ctx->jacobi_timed = true;
   return DLS_OK;
 }
 }  // namespace
@@ -374,6 +390,21 @@ dls_status finish_encode(dls_ctx* ctx) {
     HIP_TRY(hipEventElapsedTime(&ms, marks[i][0], marks[i][1]));
     ctx->stage_ms[i] = ms;
   }
+  ctx->fused_ms = ctx->jacobi_ms = 0.0;
+  if (ctx->fused_timed) {
+    HIP_TRY(hipEventElapsedTime(&ms, ctx->evf[0], ctx->evf[1]));
+    ctx->fused_ms = ms;
+  }
+  if (ctx->jacobi_timed) {
+    HIP_TRY(hipEventElapsedTime(&ms, ctx->evj[0], ctx->evj[1]));
+    ctx->jacobi_ms = ms;
+  }
+  // every path's last full readback of the counter block follows its Jacobi
+  unsigned long long js[1 + kJacobiSlots];
+  std::memcpy(js, ctx->hcnt + kJacobiAt, sizeof(js));
+  ctx->jacobi_unconverged = int64_t(js[0]);
+  ctx->jacobi_sweeps = 0;
+  for (int k = 1; k <= kJacobiSlots; ++k) ctx->jacobi_sweeps += int64_t(js[k]);
   ctx->have_result = true;
   return DLS_OK;
 }
@@ -389,9 +420,19 @@ namespace {
 // reads them again.  On success *done is set; otherwise (payload buffers too
 // small, escape list full) the buffers are grown and the caller encodes the
 // call again two-pass.
+// Fraction of the blocks above which a predicted deferral makes the call run
+// two-pass: on the 512^3 x 48 FP32 workload the single pass costs ~18 ms
+// with every block verified and the deferred blocks' second read and
+// device-driven encode ~23 ms more when all are deferred, against ~29 ms for
+// the two-pass Gram + encode, so the two break even near one half.
+constexpr double kFusedMaxPredictedDeferred = 0.5;
+
 dls_status fused_encode(dls_ctx* ctx, const void* d_field, const Problem& p, const Dims& dims, hipStream_t s,
                         bool* done) {
   *done = false;
+  ctx->fused_declined = false;
+  ctx->npredicted = ctx->npruned = 0;
+  if (int64_t(ctx->plan.items.size()) > int64_t(INT32_MAX)) return DLS_OK;  // one workgroup per slice
   const Plan& pl = ctx->plan;
   const int64_t nb = int64_t(pl.blocks.size()), ni = int64_t(pl.items.size());
   unsigned long long* cnt = ctx->counters.as<unsigned long long>();
@@ -434,25 +475,43 @@ dls_status fused_encode(dls_ctx* ctx, const void* d_field, const Problem& p, con
   const GramSplit first{ctx->item_start.as<int32_t>(), nb, nullptr, 0};
   HIP_TRY(launch_gram(wp, p.dtype, bf16, d_field, dims, ctx->desc.as<BlockDesc>(), ctx->items.as<Item>(), ni, &first,
                       ctx->gram.as<double>(), s));
-  HIP_TRY(launch_sketch_basis(ctx->gram.as<double>(), ctx->item_start.as<int32_t>(), ctx->desc.as<BlockDesc>(), nb,
-                              ctx->r1_off.as<int64_t>(), ctx->rank.as<uint8_t>(), ctx->lam.as<double>(),
-                              ctx->basis.as<double>(), ctx->qv_size.as<int64_t>(), ctx->qa_size.as<int64_t>(),
-                              ctx->qv_off.as<int64_t>(), ctx->qa_off.as<int64_t>(), fs.state, s));
-  HIP_TRY(launch_fused(bf16, int(std::min<int64_t>(ni, INT32_MAX)), static_cast<const float*>(d_field), dims,
+  HIP_TRY(launch_sketch_basis(ctx->gram.as<double>(), ctx->item_start.as<int32_t>(), ctx->items.as<Item>(),
+                              ctx->desc.as<BlockDesc>(), nb, ctx->eps_v.as<double>(), ctx->r1_off.as<int64_t>(),
+                              ctx->rank.as<uint8_t>(), ctx->lam.as<double>(), ctx->basis.as<double>(),
+                              ctx->qv_size.as<int64_t>(), ctx->qa_size.as<int64_t>(), ctx->qv_off.as<int64_t>(),
+                              ctx->qa_off.as<int64_t>(), fs.state, fs.counters, s));
+  // the sketch's prediction decides the form: a deferred block costs the
+  // single pass a second read and encode, so when more than a fraction of the
+  // blocks is predicted to fail verification the call runs two-pass
+  HIP_TRY(hipMemcpyAsync(ctx->hfused + 2, fs.counters, kFusedNCounters * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  ctx->npredicted = int64_t(ctx->hfused[2 + kFusedLikely]);
+  ctx->npruned = int64_t(ctx->hfused[2 + kFusedPruned]);
+  if (double(ctx->npredicted) > kFusedMaxPredictedDeferred * double(nb)) {
+    ctx->fused_declined = true;
+    return DLS_OK;
+  }
+  HIP_TRY(hipEventRecord(ctx->evf[0], s));
+  HIP_TRY(launch_fused(bf16, static_cast<const float*>(d_field), dims,
                        ctx->desc.as<BlockDesc>(),
                        ctx->items.as<Item>(), ni, ctx->vconst.as<VarConst>(), ctx->gram.as<double>(), fs.state,
                        ctx->basis.as<double>(), ctx->qv_off.as<int64_t>(), ctx->qa_off.as<int64_t>(),
                        ctx->code_off.as<int64_t>(), ctx->qv.as<uint8_t>(), ctx->qa.as<uint8_t>(),
                        ctx->codes.as<uint8_t>(), ctx->keep_coef ? ctx->coef.as<float>() : nullptr, esc, s));
+  HIP_TRY(hipEventRecord(ctx->evf[1], s));
+  ctx->fused_timed = true;
   HIP_TRY(hipEventRecord(ctx->evs[0], s));
   HIP_TRY(launch_verify(ctx->gram.as<double>(), ctx->item_start.as<int32_t>(), ctx->desc.as<BlockDesc>(), nb,
                         ctx->eps_v.as<double>(), ctx->basis.as<double>(), ctx->lam.as<double>(), fs, s));
   // deferred blocks: Jacobi, payload regions after the rank-1 ones, their
   // slices encoded device-driven
+  HIP_TRY(hipEventRecord(ctx->evj[0], s));
   HIP_TRY(launch_eigen(wp, ctx->gram.as<double>(), ctx->item_start.as<int32_t>(), ctx->desc.as<BlockDesc>(), nb,
                        ctx->eps_v.as<double>(), p.r_max, ctx->rank.as<uint8_t>(), ctx->lam.as<double>(),
                        ctx->basis.as<double>(), ctx->qv_size.as<int64_t>(), ctx->qa_size.as<int64_t>(), cnt + 1,
-                       fs.deferred, fs.ndeferred, s));
+                       fs.deferred, fs.ndeferred, ctx->jstats(), ctx->max_sweeps, s));
+  HIP_TRY(hipEventRecord(ctx->evj[1], s));
+  ctx->jacobi_timed = true;
   HIP_TRY(hipEventRecord(ctx->evs[1], s));
   HIP_TRY(launch_alloc_deferred(fs.deferred, fs.ndeferred, nb, ctx->qv_size.as<int64_t>(), ctx->qa_size.as<int64_t>(),
                                 fs.counters, ctx->plan_qv_r1, ctx->plan_qa_r1, ctx->qv_off.as<int64_t>(),
@@ -537,8 +596,19 @@ dls_status dls_ctx_create(int device, dls_ctx** out) {
   HIP_TRY(hipEventCreate(&c->ev0));
   HIP_TRY(hipEventCreate(&c->ev1));
   for (auto& e : c->evs) HIP_TRY(hipEventCreate(&e));
+  for (int k = 0; k < 2; ++k) {
+    HIP_TRY(hipEventCreate(&c->evf[k]));
+    HIP_TRY(hipEventCreate(&c->evj[k]));
+  }
   c->plan_scratch = plan_scratch_new();
   *out = c.release();
+  return DLS_OK;
+}
+
+dls_status dls_ctx_set_jacobi_sweeps(dls_ctx* ctx, int max_sweeps) {
+  if (ctx == nullptr) return fail(DLS_EINVAL, "ctx is NULL");
+  if (max_sweeps < 1 || max_sweeps > 64) return fail(DLS_EINVAL, "max_sweeps must lie in [1, 64]");
+  ctx->max_sweeps = max_sweeps;
   return DLS_OK;
 }
 
@@ -557,6 +627,9 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
   hipStream_t s = static_cast<hipStream_t>(stream);
   HIP_TRY(hipSetDevice(ctx->device));
   ctx->have_result = false;
+  ctx->fused_timed = ctx->jacobi_timed = false;
+  ctx->fused_declined = false;
+  ctx->npredicted = ctx->npruned = 0;
   HIP_TRY(hipEventRecord(ctx->evs[4], s));
   const bool adaptive = (p.flags & DLS_ADAPTIVE) != 0;
   if (adaptive) {
@@ -696,6 +769,7 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
     if (dls_status st = fused_encode(ctx, d_field, p, dims, s, &done)) return st;
     if (done) return finish_encode(ctx);
     ctx->nfast_accept = ctx->ndeferred = 0;  // this call is encoded again two-pass
+    ctx->fused_timed = ctx->jacobi_timed = false;
     HIP_TRY(hipEventRecord(ctx->ev0, s));
   }
   HIP_TRY(launch_gram(wp, p.dtype, p.precision == DLS_PREC_BF16, d_field, dims, ctx->desc.as<BlockDesc>(),
@@ -708,10 +782,13 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
   if (learned && warm_any) {
     if (dls_status st = learned_eigen(ctx, d_field, p, dims, s)) return st;
   } else {
+    HIP_TRY(hipEventRecord(ctx->evj[0], s));
     HIP_TRY(launch_eigen(wp, ctx->gram.as<double>(), ctx->item_start.as<int32_t>(), ctx->desc.as<BlockDesc>(),
                          nb, ctx->eps_v.as<double>(), p.r_max, ctx->rank.as<uint8_t>(), ctx->lam.as<double>(),
                          ctx->basis.as<double>(), ctx->qv_size.as<int64_t>(), ctx->qa_size.as<int64_t>(),
-                         cnt + 1, nullptr, nullptr, s));
+                         cnt + 1, nullptr, nullptr, ctx->jstats(), ctx->max_sweeps, s));
+    HIP_TRY(hipEventRecord(ctx->evj[1], s));
+    ctx->jacobi_timed = true;
   }
   HIP_TRY(hipEventRecord(ctx->evs[1], s));
   HIP_TRY(launch_scan(ctx->qv_size.as<int64_t>(), nb, ctx->qv_off.as<int64_t>(), ctx->scan_tmp.as<int64_t>(), s));
@@ -1050,6 +1127,13 @@ dls_status dls_encode_info_get(const dls_ctx* ctx, dls_encode_info* info) {
   info->nfast_accept = ctx->nfast_accept;
   info->ndeferred = ctx->ndeferred;
   info->launch_mode = ctx->launch_mode;
+  info->npredicted_deferred = ctx->npredicted;
+  info->npruned = ctx->npruned;
+  info->fused_declined = ctx->fused_declined ? 1 : 0;
+  info->jacobi_sweeps = ctx->jacobi_sweeps;
+  info->jacobi_unconverged = ctx->jacobi_unconverged;
+  info->jacobi_ms = ctx->jacobi_ms;
+  info->fused_ms = ctx->fused_ms;
   info->gpu_ms = ctx->gpu_ms;
   for (int i = 0; i < 5; ++i) info->stage_ms[i] = ctx->stage_ms[i];
   return DLS_OK;

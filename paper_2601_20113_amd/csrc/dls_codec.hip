@@ -564,8 +564,9 @@ void decode_launch(const dim3& g, const dim3& bl, hipStream_t s, void* F, const 
 //   formed beforehand by k_gram -- by power iteration from the column of the
 //   largest diagonal entry; q becomes column 0 of the block's basis, the
 //   block's payload regions are the rank-1 ones at their static offsets.
-// k_fused: slices i = blockIdx.x, + gridDim.x, ... (one workgroup per slice
-//   as launched: hardware dispatch keeps the slices in flight contiguous).
+// k_fused: slice i = blockIdx.x (one workgroup per slice: hardware dispatch
+//   keeps the slices in flight contiguous, and nothing computed before the
+//   slice's work has to stay live across a loop).
 //   Every slice is read once into registers, its Gram partial
 //   is formed on the matrix cores (FP32 or bf16 operands, FP64 across
 //   64-point chunks) and stored, and the slice is encoded at rank 1 with its
@@ -581,12 +582,15 @@ void decode_launch(const dim3& g, const dim3& bl, hipStream_t s, void* F, const 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_sketch_basis(const double* __restrict__ gpart,
                                                       const int32_t* __restrict__ item_start,
+                                                      const Item* __restrict__ items,
                                                       const BlockDesc* __restrict__ desc, int64_t nblocks,
+                                                      const double* __restrict__ eps_v,
                                                       const int64_t* __restrict__ r1_off, uint8_t* __restrict__ rank,
                                                       double* __restrict__ lam, double* __restrict__ basis,
                                                       int64_t* __restrict__ qv_size, int64_t* __restrict__ qa_size,
                                                       int64_t* __restrict__ qv_off, int64_t* __restrict__ qa_off,
-                                                      unsigned int* __restrict__ state) {
+                                                      unsigned int* __restrict__ state,
+                                                      unsigned long long* __restrict__ counters) {
   constexpr int WP = 16;
   __shared__ double sG[16][WP][WP + 1];
   __shared__ double sq[16][WP];
@@ -614,6 +618,7 @@ __global__ __launch_bounds__(256) void k_sketch_basis(const double* __restrict__
   wave_sync();
   fin = row_sum(fin ? 0.0 : 1.0) == 0.0;
   double qi = row == 0 ? 1.0 : 0.0;
+  bool pruned = false, likely = true;
   if (fin) {
     int istar = 0;
     double best = sG[grp][0][0];
@@ -640,6 +645,23 @@ __global__ __launch_bounds__(256) void k_sketch_basis(const double* __restrict__
     for (int j = 0; j < WP; ++j)
       if (fabs(sq[grp][j]) > bq) { bq = fabs(sq[grp][j]); sg = sq[grp][j] < 0.0 ? -1.0 : 1.0; }
     qi *= sg;
+    // the sketch's discarded energy under q, E_s = trace(G_s) - q^T G_s q,
+    // is a lower bound of the whole block's (the other points add a PSD
+    // Gram), so E_s > tau (by a margin over the FP32 accumulation error of
+    // G_s) rules rank 1 out; E_s scaled to the block's points predicts it
+    double y = 0.0, di = 0.0;
+#pragma unroll
+    for (int j = 0; j < WP; ++j) {
+      y = fma(a[j], sq[grp][j], y);  // G_s q, q as staged (before the sign)
+      di = j == row ? a[j] : di;
+    }
+    const double tr = row_sum(di);
+    const double es = tr - row_sum(sq[grp][row] * y);
+    const double eps = eps_v[d.var];
+    const double tau = kKappa * eps * eps * double(d.m) * double(d.w());
+    const int ms = items[item_start[b]].np;
+    pruned = es > 2.0 * tau + 1e-4 * tr;
+    likely = es * double(d.m) > tau * double(ms);
   }
   double* bb = basis + b * WP * WP;
   bb[row] = qi;  // column 0 at [0][t]; the other columns are not formed
@@ -652,7 +674,14 @@ __global__ __launch_bounds__(256) void k_sketch_basis(const double* __restrict__
     qa_size[b] = 4 * pad16(int64_t(d.m));
     qv_off[b] = r1_off[b];
     qa_off[b] = r1_off[nblocks + b];
-    state[b] = fin ? 0u : 3u;  // 3: no usable sketch, the block is left to the two-pass path
+    state[b] = fin && !pruned ? 0u : 3u;  // 3: the block is left to the two-pass path
+  }
+  // one atomic per wavefront for each count
+  const uint64_t lk = __ballot(row == 0 && likely), pr = __ballot(row == 0 && fin && pruned);
+  const int lane = int(threadIdx.x & 63);
+  if (lane == __ffsll((unsigned long long)__ballot(1)) - 1) {
+    if (lk) atomicAdd(counters + kFusedLikely, (unsigned long long)__popcll(lk));
+    if (pr) atomicAdd(counters + kFusedPruned, (unsigned long long)__popcll(pr));
   }
 }
 
@@ -675,7 +704,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
   const int tid = int(threadIdx.x), lane = tid & 63, wave = tid >> 6;
   const int tl = lane & 15, q = lane >> 4;
   constexpr uint64_t kSpeculative = uint64_t(1) << 63;
-  for (int64_t i = blockIdx.x; i < nitems; i += gridDim.x) {
+  {
+    const int64_t i = blockIdx.x;  // one slice per workgroup (the grid covers every slice)
+    if (i >= nitems) return;
     const Item it = items[i];
     const int b = it.block;
     const BlockDesc d = desc[b];
@@ -734,11 +765,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
       for (int v = 0; v < 4; ++v)
         out[(4 * q + v) * WP + tl] = ((red[0][v][lane] + red[1][v][lane]) + red[2][v][lane]) + red[3][v][lane];
     }
-    // the slice encoded at rank 1 with its block's sketch basis
+    // the slice encoded at rank 1 with its block's sketch basis (the
+    // constants copied to registers: a reference into global memory would be
+    // reloaded after every store the encode makes)
+    const VarConst K = vc[d.var];
     if (st_b == 0u)
-      encode_values<WP, float, PPT, 1, 256, true>(tid, it, b, d, 1, vc[d.var], ps0, valid, x, Vf, Qv, basis, qv_off,
+      encode_values<WP, float, PPT, 1, 256, true>(tid, it, b, d, 1, K, ps0, valid, x, Vf, Qv, basis, qv_off,
                                                   qa_off, code_off, qv_buf, qa_buf, codes, coef, esc, kSpeculative);
-    __syncthreads();  // LDS of this slice is free again
   }
 }
 
@@ -839,22 +872,26 @@ __global__ __launch_bounds__(256) void k_fix_escapes(uint64_t* __restrict__ key,
 #endif
 
 #if DLS_CODEC_PART == 3
-hipError_t launch_sketch_basis(const double* gpart, const int32_t* item_start, const BlockDesc* desc, int64_t nblocks,
-                               const int64_t* r1_off, uint8_t* rank, double* lam, double* basis, int64_t* qv_size,
-                               int64_t* qa_size, int64_t* qv_off, int64_t* qa_off, unsigned int* state, hipStream_t s) {
+hipError_t launch_sketch_basis(const double* gpart, const int32_t* item_start, const Item* items,
+                               const BlockDesc* desc, int64_t nblocks, const double* eps_v, const int64_t* r1_off,
+                               uint8_t* rank, double* lam, double* basis, int64_t* qv_size, int64_t* qa_size,
+                               int64_t* qv_off, int64_t* qa_off, unsigned int* state, unsigned long long* counters,
+                               hipStream_t s) {
   if (nblocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sketch_basis, dim3{unsigned((nblocks + 15) / 16)}, dim3{256}, 0, s, gpart, item_start, desc,
-                     nblocks, r1_off, rank, lam, basis, qv_size, qa_size, qv_off, qa_off, state);
+  hipLaunchKernelGGL(k_sketch_basis, dim3{unsigned((nblocks + 15) / 16)}, dim3{256}, 0, s, gpart, item_start, items,
+                     desc, nblocks, eps_v, r1_off, rank, lam, basis, qv_size, qa_size, qv_off, qa_off, state,
+                     counters);
   return hipGetLastError();
 }
 
-hipError_t launch_fused(bool bf16, int grid, const float* F, const Dims& dims, const BlockDesc* desc,
+hipError_t launch_fused(bool bf16, const float* F, const Dims& dims, const BlockDesc* desc,
                         const Item* items, int64_t nitems, const VarConst* vc, double* gpart,
                         const unsigned int* state, const double* basis, const int64_t* qv_off, const int64_t* qa_off,
                         const int64_t* code_off, uint8_t* qv, uint8_t* qa, uint8_t* codes, float* coef, EscOut esc,
                         hipStream_t s) {
   if (nitems == 0) return hipSuccess;
-  const dim3 g{unsigned(grid)}, bl{256};
+  if (nitems > int64_t(INT32_MAX)) return hipErrorInvalidValue;  // one workgroup per slice
+  const dim3 g{unsigned(nitems)}, bl{256};
   if (bf16)
     hipLaunchKernelGGL(k_fused<true>, g, bl, 0, s, F, dims, desc, items, nitems, vc, gpart, state, basis, qv_off,
                        qa_off, code_off, qv, qa, codes, coef, esc);

@@ -40,13 +40,20 @@ struct EncodeWork {
 // Layout of the per-encode counter block: four u64 (escapes, raw blocks,
 // warm starts accepted, rejected), kEncodeClasses u32 class counts, the u32
 // overflow flag of a device-driven encode, the u32 count of the fallback
-// list, and the two i64 payload totals (qV bytes, qA bytes).
+// list, the two i64 payload totals (qV bytes, qA bytes), and the Jacobi
+// statistics: the u64 count of blocks that reached the sweep cap
+// unconverged, then kJacobiSlots u64 partial sums of the sweeps taken (slot
+// = workgroup index mod kJacobiSlots, so the atomics spread over addresses).
 constexpr int kRankClasses = 6;  // r <= 1, 2, 4, 8, 16, 32
 constexpr int kEncodeClasses = 2 * kRankClasses;  // then the same for small slices
 constexpr size_t kOverflowAt = 4 * 8 + kEncodeClasses * 4;
 constexpr size_t kRejectCountAt = kOverflowAt + 4;  // u32: blocks the warm start left to Jacobi
 constexpr size_t kTotalsAt = 88;
-constexpr size_t kCounterBytes = kTotalsAt + 16;
+constexpr size_t kJacobiAt = kTotalsAt + 16;
+constexpr int kJacobiSlots = 64;
+constexpr size_t kCounterBytes = kJacobiAt + (1 + kJacobiSlots) * 8;
+// sweeps the plain eigensolve takes at most unless the context sets another cap
+constexpr int kJacobiMaxSweeps = 12;
 // largest slice (points) the small-slice encode takes: its team of lanes x PPT
 int encode_small_limit(int wp, int dtype);
 
@@ -77,12 +84,14 @@ DLS_CODEC_DECL(w32_f64)
 // for plans whose blocks all span at least one full slice, W <= 16, FP32.
 // Per-call state, cleared before the launch: per block a verdict (0 sketch
 // basis usable, 1 verified at rank 1, 2 deferred to the two-pass path, 3 no
-// usable sketch), the list of deferred blocks, and u64 counters: payload
-// cursors of the deferred blocks (after the rank-1 regions), blocks verified
-// at rank 1, escapes dropped.
+// usable sketch or rank 1 ruled out by the sketch alone), the list of
+// deferred blocks, and u64 counters: payload cursors of the deferred blocks
+// (after the rank-1 regions), blocks verified at rank 1, escapes dropped,
+// blocks the sketch predicts to fail verification, blocks it rules out.
 constexpr int kFusedIters = 6;          // power steps of the sketch's basis after its start column
 constexpr int kFusedMinPoints = 1024;   // every block of the plan at least this large
-constexpr int kFusedQvCursor = 0, kFusedQaCursor = 1, kFusedAccepted = 2, kFusedDropped = 3, kFusedNCounters = 4;
+constexpr int kFusedQvCursor = 0, kFusedQaCursor = 1, kFusedAccepted = 2, kFusedDropped = 3, kFusedLikely = 4,
+              kFusedPruned = 5, kFusedNCounters = 6;
 struct FusedState {
   unsigned int* state;            // [nblocks]
   int32_t* deferred;              // [nblocks]
@@ -90,10 +99,12 @@ struct FusedState {
   unsigned long long* counters;   // kFusedNCounters
 };
 // r1_off: [nblocks] static qV offsets then [nblocks] static qA offsets of the rank-1 payload
-hipError_t launch_sketch_basis(const double* gpart, const int32_t* item_start, const BlockDesc* desc, int64_t nblocks,
-                               const int64_t* r1_off, uint8_t* rank, double* lam, double* basis, int64_t* qv_size,
-                               int64_t* qa_size, int64_t* qv_off, int64_t* qa_off, unsigned int* state, hipStream_t s);
-hipError_t launch_fused(bool bf16, int grid, const float* F, const Dims& dims, const BlockDesc* desc,
+hipError_t launch_sketch_basis(const double* gpart, const int32_t* item_start, const Item* items,
+                               const BlockDesc* desc, int64_t nblocks, const double* eps_v, const int64_t* r1_off,
+                               uint8_t* rank, double* lam, double* basis, int64_t* qv_size, int64_t* qa_size,
+                               int64_t* qv_off, int64_t* qa_off, unsigned int* state, unsigned long long* counters,
+                               hipStream_t s);
+hipError_t launch_fused(bool bf16, const float* F, const Dims& dims, const BlockDesc* desc,
                         const Item* items, int64_t nitems, const VarConst* vc, double* gpart,
                         const unsigned int* state, const double* basis, const int64_t* qv_off, const int64_t* qa_off,
                         const int64_t* code_off, uint8_t* qv, uint8_t* qa, uint8_t* codes, float* coef, EscOut esc,
@@ -124,11 +135,14 @@ struct GramSplit {
 hipError_t launch_gram(int wp, int dtype, bool bf16, const void* F, const Dims& dims, const BlockDesc* desc,
                        const Item* items, int64_t nitems, const GramSplit* split, double* gpart, hipStream_t s);
 // list (may be NULL): solve only the *list_count blocks list[0..) (a
-// device-written list; the grid covers nblocks, the rest exits at once)
+// device-written list; the grid covers nblocks, the rest exits at once).
+// At most max_sweeps sweeps per block; jstats (the Jacobi statistics of the
+// counter block) is added to.
 hipError_t launch_eigen(int wp, const double* gpart, const int32_t* item_start, const BlockDesc* desc,
                         int64_t nblocks, const double* eps_v, int r_max, uint8_t* rank, double* lam,
                         double* basis, int64_t* qv_size, int64_t* qa_size, unsigned long long* nraw,
-                        const int32_t* list, const unsigned int* list_count, hipStream_t s);
+                        const int32_t* list, const unsigned int* list_count, unsigned long long* jstats,
+                        int max_sweeps, hipStream_t s);
 // list of the blocks b < n with flag[b] != 0, in any order; *count is added to
 hipError_t launch_compact_flags(const uint8_t* flag, int64_t n, int32_t* list, unsigned int* count, hipStream_t s);
 // learned warm start (dls_learned.hip)
@@ -177,7 +191,8 @@ hipError_t launch_mlp_forward(const float* raw, int64_t n, const float* norm, co
 hipError_t launch_warmstart(const double* gpart, const int32_t* item_start, const BlockDesc* desc, int64_t nblocks,
                             const double* eps_v, int r_max, const float* mlp_out, int iters, int margin,
                             uint8_t* rank, double* lam, double* basis, int64_t* qv_size, int64_t* qa_size,
-                            uint8_t* reject, unsigned long long* counters, hipStream_t s);
+                            uint8_t* reject, unsigned long long* counters, unsigned long long* jstats,
+                            hipStream_t s);
 hipError_t launch_scan(const int64_t* in, int64_t n, int64_t* out, int64_t* tmp, hipStream_t s);
 // Allocation-free range: the partials live in a fixed device array (one per
 // GPU) whose address range_scratch() returns for the current device;

@@ -338,6 +338,22 @@ __global__ __launch_bounds__(256) void k_gram_wave(const T* __restrict__ F, Dims
 // its own row and its partner's.  A group only touches its own LDS and its
 // lanes are active together, so no workgroup barrier is used.
 // ---------------------------------------------------------------------------
+// off(A) <= 1e-13 ||A|| (squared: 1e-26), A's rows held one per lane of a
+// WP-lane group, positions in natural order
+template <int WP>
+__device__ __forceinline__ bool jacobi_converged(const double (&a)[WP], int i) {
+  double off = 0.0, tot = 0.0;
+#pragma unroll
+  for (int j = 0; j < WP; ++j) {
+    const double x = a[j] * a[j];
+    tot += x;
+    off += (j == i) ? 0.0 : x;
+  }
+  off = group_sum<WP>(off);
+  tot = group_sum<WP>(tot);
+  return !(off > 1e-26 * tot);
+}
+
 template <int WP>
 __global__ __launch_bounds__(256) void k_eigen(const double* __restrict__ gpart,
                                                const int32_t* __restrict__ item_start,
@@ -350,7 +366,8 @@ __global__ __launch_bounds__(256) void k_eigen(const double* __restrict__ gpart,
                                                int64_t* __restrict__ qa_size,
                                                unsigned long long* __restrict__ nraw,
                                                const int32_t* __restrict__ list,
-                                               const unsigned int* __restrict__ list_count) {
+                                               const unsigned int* __restrict__ list_count,
+                                               unsigned long long* __restrict__ jstats, int max_sweeps) {
   constexpr int GPW = 256 / WP;
   constexpr int LD = WP + 1;
   __shared__ double sA[GPW][WP * LD];
@@ -402,18 +419,16 @@ __global__ __launch_bounds__(256) void k_eigen(const double* __restrict__ gpart,
     return;
   }
 
-  for (int sweep = 0; sweep < 12; ++sweep) {
-    // positions are in natural order at a sweep boundary
-    double off = 0.0, tot = 0.0;
-#pragma unroll
-    for (int j = 0; j < WP; ++j) {
-      const double x = a[j] * a[j];
-      tot += x;
-      off += (j == i) ? 0.0 : x;
+  // the convergence test runs before every sweep; a block that uses every
+  // sweep of the cap is counted as unconverged (its last sweep unchecked: a
+  // test after the loop costs W = 32 a wave of occupancy)
+  int sweep = 0;
+  bool converged = false;
+  for (; sweep < max_sweeps; ++sweep) {
+    if (jacobi_converged<WP>(a, i)) {
+      converged = true;
+      break;
     }
-    off = group_sum<WP>(off);
-    tot = group_sum<WP>(tot);
-    if (!(off > 1e-26 * tot)) break;
     // W = 32 keeps one step per iteration: unrolled, its rows need all 256
     // registers (one wave per SIMD)
     constexpr int kUnroll = WP == 16 ? DLS_JACOBI_UNROLL : 1;
@@ -521,6 +536,8 @@ __global__ __launch_bounds__(256) void k_eigen(const double* __restrict__ gpart,
     rank_out[b] = uint8_t(r);
     qv_size[b] = 4 * pad16(int64_t(W) * r);
     qa_size[b] = 4 * pad16(int64_t(M) * r);
+    if (sweep) atomicAdd(jstats + 1 + blockIdx.x % kJacobiSlots, (unsigned long long)sweep);
+    if (!converged) atomicAdd(jstats, 1ull);
   }
 }
 
@@ -818,15 +835,16 @@ hipError_t launch_gram(int wp, int dtype, bool bf16, const void* F, const Dims& 
 hipError_t launch_eigen(int wp, const double* gpart, const int32_t* item_start, const BlockDesc* desc,
                         int64_t nblocks, const double* eps_v, int r_max, uint8_t* rank, double* lam,
                         double* basis, int64_t* qv_size, int64_t* qa_size, unsigned long long* nraw,
-                        const int32_t* list, const unsigned int* list_count, hipStream_t s) {
+                        const int32_t* list, const unsigned int* list_count, unsigned long long* jstats,
+                        int max_sweeps, hipStream_t s) {
   if (nblocks == 0) return hipSuccess;
   const dim3 bl{256};
   if (wp == 16)
     hipLaunchKernelGGL(k_eigen<16>, dim3{unsigned((nblocks + 15) / 16)}, bl, 0, s, gpart, item_start, desc, nblocks,
-                       eps_v, r_max, rank, lam, basis, qv_size, qa_size, nraw, list, list_count);
+                       eps_v, r_max, rank, lam, basis, qv_size, qa_size, nraw, list, list_count, jstats, max_sweeps);
   else
     hipLaunchKernelGGL(k_eigen<32>, dim3{unsigned((nblocks + 7) / 8)}, bl, 0, s, gpart, item_start, desc, nblocks,
-                       eps_v, r_max, rank, lam, basis, qv_size, qa_size, nraw, list, list_count);
+                       eps_v, r_max, rank, lam, basis, qv_size, qa_size, nraw, list, list_count, jstats, max_sweeps);
   return hipGetLastError();
 }
 

@@ -625,13 +625,14 @@ __device__ __forceinline__ void orth_rows(double (&q)[kWarmMax], int r, int W, i
 
 // Cyclic Jacobi with the round-robin ordering on the leading n x n block of
 // H (LDS, leading dimension kWarmMax + 1), n <= kWarmMax, rotations
-// accumulated into U.  The 16 lanes of one group call it together.
-__device__ void jacobi_group(double* H, double* U, double* alpha, double* beta, int* partner, int n, int t) {
+// accumulated into U.  The 16 lanes of one group call it together; false
+// when kJacobiMaxSweeps sweeps left it unconverged.
+__device__ bool jacobi_group(double* H, double* U, double* alpha, double* beta, int* partner, int n, int t) {
   constexpr int LD = kWarmMax + 1;
-  if (n <= 1) return;
+  if (n <= 1) return true;
   const int ne = n + (n & 1);
   const int nn = ne * ne;
-  for (int sweep = 0; sweep < 12; ++sweep) {
+  for (int sweep = 0;; ++sweep) {
     double off = 0.0, tot = 0.0;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -645,7 +646,8 @@ __device__ void jacobi_group(double* H, double* U, double* alpha, double* beta, 
     }
     off = row_sum(off);
     tot = row_sum(tot);
-    if (!(off > 1e-26 * tot)) break;
+    if (!(off > 1e-26 * tot)) return true;
+    if (sweep >= kJacobiMaxSweeps) return false;
     for (int step = 0; step < ne - 1; ++step) {
       if (t < ne / 2) {
         int p = rr_player(t, step, ne), q = rr_player(ne - 1 - t, step, ne);
@@ -703,7 +705,8 @@ __global__ __launch_bounds__(256) void k_warmstart(const double* __restrict__ gp
                                                    uint8_t* __restrict__ rank_out, double* __restrict__ lam_out,
                                                    double* __restrict__ basis_out, int64_t* __restrict__ qv_size,
                                                    int64_t* __restrict__ qa_size, uint8_t* __restrict__ reject,
-                                                   unsigned long long* __restrict__ counters) {
+                                                   unsigned long long* __restrict__ counters,
+                                                   unsigned long long* __restrict__ jstats) {
   constexpr int RH = kWarmMax, LQ = RH, LH = RH + 1;
   __shared__ double sQ[16][16 * LQ];
   __shared__ double sH[16][RH * LH], sU[16][RH * LH];
@@ -804,7 +807,7 @@ __global__ __launch_bounds__(256) void k_warmstart(const double* __restrict__ gp
           }
         }
       wave_sync();
-      jacobi_group(H, U, sAl[grp], sBe[grp], sPa[grp], nc, t);
+      if (!jacobi_group(H, U, sAl[grp], sBe[grp], sPa[grp], nc, t) && t == 0) atomicAdd(jstats, 1ull);
       // descending order of the Ritz values (stable by index)
       if (t < nc) {
         const double dk = H[t * LH + t];
@@ -975,12 +978,13 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
 hipError_t launch_warmstart(const double* gpart, const int32_t* item_start, const BlockDesc* desc, int64_t nblocks,
                             const double* eps_v, int r_max, const float* mlp_out, int iters, int margin,
                             uint8_t* rank, double* lam, double* basis, int64_t* qv_size, int64_t* qa_size,
-                            uint8_t* reject, unsigned long long* counters, hipStream_t s) {
+                            uint8_t* reject, unsigned long long* counters, unsigned long long* jstats,
+                            hipStream_t s) {
   if (nblocks == 0) return hipSuccess;
   for (int retry = 0; retry < 2; ++retry)
     hipLaunchKernelGGL(k_warmstart, dim3{unsigned((nblocks + 15) / 16)}, dim3{256}, 0, s, gpart, item_start, desc,
                        nblocks, eps_v, r_max, mlp_out, iters, margin, retry, rank, lam, basis, qv_size, qa_size,
-                       reject, counters);
+                       reject, counters, jstats);
   return hipGetLastError();
 }
 

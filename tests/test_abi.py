@@ -96,3 +96,24 @@ def test_invalid_params_rejected_before_device_work(L):
                           ctypes.byref(ctypes.c_size_t()))
     assert st == L.DLS_EINVAL
     assert b"struct_size" in lib.dls_last_error()
+
+
+def test_null_context_refused(L):
+    """Entry points that take a context refuse NULL before any device call."""
+    lib = L.lib()
+    assert lib.dls_ctx_set_jacobi_sweeps(None, 4) == L.DLS_EINVAL
+    assert lib.dls_encode(None, ctypes.c_void_p(16), None, None, 0) == L.DLS_EINVAL
+    info = L._EncodeInfo()
+    assert lib.dls_encode_info_get(None, ctypes.byref(info)) == L.DLS_EINVAL
+
+
+def test_large_host_buffer_copied_whole(L):
+    """Streams of 2 GiB and more come back whole (ctypes.string_at takes a C
+    int length, which wraps there)."""
+    n = (1 << 31) + 4096
+    buf = ctypes.create_string_buffer(n)
+    ctypes.memset(ctypes.addressof(buf) + n - 3, 0x5A, 3)
+    b = L._take_bytes(ctypes.c_void_p(ctypes.addressof(buf)), ctypes.c_size_t(n))
+    assert len(b) == n and b[-3:] == b"\x5a\x5a\x5a" and b[0] == 0
+    del b, buf
+    assert L._take_bytes(ctypes.c_void_p(None), ctypes.c_size_t(0)) == b""

@@ -21,6 +21,9 @@ it fails), in FP32 and in bf16-Gram mode:
   ratio within 1 % of the oracle's;
 * escapes the single pass wrote for blocks it then deferred are dropped (a
   NaN, a huge outlier), those of verified blocks kept (a moderate bump);
+* a block the sketch alone rules out is deferred; when more than half the
+  blocks are predicted to fail (every variable drifting) the call runs
+  two-pass and matches the plain oracle;
 * two encodes give the same stream; a field that needs more payload than the
   buffers hold is encoded again two-pass, with the same guarantees.
 """
@@ -41,7 +44,10 @@ pytestmark = pytest.mark.gpu
 
 
 def _field(drift, seeds=(11, 12), nx=72, ny=64, nz=48, nt=40):
-    f = np.concatenate([synth.spectrum(nx, ny, nz, nt, nmodes=16, seed=s, drift=drift) for s in seeds])
+    """drift: False (every variable rank 1 in time), True (every variable
+    drifting), or a tuple of per-variable flags."""
+    flags = drift if isinstance(drift, tuple) else (drift,) * len(seeds)
+    f = np.concatenate([synth.spectrum(nx, ny, nz, nt, nmodes=16, seed=s, drift=d) for s, d in zip(seeds, flags)])
     e = [1e-3 * r for r in synth.range_of(f)]
     p = odls.Params(nx=nx, ny=ny, nz=nz, nt=nt, nvars=len(seeds), dtype="f32", px=32, py=32, pz=32,
                     window=16, eps=e)
@@ -61,8 +67,12 @@ def _check(f, p, precision, enc=None):
     enc.encode(t, _lib_params(p, precision), keep_coef=True)
     inf = enc.info()
     nb, wp = inf.nblocks, inf.wpad
-    print("launch mode %d: %d blocks, %d solved at rank 1 in the single pass, %d deferred"
-          % (inf.launch_mode, nb, inf.nfast_accept, inf.ndeferred), flush=True)
+    print("launch mode %d: %d blocks, %d solved at rank 1 in the single pass, %d deferred; sketch: %d predicted "
+          "to fail, %d ruled out, declined %d" % (inf.launch_mode, nb, inf.nfast_accept, inf.ndeferred,
+                                                  inf.npredicted_deferred, inf.npruned, inf.fused_declined),
+          flush=True)
+    assert inf.npruned <= inf.npredicted_deferred <= nb
+    assert bool(inf.fused_declined) == (inf.npredicted_deferred > nb / 2)
     rank = dls.d2h(inf.d_rank, nb).copy()
     basis = dls.d2h(inf.d_basis, nb * wp * wp * 8).view(np.float64).reshape(nb, wp, wp).copy()
     qa_off = dls.d2h(inf.d_qa_off, nb * 8).view(np.int64).copy()
@@ -114,6 +124,8 @@ def _check(f, p, precision, enc=None):
     assert not errs or max(errs) <= 1e-5
     if inf.launch_mode == 2:
         assert inf.nfast_accept + inf.ndeferred == nb
+        # a block the sketch rules out is one the whole block fails
+        assert inf.ndeferred >= inf.npruned
     stream = enc.finalize()
     out = dls.decompress(stream).cpu().numpy()
     fin = np.isfinite(f)
@@ -137,22 +149,40 @@ def _check(f, p, precision, enc=None):
     return enc, stream
 
 
+MIXED = (False, False, True)   # two rank-1 variables and one drifting: a third of the blocks deferred
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
-@pytest.mark.parametrize("drift", [False, True], ids=["rank1", "drift"])
+@pytest.mark.parametrize("drift", [False, MIXED], ids=["rank1", "mixed"])
 def test_fused_parity(drift, precision):
     print("fused single pass, drift %s, %s" % (drift, precision), flush=True)
-    f, p = _field(drift)
+    f, p = _field(drift, seeds=(11, 12, 13) if drift else (11, 12))
     enc, _ = _check(f, p, precision)
     # the same context again: buffers fit now, the single pass is used
     enc2, s2 = _check(f, p, precision, enc)
-    assert enc2.info().launch_mode == 2
+    inf = enc2.info()
+    assert inf.launch_mode == 2
+    if drift:
+        assert 0 < inf.ndeferred < inf.nblocks / 2
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_fused_declined_when_most_blocks_fail(precision):
+    """Every variable drifting: the sketch predicts most blocks to fail, so
+    the call runs two-pass (the plain method, against the plain oracle)."""
+    print("fused single pass declined, %s" % precision, flush=True)
+    f, p = _field(True)
+    enc, _ = _check(f, p, precision)
+    inf = enc.info()
+    assert inf.fused_declined == 1 and inf.launch_mode != 2 and inf.nfast_accept == 0
+    assert inf.npredicted_deferred > inf.nblocks / 2
 
 
 def test_fused_deterministic_and_regrows():
     """Two encodes of one field give one stream; a field with more payload
     than the buffers hold (higher ranks) is encoded again two-pass on the
     first call and in a single pass on the next."""
-    f1, p1 = _field(False)
+    f1, p1 = _field(False, seeds=(21, 22, 23))
     enc = dls.Encoder()
     t = torch.from_numpy(f1).cuda()
     lp = _lib_params(p1, "fp32")
@@ -161,23 +191,33 @@ def test_fused_deterministic_and_regrows():
     enc.encode(t, lp)
     assert enc.info().launch_mode == 2
     assert enc.finalize() == a
-    f2, p2 = _field(True, seeds=(21, 22))
+    f2, p2 = _field(MIXED, seeds=(21, 22, 23))
     _, _ = _check(f2, p2, "fp32", enc)
+    assert enc.info().launch_mode != 2     # the deferred blocks' payload did not fit
     _, _ = _check(f2, p2, "fp32", enc)
+    assert enc.info().launch_mode == 2
 
 
 def test_fused_escapes_kept_and_dropped():
     """A moderate bump in a verified block escapes and is kept; a NaN and a
     1e9 outlier make their blocks fail verification, so the escapes the
     single pass wrote for them are dropped and the two-pass path encodes
-    them again (the NaN block raw)."""
+    them again (the NaN block raw); a block whose sketch is noisy is ruled
+    out before the single pass encodes it."""
     f, p = _field(False)
     f = f.copy()
     e0 = p.eps[0]
     f[0, 3, 5, 40, 37] += 300.0 * e0          # block (var 0, window 0, patch (1, 1, 0)): stays rank 1
     f[0, 20, 40, 10, 10] = np.nan             # window 1, a slice after the sketch's
     f[1, 2, 1, 1, 70] = 1e9                   # var 1, window 0, inside the sketch
+    # broadband noise of 30 eps over the sketch (the first z-plane) of block
+    # (var 0, window 0, patch (1, 0, 0)): the sketch alone rules rank 1 out
+    rng = np.random.default_rng(5)
+    f[0, 0:16, 0, 0:32, 32:64] += (30.0 * e0 * rng.standard_normal((16, 32, 32))).astype(np.float32)
     enc, _ = _check(f, p, "fp32")            # first call: the deferred blocks need more room
     enc, _ = _check(f, p, "fp32", enc)       # then the single pass, dropping their escapes
     inf = enc.info()
-    assert inf.launch_mode == 2 and inf.ndeferred >= 2 and inf.nraw == 1 and inf.nescapes > 0
+    assert inf.launch_mode == 2 and inf.ndeferred >= 3 and inf.nraw == 1 and inf.nescapes > 0
+    # the noisy sketch rules its block out; the outlier's sketch does not
+    # resolve its discarded energy against the outlier's (tr ~ 1e18)
+    assert inf.npruned >= 1

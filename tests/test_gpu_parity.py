@@ -68,6 +68,22 @@ def _case(name):
         e = 1e-3 * synth.range_of(f)
         return f, odls.Params(nx=96, ny=80, nz=1, nt=20, nvars=1, dtype="f32", px=32, py=32, pz=1,
                               window=16, eps=list(e), pmin=4, adaptive=True)
+    if name == "adaptive_oct_f32_2var":
+        # FP32, rows of a multiple of 4 points: the single-read plan, ragged
+        # in y and z
+        f = np.concatenate([_bumps3d(36, 30, 22, 8, seed=s) for s in (3, 4)]).astype(np.float32)
+        e = [1e-3 * r for r in synth.range_of(f)]
+        return f, odls.Params(nx=36, ny=30, nz=22, nt=8, nvars=2, dtype="f32", px=16, py=16, pz=16,
+                              window=8, eps=e, pmin=4, adaptive=True)
+    if name == "adaptive_ramp_ties_f32":
+        # a linear ramp: every gradient magnitude is 1, so 2^20 + points tie
+        # on the order statistic (more than the single-read path's candidate
+        # list holds): the stored-gradient selection finishes it
+        nx, ny, nz = 128, 96, 96
+        x = np.arange(nx, dtype=np.float32)[None, None, None, :]
+        f = np.broadcast_to(x * np.float32(0.5), (1, 2, nz, ny, nx)).astype(np.float32).copy()
+        return f, odls.Params(nx=nx, ny=ny, nz=nz, nt=2, nvars=1, dtype="f32", px=32, py=32, pz=32,
+                              window=2, eps=[1e-3 * 63.5], pmin=8, adaptive=True)
     if name == "adaptive_oct_f64_2var":
         f = np.concatenate([_bumps3d(36, 28, 20, 12, seed=s) for s in (1, 2)])
         e = [1e-3 * r for r in synth.range_of(f)]
@@ -206,18 +222,25 @@ def test_value_range_matches_numpy():
         assert lo[v] == x.min() and hi[v] == x.max()
 
 
-@pytest.mark.parametrize("name", ["adaptive_quad_f32_96x80x20", "adaptive_oct_f64_2var"])
+@pytest.mark.parametrize("name", ["adaptive_quad_f32_96x80x20", "adaptive_oct_f64_2var", "adaptive_oct_f32_2var",
+                                  "adaptive_ramp_ties_f32"])
 def test_adaptive_plan_matches_oracle(name):
-    """Split bits and the block list (origins, extents, windows) are identical."""
+    """Split bits and the block list (origins, extents, windows) are identical:
+    on the stored-gradient plan (FP64), the single-read plan (FP32, 2D and 3D,
+    ragged) and the single-read plan's fallback (a tie of every point)."""
+    print("case", name, flush=True)
     f, p = _case(name)
-    enc = odls.encode(f, p)
+    blocks, split_bits = odls.plan(f, p)
     g = H.GpuRun(f, p)
     _, bits, nb, _, _ = container.parse_header(g.stream)
-    assert bits == enc.split_bits
-    assert sum(enc.split_bits[0]) > 0
+    assert bits == split_bits
+    if name != "adaptive_ramp_ties_f32":
+        assert all(sum(b) > 0 for b in split_bits)
+    else:
+        assert sum(split_bits[0]) == 0
     inf = g.enc.info()
     desc = dls.d2h(inf.d_desc, nb * 32).view(np.int32).reshape(nb, 8)
-    for b, blk in enumerate(enc.blocks):
+    for b, blk in enumerate(blocks):
         ext = desc[b, 4]
         got = (desc[b, 0], desc[b, 1], desc[b, 2], desc[b, 3], ext & 255, (ext >> 8) & 255,
                (ext >> 16) & 255, (ext >> 24) & 255, desc[b, 5])

@@ -9,7 +9,8 @@ decodable zlib stream (deflate, level 6 -- gzip's algorithm, Sec. 2.5) per
 batch.
 
 Header (little-endian):
-    char[4] "DLS1"; u32 version=2; u32 header_bytes; u32 flags (bit0 adaptive)
+    char[4] "DLS1"; u32 version=2; u32 header_bytes; u32 flags (bit0 adaptive,
+    bit1 L2 mode: eps holds the per-variable NRMSE targets, see oracle.l2)
     i32 ndim, nvars, dtype (0 f32, 1 f64), r_max
     i64 nx, ny, nz, nt
     i32 px, py, pz, pmin, window, batch_blocks
@@ -28,6 +29,13 @@ Uncompressed batch payload for blocks [b0, b0 + nb):
     codes      per block, u8 codes[t][p] (one plane)
     escapes    escaped input values of the batch, block then (t, p) order,
                in the storage dtype
+
+L2 mode (flag bit 1), uncompressed batch payload:
+    ranks      nb x u8 (255 = raw block, values verbatim)
+    steps      nb x f64 (coefficient step d; 0 for rank 0 and raw blocks)
+    qV         per block, zigzag(int32) of qV[k][t] (k < r, t < W_b), 4 planes
+    qA         per block, zigzag(int32) of qA[k][p] (k < r, p < M_b), 4 planes
+    raw        the raw blocks' values, block then (t, p) order, storage dtype
 """
 from __future__ import annotations
 
@@ -36,7 +44,7 @@ import zlib
 
 import numpy as np
 
-from . import dls
+from . import dls, l2
 
 MAGIC = b"DLS1"
 VERSION = 2
@@ -118,6 +126,121 @@ def pack(enc: "dls.Encoded") -> bytes:
     return fixed + eps + plan_bytes + tab + b"".join(streams)
 
 
+def _pack(p, nb, bits, payloads, flags):
+    streams, table = [], []
+    off = 0
+    for raw in payloads:
+        z = zlib.compress(raw, ZLIB_LEVEL)
+        streams.append(z)
+        table.append((off, len(z), len(raw)))
+        off += len(z)
+    plan_bytes = b"".join(_bits_bytes(bits[v] if p.adaptive else []) for v in range(p.nvars))
+    hdr_len = (_FIXED.size + 8 * p.nvars + len(plan_bytes) + 24 * len(payloads))
+    fixed = _FIXED.pack(MAGIC, VERSION, hdr_len, flags,
+                        p.ndim, p.nvars, 0 if p.dtype == "f32" else 1,
+                        p.resolved_rmax(), p.nx, p.ny, p.nz, p.nt,
+                        p.px, p.py, p.pz, p.pmin, p.window, dls.BATCH_BLOCKS,
+                        nb, len(payloads), 0)
+    eps = struct.pack("<%dd" % p.nvars, *[float(e) for e in p.eps])
+    tab = b"".join(struct.pack("<QQQ", *t) for t in table)
+    return fixed + eps + plan_bytes + tab + b"".join(streams)
+
+
+def l2_batch_payload(codes, dtype) -> bytes:
+    """Uncompressed payload of one L2-mode batch (list of l2.L2Code)."""
+    parts = [bytes(np.array([c.r for c in codes], np.uint8)),
+             np.array([c.step for c in codes], "<f8").tobytes()]
+    for c in codes:
+        if c.r != l2.RAW:
+            parts.append(planes(zigzag32(c.qV.T.ravel()), 4))
+    for c in codes:
+        if c.r != l2.RAW:
+            parts.append(planes(zigzag32(c.qA.T.ravel()), 4))
+    for c in codes:
+        if c.r == l2.RAW:
+            parts.append(np.asarray(c.raw, dtype=np.dtype(dtype).newbyteorder("<")).tobytes())
+    return b"".join(parts)
+
+
+def pack_l2(enc: "l2.L2Encoded") -> bytes:
+    p = enc.params
+    nb = len(enc.blocks)
+    payloads = [l2_batch_payload(enc.codes[i:i + dls.BATCH_BLOCKS], p.np_dtype)
+                for i in range(0, nb, dls.BATCH_BLOCKS)]
+    return _pack(p, nb, enc.split_bits, payloads, (1 if p.adaptive else 0) | 2)
+
+
+def stream_flags(buf: bytes) -> int:
+    if len(buf) < _FIXED.size:
+        raise CorruptStream("stream shorter than the fixed header")
+    return _FIXED.unpack_from(buf, 0)[3]
+
+
+def _batches(buf, p, bits, nblocks, table, hdr_len):
+    if p.adaptive:
+        try:
+            lv = [dls.leaves_from_bits(p, bits[v]) for v in range(p.nvars)]
+        except StopIteration:
+            raise CorruptStream("split bits exhausted")
+    else:
+        lv = [dls.uniform_leaves(p)] * p.nvars
+    blocks = dls.make_blocks(p, lv)
+    if len(blocks) != nblocks:
+        raise CorruptStream("block count mismatch")
+    if len(table) != (nblocks + dls.BATCH_BLOCKS - 1) // dls.BATCH_BLOCKS:
+        raise CorruptStream("batch count mismatch")
+    for i, (off, csz, usz) in enumerate(table):
+        s = hdr_len + off
+        if s + csz > len(buf):
+            raise CorruptStream("batch beyond end of stream")
+        try:
+            raw = zlib.decompress(buf[s:s + csz])
+        except zlib.error as e:
+            raise CorruptStream("zlib: %s" % e)
+        if len(raw) != usz:
+            raise CorruptStream("batch size mismatch")
+        yield blocks, blocks[i * dls.BATCH_BLOCKS:(i + 1) * dls.BATCH_BLOCKS], raw
+
+
+def unpack_l2(buf: bytes) -> "l2.L2Encoded":
+    p, bits, nblocks, table, hdr_len = parse_header(buf)
+    if not stream_flags(buf) & 2:
+        raise CorruptStream("not an L2-mode stream")
+    dtype = p.np_dtype
+    esz = np.dtype(dtype).itemsize
+    codes, blocks = [], []
+    for blocks, bl, raw in _batches(buf, p, bits, nblocks, table, hdr_len):
+        nb = len(bl)
+        pos = 0
+
+        def take(n):
+            nonlocal pos
+            if pos + n > len(raw):
+                raise CorruptStream("batch payload truncated")
+            out = raw[pos:pos + n]
+            pos += n
+            return out
+        ranks = np.frombuffer(take(nb), np.uint8)
+        steps = np.frombuffer(take(8 * nb), "<f8")
+        for b, r in zip(bl, ranks):
+            if r != l2.RAW and r > min(p.resolved_rmax(), b.w):
+                raise CorruptStream("rank out of range")
+        rk = [0 if r == l2.RAW else int(r) for r in ranks]
+        qVs = [unzigzag32(unplanes(take(4 * r * b.w), r * b.w, 4, np.uint32)).reshape(r, b.w).T
+               for b, r in zip(bl, rk)]
+        qAs = [unzigzag32(unplanes(take(4 * r * b.m), r * b.m, 4, np.uint32)).reshape(r, b.m).T
+               for b, r in zip(bl, rk)]
+        for j, b in enumerate(bl):
+            rv = None
+            if ranks[j] == l2.RAW:
+                rv = np.frombuffer(take(esz * b.w * b.m), dtype=np.dtype(dtype).newbyteorder("<")).astype(dtype)
+                rv = rv.reshape(b.w, b.m)
+            codes.append(l2.L2Code(int(ranks[j]), float(steps[j]), qVs[j], qAs[j], rv))
+        if pos != len(raw):
+            raise CorruptStream("trailing bytes in batch")
+    return l2.L2Encoded(p, blocks, codes, bits, np.zeros(p.nvars))
+
+
 def parse_header(buf: bytes):
     """(Params, split bits per var, nblocks, batch table, header length)."""
     if len(buf) < _FIXED.size:
@@ -159,6 +282,8 @@ def parse_header(buf: bytes):
 
 def unpack(buf: bytes) -> "dls.Encoded":
     p, bits, nblocks, table, hdr_len = parse_header(buf)
+    if stream_flags(buf) & 2:
+        raise CorruptStream("an L2-mode stream (decode with oracle.l2)")
     if p.adaptive:
         try:
             lv = [dls.leaves_from_bits(p, bits[v]) for v in range(p.nvars)]

@@ -13,7 +13,7 @@ from fractions import Fraction
 import numpy as np
 
 import synth
-from oracle import container, dls
+from oracle import container, dls, l2
 from oracle.jacobi import cyclic_jacobi
 
 SHAPES = [(16, 64), (16, 16), (4, 64), (32, 128), (5, 7), (1, 9), (16, 512)]
@@ -494,11 +494,139 @@ def pin_rank_one_single_pass():
     assert not ok and code.r >= 2
 
 
+# -- L2 / NRMSE-bounded mode (oracle.l2) -----------------------------------
+def _l2_gold():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "l2_block_2x2.json")
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def pin_l2_eckart_young():
+    """The eigenvalue tail after r modes is the squared error of the rank-r
+    projection (Eckart-Young), computed directly."""
+    rng = np.random.default_rng(3)
+    for W, M, rank in [(6, 40, 6), (8, 30, 3), (5, 5, 5)]:
+        X = rng.standard_normal((W, rank)) @ rng.standard_normal((rank, M)) + 1e-3 * rng.standard_normal((W, M))
+        lam, V = dls.eig_desc(X @ X.T)
+        tail = dls.tail_energies(lam)
+        for r in range(W + 1):
+            Vr = V[:, :r]
+            R = X - Vr @ (Vr.T @ X)
+            assert abs(float(np.sum(R * R)) - tail[r]) <= 1e-10 * float(np.sum(X * X)), (W, M, r)
+
+
+def _l2_hand(target):
+    u = np.array([[2.0, 0.0], [0.0, 1.0]]).reshape(1, 2, 1, 1, 2)
+    p = dls.Params(nx=2, ny=1, nz=1, nt=2, nvars=1, dtype="f64", px=2, py=1, pz=1, window=2, eps=[target])
+    return u, p
+
+
+def pin_l2_hand_case():
+    """The one-block field of tests/golden/l2_block_2x2.json, worked by hand
+    (cases A and B) and the rank rule's hand cases."""
+    g = _l2_gold()
+    for target, e in ((g["inputs"]["target"], g["expected"]), (g["inputs"]["target_b"], g["expected"]["b"])):
+        u, p = _l2_hand(target)
+        enc = l2.encode(u, p)
+        c = enc.codes[0]
+        assert abs(c.e2 - e["e2"]) <= 1e-12 * e["e2"]
+        assert c.r == e["rank"]
+        # decimal hand values fix the numbers to ~1e-15, not the last bit of FP64
+        assert abs(c.step - e["step"]) <= 1e-14 * e["step"]
+        qa = e["qA"] if isinstance(e["qA"][0], list) else [[q] for q in e["qA"]]
+        assert c.qA.tolist() == qa
+        if "qV" in e:
+            assert c.qV[:, 0].tolist() == e["qV"]
+        out = l2.reconstruct(enc)
+        assert np.allclose(out.reshape(2, 2), np.array(e["out"]), rtol=1e-14, atol=0.0)
+        assert abs(c.err - e["err"]) <= 1e-8
+    u, p = _l2_hand(g["inputs"]["target"])
+    assert abs(l2.nrmse_fraction(u, l2.reconstruct(l2.encode(u, p))) - g["expected"]["nrmse"]) <= 1e-4
+    for e2, r in g["expected"]["rank_rule"]:
+        assert l2.first_rank(np.array([4.0, 1.0]), e2, 2) == r, (e2, r)
+
+
+def pin_l2_budgets_sum():
+    """sum_b e2_b = (eps_t ||u||)^2: the block budgets are equal shares of
+    the variable's squared global budget."""
+    f = synth.blobs2d(nx=70, ny=45, nt=37, seed=3, nblobs=6)
+    p = dls.Params(nx=70, ny=45, nz=1, nt=37, nvars=1, dtype="f64", px=16, py=16, pz=1, window=16,
+                   eps=[0.01], pmin=4, adaptive=True)
+    blocks, _ = dls.plan(f, p)
+    c = l2.variable_budgets(f, p.eps)
+    total = sum(l2.block_budget(c[b.var], b) for b in blocks)
+    want = (0.01 ** 2) * float(np.sum(f.astype(np.float64) ** 2))
+    assert abs(total - want) <= 1e-12 * want
+
+
+def _l2_fields():
+    a = synth.blobs2d(nx=48, ny=40, nt=20, seed=4, nblobs=8, dtype=np.float32)
+    pa = dict(nx=48, ny=40, nz=1, nt=20, nvars=1, dtype="f32", px=16, py=8, pz=1, window=16)
+    b = np.concatenate([synth.spectrum(20, 18, 12, 14, nmodes=12, seed=s, drift=True) for s in (5, 6)])
+    pb = dict(nx=20, ny=18, nz=12, nt=14, nvars=2, dtype="f32", px=8, py=8, pz=8, window=8)
+    return [(a, pa), (b, pb)]
+
+
+def pin_l2_bound_and_round_trip(targets=(1e-2, 1e-4)):
+    """Every block's exact error within its budget, every variable's NRMSE
+    within its target, the stream reproduces the decoded field bit for bit;
+    in bf16-Gram mode a smooth field at 1e-3 needs no raw block (the
+    projection reads the exact values)."""
+    for target in targets:
+        for f, kw in _l2_fields():
+            p = dls.Params(eps=[target] * kw["nvars"], **kw)
+            enc = l2.encode(f, p)
+            out = l2.reconstruct(enc)
+            for b, c in zip(enc.blocks, enc.codes):
+                xb = dls.gather(f, b).astype(np.float64)
+                ob = dls.gather(out, b).astype(np.float64)
+                assert float(np.sum((xb - ob) ** 2)) <= c.e2
+            for v in range(p.nvars):
+                assert l2.nrmse_fraction(f[v], out[v]) <= target
+            assert np.array_equal(l2.decompress(container.pack_l2(enc)).view(np.uint8), out.view(np.uint8))
+    f, kw = _l2_fields()[1]
+    enc = l2.encode(f, dls.Params(eps=[1e-3] * kw["nvars"], precision="bf16", **kw))
+    assert all(c.r != l2.RAW for c in enc.codes)
+    assert all(l2.nrmse_fraction(f[v], l2.reconstruct(enc)[v]) <= 1e-3 for v in range(kw["nvars"]))
+
+
+def pin_l2_ranks_grow():
+    """A tighter target never takes fewer modes on average."""
+    f, kw = _l2_fields()[1]
+    means = []
+    for target in (1e-1, 1e-2, 1e-3):
+        enc = l2.encode(f, dls.Params(eps=[target] * kw["nvars"], **kw))
+        means.append(np.mean([c.r for c in enc.codes if c.r != l2.RAW]))
+    assert means[0] < means[1] < means[2]
+
+
+def pin_l2_special_blocks():
+    """A non-finite block is raw and returned exactly; a zero block takes
+    rank 0; a target below the 2^-24 basis grid makes the block raw."""
+    f = synth.blobs2d(nx=16, ny=8, nt=8, seed=7, nblobs=3)
+    f[0, :, 0, :, 8:] = 0.0
+    f[0, 3, 0, 2, 1] = np.nan
+    p = dls.Params(nx=16, ny=8, nz=1, nt=8, nvars=1, dtype="f64", px=8, py=8, pz=1, window=8, eps=[1e-2])
+    enc = l2.encode(f, p)
+    assert [c.r for c in enc.codes] == [l2.RAW, 0]
+    out = l2.reconstruct(enc)
+    assert np.array_equal(np.isnan(out), np.isnan(f))
+    assert np.array_equal(np.nan_to_num(out), np.nan_to_num(f))
+    g = synth.blobs2d(nx=8, ny=8, nt=8, seed=8, nblobs=2) + 10.0
+    q = dls.Params(nx=8, ny=8, nz=1, nt=8, nvars=1, dtype="f64", px=8, py=8, pz=1, window=8, eps=[1e-12])
+    enc = l2.encode(g, q)
+    assert enc.codes[0].r == l2.RAW
+    assert np.array_equal(l2.reconstruct(enc), g)
+
+
 ALL_PINS = [
     pin_eigenvalues_vs_svd, pin_eigenvectors_orthonormal_and_residual,
     pin_eigenvalues_vs_jacobi, pin_rank_bruteforce, pin_exact_rank_data,
     pin_pointwise_bound, pin_escapes_rare_on_smooth_data, pin_escape_threshold, pin_lattice_one_rounding,
     pin_hand_worked_rank_one, pin_special_blocks, pin_gradient_and_percentile,
     pin_adaptive_plan, pin_container_round_trip, pin_round_bf16, pin_moments_hand_case,
-    pin_nrmse_hand_case, pin_sign_tie, pin_rank_one_single_pass,
+    pin_nrmse_hand_case, pin_sign_tie, pin_rank_one_single_pass, pin_l2_eckart_young, pin_l2_hand_case,
+    pin_l2_budgets_sum, pin_l2_bound_and_round_trip, pin_l2_ranks_grow, pin_l2_special_blocks,
 ]

@@ -14,9 +14,9 @@ import pytest
 
 sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
 import oracle_pins as P  # noqa: E402
-from oracle import dls, learned  # noqa: E402
+from oracle import dls, l2, learned  # noqa: E402
 
-MODULES = {"dls": dls, "learned": learned}
+MODULES = {"dls": dls, "learned": learned, "l2": l2}
 
 # (function, original text, planted mistake); functions of oracle.learned are
 # prefixed "learned."
@@ -59,6 +59,21 @@ MUTATIONS = [
     ("lattice_values", "n = S + q * (1 << RES_SHIFT)", "n = S + q * (1 << (RES_SHIFT - 1))"),
     ("zigzag8", "-2 * q - 1", "-2 * q + 1"),
     ("encode_with_basis", "big = np.abs(q) > Q_LIMIT", "big = np.abs(q) > 2 * Q_LIMIT"),
+    ("l2.first_rank", "tau = TAIL_SHARE * e2", "tau = 0.4 * e2"),
+    ("l2.first_rank", "if tail[0] <= tau:", "if tail[1] <= tau:"),
+    ("l2.first_rank", "for r in range(1, rcap + 1):", "for r in range(2, rcap + 1):"),
+    ("l2.encode_block", "step = STEP_SHARE * math.sqrt(e2 / (r * m))", "step = STEP_SHARE * math.sqrt(e2 / m)"),
+    ("l2.encode_block", "qV = np.rint(Vr * 2.0 ** BASIS_BITS).astype(np.int64)",
+     "qV = np.rint(Vr * 2.0 ** 16).astype(np.int64)"),
+    ("l2.encode_block", "A = x.T @ Vr", "A = xg.T @ Vr"),
+    ("l2.decode_block", "vt = qV[:, k].astype(np.float64) * 2.0 ** -BASIS_BITS",
+     "vt = qV[:, k].astype(np.float64) * 2.0 ** -16"),
+    ("l2.decode_block", "ck = qA[:, k].astype(np.float64) * step", "ck = qA[:, k].astype(np.float64) / step"),
+    ("l2.variable_budgets", "c.append(float(targets[v]) ** 2 * norm2 / float(field[v].size))",
+     "c.append(float(targets[v]) * norm2 / float(field[v].size))"),
+    ("l2.block_budget", "return c_v * b.m * b.w", "return c_v * b.m"),
+    ("l2.nrmse_fraction", "return float(np.sqrt(np.sum(d * d)) / np.sqrt(np.sum(np.where(fin, a * a, 0.0))))",
+     "return float(np.sum(d * d) / np.sum(np.where(fin, a * a, 0.0)))"),
 ]
 
 

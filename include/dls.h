@@ -72,7 +72,7 @@ enum {
   DLS_LEARNED = 2,   /* warm-started eigensolve with the model attached by
                         dls_ctx_set_model (window <= 16); blocks whose
                         prediction fails the rank test fall back to Jacobi */
-  DLS_PERSISTENT = 4 /* batched launch.  Plans whose blocks all span at
+  DLS_PERSISTENT = 4, /* batched launch.  Plans whose blocks all span at
                         least 1024 points (FP32, window <= 16): one fused
                         persistent launch reads every slice once into
                         registers, forms its Gram, and the slice that
@@ -93,6 +93,24 @@ enum {
                         the call again two-pass.  The stream decodes to
                         the same guarantees; its rank-1 bases come from the
                         power iteration instead of Jacobi. */
+  DLS_L2 = 8         /* L2 / NRMSE-bounded mode, the paper's error control
+                        (Sec. 2.4: global budget eps_t ||u||, Eq. (4)
+                        equal-share local tolerance; Alg. 1 step 3: fewest
+                        coefficients meeting it).  abs_eps[v] is then the
+                        target NRMSE of variable v as a fraction (0.01 =
+                        1 %).  Each block gets the budget e2 = eps_t^2
+                        ||u_v||^2 M_b W_b / K_v (K_v values of the
+                        variable), the smallest rank whose eigenvalue tail
+                        fits 0.36 e2, coefficients quantized with step
+                        0.4 sqrt(e2 / (r M_b)) and a 2^-24 basis grid, and
+                        the exact error of the decoded values is checked:
+                        a block above e2 is encoded again one rank higher,
+                        or stored verbatim.  No residual codes.  Every
+                        variable's NRMSE is within its target.  The Gram is
+                        FP64 in this mode (precision has no effect): the
+                        rank test resolves tails of ~1e-8 of a block's
+                        energy at tight targets.  Not with DLS_LEARNED;
+                        DLS_PERSISTENT has no effect. */
 };
 
 typedef struct dls_params {
@@ -108,7 +126,8 @@ typedef struct dls_params {
                               window is truncated                           */
   int32_t r_max;           /* rank cap, 0 -> min(window, 32)                */
   int32_t precision;       /* dls_precision                                 */
-  uint32_t flags;          /* DLS_ADAPTIVE                                  */
+  uint32_t flags;          /* DLS_ADAPTIVE | DLS_LEARNED | DLS_PERSISTENT |
+                              DLS_L2                                        */
   const double* abs_eps;   /* host array of nvars absolute bounds, each
                               finite and > 0; read during the call only    */
 } dls_params;
@@ -171,6 +190,8 @@ typedef struct dls_encode_info {
                                it (its discarded energy exceeds tau)         */
   int32_t fused_declined;   /* 1: more than half the blocks were predicted to
                                fail, so the call ran two-pass                */
+  int32_t l2_passes;        /* DLS_L2: encode passes (1 when every block met
+                               its budget at the rank its eigenvalues gave)  */
 } dls_encode_info;
 
 typedef struct dls_ctx dls_ctx;

@@ -16,7 +16,11 @@ own basis, so per block and variable v:
  1. budget   -- e2 = c_v M_b W_b with c_v = (eps_t,v ||u_v||)^2 / K_v, K_v the
                 number of values of the variable and ||u_v|| the L2 norm of
                 its finite values; sum_b e2 = (eps_t,v ||u_v||)^2.
- 2. Gram, eigenpairs as in the absolute mode (``oracle.dls``), FP64.
+ 2. Gram, eigenpairs as in the absolute mode (``oracle.dls``), FP64 whatever
+                the precision parameter: the rank test below compares tails with
+                a share of e2, which at tight targets is ~1e-8 of the block's
+                energy, far below what a Gram of rounded operands resolves (the
+                paper fixes no reduced precision for this step).
  3. rank     -- r = 0 if the whole energy sum(lam) <= TAIL_SHARE e2, else the
                 smallest r >= 1 with sum_{k>r} lam_k <= TAIL_SHARE e2 (at most
                 rcap): by Eckart-Young that tail is the squared Frobenius error
@@ -114,14 +118,13 @@ def decode_block(r: int, step: float, qV: np.ndarray, qA: np.ndarray, raw, wb: i
     return acc.astype(dtype)
 
 
-def encode_block(xs: np.ndarray, e2: float, rcap: int, dtype, bf16_gram: bool = False) -> L2Code:
+def encode_block(xs: np.ndarray, e2: float, rcap: int, dtype) -> L2Code:
     """Steps 2-6 for one block X_b (W_b x M_b, storage dtype)."""
     wb, m = xs.shape
     x = xs.astype(np.float64)
     if not np.all(np.isfinite(x)):
         return L2Code(RAW, 0.0, np.zeros((wb, 0), np.int64), np.zeros((m, 0), np.int64), xs.copy())
-    xg = dls.round_bf16(x) if bf16_gram else x
-    lam, V = dls.eig_desc(xg @ xg.T)
+    lam, V = dls.eig_desc(x @ x.T)
     r = first_rank(lam, e2, min(rcap, wb))
     r0 = r
     while True:
@@ -169,8 +172,7 @@ def encode(field: np.ndarray, p: dls.Params) -> L2Encoded:
     blocks, bits = dls.plan(field, p)
     c = variable_budgets(field, p.eps)
     rcap = p.resolved_rmax()
-    codes = [encode_block(dls.gather(field, b), block_budget(c[b.var], b), rcap, p.np_dtype,
-                          p.precision == "bf16") for b in blocks]
+    codes = [encode_block(dls.gather(field, b), block_budget(c[b.var], b), rcap, p.np_dtype) for b in blocks]
     return L2Encoded(p, blocks, codes, bits, c)
 
 

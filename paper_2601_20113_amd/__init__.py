@@ -29,6 +29,7 @@ DLS_PREC_FP32, DLS_PREC_BF16 = 0, 1
 DLS_PERSISTENT = 4
 DLS_ADAPTIVE = 1
 DLS_LEARNED = 2
+DLS_L2 = 8
 NPARAM = 61968
 WARM_MAX_POINTS = 256   # the warm start applies to blocks of at most this many points
 
@@ -70,7 +71,7 @@ class _EncodeInfo(ctypes.Structure):
                 ("jacobi_sweeps", ctypes.c_int64), ("jacobi_unconverged", ctypes.c_int64),
                 ("jacobi_ms", ctypes.c_double), ("fused_ms", ctypes.c_double),
                 ("npredicted_deferred", ctypes.c_int64), ("npruned", ctypes.c_int64),
-                ("fused_declined", ctypes.c_int32)]
+                ("fused_declined", ctypes.c_int32), ("l2_passes", ctypes.c_int32)]
 
 
 class _StreamStats(ctypes.Structure):
@@ -160,6 +161,7 @@ class Params:
     adaptive: bool = False
     learned: bool = False
     persistent: bool = False  # device-driven (batched) encode launch
+    l2: bool = False          # L2 / NRMSE-bounded mode: eps holds the NRMSE targets (fractions)
     _keep: list = dc_field(default_factory=list, repr=False)
 
     def to_c(self) -> _Params:
@@ -170,7 +172,7 @@ class Params:
                        self.pmin, self.window, self.r_max,
                        DLS_PREC_BF16 if self.precision == "bf16" else DLS_PREC_FP32,
                        (DLS_ADAPTIVE if self.adaptive else 0) | (DLS_LEARNED if self.learned else 0)
-                       | (DLS_PERSISTENT if self.persistent else 0),
+                       | (DLS_PERSISTENT if self.persistent else 0) | (DLS_L2 if self.l2 else 0),
                        ctypes.cast(arr, ctypes.POINTER(ctypes.c_double)))
 
     @property
@@ -315,7 +317,7 @@ def query(buf: bytes):
     p = Params(nx=cp.nx, ny=cp.ny, nz=cp.nz, nt=cp.nt, nvars=cp.nvars,
                dtype="f32" if cp.dtype == DLS_F32 else "f64", px=cp.px, py=cp.py, pz=cp.pz,
                window=cp.window, eps=[eps[i] for i in range(cp.nvars)], pmin=cp.pmin,
-               r_max=cp.r_max, adaptive=bool(cp.flags & DLS_ADAPTIVE))
+               r_max=cp.r_max, adaptive=bool(cp.flags & DLS_ADAPTIVE), l2=bool(cp.flags & DLS_L2))
     return p, nb.value
 
 

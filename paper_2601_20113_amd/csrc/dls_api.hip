@@ -113,7 +113,9 @@ dls_status validate(const dls_params* in, Problem& p) {
   if (p.nz == 1 && p.pz != 1) return fail(DLS_EINVAL, "pz must be 1 for a 2D field");
   if (in->r_max < 0 || in->r_max > 32) return fail(DLS_EINVAL, "r_max must be in [0, 32]");
   p.r_max = in->r_max > 0 ? in->r_max : std::min(p.window, 32);
-  if (p.flags & ~uint32_t(DLS_ADAPTIVE | DLS_LEARNED | DLS_PERSISTENT)) return fail(DLS_EINVAL, "unknown flags");
+  if (p.flags & ~uint32_t(DLS_ADAPTIVE | DLS_LEARNED | DLS_PERSISTENT | DLS_L2))
+    return fail(DLS_EINVAL, "unknown flags");
+  if ((p.flags & DLS_L2) && (p.flags & DLS_LEARNED)) return fail(DLS_EINVAL, "DLS_L2 does not take DLS_LEARNED");
   if ((p.flags & DLS_LEARNED) && p.window > 16) return fail(DLS_EINVAL, "DLS_LEARNED needs window <= 16");
   if (p.precision != DLS_PREC_FP32 && p.precision != DLS_PREC_BF16)
     return fail(DLS_EINVAL, "unknown precision");
@@ -273,6 +275,9 @@ struct dls_ctx {
   bool fused_timed = false, jacobi_timed = false;
   double fused_ms = 0.0, jacobi_ms = 0.0;
   int max_sweeps = kJacobiMaxSweeps;
+  // L2 mode: per-block rank bytes, steps, budgets, errors; slice errors
+  DevBuf l2rank, l2step, l2e2, l2berr, l2ovf, l2errp, l2cv, l2part, l2tgt;
+  int l2_passes = 0;           // encode passes the last L2 call took
   int64_t jacobi_sweeps = 0, jacobi_unconverged = 0;
   unsigned long long* jstats() { return reinterpret_cast<unsigned long long*>(counters.as<uint8_t>() + kJacobiAt); }
   PlanScratch* plan_scratch = nullptr;
@@ -406,6 +411,102 @@ dls_status finish_encode(dls_ctx* ctx) {
   ctx->jacobi_sweeps = 0;
   for (int k = 1; k <= kJacobiSlots; ++k) ctx->jacobi_sweeps += int64_t(js[k]);
   ctx->have_result = true;
+  return DLS_OK;
+}
+}  // namespace
+
+namespace {
+// L2 / NRMSE-bounded encode (DLS_L2): the budget of every variable from its
+// norm, Gram and eigensolve with the eigensolve bound sqrt(0.36 c_v), then
+// encode passes until every block meets its budget (a failing block is
+// raised one rank, or stored raw).  Payload offsets come from a device scan
+// of the per-block sizes; every pass rewrites every block.
+dls_status l2_encode(dls_ctx* ctx, const void* d_field, const Problem& p, const Dims& dims, hipStream_t s) {
+  const Plan& pl = ctx->plan;
+  const int64_t nb = int64_t(pl.blocks.size()), ni = int64_t(pl.items.size());
+  const int wp = p.wpad();
+  unsigned long long* cnt = ctx->counters.as<unsigned long long>();
+  HIP_TRY(ctx->l2rank.ensure(size_t(nb)));
+  HIP_TRY(ctx->l2step.ensure(size_t(nb) * 8));
+  HIP_TRY(ctx->l2e2.ensure(size_t(nb) * 8));
+  HIP_TRY(ctx->l2berr.ensure(size_t(nb) * 8));
+  HIP_TRY(ctx->l2ovf.ensure(size_t(nb)));
+  HIP_TRY(ctx->l2errp.ensure(size_t(ni) * 8));
+  HIP_TRY(ctx->l2cv.ensure(size_t(p.nvars) * 8));
+  HIP_TRY(ctx->l2part.ensure(size_t(p.nvars) * kL2Parts * 8));
+  // the targets were uploaded as the bounds; the eigensolve takes sqrt(0.36 c_v)
+  HIP_TRY(ctx->l2tgt.ensure(size_t(p.nvars) * 8));
+  HIP_TRY(hipMemcpyAsync(ctx->l2tgt.p, ctx->eps_v.p, size_t(p.nvars) * 8, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(launch_l2_budget(p.dtype, d_field, p.nt * p.nx * p.ny * p.nz, p.nvars, ctx->l2tgt.as<double>(),
+                           ctx->l2part.as<double>(), ctx->l2cv.as<double>(), ctx->eps_v.as<double>(), s));
+  HIP_TRY(hipEventRecord(ctx->ev0, s));
+  // FP64 Gram whatever the precision: the rank test compares eigenvalue
+  // tails with a share of e2 that is ~1e-8 of the energy at tight targets
+  HIP_TRY(launch_l2_gram(wp, p.dtype, d_field, dims, ctx->desc.as<BlockDesc>(), ctx->items.as<Item>(), ni,
+                         ctx->gram.as<double>(), s));
+  HIP_TRY(hipEventRecord(ctx->evs[0], s));
+  HIP_TRY(hipEventRecord(ctx->evj[0], s));
+  HIP_TRY(launch_eigen(wp, ctx->gram.as<double>(), ctx->item_start.as<int32_t>(), ctx->desc.as<BlockDesc>(), nb,
+                       ctx->eps_v.as<double>(), p.r_max, ctx->rank.as<uint8_t>(), ctx->lam.as<double>(),
+                       ctx->basis.as<double>(), ctx->qv_size.as<int64_t>(), ctx->qa_size.as<int64_t>(), cnt + 1,
+                       nullptr, nullptr, ctx->jstats(), ctx->max_sweeps, s));
+  HIP_TRY(hipEventRecord(ctx->evj[1], s));
+  ctx->jacobi_timed = true;
+  HIP_TRY(hipEventRecord(ctx->evs[1], s));
+  int64_t* totals = reinterpret_cast<int64_t*>(reinterpret_cast<uint8_t*>(cnt) + kTotalsAt);
+  unsigned int* nfail = reinterpret_cast<unsigned int*>(reinterpret_cast<uint8_t*>(cnt) + kOverflowAt);
+  HIP_TRY(ctx->host_counters());
+  bool first = true;
+  ctx->l2_passes = 0;
+  for (int pass = 0; pass <= p.wpad() + 1; ++pass) {
+    HIP_TRY(launch_l2_params(ctx->desc.as<BlockDesc>(), nb, ctx->lam.as<double>(), wp, ctx->rank.as<uint8_t>(),
+                             ctx->l2cv.as<double>(), first, p.esize(), ctx->l2rank.as<uint8_t>(),
+                             ctx->l2step.as<double>(), ctx->l2e2.as<double>(), ctx->qv_size.as<int64_t>(),
+                             ctx->qa_size.as<int64_t>(), s));
+    first = false;
+    HIP_TRY(launch_scan(ctx->qv_size.as<int64_t>(), nb, ctx->qv_off.as<int64_t>(), ctx->scan_tmp.as<int64_t>(), s));
+    HIP_TRY(launch_scan(ctx->qa_size.as<int64_t>(), nb, ctx->qa_off.as<int64_t>(), ctx->scan_tmp.as<int64_t>(), s));
+    HIP_TRY(launch_totals(ctx->qv_off.as<int64_t>(), ctx->qv_size.as<int64_t>(), ctx->qa_off.as<int64_t>(),
+                          ctx->qa_size.as<int64_t>(), nb, totals, s));
+    HIP_TRY(hipMemcpyAsync(ctx->hcnt, cnt, kCounterBytes, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int64_t ht[2];
+    std::memcpy(ht, ctx->hcnt + kTotalsAt, sizeof(ht));
+    ctx->qv_bytes = ht[0];
+    ctx->qa_bytes = ht[1];
+    HIP_TRY(ctx->qv.ensure(size_t(std::max<int64_t>(ht[0], 16))));
+    HIP_TRY(ctx->qa.ensure(size_t(std::max<int64_t>(ht[1], 16))));
+    if (pass == 0) {
+      HIP_TRY(hipEventRecord(ctx->evs[2], s));
+      HIP_TRY(hipEventRecord(ctx->evs[3], s));
+    }
+    HIP_TRY(launch_zero(ctx->l2ovf.p, size_t(nb), s));
+    HIP_TRY(launch_zero(nfail, sizeof(unsigned int), s));
+    HIP_TRY(launch_l2_encode(wp, p.dtype, d_field, dims, ctx->desc.as<BlockDesc>(), ctx->items.as<Item>(), ni,
+                             ctx->l2rank.as<uint8_t>(), ctx->l2step.as<double>(), ctx->basis.as<double>(),
+                             ctx->qv_off.as<int64_t>(), ctx->qa_off.as<int64_t>(), ctx->qv.as<uint8_t>(),
+                             ctx->qa.as<uint8_t>(), ctx->l2ovf.as<uint8_t>(), ctx->l2errp.as<double>(), s));
+    HIP_TRY(launch_l2_check(ctx->desc.as<BlockDesc>(), ctx->item_start.as<int32_t>(), nb, ctx->l2errp.as<double>(),
+                            ctx->l2e2.as<double>(), ctx->l2ovf.as<uint8_t>(), p.r_max, ctx->l2rank.as<uint8_t>(),
+                            ctx->l2berr.as<double>(), nfail, s));
+    HIP_TRY(hipMemcpyAsync(ctx->hcnt, cnt, kCounterBytes, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    ++ctx->l2_passes;
+    unsigned int hf;
+    std::memcpy(&hf, ctx->hcnt + kOverflowAt, 4);
+    if (hf == 0) break;
+    if (pass == p.wpad() + 1) return fail(DLS_EDEVICE, "L2 encode did not settle");
+  }
+  HIP_TRY(hipEventRecord(ctx->ev1, s));
+  // raw blocks, for the info
+  std::vector<uint8_t> hr(static_cast<size_t>(nb));
+  if (nb) HIP_TRY(hipMemcpy(hr.data(), ctx->l2rank.p, size_t(nb), hipMemcpyDeviceToHost));
+  ctx->nraw = 0;
+  for (uint8_t r : hr) ctx->nraw += r == kL2Raw ? 1 : 0;
+  ctx->nesc = ctx->nesc_slots = 0;
+  ctx->nwarm_accept = ctx->nwarm_reject = 0;
+  ctx->nfast_accept = ctx->ndeferred = 0;
+  ctx->launch_mode = 0;
   return DLS_OK;
 }
 }  // namespace
@@ -577,6 +678,204 @@ dls_status fused_encode(dls_ctx* ctx, const void* d_field, const Problem& p, con
 }
 }  // namespace
 
+namespace {
+// Host half of an L2-mode encode: per batch of 1000 blocks the rank bytes,
+// the steps, the qV and qA planes and the raw blocks' values, deflated.
+dls_status l2_finalize(dls_ctx* ctx, uint8_t** out, size_t* out_bytes) {
+  const Problem& p = ctx->prob;
+  const Plan& pl = ctx->plan;
+  const int64_t nb = int64_t(pl.blocks.size());
+  std::vector<uint8_t> rank(nb), qv(std::max<int64_t>(ctx->qv_bytes, 1)), qa(std::max<int64_t>(ctx->qa_bytes, 1));
+  std::vector<double> step(nb);
+  std::vector<int64_t> qv_off(nb), qa_off(nb);
+  if (nb) {
+    HIP_TRY(hipMemcpy(rank.data(), ctx->l2rank.p, nb, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(step.data(), ctx->l2step.p, nb * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(qv_off.data(), ctx->qv_off.p, nb * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(qa_off.data(), ctx->qa_off.p, nb * 8, hipMemcpyDeviceToHost));
+  }
+  if (ctx->qv_bytes) HIP_TRY(hipMemcpy(qv.data(), ctx->qv.p, ctx->qv_bytes, hipMemcpyDeviceToHost));
+  if (ctx->qa_bytes) HIP_TRY(hipMemcpy(qa.data(), ctx->qa.p, ctx->qa_bytes, hipMemcpyDeviceToHost));
+  const int64_t nbatch = (nb + kBatchBlocks - 1) / kBatchBlocks;
+  const int es = p.esize();
+  std::vector<std::vector<uint8_t>> zs(nbatch);
+  std::vector<uint64_t> usz(nbatch);
+  std::atomic<bool> zfail{false};
+  parallel_for(nbatch, [&](int64_t bi) {
+    const int64_t b0 = bi * kBatchBlocks, b1 = std::min(nb, b0 + kBatchBlocks);
+    std::vector<uint8_t> raw;
+    raw.insert(raw.end(), rank.begin() + b0, rank.begin() + b1);
+    const uint8_t* sp = reinterpret_cast<const uint8_t*>(step.data() + b0);
+    raw.insert(raw.end(), sp, sp + 8 * (b1 - b0));
+    for (int64_t b = b0; b < b1; ++b) {
+      const int r = rank[b] == kL2Raw ? 0 : rank[b];
+      const int64_t n = int64_t(pl.blocks[b].w()) * r, pad = pad16(n);
+      for (int j = 0; j < 4; ++j) {
+        const uint8_t* src = qv.data() + qv_off[b] + j * pad;
+        raw.insert(raw.end(), src, src + n);
+      }
+    }
+    for (int64_t b = b0; b < b1; ++b) {
+      const int r = rank[b] == kL2Raw ? 0 : rank[b];
+      const int64_t n = int64_t(pl.blocks[b].m) * r, pad = pad16(n);
+      for (int j = 0; j < 4; ++j) {
+        const uint8_t* src = qa.data() + qa_off[b] + j * pad;
+        raw.insert(raw.end(), src, src + n);
+      }
+    }
+    for (int64_t b = b0; b < b1; ++b) {
+      if (rank[b] != kL2Raw) continue;
+      const int64_t n = int64_t(pl.blocks[b].w()) * pl.blocks[b].m * es;
+      const uint8_t* src = qa.data() + qa_off[b];
+      raw.insert(raw.end(), src, src + n);
+    }
+    uLongf zn = compressBound(uLong(raw.size()));
+    std::vector<uint8_t> z(zn);
+    if (compress2(z.data(), &zn, raw.data(), uLong(raw.size()), kZlibLevel) != Z_OK) {
+      zfail = true;
+      return;
+    }
+    z.resize(zn);
+    zs[bi] = std::move(z);
+    usz[bi] = raw.size();
+  });
+  if (zfail) return fail(DLS_ENOMEM, "zlib compress2 failed");
+  std::vector<StreamHeader::Batch> table(nbatch);
+  uint64_t off = 0;
+  for (int64_t i = 0; i < nbatch; ++i) {
+    table[i] = StreamHeader::Batch{off, zs[i].size(), usz[i]};
+    off += zs[i].size();
+  }
+  std::vector<uint8_t> hdr = write_header(p, nb, pl.bits, table);
+  const size_t total = hdr.size() + off;
+  uint8_t* buf = static_cast<uint8_t*>(std::malloc(total ? total : 1));
+  if (buf == nullptr) return fail(DLS_ENOMEM, "output allocation");
+  std::memcpy(buf, hdr.data(), hdr.size());
+  size_t pos = hdr.size();
+  for (auto& z : zs) {
+    std::memcpy(buf + pos, z.data(), z.size());
+    pos += z.size();
+  }
+  *out = buf;
+  *out_bytes = total;
+  return DLS_OK;
+}
+
+// One inflated L2-mode batch moved into the device layout (the encoder's
+// padding rules) at the given per-block offsets; "" on success.
+std::string l2_unpack_batch(const uint8_t* in, const StreamHeader& h, const Plan& pl, int64_t bi,
+                            std::vector<uint8_t>& rank, std::vector<double>& step, const std::vector<int64_t>& qv_off,
+                            const std::vector<int64_t>& qa_off, std::vector<uint8_t>& qv, std::vector<uint8_t>& qa) {
+  const auto& e = h.batches[bi];
+  if (e.usize > (uint64_t(1) << 40)) return "batch too large";
+  std::vector<uint8_t> raw(e.usize);
+  uLongf n = uLongf(e.usize);
+  if (uncompress(raw.data(), &n, in + h.header_bytes + e.off, uLong(e.csize)) != Z_OK || n != e.usize)
+    return "zlib stream of a batch is corrupt";
+  const int64_t nb = int64_t(pl.blocks.size());
+  const int64_t b0 = bi * kBatchBlocks, b1 = std::min(nb, b0 + kBatchBlocks);
+  const int es = h.prob.esize();
+  size_t pos = size_t(9 * (b1 - b0));
+  if (pos > raw.size()) return "batch payload truncated";
+  for (int64_t b = b0; b < b1; ++b) {
+    if (rank[b] != raw[b - b0]) return "rank table mismatch";
+    std::memcpy(&step[b], raw.data() + (b1 - b0) + 8 * (b - b0), 8);
+  }
+  for (int pass = 0; pass < 3; ++pass)
+    for (int64_t b = b0; b < b1; ++b) {
+      const BlockDesc& d = pl.blocks[b];
+      const int r = rank[b] == kL2Raw ? 0 : rank[b];
+      if (pass == 2) {
+        if (rank[b] != kL2Raw) continue;
+        const size_t nbytes = size_t(d.w()) * d.m * es;
+        if (pos + nbytes > raw.size()) return "batch payload truncated";
+        std::memcpy(qa.data() + qa_off[b], raw.data() + pos, nbytes);
+        pos += nbytes;
+        continue;
+      }
+      const int64_t cnt = int64_t(pass == 0 ? d.w() : d.m) * r, pad = pad16(cnt);
+      std::vector<uint8_t>& dst = pass == 0 ? qv : qa;
+      const int64_t base = pass == 0 ? qv_off[b] : qa_off[b];
+      for (int j = 0; j < 4; ++j) {
+        if (pos + size_t(cnt) > raw.size()) return "batch payload truncated";
+        std::memcpy(dst.data() + base + j * pad, raw.data() + pos, size_t(cnt));
+        pos += size_t(cnt);
+      }
+    }
+  if (pos != raw.size()) return "batch payload size mismatch";
+  return "";
+}
+
+// dls_decompress of an L2-mode stream: ranks first (sizes, offsets), then
+// every batch into the device layout, then the decode kernel.
+dls_status l2_decompress(const uint8_t* in, const StreamHeader& h, const Plan& pl, void* d_out, hipStream_t s) {
+  const Problem& p = h.prob;
+  const int64_t nb = h.nblocks, nbatch = int64_t(h.batches.size());
+  std::vector<uint8_t> rank(nb);
+  std::vector<double> step(nb);
+  std::vector<std::string> errs(nbatch);
+  // the rank bytes lead each batch: inflate once for them
+  parallel_for(nbatch, [&](int64_t bi) {
+    const auto& e = h.batches[bi];
+    if (e.usize > (uint64_t(1) << 40)) { errs[bi] = "batch too large"; return; }
+    std::vector<uint8_t> raw(e.usize);
+    uLongf n = uLongf(e.usize);
+    if (uncompress(raw.data(), &n, in + h.header_bytes + e.off, uLong(e.csize)) != Z_OK || n != e.usize) {
+      errs[bi] = "zlib stream of a batch is corrupt";
+      return;
+    }
+    const int64_t b0 = bi * kBatchBlocks, b1 = std::min(nb, b0 + kBatchBlocks);
+    if (raw.size() < size_t(b1 - b0)) { errs[bi] = "batch payload truncated"; return; }
+    for (int64_t b = b0; b < b1; ++b) rank[b] = raw[b - b0];
+  });
+  for (auto& e : errs)
+    if (!e.empty()) return fail(DLS_ECORRUPT, e);
+  std::vector<int64_t> qv_off(nb), qa_off(nb);
+  int64_t qv_bytes = 0, qa_bytes = 0;
+  const int es = p.esize();
+  for (int64_t b = 0; b < nb; ++b) {
+    const BlockDesc& d = pl.blocks[b];
+    const int r = rank[b];
+    if (r != kL2Raw && r > std::min(p.r_max, d.w())) return fail(DLS_ECORRUPT, "rank out of range");
+    qv_off[b] = qv_bytes;
+    qa_off[b] = qa_bytes;
+    if (r == kL2Raw) {
+      qa_bytes += pad16(int64_t(d.w()) * d.m * es);
+    } else {
+      qv_bytes += 4 * pad16(int64_t(d.w()) * r);
+      qa_bytes += 4 * pad16(int64_t(d.m) * r);
+    }
+  }
+  std::vector<uint8_t> qv(std::max<int64_t>(qv_bytes, 1)), qa(std::max<int64_t>(qa_bytes, 1));
+  parallel_for(nbatch, [&](int64_t bi) { errs[bi] = l2_unpack_batch(in, h, pl, bi, rank, step, qv_off, qa_off, qv, qa); });
+  for (auto& e : errs)
+    if (!e.empty()) return fail(DLS_ECORRUPT, e);
+  const Dims dims{p.nx, p.ny, p.nz, p.nt};
+  DevBuf d_desc, d_items, d_rank, d_step, d_qvo, d_qao, d_qv, d_qa;
+  HIP_TRY(d_desc.ensure(pl.blocks.size() * sizeof(BlockDesc)));
+  HIP_TRY(d_items.ensure(pl.items.size() * sizeof(Item)));
+  HIP_TRY(d_rank.ensure(nb));
+  HIP_TRY(d_step.ensure(nb * 8));
+  HIP_TRY(d_qvo.ensure(nb * 8));
+  HIP_TRY(d_qao.ensure(nb * 8));
+  HIP_TRY(d_qv.ensure(qv.size()));
+  HIP_TRY(d_qa.ensure(qa.size()));
+  HIP_TRY(hipMemcpyAsync(d_desc.p, pl.blocks.data(), pl.blocks.size() * sizeof(BlockDesc), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_items.p, pl.items.data(), pl.items.size() * sizeof(Item), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_rank.p, rank.data(), nb, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_step.p, step.data(), nb * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_qvo.p, qv_off.data(), nb * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_qao.p, qa_off.data(), nb * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_qv.p, qv.data(), qv.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_qa.p, qa.data(), qa.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_l2_decode(p.wpad(), p.dtype, d_out, dims, d_desc.as<BlockDesc>(), d_items.as<Item>(),
+                           int64_t(pl.items.size()), d_rank.as<uint8_t>(), d_step.as<double>(), d_qvo.as<int64_t>(),
+                           d_qao.as<int64_t>(), d_qv.as<uint8_t>(), d_qa.as<uint8_t>(), s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return DLS_OK;
+}
+}  // namespace
+
 extern "C" {
 
 const char* dls_last_error(void) { return g_err.c_str(); }
@@ -734,6 +1033,10 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
 
   const Dims dims{p.nx, p.ny, p.nz, p.nt};
   unsigned long long* cnt = ctx->counters.as<unsigned long long>();
+  if (p.flags & DLS_L2) {
+    if (dls_status st = l2_encode(ctx, d_field, p, dims, s)) return st;
+    return finish_encode(ctx);
+  }
   HIP_TRY(hipEventRecord(ctx->ev0, s));
   // batched: slices of at most kSmallSlice points share workgroups (the split
   // depends on the plan only and is uploaded once per plan)
@@ -1014,6 +1317,13 @@ dls_status dls_decode(dls_ctx* ctx, void* d_out, size_t out_bytes, void* stream)
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Dims dims{p.nx, p.ny, p.nz, p.nt};
+  if (p.flags & DLS_L2) {
+    HIP_TRY(launch_l2_decode(p.wpad(), p.dtype, d_out, dims, ctx->desc.as<BlockDesc>(), ctx->items.as<Item>(),
+                             int64_t(ctx->plan.items.size()), ctx->l2rank.as<uint8_t>(), ctx->l2step.as<double>(),
+                             ctx->qv_off.as<int64_t>(), ctx->qa_off.as<int64_t>(), ctx->qv.as<uint8_t>(),
+                             ctx->qa.as<uint8_t>(), s));
+    return DLS_OK;
+  }
   // one launch per rank class, over the encode's class lists (their counts
   // are in the host copy of the counter block the encode read back last)
   const int64_t ni = int64_t(ctx->plan.items.size());
@@ -1130,6 +1440,7 @@ dls_status dls_encode_info_get(const dls_ctx* ctx, dls_encode_info* info) {
   info->npredicted_deferred = ctx->npredicted;
   info->npruned = ctx->npruned;
   info->fused_declined = ctx->fused_declined ? 1 : 0;
+  info->l2_passes = (ctx->prob.flags & DLS_L2) ? ctx->l2_passes : 0;
   info->jacobi_sweeps = ctx->jacobi_sweeps;
   info->jacobi_unconverged = ctx->jacobi_unconverged;
   info->jacobi_ms = ctx->jacobi_ms;
@@ -1145,6 +1456,7 @@ dls_status dls_finalize(dls_ctx* ctx, uint8_t** out, size_t* out_bytes) {
   *out = nullptr;
   *out_bytes = 0;
   HIP_TRY(hipSetDevice(ctx->device));
+  if (ctx->prob.flags & DLS_L2) return l2_finalize(ctx, out, out_bytes);
   const Problem& p = ctx->prob;
   const Plan& pl = ctx->plan;
   const int64_t nb = int64_t(pl.blocks.size());
@@ -1376,6 +1688,26 @@ dls_status dls_stats(const uint8_t* in, size_t in_bytes, dls_stream_stats* s) {
   s->nblocks = h.nblocks;
   s->nbatches = int64_t(h.batches.size());
   s->stream_bytes = int64_t(in_bytes);
+  if (h.prob.flags & DLS_L2) {
+    for (int64_t bi = 0; bi < s->nbatches; ++bi) {
+      const auto& e = h.batches[bi];
+      if (e.usize > (uint64_t(1) << 40)) return fail(DLS_ECORRUPT, "batch too large");
+      std::vector<uint8_t> raw(e.usize);
+      uLongf n = uLongf(e.usize);
+      if (uncompress(raw.data(), &n, in + h.header_bytes + e.off, uLong(e.csize)) != Z_OK || n != e.usize)
+        return fail(DLS_ECORRUPT, "zlib stream of a batch is corrupt");
+      const int64_t cnt = std::min<int64_t>(kBatchBlocks, h.nblocks - bi * kBatchBlocks);
+      if (int64_t(raw.size()) < 9 * cnt) return fail(DLS_ECORRUPT, "batch payload truncated");
+      for (int64_t j = 0; j < cnt; ++j) {
+        const int r = raw[j];
+        if (r == kL2Raw) s->nraw++;
+        else if (r <= 32) s->rank_hist[r]++;
+        else return fail(DLS_ECORRUPT, "rank out of range");
+      }
+      s->payload_bytes += int64_t(raw.size());
+    }
+    return DLS_OK;
+  }
   for (int64_t bi = 0; bi < s->nbatches; ++bi) {
     BatchView bv;
     err = inflate_batch(in, h, pl, bi, bv);
@@ -1403,6 +1735,7 @@ dls_status dls_decompress(const uint8_t* in, size_t in_bytes, void* d_out, void*
   Plan pl;
   err = plan_from_header(h, pl, 1024);
   if (!err.empty()) return fail(DLS_ECORRUPT, err);
+  if (p.flags & DLS_L2) return l2_decompress(in, h, pl, d_out, static_cast<hipStream_t>(stream));
   const int64_t nb = h.nblocks, nbatch = int64_t(h.batches.size());
   std::vector<BatchView> views(nbatch);
   std::vector<std::string> errs(nbatch);

@@ -5,7 +5,9 @@
 // how long it is, followed by the packed, independently decodable batches.
 //
 // Header, little-endian:
-//   char[4] "DLS1"; u32 version = 2; u32 header_bytes; u32 flags (bit0 adaptive)
+//   char[4] "DLS1"; u32 version = 2; u32 header_bytes; u32 flags (bit0 adaptive,
+//   bit1 L2 mode: bounds are NRMSE targets, batches hold ranks, steps, qV, qA
+//   and raw values)
 //   i32 ndim, nvars, dtype (0 f32, 1 f64), r_max
 //   i64 nx, ny, nz, nt
 //   i32 px, py, pz, pmin, window, batch_blocks (= 1000)
@@ -17,6 +19,7 @@
 #include <algorithm>
 #include <cstring>
 
+#include "../../include/dls.h"
 #include "dls_internal.h"
 
 namespace dls {
@@ -168,7 +171,7 @@ std::vector<uint8_t> write_header(const Problem& p, int64_t nblocks,
   out.insert(out.end(), {'D', 'L', 'S', '1'});
   put<uint32_t>(out, kVersion);
   put<uint32_t>(out, hdr);
-  put<uint32_t>(out, p.flags & 1);
+  put<uint32_t>(out, (p.flags & 1) | ((p.flags & DLS_L2) ? 2u : 0u));
   put<int32_t>(out, p.ndim());
   put<int32_t>(out, p.nvars);
   put<int32_t>(out, p.dtype);
@@ -219,7 +222,7 @@ std::string parse_header(const uint8_t* buf, size_t n, StreamHeader& h) {
   int bb = get<int32_t>(buf + 84);
   h.nblocks = int64_t(get<uint64_t>(buf + 88));
   uint32_t nbatches = get<uint32_t>(buf + 96);
-  p.flags = flags & 1;
+  p.flags = (flags & 1) | ((flags & 2) ? uint32_t(DLS_L2) : 0u);
   p.precision = 0;
   if (hdr > n || hdr < kFixed) return "bad header length";
   if (p.nvars < 1 || p.nvars > 65536 || (p.dtype != 0 && p.dtype != 1) || bb != kBatchBlocks)

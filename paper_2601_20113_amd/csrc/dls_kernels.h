@@ -194,6 +194,29 @@ hipError_t launch_warmstart(const double* gpart, const int32_t* item_start, cons
                             uint8_t* reject, unsigned long long* counters, unsigned long long* jstats,
                             hipStream_t s);
 hipError_t launch_scan(const int64_t* in, int64_t n, int64_t* out, int64_t* tmp, hipStream_t s);
+// L2 / NRMSE-bounded mode (dls_l2.hip).  Per block: rank byte (kL2Raw =
+// values stored verbatim), coefficient step, budget; the squared error of
+// every slice; payload regions as in the absolute mode (qV, qA planes; a
+// raw block's values in its qA region).
+constexpr int kL2Raw = 255;
+constexpr int kL2Parts = 1024;  // partial sums per variable of the norm
+hipError_t launch_l2_budget(int dtype, const void* F, int64_t per_var, int nvars, const double* target,
+                            double* part, double* cv, double* eig_eps, hipStream_t s);
+hipError_t launch_l2_gram(int wp, int dtype, const void* F, const Dims& dims, const BlockDesc* desc,
+                          const Item* items, int64_t nitems, double* gpart, hipStream_t s);
+hipError_t launch_l2_params(const BlockDesc* desc, int64_t nblocks, const double* lam, int wp,
+                            const uint8_t* eig_rank, const double* cv, bool first, int esize, uint8_t* l2rank,
+                            double* step, double* e2, int64_t* qv_size, int64_t* qa_size, hipStream_t s);
+hipError_t launch_l2_encode(int wp, int dtype, const void* F, const Dims& dims, const BlockDesc* desc,
+                            const Item* items, int64_t nitems, const uint8_t* l2rank, const double* step,
+                            const double* basis, const int64_t* qv_off, const int64_t* qa_off, uint8_t* qv,
+                            uint8_t* qa, uint8_t* overflow, double* errp, hipStream_t s);
+hipError_t launch_l2_check(const BlockDesc* desc, const int32_t* item_start, int64_t nblocks, const double* errp,
+                           const double* e2, const uint8_t* overflow, int rcap, uint8_t* l2rank, double* berr,
+                           unsigned int* nfail, hipStream_t s);
+hipError_t launch_l2_decode(int wp, int dtype, void* F, const Dims& dims, const BlockDesc* desc, const Item* items,
+                            int64_t nitems, const uint8_t* l2rank, const double* step, const int64_t* qv_off,
+                            const int64_t* qa_off, const uint8_t* qv, const uint8_t* qa, hipStream_t s);
 // Allocation-free range: the partials live in a fixed device array (one per
 // GPU) whose address range_scratch() returns for the current device;
 // results at scratch_ptr + nvars * 2 * 1024 as (min, max) per variable.

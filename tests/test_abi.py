@@ -117,3 +117,31 @@ def test_large_host_buffer_copied_whole(L):
     assert len(b) == n and b[-3:] == b"\x5a\x5a\x5a" and b[0] == 0
     del b, buf
     assert L._take_bytes(ctypes.c_void_p(None), ctypes.c_size_t(0)) == b""
+
+
+def test_query_and_stats_of_oracle_l2_stream(L):
+    """An L2-mode stream written by the oracle: the header carries the mode,
+    the stats count its ranks and raw blocks."""
+    from oracle import l2
+    f = synth.blobs2d(nx=40, ny=36, nt=20, seed=2)
+    f[0, 2, 0, 3, 4] = np.nan
+    p = odls.Params(nx=40, ny=36, nz=1, nt=20, nvars=1, dtype="f64", px=8, py=8, pz=1, window=16, eps=[1e-3])
+    enc = l2.encode(f, p)
+    buf = container.pack_l2(enc)
+    q, nb = L.query(buf)
+    assert nb == len(enc.blocks) and q.l2 and q.eps[0] == 1e-3
+    st = L.stats(buf)
+    ranks = [c.r for c in enc.codes]
+    assert st["nraw"] == ranks.count(l2.RAW) == 1
+    assert st["rank_hist"][:17] == [ranks.count(r) for r in range(17)]
+    assert st["nescapes"] == 0
+
+
+def test_l2_with_learned_rejected_before_device_work(L):
+    lib = L.lib()
+    p = L.Params(nx=64, ny=64, nz=1, nt=32, nvars=1, dtype="f64", px=8, py=8, pz=1, window=16, eps=[1e-3],
+                 l2=True, learned=True)
+    cp = p.to_c()
+    st = lib.dls_compress(ctypes.c_void_p(16), ctypes.byref(cp), None, ctypes.byref(ctypes.c_void_p()),
+                          ctypes.byref(ctypes.c_size_t()))
+    assert st == L.DLS_EINVAL and b"DLS_L2" in lib.dls_last_error()

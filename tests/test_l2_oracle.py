@@ -10,7 +10,7 @@ test_oracle_mutations.py are checked against them too):
 * the block budgets add up to the variable's squared global budget;
 * every block's exact error within its budget and every variable's NRMSE
   within its target on blob and drifting-spectrum fields (1e-1 .. 1e-4),
-  stream round trip bit for bit, bf16-Gram mode without raw blocks;
+  stream round trip bit for bit, the precision parameter without effect;
 * ranks grow as the target tightens; non-finite, zero and too-tight blocks.
 """
 import os

@@ -413,6 +413,71 @@ def error_stats(field, out, eps, rel_eps):
     return res
 
 
+def nrmse(field, out):
+    """Per variable, ||u - u_hat|| / ||u|| over the finite values (the NRMSE
+    of Sec. 2.4 as a fraction), on the device in FP64."""
+    res = []
+    for v in range(field.shape[0]):
+        se = ss = 0.0
+        for t in range(field.shape[1]):
+            x = field[v, t].double()
+            fin = x.isfinite()
+            d = (out[v, t].double() - x).masked_fill(~fin, 0.0)
+            x = x.masked_fill(~fin, 0.0)
+            se += (d * d).sum().item()
+            ss += (x * x).sum().item()
+        res.append(math.sqrt(se / ss) if ss > 0 else 0.0)
+    return res
+
+
+def run_l2(field, cfg, targets, steps, warmup, no_ratio, log):
+    """The L2 / NRMSE-bounded mode (Sec. 2.4) on the same field: per target,
+    the encode time (wall, between synchronizations), the passes it took,
+    the decoded field's NRMSE per variable and the compression ratio."""
+    import torch
+    import paper_2601_20113_amd as dls
+    in_bytes = field.numel() * field.element_size()
+    curve = []
+    stream = torch.cuda.current_stream()
+    for tg in targets:
+        p = dls.Params(nx=cfg["nx"], ny=cfg["ny"], nz=cfg["nz"], nt=cfg["nt"], nvars=cfg["nvars"],
+                       dtype=cfg["dtype"], px=cfg["px"], py=cfg["py"], pz=cfg["pz"], window=cfg["window"],
+                       eps=[tg] * cfg["nvars"], pmin=cfg.get("pmin", 0), adaptive=cfg.get("adaptive", False),
+                       l2=True)
+        enc = dls.Encoder()
+        for _ in range(warmup):
+            enc.encode(field, p, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            enc.encode(field, p, stream=stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        inf = enc.info()
+        out = torch.empty_like(field)
+        enc.decode(out, stream=stream)
+        torch.cuda.synchronize()
+        nr = nrmse(field, out)
+        del out
+        e = {"target": tg, "ms": round(ms, 3), "value": round(in_bytes / (ms * 1e-3) / 1e9, 2), "unit": "GB/s",
+             "passes": int(inf.l2_passes), "raw_blocks": int(inf.nraw),
+             "nrmse": [float("%.4g" % x) for x in nr], "within_target": bool(all(x <= tg for x in nr)),
+             "stage_ms": {"gram": round(inf.stage_ms[1], 4), "eigen": round(inf.stage_ms[2], 4),
+                          "encode+check": round(inf.stage_ms[4], 4)}}
+        if not no_ratio:
+            t1 = time.perf_counter()
+            e["compression_ratio"] = round(in_bytes / len(enc.finalize()), 3)
+            e["finalize_s"] = round(time.perf_counter() - t1, 3)
+        enc.close()
+        torch.cuda.empty_cache()
+        log("l2 %g: %.3f ms, %.1f GB/s, %d passes, NRMSE %s, CR %s" % (tg, ms, e["value"], e["passes"], e["nrmse"],
+                                                                     e.get("compression_ratio")))
+        curve.append(e)
+    return {"workload": "the headline field", "what": "L2 / NRMSE-bounded mode (DLS_L2): per-variable target "
+            "eps_t on ||u - u_hat|| / ||u||, FP64 Gram, rank by the eigenvalue tail, exact block error check",
+            "curve": curve}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -426,6 +491,8 @@ def main():
     ap.add_argument("--no-decode", action="store_true", help="skip the device decode measurement")
     ap.add_argument("--no-drift", action="store_true",
                     help="skip the drift variant (modes with a per-step phase drift) of the spectrum workloads")
+    ap.add_argument("--l2-targets", default="1e-2,1e-3,1e-4",
+                    help="NRMSE targets of the L2-bounded mode measured on the headline field (empty: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 4 GiB device-to-device copy twice (the reference the "
                          "HBM byte counters are scaled by) and exit")
@@ -556,6 +623,11 @@ def main():
     for r in res.values():
         r["enc"].close()
     res.clear()
+    torch.cuda.empty_cache()
+
+    targets = [float(x) for x in args.l2_targets.split(",") if x]
+    if targets:
+        out["l2"] = run_l2(field, cfg, targets, min(args.steps, 3), 1, args.no_ratio, log)
 
     # the drift variant: every mode's phase advances per step, so windows
     # have ranks above 1 (the literal generator is rank 1 in time)

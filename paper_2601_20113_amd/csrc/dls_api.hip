@@ -276,7 +276,7 @@ struct dls_ctx {
   double fused_ms = 0.0, jacobi_ms = 0.0;
   int max_sweeps = kJacobiMaxSweeps;
   // L2 mode: per-block rank bytes, steps, budgets, errors; slice errors
-  DevBuf l2rank, l2step, l2e2, l2berr, l2ovf, l2errp, l2cv, l2part, l2tgt;
+  DevBuf l2rank, l2step, l2e2, l2berr, l2ovf, l2errp, l2cv, l2part, l2tgt;  // l2part: per-slice sums of squares
   int l2_passes = 0;           // encode passes the last L2 call took
   int64_t jacobi_sweeps = 0, jacobi_unconverged = 0;
   unsigned long long* jstats() { return reinterpret_cast<unsigned long long*>(counters.as<uint8_t>() + kJacobiAt); }
@@ -433,17 +433,20 @@ dls_status l2_encode(dls_ctx* ctx, const void* d_field, const Problem& p, const 
   HIP_TRY(ctx->l2ovf.ensure(size_t(nb)));
   HIP_TRY(ctx->l2errp.ensure(size_t(ni) * 8));
   HIP_TRY(ctx->l2cv.ensure(size_t(p.nvars) * 8));
-  HIP_TRY(ctx->l2part.ensure(size_t(p.nvars) * kL2Parts * 8));
+  HIP_TRY(ctx->l2part.ensure(size_t(std::max<int64_t>(ni, 1)) * 8));
   // the targets were uploaded as the bounds; the eigensolve takes sqrt(0.36 c_v)
   HIP_TRY(ctx->l2tgt.ensure(size_t(p.nvars) * 8));
   HIP_TRY(hipMemcpyAsync(ctx->l2tgt.p, ctx->eps_v.p, size_t(p.nvars) * 8, hipMemcpyDeviceToDevice, s));
-  HIP_TRY(launch_l2_budget(p.dtype, d_field, p.nt * p.nx * p.ny * p.nz, p.nvars, ctx->l2tgt.as<double>(),
-                           ctx->l2part.as<double>(), ctx->l2cv.as<double>(), ctx->eps_v.as<double>(), s));
   HIP_TRY(hipEventRecord(ctx->ev0, s));
   // FP64 Gram whatever the precision: the rank test compares eigenvalue
-  // tails with a share of e2 that is ~1e-8 of the energy at tight targets
+  // tails with a share of e2 that is ~1e-8 of the energy at tight targets.
+  // The same read gives every slice's finite sum of squares, so the budget
+  // takes no pass of its own.
   HIP_TRY(launch_l2_gram(wp, p.dtype, d_field, dims, ctx->desc.as<BlockDesc>(), ctx->items.as<Item>(), ni,
-                         ctx->gram.as<double>(), s));
+                         ctx->gram.as<double>(), ctx->l2part.as<double>(), s));
+  HIP_TRY(launch_l2_budget(ctx->items.as<Item>(), ctx->desc.as<BlockDesc>(), ni, ctx->l2part.as<double>(),
+                           ctx->l2tgt.as<double>(), p.nt * p.nx * p.ny * p.nz, p.nvars, ctx->l2cv.as<double>(),
+                           ctx->eps_v.as<double>(), s));
   HIP_TRY(hipEventRecord(ctx->evs[0], s));
   HIP_TRY(hipEventRecord(ctx->evj[0], s));
   HIP_TRY(launch_eigen(wp, ctx->gram.as<double>(), ctx->item_start.as<int32_t>(), ctx->desc.as<BlockDesc>(), nb,

@@ -199,11 +199,11 @@ hipError_t launch_scan(const int64_t* in, int64_t n, int64_t* out, int64_t* tmp,
 // every slice; payload regions as in the absolute mode (qV, qA planes; a
 // raw block's values in its qA region).
 constexpr int kL2Raw = 255;
-constexpr int kL2Parts = 1024;  // partial sums per variable of the norm
-hipError_t launch_l2_budget(int dtype, const void* F, int64_t per_var, int nvars, const double* target,
-                            double* part, double* cv, double* eig_eps, hipStream_t s);
 hipError_t launch_l2_gram(int wp, int dtype, const void* F, const Dims& dims, const BlockDesc* desc,
-                          const Item* items, int64_t nitems, double* gpart, hipStream_t s);
+                          const Item* items, int64_t nitems, double* gpart, double* fsq, hipStream_t s);
+hipError_t launch_l2_budget(const Item* items, const BlockDesc* desc, int64_t nitems, const double* fsq,
+                            const double* target, int64_t per_var, int nvars, double* cv, double* eig_eps,
+                            hipStream_t s);
 hipError_t launch_l2_params(const BlockDesc* desc, int64_t nblocks, const double* lam, int wp,
                             const uint8_t* eig_rank, const double* cv, bool first, int esize, uint8_t* l2rank,
                             double* step, double* e2, int64_t* qv_size, int64_t* qa_size, hipStream_t s);

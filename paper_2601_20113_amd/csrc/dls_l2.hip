@@ -17,10 +17,9 @@
 //         candidates are tested until the tolerance holds), and stored
 //         verbatim (raw) past the rank cap or when a coefficient overflows.
 //
-//   k_l2_sumsq    sum of squares of the finite values of every variable
-//                 (fixed partial grid, fixed summation order)
+//   k_l2_gram     the slices' Gram partials in FP64 (matrix cores) and the
+//                 sums of squares of their finite values
 //   k_l2_budget   c_v and the eigensolve bound sqrt(0.36 c_v)
-//   k_l2_gram     the slices' Gram partials in FP64
 //   k_l2_params   per block: budget, rank (first pass), step, payload sizes
 //   k_l2_encode   one workgroup per slice: projection, quantization, the
 //                 decoder's values and the slice's squared error
@@ -45,85 +44,139 @@ constexpr double kL2BasisUnit = 1.0 / 16777216.0;  // 2^-24
 __device__ __forceinline__ uint32_t zz32(int32_t v) { return (uint32_t(v) << 1) ^ uint32_t(v >> 31); }
 __device__ __forceinline__ int32_t unzz32(uint32_t z) { return int32_t(z >> 1) ^ -int32_t(z & 1); }
 
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// One slice's four consecutive points of one time row (zero past the
+// slice's end, or for a padded row); `cont` when the four are one aligned
+// run in memory (a block whose patch rows are 16-byte aligned runs of 4k
+// values, and slices that start on a patch row).
 template <typename T>
-__global__ __launch_bounds__(256) void k_l2_sumsq(const T* __restrict__ F, int64_t per_var,
-                                                  double* __restrict__ part) {
-  __shared__ double red[256];
-  const int v = blockIdx.y;
-  const T* f = F + int64_t(v) * per_var;
-  double s = 0.0;
-  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < per_var; i += int64_t(gridDim.x) * 256) {
-    const double x = double(f[i]);
-    if (isfinite(x)) s += x * x;
+__device__ __forceinline__ void l2_load4(const T* row, int p0, int pb, int np, bool cont, int px, int py,
+                                         int64_t nx, int64_t nxy, double x[4]) {
+  if (row == nullptr) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[j] = 0.0;
+    return;
   }
+  if (cont && pb + 3 < np) {
+    const int64_t off = point_off(p0 + pb, px, py, nx, nxy);
+    if constexpr (sizeof(T) == 4) {
+      const float4 v = *reinterpret_cast<const float4*>(row + off);
+      x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) x[j] = double(row[off + j]);
+    }
+    return;
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    x[j] = pb + j < np ? double(row[point_off(p0 + pb + j, px, py, nx, nxy)]) : 0.0;
+}
+
+// The Gram partial of one slice in FP64 (the L2 mode's ranks come from
+// eigenvalue tails compared with 0.36 e2, which at tight targets is ~1e-8 of
+// the block's energy: an FP32-accumulated Gram cannot resolve it), on the
+// FP64 matrix cores: v_mfma_f64_16x16x4f64 takes 16 rows x 4 points, lane l
+// holding row l % 16 of point slot l / 16, and the same register feeds both
+// operands (G = X X^T).  A lane loads four consecutive points of its row and
+// gives one to each of four MFMAs, so a wave covers 16 points per step and
+// the four waves of the workgroup interleave.  Also the sum of squares of
+// the slice's finite values (the variable's norm, for the budget).
+template <int WP, typename T>
+__global__ __launch_bounds__(256) void k_l2_gram(const T* __restrict__ F, Dims dims,
+                                                 const BlockDesc* __restrict__ desc,
+                                                 const Item* __restrict__ items, int64_t nitems,
+                                                 double* __restrict__ gpart, double* __restrict__ fsq) {
+  constexpr int NT = WP == 16 ? 1 : 3;  // tiles 00 (and 01, 11)
+  __shared__ f64x4 red[4][NT][64];
+  __shared__ double fred[4];
+  const int64_t i = blockIdx.x;
+  if (i >= nitems) return;
+  const Item it = items[i];
+  const BlockDesc d = desc[it.block];
+  const int W = d.w();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int t = lane & 15, slot = lane >> 4;
+  const int64_t nxy = dims.nx * dims.ny, tstride = dims.nz * nxy;
+  const T* base = F + fidx(dims, d.var, d.t0, d.z0, d.y0, d.x0);
+  const T* row0 = t < W ? base + int64_t(t) * tstride : nullptr;
+  const T* row1 = (WP == 32 && t + 16 < W) ? base + int64_t(t + 16) * tstride : nullptr;
+  const bool cont = d.vec != 0;
+  const int px = d.px(), py = d.py();
+  f64x4 acc[NT];
+#pragma unroll
+  for (int a = 0; a < NT; ++a) acc[a] = f64x4{0.0, 0.0, 0.0, 0.0};
+  double fs = 0.0;
+  for (int c = wave * 16; c < it.np; c += 64) {
+    const int pb = c + 4 * slot;
+    double x0[4], x1[4];
+    l2_load4(row0, it.p0, pb, it.np, cont, px, py, dims.nx, nxy, x0);
+    if (WP == 32) l2_load4(row1, it.p0, pb, it.np, cont, px, py, dims.nx, nxy, x1);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      fs += isfinite(x0[j]) ? x0[j] * x0[j] : 0.0;
+      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[j], x0[j], acc[0], 0, 0, 0);
+      if (WP == 32) {
+        fs += isfinite(x1[j]) ? x1[j] * x1[j] : 0.0;
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[j], x1[j], acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[j], x1[j], acc[2], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < NT; ++a) red[wave][a][lane] = acc[a];
+  fs = wave_sum(fs);
+  if (lane == 0) fred[wave] = fs;
+  __syncthreads();
+  // the FP64 accumulator holds D[l / 16 + 4 v][l % 16] in lane l, element v
+  // (not the FP32 instruction's D[4 (l / 16) + v][l % 16]); the four waves'
+  // partials are summed in wave order
+  double* out = gpart + i * WP * WP;
+  const int ei = int(threadIdx.x) >> 4, ej = int(threadIdx.x) & 15;
+  const int l = ej + 16 * (ei & 3), v = ei >> 2;
+#pragma unroll
+  for (int a = 0; a < NT; ++a) {
+    double g = 0.0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) g += red[w][a][l][v];
+    if (a == 0) {
+      out[ei * WP + ej] = g;
+    } else if (a == 1) {
+      out[ei * WP + 16 + ej] = g;
+      out[(16 + ej) * WP + ei] = g;
+    } else {
+      out[(16 + ei) * WP + 16 + ej] = g;
+    }
+  }
+  if (threadIdx.x == 0) fsq[i] = ((fred[0] + fred[1]) + fred[2]) + fred[3];
+}
+
+// c_v = (eps_t,v)^2 ||u_v||^2 / K_v and the eigensolve's bound sqrt(0.36 c_v);
+// ||u_v||^2 is the sum of the variable's slices' finite sums of squares (the
+// plan tiles the field, so every value is in exactly one slice), strided
+// over the slices in a fixed order, one workgroup per variable
+__global__ __launch_bounds__(256) void k_l2_budget(const Item* __restrict__ items,
+                                                   const BlockDesc* __restrict__ desc, int64_t nitems,
+                                                   const double* __restrict__ fsq,
+                                                   const double* __restrict__ target, int64_t per_var,
+                                                   double* __restrict__ cv, double* __restrict__ eig_eps) {
+  __shared__ double red[256];
+  const int v = blockIdx.x;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < nitems; i += 256)
+    if (desc[items[i].block].var == v) s += fsq[i];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
     if (int(threadIdx.x) < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[int64_t(v) * kL2Parts + blockIdx.x] = red[0];
-}
-
-// The Gram partial of one slice in FP64 (the L2 mode's ranks come from
-// eigenvalue tails compared with 0.36 e2, which at tight targets is ~1e-8 of
-// the block's energy: an FP32-accumulated Gram cannot resolve it).  One
-// workgroup per slice; 64-point chunks staged in LDS; thread e owns entries
-// e, e + 256, ... of the WP x WP matrix and sums its products over the
-// slice's points in order.
-template <int WP, typename T>
-__global__ __launch_bounds__(256) void k_l2_gram(const T* __restrict__ F, Dims dims,
-                                                 const BlockDesc* __restrict__ desc,
-                                                 const Item* __restrict__ items, int64_t nitems,
-                                                 double* __restrict__ gpart) {
-  constexpr int CP = 64, NE = WP * WP / 256;
-  __shared__ double sx[WP][CP + 1];
-  const int64_t i = blockIdx.x;
-  if (i >= nitems) return;
-  const Item it = items[i];
-  const BlockDesc d = desc[it.block];
-  const int W = d.w();
-  const T* base = F + fidx(dims, d.var, d.t0, d.z0, d.y0, d.x0);
-  const int64_t nxy = dims.nx * dims.ny, tstride = dims.nz * nxy;
-  double acc[NE];
-#pragma unroll
-  for (int e = 0; e < NE; ++e) acc[e] = 0.0;
-  for (int c0 = 0; c0 < it.np; c0 += CP) {
-    const int n = it.np - c0 < CP ? it.np - c0 : CP;
-    for (int idx = threadIdx.x; idx < WP * CP; idx += 256) {
-      const int t = idx / CP, q = idx % CP;
-      double v = 0.0;
-      if (t < W && q < n) {
-        const int64_t off = point_off(it.p0 + c0 + q, d.px(), d.py(), dims.nx, nxy);
-        v = double(base[int64_t(t) * tstride + off]);
-      }
-      sx[t][q] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < NE; ++e) {
-      const int ent = int(threadIdx.x) + 256 * e, r = ent / WP, c = ent % WP;
-      double a = acc[e];
-      for (int q = 0; q < n; ++q) a = fma(sx[r][q], sx[c][q], a);
-      acc[e] = a;
-    }
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    const double c = target[v] * target[v] * red[0] / double(per_var);
+    cv[v] = c;
+    eig_eps[v] = sqrt(kL2TailShare * c);
   }
-  double* out = gpart + i * WP * WP;
-#pragma unroll
-  for (int e = 0; e < NE; ++e) out[threadIdx.x + 256 * e] = acc[e];
-}
-
-// c_v = (eps_t,v)^2 ||u_v||^2 / K_v and the eigensolve's bound sqrt(0.36 c_v)
-__global__ void k_l2_budget(const double* __restrict__ part, const double* __restrict__ target, int64_t per_var,
-                            int nvars, double* __restrict__ cv, double* __restrict__ eig_eps) {
-  const int v = int(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (v >= nvars) return;
-  double s = 0.0;
-  for (int j = 0; j < kL2Parts; ++j) s += part[int64_t(v) * kL2Parts + j];
-  const double c = target[v] * target[v] * s / double(per_var);
-  cv[v] = c;
-  eig_eps[v] = sqrt(kL2TailShare * c);
 }
 
 // first: the rank from the eigensolve (0 when the energy fits the tail
@@ -215,55 +268,55 @@ __global__ __launch_bounds__(256) void k_l2_encode(const T* __restrict__ F, Dims
   for (int q = threadIdx.x; q < it.np; q += 256) {
     const int p = it.p0 + q;
     const int64_t off = point_off(p, d.px(), d.py(), dims.nx, nxy);
+    // the point's W values, every load issued before the first use
+    T xs[WP];
+#pragma unroll
+    for (int t = 0; t < WP; ++t) xs[t] = t < W ? base[int64_t(t) * tstride + off] : T(0);
     if (r == kL2Raw) {
       uint8_t* dst = qa_buf + qa_off[b];
-      for (int t = 0; t < W; ++t)
-        *reinterpret_cast<T*>(dst + (int64_t(t) * M + p) * int64_t(sizeof(T))) = base[int64_t(t) * tstride + off];
+#pragma unroll
+      for (int t = 0; t < WP; ++t)
+        if (t < W) *reinterpret_cast<T*>(dst + (int64_t(t) * M + p) * int64_t(sizeof(T))) = xs[t];
       continue;
     }
     if (r == 0) {
-      for (int t = 0; t < W; ++t) {
-        const double x = double(base[int64_t(t) * tstride + off]);
-        err += x * x;
+#pragma unroll
+      for (int t = 0; t < WP; ++t) {
+        const double x = double(xs[t]);
+        if (t < W) err += x * x;
       }
       continue;
     }
-    // projection: per mode a running FMA over the steps in order (the mode
-    // index is compile-time, so a[] and c[] stay in registers)
-    double a[WP];
+    // per mode k (in order): the projection, a running FMA over the steps in
+    // order; its quantized coefficient; and its term of the decoder's
+    // values, which sum the modes in order k = 0, 1, ...  (step indices are
+    // compile-time, so xs[] and rec[] stay in registers)
+    double rec[WP];
 #pragma unroll
-    for (int k = 0; k < WP; ++k) a[k] = 0.0;
-    for (int t = 0; t < W; ++t) {
-      const double x = double(base[int64_t(t) * tstride + off]);
-#pragma unroll
-      for (int k = 0; k < WP; ++k)
-        if (k < R) a[k] = fma(x, Vs[k][t], a[k]);
-    }
-    double c[WP];
+    for (int t = 0; t < WP; ++t) rec[t] = 0.0;
     bool ovf = false;
     const int64_t plane = pad16(int64_t(M) * r);
     uint8_t* dst = qa_buf + qa_off[b];
+    for (int k = 0; k < R; ++k) {
+      double a = 0.0;
 #pragma unroll
-    for (int k = 0; k < WP; ++k) {
-      c[k] = 0.0;
-      if (k >= R) continue;
-      const double qa = rint(a[k] / dstep);
+      for (int t = 0; t < WP; ++t)
+        if (t < W) a = fma(double(xs[t]), Vs[k][t], a);
+      const double qa = rint(a / dstep);
       const bool ok = fabs(qa) < 2147483648.0;
       ovf = ovf || !ok;
       const int32_t qi = ok ? int32_t(qa) : 0;
-      c[k] = double(qi) * dstep;
+      const double c = double(qi) * dstep;
       const uint32_t z = zz32(qi);
       for (int j = 0; j < 4; ++j) dst[j * plane + int64_t(k) * M + p] = uint8_t(z >> (8 * j));
+#pragma unroll
+      for (int t = 0; t < WP; ++t) rec[t] = rec[t] + Vq[k][t] * c;
     }
     if (ovf) overflow[b] = 1;
-    // the decoder's values: per step, the modes summed in order k = 0, 1, ...
-    for (int t = 0; t < W; ++t) {
-      double acc = 0.0;
 #pragma unroll
-      for (int k = 0; k < WP; ++k)
-        if (k < R) acc = acc + Vq[k][t] * c[k];
-      const double e = double(base[int64_t(t) * tstride + off]) - double(T(acc));
-      err += e * e;
+    for (int t = 0; t < WP; ++t) {
+      const double e = double(xs[t]) - double(T(rec[t]));
+      if (t < W) err += e * e;
     }
   }
   red[threadIdx.x] = err;
@@ -367,28 +420,26 @@ __global__ __launch_bounds__(256) void k_l2_decode(T* __restrict__ F, Dims dims,
 
 }  // namespace
 
-hipError_t launch_l2_budget(int dtype, const void* F, int64_t per_var, int nvars, const double* target,
-                            double* part, double* cv, double* eig_eps, hipStream_t s) {
-  const dim3 g{unsigned(kL2Parts), unsigned(nvars)};
-  if (dtype == 0)
-    hipLaunchKernelGGL(k_l2_sumsq<float>, g, dim3{256}, 0, s, static_cast<const float*>(F), per_var, part);
-  else
-    hipLaunchKernelGGL(k_l2_sumsq<double>, g, dim3{256}, 0, s, static_cast<const double*>(F), per_var, part);
-  hipLaunchKernelGGL(k_l2_budget, dim3{unsigned((nvars + 63) / 64)}, dim3{64}, 0, s, part, target, per_var, nvars,
-                     cv, eig_eps);
-  return hipGetLastError();
-}
-
 hipError_t launch_l2_gram(int wp, int dtype, const void* F, const Dims& dims, const BlockDesc* desc,
-                          const Item* items, int64_t nitems, double* gpart, hipStream_t s) {
+                          const Item* items, int64_t nitems, double* gpart, double* fsq, hipStream_t s) {
   if (nitems == 0) return hipSuccess;
   if (nitems > int64_t(INT32_MAX)) return hipErrorInvalidValue;
   const dim3 g{unsigned(nitems)}, bl{256};
-#define DLS_L2G(WPV, TV) \
-  hipLaunchKernelGGL((k_l2_gram<WPV, TV>), g, bl, 0, s, static_cast<const TV*>(F), dims, desc, items, nitems, gpart)
+#define DLS_L2G(WPV, TV)                                                                                         \
+  hipLaunchKernelGGL((k_l2_gram<WPV, TV>), g, bl, 0, s, static_cast<const TV*>(F), dims, desc, items, nitems, \
+                     gpart, fsq)
   if (wp == 16) { if (dtype == 0) DLS_L2G(16, float); else DLS_L2G(16, double); }
   else { if (dtype == 0) DLS_L2G(32, float); else DLS_L2G(32, double); }
 #undef DLS_L2G
+  return hipGetLastError();
+}
+
+hipError_t launch_l2_budget(const Item* items, const BlockDesc* desc, int64_t nitems, const double* fsq,
+                            const double* target, int64_t per_var, int nvars, double* cv, double* eig_eps,
+                            hipStream_t s) {
+  if (nvars == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_l2_budget, dim3{unsigned(nvars)}, dim3{256}, 0, s, items, desc, nitems, fsq, target, per_var,
+                     cv, eig_eps);
   return hipGetLastError();
 }
 

@@ -30,6 +30,17 @@ Uncompressed batch payload for blocks [b0, b0 + nb):
     escapes    escaped input values of the batch, block then (t, p) order,
                in the storage dtype
 
+Global-basis mode (flag bit 2; window 1, so a block is one patch of one
+snapshot; see oracle.globalbasis): the batch table lists ceil(nblocks / 1000)
+patch batches, then one basis batch per variable.  Patch batch payload:
+    counts     nb x u16, 2 planes (0xFFFF = raw patch, values verbatim)
+    exponents  nb x i16, 2 planes (coefficient step 2^k; 0 when none)
+    indices    the kept basis indices of every patch, ascending, u16, 2 planes
+    coeffs     their zigzag(int32) coefficients, 4 planes
+    raw        the raw patches' values, patch then point order, storage dtype
+Basis batch payload: u32 kind (0 svd, 1 cosine, 2 random), u32 M, f64 c_v,
+then zigzag(int32) of rint(Phi 2^24), Phi[i][s] row-major, 4 planes.
+
 L2 mode (flag bit 1), uncompressed batch payload:
     ranks      nb x u8 (255 = raw block, values verbatim)
     steps      nb x f64 (coefficient step d; 0 for rank 0 and raw blocks)
@@ -44,7 +55,7 @@ import zlib
 
 import numpy as np
 
-from . import dls, l2
+from . import dls, globalbasis, l2
 
 MAGIC = b"DLS1"
 VERSION = 2
@@ -241,6 +252,119 @@ def unpack_l2(buf: bytes) -> "l2.L2Encoded":
     return l2.L2Encoded(p, blocks, codes, bits, np.zeros(p.nvars))
 
 
+def global_batch_payload(codes, dtype) -> bytes:
+    """Uncompressed payload of one global-mode patch batch (list of
+    globalbasis.PatchCode)."""
+    live = [c for c in codes if c.n not in (0, globalbasis.RAW)]
+    idx = np.concatenate([c.kept for c in live]) if live else np.zeros(0, np.int64)
+    q = np.concatenate([c.q for c in live]) if live else np.zeros(0, np.int64)
+    parts = [planes(np.array([c.n for c in codes], np.uint16), 2),
+             planes(np.array([c.k for c in codes], np.int64).astype(np.int16).view(np.uint16), 2),
+             planes(idx.astype(np.uint16), 2), planes(zigzag32(q), 4)]
+    for c in codes:
+        if c.n == globalbasis.RAW:
+            parts.append(np.asarray(c.raw, dtype=np.dtype(dtype).newbyteorder("<")).tobytes())
+    return b"".join(parts)
+
+
+def global_basis_payload(kind: int, phi: np.ndarray, cv: float) -> bytes:
+    m = phi.shape[0]
+    qphi = np.rint(phi * 2.0 ** globalbasis.BASIS_BITS).astype(np.int64)
+    return struct.pack("<IId", kind, m, cv) + planes(zigzag32(qphi.ravel()), 4)
+
+
+def pack_global(enc: "globalbasis.GlobalEncoded") -> bytes:
+    p = enc.params
+    nb = len(enc.blocks)
+    payloads = [global_batch_payload(enc.codes[i:i + dls.BATCH_BLOCKS], p.np_dtype)
+                for i in range(0, nb, dls.BATCH_BLOCKS)]
+    payloads += [global_basis_payload(enc.kind, enc.bases[v], float(enc.budgets[v])) for v in range(p.nvars)]
+    return _pack(p, nb, [[]] * p.nvars, payloads, 4)
+
+
+def unpack_global(buf: bytes) -> "globalbasis.GlobalEncoded":
+    p, bits, nblocks, table, hdr_len = parse_header(buf)
+    if not stream_flags(buf) & 4:
+        raise CorruptStream("not a global-basis stream")
+    if p.window != 1:
+        raise CorruptStream("global-basis stream with window != 1")
+    m = p.px * p.py * p.pz
+    if m > globalbasis.MAX_M or p.px > p.nx or p.py > p.ny or p.pz > p.nz:
+        raise CorruptStream("bad patch size")
+    npb = (nblocks + dls.BATCH_BLOCKS - 1) // dls.BATCH_BLOCKS
+    if len(table) != npb + p.nvars:
+        raise CorruptStream("batch count mismatch")
+    blocks = dls.make_blocks(p, [dls.uniform_leaves(p)] * p.nvars)
+    if len(blocks) != nblocks:
+        raise CorruptStream("block count mismatch")
+
+    def inflate(i):
+        off, csz, usz = table[i]
+        s0 = hdr_len + off
+        if s0 + csz > len(buf):
+            raise CorruptStream("batch beyond end of stream")
+        try:
+            raw = zlib.decompress(buf[s0:s0 + csz])
+        except zlib.error as e:
+            raise CorruptStream("zlib: %s" % e)
+        if len(raw) != usz:
+            raise CorruptStream("batch size mismatch")
+        return raw
+    bases, cvs, kind = [], [], 0
+    for v in range(p.nvars):
+        raw = inflate(npb + v)
+        if len(raw) != 16 + 4 * m * m:
+            raise CorruptStream("basis batch size")
+        kind, mm, cv = struct.unpack_from("<IId", raw, 0)
+        if mm != m:
+            raise CorruptStream("basis size mismatch")
+        q = unzigzag32(unplanes(raw[16:], m * m, 4, np.uint32)).reshape(m, m)
+        bases.append(q.astype(np.float64) * 2.0 ** -globalbasis.BASIS_BITS)
+        cvs.append(cv)
+    dtype = p.np_dtype
+    esz = np.dtype(dtype).itemsize
+    codes = []
+    for i in range(npb):
+        raw = inflate(i)
+        bl = blocks[i * dls.BATCH_BLOCKS:(i + 1) * dls.BATCH_BLOCKS]
+        nb = len(bl)
+        pos = 0
+
+        def take(n):
+            nonlocal pos
+            if pos + n > len(raw):
+                raise CorruptStream("batch payload truncated")
+            out = raw[pos:pos + n]
+            pos += n
+            return out
+        counts = unplanes(take(2 * nb), nb, 2, np.int64)
+        exps = unplanes(take(2 * nb), nb, 2, np.uint16).astype(np.uint16).view(np.int16).astype(np.int64)
+        for c in counts:
+            if c != globalbasis.RAW and c > m:
+                raise CorruptStream("coefficient count out of range")
+        live = [int(c) for c in counts if c != globalbasis.RAW]
+        tot = sum(live)
+        idx = unplanes(take(2 * tot), tot, 2, np.int64)
+        qs = unzigzag32(unplanes(take(4 * tot), tot, 4, np.uint32))
+        if tot and (idx.max() >= m):
+            raise CorruptStream("basis index out of range")
+        at = 0
+        for b, c, k in zip(bl, counts, exps):
+            if c == globalbasis.RAW:
+                rv = np.frombuffer(take(esz * b.m), dtype=np.dtype(dtype).newbyteorder("<")).astype(dtype)
+                codes.append(globalbasis.PatchCode(globalbasis.RAW, 0, np.zeros(0, np.int64), np.zeros(0, np.int64),
+                                                   rv))
+                continue
+            kept = idx[at:at + c]
+            if c > 1 and np.any(np.diff(kept) <= 0):
+                raise CorruptStream("basis indices not ascending")
+            codes.append(globalbasis.PatchCode(int(c), int(k), kept, qs[at:at + c], None))
+            at += int(c)
+        if pos != len(raw):
+            raise CorruptStream("trailing bytes in batch")
+    return globalbasis.GlobalEncoded(p, int(kind), 0, bases, np.array(cvs), blocks, codes)
+
+
 def parse_header(buf: bytes):
     """(Params, split bits per var, nblocks, batch table, header length)."""
     if len(buf) < _FIXED.size:
@@ -284,6 +408,8 @@ def unpack(buf: bytes) -> "dls.Encoded":
     p, bits, nblocks, table, hdr_len = parse_header(buf)
     if stream_flags(buf) & 2:
         raise CorruptStream("an L2-mode stream (decode with oracle.l2)")
+    if stream_flags(buf) & 4:
+        raise CorruptStream("a global-basis stream (decode with oracle.globalbasis)")
     if p.adaptive:
         try:
             lv = [dls.leaves_from_bits(p, bits[v]) for v in range(p.nvars)]

@@ -14,6 +14,7 @@ import numpy as np
 
 import synth
 from oracle import container, dls, l2
+from oracle import globalbasis as gb
 from oracle.jacobi import cyclic_jacobi
 
 SHAPES = [(16, 64), (16, 16), (4, 64), (32, 128), (5, 7), (1, 9), (16, 512)]
@@ -620,6 +621,154 @@ def pin_l2_special_blocks():
     assert np.array_equal(l2.reconstruct(enc), g)
 
 
+# ---------------------------------------------------------------- global basis
+
+def pin_splitmix64_published():
+    """The generator's first outputs from state 0, as published with it."""
+    g = gb.SplitMix64(0)
+    assert [g.next() for _ in range(3)] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def pin_cosine_basis():
+    """The cosine basis is the orthonormal DCT-II: its 1D factor equals the
+    library's orthonormal DCT-II matrix, the tensor basis is orthonormal and
+    the 2 x 2 case is the hand-worked one."""
+    from scipy.fft import dct
+    for n in (1, 2, 5, 8):
+        assert np.allclose(gb.cosine_basis(n, 1, 1), dct(np.eye(n), type=2, norm="ortho", axis=0).T, atol=1e-15)
+    phi = gb.cosine_basis(4, 3, 2)
+    assert np.abs(phi.T @ phi - np.eye(24)).max() < 1e-14
+    h = np.array([[0.5, 0.5, 0.5, 0.5], [0.5, -0.5, 0.5, -0.5], [0.5, 0.5, -0.5, -0.5], [0.5, -0.5, -0.5, 0.5]]).T
+    assert np.abs(gb.cosine_basis(2, 2, 1) - h).max() < 1e-15
+
+
+def pin_global_sampling_and_svd_basis():
+    """Q holds S = 4M patches of snapshot 0 at in-range positions (checked
+    against the field by brute force); the learned basis diagonalises Q^T Q
+    with eigenvalues equal to the squared singular values from the library's
+    SVD, descending, canonical signs, orthonormal to the 2^-24 grid."""
+    f = synth.blobs2d(nx=20, ny=12, nt=3, seed=3, nblobs=3)
+    p = dls.Params(nx=20, ny=12, nz=1, nt=3, nvars=1, dtype="f64", px=4, py=3, pz=1, window=1, eps=[1e-3])
+    pos = gb.sample_positions(p, 0, 5, 48)
+    assert len(pos) == 48 and all(0 <= x <= 16 and 0 <= y <= 9 and z == 0 for x, y, z in pos)
+    assert len(set(pos)) > 30
+    Q = gb.sample_matrix(f, p, 0, 5)
+    assert Q.shape == (48, 12)
+    for r, (x0, y0, _) in enumerate(pos):
+        for j in range(3):
+            for i in range(4):
+                assert Q[r, j * 4 + i] == f[0, 0, 0, y0 + j, x0 + i]
+    phi = gb.learn_basis(f, p, 0, gb.KIND_SVD, 5)
+    sv = np.linalg.svd(Q, compute_uv=False)
+    lam = np.diag(phi.T @ (Q.T @ Q) @ phi)
+    assert np.all(np.diff(lam) <= 1e-9 * lam[0])
+    assert np.allclose(lam, sv ** 2, rtol=1e-6, atol=1e-9 * sv[0] ** 2)
+    assert np.abs(phi.T @ phi - np.eye(12)).max() < 1e-6
+    for k in range(12):
+        i = int(np.argmax(np.abs(phi[:, k])))
+        assert phi[i, k] > 0
+    assert np.all(np.rint(phi * 2.0 ** 24) == phi * 2.0 ** 24)
+    # the random basis: eigenbasis of a uniform [-1, 1) matrix, orthonormal
+    R = gb.random_matrix(p, 0, 5)
+    assert R.shape == (12, 12) and R.min() >= -1.0 and R.max() < 1.0 and abs(R.mean()) < 0.2
+    pr = gb.learn_basis(f, p, 0, gb.KIND_RANDOM, 5)
+    assert np.abs(pr.T @ pr - np.eye(12)).max() < 1e-6
+
+
+def pin_global_hand_case():
+    """The hand-worked 2 x 2 patch (tests/golden/global_patch_2x2.json)."""
+    fx = _golden("global_patch_2x2.json")
+    u = np.array(fx["inputs"]["u"]).reshape(1, 1, 1, 2, 2)
+    for t, ex in ((fx["inputs"]["target"], fx["expected"]), (fx["inputs"]["target_b"], fx["expected"]["b"])):
+        p = dls.Params(nx=2, ny=2, nz=1, nt=1, nvars=1, dtype="f64", px=2, py=2, pz=1, window=1, eps=[t])
+        enc = gb.encode(u, p, gb.KIND_COSINE)
+        c = enc.codes[0]
+        assert (c.n, c.k, list(c.kept), list(c.q)) == (ex["n"], ex["k"], ex["kept"], ex["q"])
+        assert c.e2 == ex["e2"] and c.err == ex["err"]
+        assert list(gb.reconstruct(enc).ravel()) == ex["xhat"]
+    assert list(enc.bases[0].T @ np.array(fx["inputs"]["u"])) == fx["expected"]["alpha"]
+    assert np.abs(gb.cosine_basis(2, 2, 1).T @ np.array(fx["inputs"]["u"]) - fx["expected"]["alpha"]).max() < 1e-14
+
+
+def _global_fields():
+    a = synth.blobs2d(nx=40, ny=24, nt=6, seed=9, nblobs=5, dtype=np.float32)
+    pa = dict(nx=40, ny=24, nz=1, nt=6, nvars=1, dtype="f32", px=8, py=8, pz=1, window=1)
+    b = np.concatenate([synth.spectrum(12, 10, 8, 3, nmodes=8, seed=s, drift=True) for s in (3, 4)])
+    pb = dict(nx=12, ny=10, nz=8, nt=3, nvars=2, dtype="f32", px=4, py=4, pz=4, window=1)
+    return [(a, pa), (b, pb)]
+
+
+def pin_global_bound_and_round_trip():
+    """For every basis kind: every patch's exact error within its e2 (the
+    sum of the e2 is the squared global budget), every variable's NRMSE
+    within its target, the kept count never below the energy rule's, and
+    the stream reproduces the decoded field bit for bit (edge patches of
+    the 3D field are truncated)."""
+    for kind in (gb.KIND_SVD, gb.KIND_COSINE, gb.KIND_RANDOM):
+        for target in (1e-2, 1e-4):
+            for f, kw in _global_fields():
+                p = dls.Params(eps=[target] * kw["nvars"], **kw)
+                enc = gb.encode(f, p, kind, seed=11)
+                out = gb.reconstruct(enc)
+                for b, c in zip(enc.blocks, enc.codes):
+                    xb = dls.gather(f, b).astype(np.float64)
+                    ob = dls.gather(out, b).astype(np.float64)
+                    assert float(np.sum((xb - ob) ** 2)) <= c.e2
+                    assert c.n == gb.RAW or c.n >= c.n0
+                for v in range(p.nvars):
+                    e2sum = sum(c.e2 for b, c in zip(enc.blocks, enc.codes) if b.var == v)
+                    want = target ** 2 * float(np.sum(f[v].astype(np.float64) ** 2))
+                    assert abs(e2sum - want) <= 1e-9 * want
+                    assert l2.nrmse_fraction(f[v], out[v]) <= target
+                assert np.array_equal(gb.decompress(container.pack_global(enc)).view(np.uint8), out.view(np.uint8))
+
+
+def pin_global_parseval_selection():
+    """With an orthonormal basis the energy rule's dropped energy is the
+    squared projection error of the kept coefficients (before rounding),
+    and no other set of the same size drops less (brute force over all
+    subsets of a 6-point patch)."""
+    import itertools
+    rng = np.random.default_rng(4)
+    phi = gb.cosine_basis(3, 2, 1)
+    for _ in range(20):
+        u = rng.normal(size=6)
+        alpha = phi.T @ u
+        order = np.argsort(-np.abs(alpha), kind="stable")
+        for n in range(7):
+            kept = order[:n]
+            proj = phi[:, kept] @ alpha[kept]
+            dropped = float(np.sum(alpha[order[n:]] ** 2))
+            assert abs(float(np.sum((u - proj) ** 2)) - dropped) <= 1e-12 * float(u @ u)
+            best = min(float(np.sum(np.delete(alpha, list(c)) ** 2)) for c in itertools.combinations(range(6), n))
+            assert dropped <= best + 1e-12
+
+
+def pin_global_special_patches():
+    """A non-finite patch is raw and returned exactly; a zero patch keeps
+    no coefficient; a target below the dtype's resolution makes patches
+    raw; the SVD basis beats the random one on a smooth field (fewer kept
+    coefficients), the study's qualitative ordering."""
+    f = synth.blobs2d(nx=16, ny=8, nt=2, seed=7, nblobs=3)
+    f[0, :, 0, :, 8:] = 0.0
+    f[0, 1, 0, 2, 1] = np.nan
+    p = dls.Params(nx=16, ny=8, nz=1, nt=2, nvars=1, dtype="f64", px=8, py=8, pz=1, window=1, eps=[1e-2])
+    enc = gb.encode(f, p, gb.KIND_COSINE)
+    ns = [c.n for c in enc.codes]
+    assert ns[1] == 0 and ns[3] == 0 and ns[2] == gb.RAW and ns[0] not in (0, gb.RAW)
+    out = gb.reconstruct(enc)
+    assert np.array_equal(np.isnan(out), np.isnan(f))
+    g = (synth.blobs2d(nx=8, ny=8, nt=1, seed=8, nblobs=2) + 1e6).astype(np.float32)
+    q = dls.Params(nx=8, ny=8, nz=1, nt=1, nvars=1, dtype="f32", px=8, py=8, pz=1, window=1, eps=[1e-12])
+    enc = gb.encode(g, q, gb.KIND_SVD, seed=1)
+    assert enc.codes[0].n == gb.RAW and np.array_equal(gb.reconstruct(enc), g)
+    h = synth.blobs2d(nx=48, ny=48, nt=2, seed=2, nblobs=6)
+    r = dls.Params(nx=48, ny=48, nz=1, nt=2, nvars=1, dtype="f64", px=8, py=8, pz=1, window=1, eps=[1e-3])
+    svd = np.mean([c.n for c in gb.encode(h, r, gb.KIND_SVD, seed=2).codes])
+    rnd = np.mean([c.n for c in gb.encode(h, r, gb.KIND_RANDOM, seed=2).codes])
+    assert svd < rnd
+
+
 ALL_PINS = [
     pin_eigenvalues_vs_svd, pin_eigenvectors_orthonormal_and_residual,
     pin_eigenvalues_vs_jacobi, pin_rank_bruteforce, pin_exact_rank_data,
@@ -628,4 +777,6 @@ ALL_PINS = [
     pin_adaptive_plan, pin_container_round_trip, pin_round_bf16, pin_moments_hand_case,
     pin_nrmse_hand_case, pin_sign_tie, pin_rank_one_single_pass, pin_l2_eckart_young, pin_l2_hand_case,
     pin_l2_budgets_sum, pin_l2_bound_and_round_trip, pin_l2_ranks_grow, pin_l2_special_blocks,
+    pin_splitmix64_published, pin_cosine_basis, pin_global_sampling_and_svd_basis, pin_global_hand_case,
+    pin_global_bound_and_round_trip, pin_global_parseval_selection, pin_global_special_patches,
 ]

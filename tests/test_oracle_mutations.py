@@ -15,8 +15,9 @@ import pytest
 sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
 import oracle_pins as P  # noqa: E402
 from oracle import dls, l2, learned  # noqa: E402
+from oracle import globalbasis  # noqa: E402
 
-MODULES = {"dls": dls, "learned": learned, "l2": l2}
+MODULES = {"dls": dls, "learned": learned, "l2": l2, "globalbasis": globalbasis}
 
 # (function, original text, planted mistake); functions of oracle.learned are
 # prefixed "learned."
@@ -74,6 +75,24 @@ MUTATIONS = [
     ("l2.block_budget", "return c_v * b.m * b.w", "return c_v * b.m"),
     ("l2.nrmse_fraction", "return float(np.sqrt(np.sum(d * d)) / np.sqrt(np.sum(np.where(fin, a * a, 0.0))))",
      "return float(np.sum(d * d) / np.sum(np.where(fin, a * a, 0.0)))"),
+    ("globalbasis.SplitMix64", "z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK",
+     "z = ((z ^ (z >> 31)) * 0xBF58476D1CE4E5B9) & _MASK"),
+    ("globalbasis.cosine_basis", "math.sqrt((1.0 if a == 0 else 2.0) / n)", "math.sqrt(2.0 / n)"),
+    ("globalbasis.cosine_basis", "math.cos(math.pi * (2 * i + 1) * a / (2 * n))",
+     "math.cos(math.pi * (2 * i + 1) * a / n)"),
+    ("globalbasis.sample_matrix", "patch = field[v, 0, z0:z0 + p.pz, y0:y0 + p.py, x0:x0 + p.px]",
+     "patch = field[v, 1, z0:z0 + p.pz, y0:y0 + p.py, x0:x0 + p.px]"),
+    ("globalbasis.sample_positions", "x0 = g.next() % (p.nx - p.px + 1)", "x0 = g.next() % (p.nx - p.px + 2)"),
+    ("globalbasis.learn_basis", "_, V = dls.eig_desc(Q.T @ Q)", "_, V = dls.eig_desc(Q.T @ Q[::-1])"),
+    ("globalbasis.variable_budgets", "c.append(float(targets[v]) ** 2 * float(np.sum(x * x))",
+     "c.append(float(targets[v]) * float(np.sum(x * x))"),
+    ("globalbasis.encode_patch", "order = np.argsort(-np.abs(alpha), kind=\"stable\")",
+     "order = np.argsort(np.abs(alpha), kind=\"stable\")"),
+    ("globalbasis.encode_patch", "if tail[j] <= TAIL_SHARE * e2", "if tail[j] <= e2"),
+    ("globalbasis.step_exponent", "return e - 1", "return e"),
+    ("globalbasis.encode_patch", "kept = np.sort(order[:n])", "kept = order[:n]"),
+    ("globalbasis.decode_patch", "acc = acc + phi[idx, s] * (float(qs) * d)",
+     "acc = acc + phi[s, idx] * (float(qs) * d)"),
 ]
 
 

@@ -93,7 +93,7 @@ enum {
                         the call again two-pass.  The stream decodes to
                         the same guarantees; its rank-1 bases come from the
                         power iteration instead of Jacobi. */
-  DLS_L2 = 8         /* L2 / NRMSE-bounded mode, the paper's error control
+  DLS_L2 = 8,        /* L2 / NRMSE-bounded mode, the paper's error control
                         (Sec. 2.4: global budget eps_t ||u||, Eq. (4)
                         equal-share local tolerance; Alg. 1 step 3: fewest
                         coefficients meeting it).  abs_eps[v] is then the
@@ -111,7 +111,39 @@ enum {
                         rank test resolves tails of ~1e-8 of a block's
                         energy at tight targets.  Not with DLS_LEARNED;
                         DLS_PERSISTENT has no effect. */
+  DLS_GLOBAL = 16    /* the paper's global-basis method (Sec. 2.2-2.5,
+                        Alg. 1): one M x M basis per variable (M = px py pz
+                        <= 1024, px <= nx, py <= ny, pz <= nz) learned once
+                        (dls_params.basis), applied to every patch of every
+                        snapshot (window must be 1).  DLS_BASIS_SVD: S = 4M
+                        patches of snapshot 0 at SplitMix64 positions
+                        (state seed + v, three draws per patch: x0, y0, z0
+                        modulo their ranges) form Q; the full eigenbasis of
+                        Q^T Q, eigenvalues descending, canonical signs
+                        (Eqs. (2)-(3), no truncation).  DLS_BASIS_COSINE /
+                        DLS_BASIS_RANDOM: the orthonormal DCT-II tensor
+                        basis / the eigenbasis of an M x M matrix of
+                        uniform [-1, 1) SplitMix64 draws (Sec. 4's study).
+                        The basis is stored on the 2^-24 grid.  abs_eps[v]
+                        is the NRMSE target as in DLS_L2; a patch of one
+                        snapshot gets e2 = eps_t^2 ||u_v||^2 M_b / K_v and
+                        keeps the fewest coefficients alpha = Phi^T u in
+                        decreasing |alpha| (ties: lower index) whose
+                        dropped energy is <= 0.36 e2 (Eq. (6)), groomed to
+                        the grid 2^floor(log2(0.4 sqrt(e2 / n))); the exact
+                        error of the decoded values must be <= e2, else one
+                        more coefficient, and the patch is stored verbatim
+                        past n = M.  Edge patches are zero-padded.  Not with
+                        DLS_ADAPTIVE, DLS_LEARNED or DLS_L2; precision and
+                        DLS_PERSISTENT have no effect.  Device memory:
+                        16 B per value beyond the field (coefficients and
+                        per-patch slots). */
 };
+
+/* dls_params.basis (DLS_GLOBAL) */
+typedef enum { DLS_BASIS_SVD = 0, DLS_BASIS_COSINE = 1, DLS_BASIS_RANDOM = 2 } dls_basis_kind;
+
+struct dls_model;
 
 typedef struct dls_params {
   uint32_t struct_size;    /* = sizeof(dls_params); ABI versioning          */
@@ -127,9 +159,19 @@ typedef struct dls_params {
   int32_t r_max;           /* rank cap, 0 -> min(window, 32)                */
   int32_t precision;       /* dls_precision                                 */
   uint32_t flags;          /* DLS_ADAPTIVE | DLS_LEARNED | DLS_PERSISTENT |
-                              DLS_L2                                        */
+                              DLS_L2 | DLS_GLOBAL                           */
   const double* abs_eps;   /* host array of nvars absolute bounds, each
                               finite and > 0; read during the call only    */
+  int32_t basis;           /* DLS_GLOBAL: dls_basis_kind                    */
+  uint64_t seed;           /* DLS_GLOBAL: state of the learning draws       */
+  struct dls_model* model; /* DLS_LEARNED in dls_compress: the warm-start
+                              model (dls_model_create / dls_model_set);
+                              NULL otherwise.  Not owned; must outlive the
+                              call.  The context API takes it through
+                              dls_ctx_set_model instead (this field is
+                              ignored by dls_encode).                        */
+  int32_t warm_iters;      /* with model: subspace iterations, 0 -> 2       */
+  int32_t rank_margin;     /* with model: predicted-rank margin, 0..8       */
 } dls_params;
 
 /* Per-call results of dls_encode, in device memory owned by the context
@@ -312,7 +354,7 @@ dls_status dls_stats(const uint8_t* in, size_t in_bytes, dls_stream_stats* s);
 #define DLS_MODEL_NPARAM 61968
 #define DLS_NFEAT 80
 #define DLS_NOUT 272
-typedef struct dls_model dls_model;
+typedef struct dls_model dls_model;  /* declared above as struct dls_model */
 /* Create a model on `device` with all parameters zero and identity
  * normalisation; set them with dls_model_set. */
 dls_status dls_model_create(int device, dls_model** out);

@@ -14,7 +14,8 @@ Header (little-endian):
     i32 ndim, nvars, dtype (0 f32, 1 f64), r_max
     i64 nx, ny, nz, nt
     i32 px, py, pz, pmin, window, batch_blocks
-    u64 nblocks; u32 nbatches; u32 reserved (0)
+    u64 nblocks; u32 nbatches; u32 extra (the basis kind in the global-basis
+    mode, else 0)
     f64 eps[nvars]
     per variable: u32 nbits, then ceil(nbits/8) bytes of split bits (LSB first)
     per batch:    u64 offset (from header end), u64 compressed size,
@@ -137,7 +138,7 @@ def pack(enc: "dls.Encoded") -> bytes:
     return fixed + eps + plan_bytes + tab + b"".join(streams)
 
 
-def _pack(p, nb, bits, payloads, flags):
+def _pack(p, nb, bits, payloads, flags, extra=0):
     streams, table = [], []
     off = 0
     for raw in payloads:
@@ -151,7 +152,7 @@ def _pack(p, nb, bits, payloads, flags):
                         p.ndim, p.nvars, 0 if p.dtype == "f32" else 1,
                         p.resolved_rmax(), p.nx, p.ny, p.nz, p.nt,
                         p.px, p.py, p.pz, p.pmin, p.window, dls.BATCH_BLOCKS,
-                        nb, len(payloads), 0)
+                        nb, len(payloads), extra)
     eps = struct.pack("<%dd" % p.nvars, *[float(e) for e in p.eps])
     tab = b"".join(struct.pack("<QQQ", *t) for t in table)
     return fixed + eps + plan_bytes + tab + b"".join(streams)
@@ -279,7 +280,7 @@ def pack_global(enc: "globalbasis.GlobalEncoded") -> bytes:
     payloads = [global_batch_payload(enc.codes[i:i + dls.BATCH_BLOCKS], p.np_dtype)
                 for i in range(0, nb, dls.BATCH_BLOCKS)]
     payloads += [global_basis_payload(enc.kind, enc.bases[v], float(enc.budgets[v])) for v in range(p.nvars)]
-    return _pack(p, nb, [[]] * p.nvars, payloads, 4)
+    return _pack(p, nb, [[]] * p.nvars, payloads, 4, enc.kind)
 
 
 def unpack_global(buf: bytes) -> "globalbasis.GlobalEncoded":
@@ -310,14 +311,17 @@ def unpack_global(buf: bytes) -> "globalbasis.GlobalEncoded":
         if len(raw) != usz:
             raise CorruptStream("batch size mismatch")
         return raw
-    bases, cvs, kind = [], [], 0
+    bases, cvs = [], []
+    kind = _FIXED.unpack_from(buf, 0)[-1]
+    if kind > 2:
+        raise CorruptStream("unknown basis kind")
     for v in range(p.nvars):
         raw = inflate(npb + v)
         if len(raw) != 16 + 4 * m * m:
             raise CorruptStream("basis batch size")
-        kind, mm, cv = struct.unpack_from("<IId", raw, 0)
-        if mm != m:
-            raise CorruptStream("basis size mismatch")
+        k2, mm, cv = struct.unpack_from("<IId", raw, 0)
+        if mm != m or k2 != kind:
+            raise CorruptStream("basis batch header")
         q = unzigzag32(unplanes(raw[16:], m * m, 4, np.uint32)).reshape(m, m)
         bases.append(q.astype(np.float64) * 2.0 ** -globalbasis.BASIS_BITS)
         cvs.append(cv)

@@ -30,6 +30,8 @@ DLS_PERSISTENT = 4
 DLS_ADAPTIVE = 1
 DLS_LEARNED = 2
 DLS_L2 = 8
+DLS_GLOBAL = 16
+BASIS_KINDS = {"svd": 0, "cosine": 1, "random": 2}
 NPARAM = 61968
 WARM_MAX_POINTS = 256   # the warm start applies to blocks of at most this many points
 
@@ -54,7 +56,9 @@ class _Params(ctypes.Structure):
                 ("px", ctypes.c_int32), ("py", ctypes.c_int32), ("pz", ctypes.c_int32),
                 ("pmin", ctypes.c_int32), ("window", ctypes.c_int32), ("r_max", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("abs_eps", ctypes.POINTER(ctypes.c_double))]
+                ("abs_eps", ctypes.POINTER(ctypes.c_double)), ("basis", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("model", ctypes.c_void_p), ("warm_iters", ctypes.c_int32),
+                ("rank_margin", ctypes.c_int32)]
 
 
 class _EncodeInfo(ctypes.Structure):
@@ -162,6 +166,12 @@ class Params:
     learned: bool = False
     persistent: bool = False  # device-driven (batched) encode launch
     l2: bool = False          # L2 / NRMSE-bounded mode: eps holds the NRMSE targets (fractions)
+    global_basis: bool = False  # the paper's global-basis method (window 1, eps = NRMSE targets)
+    basis: str = "svd"        # global basis: "svd" | "cosine" | "random"
+    seed: int = 0             # global basis: state of the learning draws
+    model: object = None      # dls_compress with learned: the warm-start Model
+    warm_iters: int = 0       # with model: 0 -> 2
+    rank_margin: int = 1      # with model
     _keep: list = dc_field(default_factory=list, repr=False)
 
     def to_c(self) -> _Params:
@@ -172,8 +182,11 @@ class Params:
                        self.pmin, self.window, self.r_max,
                        DLS_PREC_BF16 if self.precision == "bf16" else DLS_PREC_FP32,
                        (DLS_ADAPTIVE if self.adaptive else 0) | (DLS_LEARNED if self.learned else 0)
-                       | (DLS_PERSISTENT if self.persistent else 0) | (DLS_L2 if self.l2 else 0),
-                       ctypes.cast(arr, ctypes.POINTER(ctypes.c_double)))
+                       | (DLS_PERSISTENT if self.persistent else 0) | (DLS_L2 if self.l2 else 0)
+                       | (DLS_GLOBAL if self.global_basis else 0),
+                       ctypes.cast(arr, ctypes.POINTER(ctypes.c_double)), BASIS_KINDS[self.basis],
+                       int(self.seed) & ((1 << 64) - 1),
+                       self.model._h if self.model is not None else None, self.warm_iters, self.rank_margin)
 
     @property
     def torch_dtype(self):
@@ -317,7 +330,9 @@ def query(buf: bytes):
     p = Params(nx=cp.nx, ny=cp.ny, nz=cp.nz, nt=cp.nt, nvars=cp.nvars,
                dtype="f32" if cp.dtype == DLS_F32 else "f64", px=cp.px, py=cp.py, pz=cp.pz,
                window=cp.window, eps=[eps[i] for i in range(cp.nvars)], pmin=cp.pmin,
-               r_max=cp.r_max, adaptive=bool(cp.flags & DLS_ADAPTIVE), l2=bool(cp.flags & DLS_L2))
+               r_max=cp.r_max, adaptive=bool(cp.flags & DLS_ADAPTIVE), l2=bool(cp.flags & DLS_L2),
+               global_basis=bool(cp.flags & DLS_GLOBAL),
+               basis={v: k for k, v in BASIS_KINDS.items()}.get(cp.basis, "svd"))
     return p, nb.value
 
 

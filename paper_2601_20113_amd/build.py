@@ -19,7 +19,7 @@ HIP_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-pass-failed",
 ]
-HIP_SOURCES = ["dls_kernels.hip", "dls_plan.hip", "dls_learned.hip", "dls_l2.hip", "dls_api.hip"]
+HIP_SOURCES = ["dls_kernels.hip", "dls_plan.hip", "dls_learned.hip", "dls_l2.hip", "dls_global.hip", "dls_api.hip"]
 # dls_codec.hip holds the encode / decode kernels; it is compiled once per
 # (padded window, element type, part) so that its rank-class instantiations
 # build in parallel: (tag, W, element type, points per thread)

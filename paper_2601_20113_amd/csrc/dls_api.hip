@@ -113,9 +113,21 @@ dls_status validate(const dls_params* in, Problem& p) {
   if (p.nz == 1 && p.pz != 1) return fail(DLS_EINVAL, "pz must be 1 for a 2D field");
   if (in->r_max < 0 || in->r_max > 32) return fail(DLS_EINVAL, "r_max must be in [0, 32]");
   p.r_max = in->r_max > 0 ? in->r_max : std::min(p.window, 32);
-  if (p.flags & ~uint32_t(DLS_ADAPTIVE | DLS_LEARNED | DLS_PERSISTENT | DLS_L2))
+  if (p.flags & ~uint32_t(DLS_ADAPTIVE | DLS_LEARNED | DLS_PERSISTENT | DLS_L2 | DLS_GLOBAL))
     return fail(DLS_EINVAL, "unknown flags");
   if ((p.flags & DLS_L2) && (p.flags & DLS_LEARNED)) return fail(DLS_EINVAL, "DLS_L2 does not take DLS_LEARNED");
+  if (p.flags & DLS_GLOBAL) {
+    if (p.flags & (DLS_ADAPTIVE | DLS_LEARNED | DLS_L2))
+      return fail(DLS_EINVAL, "DLS_GLOBAL does not take DLS_ADAPTIVE, DLS_LEARNED or DLS_L2");
+    if (p.window != 1) return fail(DLS_EINVAL, "DLS_GLOBAL encodes every snapshot on its own: window must be 1");
+    if (int64_t(p.px) * p.py * p.pz > kGbMaxM) return fail(DLS_EINVAL, "DLS_GLOBAL needs px * py * pz <= 1024");
+    if (p.px > p.nx || p.py > p.ny || p.pz > p.nz) return fail(DLS_EINVAL, "DLS_GLOBAL needs the patch inside the grid");
+    if (in->basis < DLS_BASIS_SVD || in->basis > DLS_BASIS_RANDOM) return fail(DLS_EINVAL, "unknown basis kind");
+    p.basis = in->basis;
+    p.seed = in->seed;
+  }
+  if (in->warm_iters < 0 || in->warm_iters > 8) return fail(DLS_EINVAL, "warm_iters must be in [0, 8]");
+  if (in->rank_margin < 0 || in->rank_margin > 8) return fail(DLS_EINVAL, "rank_margin must be in [0, 8]");
   if ((p.flags & DLS_LEARNED) && p.window > 16) return fail(DLS_EINVAL, "DLS_LEARNED needs window <= 16");
   if (p.precision != DLS_PREC_FP32 && p.precision != DLS_PREC_BF16)
     return fail(DLS_EINVAL, "unknown precision");
@@ -278,6 +290,14 @@ struct dls_ctx {
   // L2 mode: per-block rank bytes, steps, budgets, errors; slice errors
   DevBuf l2rank, l2step, l2e2, l2berr, l2ovf, l2errp, l2cv, l2part, l2tgt;  // l2part: per-slice sums of squares
   int l2_passes = 0;           // encode passes the last L2 call took
+  // global-basis mode: bases, budgets, learning workspace, coefficients,
+  // per-patch counts / exponents / slots, packed payload
+  DevBuf gb_phi, gb_cv, gb_part, gb_tgt, gb_Q, gb_A0, gb_A1, gb_V, gb_norm, gb_alpha, gb_count, gb_kexp, gb_n0;
+  DevBuf gb_slot, gb_nidx, gb_nraw, gb_idx_off, gb_raw_off, gb_idx, gb_q, gb_raw, gb_tot;
+  int64_t gb_total = 0, gb_raw_bytes = 0;
+  int gb_M = 0;
+  std::vector<int32_t> gb_hcount;   // per-patch counts of the last call (host)
+  double* gb_host = nullptr;        // pinned: sweep norms, payload totals
   int64_t jacobi_sweeps = 0, jacobi_unconverged = 0;
   unsigned long long* jstats() { return reinterpret_cast<unsigned long long*>(counters.as<uint8_t>() + kJacobiAt); }
   PlanScratch* plan_scratch = nullptr;
@@ -315,6 +335,7 @@ struct dls_ctx {
     if (pinned) (void)hipHostFree(pinned);
     if (hcnt) (void)hipHostFree(hcnt);
     if (hfused) (void)hipHostFree(hfused);
+    if (gb_host) (void)hipHostFree(gb_host);
   }
 };
 
@@ -405,11 +426,14 @@ dls_status finish_encode(dls_ctx* ctx) {
     ctx->jacobi_ms = ms;
   }
   // every path's last full readback of the counter block follows its Jacobi
-  unsigned long long js[1 + kJacobiSlots];
-  std::memcpy(js, ctx->hcnt + kJacobiAt, sizeof(js));
-  ctx->jacobi_unconverged = int64_t(js[0]);
-  ctx->jacobi_sweeps = 0;
-  for (int k = 1; k <= kJacobiSlots; ++k) ctx->jacobi_sweeps += int64_t(js[k]);
+  // (the global-basis mode counts its sweeps on the host)
+  if (!(ctx->prob.flags & DLS_GLOBAL)) {
+    unsigned long long js[1 + kJacobiSlots];
+    std::memcpy(js, ctx->hcnt + kJacobiAt, sizeof(js));
+    ctx->jacobi_unconverged = int64_t(js[0]);
+    ctx->jacobi_sweeps = 0;
+    for (int k = 1; k <= kJacobiSlots; ++k) ctx->jacobi_sweeps += int64_t(js[k]);
+  }
   ctx->have_result = true;
   return DLS_OK;
 }
@@ -510,6 +534,383 @@ dls_status l2_encode(dls_ctx* ctx, const void* d_field, const Problem& p, const 
   ctx->nwarm_accept = ctx->nwarm_reject = 0;
   ctx->nfast_accept = ctx->ndeferred = 0;
   ctx->launch_mode = 0;
+  return DLS_OK;
+}
+}  // namespace
+
+namespace {
+// Global-basis encode (DLS_GLOBAL; Alg. 1 as the paper states it): the
+// budget of every variable, then per variable its basis (learned by the
+// parallel Jacobi on the FP64 Gram of the learning patches, or the cosine
+// basis), then the coefficients of every patch-snapshot on the matrix
+// cores, the per-patch selection with its exact check, and the packed
+// payload.  One host round trip per Jacobi sweep (its convergence test)
+// and one for the payload totals.
+dls_status global_encode(dls_ctx* ctx, const void* d_field, const Problem& p, const Dims& dims, hipStream_t s) {
+  const Plan& pl = ctx->plan;
+  const int64_t nb = int64_t(pl.blocks.size());
+  const int M = p.px * p.py * p.pz, Mp = M + (M & 1);
+  const int es = p.esize();
+  ctx->gb_M = M;
+  if (nb % p.nvars != 0) return fail(DLS_EDEVICE, "global plan is not variable-major");
+  const int64_t nbv = nb / p.nvars;
+  if (ctx->gb_host == nullptr) {
+    void* q = nullptr;
+    HIP_TRY(hipHostMalloc(&q, 64, hipHostMallocDefault));
+    ctx->gb_host = static_cast<double*>(q);
+  }
+  HIP_TRY(ctx->gb_tgt.ensure(size_t(p.nvars) * 8));
+  HIP_TRY(ctx->gb_cv.ensure(size_t(p.nvars) * 8));
+  HIP_TRY(ctx->gb_part.ensure((size_t(p.nvars) + 2) * kGbParts * 8));
+  HIP_TRY(ctx->gb_norm.ensure(16));
+  HIP_TRY(ctx->gb_tot.ensure(16));
+  HIP_TRY(ctx->gb_phi.ensure(size_t(p.nvars) * M * M * 8));
+  HIP_TRY(hipMemcpyAsync(ctx->gb_tgt.p, p.eps.data(), size_t(p.nvars) * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipEventRecord(ctx->ev0, s));
+  HIP_TRY(launch_gb_budget(p.dtype, d_field, p.nt * p.nz * p.ny * p.nx, p.nvars, ctx->gb_tgt.as<double>(),
+                           ctx->gb_part.as<double>(), ctx->gb_cv.as<double>(), s));
+  // bases
+  ctx->jacobi_sweeps = ctx->jacobi_unconverged = 0;
+  HIP_TRY(hipEventRecord(ctx->evj[0], s));
+  double* normpart = ctx->gb_part.as<double>() + size_t(p.nvars) * kGbParts;
+  for (int v = 0; v < p.nvars; ++v) {
+    double* phi = ctx->gb_phi.as<double>() + size_t(v) * M * M;
+    if (p.basis == DLS_BASIS_COSINE) {
+      HIP_TRY(launch_gb_cosine(p.px, p.py, p.pz, phi, s));
+      continue;
+    }
+    const int64_t S = p.basis == DLS_BASIS_SVD ? 4 * int64_t(M) : M;
+    HIP_TRY(ctx->gb_Q.ensure(size_t(S) * M * 8));
+    HIP_TRY(ctx->gb_A0.ensure(size_t(Mp) * Mp * 8));
+    HIP_TRY(ctx->gb_A1.ensure(size_t(Mp) * Mp * 8));
+    HIP_TRY(ctx->gb_V.ensure(size_t(Mp) * Mp * 8));
+    double *A0 = ctx->gb_A0.as<double>(), *A1 = ctx->gb_A1.as<double>(), *V = ctx->gb_V.as<double>();
+    HIP_TRY(launch_gb_samples(p.dtype, d_field, dims, v, p.px, p.py, p.pz, p.basis, p.seed + uint64_t(v), S,
+                              ctx->gb_Q.as<double>(), s));
+    HIP_TRY(launch_gb_gram(ctx->gb_Q.as<double>(), S, M, Mp, A0, s));
+    HIP_TRY(launch_gb_eye(V, Mp, s));
+    // sweeps of Mp - 1 rounds (odd, so each ends in A1; the norm kernel
+    // copies it back to A0) until off(A) <= 4e-16 M ||A||_F (the rounding
+    // floor of M^2 entries), or until a sweep leaves off(A) within 5 % of
+    // the previous one (stalled at the floor; early sweeps can shrink it
+    // by as little as a third, so only a stall counts)
+    bool conv = false;
+    int sweep = 0;
+    double prev = HUGE_VAL;
+    const double floor2 = (4e-16 * M) * (4e-16 * M);
+    while (!conv && sweep < kGbMaxSweeps) {
+      for (int r = 0; r < Mp - 1; ++r)
+        HIP_TRY(launch_gb_jacobi_round((r & 1) ? A1 : A0, (r & 1) ? A0 : A1, V, Mp, r, s));
+      HIP_TRY(launch_gb_offnorm(A1, A0, Mp, normpart, ctx->gb_norm.as<double>(), s));
+      HIP_TRY(hipMemcpyAsync(ctx->gb_host, ctx->gb_norm.p, 16, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      ++sweep;
+      const double off = ctx->gb_host[0], tot = ctx->gb_host[1];
+      conv = off <= floor2 * tot || off >= 0.9 * prev;
+      prev = off;
+    }
+    ctx->jacobi_sweeps += sweep;
+    if (!conv) ++ctx->jacobi_unconverged;
+    HIP_TRY(launch_gb_finish(A0, V, M, Mp, phi, s));
+  }
+  HIP_TRY(hipEventRecord(ctx->evj[1], s));
+  ctx->jacobi_timed = true;
+  HIP_TRY(hipEventRecord(ctx->evs[0], s));
+  // coefficients, one launch per variable (one basis per launch)
+  HIP_TRY(ctx->gb_alpha.ensure(size_t(nb) * M * 8));
+  for (int v = 0; v < p.nvars; ++v)
+    HIP_TRY(launch_gb_project(p.dtype, d_field, dims, ctx->desc.as<BlockDesc>(), v * nbv, (v + 1) * nbv,
+                              ctx->gb_phi.as<double>() + size_t(v) * M * M, p.px, p.py, M,
+                              ctx->gb_alpha.as<double>(), s));
+  HIP_TRY(hipEventRecord(ctx->evs[1], s));
+  HIP_TRY(ctx->gb_count.ensure(size_t(nb) * 4));
+  HIP_TRY(ctx->gb_kexp.ensure(size_t(nb) * 4));
+  HIP_TRY(ctx->gb_n0.ensure(size_t(nb) * 4));
+  HIP_TRY(ctx->gb_slot.ensure(size_t(nb) * 8 * M));
+  HIP_TRY(launch_gb_select(p.dtype, d_field, dims, ctx->desc.as<BlockDesc>(), nb, ctx->gb_phi.as<double>(),
+                           ctx->gb_cv.as<double>(), ctx->gb_alpha.as<double>(), p.px, p.py, M,
+                           ctx->gb_count.as<int32_t>(), ctx->gb_kexp.as<int32_t>(), ctx->gb_slot.as<uint8_t>(),
+                           ctx->gb_n0.as<int32_t>(), s));
+  HIP_TRY(hipEventRecord(ctx->evs[2], s));
+  HIP_TRY(hipEventRecord(ctx->evs[3], s));
+  // packed payload: offsets of the kept coefficients and of the raw values
+  HIP_TRY(ctx->gb_nidx.ensure(size_t(nb) * 8));
+  HIP_TRY(ctx->gb_nraw.ensure(size_t(nb) * 8));
+  HIP_TRY(ctx->gb_idx_off.ensure(size_t(nb) * 8));
+  HIP_TRY(ctx->gb_raw_off.ensure(size_t(nb) * 8));
+  HIP_TRY(ctx->scan_tmp.ensure(size_t(4 * (nb / 1024 + 4)) * sizeof(int64_t)));
+  HIP_TRY(launch_gb_sizes(ctx->desc.as<BlockDesc>(), nb, ctx->gb_count.as<int32_t>(), es,
+                          ctx->gb_nidx.as<int64_t>(), ctx->gb_nraw.as<int64_t>(), s));
+  HIP_TRY(launch_scan(ctx->gb_nidx.as<int64_t>(), nb, ctx->gb_idx_off.as<int64_t>(), ctx->scan_tmp.as<int64_t>(), s));
+  HIP_TRY(launch_scan(ctx->gb_nraw.as<int64_t>(), nb, ctx->gb_raw_off.as<int64_t>(), ctx->scan_tmp.as<int64_t>(), s));
+  HIP_TRY(launch_totals(ctx->gb_idx_off.as<int64_t>(), ctx->gb_nidx.as<int64_t>(), ctx->gb_raw_off.as<int64_t>(),
+                        ctx->gb_nraw.as<int64_t>(), nb, ctx->gb_tot.as<int64_t>(), s));
+  HIP_TRY(hipMemcpyAsync(ctx->gb_host + 2, ctx->gb_tot.p, 16, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  int64_t tot[2];
+  std::memcpy(tot, ctx->gb_host + 2, 16);
+  ctx->gb_total = tot[0];
+  ctx->gb_raw_bytes = tot[1];
+  HIP_TRY(ctx->gb_idx.ensure(size_t(std::max<int64_t>(tot[0], 1)) * 2));
+  HIP_TRY(ctx->gb_q.ensure(size_t(std::max<int64_t>(tot[0], 1)) * 4));
+  HIP_TRY(ctx->gb_raw.ensure(size_t(std::max<int64_t>(tot[1], 1))));
+  HIP_TRY(launch_gb_compact(ctx->desc.as<BlockDesc>(), nb, M, ctx->gb_count.as<int32_t>(), ctx->gb_slot.as<uint8_t>(),
+                            ctx->gb_idx_off.as<int64_t>(), ctx->gb_raw_off.as<int64_t>(), es,
+                            ctx->gb_idx.as<uint16_t>(), ctx->gb_q.as<int32_t>(), ctx->gb_raw.as<uint8_t>(), s));
+  HIP_TRY(hipEventRecord(ctx->ev1, s));
+  ctx->gb_hcount.resize(size_t(nb));
+  if (nb) HIP_TRY(hipMemcpyAsync(ctx->gb_hcount.data(), ctx->gb_count.p, size_t(nb) * 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  ctx->nraw = 0;
+  for (int32_t c : ctx->gb_hcount) ctx->nraw += c == kGbRaw ? 1 : 0;
+  ctx->nesc = ctx->nesc_slots = 0;
+  ctx->nwarm_accept = ctx->nwarm_reject = 0;
+  ctx->nfast_accept = ctx->ndeferred = 0;
+  ctx->launch_mode = 0;
+  ctx->qv_bytes = 0;
+  ctx->qa_bytes = 6 * tot[0] + tot[1];
+  return DLS_OK;
+}
+
+void put_planes(std::vector<uint8_t>& out, const uint8_t* src, int64_t n, int nbytes) {
+  for (int j = 0; j < nbytes; ++j)
+    for (int64_t i = 0; i < n; ++i) out.push_back(src[i * nbytes + j]);
+}
+
+dls_status global_finalize(dls_ctx* ctx, uint8_t** out, size_t* out_bytes) {
+  const Problem& p = ctx->prob;
+  const Plan& pl = ctx->plan;
+  const int64_t nb = int64_t(pl.blocks.size());
+  const int M = ctx->gb_M, es = p.esize();
+  std::vector<int32_t> kexp(nb);
+  std::vector<int64_t> ioff(nb), roff(nb);
+  std::vector<uint16_t> idx(std::max<int64_t>(ctx->gb_total, 1));
+  std::vector<int32_t> q(std::max<int64_t>(ctx->gb_total, 1));
+  std::vector<uint8_t> raw(std::max<int64_t>(ctx->gb_raw_bytes, 1));
+  std::vector<double> phi(size_t(p.nvars) * M * M), cv(p.nvars);
+  if (nb) {
+    HIP_TRY(hipMemcpy(kexp.data(), ctx->gb_kexp.p, nb * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(ioff.data(), ctx->gb_idx_off.p, nb * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(roff.data(), ctx->gb_raw_off.p, nb * 8, hipMemcpyDeviceToHost));
+  }
+  if (ctx->gb_total) {
+    HIP_TRY(hipMemcpy(idx.data(), ctx->gb_idx.p, ctx->gb_total * 2, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(q.data(), ctx->gb_q.p, ctx->gb_total * 4, hipMemcpyDeviceToHost));
+  }
+  if (ctx->gb_raw_bytes) HIP_TRY(hipMemcpy(raw.data(), ctx->gb_raw.p, ctx->gb_raw_bytes, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(phi.data(), ctx->gb_phi.p, phi.size() * 8, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(cv.data(), ctx->gb_cv.p, cv.size() * 8, hipMemcpyDeviceToHost));
+  const std::vector<int32_t>& cnt = ctx->gb_hcount;
+  const int64_t npb = (nb + kBatchBlocks - 1) / kBatchBlocks;
+  const int64_t nbatch = npb + p.nvars;
+  std::vector<std::vector<uint8_t>> zs(nbatch);
+  std::vector<uint64_t> usz(nbatch);
+  std::atomic<bool> zfail{false};
+  parallel_for(nbatch, [&](int64_t bi) {
+    std::vector<uint8_t> rb;
+    if (bi < npb) {
+      const int64_t b0 = bi * kBatchBlocks, b1 = std::min(nb, b0 + kBatchBlocks);
+      std::vector<uint16_t> c16(b1 - b0);
+      std::vector<int16_t> k16(b1 - b0);
+      for (int64_t b = b0; b < b1; ++b) {
+        c16[b - b0] = uint16_t(cnt[b]);
+        k16[b - b0] = int16_t(kexp[b]);
+      }
+      put_planes(rb, reinterpret_cast<const uint8_t*>(c16.data()), b1 - b0, 2);
+      put_planes(rb, reinterpret_cast<const uint8_t*>(k16.data()), b1 - b0, 2);
+      int64_t i0 = b0 < nb ? ioff[b0] : 0, i1 = i0;
+      for (int64_t b = b0; b < b1; ++b) i1 += cnt[b] == kGbRaw ? 0 : cnt[b];
+      put_planes(rb, reinterpret_cast<const uint8_t*>(idx.data() + i0), i1 - i0, 2);
+      std::vector<uint32_t> z(i1 - i0);
+      for (int64_t i = i0; i < i1; ++i) z[i - i0] = (uint32_t(q[i]) << 1) ^ uint32_t(q[i] >> 31);
+      put_planes(rb, reinterpret_cast<const uint8_t*>(z.data()), i1 - i0, 4);
+      for (int64_t b = b0; b < b1; ++b)
+        if (cnt[b] == kGbRaw) {
+          const int64_t n = int64_t(pl.blocks[b].m) * es;
+          rb.insert(rb.end(), raw.begin() + roff[b], raw.begin() + roff[b] + n);
+        }
+    } else {
+      const int v = int(bi - npb);
+      uint32_t hdr[2] = {uint32_t(p.basis), uint32_t(M)};
+      const uint8_t* hp = reinterpret_cast<const uint8_t*>(hdr);
+      rb.insert(rb.end(), hp, hp + 8);
+      const uint8_t* cp = reinterpret_cast<const uint8_t*>(&cv[v]);
+      rb.insert(rb.end(), cp, cp + 8);
+      std::vector<uint32_t> z(size_t(M) * M);
+      for (size_t i = 0; i < z.size(); ++i) {
+        const int32_t qi = int32_t(std::nearbyint(phi[size_t(v) * M * M + i] * 16777216.0));
+        z[i] = (uint32_t(qi) << 1) ^ uint32_t(qi >> 31);
+      }
+      put_planes(rb, reinterpret_cast<const uint8_t*>(z.data()), int64_t(z.size()), 4);
+    }
+    uLongf zn = compressBound(uLong(rb.size()));
+    std::vector<uint8_t> zb(zn);
+    if (compress2(zb.data(), &zn, rb.data(), uLong(rb.size()), kZlibLevel) != Z_OK) {
+      zfail = true;
+      return;
+    }
+    zb.resize(zn);
+    zs[bi] = std::move(zb);
+    usz[bi] = rb.size();
+  });
+  if (zfail) return fail(DLS_ENOMEM, "zlib compress2 failed");
+  std::vector<StreamHeader::Batch> table(nbatch);
+  uint64_t off = 0;
+  for (int64_t i = 0; i < nbatch; ++i) {
+    table[i] = StreamHeader::Batch{off, zs[i].size(), usz[i]};
+    off += zs[i].size();
+  }
+  std::vector<uint8_t> hdr = write_header(p, nb, pl.bits, table, uint32_t(p.basis));
+  const size_t total = hdr.size() + off;
+  uint8_t* buf = static_cast<uint8_t*>(std::malloc(total ? total : 1));
+  if (buf == nullptr) return fail(DLS_ENOMEM, "output allocation");
+  std::memcpy(buf, hdr.data(), hdr.size());
+  size_t pos = hdr.size();
+  for (auto& z : zs) {
+    std::memcpy(buf + pos, z.data(), z.size());
+    pos += z.size();
+  }
+  *out = buf;
+  *out_bytes = total;
+  return DLS_OK;
+}
+
+// The patch-snapshot arrays of a global-basis stream, checked and moved into
+// the device layout: counts, exponents, offsets of the kept coefficients and
+// of the raw values, packed indices, coefficients, raw bytes, and the bases.
+struct GlobalPayload {
+  std::vector<int32_t> cnt, kexp;
+  std::vector<int64_t> ioff, roff;
+  std::vector<uint16_t> idx;
+  std::vector<int32_t> q;
+  std::vector<uint8_t> raw;
+  std::vector<double> phi;
+};
+
+std::string global_unpack(const uint8_t* in, const StreamHeader& h, const Plan& pl, GlobalPayload& g) {
+  const Problem& p = h.prob;
+  const int64_t nb = h.nblocks;
+  const int M = p.px * p.py * p.pz, es = p.esize();
+  const int64_t npb = (nb + kBatchBlocks - 1) / kBatchBlocks;
+  std::vector<std::vector<uint8_t>> raws(h.batches.size());
+  std::vector<std::string> errs(h.batches.size());
+  parallel_for(int64_t(h.batches.size()), [&](int64_t bi) {
+    const auto& e = h.batches[bi];
+    if (e.usize > (uint64_t(1) << 40)) {
+      errs[bi] = "batch too large";
+      return;
+    }
+    raws[bi].resize(e.usize);
+    uLongf n = uLongf(e.usize);
+    if (uncompress(raws[bi].data(), &n, in + h.header_bytes + e.off, uLong(e.csize)) != Z_OK || n != e.usize)
+      errs[bi] = "zlib stream of a batch is corrupt";
+  });
+  for (auto& e : errs)
+    if (!e.empty()) return e;
+  g.cnt.resize(nb);
+  g.kexp.resize(nb);
+  g.ioff.resize(nb);
+  g.roff.resize(nb);
+  int64_t ti = 0, tr = 0;
+  // first pass: counts and sizes
+  for (int64_t bi = 0; bi < npb; ++bi) {
+    const auto& r = raws[bi];
+    const int64_t b0 = bi * kBatchBlocks, b1 = std::min(nb, b0 + kBatchBlocks), n = b1 - b0;
+    if (int64_t(r.size()) < 4 * n) return "batch payload truncated";
+    int64_t kept = 0, rawb = 0;
+    for (int64_t j = 0; j < n; ++j) {
+      const int c = int(r[j]) | (int(r[n + j]) << 8);
+      const int16_t k = int16_t(uint16_t(r[2 * n + j]) | (uint16_t(r[3 * n + j]) << 8));
+      if (c != kGbRaw && c > M) return "coefficient count out of range";
+      g.cnt[b0 + j] = c;
+      g.kexp[b0 + j] = k;
+      g.ioff[b0 + j] = ti + kept;
+      g.roff[b0 + j] = tr + rawb;
+      if (c == kGbRaw) rawb += int64_t(pl.blocks[b0 + j].m) * es;
+      else kept += c;
+    }
+    if (int64_t(r.size()) != 4 * n + 6 * kept + rawb) return "batch size mismatch";
+    ti += kept;
+    tr += rawb;
+  }
+  g.idx.resize(std::max<int64_t>(ti, 1));
+  g.q.resize(std::max<int64_t>(ti, 1));
+  g.raw.resize(std::max<int64_t>(tr, 1));
+  for (int64_t bi = 0; bi < npb; ++bi) {
+    const auto& r = raws[bi];
+    const int64_t b0 = bi * kBatchBlocks, b1 = std::min(nb, b0 + kBatchBlocks), n = b1 - b0;
+    const int64_t i0 = g.ioff[b0];
+    int64_t kept = 0;
+    for (int64_t b = b0; b < b1; ++b) kept += g.cnt[b] == kGbRaw ? 0 : g.cnt[b];
+    const uint8_t* ip = r.data() + 4 * n;
+    const uint8_t* qp = ip + 2 * kept;
+    for (int64_t i = 0; i < kept; ++i) {
+      g.idx[i0 + i] = uint16_t(ip[i] | (ip[kept + i] << 8));
+      const uint32_t z = uint32_t(qp[i]) | (uint32_t(qp[kept + i]) << 8) | (uint32_t(qp[2 * kept + i]) << 16) |
+                         (uint32_t(qp[3 * kept + i]) << 24);
+      g.q[i0 + i] = int32_t(z >> 1) ^ -int32_t(z & 1);
+    }
+    for (int64_t b = b0; b < b1; ++b) {
+      if (g.cnt[b] == kGbRaw) continue;
+      for (int j = 0; j < g.cnt[b]; ++j) {
+        const int s = g.idx[g.ioff[b] + j];
+        if (s >= M || (j > 0 && s <= g.idx[g.ioff[b] + j - 1])) return "basis indices out of order";
+      }
+    }
+    const uint8_t* rp = qp + 4 * kept;
+    const int64_t rawb = int64_t(r.size()) - (rp - r.data());
+    if (rawb > 0) std::memcpy(g.raw.data() + g.roff[b0], rp, size_t(rawb));
+  }
+  g.phi.resize(size_t(p.nvars) * M * M);
+  for (int v = 0; v < p.nvars; ++v) {
+    const auto& r = raws[npb + v];
+    if (int64_t(r.size()) != 16 + 4 * int64_t(M) * M) return "basis batch size";
+    uint32_t kind, mm;
+    std::memcpy(&kind, r.data(), 4);
+    std::memcpy(&mm, r.data() + 4, 4);
+    if (int(mm) != M || kind != h.extra) return "basis batch header";
+    const int64_t n = int64_t(M) * M;
+    const uint8_t* zp = r.data() + 16;
+    for (int64_t i = 0; i < n; ++i) {
+      const uint32_t z = uint32_t(zp[i]) | (uint32_t(zp[n + i]) << 8) | (uint32_t(zp[2 * n + i]) << 16) |
+                         (uint32_t(zp[3 * n + i]) << 24);
+      g.phi[size_t(v) * n + i] = double(int32_t(z >> 1) ^ -int32_t(z & 1)) / 16777216.0;
+    }
+  }
+  return "";
+}
+
+dls_status global_decompress(const uint8_t* in, const StreamHeader& h, const Plan& pl, void* d_out, hipStream_t s) {
+  const Problem& p = h.prob;
+  GlobalPayload g;
+  std::string err = global_unpack(in, h, pl, g);
+  if (!err.empty()) return fail(DLS_ECORRUPT, err);
+  const int64_t nb = h.nblocks;
+  const int M = p.px * p.py * p.pz;
+  DevBuf desc, cnt, kexp, ioff, roff, idx, q, raw, phi;
+  HIP_TRY(desc.ensure(size_t(nb) * sizeof(BlockDesc)));
+  HIP_TRY(cnt.ensure(size_t(nb) * 4));
+  HIP_TRY(kexp.ensure(size_t(nb) * 4));
+  HIP_TRY(ioff.ensure(size_t(nb) * 8));
+  HIP_TRY(roff.ensure(size_t(nb) * 8));
+  HIP_TRY(idx.ensure(g.idx.size() * 2));
+  HIP_TRY(q.ensure(g.q.size() * 4));
+  HIP_TRY(raw.ensure(g.raw.size()));
+  HIP_TRY(phi.ensure(g.phi.size() * 8));
+  HIP_TRY(hipMemcpy(desc.p, pl.blocks.data(), size_t(nb) * sizeof(BlockDesc), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(cnt.p, g.cnt.data(), size_t(nb) * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(kexp.p, g.kexp.data(), size_t(nb) * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(ioff.p, g.ioff.data(), size_t(nb) * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(roff.p, g.roff.data(), size_t(nb) * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(idx.p, g.idx.data(), g.idx.size() * 2, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(q.p, g.q.data(), g.q.size() * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(raw.p, g.raw.data(), g.raw.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(phi.p, g.phi.data(), g.phi.size() * 8, hipMemcpyHostToDevice));
+  const Dims dims{p.nx, p.ny, p.nz, p.nt};
+  HIP_TRY(launch_gb_decode(p.dtype, d_out, dims, desc.as<BlockDesc>(), nb, phi.as<double>(), p.px, p.py, M,
+                           cnt.as<int32_t>(), kexp.as<int32_t>(), ioff.as<int64_t>(), roff.as<int64_t>(),
+                           idx.as<uint16_t>(), q.as<int32_t>(), raw.as<uint8_t>(), s));
+  HIP_TRY(hipStreamSynchronize(s));
   return DLS_OK;
 }
 }  // namespace
@@ -1008,6 +1409,11 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
   const int64_t nb = int64_t(pl.blocks.size());
   const int64_t ni = int64_t(pl.items.size());
   const int wp = p.wpad();
+  if (p.flags & DLS_GLOBAL) {
+    const Dims gdims{p.nx, p.ny, p.nz, p.nt};
+    if (dls_status st = global_encode(ctx, d_field, p, gdims, s)) return st;
+    return finish_encode(ctx);
+  }
 
   HIP_TRY(ctx->gram.ensure(size_t(ni) * wp * wp * sizeof(double)));
   HIP_TRY(ctx->rank.ensure(size_t(nb)));
@@ -1327,6 +1733,13 @@ dls_status dls_decode(dls_ctx* ctx, void* d_out, size_t out_bytes, void* stream)
                              ctx->qa.as<uint8_t>(), s));
     return DLS_OK;
   }
+  if (p.flags & DLS_GLOBAL) {
+    HIP_TRY(launch_gb_decode(p.dtype, d_out, dims, ctx->desc.as<BlockDesc>(), int64_t(ctx->plan.blocks.size()),
+                             ctx->gb_phi.as<double>(), p.px, p.py, ctx->gb_M, ctx->gb_count.as<int32_t>(),
+                             ctx->gb_kexp.as<int32_t>(), ctx->gb_idx_off.as<int64_t>(), ctx->gb_raw_off.as<int64_t>(),
+                             ctx->gb_idx.as<uint16_t>(), ctx->gb_q.as<int32_t>(), ctx->gb_raw.as<uint8_t>(), s));
+    return DLS_OK;
+  }
   // one launch per rank class, over the encode's class lists (their counts
   // are in the host copy of the counter block the encode read back last)
   const int64_t ni = int64_t(ctx->plan.items.size());
@@ -1460,6 +1873,7 @@ dls_status dls_finalize(dls_ctx* ctx, uint8_t** out, size_t* out_bytes) {
   *out_bytes = 0;
   HIP_TRY(hipSetDevice(ctx->device));
   if (ctx->prob.flags & DLS_L2) return l2_finalize(ctx, out, out_bytes);
+  if (ctx->prob.flags & DLS_GLOBAL) return global_finalize(ctx, out, out_bytes);
   const Problem& p = ctx->prob;
   const Plan& pl = ctx->plan;
   const int64_t nb = int64_t(pl.blocks.size());
@@ -1573,7 +1987,9 @@ dls_status dls_compress(const void* d_field, const dls_params* p, void* stream, 
   HIP_TRY(hipGetDevice(&dev));
   dls_ctx* ctx = nullptr;
   if (dls_status s = dls_ctx_create(dev, &ctx)) return s;
-  dls_status s = dls_encode(ctx, d_field, p, stream, 0);
+  dls_status s = DLS_OK;
+  if (p->model != nullptr) s = dls_ctx_set_model(ctx, p->model, p->warm_iters > 0 ? p->warm_iters : 2, p->rank_margin);
+  if (s == DLS_OK) s = dls_encode(ctx, d_field, p, stream, 0);
   if (s == DLS_OK) s = dls_finalize(ctx, out, out_bytes);
   dls_ctx_destroy(ctx);
   return s;
@@ -1597,6 +2013,7 @@ dls_status dls_query(const uint8_t* in, size_t in_bytes, dls_params* p_out, doub
   p_out->precision = 0;
   p_out->flags = p.flags;
   p_out->abs_eps = nullptr;
+  p_out->basis = (p.flags & DLS_GLOBAL) ? int32_t(h.extra) : 0;
   if (eps_out != nullptr)
     for (int v = 0; v < std::min<int>(p.nvars, std::max(0, eps_cap)); ++v) eps_out[v] = p.eps[v];
   if (nblocks != nullptr) *nblocks = h.nblocks;
@@ -1691,6 +2108,18 @@ dls_status dls_stats(const uint8_t* in, size_t in_bytes, dls_stream_stats* s) {
   s->nblocks = h.nblocks;
   s->nbatches = int64_t(h.batches.size());
   s->stream_bytes = int64_t(in_bytes);
+  if (h.prob.flags & DLS_GLOBAL) {
+    // coefficient counts per patch-snapshot: rank_hist[min(n, 32)]
+    GlobalPayload g;
+    err = global_unpack(in, h, pl, g);
+    if (!err.empty()) return fail(DLS_ECORRUPT, err);
+    for (int32_t c : g.cnt) {
+      if (c == kGbRaw) s->nraw++;
+      else s->rank_hist[std::min(c, 32)]++;
+    }
+    for (const auto& e : h.batches) s->payload_bytes += int64_t(e.usize);
+    return DLS_OK;
+  }
   if (h.prob.flags & DLS_L2) {
     for (int64_t bi = 0; bi < s->nbatches; ++bi) {
       const auto& e = h.batches[bi];
@@ -1739,6 +2168,7 @@ dls_status dls_decompress(const uint8_t* in, size_t in_bytes, void* d_out, void*
   err = plan_from_header(h, pl, 1024);
   if (!err.empty()) return fail(DLS_ECORRUPT, err);
   if (p.flags & DLS_L2) return l2_decompress(in, h, pl, d_out, static_cast<hipStream_t>(stream));
+  if (p.flags & DLS_GLOBAL) return global_decompress(in, h, pl, d_out, static_cast<hipStream_t>(stream));
   const int64_t nb = h.nblocks, nbatch = int64_t(h.batches.size());
   std::vector<BatchView> views(nbatch);
   std::vector<std::string> errs(nbatch);

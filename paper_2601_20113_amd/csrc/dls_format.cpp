@@ -154,7 +154,7 @@ void build_blocks(const Problem& p, Plan& plan, int slice_points) {
 
 std::vector<uint8_t> write_header(const Problem& p, int64_t nblocks,
                                   const std::vector<std::vector<uint8_t>>& bits,
-                                  const std::vector<StreamHeader::Batch>& batches) {
+                                  const std::vector<StreamHeader::Batch>& batches, uint32_t extra) {
   std::vector<uint8_t> planb;
   for (int v = 0; v < p.nvars; ++v) {
     const std::vector<uint8_t> empty;
@@ -171,7 +171,7 @@ std::vector<uint8_t> write_header(const Problem& p, int64_t nblocks,
   out.insert(out.end(), {'D', 'L', 'S', '1'});
   put<uint32_t>(out, kVersion);
   put<uint32_t>(out, hdr);
-  put<uint32_t>(out, (p.flags & 1) | ((p.flags & DLS_L2) ? 2u : 0u));
+  put<uint32_t>(out, (p.flags & 1) | ((p.flags & DLS_L2) ? 2u : 0u) | ((p.flags & DLS_GLOBAL) ? 4u : 0u));
   put<int32_t>(out, p.ndim());
   put<int32_t>(out, p.nvars);
   put<int32_t>(out, p.dtype);
@@ -188,7 +188,7 @@ std::vector<uint8_t> write_header(const Problem& p, int64_t nblocks,
   put<int32_t>(out, kBatchBlocks);
   put<uint64_t>(out, uint64_t(nblocks));
   put<uint32_t>(out, uint32_t(batches.size()));
-  put<uint32_t>(out, 0);
+  put<uint32_t>(out, extra);
   for (int v = 0; v < p.nvars; ++v) put<double>(out, p.eps[v]);
   out.insert(out.end(), planb.begin(), planb.end());
   for (const auto& b : batches) {
@@ -222,7 +222,9 @@ std::string parse_header(const uint8_t* buf, size_t n, StreamHeader& h) {
   int bb = get<int32_t>(buf + 84);
   h.nblocks = int64_t(get<uint64_t>(buf + 88));
   uint32_t nbatches = get<uint32_t>(buf + 96);
-  p.flags = (flags & 1) | ((flags & 2) ? uint32_t(DLS_L2) : 0u);
+  p.flags = (flags & 1) | ((flags & 2) ? uint32_t(DLS_L2) : 0u) | ((flags & 4) ? uint32_t(DLS_GLOBAL) : 0u);
+  h.extra = get<uint32_t>(buf + 100);
+  if (flags & ~7u) return "unknown stream flags";
   p.precision = 0;
   if (hdr > n || hdr < kFixed) return "bad header length";
   if (p.nvars < 1 || p.nvars > 65536 || (p.dtype != 0 && p.dtype != 1) || bb != kBatchBlocks)
@@ -256,7 +258,14 @@ std::string parse_header(const uint8_t* buf, size_t n, StreamHeader& h) {
     pos += nbyte;
   }
   if (pos + 24 * size_t(nbatches) != hdr) return "header length mismatch";
-  if (int64_t(nbatches) != (h.nblocks + kBatchBlocks - 1) / kBatchBlocks) return "batch count mismatch";
+  // the global-basis mode appends one basis batch per variable
+  const int64_t want = (h.nblocks + kBatchBlocks - 1) / kBatchBlocks + ((p.flags & DLS_GLOBAL) ? p.nvars : 0);
+  if (int64_t(nbatches) != want) return "batch count mismatch";
+  if (p.flags & DLS_GLOBAL) {
+    if ((p.flags & (DLS_L2 | 1u)) || p.window != 1 || int64_t(p.px) * p.py * p.pz > 1024 || p.px > p.nx ||
+        p.py > p.ny || p.pz > p.nz || h.extra > 2)
+      return "bad global-basis header";
+  }
   h.batches.resize(nbatches);
   for (uint32_t i = 0; i < nbatches; ++i) {
     h.batches[i].off = get<uint64_t>(buf + pos);

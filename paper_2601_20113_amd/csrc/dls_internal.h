@@ -68,6 +68,8 @@ struct Problem {               // validated copy of dls_params
   int px, py, pz, pmin, window, r_max;
   int precision;
   uint32_t flags;
+  int basis = 0;               // global-basis mode: dls_basis_kind
+  uint64_t seed = 0;           // global-basis mode: learning-patch draws
   std::vector<double> eps;
   int ndim() const { return nz > 1 ? 3 : 2; }
   int esize() const { return dtype == 0 ? 4 : 8; }
@@ -102,12 +104,13 @@ struct StreamHeader {
   struct Batch { uint64_t off, csize, usize; };
   std::vector<Batch> batches;
   size_t header_bytes = 0;
+  uint32_t extra = 0;   // global-basis mode: the basis kind
 };
 
 // Returns "" on success, else a message (stream is corrupt).
 std::string parse_header(const uint8_t* buf, size_t n, StreamHeader& h);
 std::vector<uint8_t> write_header(const Problem& p, int64_t nblocks,
                                   const std::vector<std::vector<uint8_t>>& bits,
-                                  const std::vector<StreamHeader::Batch>& batches);
+                                  const std::vector<StreamHeader::Batch>& batches, uint32_t extra = 0);
 
 }  // namespace dls

@@ -199,6 +199,38 @@ hipError_t launch_scan(const int64_t* in, int64_t n, int64_t* out, int64_t* tmp,
 // every slice; payload regions as in the absolute mode (qV, qA planes; a
 // raw block's values in its qA region).
 constexpr int kL2Raw = 255;
+// Global-basis mode (dls_global.hip).  Per variable an M x M basis Phi[i][s]
+// (FP64 values on the 2^-24 grid); per patch-snapshot a coefficient count
+// (0xFFFF = raw), a step exponent and a slot of 8 M bytes (kept indices u16
+// at 0, coefficients int32 at 4 M, or the raw values) compacted afterwards.
+constexpr int kGbParts = 256;
+constexpr int kGbRaw = 0xFFFF;
+constexpr int kGbMaxM = 1024;
+hipError_t launch_gb_budget(int dtype, const void* F, int64_t per_var, int nvars, const double* target,
+                            double* part, double* cv, hipStream_t s);
+hipError_t launch_gb_samples(int dtype, const void* F, const Dims& dims, int var, int px, int py, int pz, int kind,
+                             uint64_t s0, int64_t S, double* Q, hipStream_t s);
+hipError_t launch_gb_gram(const double* Q, int64_t S, int M, int Mp, double* G, hipStream_t s);
+hipError_t launch_gb_eye(double* V, int Mp, hipStream_t s);
+hipError_t launch_gb_jacobi_round(const double* Ain, double* Aout, double* V, int Mp, int round, hipStream_t s);
+constexpr int kGbMaxSweeps = 40;
+hipError_t launch_gb_offnorm(const double* A, double* Acopy, int Mp, double* part, double* out, hipStream_t s);
+hipError_t launch_gb_finish(const double* A, const double* V, int M, int Mp, double* Phi, hipStream_t s);
+hipError_t launch_gb_cosine(int px, int py, int pz, double* Phi, hipStream_t s);
+hipError_t launch_gb_project(int dtype, const void* F, const Dims& dims, const BlockDesc* desc, int64_t nb0,
+                             int64_t nb1, const double* phi, int px, int py, int M, double* alpha, hipStream_t s);
+hipError_t launch_gb_select(int dtype, const void* F, const Dims& dims, const BlockDesc* desc, int64_t nblocks,
+                            const double* phi, const double* cv, const double* alpha, int px, int py, int M,
+                            int32_t* count, int32_t* kexp, uint8_t* slot, int32_t* n0, hipStream_t s);
+hipError_t launch_gb_sizes(const BlockDesc* desc, int64_t nblocks, const int32_t* count, int esize, int64_t* nidx,
+                           int64_t* nraw, hipStream_t s);
+hipError_t launch_gb_compact(const BlockDesc* desc, int64_t nblocks, int M, const int32_t* count, const uint8_t* slot,
+                             const int64_t* idx_off, const int64_t* raw_off, int esize, uint16_t* idx_out,
+                             int32_t* q_out, uint8_t* raw_out, hipStream_t s);
+hipError_t launch_gb_decode(int dtype, void* F, const Dims& dims, const BlockDesc* desc, int64_t nblocks,
+                            const double* phi, int px, int py, int M, const int32_t* count, const int32_t* kexp,
+                            const int64_t* idx_off, const int64_t* raw_off, const uint16_t* idx, const int32_t* q,
+                            const uint8_t* raw, hipStream_t s);
 hipError_t launch_l2_gram(int wp, int dtype, const void* F, const Dims& dims, const BlockDesc* desc,
                           const Item* items, int64_t nitems, double* gpart, double* fsq, hipStream_t s);
 hipError_t launch_l2_budget(const Item* items, const BlockDesc* desc, int64_t nitems, const double* fsq,

@@ -34,9 +34,22 @@ def test_library_exports_every_declared_symbol(L):
     assert sorted(L.EXPORTS) == names
 
 
-def test_param_struct_size_matches_header(L):
-    # the ctypes mirror must match the C layout (8-byte aligned fields)
-    assert ctypes.sizeof(L._Params) == 88
+def test_param_struct_layout_matches_header(L, tmp_path):
+    """The ctypes mirror of dls_params has the C compiler's size and field
+    offsets (compiled from include/dls.h with gcc)."""
+    import subprocess
+    names = [f[0] for f in L._Params._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"dls.h\"\nint main(void) {\n"
+                   "  printf(\"%zu\\n\", sizeof(dls_params));\n"
+                   + "".join("  printf(\"%%zu\\n\", offsetof(dls_params, %s));\n" % n for n in names)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.check_call(["gcc", "-std=c11", "-I", inc, str(src), "-o", str(exe)])
+    vals = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert vals[0] == ctypes.sizeof(L._Params)
+    assert vals[1:] == [getattr(L._Params, n).offset for n in names]
 
 
 def _oracle_stream(dtype=np.float64, adaptive=False):
@@ -145,3 +158,32 @@ def test_l2_with_learned_rejected_before_device_work(L):
     st = lib.dls_compress(ctypes.c_void_p(16), ctypes.byref(cp), None, ctypes.byref(ctypes.c_void_p()),
                           ctypes.byref(ctypes.c_size_t()))
     assert st == L.DLS_EINVAL and b"DLS_L2" in lib.dls_last_error()
+
+
+@pytest.mark.parametrize("kind", ["svd", "cosine", "random"])
+def test_query_and_stats_of_oracle_global_stream(L, kind):
+    """The library's host parser reads a global-basis stream the oracle
+    wrote: the problem statement, the basis kind, the patch count, the raw
+    patches and the coefficient-count histogram."""
+    from oracle import globalbasis as gb
+    f = synth.blobs2d(nx=24, ny=16, nt=3, seed=5, nblobs=3)
+    f[0, 1, 0, 3, 3] = np.nan
+    p = odls.Params(nx=24, ny=16, nz=1, nt=3, nvars=1, dtype="f64", px=8, py=8, pz=1, window=1, eps=[1e-3])
+    enc = gb.encode(f, p, gb.KINDS[kind], seed=3)
+    buf = container.pack_global(enc)
+    q, nb = L.query(buf)
+    assert nb == len(enc.blocks) == 18
+    assert q.global_basis and q.basis == kind and q.window == 1 and not q.l2
+    st = L.stats(buf)
+    ns = [c.n for c in enc.codes]
+    assert st["nraw"] == sum(n == gb.RAW for n in ns) == 1
+    hist = [0] * 33
+    for n in ns:
+        if n != gb.RAW:
+            hist[min(n, 32)] += 1
+    assert st["rank_hist"] == hist
+    # a corrupted basis kind is refused
+    bad = bytearray(buf)
+    bad[100] = 7
+    with pytest.raises(L.DlsError):
+        L.stats(bytes(bad))

@@ -478,6 +478,89 @@ def run_l2(field, cfg, targets, steps, warmup, no_ratio, log):
             "curve": curve}
 
 
+def global_params(nx, ny, nt, px, target, kind, seed=1):
+    import paper_2601_20113_amd as dls
+    return dls.Params(nx=nx, ny=ny, nz=1, nt=nt, nvars=1, dtype="f32", px=px, py=px, pz=1, window=1,
+                      eps=[target], global_basis=True, basis=kind, seed=seed)
+
+
+def run_global_one(field, p, steps, warmup, no_ratio):
+    """Encode time (wall, between synchronizations), stage times, kept
+    coefficients, NRMSE and compression ratio of one global-basis setting."""
+    import torch
+    import paper_2601_20113_amd as dls
+    enc = dls.Encoder()
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        enc.encode(field, p, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        enc.encode(field, p, stream=stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    inf = enc.info()
+    out = torch.empty_like(field)
+    enc.decode(out, stream=stream)
+    torch.cuda.synchronize()
+    nr = nrmse(field, out)[0]
+    del out
+    in_bytes = field.numel() * field.element_size()
+    e = {"ms": round(ms, 3), "value": round(in_bytes / (ms * 1e-3) / 1e9, 2), "unit": "GB/s",
+         "nrmse": float("%.4g" % nr), "within_target": bool(nr <= p.eps[0]),
+         "learn_ms": round(inf.jacobi_ms, 3), "jacobi_sweeps": int(inf.jacobi_sweeps),
+         "stage_ms": {"budget+basis": round(inf.stage_ms[1], 3), "coefficients": round(inf.stage_ms[2], 3),
+                      "selection": round(inf.stage_ms[3], 3), "pack": round(inf.stage_ms[4], 3)},
+         "raw_patches": int(inf.nraw)}
+    if not no_ratio:
+        buf = enc.finalize()
+        e["compression_ratio"] = round(in_bytes / len(buf), 3)
+        st = dls.stats(buf)
+        live = sum(st["rank_hist"])
+        e["mean_kept"] = round(sum(min(k, 32) * c for k, c in enumerate(st["rank_hist"])) / max(live, 1), 2)
+    enc.close()
+    return e
+
+
+def run_global(steps, warmup, no_ratio, log):
+    """The paper's global-basis method (Alg. 1) on 2D FP32 blob fields:
+    throughput on the 4096 x 2048 x 100 field with 8 x 8 patches and the
+    learned (SVD) basis at NRMSE 1e-3, and the basis study of Sec. 4 (SVD,
+    cosine and random bases; patch edges 4, 8, 16; NRMSE 1e-2 and 1e-3) on a
+    1024 x 1024 x 16 field of the same generator."""
+    import torch
+    from synth import gpu as sg
+    res = {"what": "global-basis mode (DLS_GLOBAL): one basis per variable learned from 4M random patches of "
+                   "snapshot 0, every patch of every snapshot projected on it, coefficients kept in decreasing "
+                   "magnitude until the local L2 share holds, power-of-two grooming, exact error check"}
+    f = torch.empty((1, 100, 1, 2048, 4096), dtype=torch.float32, device="cuda")
+    sg.blobs_into(f[0], nblobs=8192, seed=31)
+    p = global_params(4096, 2048, 100, 8, 1e-3, "svd")
+    e = run_global_one(f, p, steps, warmup, no_ratio)
+    log("global 4096x2048x100 svd 8x8 1e-3: %s" % e)
+    res["throughput"] = dict(e, workload="2D FP32 4096x2048 x 100 steps, 8192 moving Gaussian blobs, 8x8 patches, "
+                                         "SVD basis, NRMSE 1e-3")
+    del f
+    torch.cuda.empty_cache()
+    g = torch.empty((1, 16, 1, 1024, 1024), dtype=torch.float32, device="cuda")
+    sg.blobs_into(g[0], nblobs=1024, seed=41)
+    study = []
+    for px in (4, 8, 16):
+        for kind in ("svd", "cosine", "random"):
+            for tg in (1e-2, 1e-3):
+                e = run_global_one(g, global_params(1024, 1024, 16, px, tg, kind), 1, 1, no_ratio)
+                e.update(patch=px, basis=kind, target=tg)
+                log("basis study %s %dx%d %g: CR %s NRMSE %s kept %s" % (kind, px, px, tg,
+                                                                        e.get("compression_ratio"), e["nrmse"],
+                                                                        e.get("mean_kept")))
+                study.append(e)
+    res["basis_study"] = {"workload": "2D FP32 1024x1024 x 16 steps, 1024 moving Gaussian blobs",
+                          "rows": study}
+    del g
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -493,6 +576,8 @@ def main():
                     help="skip the drift variant (modes with a per-step phase drift) of the spectrum workloads")
     ap.add_argument("--l2-targets", default="1e-2,1e-3,1e-4",
                     help="NRMSE targets of the L2-bounded mode measured on the headline field (empty: skip)")
+    ap.add_argument("--no-global", action="store_true",
+                    help="skip the global-basis mode (its throughput and the basis study)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 4 GiB device-to-device copy twice (the reference the "
                          "HBM byte counters are scaled by) and exit")
@@ -628,11 +713,16 @@ def main():
     targets = [float(x) for x in args.l2_targets.split(",") if x]
     if targets:
         out["l2"] = run_l2(field, cfg, targets, min(args.steps, 3), 1, args.no_ratio, log)
+    if not args.no_global:
+        del field
+        torch.cuda.empty_cache()
+        out["global"] = run_global(min(args.steps, 3), 1, args.no_ratio, log)
+        field = None
 
     # the drift variant: every mode's phase advances per step, so windows
     # have ranks above 1 (the literal generator is rank 1 in time)
     if cfg["kind"] == "spectrum" and not args.no_drift:
-        del field
+        field = None
         torch.cuda.empty_cache()
         dcfg = dict(cfg, drift=True)
         log("generating the drift variant of %s" % args.config)

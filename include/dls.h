@@ -312,10 +312,16 @@ dls_status dls_decode(dls_ctx* ctx, void* d_out, size_t out_bytes, void* stream)
 dls_status dls_compress(const void* d_field, const dls_params* p, void* stream,
                         uint8_t** out, size_t* out_bytes);
 
-/* Read the header of a stream (host buffer in[0..in_bytes)).  Writes the
- * problem statement to *p_out (abs_eps is set to NULL), the bounds to
- * eps_out[0..min(nvars, eps_cap)) when eps_out is not NULL, and the block
- * count to *nblocks when not NULL.  DLS_ECORRUPT on a bad header. */
+/* Read the header of a stream (host buffer in[0..in_bytes)): the
+ * addressable header of Sec. 2.7.2 (problem statement, per-variable bounds,
+ * adaptive split bits, one (offset, size) entry per batch of 1000 blocks).
+ * Writes the problem statement to *p_out (abs_eps is set to NULL; flags
+ * carry DLS_ADAPTIVE / DLS_L2 / DLS_GLOBAL, basis the global basis kind),
+ * the bounds (or NRMSE targets) to eps_out[0..min(nvars, eps_cap)) when
+ * eps_out is not NULL, and the block count (patch-snapshots in the global
+ * mode) to *nblocks when not NULL.  The bounds and the count are separate
+ * outputs because dls_params holds a pointer to caller-owned bounds.  No
+ * device work.  DLS_ECORRUPT on a bad header, DLS_EINVAL on a NULL p_out. */
 dls_status dls_query(const uint8_t* in, size_t in_bytes, dls_params* p_out,
                      double* eps_out, int32_t eps_cap, int64_t* nblocks);
 
@@ -326,10 +332,16 @@ dls_status dls_query(const uint8_t* in, size_t in_bytes, dls_params* p_out,
 dls_status dls_decompress(const uint8_t* in, size_t in_bytes, void* d_field_out,
                           void* stream);
 
-/* Summary of a stream, computed on the host (no device work). */
+/* Summary of a stream, computed on the host (no device work): every batch
+ * of Sec. 2.7.2 is inflated and its per-block sections read.  Counts that
+ * only the encoder knows (warm starts accepted, Jacobi fallbacks and sweeps)
+ * are not in the stream; dls_encode_info reports them.  DLS_ECORRUPT on a
+ * truncated or inconsistent stream. */
 typedef struct dls_stream_stats {
   int64_t nblocks, nbatches, nraw, nescapes;
-  int64_t rank_hist[33];     /* rank_hist[r] = blocks with rank r           */
+  int64_t rank_hist[33];     /* rank_hist[r] = blocks with rank r (global
+                                mode: patches keeping r coefficients, 32 for
+                                32 or more)                                 */
   int64_t payload_bytes;     /* uncompressed payload                        */
   int64_t stream_bytes;      /* whole stream                                */
 } dls_stream_stats;

@@ -616,21 +616,32 @@ dls_status global_encode(dls_ctx* ctx, const void* d_field, const Problem& p, co
   HIP_TRY(hipEventRecord(ctx->evj[1], s));
   ctx->jacobi_timed = true;
   HIP_TRY(hipEventRecord(ctx->evs[0], s));
-  // coefficients, one launch per variable (one basis per launch)
-  HIP_TRY(ctx->gb_alpha.ensure(size_t(nb) * M * 8));
-  for (int v = 0; v < p.nvars; ++v)
-    HIP_TRY(launch_gb_project(p.dtype, d_field, dims, ctx->desc.as<BlockDesc>(), v * nbv, (v + 1) * nbv,
-                              ctx->gb_phi.as<double>() + size_t(v) * M * M, p.px, p.py, M,
-                              ctx->gb_alpha.as<double>(), s));
-  HIP_TRY(hipEventRecord(ctx->evs[1], s));
   HIP_TRY(ctx->gb_count.ensure(size_t(nb) * 4));
   HIP_TRY(ctx->gb_kexp.ensure(size_t(nb) * 4));
   HIP_TRY(ctx->gb_n0.ensure(size_t(nb) * 4));
   HIP_TRY(ctx->gb_slot.ensure(size_t(nb) * 8 * M));
-  HIP_TRY(launch_gb_select(p.dtype, d_field, dims, ctx->desc.as<BlockDesc>(), nb, ctx->gb_phi.as<double>(),
-                           ctx->gb_cv.as<double>(), ctx->gb_alpha.as<double>(), p.px, p.py, M,
-                           ctx->gb_count.as<int32_t>(), ctx->gb_kexp.as<int32_t>(), ctx->gb_slot.as<uint8_t>(),
-                           ctx->gb_n0.as<int32_t>(), s));
+  if (M <= 64) {
+    // one wave per patch-snapshot forms the coefficients and selects them
+    HIP_TRY(hipEventRecord(ctx->evs[1], s));
+    for (int v = 0; v < p.nvars; ++v)
+      HIP_TRY(launch_gb_patch64(p.dtype, d_field, dims, ctx->desc.as<BlockDesc>(), v * nbv, (v + 1) * nbv,
+                                ctx->gb_phi.as<double>() + size_t(v) * M * M, ctx->gb_cv.as<double>(), p.px, p.py, M,
+                                ctx->gb_count.as<int32_t>(), ctx->gb_kexp.as<int32_t>(), ctx->gb_slot.as<uint8_t>(),
+                                ctx->gb_n0.as<int32_t>(), s));
+  } else {
+    // coefficients on the matrix cores, one launch per variable (one basis
+    // per launch), then one workgroup per patch-snapshot selects them
+    HIP_TRY(ctx->gb_alpha.ensure(size_t(nb) * M * 8));
+    for (int v = 0; v < p.nvars; ++v)
+      HIP_TRY(launch_gb_project(p.dtype, d_field, dims, ctx->desc.as<BlockDesc>(), v * nbv, (v + 1) * nbv,
+                                ctx->gb_phi.as<double>() + size_t(v) * M * M, p.px, p.py, M,
+                                ctx->gb_alpha.as<double>(), s));
+    HIP_TRY(hipEventRecord(ctx->evs[1], s));
+    HIP_TRY(launch_gb_select(p.dtype, d_field, dims, ctx->desc.as<BlockDesc>(), nb, ctx->gb_phi.as<double>(),
+                             ctx->gb_cv.as<double>(), ctx->gb_alpha.as<double>(), p.px, p.py, M,
+                             ctx->gb_count.as<int32_t>(), ctx->gb_kexp.as<int32_t>(), ctx->gb_slot.as<uint8_t>(),
+                             ctx->gb_n0.as<int32_t>(), s));
+  }
   HIP_TRY(hipEventRecord(ctx->evs[2], s));
   HIP_TRY(hipEventRecord(ctx->evs[3], s));
   // packed payload: offsets of the kept coefficients and of the raw values

@@ -30,12 +30,16 @@
 //   k_gb_cosine                the DCT-II tensor basis
 //   k_gb_project               alpha = U Phi on the FP64 matrix cores
 //   k_gb_select                per patch: order, count, grooming, exact check
+//   k_gb_patch64               the same with the coefficients, one wave per
+//                              patch of at most 64 points
 //   k_gb_compact               the per-patch slots into packed arrays
 //   k_gb_decode                the decoder
 //
 // Compiled with -ffp-contract=off: encoder and decoder must round the
 // reconstruction identically.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "dls_device.h"
 #include "dls_kernels.h"
@@ -500,6 +504,165 @@ __global__ __launch_bounds__(256) void k_gb_select(const T* __restrict__ F, Dims
   }
 }
 
+// Patches of at most 64 points: one wave per patch-snapshot, no barriers
+// after the basis is staged.  One launch per variable: the workgroup copies
+// the variable's Phi into LDS once (rows padded to M + 1 doubles, so both
+// the row reads of the coefficients and the column reads of the decoder
+// are conflict-free) and its four waves walk the patches [nb0, nb1) with a
+// grid stride.  Lane i holds point i (zero-padded), then coefficient
+// alpha_i = sum_k Phi[k][i] u_k (points broadcast from LDS in order, FP64
+// FMA), then the i-th entry of the magnitude order (bitonic exchange across
+// lanes); the energy rule runs as the sequential recurrence over the sorted
+// values (broadcast from LDS); the kept set is a ballot over basis
+// indices, its ascending list positions come from the lanes below; the
+// decoder's values are summed over the kept indices in ascending order.
+// Same slot layout as k_gb_select.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gb_patch64(const T* __restrict__ F, Dims dims,
+                                                    const BlockDesc* __restrict__ desc, int64_t nb0, int64_t nb1,
+                                                    const double* __restrict__ phi_g, const double* __restrict__ cv,
+                                                    int px, int py, int M, int32_t* __restrict__ count,
+                                                    int32_t* __restrict__ kexp, uint8_t* __restrict__ slot,
+                                                    int32_t* __restrict__ n0_out) {
+  // the basis values are k 2^-24 with |k| <= 2^24, exact in FP32
+  __shared__ float phi[64 * 65];
+  __shared__ double xs[4][64], sa[4][64], tq[4][64];
+  __shared__ int pos_s[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ld = M + 1;
+  for (int e = threadIdx.x; e < M * M; e += 256) phi[(e / M) * ld + e % M] = float(phi_g[e]);
+  __syncthreads();
+  for (int64_t b = nb0 + int64_t(blockIdx.x) * 4 + wave; b < nb1; b += int64_t(gridDim.x) * 4) {
+    const BlockDesc d = desc[b];
+    const double e2 = cv[d.var] * double(d.m);
+    bool in = false;
+    const double x = lane < M ? gb_point(F, dims, d, px, py, lane, in) : 0.0;
+    uint8_t* out = slot + b * int64_t(8) * M;
+    if (__any(in && !isfinite(x))) {
+      if (lane < d.m) {
+        const int ix = lane % d.px(), jy = (lane / d.px()) % d.py(), kz = lane / (d.px() * d.py());
+        reinterpret_cast<T*>(out)[lane] = F[fidx(dims, d.var, d.t0, d.z0 + kz, d.y0 + jy, d.x0 + ix)];
+      }
+      if (lane == 0) {
+        count[b] = kGbRaw;
+        kexp[b] = 0;
+        n0_out[b] = 0;
+      }
+      continue;
+    }
+    xs[wave][lane] = x;
+    wave_sync();
+    // coefficients
+    double a = 0.0;
+    if (lane < M)
+      for (int k = 0; k < M; ++k) a = fma(double(phi[k * ld + lane]), xs[wave][k], a);
+    // magnitude order: (|alpha| desc, index asc); lanes >= M sort last
+    double key = lane < M ? fabs(a) : -1.0;
+    int idx = lane;
+    double av = a;
+    for (int size = 2; size <= 64; size <<= 1) {
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        const double ko = __shfl_xor(key, stride, 64);
+        const int io = __shfl_xor(idx, stride, 64);
+        const double ao = __shfl_xor(av, stride, 64);
+        const bool lower = (lane & stride) == 0;
+        const bool self_first = key > ko || (key == ko && idx < io);
+        const bool desc_dir = (lane & size) == 0;
+        // the lower lane of a pair keeps the element that comes first in
+        // this segment's direction
+        const bool keep = (lower == desc_dir) ? self_first : !self_first;
+        if (!keep) {
+          key = ko;
+          idx = io;
+          av = ao;
+        }
+      }
+    }
+    pos_s[wave][idx] = lane;  // sorted position of basis index idx
+    sa[wave][lane] = av;
+    wave_sync();
+    // the energy rule: tail from the end, the same recurrence in every lane,
+    // eight sorted values loaded ahead of their additions
+    const double tau = kGbTailShare * e2;
+    double t = 0.0;
+    int n = 0;
+    bool found = false;
+    for (int j0 = M - 1; j0 >= 0 && !found; j0 -= 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = j0 - u >= 0 ? sa[wave][j0 - u] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (found || j0 - u < 0) continue;
+        const double tn = t + v[u] * v[u];
+        if (tn > tau) {
+          n = j0 - u + 1;
+          found = true;
+        } else {
+          t = tn;
+        }
+      }
+    }
+    if (lane == 0) n0_out[b] = n;
+    const int mypos = lane < M ? pos_s[wave][lane] : 64;
+    bool done = false;
+    for (;;) {
+      if (n > M || (!(e2 > 0.0) && n > 0)) break;
+      const bool kept = lane < M && mypos < n;
+      const unsigned long long mask = __ballot(kept);
+      double dd = 1.0;
+      int kx = 0;
+      if (n > 0) {
+        int ex;
+        frexp(kGbStepShare * sqrt(e2 / double(n)), &ex);
+        kx = ex - 1;
+        dd = ldexp(1.0, kx);
+      }
+      const double qa = rint(a / dd);
+      if (!__all(!kept || fabs(qa) < 2147483648.0)) break;
+      const int32_t qi = kept ? int32_t(qa) : 0;
+      tq[wave][lane] = double(qi) * dd;
+      wave_sync();
+      // the decoder's values at this lane's point
+      double acc = 0.0;
+      unsigned long long m = mask;
+      const int row = lane < M ? lane : 0;
+      while (m) {
+        const int s = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        acc = acc + double(phi[row * ld + s]) * tq[wave][s];
+      }
+      double e = in ? x - double(T(acc)) : 0.0;
+      const double err = wave_sum(e * e);
+      wave_sync();
+      if (err <= e2) {
+        if (kept) {
+          const int j = __popcll(mask & ((1ull << lane) - 1ull));
+          reinterpret_cast<uint16_t*>(out)[j] = uint16_t(lane);
+          reinterpret_cast<int32_t*>(out + 4 * int64_t(M))[j] = qi;
+        }
+        if (lane == 0) {
+          count[b] = n;
+          kexp[b] = n > 0 ? kx : 0;
+        }
+        done = true;
+        break;
+      }
+      ++n;
+    }
+    if (!done) {
+      if (lane < d.m) {
+        const int ix = lane % d.px(), jy = (lane / d.px()) % d.py(), kz = lane / (d.px() * d.py());
+        reinterpret_cast<T*>(out)[lane] = F[fidx(dims, d.var, d.t0, d.z0 + kz, d.y0 + jy, d.x0 + ix)];
+      }
+      if (lane == 0) {
+        count[b] = kGbRaw;
+        kexp[b] = 0;
+      }
+    }
+  }
+}
+
 // sizes per patch: kept indices (2 n B), coefficients (4 n B), raw values
 __global__ __launch_bounds__(256) void k_gb_sizes(const BlockDesc* __restrict__ desc, int64_t nblocks,
                                                   const int32_t* __restrict__ count, int esize,
@@ -665,6 +828,23 @@ hipError_t launch_gb_select(int dtype, const void* F, const Dims& dims, const Bl
   else
     hipLaunchKernelGGL(k_gb_select<double>, g, dim3{256}, lds, s, static_cast<const double*>(F), dims, desc, nblocks,
                        phi, cv, alpha, px, py, M, Mpow, count, kexp, slot, n0);
+  return hipGetLastError();
+}
+
+hipError_t launch_gb_patch64(int dtype, const void* F, const Dims& dims, const BlockDesc* desc, int64_t nb0,
+                             int64_t nb1, const double* phi, const double* cv, int px, int py, int M, int32_t* count,
+                             int32_t* kexp, uint8_t* slot, int32_t* n0, hipStream_t s) {
+  if (nb1 <= nb0) return hipSuccess;
+  if (M > 64) return hipErrorInvalidValue;
+  // enough workgroups to fill the chip several times; each stages Phi once
+  const int64_t want = (nb1 - nb0 + 3) / 4;
+  const dim3 g{unsigned(std::min<int64_t>(want, 8192))};
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_gb_patch64<float>, g, dim3{256}, 0, s, static_cast<const float*>(F), dims, desc, nb0, nb1,
+                       phi, cv, px, py, M, count, kexp, slot, n0);
+  else
+    hipLaunchKernelGGL(k_gb_patch64<double>, g, dim3{256}, 0, s, static_cast<const double*>(F), dims, desc, nb0,
+                       nb1, phi, cv, px, py, M, count, kexp, slot, n0);
   return hipGetLastError();
 }
 

@@ -222,6 +222,9 @@ hipError_t launch_gb_project(int dtype, const void* F, const Dims& dims, const B
 hipError_t launch_gb_select(int dtype, const void* F, const Dims& dims, const BlockDesc* desc, int64_t nblocks,
                             const double* phi, const double* cv, const double* alpha, int px, int py, int M,
                             int32_t* count, int32_t* kexp, uint8_t* slot, int32_t* n0, hipStream_t s);
+hipError_t launch_gb_patch64(int dtype, const void* F, const Dims& dims, const BlockDesc* desc, int64_t nb0,
+                             int64_t nb1, const double* phi, const double* cv, int px, int py, int M, int32_t* count,
+                             int32_t* kexp, uint8_t* slot, int32_t* n0, hipStream_t s);
 hipError_t launch_gb_sizes(const BlockDesc* desc, int64_t nblocks, const int32_t* count, int esize, int64_t* nidx,
                            int64_t* nraw, hipStream_t s);
 hipError_t launch_gb_compact(const BlockDesc* desc, int64_t nblocks, int M, const int32_t* count, const uint8_t* slot,

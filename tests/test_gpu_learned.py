@@ -221,3 +221,31 @@ def test_warm_start_parity(case):
     out = dls.decompress(stream).cpu().numpy()
     assert np.all(np.abs(out.astype(np.float64) - f.astype(np.float64)) <= p.eps[0])
     assert np.array_equal(odls.decompress(stream).view(np.uint8), out.view(np.uint8))
+
+
+def test_compress_with_model_equals_context_route():
+    """dls_compress with the model in dls_params runs the full form (learned
+    warm start) in one call: its stream equals the context route's (set_model
+    + encode + finalize) byte for byte, warm starts are accepted, and the
+    bound holds."""
+    f, p = _fields()[0]
+    print("compress route with a model", flush=True)
+    m = _fixed_guess_model(4)
+    lp = H.to_lib_params(p)
+    lp.learned = True
+    lp.model = m
+    lp.warm_iters = 2
+    lp.rank_margin = 0
+    t = torch.from_numpy(f).cuda()
+    one = dls.compress(t, lp)
+    enc = dls.Encoder()
+    enc.set_model(m, 2, margin=0)
+    enc.encode(t, lp)
+    assert enc.info().nwarm_accept > 0
+    assert enc.finalize() == one
+    out = dls.decompress(one).cpu().numpy()
+    assert np.all(np.abs(out.astype(np.float64) - f.astype(np.float64)) <= p.eps[0])
+    # without a model the learned form is refused
+    lp.model = None
+    with pytest.raises(dls.DlsError):
+        dls.compress(t, lp)

@@ -244,6 +244,14 @@ typedef struct dls_ctx dls_ctx;
 dls_status dls_ctx_create(int device, dls_ctx** out);
 void dls_ctx_destroy(dls_ctx* ctx);
 
+/* Graph replay of the global basis's Jacobi sweeps (DLS_GLOBAL with the
+ * SVD or random basis): when enabled (the default), one sweep -- its M - 1
+ * rotation rounds and the norm kernels -- is captured once per workspace on
+ * a stream of the context and replayed on the caller's stream, so a sweep
+ * costs one launch instead of M + 1.  0 launches the kernels one by one;
+ * the results are identical.  DLS_EINVAL unless enabled is 0 or 1. */
+dls_status dls_ctx_set_graphs(dls_ctx* ctx, int enabled);
+
 /* Cap on the sweeps of the plain Jacobi eigensolve (Sec. 2.7.1: the basis
  * is the eigenvector set of the block's Gram) for later encodes in this
  * context; default 12, which the tested workloads never reach.  A lower cap

@@ -40,7 +40,7 @@ EXPORTS = ["dls_ctx_create", "dls_ctx_destroy", "dls_encode", "dls_encode_info_g
            "dls_free", "dls_last_error", "dls_model_create", "dls_model_destroy", "dls_model_set",
            "dls_model_get", "dls_model_forward", "dls_model_grad", "dls_model_train_step",
            "dls_features", "dls_ctx_set_model", "dls_decode", "dls_range_noalloc",
-           "dls_ctx_set_jacobi_sweeps"]
+           "dls_ctx_set_jacobi_sweeps", "dls_ctx_set_graphs"]
 
 
 class DlsError(RuntimeError):
@@ -252,6 +252,10 @@ class Encoder:
         """Attach a model for encodes with learned=True (None detaches)."""
         self._model = model
         _check(lib().dls_ctx_set_model(self._h, model._h if model is not None else None, iters, margin))
+
+    def set_graphs(self, enabled: bool):
+        """Graph replay of the global basis's Jacobi sweeps (default on)."""
+        _check(lib().dls_ctx_set_graphs(self._h, int(enabled)))
 
     def set_jacobi_sweeps(self, max_sweeps: int):
         """Cap the plain eigensolve's sweeps for later encodes (default 12)."""

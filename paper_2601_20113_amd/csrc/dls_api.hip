@@ -296,8 +296,14 @@ struct dls_ctx {
   DevBuf gb_slot, gb_nidx, gb_nraw, gb_idx_off, gb_raw_off, gb_idx, gb_q, gb_raw, gb_tot;
   int64_t gb_total = 0, gb_raw_bytes = 0;
   int gb_M = 0;
-  std::vector<int32_t> gb_hcount;   // per-patch counts of the last call (host)
   double* gb_host = nullptr;        // pinned: sweep norms, payload totals
+  // one Jacobi sweep of the global basis (its rounds and the norm kernels)
+  // captured once per workspace layout and replayed per sweep
+  bool use_graphs = true;
+  hipStream_t gb_cap = nullptr;     // capture stream (default priority)
+  hipGraphExec_t gb_sweep = nullptr;
+  const void* gb_sweep_key[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  int gb_sweep_mp = 0;
   int64_t jacobi_sweeps = 0, jacobi_unconverged = 0;
   unsigned long long* jstats() { return reinterpret_cast<unsigned long long*>(counters.as<uint8_t>() + kJacobiAt); }
   PlanScratch* plan_scratch = nullptr;
@@ -336,6 +342,8 @@ struct dls_ctx {
     if (hcnt) (void)hipHostFree(hcnt);
     if (hfused) (void)hipHostFree(hfused);
     if (gb_host) (void)hipHostFree(gb_host);
+    if (gb_sweep) (void)hipGraphExecDestroy(gb_sweep);
+    if (gb_cap) (void)hipStreamDestroy(gb_cap);
   }
 };
 
@@ -539,6 +547,51 @@ dls_status l2_encode(dls_ctx* ctx, const void* d_field, const Problem& p, const 
 }  // namespace
 
 namespace {
+// One Jacobi sweep of order Mp (Mp - 1 rounds, ending in A1) and its norm
+// kernels (A1 copied back to A0, the off-diagonal and total sums of
+// squares to out[0..1]).
+hipError_t gb_sweep_launches(double* A0, double* A1, double* V, int Mp, double* part, double* out, hipStream_t s) {
+  for (int r = 0; r < Mp - 1; ++r) {
+    hipError_t e = launch_gb_jacobi_round((r & 1) ? A1 : A0, (r & 1) ? A0 : A1, V, Mp, r, s);
+    if (e != hipSuccess) return e;
+  }
+  return launch_gb_offnorm(A1, A0, Mp, part, out, s);
+}
+
+// Runs one sweep on s: replays the captured graph of the current workspace
+// (capturing it first when the buffers or the order changed), or launches
+// the kernels one by one when graphs are off.
+dls_status gb_sweep(dls_ctx* ctx, double* A0, double* A1, double* V, int Mp, double* part, double* out,
+                    hipStream_t s) {
+  if (!ctx->use_graphs) {
+    HIP_TRY(gb_sweep_launches(A0, A1, V, Mp, part, out, s));
+    return DLS_OK;
+  }
+  const void* key[6] = {A0, A1, V, part, out, nullptr};
+  if (ctx->gb_sweep == nullptr || ctx->gb_sweep_mp != Mp || !std::equal(key, key + 6, ctx->gb_sweep_key)) {
+    if (ctx->gb_sweep) {
+      HIP_TRY(hipGraphExecDestroy(ctx->gb_sweep));
+      ctx->gb_sweep = nullptr;
+    }
+    if (ctx->gb_cap == nullptr) HIP_TRY(hipStreamCreateWithFlags(&ctx->gb_cap, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(ctx->gb_cap, hipStreamCaptureModeThreadLocal));
+    hipError_t le = gb_sweep_launches(A0, A1, V, Mp, part, out, ctx->gb_cap);
+    hipGraph_t g = nullptr;
+    hipError_t ce = hipStreamEndCapture(ctx->gb_cap, &g);
+    if (le != hipSuccess || ce != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(DLS_EDEVICE, "capture of the Jacobi sweep failed");
+    }
+    hipError_t ie = hipGraphInstantiate(&ctx->gb_sweep, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIP_TRY(ie);
+    std::copy(key, key + 6, ctx->gb_sweep_key);
+    ctx->gb_sweep_mp = Mp;
+  }
+  HIP_TRY(hipGraphLaunch(ctx->gb_sweep, s));
+  return DLS_OK;
+}
+
 // Global-basis encode (DLS_GLOBAL; Alg. 1 as the paper states it): the
 // budget of every variable, then per variable its basis (learned by the
 // parallel Jacobi on the FP64 Gram of the learning patches, or the cosine
@@ -563,7 +616,7 @@ dls_status global_encode(dls_ctx* ctx, const void* d_field, const Problem& p, co
   HIP_TRY(ctx->gb_cv.ensure(size_t(p.nvars) * 8));
   HIP_TRY(ctx->gb_part.ensure((size_t(p.nvars) + 2) * kGbParts * 8));
   HIP_TRY(ctx->gb_norm.ensure(16));
-  HIP_TRY(ctx->gb_tot.ensure(16));
+  HIP_TRY(ctx->gb_tot.ensure(32));
   HIP_TRY(ctx->gb_phi.ensure(size_t(p.nvars) * M * M * 8));
   HIP_TRY(hipMemcpyAsync(ctx->gb_tgt.p, p.eps.data(), size_t(p.nvars) * 8, hipMemcpyHostToDevice, s));
   HIP_TRY(hipEventRecord(ctx->ev0, s));
@@ -588,6 +641,19 @@ dls_status global_encode(dls_ctx* ctx, const void* d_field, const Problem& p, co
     HIP_TRY(launch_gb_samples(p.dtype, d_field, dims, v, p.px, p.py, p.pz, p.basis, p.seed + uint64_t(v), S,
                               ctx->gb_Q.as<double>(), s));
     HIP_TRY(launch_gb_gram(ctx->gb_Q.as<double>(), S, M, Mp, A0, s));
+    const double floor2 = (4e-16 * M) * (4e-16 * M);
+    if (Mp <= 64) {
+      // the whole eigensolve in one workgroup (A and V in LDS)
+      HIP_TRY(launch_gb_jacobi_lds(A0, Mp, floor2, kGbMaxSweeps, A1, V, reinterpret_cast<int*>(ctx->gb_tot.p), s));
+      HIP_TRY(hipMemcpyAsync(ctx->gb_host, ctx->gb_tot.p, 8, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      int inf2[2];
+      std::memcpy(inf2, ctx->gb_host, 8);
+      ctx->jacobi_sweeps += inf2[0];
+      ctx->jacobi_unconverged += inf2[1];
+      HIP_TRY(launch_gb_finish(A1, V, M, Mp, phi, s));
+      continue;
+    }
     HIP_TRY(launch_gb_eye(V, Mp, s));
     // sweeps of Mp - 1 rounds (odd, so each ends in A1; the norm kernel
     // copies it back to A0) until off(A) <= 4e-16 M ||A||_F (the rounding
@@ -597,11 +663,8 @@ dls_status global_encode(dls_ctx* ctx, const void* d_field, const Problem& p, co
     bool conv = false;
     int sweep = 0;
     double prev = HUGE_VAL;
-    const double floor2 = (4e-16 * M) * (4e-16 * M);
     while (!conv && sweep < kGbMaxSweeps) {
-      for (int r = 0; r < Mp - 1; ++r)
-        HIP_TRY(launch_gb_jacobi_round((r & 1) ? A1 : A0, (r & 1) ? A0 : A1, V, Mp, r, s));
-      HIP_TRY(launch_gb_offnorm(A1, A0, Mp, normpart, ctx->gb_norm.as<double>(), s));
+      if (dls_status st = gb_sweep(ctx, A0, A1, V, Mp, normpart, ctx->gb_norm.as<double>(), s)) return st;
       HIP_TRY(hipMemcpyAsync(ctx->gb_host, ctx->gb_norm.p, 16, hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
       ++sweep;
@@ -650,16 +713,19 @@ dls_status global_encode(dls_ctx* ctx, const void* d_field, const Problem& p, co
   HIP_TRY(ctx->gb_idx_off.ensure(size_t(nb) * 8));
   HIP_TRY(ctx->gb_raw_off.ensure(size_t(nb) * 8));
   HIP_TRY(ctx->scan_tmp.ensure(size_t(4 * (nb / 1024 + 4)) * sizeof(int64_t)));
+  HIP_TRY(ctx->gb_tot.ensure(32));
+  unsigned long long* raw_cnt = reinterpret_cast<unsigned long long*>(ctx->gb_tot.as<uint8_t>() + 16);
+  HIP_TRY(launch_zero(raw_cnt, 8, s));
   HIP_TRY(launch_gb_sizes(ctx->desc.as<BlockDesc>(), nb, ctx->gb_count.as<int32_t>(), es,
-                          ctx->gb_nidx.as<int64_t>(), ctx->gb_nraw.as<int64_t>(), s));
+                          ctx->gb_nidx.as<int64_t>(), ctx->gb_nraw.as<int64_t>(), raw_cnt, s));
   HIP_TRY(launch_scan(ctx->gb_nidx.as<int64_t>(), nb, ctx->gb_idx_off.as<int64_t>(), ctx->scan_tmp.as<int64_t>(), s));
   HIP_TRY(launch_scan(ctx->gb_nraw.as<int64_t>(), nb, ctx->gb_raw_off.as<int64_t>(), ctx->scan_tmp.as<int64_t>(), s));
   HIP_TRY(launch_totals(ctx->gb_idx_off.as<int64_t>(), ctx->gb_nidx.as<int64_t>(), ctx->gb_raw_off.as<int64_t>(),
                         ctx->gb_nraw.as<int64_t>(), nb, ctx->gb_tot.as<int64_t>(), s));
-  HIP_TRY(hipMemcpyAsync(ctx->gb_host + 2, ctx->gb_tot.p, 16, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(ctx->gb_host + 2, ctx->gb_tot.p, 24, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  int64_t tot[2];
-  std::memcpy(tot, ctx->gb_host + 2, 16);
+  int64_t tot[3];
+  std::memcpy(tot, ctx->gb_host + 2, 24);
   ctx->gb_total = tot[0];
   ctx->gb_raw_bytes = tot[1];
   HIP_TRY(ctx->gb_idx.ensure(size_t(std::max<int64_t>(tot[0], 1)) * 2));
@@ -669,11 +735,8 @@ dls_status global_encode(dls_ctx* ctx, const void* d_field, const Problem& p, co
                             ctx->gb_idx_off.as<int64_t>(), ctx->gb_raw_off.as<int64_t>(), es,
                             ctx->gb_idx.as<uint16_t>(), ctx->gb_q.as<int32_t>(), ctx->gb_raw.as<uint8_t>(), s));
   HIP_TRY(hipEventRecord(ctx->ev1, s));
-  ctx->gb_hcount.resize(size_t(nb));
-  if (nb) HIP_TRY(hipMemcpyAsync(ctx->gb_hcount.data(), ctx->gb_count.p, size_t(nb) * 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  ctx->nraw = 0;
-  for (int32_t c : ctx->gb_hcount) ctx->nraw += c == kGbRaw ? 1 : 0;
+  ctx->nraw = tot[2];
   ctx->nesc = ctx->nesc_slots = 0;
   ctx->nwarm_accept = ctx->nwarm_reject = 0;
   ctx->nfast_accept = ctx->ndeferred = 0;
@@ -711,7 +774,8 @@ dls_status global_finalize(dls_ctx* ctx, uint8_t** out, size_t* out_bytes) {
   if (ctx->gb_raw_bytes) HIP_TRY(hipMemcpy(raw.data(), ctx->gb_raw.p, ctx->gb_raw_bytes, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(phi.data(), ctx->gb_phi.p, phi.size() * 8, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(cv.data(), ctx->gb_cv.p, cv.size() * 8, hipMemcpyDeviceToHost));
-  const std::vector<int32_t>& cnt = ctx->gb_hcount;
+  std::vector<int32_t> cnt(nb);
+  if (nb) HIP_TRY(hipMemcpy(cnt.data(), ctx->gb_count.p, size_t(nb) * 4, hipMemcpyDeviceToHost));
   const int64_t npb = (nb + kBatchBlocks - 1) / kBatchBlocks;
   const int64_t nbatch = npb + p.nvars;
   std::vector<std::vector<uint8_t>> zs(nbatch);
@@ -1316,6 +1380,12 @@ dls_status dls_ctx_create(int device, dls_ctx** out) {
   }
   c->plan_scratch = plan_scratch_new();
   *out = c.release();
+  return DLS_OK;
+}
+
+dls_status dls_ctx_set_graphs(dls_ctx* ctx, int enabled) {
+  if (ctx == nullptr || (enabled != 0 && enabled != 1)) return fail(DLS_EINVAL, "bad argument");
+  ctx->use_graphs = enabled != 0;
   return DLS_OK;
 }
 

@@ -26,6 +26,7 @@
 //   k_gb_jacobi_round          one round of the parallel cyclic Jacobi:
 //                              M/2 disjoint rotations applied at once
 //   k_gb_offnorm / k_gb_sum    the sweep's off-diagonal and total norms
+//   k_gb_jacobi_lds            the whole eigensolve of order <= 64 in LDS
 //   k_gb_finish                order, signs, 2^-24 grid
 //   k_gb_cosine                the DCT-II tensor basis
 //   k_gb_project               alpha = U Phi on the FP64 matrix cores
@@ -202,6 +203,99 @@ __global__ __launch_bounds__(256) void k_gb_jacobi_round(const double* __restric
   V[pa * n + qb] = sb * v00 + cb * v01;
   V[qa * n + pb] = cb * v10 - sb * v11;
   V[qa * n + qb] = sb * v10 + cb * v11;
+}
+
+// The whole eigensolve of a basis of order Mp <= 64 in one workgroup of
+// 1024 threads with A (two buffers) and V in LDS: the same rounds and
+// rotations as k_gb_jacobi_round, a barrier between rounds, and after each
+// sweep the off-diagonal and total sums of squares (fixed tree order) for
+// the same stopping rule as the host loop (off <= floor2 * total, or a
+// sweep that leaves off above 0.9 of the previous one), at most max_sweeps.
+// A (the diagonal carries the eigenvalues) and V go back to global memory;
+// info[0] = sweeps, info[1] = 1 when the rule was not met.
+__global__ __launch_bounds__(1024) void k_gb_jacobi_lds(const double* __restrict__ G, int Mp, double floor2,
+                                                        int max_sweeps, double* __restrict__ Aout,
+                                                        double* __restrict__ Vout, int* __restrict__ info) {
+  __shared__ double A[2][64 * 64], V[64 * 64];
+  __shared__ double r0[1024], r1[1024];
+  const int tid = threadIdx.x;
+  const int n2 = Mp * Mp;
+  for (int e = tid; e < n2; e += 1024) {
+    A[0][e] = G[e];
+    V[e] = (e / Mp == e % Mp) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int P = Mp / 2;
+  const int a = tid >> 5, b = tid & 31;
+  const bool act = a < P && b < P;
+  int cur = 0, sweep = 0;
+  bool conv = false;
+  double prev = HUGE_VAL;
+  while (!conv && sweep < max_sweeps) {
+    for (int round = 0; round < Mp - 1; ++round) {
+      const double* Ai = A[cur];
+      double* Ao = A[cur ^ 1];
+      if (act) {
+        const int pa = gb_player(a, round, Mp), qa = gb_player(Mp - 1 - a, round, Mp);
+        const int pb = gb_player(b, round, Mp), qb = gb_player(Mp - 1 - b, round, Mp);
+        double ca, sa, ta, cb, sb, tb;
+        gb_rotation(Ai[pa * Mp + pa], Ai[qa * Mp + qa], Ai[pa * Mp + qa], ca, sa, ta);
+        gb_rotation(Ai[pb * Mp + pb], Ai[qb * Mp + qb], Ai[pb * Mp + qb], cb, sb, tb);
+        if (a == b) {
+          const double apq = Ai[pa * Mp + qa];
+          Ao[pa * Mp + pa] = Ai[pa * Mp + pa] - ta * apq;
+          Ao[qa * Mp + qa] = Ai[qa * Mp + qa] + ta * apq;
+          Ao[pa * Mp + qa] = 0.0;
+          Ao[qa * Mp + pa] = 0.0;
+        } else {
+          const double b00 = Ai[pa * Mp + pb], b01 = Ai[pa * Mp + qb], b10 = Ai[qa * Mp + pb], b11 = Ai[qa * Mp + qb];
+          const double t00 = cb * b00 - sb * b01, t01 = sb * b00 + cb * b01;
+          const double t10 = cb * b10 - sb * b11, t11 = sb * b10 + cb * b11;
+          Ao[pa * Mp + pb] = ca * t00 - sa * t10;
+          Ao[pa * Mp + qb] = ca * t01 - sa * t11;
+          Ao[qa * Mp + pb] = sa * t00 + ca * t10;
+          Ao[qa * Mp + qb] = sa * t01 + ca * t11;
+        }
+        const double v00 = V[pa * Mp + pb], v01 = V[pa * Mp + qb], v10 = V[qa * Mp + pb], v11 = V[qa * Mp + qb];
+        V[pa * Mp + pb] = cb * v00 - sb * v01;
+        V[pa * Mp + qb] = sb * v00 + cb * v01;
+        V[qa * Mp + pb] = cb * v10 - sb * v11;
+        V[qa * Mp + qb] = sb * v10 + cb * v11;
+      }
+      cur ^= 1;
+      __syncthreads();
+    }
+    double off = 0.0, tot = 0.0;
+    for (int e = tid; e < n2; e += 1024) {
+      const double x = A[cur][e];
+      tot += x * x;
+      if (e / Mp != e % Mp) off += x * x;
+    }
+    r0[tid] = off;
+    r1[tid] = tot;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+      if (tid < o) {
+        r0[tid] += r0[tid + o];
+        r1[tid] += r1[tid + o];
+      }
+      __syncthreads();
+    }
+    off = r0[0];
+    tot = r1[0];
+    ++sweep;
+    conv = off <= floor2 * tot || off >= 0.9 * prev;
+    prev = off;
+    __syncthreads();
+  }
+  for (int e = tid; e < n2; e += 1024) {
+    Aout[e] = A[cur][e];
+    Vout[e] = V[e];
+  }
+  if (tid == 0) {
+    info[0] = sweep;
+    info[1] = conv ? 0 : 1;
+  }
 }
 
 // Per block of a fixed grid: the sums of squares of the off-diagonal and of
@@ -666,14 +760,19 @@ __global__ __launch_bounds__(256) void k_gb_patch64(const T* __restrict__ F, Dim
 // sizes per patch: kept indices (2 n B), coefficients (4 n B), raw values
 __global__ __launch_bounds__(256) void k_gb_sizes(const BlockDesc* __restrict__ desc, int64_t nblocks,
                                                   const int32_t* __restrict__ count, int esize,
-                                                  int64_t* __restrict__ nidx, int64_t* __restrict__ nraw) {
+                                                  int64_t* __restrict__ nidx, int64_t* __restrict__ nraw,
+                                                  unsigned long long* __restrict__ raw_patches) {
   const int64_t b = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const bool raw = b < nblocks && count[b] == kGbRaw;
+  const unsigned long long m = __ballot(raw);
+  if ((threadIdx.x & 63) == 0 && m) atomicAdd(raw_patches, (unsigned long long)__popcll(m));
   if (b >= nblocks) return;
   const int c = count[b];
-  nidx[b] = c == 0xFFFF ? 0 : c;
-  nraw[b] = c == 0xFFFF ? int64_t(desc[b].m) * esize : 0;
+  nidx[b] = raw ? 0 : c;
+  nraw[b] = raw ? int64_t(desc[b].m) * esize : 0;
 }
 
+// One wave per patch-snapshot, four per workgroup.
 __global__ __launch_bounds__(256) void k_gb_compact(const BlockDesc* __restrict__ desc, int64_t nblocks, int M,
                                                     const int32_t* __restrict__ count,
                                                     const uint8_t* __restrict__ slot,
@@ -681,16 +780,17 @@ __global__ __launch_bounds__(256) void k_gb_compact(const BlockDesc* __restrict_
                                                     const int64_t* __restrict__ raw_off, int esize,
                                                     uint16_t* __restrict__ idx_out, int32_t* __restrict__ q_out,
                                                     uint8_t* __restrict__ raw_out) {
-  const int64_t b = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t b = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
   if (b >= nblocks) return;
   const int c = count[b];
   const uint8_t* s = slot + b * int64_t(8) * M;
-  if (c == 0xFFFF) {
+  if (c == kGbRaw) {
     const int64_t nb = int64_t(desc[b].m) * esize;
-    for (int64_t j = threadIdx.x; j < nb; j += 256) raw_out[raw_off[b] + j] = s[j];
+    for (int64_t j = lane; j < nb; j += 64) raw_out[raw_off[b] + j] = s[j];
     return;
   }
-  for (int j = threadIdx.x; j < c; j += 256) {
+  for (int j = lane; j < c; j += 64) {
     idx_out[idx_off[b] + j] = reinterpret_cast<const uint16_t*>(s)[j];
     q_out[idx_off[b] + j] = reinterpret_cast<const int32_t*>(s + 4 * int64_t(M))[j];
   }
@@ -778,6 +878,13 @@ hipError_t launch_gb_jacobi_round(const double* Ain, double* Aout, double* V, in
   return hipGetLastError();
 }
 
+hipError_t launch_gb_jacobi_lds(const double* G, int Mp, double floor2, int max_sweeps, double* A, double* V,
+                                int* info, hipStream_t s) {
+  if (Mp > 64 || (Mp & 1)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gb_jacobi_lds, dim3{1}, dim3{1024}, 0, s, G, Mp, floor2, max_sweeps, A, V, info);
+  return hipGetLastError();
+}
+
 hipError_t launch_gb_offnorm(const double* A, double* Acopy, int Mp, double* part, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_gb_offnorm, dim3{unsigned(kGbParts)}, dim3{256}, 0, s, A, Acopy, Mp, part);
   hipLaunchKernelGGL(k_gb_sum, dim3{1}, dim3{64}, 0, s, part, int(kGbParts), out);
@@ -849,10 +956,10 @@ hipError_t launch_gb_patch64(int dtype, const void* F, const Dims& dims, const B
 }
 
 hipError_t launch_gb_sizes(const BlockDesc* desc, int64_t nblocks, const int32_t* count, int esize, int64_t* nidx,
-                           int64_t* nraw, hipStream_t s) {
+                           int64_t* nraw, unsigned long long* raw_patches, hipStream_t s) {
   if (nblocks == 0) return hipSuccess;
   hipLaunchKernelGGL(k_gb_sizes, dim3{unsigned((nblocks + 255) / 256)}, dim3{256}, 0, s, desc, nblocks, count, esize,
-                     nidx, nraw);
+                     nidx, nraw, raw_patches);
   return hipGetLastError();
 }
 
@@ -860,9 +967,9 @@ hipError_t launch_gb_compact(const BlockDesc* desc, int64_t nblocks, int M, cons
                              const int64_t* idx_off, const int64_t* raw_off, int esize, uint16_t* idx_out,
                              int32_t* q_out, uint8_t* raw_out, hipStream_t s) {
   if (nblocks == 0) return hipSuccess;
-  if (nblocks > int64_t(INT32_MAX)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_gb_compact, dim3{unsigned(nblocks)}, dim3{256}, 0, s, desc, nblocks, M, count, slot, idx_off,
-                     raw_off, esize, idx_out, q_out, raw_out);
+  if ((nblocks + 3) / 4 > int64_t(INT32_MAX)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gb_compact, dim3{unsigned((nblocks + 3) / 4)}, dim3{256}, 0, s, desc, nblocks, M, count, slot,
+                     idx_off, raw_off, esize, idx_out, q_out, raw_out);
   return hipGetLastError();
 }
 

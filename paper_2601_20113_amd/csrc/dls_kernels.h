@@ -214,6 +214,8 @@ hipError_t launch_gb_gram(const double* Q, int64_t S, int M, int Mp, double* G, 
 hipError_t launch_gb_eye(double* V, int Mp, hipStream_t s);
 hipError_t launch_gb_jacobi_round(const double* Ain, double* Aout, double* V, int Mp, int round, hipStream_t s);
 constexpr int kGbMaxSweeps = 40;
+hipError_t launch_gb_jacobi_lds(const double* G, int Mp, double floor2, int max_sweeps, double* A, double* V,
+                                int* info, hipStream_t s);
 hipError_t launch_gb_offnorm(const double* A, double* Acopy, int Mp, double* part, double* out, hipStream_t s);
 hipError_t launch_gb_finish(const double* A, const double* V, int M, int Mp, double* Phi, hipStream_t s);
 hipError_t launch_gb_cosine(int px, int py, int pz, double* Phi, hipStream_t s);
@@ -226,7 +228,7 @@ hipError_t launch_gb_patch64(int dtype, const void* F, const Dims& dims, const B
                              int64_t nb1, const double* phi, const double* cv, int px, int py, int M, int32_t* count,
                              int32_t* kexp, uint8_t* slot, int32_t* n0, hipStream_t s);
 hipError_t launch_gb_sizes(const BlockDesc* desc, int64_t nblocks, const int32_t* count, int esize, int64_t* nidx,
-                           int64_t* nraw, hipStream_t s);
+                           int64_t* nraw, unsigned long long* raw_patches, hipStream_t s);
 hipError_t launch_gb_compact(const BlockDesc* desc, int64_t nblocks, int M, const int32_t* count, const uint8_t* slot,
                              const int64_t* idx_off, const int64_t* raw_off, int esize, uint16_t* idx_out,
                              int32_t* q_out, uint8_t* raw_out, hipStream_t s);

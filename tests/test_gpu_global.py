@@ -188,3 +188,32 @@ def test_global_compress_route_and_refusals():
                    global_basis=True)
     with pytest.raises(dls.DlsError):
         dls.Encoder().encode(big, q)
+
+
+@pytest.mark.parametrize("kind", ["svd", "random"])
+def test_global_graph_replay_equals_eager(kind):
+    """The Jacobi sweeps of a 256-point basis replayed from the captured
+    graph give the eager launches' stream byte for byte, on two variables
+    (two bases in one call, the graph reused) and on a second call in the
+    same context; the learning step's time is printed for both."""
+    print("case graph replay", kind, flush=True)
+    f, p = _case("blobs_f32_80x72x3_p16", 1e-3)
+    f = np.concatenate([f, f[:, :, :, ::-1, :].copy()])
+    p = odls.Params(**{**p.__dict__, "nvars": 2, "eps": [1e-3, 1e-3]})
+    t = torch.from_numpy(f).cuda()
+    lp = _lib(p, kind, 7)
+    eg = dls.Encoder()
+    eg.encode(t, lp)
+    a = eg.finalize()
+    ms_g, sw_g = eg.info().jacobi_ms, eg.info().jacobi_sweeps
+    eg.encode(t, lp)
+    assert eg.finalize() == a
+    ee = dls.Encoder()
+    ee.set_graphs(False)
+    ee.encode(t, lp)
+    assert ee.finalize() == a
+    print("learning: graph %.3f ms, eager %.3f ms, sweeps %d / %d" % (ms_g, ee.info().jacobi_ms, sw_g,
+                                                                     ee.info().jacobi_sweeps), flush=True)
+    assert ee.info().jacobi_sweeps == sw_g
+    with pytest.raises(dls.DlsError):
+        ee.set_graphs(2)

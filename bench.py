@@ -512,12 +512,14 @@ def run_global_one(field, p, steps, warmup, no_ratio):
          "stage_ms": {"budget+basis": round(inf.stage_ms[1], 3), "coefficients": round(inf.stage_ms[2], 3),
                       "selection": round(inf.stage_ms[3], 3), "pack": round(inf.stage_ms[4], 3)},
          "raw_patches": int(inf.nraw)}
+    # the payload holds 6 bytes per kept coefficient (index, value) and the
+    # raw patches' values
+    m = p.px * p.py * p.pz
+    kept = (inf.qa_bytes - inf.nraw * m * field.element_size()) / 6.0
+    e["mean_kept"] = round(kept / max(inf.nblocks - inf.nraw, 1), 2)
     if not no_ratio:
         buf = enc.finalize()
         e["compression_ratio"] = round(in_bytes / len(buf), 3)
-        st = dls.stats(buf)
-        live = sum(st["rank_hist"])
-        e["mean_kept"] = round(sum(min(k, 32) * c for k, c in enumerate(st["rank_hist"])) / max(live, 1), 2)
     enc.close()
     return e
 

@@ -188,7 +188,9 @@ typedef struct dls_encode_info {
                                at [k][t], canonical signs                   */
   const int32_t* d_desc;    /* [nblocks][8] x0, y0, z0, t0, extents (px | py<<8 |
                                pz<<16 | w<<24), var, M_b, vector flag      */
-  int64_t qa_bytes, codes_bytes;
+  int64_t qa_bytes, codes_bytes;  /* payload bytes (DLS_GLOBAL: 6 per kept
+                               coefficient -- index and value -- plus the raw
+                               patches' values; codes_bytes 0)               */
   const uint8_t* d_qa;      /* qA planes, per block at d_qa_off[b]          */
   const uint8_t* d_codes;   /* residual codes, one byte per value (zigzag  */
                             /* int8, 0xFF = escape), per block at d_code_off */

@@ -2111,28 +2111,6 @@ struct BatchView {
   size_t ranks = 0, esc = 0, qv = 0, qa = 0, codes = 0, vals = 0;
 };
 
-// Rebuild the plan of a parsed header; "" on success.
-std::string plan_from_header(const StreamHeader& h, Plan& pl, int slice) {
-  const Problem& p = h.prob;
-  pl.leaves.assign(p.nvars, {});
-  pl.bits = h.bits;
-  for (int v = 0; v < p.nvars; ++v) {
-    if (p.flags & DLS_ADAPTIVE) {
-      bool ok = true;
-      pl.leaves[v] = leaves_from_bits(p, h.bits[v], &ok);
-      if (!ok) return "split bits inconsistent with the grid";
-    } else {
-      if (!h.bits[v].empty()) return "split bits in a uniform stream";
-      pl.leaves[v] = uniform_leaves(p);
-    }
-  }
-  int64_t nb = 0;
-  for (int v = 0; v < p.nvars; ++v) nb += int64_t(pl.leaves[v].size()) * ((p.nt + p.window - 1) / p.window);
-  if (nb != h.nblocks) return "block count mismatch";
-  build_blocks(p, pl, slice);
-  return "";
-}
-
 // Inflate batch bi and locate its sections; "" on success.
 std::string inflate_batch(const uint8_t* in, const StreamHeader& h, const Plan& pl, int64_t bi, BatchView& bv) {
   const auto& e = h.batches[bi];

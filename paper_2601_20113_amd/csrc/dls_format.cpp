@@ -7,11 +7,12 @@
 // Header, little-endian:
 //   char[4] "DLS1"; u32 version = 2; u32 header_bytes; u32 flags (bit0 adaptive,
 //   bit1 L2 mode: bounds are NRMSE targets, batches hold ranks, steps, qV, qA
-//   and raw values)
+//   and raw values; bit2 global-basis mode: window 1, the batch table ends
+//   with one basis batch per variable)
 //   i32 ndim, nvars, dtype (0 f32, 1 f64), r_max
 //   i64 nx, ny, nz, nt
 //   i32 px, py, pz, pmin, window, batch_blocks (= 1000)
-//   u64 nblocks; u32 nbatches; u32 reserved
+//   u64 nblocks; u32 nbatches; u32 extra (global-basis mode: basis kind)
 //   f64 eps[nvars]
 //   per variable: u32 nbits, ceil(nbits / 8) bytes of split bits, LSB first
 //   per batch: u64 offset (from the end of the header), u64 compressed size,
@@ -235,9 +236,15 @@ std::string parse_header(const uint8_t* buf, size_t n, StreamHeader& h) {
     return "bad sizes";
   if ((p.flags & 1) && (!is_pow2(p.px) || !is_pow2(p.pmin) || p.pmin > p.px))
     return "bad adaptive sizes";
-  if (p.values() <= 0 || p.nx > (int64_t(1) << 31) || p.ny > (int64_t(1) << 31) ||
-      p.nz > (int64_t(1) << 31) || p.nt > (int64_t(1) << 31))
+  if (p.nx > (int64_t(1) << 31) || p.ny > (int64_t(1) << 31) || p.nz > (int64_t(1) << 31) ||
+      p.nt > (int64_t(1) << 31))
     return "bad sizes";
+  // the value count, without overflow: at most 2^50
+  {
+    const double vals = double(p.nvars) * double(p.nt) * double(p.nz) * double(p.ny) * double(p.nx);
+    if (!(vals <= double(int64_t(1) << 50))) return "grid too large";
+  }
+  if (h.nblocks < 1 || h.nblocks > p.values()) return "bad block count";
   size_t pos = kFixed;
   if (pos + 8 * size_t(p.nvars) > hdr) return "truncated bounds";
   p.eps.resize(p.nvars);
@@ -277,6 +284,37 @@ std::string parse_header(const uint8_t* buf, size_t n, StreamHeader& h) {
       return "batch beyond end of stream";
   }
   h.header_bytes = hdr;
+  return "";
+}
+
+std::string plan_from_header(const StreamHeader& h, Plan& pl, int slice) {
+  const Problem& p = h.prob;
+  // the block count of a uniform plan (for an adaptive plan: its roots, a
+  // lower bound), from the sizes alone, before any leaf is built: a corrupt
+  // header must not make the parser allocate its grid
+  {
+    const double per = double((p.nx + p.px - 1) / p.px) * double((p.ny + p.py - 1) / p.py) *
+                       double((p.nz + p.pz - 1) / p.pz);
+    const double nb = double(p.nvars) * double((p.nt + p.window - 1) / p.window) * per;
+    if ((p.flags & DLS_ADAPTIVE) ? nb > double(h.nblocks) : nb != double(h.nblocks)) return "block count mismatch";
+  }
+  if (h.nblocks > (int64_t(1) << 31)) return "too many blocks";
+  pl.leaves.assign(p.nvars, {});
+  pl.bits = h.bits;
+  for (int v = 0; v < p.nvars; ++v) {
+    if (p.flags & DLS_ADAPTIVE) {
+      bool ok = true;
+      pl.leaves[v] = leaves_from_bits(p, h.bits[v], &ok);
+      if (!ok) return "split bits inconsistent with the grid";
+    } else {
+      if (!h.bits[v].empty()) return "split bits in a uniform stream";
+      pl.leaves[v] = uniform_leaves(p);
+    }
+  }
+  int64_t nb = 0;
+  for (int v = 0; v < p.nvars; ++v) nb += int64_t(pl.leaves[v].size()) * ((p.nt + p.window - 1) / p.window);
+  if (nb != h.nblocks) return "block count mismatch";
+  build_blocks(p, pl, slice);
   return "";
 }
 

@@ -109,6 +109,8 @@ struct StreamHeader {
 
 // Returns "" on success, else a message (stream is corrupt).
 std::string parse_header(const uint8_t* buf, size_t n, StreamHeader& h);
+// Rebuild the plan of a parsed header (leaves, blocks, items); "" on success.
+std::string plan_from_header(const StreamHeader& h, Plan& pl, int slice);
 std::vector<uint8_t> write_header(const Problem& p, int64_t nblocks,
                                   const std::vector<std::vector<uint8_t>>& bits,
                                   const std::vector<StreamHeader::Batch>& batches, uint32_t extra = 0);

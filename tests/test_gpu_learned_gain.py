@@ -6,7 +6,8 @@ block) and against a non-learned warm start (a fixed guess: rank 3, the
 first unit vectors), the learned path must keep the bound at every point,
 stay within 1 % of the plain compression ratio, keep the plain ranks on the
 large majority of blocks, accept the warm start on most blocks, and spend
-less device time in the eigensolve stage.
+less device time in the eigensolve stage than both (medians of seven
+encodes), with a mean rank no higher than the fixed guess's.
 """
 import os
 import sys
@@ -22,13 +23,17 @@ from paper_2601_20113_amd import train as T  # noqa: E402
 pytestmark = pytest.mark.gpu
 
 
-def _encode(enc, t, p, reps=3):
-    """Encode `reps` times, return (stage eigen ms of the last, info, ranks, stream)."""
+def _encode(enc, t, p, reps=7):
+    """Encode `reps` times (after one untimed call), return (median eigen-stage
+    ms over the reps, info, ranks, stream)."""
+    enc.encode(t, p)
+    ms = []
     for _ in range(reps):
         enc.encode(t, p)
+        ms.append(enc.info().stage_ms[2])
     inf = enc.info()
     ranks = dls.d2h(inf.d_rank, inf.nblocks).copy()
-    return inf.stage_ms[2], inf, ranks, enc.finalize()
+    return float(np.median(ms)), inf, ranks, enc.finalize()
 
 
 def test_learned_warm_start_gain():
@@ -66,3 +71,7 @@ def test_learned_warm_start_gain():
     assert inf_l.nwarm_accept >= 0.9 * nb
     assert inf_l.nwarm_accept >= inf_f.nwarm_accept
     assert ms_learn < ms_plain
+    # what the network buys over a non-learned warm start: less eigensolve
+    # time (medians of seven encodes in this process) and no higher ranks
+    assert ms_learn < ms_fix
+    assert float(np.mean(r_learn)) <= float(np.mean(r_fix)) + 1e-9

@@ -464,6 +464,18 @@ def run_l2(field, cfg, targets, steps, warmup, no_ratio, log):
              "nrmse": [float("%.4g" % x) for x in nr], "within_target": bool(all(x <= tg for x in nr)),
              "stage_ms": {"gram": round(inf.stage_ms[1], 4), "eigen": round(inf.stage_ms[2], 4),
                           "encode+check": round(inf.stage_ms[4], 4)}}
+        # the two field reads of the mode: the FP64 Gram (with the norm) and
+        # the encode; HIP-event time of each stage on the launch stream
+        gb = in_bytes  # the field read once
+        ach_g = gb / (inf.stage_ms[1] * 1e-3) / 1e9
+        eb = in_bytes + int(inf.qa_bytes)
+        ach_e = eb / (inf.stage_ms[4] * 1e-3) / 1e9
+        e["roofline"] = {"gram": {"kernel": "k_l2_gram (+ k_l2_fsq_part, k_l2_budget)", "bound": "hbm",
+                                  "achieved": round(ach_g, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": round(ach_g / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": int(gb)},
+                         "encode": {"kernel": "k_l2_encode (+ k_l2_params, scans, k_l2_check)", "bound": "hbm",
+                                    "achieved": round(ach_e, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                    "frac": round(ach_e / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": int(eb)}}
         if not no_ratio:
             t1 = time.perf_counter()
             e["compression_ratio"] = round(in_bytes / len(enc.finalize()), 3)

@@ -289,6 +289,7 @@ struct dls_ctx {
   int max_sweeps = kJacobiMaxSweeps;
   // L2 mode: per-block rank bytes, steps, budgets, errors; slice errors
   DevBuf l2rank, l2step, l2e2, l2berr, l2ovf, l2errp, l2cv, l2part, l2tgt;  // l2part: per-slice sums of squares
+  DevBuf l2range, l2fpart;     // per-variable slice ranges, partial sums
   int l2_passes = 0;           // encode passes the last L2 call took
   // global-basis mode: bases, budgets, learning workspace, coefficients,
   // per-patch counts / exponents / slots, packed payload
@@ -476,9 +477,19 @@ dls_status l2_encode(dls_ctx* ctx, const void* d_field, const Problem& p, const 
   // takes no pass of its own.
   HIP_TRY(launch_l2_gram(wp, p.dtype, d_field, dims, ctx->desc.as<BlockDesc>(), ctx->items.as<Item>(), ni,
                          ctx->gram.as<double>(), ctx->l2part.as<double>(), s));
-  HIP_TRY(launch_l2_budget(ctx->items.as<Item>(), ctx->desc.as<BlockDesc>(), ni, ctx->l2part.as<double>(),
-                           ctx->l2tgt.as<double>(), p.nt * p.nx * p.ny * p.nz, p.nvars, ctx->l2cv.as<double>(),
-                           ctx->eps_v.as<double>(), s));
+  {
+    // each variable's slice range (blocks are variable-major)
+    std::vector<int64_t> range(2 * size_t(p.nvars), 0);
+    for (int64_t b = nb - 1; b >= 0; --b) range[2 * pl.blocks[b].var] = pl.item_start[b];
+    for (int64_t b = 0; b < nb; ++b) range[2 * pl.blocks[b].var + 1] = pl.item_start[b + 1];
+    HIP_TRY(ctx->l2range.ensure(range.size() * 8));
+    HIP_TRY(ctx->l2fpart.ensure(size_t(p.nvars) * 256 * 8));
+    HIP_TRY(hipMemcpyAsync(ctx->l2range.p, range.data(), range.size() * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_l2_budget(ctx->l2part.as<double>(), ctx->l2range.as<int64_t>(), ctx->l2fpart.as<double>(),
+                             ctx->l2tgt.as<double>(), p.nt * p.nx * p.ny * p.nz, p.nvars, ctx->l2cv.as<double>(),
+                             ctx->eps_v.as<double>(), s));
+    HIP_TRY(hipStreamSynchronize(s));  // the range vector is pageable host memory
+  }
   HIP_TRY(hipEventRecord(ctx->evs[0], s));
   HIP_TRY(hipEventRecord(ctx->evj[0], s));
   HIP_TRY(launch_eigen(wp, ctx->gram.as<double>(), ctx->item_start.as<int32_t>(), ctx->desc.as<BlockDesc>(), nb,

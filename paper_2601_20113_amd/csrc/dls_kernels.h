@@ -238,9 +238,10 @@ hipError_t launch_gb_decode(int dtype, void* F, const Dims& dims, const BlockDes
                             const uint8_t* raw, hipStream_t s);
 hipError_t launch_l2_gram(int wp, int dtype, const void* F, const Dims& dims, const BlockDesc* desc,
                           const Item* items, int64_t nitems, double* gpart, double* fsq, hipStream_t s);
-hipError_t launch_l2_budget(const Item* items, const BlockDesc* desc, int64_t nitems, const double* fsq,
-                            const double* target, int64_t per_var, int nvars, double* cv, double* eig_eps,
-                            hipStream_t s);
+// range: per variable its slice range [range[2v], range[2v + 1]); part:
+// 256 partial sums per variable
+hipError_t launch_l2_budget(const double* fsq, const int64_t* range, double* part, const double* target,
+                            int64_t per_var, int nvars, double* cv, double* eig_eps, hipStream_t s);
 hipError_t launch_l2_params(const BlockDesc* desc, int64_t nblocks, const double* lam, int wp,
                             const uint8_t* eig_rank, const double* cv, bool first, int esize, uint8_t* l2rank,
                             double* step, double* e2, int64_t* qv_size, int64_t* qa_size, hipStream_t s);

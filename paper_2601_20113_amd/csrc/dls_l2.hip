@@ -19,7 +19,7 @@
 //
 //   k_l2_gram     the slices' Gram partials in FP64 (matrix cores) and the
 //                 sums of squares of their finite values
-//   k_l2_budget   c_v and the eigensolve bound sqrt(0.36 c_v)
+//   k_l2_fsq_part / k_l2_budget   c_v and the eigensolve bound sqrt(0.36 c_v)
 //   k_l2_params   per block: budget, rank (first pass), step, payload sizes
 //   k_l2_encode   one workgroup per slice: projection, quantization, the
 //                 decoder's values and the slice's squared error
@@ -154,29 +154,38 @@ __global__ __launch_bounds__(256) void k_l2_gram(const T* __restrict__ F, Dims d
 
 // c_v = (eps_t,v)^2 ||u_v||^2 / K_v and the eigensolve's bound sqrt(0.36 c_v);
 // ||u_v||^2 is the sum of the variable's slices' finite sums of squares (the
-// plan tiles the field, so every value is in exactly one slice), strided
-// over the slices in a fixed order, one workgroup per variable
-__global__ __launch_bounds__(256) void k_l2_budget(const Item* __restrict__ items,
-                                                   const BlockDesc* __restrict__ desc, int64_t nitems,
-                                                   const double* __restrict__ fsq,
-                                                   const double* __restrict__ target, int64_t per_var,
-                                                   double* __restrict__ cv, double* __restrict__ eig_eps) {
+// plan tiles the field, so every value is in exactly one slice).  The
+// slices of variable v are the contiguous range [range[2v], range[2v + 1])
+// (blocks are variable-major); a fixed grid of partial sums, then the
+// partials in order.
+constexpr int kL2Parts = 256;
+
+__global__ __launch_bounds__(256) void k_l2_fsq_part(const double* __restrict__ fsq,
+                                                     const int64_t* __restrict__ range,
+                                                     double* __restrict__ part) {
   __shared__ double red[256];
-  const int v = blockIdx.x;
+  const int v = blockIdx.y;
+  const int64_t i0 = range[2 * v], i1 = range[2 * v + 1];
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < nitems; i += 256)
-    if (desc[items[i].block].var == v) s += fsq[i];
+  for (int64_t i = i0 + int64_t(blockIdx.x) * 256 + threadIdx.x; i < i1; i += int64_t(kL2Parts) * 256) s += fsq[i];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
     if (int(threadIdx.x) < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    const double c = target[v] * target[v] * red[0] / double(per_var);
-    cv[v] = c;
-    eig_eps[v] = sqrt(kL2TailShare * c);
-  }
+  if (threadIdx.x == 0) part[int64_t(v) * kL2Parts + blockIdx.x] = red[0];
+}
+
+__global__ void k_l2_budget(const double* __restrict__ part, const double* __restrict__ target, int64_t per_var,
+                            int nvars, double* __restrict__ cv, double* __restrict__ eig_eps) {
+  const int v = int(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v >= nvars) return;
+  double s = 0.0;
+  for (int j = 0; j < kL2Parts; ++j) s += part[int64_t(v) * kL2Parts + j];
+  const double c = target[v] * target[v] * s / double(per_var);
+  cv[v] = c;
+  eig_eps[v] = sqrt(kL2TailShare * c);
 }
 
 // first: the rank from the eigensolve (0 when the energy fits the tail
@@ -434,12 +443,13 @@ hipError_t launch_l2_gram(int wp, int dtype, const void* F, const Dims& dims, co
   return hipGetLastError();
 }
 
-hipError_t launch_l2_budget(const Item* items, const BlockDesc* desc, int64_t nitems, const double* fsq,
-                            const double* target, int64_t per_var, int nvars, double* cv, double* eig_eps,
-                            hipStream_t s) {
+hipError_t launch_l2_budget(const double* fsq, const int64_t* range, double* part, const double* target,
+                            int64_t per_var, int nvars, double* cv, double* eig_eps, hipStream_t s) {
   if (nvars == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_l2_budget, dim3{unsigned(nvars)}, dim3{256}, 0, s, items, desc, nitems, fsq, target, per_var,
-                     cv, eig_eps);
+  const dim3 g = dim3(unsigned(kL2Parts), unsigned(nvars));
+  hipLaunchKernelGGL(k_l2_fsq_part, g, dim3{256}, 0, s, fsq, range, part);
+  hipLaunchKernelGGL(k_l2_budget, dim3{unsigned((nvars + 63) / 64)}, dim3{64}, 0, s, part, target, per_var, nvars, cv,
+                     eig_eps);
   return hipGetLastError();
 }
 

@@ -44,6 +44,12 @@ dls_status fail(dls_status s, const std::string& msg) {
                   std::string(#expr) + ": " + hipGetErrorString(e_));              \
   } while (0)
 
+// Device (re)allocations by DevBuf, process-wide: a captured launch sequence
+// stays valid only while every buffer it names stays where it was.
+std::atomic<uint64_t> g_alloc_epoch{0};
+// words of the key of a captured device-driven encode sequence
+constexpr int kDdKey = 16;
+
 struct DevBuf {
   void* p = nullptr;
   size_t n = 0;
@@ -52,7 +58,10 @@ struct DevBuf {
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      (void)hipFree(p);
+      ++g_alloc_epoch;
+    }
     p = nullptr;
     n = 0;
   }
@@ -63,6 +72,7 @@ struct DevBuf {
     hipError_t e = hipMalloc(&p, bytes);
     if (e == hipSuccess) n = bytes;
     else p = nullptr;
+    ++g_alloc_epoch;
     return e;
   }
   // at least `bytes`, contents not kept
@@ -171,6 +181,7 @@ struct dls_model {
   DevBuf params, norm, m, v, grad;
   DevBuf packed;           // bf16 weights in the fused forward's LDS layout
   bool packed_valid = false;
+  uint64_t version = 0;    // bumped whenever the parameters change
   int64_t step = 0;
   DevBuf z, h1, h2, out, gout, dh2, dh1, loss;  // workspace for a batch
   int64_t ws_n = 0;
@@ -298,6 +309,11 @@ struct dls_ctx {
   int64_t gb_total = 0, gb_raw_bytes = 0;
   int gb_M = 0;
   double* gb_host = nullptr;        // pinned: sweep norms, payload totals
+  // the device-driven encode sequence (Gram to encode) captured once per
+  // layout and replayed; key: field, problem, buffers, model, knobs
+  hipGraphExec_t dd_graph = nullptr;
+  uint64_t dd_key[kDdKey] = {};
+  bool dd_replayed = false;      // the last encode replayed the graph
   // one Jacobi sweep of the global basis (its rounds and the norm kernels)
   // captured once per workspace layout and replayed per sweep
   bool use_graphs = true;
@@ -344,6 +360,7 @@ struct dls_ctx {
     if (hfused) (void)hipHostFree(hfused);
     if (gb_host) (void)hipHostFree(gb_host);
     if (gb_sweep) (void)hipGraphExecDestroy(gb_sweep);
+    if (dd_graph) (void)hipGraphExecDestroy(dd_graph);
     if (gb_cap) (void)hipStreamDestroy(gb_cap);
   }
 };
@@ -376,7 +393,8 @@ dls_status feature_lists(dls_ctx* ctx, FeatureLists& L) {
 
 // Eigen stage of a DLS_LEARNED encode: features, network forward (bf16),
 // warm-started eigensolve, Jacobi on the rejected blocks.
-dls_status learned_eigen(dls_ctx* ctx, const void* d_field, const Problem& p, const Dims& dims, hipStream_t s) {
+dls_status learned_eigen(dls_ctx* ctx, const void* d_field, const Problem& p, const Dims& dims, hipStream_t s,
+                         bool events = true) {
   dls_model* m = ctx->model;
   if (m == nullptr) return fail(DLS_EINVAL, "DLS_LEARNED without a model (dls_ctx_set_model)");
   if (m->device != ctx->device) return fail(DLS_EINVAL, "model lives on another device");
@@ -400,19 +418,150 @@ dls_status learned_eigen(dls_ctx* ctx, const void* d_field, const Problem& p, co
   unsigned int* nrej = reinterpret_cast<unsigned int*>(reinterpret_cast<uint8_t*>(cnt) + kRejectCountAt);
   HIP_TRY(ctx->reject_list.ensure(size_t(nb) * sizeof(int32_t)));
   HIP_TRY(launch_compact_flags(ctx->reject.as<uint8_t>(), nb, ctx->reject_list.as<int32_t>(), nrej, s));
-  HIP_TRY(hipEventRecord(ctx->evj[0], s));
+  if (events) HIP_TRY(hipEventRecord(ctx->evj[0], s));
   HIP_TRY(launch_eigen(16, ctx->gram.as<double>(), ctx->item_start.as<int32_t>(), ctx->desc.as<BlockDesc>(), nb,
                        ctx->eps_v.as<double>(), p.r_max, ctx->rank.as<uint8_t>(), ctx->lam.as<double>(),
                        ctx->basis.as<double>(), ctx->qv_size.as<int64_t>(), ctx->qa_size.as<int64_t>(), cnt + 1,
                        ctx->reject_list.as<int32_t>(), nrej, ctx->jstats(), ctx->max_sweeps, s));
-  HIP_TRY(hipEventRecord(ctx->evj[1], s));
-  ctx->jacobi_timed = true;
+  if (events) {
+    HIP_TRY(hipEventRecord(ctx->evj[1], s));
+    ctx->jacobi_timed = true;
+  }
   return DLS_OK;
 }
 }  // namespace
 
 namespace {
 constexpr int64_t kDeviceDrivenMaxItems = 65536;
+
+// The launches from the Gram to the classified rank lists, shared by both
+// encode launches; `events` records the stage events (off while a graph is
+// being captured).
+dls_status enqueue_front(dls_ctx* ctx, const void* d_field, const Problem& p, const Dims& dims,
+                         const GramSplit* split, hipStream_t s, bool events) {
+  const Plan& pl = ctx->plan;
+  const int64_t nb = int64_t(pl.blocks.size()), ni = int64_t(pl.items.size());
+  const int wp = p.wpad();
+  unsigned long long* cnt = ctx->counters.as<unsigned long long>();
+  HIP_TRY(launch_gram(wp, p.dtype, p.precision == DLS_PREC_BF16, d_field, dims, ctx->desc.as<BlockDesc>(),
+                      ctx->items.as<Item>(), ni, split, ctx->gram.as<double>(), s));
+  if (events) HIP_TRY(hipEventRecord(ctx->evs[0], s));
+  // the warm start applies to blocks of at most kWarmMaxPoints points; a plan
+  // without any takes the plain eigensolve directly
+  if ((p.flags & DLS_LEARNED) && ctx->plan_warm_blocks > 0) {
+    if (dls_status st = learned_eigen(ctx, d_field, p, dims, s, events)) return st;
+  } else {
+    if (events) HIP_TRY(hipEventRecord(ctx->evj[0], s));
+    HIP_TRY(launch_eigen(wp, ctx->gram.as<double>(), ctx->item_start.as<int32_t>(), ctx->desc.as<BlockDesc>(),
+                         nb, ctx->eps_v.as<double>(), p.r_max, ctx->rank.as<uint8_t>(), ctx->lam.as<double>(),
+                         ctx->basis.as<double>(), ctx->qv_size.as<int64_t>(), ctx->qa_size.as<int64_t>(),
+                         cnt + 1, nullptr, nullptr, ctx->jstats(), ctx->max_sweeps, s));
+    if (events) {
+      HIP_TRY(hipEventRecord(ctx->evj[1], s));
+      ctx->jacobi_timed = true;
+    }
+  }
+  if (events) HIP_TRY(hipEventRecord(ctx->evs[1], s));
+  HIP_TRY(launch_scan(ctx->qv_size.as<int64_t>(), nb, ctx->qv_off.as<int64_t>(), ctx->scan_tmp.as<int64_t>(), s));
+  HIP_TRY(launch_scan(ctx->qa_size.as<int64_t>(), nb, ctx->qa_off.as<int64_t>(), ctx->scan_tmp.as<int64_t>(), s));
+  unsigned int* cls_count = reinterpret_cast<unsigned int*>(cnt + 4);
+  HIP_TRY(launch_classify(ctx->items.as<Item>(), ni, ctx->rank.as<uint8_t>(),
+                          split ? encode_small_limit(wp, p.dtype) : 0, cls_count, ctx->cls_lists.as<int32_t>(), s));
+  if (events) HIP_TRY(hipEventRecord(ctx->evs[2], s));
+  return DLS_OK;
+}
+
+// The device-driven encode: payload totals and one launch per rank class
+// over the device-written class lists, into the payload buffers as sized.
+dls_status enqueue_dd_encode(dls_ctx* ctx, const void* d_field, const Problem& p, const Dims& dims, hipStream_t s,
+                             bool events) {
+  const Plan& pl = ctx->plan;
+  const int64_t nb = int64_t(pl.blocks.size()), ni = int64_t(pl.items.size());
+  const int wp = p.wpad();
+  unsigned long long* cnt = ctx->counters.as<unsigned long long>();
+  unsigned int* cls_count = reinterpret_cast<unsigned int*>(cnt + 4);
+  unsigned int* overflow = reinterpret_cast<unsigned int*>(reinterpret_cast<uint8_t*>(cnt) + kOverflowAt);
+  int64_t* totals = reinterpret_cast<int64_t*>(reinterpret_cast<uint8_t*>(cnt) + kTotalsAt);
+  HIP_TRY(launch_totals(ctx->qv_off.as<int64_t>(), ctx->qv_size.as<int64_t>(), ctx->qa_off.as<int64_t>(),
+                        ctx->qa_size.as<int64_t>(), nb, totals, s));
+  EscOut esc{cnt, ctx->esc_key.as<uint64_t>(), ctx->esc_val.as<uint64_t>(), ctx->esc_cap};
+  if (events) HIP_TRY(hipEventRecord(ctx->evs[3], s));
+  for (int c = 0; c < kEncodeClasses; ++c) {
+    const EncodeWork work{cls_count + c, ni, int64_t(ctx->qv.n), int64_t(ctx->qa.n), overflow};
+    HIP_TRY(launch_encode(wp, p.dtype, c, d_field, dims, ctx->desc.as<BlockDesc>(), ctx->items.as<Item>(),
+                          ctx->cls_lists.as<int32_t>() + int64_t(c) * ni, work, ctx->rank.as<uint8_t>(),
+                          ctx->basis.as<double>(), ctx->qv_off.as<int64_t>(), ctx->qa_off.as<int64_t>(),
+                          ctx->code_off.as<int64_t>(), ctx->vconst.as<VarConst>(), ctx->qv.as<uint8_t>(),
+                          ctx->qa.as<uint8_t>(), ctx->codes.as<uint8_t>(),
+                          ctx->keep_coef ? ctx->coef.as<float>() : nullptr, esc, s));
+  }
+  return DLS_OK;
+}
+
+// What a captured device-driven sequence bakes in: every buffer address
+// (through the allocation epoch), the field, the launch shapes, the model
+// and the knobs (kDdKey words).
+void dd_key(const dls_ctx* ctx, const void* d_field, const Problem& p, uint64_t key[kDdKey]) {
+  const bool learned = (p.flags & DLS_LEARNED) != 0;
+  key[0] = g_alloc_epoch.load();
+  key[1] = uint64_t(reinterpret_cast<uintptr_t>(d_field));
+  key[2] = uint64_t(p.flags) | (uint64_t(p.precision) << 8) | (uint64_t(p.dtype) << 12) | (uint64_t(p.r_max) << 16) |
+           (uint64_t(p.wpad()) << 24) | (uint64_t(ctx->keep_coef) << 32) | (uint64_t(ctx->max_sweeps) << 40);
+  key[3] = uint64_t(ctx->plan.blocks.size());
+  key[4] = uint64_t(ctx->plan.items.size());
+  key[5] = learned ? uint64_t(reinterpret_cast<uintptr_t>(ctx->model)) : 0;
+  key[6] = learned && ctx->model ? ctx->model->version : 0;
+  key[7] = uint64_t(ctx->warm_iters) | (uint64_t(ctx->warm_margin) << 16) | (uint64_t(ctx->plan_warm_blocks) << 32);
+  key[8] = ctx->esc_cap;
+  key[9] = uint64_t(ctx->split_nlarge);
+  key[10] = uint64_t(ctx->split_nsmall);
+  key[11] = uint64_t(ctx->feat_n[0]);
+  key[12] = uint64_t(ctx->feat_n[1]);
+  key[13] = uint64_t(ctx->feat_n[2]);
+  key[14] = uint64_t(p.nx) ^ (uint64_t(p.ny) << 20) ^ (uint64_t(p.nz) << 40) ^ (uint64_t(p.nt) << 52);
+  key[15] = uint64_t(p.px) | (uint64_t(p.py) << 8) | (uint64_t(p.pz) << 16) | (uint64_t(p.window) << 24) |
+            (uint64_t(ctx->split_valid) << 32) | (uint64_t(ctx->feat_valid) << 33);
+}
+
+// Captures the device-driven sequence for the next calls with the same key
+// (after an eager call, so every buffer and upload is in place).  A capture
+// that fails leaves the eager launches in use.
+void dd_capture(dls_ctx* ctx, const void* d_field, const Problem& p, const Dims& dims, const GramSplit* split) {
+  if (ctx->dd_graph) {
+    (void)hipGraphExecDestroy(ctx->dd_graph);
+    ctx->dd_graph = nullptr;
+  }
+  if (ctx->gb_cap == nullptr && hipStreamCreateWithFlags(&ctx->gb_cap, hipStreamNonBlocking) != hipSuccess) {
+    ctx->gb_cap = nullptr;
+    (void)hipGetLastError();
+    return;
+  }
+  uint64_t key[kDdKey];
+  dd_key(ctx, d_field, p, key);
+  if (hipStreamBeginCapture(ctx->gb_cap, hipStreamCaptureModeRelaxed) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  const std::string saved = g_err;
+  dls_status st = enqueue_front(ctx, d_field, p, dims, split, ctx->gb_cap, false);
+  if (st == DLS_OK) st = enqueue_dd_encode(ctx, d_field, p, dims, ctx->gb_cap, false);
+  hipGraph_t g = nullptr;
+  const hipError_t ce = hipStreamEndCapture(ctx->gb_cap, &g);
+  g_err = saved;
+  if (st != DLS_OK || ce != hipSuccess || g == nullptr) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return;
+  }
+  const hipError_t ie = hipGraphInstantiate(&ctx->dd_graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) {
+    ctx->dd_graph = nullptr;
+    (void)hipGetLastError();
+    return;
+  }
+  std::copy(key, key + kDdKey, ctx->dd_key);
+}
 
 // device time of the whole encode and of its five stages, from the events
 dls_status finish_encode(dls_ctx* ctx) {
@@ -1576,55 +1725,35 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
     ctx->fused_timed = ctx->jacobi_timed = false;
     HIP_TRY(hipEventRecord(ctx->ev0, s));
   }
-  HIP_TRY(launch_gram(wp, p.dtype, p.precision == DLS_PREC_BF16, d_field, dims, ctx->desc.as<BlockDesc>(),
-                      ctx->items.as<Item>(), ni, batched ? &split : nullptr, ctx->gram.as<double>(), s));
-  HIP_TRY(hipEventRecord(ctx->evs[0], s));
   const bool learned = (p.flags & DLS_LEARNED) != 0;
-  // the warm start applies to blocks of at most kWarmMaxPoints points; a plan
-  // without any takes the plain eigensolve directly
   const bool warm_any = ctx->plan_warm_blocks > 0;
-  if (learned && warm_any) {
-    if (dls_status st = learned_eigen(ctx, d_field, p, dims, s)) return st;
-  } else {
-    HIP_TRY(hipEventRecord(ctx->evj[0], s));
-    HIP_TRY(launch_eigen(wp, ctx->gram.as<double>(), ctx->item_start.as<int32_t>(), ctx->desc.as<BlockDesc>(),
-                         nb, ctx->eps_v.as<double>(), p.r_max, ctx->rank.as<uint8_t>(), ctx->lam.as<double>(),
-                         ctx->basis.as<double>(), ctx->qv_size.as<int64_t>(), ctx->qa_size.as<int64_t>(),
-                         cnt + 1, nullptr, nullptr, ctx->jstats(), ctx->max_sweeps, s));
-    HIP_TRY(hipEventRecord(ctx->evj[1], s));
-    ctx->jacobi_timed = true;
-  }
-  HIP_TRY(hipEventRecord(ctx->evs[1], s));
-  HIP_TRY(launch_scan(ctx->qv_size.as<int64_t>(), nb, ctx->qv_off.as<int64_t>(), ctx->scan_tmp.as<int64_t>(), s));
-  HIP_TRY(launch_scan(ctx->qa_size.as<int64_t>(), nb, ctx->qa_off.as<int64_t>(), ctx->scan_tmp.as<int64_t>(), s));
-  unsigned int* cls_count = reinterpret_cast<unsigned int*>(cnt + 4);
-  HIP_TRY(launch_classify(ctx->items.as<Item>(), ni, ctx->rank.as<uint8_t>(),
-                          batched ? encode_small_limit(wp, p.dtype) : 0, cls_count,
-                          ctx->cls_lists.as<int32_t>(), s));
-  HIP_TRY(hipEventRecord(ctx->evs[2], s));
   unsigned int* overflow = reinterpret_cast<unsigned int*>(reinterpret_cast<uint8_t*>(cnt) + kOverflowAt);
   int64_t* totals = reinterpret_cast<int64_t*>(reinterpret_cast<uint8_t*>(cnt) + kTotalsAt);
+  const GramSplit* gsplit = batched ? &split : nullptr;
   // the device-driven launch saves the host round trip (~0.1-0.2 ms) but its
   // looping workgroups encode large lists more slowly than one workgroup per
   // item; measured on the synthetic workloads the crossover lies between
   // ~10^4 and ~2 x 10^5 items, so larger plans keep the host-driven launch
-  if ((p.flags & DLS_PERSISTENT) && ni <= kDeviceDrivenMaxItems) {
+  const bool dd = (p.flags & DLS_PERSISTENT) && ni <= kDeviceDrivenMaxItems;
+  ctx->dd_replayed = false;
+  if (!dd) {
+    if (dls_status st = enqueue_front(ctx, d_field, p, dims, gsplit, s, true)) return st;
+  } else {
     // device-driven encode into the buffers as they are; one readback at the end
     HIP_TRY(ctx->qv.ensure(16));
     HIP_TRY(ctx->qa.ensure(16));
     if (ctx->keep_coef) HIP_TRY(ctx->coef.ensure(ctx->qa.n));
-    HIP_TRY(launch_totals(ctx->qv_off.as<int64_t>(), ctx->qv_size.as<int64_t>(), ctx->qa_off.as<int64_t>(),
-                          ctx->qa_size.as<int64_t>(), nb, totals, s));
-    EscOut esc{cnt, ctx->esc_key.as<uint64_t>(), ctx->esc_val.as<uint64_t>(), ctx->esc_cap};
-    HIP_TRY(hipEventRecord(ctx->evs[3], s));
-    for (int c = 0; c < kEncodeClasses; ++c) {
-      const EncodeWork work{cls_count + c, ni, int64_t(ctx->qv.n), int64_t(ctx->qa.n), overflow};
-      HIP_TRY(launch_encode(wp, p.dtype, c, d_field, dims, ctx->desc.as<BlockDesc>(), ctx->items.as<Item>(),
-                            ctx->cls_lists.as<int32_t>() + int64_t(c) * ni, work, ctx->rank.as<uint8_t>(),
-                            ctx->basis.as<double>(), ctx->qv_off.as<int64_t>(), ctx->qa_off.as<int64_t>(),
-                            ctx->code_off.as<int64_t>(), ctx->vconst.as<VarConst>(), ctx->qv.as<uint8_t>(),
-                            ctx->qa.as<uint8_t>(), ctx->codes.as<uint8_t>(),
-                            ctx->keep_coef ? ctx->coef.as<float>() : nullptr, esc, s));
+    uint64_t key[kDdKey];
+    dd_key(ctx, d_field, p, key);
+    if (ctx->use_graphs && ctx->dd_graph != nullptr && std::equal(key, key + kDdKey, ctx->dd_key)) {
+      // replay of the captured sequence; its stages are not separated (the
+      // whole replay counts as the encode stage)
+      for (int k = 0; k < 4; ++k) HIP_TRY(hipEventRecord(ctx->evs[k], s));
+      HIP_TRY(hipGraphLaunch(ctx->dd_graph, s));
+      ctx->dd_replayed = true;
+    } else {
+      if (dls_status st = enqueue_front(ctx, d_field, p, dims, gsplit, s, true)) return st;
+      if (dls_status st = enqueue_dd_encode(ctx, d_field, p, dims, s, true)) return st;
     }
     HIP_TRY(hipEventRecord(ctx->ev1, s));
     HIP_TRY(ctx->host_counters());
@@ -1645,6 +1774,7 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
     ctx->nwarm_reject = learned ? (warm_any ? int64_t(hc[3]) : nb) : 0;
     if (hov == 0 && hc[0] <= ctx->esc_cap) {
       ctx->launch_mode = 1;
+      if (ctx->use_graphs && !ctx->dd_replayed) dd_capture(ctx, d_field, p, dims, gsplit);
       return finish_encode(ctx);
     }
     // did not fit: grow with headroom for later calls, then the host-driven
@@ -1747,6 +1877,7 @@ dls_status dls_model_set(dls_model* m, const float* params, const float* norm) {
       if (!(norm[i] > 0.f)) return fail(DLS_EINVAL, "normalisation scales must be > 0");
   HIP_TRY(hipMemcpy(m->params.p, params, kNParam * 4, hipMemcpyHostToDevice));
   m->packed_valid = false;
+  ++m->version;
   if (norm != nullptr) HIP_TRY(hipMemcpy(m->norm.p, norm, 32 * 4, hipMemcpyHostToDevice));
   HIP_TRY(hipMemset(m->m.p, 0, kNParam * 4));
   HIP_TRY(hipMemset(m->v.p, 0, kNParam * 4));
@@ -1803,6 +1934,7 @@ dls_status dls_model_train_step(dls_model* m, const float* d_feat, const int32_t
   const float c1 = float(1.0 - std::pow(0.9, double(m->step)));
   const float c2 = float(1.0 - std::pow(0.999, double(m->step)));
   m->packed_valid = false;
+  ++m->version;
   HIP_TRY(launch_adam(m->params.as<float>(), m->grad.as<float>(), m->m.as<float>(), m->v.as<float>(), kNParam, lr, c1,
                       c2, s));
   if (loss_out == nullptr) HIP_TRY(hipStreamSynchronize(s));

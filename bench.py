@@ -554,6 +554,22 @@ def run_global(steps, warmup, no_ratio, log):
     log("global 4096x2048x100 svd 8x8 1e-3: %s" % e)
     res["throughput"] = dict(e, workload="2D FP32 4096x2048 x 100 steps, 8192 moving Gaussian blobs, 8x8 patches, "
                                          "SVD basis, NRMSE 1e-3")
+    # the launch-strategy autotuner on the same field as the quadtree
+    # workload (absolute bound, bf16 Gram, batched form without a model)
+    import paper_2601_20113_amd as dls
+    from paper_2601_20113_amd import autotune
+    c3 = CONFIGS["c3"]
+    lo, hi = dls.value_range(f)
+    pq = params_for(dict(c3), [c3["rel_eps"] * (hi[0] - lo[0])], "full")
+    pq.learned = False
+    enc = dls.Encoder()
+    choice = autotune.tune(f, pq, enc, reps=3, cache=None, check_streams=True)
+    enc.close()
+    log("launch tuning on the quadtree workload: %s" % choice)
+    res["launch_tuning"] = dict(choice, workload="c3 field, absolute bound 1e-3*range, quadtree, bf16 Gram, batched "
+                                                "form without the warm start",
+                                what="time per encode (median of 3) for each device-driven limit (slices) / graph "
+                                     "replay; every candidate wrote the same stream")
     del f
     torch.cuda.empty_cache()
     g = torch.empty((1, 16, 1, 1024, 1024), dtype=torch.float32, device="cuda")

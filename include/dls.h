@@ -246,12 +246,30 @@ typedef struct dls_ctx dls_ctx;
 dls_status dls_ctx_create(int device, dls_ctx** out);
 void dls_ctx_destroy(dls_ctx* ctx);
 
-/* Graph replay of the global basis's Jacobi sweeps (DLS_GLOBAL with the
- * SVD or random basis): when enabled (the default), one sweep -- its M - 1
- * rotation rounds and the norm kernels -- is captured once per workspace on
- * a stream of the context and replayed on the caller's stream, so a sweep
- * costs one launch instead of M + 1.  0 launches the kernels one by one;
- * the results are identical.  DLS_EINVAL unless enabled is 0 or 1. */
+/* Launch strategy of DLS_PERSISTENT plans that do not take the single pass:
+ * plans of at most device_driven_max_items slices take the device-driven
+ * encode (no host round trip between the eigensolve and the encode, the
+ * encode kernels walk device-written rank-class lists); larger plans the
+ * host-driven one (one launch per rank class sized from a readback).  The
+ * two write identical streams; which is faster depends on the plan (the
+ * device-driven launch's looping workgroups are slower on very long lists).
+ * Default 65536; 0 always host-driven.  The autotuner of the Python package
+ * (paper_2601_20113_amd.autotune) times the choices on a workload and caches
+ * the fastest.  DLS_EINVAL on a negative count. */
+dls_status dls_ctx_set_launch(dls_ctx* ctx, int64_t device_driven_max_items);
+
+/* Graph replay (enabled by default; 0 launches every kernel on its own,
+ * with identical results):
+ *  - the device-driven encode (see dls_ctx_set_launch): after an eager call
+ *    the sequence from the Gram to the encode is captured on a stream of
+ *    the context and replayed on the caller's stream by later calls while
+ *    the field pointer, the problem, every workspace buffer, the model and
+ *    its parameters and the launch shapes are unchanged (otherwise the call
+ *    runs eagerly and captures again); the replay's stages are not timed
+ *    separately (dls_encode_info.stage_ms counts it as the encode stage);
+ *  - the global basis's Jacobi sweeps (DLS_GLOBAL, bases of order > 64):
+ *    one sweep's M - 1 rotation rounds and norm kernels, replayed per sweep.
+ * DLS_EINVAL unless enabled is 0 or 1. */
 dls_status dls_ctx_set_graphs(dls_ctx* ctx, int enabled);
 
 /* Cap on the sweeps of the plain Jacobi eigensolve (Sec. 2.7.1: the basis

@@ -40,7 +40,7 @@ EXPORTS = ["dls_ctx_create", "dls_ctx_destroy", "dls_encode", "dls_encode_info_g
            "dls_free", "dls_last_error", "dls_model_create", "dls_model_destroy", "dls_model_set",
            "dls_model_get", "dls_model_forward", "dls_model_grad", "dls_model_train_step",
            "dls_features", "dls_ctx_set_model", "dls_decode", "dls_range_noalloc",
-           "dls_ctx_set_jacobi_sweeps", "dls_ctx_set_graphs"]
+           "dls_ctx_set_jacobi_sweeps", "dls_ctx_set_graphs", "dls_ctx_set_launch"]
 
 
 class DlsError(RuntimeError):
@@ -100,6 +100,8 @@ def lib():
         L.dls_ctx_destroy.argtypes = [ctypes.c_void_p]
         L.dls_ctx_destroy.restype = None
         L.dls_ctx_set_jacobi_sweeps.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.dls_ctx_set_graphs.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.dls_ctx_set_launch.argtypes = [ctypes.c_void_p, ctypes.c_int64]
         L.dls_encode.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Params),
                                  ctypes.c_void_p, ctypes.c_int]
         L.dls_encode_info_get.argtypes = [ctypes.c_void_p, ctypes.POINTER(_EncodeInfo)]
@@ -252,6 +254,10 @@ class Encoder:
         """Attach a model for encodes with learned=True (None detaches)."""
         self._model = model
         _check(lib().dls_ctx_set_model(self._h, model._h if model is not None else None, iters, margin))
+
+    def set_launch(self, device_driven_max_items: int):
+        """Plans of at most this many slices take the device-driven encode."""
+        _check(lib().dls_ctx_set_launch(self._h, ctypes.c_int64(int(device_driven_max_items))))
 
     def set_graphs(self, enabled: bool):
         """Graph replay of the global basis's Jacobi sweeps (default on)."""

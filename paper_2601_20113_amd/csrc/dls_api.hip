@@ -317,6 +317,9 @@ struct dls_ctx {
   // one Jacobi sweep of the global basis (its rounds and the norm kernels)
   // captured once per workspace layout and replayed per sweep
   bool use_graphs = true;
+  int64_t dd_max_items = 65536;     // device-driven launch up to this many slices
+                                    // (looping encode workgroups measured slower
+                                    // than one per slice above ~10^5 slices)
   hipStream_t gb_cap = nullptr;     // capture stream (default priority)
   hipGraphExec_t gb_sweep = nullptr;
   const void* gb_sweep_key[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -432,7 +435,6 @@ dls_status learned_eigen(dls_ctx* ctx, const void* d_field, const Problem& p, co
 }  // namespace
 
 namespace {
-constexpr int64_t kDeviceDrivenMaxItems = 65536;
 
 // The launches from the Gram to the classified rank lists, shared by both
 // encode launches; `events` records the stage events (off while a graph is
@@ -1543,6 +1545,12 @@ dls_status dls_ctx_create(int device, dls_ctx** out) {
   return DLS_OK;
 }
 
+dls_status dls_ctx_set_launch(dls_ctx* ctx, int64_t device_driven_max_items) {
+  if (ctx == nullptr || device_driven_max_items < 0) return fail(DLS_EINVAL, "bad argument");
+  ctx->dd_max_items = device_driven_max_items;
+  return DLS_OK;
+}
+
 dls_status dls_ctx_set_graphs(dls_ctx* ctx, int enabled) {
   if (ctx == nullptr || (enabled != 0 && enabled != 1)) return fail(DLS_EINVAL, "bad argument");
   ctx->use_graphs = enabled != 0;
@@ -1734,7 +1742,7 @@ dls_status dls_encode(dls_ctx* ctx, const void* d_field, const dls_params* param
   // looping workgroups encode large lists more slowly than one workgroup per
   // item; measured on the synthetic workloads the crossover lies between
   // ~10^4 and ~2 x 10^5 items, so larger plans keep the host-driven launch
-  const bool dd = (p.flags & DLS_PERSISTENT) && ni <= kDeviceDrivenMaxItems;
+  const bool dd = (p.flags & DLS_PERSISTENT) && ni <= ctx->dd_max_items;
   ctx->dd_replayed = false;
   if (!dd) {
     if (dls_status st = enqueue_front(ctx, d_field, p, dims, gsplit, s, true)) return st;

@@ -388,7 +388,10 @@ __global__ __launch_bounds__(256) void k_encode(const T* __restrict__ F, Dims di
 // by the escape scatter (k_scatter or k_scatter_keys) that follows.
 // ---------------------------------------------------------------------------
 // RMAX bounds the rank of every block of the launch (a rank class, or WP).
-template <int WP, typename T, int RMAX>
+// TEAM = 0: one workgroup per slice; TEAM = 16: sixteen 16-lane teams per
+// 256-thread workgroup, one slice each (slices of at most 16 PPT points),
+// entries blockIdx.x * 16 + team of the list, up to count.
+template <int WP, typename T, int RMAX, int TEAM>
 __global__ __launch_bounds__(256) void k_decode(T* __restrict__ F, Dims dims,
                                                 const BlockDesc* __restrict__ desc,
                                                 const Item* __restrict__ items,
@@ -400,18 +403,25 @@ __global__ __launch_bounds__(256) void k_decode(T* __restrict__ F, Dims dims,
                                                 const VarConst* __restrict__ vc,
                                                 const uint8_t* __restrict__ qv_buf,
                                                 const uint8_t* __restrict__ qa_buf,
-                                                const uint8_t* __restrict__ codes) {
+                                                const uint8_t* __restrict__ codes, int64_t count) {
   // PPT consecutive points per thread: 4-byte code and coefficient-plane
   // loads and 16-byte (FP32) stores for 4-aligned patch rows
   constexpr int PPT = WP == 16 ? 4 : 2;
-  __shared__ double Qv[WP][RMAX];  // [t][k]
-  const Item it = items[list ? list[blockIdx.x] : int32_t(blockIdx.x)];
+  constexpr int NT = TEAM ? 256 / TEAM : 1;     // slices per workgroup
+  constexpr int LANES = TEAM ? TEAM : 256;     // threads per slice
+  __shared__ double Qv_all[NT][WP][RMAX];      // [t][k] per slice
+  const int team = TEAM ? int(threadIdx.x) / TEAM : 0;
+  const int tl = TEAM ? int(threadIdx.x) % TEAM : int(threadIdx.x);
+  const int64_t entry = TEAM ? int64_t(blockIdx.x) * NT + team : int64_t(blockIdx.x);
+  const bool live = !TEAM || entry < count;
+  const Item it = items[list ? list[live ? entry : 0] : int32_t(live ? entry : 0)];
   const int b = it.block;
   const BlockDesc d = desc[b];
   const int W = d.w(), M = d.m, r = rank[b];
   const VarConst K = vc[d.var];
   const int64_t vplane = pad16(int64_t(W) * r);
-  for (int idx = threadIdx.x; idx < WP * RMAX; idx += blockDim.x) {
+  auto& Qv = Qv_all[team];
+  for (int idx = tl; idx < WP * RMAX; idx += LANES) {
     const int k = idx / WP, t = idx % WP;
     double v = 0.0;
     if (k < r && t < W) {
@@ -423,12 +433,13 @@ __global__ __launch_bounds__(256) void k_decode(T* __restrict__ F, Dims dims,
     Qv[t][k] = v;
   }
   __syncthreads();
+  if (!live) return;
   const int64_t aplane = pad16(int64_t(M) * r);
   const int64_t nxy = dims.nx * dims.ny;
   T* base = F + fidx(dims, d.var, d.t0, d.z0, d.y0, d.x0);
   const int64_t tstride = dims.nz * nxy;
   const bool vec = d.vec != 0;
-  for (int ps0 = threadIdx.x * PPT; ps0 < it.np; ps0 += blockDim.x * PPT) {
+  for (int ps0 = tl * PPT; ps0 < it.np; ps0 += LANES * PPT) {
     const int valid = (it.np - ps0) < PPT ? (it.np - ps0) : PPT;
     const bool full = vec && valid == PPT;
     const int p = it.p0 + ps0;
@@ -550,9 +561,15 @@ template <int WP, typename T, int RMAX>
 void decode_launch(const dim3& g, const dim3& bl, hipStream_t s, void* F, const Dims& dims,
                           const BlockDesc* desc, const Item* items, const int32_t* list, const uint8_t* rank,
                           const int64_t* qv_off, const int64_t* qa_off, const int64_t* code_off, const VarConst* vc,
-                          const uint8_t* qv, const uint8_t* qa, const uint8_t* codes) {
-  hipLaunchKernelGGL((k_decode<WP, T, RMAX>), g, bl, 0, s, (T*)F, dims, desc, items, list, rank, qv_off, qa_off,
-                     code_off, vc, qv, qa, codes);
+                          const uint8_t* qv, const uint8_t* qa, const uint8_t* codes, int64_t count, bool team) {
+  if (team) {
+    const dim3 gt{unsigned((count + 15) / 16)};
+    hipLaunchKernelGGL((k_decode<WP, T, RMAX, 16>), gt, dim3{256}, 0, s, (T*)F, dims, desc, items, list, rank,
+                       qv_off, qa_off, code_off, vc, qv, qa, codes, count);
+  } else {
+    hipLaunchKernelGGL((k_decode<WP, T, RMAX, 0>), g, bl, 0, s, (T*)F, dims, desc, items, list, rank, qv_off,
+                       qa_off, code_off, vc, qv, qa, codes, count);
+  }
 }
 
 #if DLS_CODEC_PART == 3
@@ -934,10 +951,13 @@ hipError_t DLS_CODEC_FN(decode_part)(int rc, const dim3& g, const dim3& bl, hipS
                                      const Dims& dims, const BlockDesc* desc, const Item* items,
                                      const int32_t* list, const uint8_t* rank, const int64_t* qv_off,
                                      const int64_t* qa_off, const int64_t* code_off, const VarConst* vc,
-                                     const uint8_t* qv, const uint8_t* qa, const uint8_t* codes) {
+                                     const uint8_t* qv, const uint8_t* qa, const uint8_t* codes, int64_t count,
+                                     bool team) {
   using T = DLS_CODEC_T;
   constexpr int WP = DLS_CODEC_WP;
-#define DLS_DEC(R) decode_launch<WP, T, R>(g, bl, s, F, dims, desc, items, list, rank, qv_off, qa_off, code_off, vc, qv, qa, codes)
+#define DLS_DEC(R)                                                                                                 \
+  decode_launch<WP, T, R>(g, bl, s, F, dims, desc, items, list, rank, qv_off, qa_off, code_off, vc, qv, qa, codes, \
+                          count, team)
   switch (rc) {
     case 0: DLS_DEC(1); break;
     case 1: DLS_DEC(2); break;

@@ -72,7 +72,8 @@ int encode_small_limit(int wp, int dtype);
   hipError_t decode_part_##TAG(int rc, const dim3& g, const dim3& bl, hipStream_t s, void* F, const Dims& dims,   \
                                const BlockDesc* desc, const Item* items, const int32_t* list, const uint8_t* rank, \
                                const int64_t* qv_off, const int64_t* qa_off, const int64_t* code_off,           \
-                               const VarConst* vc, const uint8_t* qv, const uint8_t* qa, const uint8_t* codes);
+                               const VarConst* vc, const uint8_t* qv, const uint8_t* qa, const uint8_t* codes,  \
+                               int64_t count, bool team);
 DLS_CODEC_DECL(w16_f32)
 DLS_CODEC_DECL(w16_f64)
 DLS_CODEC_DECL(w32_f32)

@@ -928,9 +928,10 @@ static hipError_t decode_dispatch(int wp, int dtype, int rc, const dim3& g, cons
                                   const Dims& dims, const BlockDesc* desc, const Item* items, const int32_t* list,
                                   const uint8_t* rank, const int64_t* qv_off, const int64_t* qa_off,
                                   const int64_t* code_off, const VarConst* vc, const uint8_t* qv, const uint8_t* qa,
-                                  const uint8_t* codes) {
-#define DLS_DEC_PART(TAG) \
-  decode_part_##TAG(rc, g, bl, s, F, dims, desc, items, list, rank, qv_off, qa_off, code_off, vc, qv, qa, codes)
+                                  const uint8_t* codes, int64_t count = 0, bool team = false) {
+#define DLS_DEC_PART(TAG)                                                                                        \
+  decode_part_##TAG(rc, g, bl, s, F, dims, desc, items, list, rank, qv_off, qa_off, code_off, vc, qv, qa, codes, \
+                    count, team)
   if (wp == 16 && dtype == 0) return DLS_DEC_PART(w16_f32);
   if (wp == 16) return DLS_DEC_PART(w16_f64);
   if (dtype == 0) return DLS_DEC_PART(w32_f32);
@@ -953,8 +954,12 @@ hipError_t launch_decode_class(int wp, int dtype, int rc, bool small, const int3
                                const VarConst* vc, const uint8_t* qv, const uint8_t* qa, const uint8_t* codes,
                                hipStream_t s) {
   if (count == 0) return hipSuccess;
+  // small slices: 16-lane teams, sixteen slices per workgroup, where a team
+  // covers the class's slices in one pass (FP32 at W <= 16: 64 points), as
+  // the encode does; otherwise one wave per small slice
+  const bool team = small && wp == 16 && dtype == 0;
   return decode_dispatch(wp, dtype, rc, dim3{unsigned(count)}, dim3{small ? 64u : 256u}, s, F, dims, desc, items,
-                         list, rank, qv_off, qa_off, code_off, vc, qv, qa, codes);
+                         list, rank, qv_off, qa_off, code_off, vc, qv, qa, codes, count, team);
 }
 
 hipError_t launch_scatter_keys(int dtype, void* F, const Dims& dims, const BlockDesc* desc, const uint64_t* key,

@@ -90,3 +90,26 @@ def test_device_decode_refuses_a_short_buffer():
     assert bool((small == 0).all())
     with pytest.raises(ValueError):
         enc.decode(small)
+
+
+@pytest.mark.parametrize("name", ["adaptive_quad_f32_96x80x20", "blobs_f32_96x64x20"])
+def test_device_decode_batched_small_slices(name):
+    """The batched form (DLS_PERSISTENT) puts slices of at most 64 points in
+    small-slice classes, which the device decode runs in 16-lane teams: the
+    result equals the oracle's decoder on the stream, bit for bit, on two
+    calls in a row (the second replays the captured encode)."""
+    print("batched decode", name, flush=True)
+    f, p = _case(name)
+    lp = H.to_lib_params(p)
+    lp.persistent = True
+    t = torch.from_numpy(f).cuda()
+    enc = dls.Encoder()
+    for call in range(2):
+        enc.encode(t, lp)
+        out = torch.full_like(t, float("nan"))
+        enc.decode(out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        stream = enc.finalize()
+        assert np.array_equal(got.view(np.uint8), odls.decompress(stream).view(np.uint8)), call
+        assert np.all(np.abs(got.astype(np.float64) - f.astype(np.float64)) <= np.array(p.eps)[:, None, None, None, None])

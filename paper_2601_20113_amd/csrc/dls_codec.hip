@@ -262,40 +262,51 @@ __device__ __forceinline__ void encode_values(int tid, const Item& it, int b, co
     }
   }
 
-  // lattice reconstruction (exact in FP64) and residual codes
+  // lattice reconstruction (exact in FP64) and residual codes; the per-value
+  // work is branch-free (selects), one rarely taken branch per step records
+  // that step's escapes
+  double qd[RMAX][PPT];
+#pragma unroll
+  for (int k = 0; k < RMAX; ++k)
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) qd[k][e] = double(qa[k][e]);
 #pragma unroll
   for (int t = 0; t < WP; ++t) {
     if (t >= W) continue;
     uint32_t cd[PPT];
+    bool esc_pt[PPT];
+    bool any = false;
 #pragma unroll
     for (int e = 0; e < PPT; ++e) {
       double S = 0.0;
 #pragma unroll
       for (int k = 0; k < RMAX; ++k)
-        if (k < r) S = fma(Qv[t][k], double(qa[k][e]), S);
+        if (k < r) S = fma(Qv[t][k], qd[k][e], S);
       const double xv = double(x[t][e]);
       const double xhat = S * K.c;
       const double dlt = xv - xhat;
-      double q = rint(dlt * K.inv2eps);
-      bool esc_pt = fabs(q) > double(kQLimit);
-      if (esc_pt) q = 0.0;
-      const double n = S + q * 131072.0;
+      const double q0 = rint(dlt * K.inv2eps);
+      const bool big = fabs(q0) > double(kQLimit);
+      const double q = big ? 0.0 : q0;
+      const double n = fma(q, 131072.0, S);  // q 2^17 is exact: S + q 2^17 rounded once
       const T outv = T(n * K.c);
-      esc_pt = esc_pt || (fabs(xv - double(outv)) > K.eps);
-      uint32_t code = kEscCode;
-      if (!esc_pt) {
-        const int32_t qi = int32_t(q);
-        code = uint32_t((qi << 1) ^ (qi >> 31));  // zigzag, <= 254
-      } else if (e < valid) {
+      esc_pt[e] = big || (fabs(xv - double(outv)) > K.eps);
+      const int32_t qi = int32_t(q);
+      cd[e] = esc_pt[e] ? uint32_t(kEscCode) : uint32_t((qi << 1) ^ (qi >> 31));  // zigzag, <= 254
+      any = any || (esc_pt[e] && e < valid);
+    }
+    store_bytes<PPT>(codes + code_at + int64_t(t) * M, cd, valid, vec);
+    if (any) {
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) {
+        if (!esc_pt[e] || e >= valid) continue;
         const unsigned long long slot = atomicAdd(esc.count, 1ULL);
         if (slot < esc.cap) {
           esc.key[slot] = key_mark | (uint64_t(b) << 32) | uint64_t(uint32_t(t * M + p + e));
           esc.val[slot] = bits_of<T>(x[t][e]);
         }
       }
-      cd[e] = code;
     }
-    store_bytes<PPT>(codes + code_at + int64_t(t) * M, cd, valid, vec);
   }
 }
 

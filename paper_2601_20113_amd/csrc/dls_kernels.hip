@@ -26,10 +26,13 @@
 
 // steps of a Jacobi sweep unrolled per loop iteration: the position
 // rotation after each step is a register permutation, which unrolling turns
-// into renaming for all but every third step (measured at W = 16: 6 %
-// faster than no unrolling; 5 is no better)
+// into renaming.  With the partner row read pair by pair and four waves per
+// SIMD (128 registers), one step per iteration is as fast as three or five
+// at three waves (W = 16, 247 583 quadtree blocks: 3.11 / 3.17 / 3.15 ms);
+// the kernel is bound by its LDS traffic and per-step latency, not by the
+// few register moves.
 #ifndef DLS_JACOBI_UNROLL
-#define DLS_JACOBI_UNROLL 3
+#define DLS_JACOBI_UNROLL 1
 #endif
 
 namespace dls {
@@ -355,7 +358,7 @@ __device__ __forceinline__ bool jacobi_converged(const double (&a)[WP], int i) {
 }
 
 template <int WP>
-__global__ __launch_bounds__(256) void k_eigen(const double* __restrict__ gpart,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WP == 16 ? 4 : 1, 8))) void k_eigen(const double* __restrict__ gpart,
                                                const int32_t* __restrict__ item_start,
                                                const BlockDesc* __restrict__ desc, int64_t nblocks,
                                                const double* __restrict__ eps_v, int r_max,
@@ -373,8 +376,7 @@ __global__ __launch_bounds__(256) void k_eigen(const double* __restrict__ gpart,
   __shared__ double sA[GPW][WP * LD];
   // one (c, s) per position pair, kept at its lower position k < WP / 2
   __shared__ double2 sCS[GPW][WP / 2];
-  __shared__ double sLam[GPW][WP], sSg[GPW][WP];
-  __shared__ int sPerm[GPW][WP];
+  __shared__ double sLam[GPW][WP];
   const int grp = threadIdx.x / WP, i = threadIdx.x % WP;
   // every block, or (list != NULL) the blocks of the device-written list
   const int64_t li = int64_t(blockIdx.x) * GPW + grp;
@@ -382,6 +384,10 @@ __global__ __launch_bounds__(256) void k_eigen(const double* __restrict__ gpart,
   const int64_t b = list ? int64_t(list[li]) : li;
   double* A = sA[grp];
   double2* CS = sCS[grp];
+  // after the sweeps: the sort permutation in the rotation slots (WP ints
+  // in WP / 2 double2) and the column signs in the pad column of A, so that
+  // four workgroups of W = 16 fit in one compute unit's LDS
+  int* Perm = reinterpret_cast<int*>(CS);
   const BlockDesc d = desc[b];
   const int W = d.w(), M = d.m;
   const int i0 = item_start[b], i1 = item_start[b + 1];
@@ -424,6 +430,12 @@ __global__ __launch_bounds__(256) void k_eigen(const double* __restrict__ gpart,
   // test after the loop costs W = 32 a wave of occupancy)
   int sweep = 0;
   bool converged = false;
+  // round-robin state of this lane, advanced step by step (it returns to
+  // its start after the WP - 1 steps of a sweep): its position, and mm with
+  // partner m = mm + 1 (player 0 when the lane sits at position WP - 1)
+  int pos = rr_slot(i, 0, WP);
+  const int inc = i == 0 ? 1 : 2;
+  int mm = i == 0 ? WP - 2 : (WP - 2 - i) % (WP - 1);
   for (; sweep < max_sweeps; ++sweep) {
     if (jacobi_converged<WP>(a, i)) {
       converged = true;
@@ -437,9 +449,8 @@ __global__ __launch_bounds__(256) void k_eigen(const double* __restrict__ gpart,
 #pragma unroll
       for (int k = 0; k < WP; ++k) A[i * LD + k] = a[k];
       wave_sync();
-      const int pos = rr_slot(i, step, WP);
       const int mpos = WP - 1 - pos;
-      const int m = rr_player(mpos, step, WP);
+      const int m = pos == WP - 1 ? 0 : mm + 1;  // rr_player(mpos, step, WP)
       if (i < m) {
         double c, s;
         jacobi_rotation(A[i * LD + pos], A[m * LD + mpos], A[i * LD + mpos], c, s);
@@ -450,16 +461,14 @@ __global__ __launch_bounds__(256) void k_eigen(const double* __restrict__ gpart,
       wave_sync();
       double2 ci = CS[pos < mpos ? pos : mpos];
       if (pos > mpos) ci.y = -ci.y;
-      double pm[WP];
-#pragma unroll
-      for (int k = 0; k < WP; ++k) pm[k] = A[m * LD + k];
 #pragma unroll
       for (int k = 0; k < WP / 2; ++k) {
         const int mk = WP - 1 - k;
+        const double pk = A[m * LD + k], pmk = A[m * LD + mk];  // the partner's row, pair by pair
         const double2 ck = CS[k], cm = make_double2(ck.x, -ck.y);
         // row rotation (own row with the partner's), then column rotation
-        const double rk = fma(ci.x, a[k], ci.y * pm[k]);
-        const double rm = fma(ci.x, a[mk], ci.y * pm[mk]);
+        const double rk = fma(ci.x, a[k], ci.y * pk);
+        const double rm = fma(ci.x, a[mk], ci.y * pmk);
         a[k] = fma(ck.x, rk, ck.y * rm);
         a[mk] = fma(cm.x, rm, cm.y * rk);
         const double vk = fma(ck.x, v[k], ck.y * v[mk]);
@@ -477,6 +486,9 @@ __global__ __launch_bounds__(256) void k_eigen(const double* __restrict__ gpart,
       }
       a[WP - 1] = a1;
       v[WP - 1] = v1;
+      pos = i == 0 ? 0 : (pos == 1 ? WP - 1 : pos - 1);
+      mm += inc;
+      mm -= mm >= WP - 1 ? WP - 1 : 0;
       wave_sync();
     }
   }
@@ -499,12 +511,12 @@ __global__ __launch_bounds__(256) void k_eigen(const double* __restrict__ gpart,
       const double dj = sLam[grp][j];
       pos += (dj > dk || (dj == dk && j < i)) ? 1 : 0;
     }
-    sPerm[grp][pos] = i;
+    Perm[pos] = i;
   }
   wave_sync();
   // sorted column i: its eigenvalue and canonical sign (largest |component|
   // positive, lowest row on a tie)
-  const int col = sPerm[grp][i];
+  const int col = Perm[i];
   const double lam = fmax(i < W ? sLam[grp][col] : 0.0, 0.0);
   {
     double best = -1.0, sg = 1.0;
@@ -512,13 +524,13 @@ __global__ __launch_bounds__(256) void k_eigen(const double* __restrict__ gpart,
       const double x = A[t * LD + col];
       if (fabs(x) > best) { best = fabs(x); sg = x < 0.0 ? -1.0 : 1.0; }
     }
-    sSg[grp][i] = sg;
+    A[i * LD + WP] = sg;  // the sign of sorted column i, in row i's pad entry
   }
   wave_sync();
   sLam[grp][i] = lam;
   lam_out[b * WP + i] = lam;
 #pragma unroll 4
-  for (int k = 0; k < WP; ++k) basis_out[(b * WP + k) * WP + i] = sSg[grp][k] * A[i * LD + sPerm[grp][k]];
+  for (int k = 0; k < WP; ++k) basis_out[(b * WP + k) * WP + i] = A[k * LD + WP] * A[i * LD + Perm[k]];
   wave_sync();
   if (i == 0) {
     const double eps = eps_v[d.var];

@@ -232,8 +232,29 @@ __global__ __launch_bounds__(256) void k_l2_params(const BlockDesc* __restrict__
   }
 }
 
-// One workgroup per slice, one thread per point (256 threads, up to four
-// points each).  RMAX: the rank class of the launch.
+// PPT consecutive points of one time row as one aligned vector load (the
+// run is contiguous and aligned: a block whose patch rows are 16-byte
+// aligned runs of 4k values, the run starting at a multiple of PPT).
+template <typename T, int PPT>
+__device__ __forceinline__ void l2_load_run(const T* __restrict__ src, T (&v)[PPT]) {
+  if constexpr (sizeof(T) == 4 && PPT == 4) {
+    const float4 a = *reinterpret_cast<const float4*>(src);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  } else if constexpr (sizeof(T) == 4 && PPT == 2) {
+    const float2 a = *reinterpret_cast<const float2*>(src);
+    v[0] = a.x; v[1] = a.y;
+  } else if constexpr (sizeof(T) == 8 && PPT == 2) {
+    const double2 a = *reinterpret_cast<const double2*>(src);
+    v[0] = a.x; v[1] = a.y;
+  } else {
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) v[e] = src[e];
+  }
+}
+
+// One workgroup per slice; each thread takes PPT consecutive points (every
+// step's values of all of them loaded before the first use, so a slice is
+// one round of loads), then encodes them one after the other.
 template <int WP, typename T>
 __global__ __launch_bounds__(256) void k_l2_encode(const T* __restrict__ F, Dims dims,
                                                    const BlockDesc* __restrict__ desc,
@@ -245,6 +266,9 @@ __global__ __launch_bounds__(256) void k_l2_encode(const T* __restrict__ F, Dims
                                                    const int64_t* __restrict__ qa_off, uint8_t* __restrict__ qv_buf,
                                                    uint8_t* __restrict__ qa_buf, uint8_t* __restrict__ overflow,
                                                    double* __restrict__ errp) {
+  // four points per thread for W = 16 FP32 (16 float4 loads in flight); one
+  // otherwise, where more would not fit the registers of W rows
+  constexpr int PPT = (WP == 16 && sizeof(T) == 4) ? 4 : 1;
   __shared__ double Vs[WP][WP];   // FP64 basis, [k][t]
   __shared__ double Vq[WP][WP];   // quantized basis qV 2^-24, [k][t]
   __shared__ double red[256];
@@ -274,58 +298,84 @@ __global__ __launch_bounds__(256) void k_l2_encode(const T* __restrict__ F, Dims
   const T* base = F + fidx(dims, d.var, d.t0, d.z0, d.y0, d.x0);
   const int64_t nxy = dims.nx * dims.ny, tstride = dims.nz * nxy;
   double err = 0.0;
-  for (int q = threadIdx.x; q < it.np; q += 256) {
-    const int p = it.p0 + q;
-    const int64_t off = point_off(p, d.px(), d.py(), dims.nx, nxy);
-    // the point's W values, every load issued before the first use
-    T xs[WP];
+  const bool cont = d.vec != 0;
+  for (int pb = PPT * int(threadIdx.x); pb < it.np; pb += 256 * PPT) {
+    const int valid = (it.np - pb) < PPT ? (it.np - pb) : PPT;
+    const bool run = cont && valid == PPT;
+    int64_t offs[PPT];
 #pragma unroll
-    for (int t = 0; t < WP; ++t) xs[t] = t < W ? base[int64_t(t) * tstride + off] : T(0);
-    if (r == kL2Raw) {
-      uint8_t* dst = qa_buf + qa_off[b];
-#pragma unroll
-      for (int t = 0; t < WP; ++t)
-        if (t < W) *reinterpret_cast<T*>(dst + (int64_t(t) * M + p) * int64_t(sizeof(T))) = xs[t];
-      continue;
-    }
-    if (r == 0) {
-#pragma unroll
-      for (int t = 0; t < WP; ++t) {
-        const double x = double(xs[t]);
-        if (t < W) err += x * x;
-      }
-      continue;
-    }
-    // per mode k (in order): the projection, a running FMA over the steps in
-    // order; its quantized coefficient; and its term of the decoder's
-    // values, which sum the modes in order k = 0, 1, ...  (step indices are
-    // compile-time, so xs[] and rec[] stay in registers)
-    double rec[WP];
-#pragma unroll
-    for (int t = 0; t < WP; ++t) rec[t] = 0.0;
-    bool ovf = false;
-    const int64_t plane = pad16(int64_t(M) * r);
-    uint8_t* dst = qa_buf + qa_off[b];
-    for (int k = 0; k < R; ++k) {
-      double a = 0.0;
-#pragma unroll
-      for (int t = 0; t < WP; ++t)
-        if (t < W) a = fma(double(xs[t]), Vs[k][t], a);
-      const double qa = rint(a / dstep);
-      const bool ok = fabs(qa) < 2147483648.0;
-      ovf = ovf || !ok;
-      const int32_t qi = ok ? int32_t(qa) : 0;
-      const double c = double(qi) * dstep;
-      const uint32_t z = zz32(qi);
-      for (int j = 0; j < 4; ++j) dst[j * plane + int64_t(k) * M + p] = uint8_t(z >> (8 * j));
-#pragma unroll
-      for (int t = 0; t < WP; ++t) rec[t] = rec[t] + Vq[k][t] * c;
-    }
-    if (ovf) overflow[b] = 1;
+    for (int e = 0; e < PPT; ++e)
+      offs[e] = point_off(it.p0 + pb + (run ? 0 : (e < valid ? e : 0)), d.px(), d.py(), dims.nx, nxy);
+    // the points' W values, every load issued before the first use
+    T xv[WP][PPT];
 #pragma unroll
     for (int t = 0; t < WP; ++t) {
-      const double e = double(xs[t]) - double(T(rec[t]));
-      if (t < W) err += e * e;
+      if (t < W) {
+        const T* row = base + int64_t(t) * tstride;
+        if (run) {
+          l2_load_run<T, PPT>(row + offs[0], xv[t]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < PPT; ++e) xv[t][e] = e < valid ? row[offs[e]] : T(0);
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < PPT; ++e) xv[t][e] = T(0);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) {
+      if (e >= valid) continue;
+      const int p = it.p0 + pb + e;
+      T xs[WP];
+#pragma unroll
+      for (int t = 0; t < WP; ++t) xs[t] = xv[t][e];
+      if (r == kL2Raw) {
+        uint8_t* dst = qa_buf + qa_off[b];
+#pragma unroll
+        for (int t = 0; t < WP; ++t)
+          if (t < W) *reinterpret_cast<T*>(dst + (int64_t(t) * M + p) * int64_t(sizeof(T))) = xs[t];
+        continue;
+      }
+      if (r == 0) {
+#pragma unroll
+        for (int t = 0; t < WP; ++t) {
+          const double x = double(xs[t]);
+          if (t < W) err += x * x;
+        }
+        continue;
+      }
+      // per mode k (in order): the projection, a running FMA over the steps in
+      // order; its quantized coefficient; and its term of the decoder's
+      // values, which sum the modes in order k = 0, 1, ...  (step indices are
+      // compile-time, so xs[] and rec[] stay in registers)
+      double rec[WP];
+#pragma unroll
+      for (int t = 0; t < WP; ++t) rec[t] = 0.0;
+      bool ovf = false;
+      const int64_t plane = pad16(int64_t(M) * r);
+      uint8_t* dst = qa_buf + qa_off[b];
+      for (int k = 0; k < R; ++k) {
+        double a = 0.0;
+#pragma unroll
+        for (int t = 0; t < WP; ++t)
+          if (t < W) a = fma(double(xs[t]), Vs[k][t], a);
+        const double qa = rint(a / dstep);
+        const bool ok = fabs(qa) < 2147483648.0;
+        ovf = ovf || !ok;
+        const int32_t qi = ok ? int32_t(qa) : 0;
+        const double c = double(qi) * dstep;
+        const uint32_t z = zz32(qi);
+        for (int j = 0; j < 4; ++j) dst[j * plane + int64_t(k) * M + p] = uint8_t(z >> (8 * j));
+#pragma unroll
+        for (int t = 0; t < WP; ++t) rec[t] = rec[t] + Vq[k][t] * c;
+      }
+      if (ovf) overflow[b] = 1;
+#pragma unroll
+      for (int t = 0; t < WP; ++t) {
+        const double dx = double(xs[t]) - double(T(rec[t]));
+        if (t < W) err += dx * dx;
+      }
     }
   }
   red[threadIdx.x] = err;

@@ -650,30 +650,20 @@ __global__ __launch_bounds__(256) void k_gb_patch64(const T* __restrict__ F, Dim
     double a = 0.0;
     if (lane < M)
       for (int k = 0; k < M; ++k) a = fma(double(phi[k * ld + lane]), xs[wave][k], a);
-    // magnitude order: (|alpha| desc, index asc); lanes >= M sort last
-    double key = lane < M ? fabs(a) : -1.0;
-    int idx = lane;
-    double av = a;
-    for (int size = 2; size <= 64; size <<= 1) {
-      for (int stride = size >> 1; stride > 0; stride >>= 1) {
-        const double ko = __shfl_xor(key, stride, 64);
-        const int io = __shfl_xor(idx, stride, 64);
-        const double ao = __shfl_xor(av, stride, 64);
-        const bool lower = (lane & stride) == 0;
-        const bool self_first = key > ko || (key == ko && idx < io);
-        const bool desc_dir = (lane & size) == 0;
-        // the lower lane of a pair keeps the element that comes first in
-        // this segment's direction
-        const bool keep = (lower == desc_dir) ? self_first : !self_first;
-        if (!keep) {
-          key = ko;
-          idx = io;
-          av = ao;
-        }
-      }
+    // magnitude order (|alpha| desc, index asc; lanes >= M last): every
+    // lane counts the keys that precede its own, which is its position in
+    // that total order, and places its coefficient there
+    const double key = lane < M ? fabs(a) : -1.0;
+    tq[wave][lane] = key;
+    wave_sync();
+    int rank = 0;
+#pragma unroll 8
+    for (int j = 0; j < 64; ++j) {
+      const double kj = tq[wave][j];
+      rank += (kj > key || (kj == key && j < lane)) ? 1 : 0;
     }
-    pos_s[wave][idx] = lane;  // sorted position of basis index idx
-    sa[wave][lane] = av;
+    pos_s[wave][lane] = rank;  // sorted position of basis index lane
+    sa[wave][rank] = a;
     wave_sync();
     // the energy rule: tail from the end, the same recurrence in every lane,
     // eight sorted values loaded ahead of their additions

@@ -331,10 +331,25 @@ __device__ __forceinline__ void quad_load(const float* __restrict__ f0, int64_t 
   in.zp = *reinterpret_cast<const float4*>(row(zp, y) + x);
 }
 
+// The same loads for a row interior in y and z (or of a 2D snapshot, sz =
+// 0): the neighbour rows at fixed strides from the quad's row rp, so the
+// addresses equal the clamped ones of quad_load.
+__device__ __forceinline__ void quad_load_in(const float* __restrict__ rp, int64_t nx, int64_t sy, int64_t sz,
+                                             int64_t x, QuadIn& in) {
+  in.c = *reinterpret_cast<const float4*>(rp + x);
+  in.l = rp[x > 0 ? x - 1 : x];
+  in.r = rp[x + 4 < nx ? x + 4 : x + 3];
+  in.ym = *reinterpret_cast<const float4*>(rp - sy + x);
+  in.yp = *reinterpret_cast<const float4*>(rp + sy + x);
+  in.zm = *reinterpret_cast<const float4*>(rp - sz + x);
+  in.zp = *reinterpret_cast<const float4*>(rp + sz + x);
+}
+
 // squared gradient magnitudes s = dx^2 + dy^2 + dz^2 of the quad, with the
 // arithmetic of grad_mag / k_gradient4: sqrt(s) is bitwise their g, and the
 // order statistics of g are the square roots of those of s (a correctly
 // rounded square root is monotone), so the selection never takes a root
+template <bool IN = false>
 __device__ __forceinline__ void quad_sq(const QuadIn& in, int64_t nx, int64_t ny, int64_t nz, int64_t x, int64_t y,
                                         int64_t z, double (&g)[4]) {
   // each difference as (a - b) * h: the central difference (h = 1/2) inside,
@@ -351,13 +366,13 @@ __device__ __forceinline__ void quad_sq(const QuadIn& in, int64_t nx, int64_t ny
     dx[3] = ((hi ? v[3] : r) - v[2]) * (hi ? 1.0 : 0.5);
   }
   if (ny > 1) {
-    const bool lo = y == 0, hi = y == ny - 1;
+    const bool lo = !IN && y == 0, hi = !IN && y == ny - 1;
     const double h = (lo || hi) ? 1.0 : 0.5;
     const double a[4] = {in.yp.x, in.yp.y, in.yp.z, in.yp.w}, b[4] = {in.ym.x, in.ym.y, in.ym.z, in.ym.w};
     for (int e = 0; e < 4; ++e) dy[e] = ((hi ? v[e] : a[e]) - (lo ? v[e] : b[e])) * h;
   }
   if (nz > 1) {
-    const bool lo = z == 0, hi = z == nz - 1;
+    const bool lo = !IN && z == 0, hi = !IN && z == nz - 1;
     const double h = (lo || hi) ? 1.0 : 0.5;
     const double a[4] = {in.zp.x, in.zp.y, in.zp.z, in.zp.w}, b[4] = {in.zm.x, in.zm.y, in.zm.z, in.zm.w};
     for (int e = 0; e < 4; ++e) dz[e] = ((hi ? v[e] : a[e]) - (lo ? v[e] : b[e])) * h;
@@ -395,6 +410,72 @@ struct PassGeom {
   int64_t nchunk, NXf, NYf, NZf;   // x chunks; finest node grid
 };
 
+// The quads of one pass-0 workgroup: item idx = row * nq + q (row = z * ry
+// + y within the chunk), 256 items per step, U steps' loads issued
+// together.  A thread's (q, row) and (y, z) advance by fixed increments
+// (no division per quad).
+template <bool IN>
+__device__ __forceinline__ void pass0_quads(const float* __restrict__ f0, const PassGeom& G, int64_t x0, int64_t y0,
+                                            int64_t z0, int ry, int nq, int nitem, double* __restrict__ qs,
+                                            unsigned int* __restrict__ h, uint32_t* __restrict__ tv) {
+  constexpr int U = 2;  // quads per thread whose loads are issued together
+  const int dq = 256 % nq, drow = 256 / nq, drm = drow % ry, drz = drow / ry;
+  const int64_t sy = G.nx, sz = G.nz > 1 ? G.nx * G.ny : 0;
+  int q = int(threadIdx.x) % nq, row = int(threadIdx.x) / nq;
+  int ym = row % ry, zq = row / ry;
+  for (int base = 0; base < nitem; base += 256 * U) {
+    QuadIn in[U];
+    int64_t qx[U], qy[U], qz[U], ro[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = base + 256 * u + int(threadIdx.x);
+      qx[u] = x0 + 4 * q;
+      qy[u] = y0 + ym;
+      qz[u] = z0 + zq;
+      ro[u] = (qz[u] * G.ny + qy[u]) * G.nx;  // the quad's row
+      if (idx < nitem) {
+        if constexpr (IN) quad_load_in(f0 + ro[u], G.nx, sy, sz, qx[u], in[u]);
+        else quad_load(f0, G.nx, G.ny, G.nz, qx[u], qy[u], qz[u], in[u]);
+      }
+      // the next item of this thread: idx + 256
+      q += dq;
+      const int c = q >= nq ? 1 : 0;
+      q -= c ? nq : 0;
+      ym += drm + c;
+      zq += drz;
+      if (ym >= ry) {
+        ym -= ry;
+        ++zq;
+      }
+    }
+    // exponent digits counted in runs (neighbouring points share them), one
+    // LDS atomic per run
+    uint32_t run_d = 0xFFFFFFFFu, run_n = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = base + 256 * u + int(threadIdx.x);
+      if (idx >= nitem) continue;
+      double sq[4];
+      quad_sq<IN>(in[u], G.nx, G.ny, G.nz, qx[u], qy[u], qz[u], sq);
+      qs[idx] = ((sqrt(sq[0]) + sqrt(sq[1])) + sqrt(sq[2])) + sqrt(sq[3]);
+      uint32_t hi[4];
+      for (int e = 0; e < 4; ++e) {
+        const uint64_t b = uint64_t(__double_as_longlong(sq[e]));
+        hi[e] = uint32_t(b >> 32);
+        const uint32_t d = uint32_t(b >> 52);
+        if (d != run_d) {
+          if (run_n) atomicAdd(&h[run_d], run_n);
+          run_d = d;
+          run_n = 0;
+        }
+        ++run_n;
+      }
+      *reinterpret_cast<uint4*>(tv + ro[u] + qx[u]) = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+    }
+    if (run_n) atomicAdd(&h[run_d], run_n);
+  }
+}
+
 // Pass 0, one workgroup per (x chunk, finest node row in y, in z) of one
 // variable: the squared gradient s of every point, the finest-level node
 // sums of g = sqrt(s), the histogram of bits 52..63 of s, and the high 32
@@ -417,45 +498,11 @@ __global__ __launch_bounds__(256) void k_plan_pass0(const float* __restrict__ F,
   const int nq = xw / 4, R = ry * rz, nitem = R * nq;
   for (int j = threadIdx.x; j < 4096; j += 256) h[j] = 0;
   __syncthreads();
-  constexpr int U = 2;  // quads per thread whose loads are issued together
-  for (int base = 0; base < nitem; base += 256 * U) {
-    QuadIn in[U];
-    int64_t qx[U], qy[U], qz[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int idx = base + 256 * u + int(threadIdx.x);
-      const int row = idx < nitem ? idx / nq : 0, q = idx < nitem ? idx - row * nq : 0;
-      qx[u] = x0 + 4 * q;
-      qy[u] = y0 + row % ry;
-      qz[u] = z0 + row / ry;
-      if (idx < nitem) quad_load(f0, G.nx, G.ny, G.nz, qx[u], qy[u], qz[u], in[u]);
-    }
-    // exponent digits counted in runs (neighbouring points share them), one
-    // LDS atomic per run
-    uint32_t run_d = 0xFFFFFFFFu, run_n = 0;
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int idx = base + 256 * u + int(threadIdx.x);
-      if (idx >= nitem) continue;
-      double sq[4];
-      quad_sq(in[u], G.nx, G.ny, G.nz, qx[u], qy[u], qz[u], sq);
-      qs[idx] = ((sqrt(sq[0]) + sqrt(sq[1])) + sqrt(sq[2])) + sqrt(sq[3]);
-      uint32_t hi[4];
-      for (int e = 0; e < 4; ++e) {
-        const uint64_t b = uint64_t(__double_as_longlong(sq[e]));
-        hi[e] = uint32_t(b >> 32);
-        const uint32_t d = uint32_t(b >> 52);
-        if (d != run_d) {
-          if (run_n) atomicAdd(&h[run_d], run_n);
-          run_d = d;
-          run_n = 0;
-        }
-        ++run_n;
-      }
-      *reinterpret_cast<uint4*>(tv + (qz[u] * G.ny + qy[u]) * G.nx + qx[u]) = make_uint4(hi[0], hi[1], hi[2], hi[3]);
-    }
-    if (run_n) atomicAdd(&h[run_d], run_n);
-  }
+  // every row of the workgroup interior in y and z (or a 2D snapshot): no
+  // boundary differences and no clamped neighbour rows
+  const bool interior = G.ny > 2 && y0 > 0 && y0 + ry < G.ny && (G.nz == 1 || (z0 > 0 && z0 + rz < G.nz));
+  if (interior) pass0_quads<true>(f0, G, x0, y0, z0, ry, nq, nitem, qs, h, tv);
+  else pass0_quads<false>(f0, G, x0, y0, z0, ry, nq, nitem, qs, h, tv);
   __syncthreads();
   unsigned int* gh = hist + int64_t(v) * 4096;
   for (int j = threadIdx.x; j < 4096; j += 256)

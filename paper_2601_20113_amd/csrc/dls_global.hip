@@ -598,46 +598,54 @@ __global__ __launch_bounds__(256) void k_gb_select(const T* __restrict__ F, Dims
   }
 }
 
-// Patches of at most 64 points: one wave per patch-snapshot, no barriers
-// after the basis is staged.  One launch per variable: the workgroup copies
-// the variable's Phi into LDS once (rows padded to M + 1 doubles, so both
-// the row reads of the coefficients and the column reads of the decoder
-// are conflict-free) and its four waves walk the patches [nb0, nb1) with a
-// grid stride.  Lane i holds point i (zero-padded), then coefficient
-// alpha_i = sum_k Phi[k][i] u_k (points broadcast from LDS in order, FP64
-// FMA), then the i-th entry of the magnitude order (bitonic exchange across
-// lanes); the energy rule runs as the sequential recurrence over the sorted
-// values (broadcast from LDS); the kept set is a ballot over basis
-// indices, its ascending list positions come from the lanes below; the
-// decoder's values are summed over the kept indices in ascending order.
-// Same slot layout as k_gb_select.
-template <typename T>
+// Patches of at most S points (S = 64, 32 or 16): one team of S lanes per
+// patch-snapshot, 64 / S teams per wave, no barriers after the basis is
+// staged.  One launch per variable: the workgroup copies the variable's Phi
+// into LDS once (rows padded to M + 1, so both the row reads of the
+// coefficients and the column reads of the decoder are conflict-free) and
+// its teams walk the patches [nb0, nb1) with a grid stride.  Team lane i
+// holds point i (zero-padded), then coefficient alpha_i = sum_k Phi[k][i]
+// u_k (points broadcast from LDS in order, FP64 FMA), then its position in
+// the magnitude order (|alpha| descending, index ascending: the number of
+// keys before its own), where it writes its coefficient; the energy rule
+// runs as the sequential recurrence over the sorted values (broadcast from
+// LDS); the kept set is a ballot over basis indices, its ascending list
+// positions come from the lanes below; the decoder's values are summed over
+// the kept indices in ascending order.  Every cross-lane step is confined
+// to the team (ballots masked to its lanes, sums over its lanes), and every
+// branch that leaves a loop is taken by a whole team.  Same slot layout as
+// k_gb_select.
+template <typename T, int S>
 __global__ __launch_bounds__(256) void k_gb_patch64(const T* __restrict__ F, Dims dims,
                                                     const BlockDesc* __restrict__ desc, int64_t nb0, int64_t nb1,
                                                     const double* __restrict__ phi_g, const double* __restrict__ cv,
                                                     int px, int py, int M, int32_t* __restrict__ count,
                                                     int32_t* __restrict__ kexp, uint8_t* __restrict__ slot,
                                                     int32_t* __restrict__ n0_out) {
+  constexpr int NTM = 64 / S;  // teams per wave
   // the basis values are k 2^-24 with |k| <= 2^24, exact in FP32
-  __shared__ float phi[64 * 65];
+  __shared__ float phi[S * (S + 1)];
   __shared__ double xs[4][64], sa[4][64], tq[4][64];
-  __shared__ int pos_s[4][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tb = S == 64 ? 0 : lane & ~(S - 1), tl = lane - tb;  // team's first lane, lane in the team
+  const unsigned long long tmask = (S == 64 ? ~0ull : ((1ull << S) - 1ull)) << tb;
   const int ld = M + 1;
   for (int e = threadIdx.x; e < M * M; e += 256) phi[(e / M) * ld + e % M] = float(phi_g[e]);
   __syncthreads();
-  for (int64_t b = nb0 + int64_t(blockIdx.x) * 4 + wave; b < nb1; b += int64_t(gridDim.x) * 4) {
+  for (int64_t b0 = nb0 + (int64_t(blockIdx.x) * 4 + wave) * NTM; b0 < nb1; b0 += int64_t(gridDim.x) * 4 * NTM) {
+    const int64_t b = b0 + tb / S;
+    if (b >= nb1) continue;  // a whole team (the wave's last teams)
     const BlockDesc d = desc[b];
     const double e2 = cv[d.var] * double(d.m);
     bool in = false;
-    const double x = lane < M ? gb_point(F, dims, d, px, py, lane, in) : 0.0;
+    const double x = tl < M ? gb_point(F, dims, d, px, py, tl, in) : 0.0;
     uint8_t* out = slot + b * int64_t(8) * M;
-    if (__any(in && !isfinite(x))) {
-      if (lane < d.m) {
-        const int ix = lane % d.px(), jy = (lane / d.px()) % d.py(), kz = lane / (d.px() * d.py());
-        reinterpret_cast<T*>(out)[lane] = F[fidx(dims, d.var, d.t0, d.z0 + kz, d.y0 + jy, d.x0 + ix)];
+    if ((__ballot(in && !isfinite(x)) & tmask) != 0) {
+      if (tl < d.m) {
+        const int ix = tl % d.px(), jy = (tl / d.px()) % d.py(), kz = tl / (d.px() * d.py());
+        reinterpret_cast<T*>(out)[tl] = F[fidx(dims, d.var, d.t0, d.z0 + kz, d.y0 + jy, d.x0 + ix)];
       }
-      if (lane == 0) {
+      if (tl == 0) {
         count[b] = kGbRaw;
         kexp[b] = 0;
         n0_out[b] = 0;
@@ -648,25 +656,24 @@ __global__ __launch_bounds__(256) void k_gb_patch64(const T* __restrict__ F, Dim
     wave_sync();
     // coefficients
     double a = 0.0;
-    if (lane < M)
-      for (int k = 0; k < M; ++k) a = fma(double(phi[k * ld + lane]), xs[wave][k], a);
+    if (tl < M)
+      for (int k = 0; k < M; ++k) a = fma(double(phi[k * ld + tl]), xs[wave][tb + k], a);
     // magnitude order (|alpha| desc, index asc; lanes >= M last): every
     // lane counts the keys that precede its own, which is its position in
     // that total order, and places its coefficient there
-    const double key = lane < M ? fabs(a) : -1.0;
+    const double key = tl < M ? fabs(a) : -1.0;
     tq[wave][lane] = key;
     wave_sync();
-    int rank = 0;
+    int mypos = 0;
 #pragma unroll 8
-    for (int j = 0; j < 64; ++j) {
-      const double kj = tq[wave][j];
-      rank += (kj > key || (kj == key && j < lane)) ? 1 : 0;
+    for (int j = 0; j < S; ++j) {
+      const double kj = tq[wave][tb + j];
+      mypos += (kj > key || (kj == key && j < tl)) ? 1 : 0;
     }
-    pos_s[wave][lane] = rank;  // sorted position of basis index lane
-    sa[wave][rank] = a;
+    sa[wave][tb + mypos] = a;
     wave_sync();
-    // the energy rule: tail from the end, the same recurrence in every lane,
-    // eight sorted values loaded ahead of their additions
+    // the energy rule: tail from the end, the same recurrence in every lane
+    // of the team, eight sorted values loaded ahead of their additions
     const double tau = kGbTailShare * e2;
     double t = 0.0;
     int n = 0;
@@ -674,7 +681,7 @@ __global__ __launch_bounds__(256) void k_gb_patch64(const T* __restrict__ F, Dim
     for (int j0 = M - 1; j0 >= 0 && !found; j0 -= 8) {
       double v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = j0 - u >= 0 ? sa[wave][j0 - u] : 0.0;
+      for (int u = 0; u < 8; ++u) v[u] = j0 - u >= 0 ? sa[wave][tb + j0 - u] : 0.0;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         if (found || j0 - u < 0) continue;
@@ -687,13 +694,13 @@ __global__ __launch_bounds__(256) void k_gb_patch64(const T* __restrict__ F, Dim
         }
       }
     }
-    if (lane == 0) n0_out[b] = n;
-    const int mypos = lane < M ? pos_s[wave][lane] : 64;
+    if (tl == 0) n0_out[b] = n;
+    if (tl >= M) mypos = 64;
     bool done = false;
     for (;;) {
       if (n > M || (!(e2 > 0.0) && n > 0)) break;
-      const bool kept = lane < M && mypos < n;
-      const unsigned long long mask = __ballot(kept);
+      const bool kept = tl < M && mypos < n;
+      const unsigned long long mask = __ballot(kept) & tmask;
       double dd = 1.0;
       int kx = 0;
       if (n > 0) {
@@ -703,29 +710,31 @@ __global__ __launch_bounds__(256) void k_gb_patch64(const T* __restrict__ F, Dim
         dd = ldexp(1.0, kx);
       }
       const double qa = rint(a / dd);
-      if (!__all(!kept || fabs(qa) < 2147483648.0)) break;
+      if ((__ballot(kept && !(fabs(qa) < 2147483648.0)) & tmask) != 0) break;
       const int32_t qi = kept ? int32_t(qa) : 0;
       tq[wave][lane] = double(qi) * dd;
       wave_sync();
       // the decoder's values at this lane's point
       double acc = 0.0;
       unsigned long long m = mask;
-      const int row = lane < M ? lane : 0;
+      const int row = tl < M ? tl : 0;
       while (m) {
-        const int s = __ffsll((long long)m) - 1;
+        const int sl = __ffsll((long long)m) - 1;
         m &= m - 1;
-        acc = acc + double(phi[row * ld + s]) * tq[wave][s];
+        acc = acc + double(phi[row * ld + (sl - tb)]) * tq[wave][sl];
       }
       double e = in ? x - double(T(acc)) : 0.0;
-      const double err = wave_sum(e * e);
+      double err = e * e;
+#pragma unroll
+      for (int o = S / 2; o >= 1; o >>= 1) err += __shfl_xor(err, o, 64);
       wave_sync();
       if (err <= e2) {
         if (kept) {
           const int j = __popcll(mask & ((1ull << lane) - 1ull));
-          reinterpret_cast<uint16_t*>(out)[j] = uint16_t(lane);
+          reinterpret_cast<uint16_t*>(out)[j] = uint16_t(tl);
           reinterpret_cast<int32_t*>(out + 4 * int64_t(M))[j] = qi;
         }
-        if (lane == 0) {
+        if (tl == 0) {
           count[b] = n;
           kexp[b] = n > 0 ? kx : 0;
         }
@@ -735,11 +744,11 @@ __global__ __launch_bounds__(256) void k_gb_patch64(const T* __restrict__ F, Dim
       ++n;
     }
     if (!done) {
-      if (lane < d.m) {
-        const int ix = lane % d.px(), jy = (lane / d.px()) % d.py(), kz = lane / (d.px() * d.py());
-        reinterpret_cast<T*>(out)[lane] = F[fidx(dims, d.var, d.t0, d.z0 + kz, d.y0 + jy, d.x0 + ix)];
+      if (tl < d.m) {
+        const int ix = tl % d.px(), jy = (tl / d.px()) % d.py(), kz = tl / (d.px() * d.py());
+        reinterpret_cast<T*>(out)[tl] = F[fidx(dims, d.var, d.t0, d.z0 + kz, d.y0 + jy, d.x0 + ix)];
       }
-      if (lane == 0) {
+      if (tl == 0) {
         count[b] = kGbRaw;
         kexp[b] = 0;
       }
@@ -933,15 +942,21 @@ hipError_t launch_gb_patch64(int dtype, const void* F, const Dims& dims, const B
                              int32_t* kexp, uint8_t* slot, int32_t* n0, hipStream_t s) {
   if (nb1 <= nb0) return hipSuccess;
   if (M > 64) return hipErrorInvalidValue;
-  // enough workgroups to fill the chip several times; each stages Phi once
-  const int64_t want = (nb1 - nb0 + 3) / 4;
+  // teams of S lanes, S the smallest of 16, 32, 64 that holds the patch;
+  // enough workgroups to fill the chip several times (each stages Phi once)
+  const int S = M <= 16 ? 16 : (M <= 32 ? 32 : 64);
+  const int64_t per_wg = 4 * (64 / S);
+  const int64_t want = (nb1 - nb0 + per_wg - 1) / per_wg;
   const dim3 g{unsigned(std::min<int64_t>(want, 8192))};
-  if (dtype == 0)
-    hipLaunchKernelGGL(k_gb_patch64<float>, g, dim3{256}, 0, s, static_cast<const float*>(F), dims, desc, nb0, nb1,
-                       phi, cv, px, py, M, count, kexp, slot, n0);
-  else
-    hipLaunchKernelGGL(k_gb_patch64<double>, g, dim3{256}, 0, s, static_cast<const double*>(F), dims, desc, nb0,
-                       nb1, phi, cv, px, py, M, count, kexp, slot, n0);
+#define DLS_GBP(TV, SV)                                                                                       \
+  hipLaunchKernelGGL((k_gb_patch64<TV, SV>), g, dim3{256}, 0, s, static_cast<const TV*>(F), dims, desc, nb0, \
+                     nb1, phi, cv, px, py, M, count, kexp, slot, n0)
+  if (dtype == 0) {
+    if (S == 16) DLS_GBP(float, 16); else if (S == 32) DLS_GBP(float, 32); else DLS_GBP(float, 64);
+  } else {
+    if (S == 16) DLS_GBP(double, 16); else if (S == 32) DLS_GBP(double, 32); else DLS_GBP(double, 64);
+  }
+#undef DLS_GBP
   return hipGetLastError();
 }
 

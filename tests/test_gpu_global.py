@@ -16,8 +16,10 @@ against the FP64 oracle (oracle.globalbasis) on the same seeded fields:
   raw patches exactly where the oracle has them; the compression ratio
   within 1 % of the oracle's own encode; dls_stats agrees with the stream.
 Cases: 2D FP64 blobs (8 x 8 patches), 3D FP32 spectrum with truncated edge
-patches (4^3), 2D FP32 with 16 x 16 patches (M = 256), an odd M (5 x 5),
-every basis kind, targets 1e-2 and 1e-3 (1e-4 on the blobs).
+patches (4^3), 2D FP32 with 16 x 16 patches (M = 256), an odd M (5 x 5,
+two patches per wavefront), 4 x 4 and 3 x 3 patches with ragged edges
+(four patches per wavefront), every basis kind, targets 1e-2 and 1e-3 (1e-4
+on the blobs).
 """
 import os
 import sys
@@ -47,6 +49,12 @@ def _case(name, target):
     elif name == "blobs_f64_40x35x3_p5":
         f = synth.blobs2d(nx=40, ny=35, nt=3, seed=6, nblobs=5)
         kw = dict(nx=40, ny=35, nz=1, nt=3, nvars=1, dtype="f64", px=5, py=5, pz=1)
+    elif name == "blobs_f32_70x45x4_p4":
+        f = synth.blobs2d(nx=70, ny=45, nt=4, seed=8, nblobs=6, dtype=np.float32)
+        kw = dict(nx=70, ny=45, nz=1, nt=4, nvars=1, dtype="f32", px=4, py=4, pz=1)
+    elif name == "blobs_f64_31x26x3_p3":
+        f = synth.blobs2d(nx=31, ny=26, nt=3, seed=9, nblobs=4)
+        kw = dict(nx=31, ny=26, nz=1, nt=3, nvars=1, dtype="f64", px=3, py=3, pz=1)
     else:
         raise KeyError(name)
     return f, odls.Params(window=1, eps=[target] * kw["nvars"], **kw)
@@ -139,7 +147,9 @@ def _check(f, p, kind, seed=7, share=0.99):
 CASES = ([("blobs_f64_64x64x8_p8", k, t) for k in ("svd", "cosine", "random") for t in (1e-2, 1e-3, 1e-4)]
          + [("spec_f32_22x18x16x3_p4_2var", k, t) for k in ("svd", "cosine") for t in (1e-2, 1e-3)]
          + [("blobs_f32_80x72x3_p16", k, 1e-3) for k in ("svd", "cosine", "random")]
-         + [("blobs_f64_40x35x3_p5", k, 1e-3) for k in ("svd", "cosine")])
+         + [("blobs_f64_40x35x3_p5", k, 1e-3) for k in ("svd", "cosine")]
+         + [("blobs_f32_70x45x4_p4", k, t) for k in ("svd", "random") for t in (1e-2, 1e-3)]
+         + [("blobs_f64_31x26x3_p3", k, 1e-3) for k in ("svd", "cosine")])
 
 
 @pytest.mark.parametrize("name,kind,target", CASES, ids=["%s-%s-%g" % c for c in CASES])

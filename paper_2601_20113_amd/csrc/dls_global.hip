@@ -771,7 +771,9 @@ __global__ __launch_bounds__(256) void k_gb_sizes(const BlockDesc* __restrict__ 
   nraw[b] = raw ? int64_t(desc[b].m) * esize : 0;
 }
 
-// One wave per patch-snapshot, four per workgroup.
+// One team of S lanes per patch-snapshot (S = 64, or 32 / 16 for patches
+// of at most that many points), 256 / S per workgroup.
+template <int S>
 __global__ __launch_bounds__(256) void k_gb_compact(const BlockDesc* __restrict__ desc, int64_t nblocks, int M,
                                                     const int32_t* __restrict__ count,
                                                     const uint8_t* __restrict__ slot,
@@ -779,17 +781,17 @@ __global__ __launch_bounds__(256) void k_gb_compact(const BlockDesc* __restrict_
                                                     const int64_t* __restrict__ raw_off, int esize,
                                                     uint16_t* __restrict__ idx_out, int32_t* __restrict__ q_out,
                                                     uint8_t* __restrict__ raw_out) {
-  const int lane = threadIdx.x & 63;
-  const int64_t b = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int lane = int(threadIdx.x) % S;
+  const int64_t b = int64_t(blockIdx.x) * (256 / S) + int(threadIdx.x) / S;
   if (b >= nblocks) return;
   const int c = count[b];
   const uint8_t* s = slot + b * int64_t(8) * M;
   if (c == kGbRaw) {
     const int64_t nb = int64_t(desc[b].m) * esize;
-    for (int64_t j = lane; j < nb; j += 64) raw_out[raw_off[b] + j] = s[j];
+    for (int64_t j = lane; j < nb; j += S) raw_out[raw_off[b] + j] = s[j];
     return;
   }
-  for (int j = lane; j < c; j += 64) {
+  for (int j = lane; j < c; j += S) {
     idx_out[idx_off[b] + j] = reinterpret_cast<const uint16_t*>(s)[j];
     q_out[idx_off[b] + j] = reinterpret_cast<const int32_t*>(s + 4 * int64_t(M))[j];
   }
@@ -972,9 +974,15 @@ hipError_t launch_gb_compact(const BlockDesc* desc, int64_t nblocks, int M, cons
                              const int64_t* idx_off, const int64_t* raw_off, int esize, uint16_t* idx_out,
                              int32_t* q_out, uint8_t* raw_out, hipStream_t s) {
   if (nblocks == 0) return hipSuccess;
-  if ((nblocks + 3) / 4 > int64_t(INT32_MAX)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_gb_compact, dim3{unsigned((nblocks + 3) / 4)}, dim3{256}, 0, s, desc, nblocks, M, count, slot,
-                     idx_off, raw_off, esize, idx_out, q_out, raw_out);
+  const int S = M <= 16 ? 16 : (M <= 32 ? 32 : 64);
+  const int64_t per_wg = 256 / S, nwg = (nblocks + per_wg - 1) / per_wg;
+  if (nwg > int64_t(INT32_MAX)) return hipErrorInvalidValue;
+  const dim3 g{unsigned(nwg)};
+#define DLS_GBC(SV)                                                                                            \
+  hipLaunchKernelGGL((k_gb_compact<SV>), g, dim3{256}, 0, s, desc, nblocks, M, count, slot, idx_off, raw_off, \
+                     esize, idx_out, q_out, raw_out)
+  if (S == 16) DLS_GBC(16); else if (S == 32) DLS_GBC(32); else DLS_GBC(64);
+#undef DLS_GBC
   return hipGetLastError();
 }
 

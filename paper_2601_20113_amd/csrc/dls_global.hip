@@ -436,7 +436,8 @@ __global__ __launch_bounds__(256) void k_gb_select(const T* __restrict__ F, Dims
                                                    const double* __restrict__ phi_all, const double* __restrict__ cv,
                                                    const double* __restrict__ alpha, int px, int py, int M, int Mpow,
                                                    int32_t* __restrict__ count, int32_t* __restrict__ kexp,
-                                                   uint8_t* __restrict__ slot, int32_t* __restrict__ n0_out) {
+                                                   uint8_t* __restrict__ slot, int32_t* __restrict__ n0_out,
+                                                   int64_t off) {
   extern __shared__ __align__(16) unsigned char smem[];
   double* key = reinterpret_cast<double*>(smem);          // Mpow: |alpha| (-1 padding)
   int* idx = reinterpret_cast<int*>(key + Mpow);           // Mpow: basis index
@@ -446,7 +447,7 @@ __global__ __launch_bounds__(256) void k_gb_select(const T* __restrict__ F, Dims
   int* list = flag + M;                                    // M: kept indices ascending
   double* red = reinterpret_cast<double*>(list + M);       // 256
   __shared__ int sh_n, sh_fin, sh_bad;
-  const int64_t b = blockIdx.x;
+  const int64_t b = off + int64_t(blockIdx.x);
   if (b >= nblocks) return;
   const BlockDesc d = desc[b];
   const double* phi = phi_all + int64_t(d.var) * M * M;
@@ -780,9 +781,9 @@ __global__ __launch_bounds__(256) void k_gb_compact(const BlockDesc* __restrict_
                                                     const int64_t* __restrict__ idx_off,
                                                     const int64_t* __restrict__ raw_off, int esize,
                                                     uint16_t* __restrict__ idx_out, int32_t* __restrict__ q_out,
-                                                    uint8_t* __restrict__ raw_out) {
+                                                    uint8_t* __restrict__ raw_out, int64_t off) {
   const int lane = int(threadIdx.x) % S;
-  const int64_t b = int64_t(blockIdx.x) * (256 / S) + int(threadIdx.x) / S;
+  const int64_t b = off + int64_t(blockIdx.x) * (256 / S) + int(threadIdx.x) / S;
   if (b >= nblocks) return;
   const int c = count[b];
   const uint8_t* s = slot + b * int64_t(8) * M;
@@ -797,8 +798,13 @@ __global__ __launch_bounds__(256) void k_gb_compact(const BlockDesc* __restrict_
   }
 }
 
-// The decoder: one workgroup per patch-snapshot.
-template <typename T>
+// Workgroups per launch of the one-patch-per-team kernels: a dispatch's
+// work-item count (workgroups x 256) must stay below 2^32.
+constexpr int64_t kGbLaunchGroups = int64_t(1) << 23;
+
+// The decoder: one team of S lanes per patch-snapshot (S = 256, or 64, 32,
+// 16 for patches of at most that many points), 256 / S per workgroup.
+template <typename T, int S>
 __global__ __launch_bounds__(256) void k_gb_decode(T* __restrict__ F, Dims dims, const BlockDesc* __restrict__ desc,
                                                    int64_t nblocks, const double* __restrict__ phi_all, int px, int py,
                                                    int M, const int32_t* __restrict__ count,
@@ -806,14 +812,16 @@ __global__ __launch_bounds__(256) void k_gb_decode(T* __restrict__ F, Dims dims,
                                                    const int64_t* __restrict__ idx_off,
                                                    const int64_t* __restrict__ raw_off,
                                                    const uint16_t* __restrict__ idx,
-                                                   const int32_t* __restrict__ q, const uint8_t* __restrict__ raw) {
-  const int64_t b = blockIdx.x;
+                                                   const int32_t* __restrict__ q, const uint8_t* __restrict__ raw,
+                                                   int64_t off) {
+  const int tl = int(threadIdx.x) % S;
+  const int64_t b = off + int64_t(blockIdx.x) * (256 / S) + int(threadIdx.x) / S;
   if (b >= nblocks) return;
   const BlockDesc d = desc[b];
   const int c = count[b];
   if (c == 0xFFFF) {
     const T* src = reinterpret_cast<const T*>(raw + raw_off[b]);
-    for (int k = threadIdx.x; k < d.m; k += 256) {
+    for (int k = tl; k < d.m; k += S) {
       const int ix = k % d.px(), jy = (k / d.px()) % d.py(), kz = k / (d.px() * d.py());
       F[fidx(dims, d.var, d.t0, d.z0 + kz, d.y0 + jy, d.x0 + ix)] = src[k];
     }
@@ -823,7 +831,7 @@ __global__ __launch_bounds__(256) void k_gb_decode(T* __restrict__ F, Dims dims,
   const double dd = ldexp(1.0, kexp[b]);
   const uint16_t* li = idx + idx_off[b];
   const int32_t* lq = q + idx_off[b];
-  for (int k = threadIdx.x; k < M; k += 256) {
+  for (int k = tl; k < M; k += S) {
     const int ix = k % px, jy = (k / px) % py, kz = k / (px * py);
     if (ix >= d.px() || jy >= d.py() || kz >= d.pz()) continue;
     double acc = 0.0;
@@ -925,17 +933,20 @@ hipError_t launch_gb_select(int dtype, const void* F, const Dims& dims, const Bl
                             const double* phi, const double* cv, const double* alpha, int px, int py, int M,
                             int32_t* count, int32_t* kexp, uint8_t* slot, int32_t* n0, hipStream_t s) {
   if (nblocks == 0) return hipSuccess;
-  if (nblocks > int64_t(INT32_MAX)) return hipErrorInvalidValue;
   int Mpow = 1;
   while (Mpow < M) Mpow <<= 1;
   const size_t lds = gb_select_lds(M, Mpow);
-  const dim3 g{unsigned(nblocks)};
-  if (dtype == 0)
-    hipLaunchKernelGGL(k_gb_select<float>, g, dim3{256}, lds, s, static_cast<const float*>(F), dims, desc, nblocks,
-                       phi, cv, alpha, px, py, M, Mpow, count, kexp, slot, n0);
-  else
-    hipLaunchKernelGGL(k_gb_select<double>, g, dim3{256}, lds, s, static_cast<const double*>(F), dims, desc, nblocks,
-                       phi, cv, alpha, px, py, M, Mpow, count, kexp, slot, n0);
+  // launches of at most kGbLaunchGroups workgroups (a dispatch holds under
+  // 2^32 work-items)
+  for (int64_t off = 0; off < nblocks; off += kGbLaunchGroups) {
+    const dim3 g{unsigned(std::min<int64_t>(nblocks - off, kGbLaunchGroups))};
+    if (dtype == 0)
+      hipLaunchKernelGGL(k_gb_select<float>, g, dim3{256}, lds, s, static_cast<const float*>(F), dims, desc, nblocks,
+                         phi, cv, alpha, px, py, M, Mpow, count, kexp, slot, n0, off);
+    else
+      hipLaunchKernelGGL(k_gb_select<double>, g, dim3{256}, lds, s, static_cast<const double*>(F), dims, desc,
+                         nblocks, phi, cv, alpha, px, py, M, Mpow, count, kexp, slot, n0, off);
+  }
   return hipGetLastError();
 }
 
@@ -975,14 +986,16 @@ hipError_t launch_gb_compact(const BlockDesc* desc, int64_t nblocks, int M, cons
                              int32_t* q_out, uint8_t* raw_out, hipStream_t s) {
   if (nblocks == 0) return hipSuccess;
   const int S = M <= 16 ? 16 : (M <= 32 ? 32 : 64);
-  const int64_t per_wg = 256 / S, nwg = (nblocks + per_wg - 1) / per_wg;
-  if (nwg > int64_t(INT32_MAX)) return hipErrorInvalidValue;
-  const dim3 g{unsigned(nwg)};
-#define DLS_GBC(SV)                                                                                            \
-  hipLaunchKernelGGL((k_gb_compact<SV>), g, dim3{256}, 0, s, desc, nblocks, M, count, slot, idx_off, raw_off, \
-                     esize, idx_out, q_out, raw_out)
-  if (S == 16) DLS_GBC(16); else if (S == 32) DLS_GBC(32); else DLS_GBC(64);
+  const int64_t per_wg = 256 / S, per_launch = kGbLaunchGroups * per_wg;
+  for (int64_t off = 0; off < nblocks; off += per_launch) {
+    const int64_t n = std::min<int64_t>(nblocks - off, per_launch);
+    const dim3 g{unsigned((n + per_wg - 1) / per_wg)};
+#define DLS_GBC(SV)                                                                                              \
+  hipLaunchKernelGGL((k_gb_compact<SV>), g, dim3{256}, 0, s, desc, nblocks, M, count, slot, idx_off, raw_off,   \
+                     esize, idx_out, q_out, raw_out, off)
+    if (S == 16) DLS_GBC(16); else if (S == 32) DLS_GBC(32); else DLS_GBC(64);
 #undef DLS_GBC
+  }
   return hipGetLastError();
 }
 
@@ -991,14 +1004,23 @@ hipError_t launch_gb_decode(int dtype, void* F, const Dims& dims, const BlockDes
                             const int64_t* idx_off, const int64_t* raw_off, const uint16_t* idx, const int32_t* q,
                             const uint8_t* raw, hipStream_t s) {
   if (nblocks == 0) return hipSuccess;
-  if (nblocks > int64_t(INT32_MAX)) return hipErrorInvalidValue;
-  const dim3 g{unsigned(nblocks)};
-  if (dtype == 0)
-    hipLaunchKernelGGL(k_gb_decode<float>, g, dim3{256}, 0, s, static_cast<float*>(F), dims, desc, nblocks, phi, px,
-                       py, M, count, kexp, idx_off, raw_off, idx, q, raw);
-  else
-    hipLaunchKernelGGL(k_gb_decode<double>, g, dim3{256}, 0, s, static_cast<double*>(F), dims, desc, nblocks, phi, px,
-                       py, M, count, kexp, idx_off, raw_off, idx, q, raw);
+  const int S = M <= 16 ? 16 : (M <= 32 ? 32 : (M <= 64 ? 64 : 256));
+  const int64_t per_wg = 256 / S, per_launch = kGbLaunchGroups * per_wg;
+  for (int64_t off = 0; off < nblocks; off += per_launch) {
+    const int64_t n = std::min<int64_t>(nblocks - off, per_launch);
+    const dim3 g{unsigned((n + per_wg - 1) / per_wg)};
+#define DLS_GBD(TV, SV)                                                                                        \
+  hipLaunchKernelGGL((k_gb_decode<TV, SV>), g, dim3{256}, 0, s, static_cast<TV*>(F), dims, desc, nblocks, phi, \
+                     px, py, M, count, kexp, idx_off, raw_off, idx, q, raw, off)
+    if (dtype == 0) {
+      if (S == 16) DLS_GBD(float, 16); else if (S == 32) DLS_GBD(float, 32);
+      else if (S == 64) DLS_GBD(float, 64); else DLS_GBD(float, 256);
+    } else {
+      if (S == 16) DLS_GBD(double, 16); else if (S == 32) DLS_GBD(double, 32);
+      else if (S == 64) DLS_GBD(double, 64); else DLS_GBD(double, 256);
+    }
+#undef DLS_GBD
+  }
   return hipGetLastError();
 }
 

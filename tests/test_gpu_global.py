@@ -227,3 +227,27 @@ def test_global_graph_replay_equals_eager(kind):
     assert ee.info().jacobi_sweeps == sw_g
     with pytest.raises(dls.DlsError):
         ee.set_graphs(2)
+
+
+def test_global_decode_many_patches():
+    """More patch-snapshots than one dispatch of one-patch workgroups can
+    hold (21 M of 2 x 2 points, above 2^32 / 256): the device decode and the
+    stream decoder write every value (a NaN-filled output keeps none) and
+    meet the target; the two agree bit for bit."""
+    print("case 4096 x 4096 x 5 FP32, 2 x 2 patches", flush=True)
+    from synth import gpu as sg
+    f = torch.empty((1, 5, 1, 4096, 4096), dtype=torch.float32, device="cuda")
+    sg.blobs_into(f[0], nblobs=2048, seed=41)
+    p = dls.Params(nx=4096, ny=4096, nz=1, nt=5, nvars=1, dtype="f32", px=2, py=2, pz=1, window=1, eps=[1e-3],
+                   global_basis=True, basis="svd", seed=3)
+    e = dls.Encoder()
+    e.encode(f, p)
+    assert e.info().nblocks == 5 * 2048 * 2048
+    out = torch.full_like(f, float("nan"))
+    e.decode(out)
+    torch.cuda.synchronize()
+    assert not torch.isnan(out).any().item()
+    d = (f.double() - out.double()).pow(2).sum().sqrt() / f.double().pow(2).sum().sqrt()
+    assert d.item() <= 1e-3, d.item()
+    back = dls.decompress(e.finalize())
+    assert torch.equal(back.view(torch.int32), out.view(torch.int32))

@@ -909,6 +909,10 @@ hipError_t launch_alloc_deferred(const int32_t* list, const unsigned int* count,
   return hipGetLastError();
 }
 
+// Workgroups per dispatch of the one-team-per-slice launches: a dispatch's
+// work-items (workgroups x threads) must stay below 2^32.
+constexpr int64_t kDecodeLaunchItems = int64_t(1) << 23;
+
 int encode_small_limit(int wp, int dtype) { return (wp == 16 && dtype == 0) ? 16 * 4 : 64 * 2; }
 
 hipError_t launch_encode(int wp, int dtype, int cls, const void* F, const Dims& dims, const BlockDesc* desc,
@@ -922,17 +926,30 @@ hipError_t launch_encode(int wp, int dtype, int cls, const void* F, const Dims& 
   const bool small = cls >= kRankClasses;
   const int rc = cls % kRankClasses;
   const int64_t per = small ? ((wp == 16 && dtype == 0) ? 16 : 4) : 1;
-  const int64_t need = (work.count + per - 1) / per;
-  const int64_t grid = work.dcount ? std::min<int64_t>(need, 4096) : need;
-  if (grid == 0) return hipSuccess;
-  const dim3 g{unsigned(grid)};
-#define DLS_ENC_PART(TAG)                                                                                          \
-  (small ? encode_small_##TAG : encode_large_##TAG)(rc, g, s, F, dims, desc, items, list, rank, basis, qv_off, qa_off, \
-                                                    code_off, vc, qv, qa, codes, coef, esc, work)
-  if (wp == 16 && dtype == 0) return DLS_ENC_PART(w16_f32);
-  if (wp == 16) return DLS_ENC_PART(w16_f64);
-  if (dtype == 0) return DLS_ENC_PART(w32_f32);
-  return DLS_ENC_PART(w32_f64);
+#define DLS_ENC_PART(TAG, G, L, W)                                                                                \
+  (small ? encode_small_##TAG : encode_large_##TAG)(rc, G, s, F, dims, desc, items, L, rank, basis, qv_off, qa_off, \
+                                                    code_off, vc, qv, qa, codes, coef, esc, W)
+#define DLS_ENC_ANY(G, L, W)                                       \
+  ((wp == 16 && dtype == 0) ? DLS_ENC_PART(w16_f32, G, L, W)      \
+   : (wp == 16)             ? DLS_ENC_PART(w16_f64, G, L, W)      \
+   : (dtype == 0)           ? DLS_ENC_PART(w32_f32, G, L, W)      \
+                            : DLS_ENC_PART(w32_f64, G, L, W))
+  if (work.dcount) {
+    const int64_t grid = std::min<int64_t>((work.count + per - 1) / per, 4096);
+    if (grid == 0) return hipSuccess;
+    return DLS_ENC_ANY(dim3{unsigned(grid)}, list, work);
+  }
+  // host-driven: one team per slice, in dispatches of at most
+  // kDecodeLaunchItems workgroups (a dispatch holds under 2^32 work-items)
+  const int64_t per_launch = kDecodeLaunchItems * per;
+  for (int64_t off = 0; off < work.count; off += per_launch) {
+    EncodeWork w = work;
+    w.count = std::min<int64_t>(work.count - off, per_launch);
+    const hipError_t e = DLS_ENC_ANY(dim3{unsigned((w.count + per - 1) / per)}, list + off, w);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+#undef DLS_ENC_ANY
 #undef DLS_ENC_PART
 }
 
@@ -956,8 +973,15 @@ hipError_t launch_decode(int wp, int dtype, void* F, const Dims& dims, const Blo
                          const int64_t* qa_off, const int64_t* code_off, const VarConst* vc,
                          const uint8_t* qv, const uint8_t* qa, const uint8_t* codes, hipStream_t s) {
   if (nitems == 0) return hipSuccess;
-  return decode_dispatch(wp, dtype, -1, dim3{unsigned(nitems)}, dim3{256}, s, F, dims, desc, items, nullptr, rank,
-                         qv_off, qa_off, code_off, vc, qv, qa, codes);
+  // one workgroup per slice, in dispatches of at most kDecodeLaunchItems
+  // workgroups (a dispatch holds under 2^32 work-items)
+  for (int64_t off = 0; off < nitems; off += kDecodeLaunchItems) {
+    const int64_t n = std::min<int64_t>(nitems - off, kDecodeLaunchItems);
+    const hipError_t e = decode_dispatch(wp, dtype, -1, dim3{unsigned(n)}, dim3{256}, s, F, dims, desc, items + off,
+                                         nullptr, rank, qv_off, qa_off, code_off, vc, qv, qa, codes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_decode_class(int wp, int dtype, int rc, bool small, const int32_t* list, int64_t count, void* F,
@@ -970,8 +994,14 @@ hipError_t launch_decode_class(int wp, int dtype, int rc, bool small, const int3
   // covers the class's slices in one pass (FP32 at W <= 16: 64 points), as
   // the encode does; otherwise one wave per small slice
   const bool team = small && wp == 16 && dtype == 0;
-  return decode_dispatch(wp, dtype, rc, dim3{unsigned(count)}, dim3{small ? 64u : 256u}, s, F, dims, desc, items,
-                         list, rank, qv_off, qa_off, code_off, vc, qv, qa, codes, count, team);
+  for (int64_t off = 0; off < count; off += kDecodeLaunchItems) {
+    const int64_t n = std::min<int64_t>(count - off, kDecodeLaunchItems);
+    const hipError_t e = decode_dispatch(wp, dtype, rc, dim3{unsigned(n)}, dim3{small ? 64u : 256u}, s, F, dims,
+                                         desc, items, list + off, rank, qv_off, qa_off, code_off, vc, qv, qa, codes,
+                                         n, team);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_scatter_keys(int dtype, void* F, const Dims& dims, const BlockDesc* desc, const uint64_t* key,

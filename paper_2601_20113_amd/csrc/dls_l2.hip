@@ -30,12 +30,15 @@
 // reconstruction identically.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "dls_device.h"
 #include "dls_kernels.h"
 
 namespace dls {
 namespace {
 
+constexpr int64_t kL2LaunchItems = int64_t(1) << 23;
 constexpr double kL2TailShare = 0.36;
 constexpr double kL2StepShare = 0.4;
 constexpr double kL2BasisScale = 16777216.0;       // 2^24
@@ -481,15 +484,20 @@ __global__ __launch_bounds__(256) void k_l2_decode(T* __restrict__ F, Dims dims,
 
 hipError_t launch_l2_gram(int wp, int dtype, const void* F, const Dims& dims, const BlockDesc* desc,
                           const Item* items, int64_t nitems, double* gpart, double* fsq, hipStream_t s) {
-  if (nitems == 0) return hipSuccess;
-  if (nitems > int64_t(INT32_MAX)) return hipErrorInvalidValue;
-  const dim3 g{unsigned(nitems)}, bl{256};
-#define DLS_L2G(WPV, TV)                                                                                         \
-  hipLaunchKernelGGL((k_l2_gram<WPV, TV>), g, bl, 0, s, static_cast<const TV*>(F), dims, desc, items, nitems, \
-                     gpart, fsq)
-  if (wp == 16) { if (dtype == 0) DLS_L2G(16, float); else DLS_L2G(16, double); }
-  else { if (dtype == 0) DLS_L2G(32, float); else DLS_L2G(32, double); }
+  // one workgroup per slice, in dispatches of at most kL2LaunchItems
+  // workgroups (a dispatch holds under 2^32 work-items)
+  for (int64_t off = 0; off < nitems; off += kL2LaunchItems) {
+    const int64_t n = std::min<int64_t>(nitems - off, kL2LaunchItems);
+    const dim3 g{unsigned(n)}, bl{256};
+    const Item* it = items + off;
+    double* gp = gpart + off * wp * wp;
+    double* fs = fsq + off;
+#define DLS_L2G(WPV, TV) \
+  hipLaunchKernelGGL((k_l2_gram<WPV, TV>), g, bl, 0, s, static_cast<const TV*>(F), dims, desc, it, n, gp, fs)
+    if (wp == 16) { if (dtype == 0) DLS_L2G(16, float); else DLS_L2G(16, double); }
+    else { if (dtype == 0) DLS_L2G(32, float); else DLS_L2G(32, double); }
 #undef DLS_L2G
+  }
   return hipGetLastError();
 }
 
@@ -517,14 +525,18 @@ hipError_t launch_l2_encode(int wp, int dtype, const void* F, const Dims& dims, 
                             const double* basis, const int64_t* qv_off, const int64_t* qa_off, uint8_t* qv,
                             uint8_t* qa, uint8_t* overflow, double* errp, hipStream_t s) {
   if (nitems == 0) return hipSuccess;
-  if (nitems > int64_t(INT32_MAX)) return hipErrorInvalidValue;
-  const dim3 g{unsigned(nitems)}, bl{256};
-#define DLS_L2E(WPV, TV)                                                                                           \
-  hipLaunchKernelGGL((k_l2_encode<WPV, TV>), g, bl, 0, s, static_cast<const TV*>(F), dims, desc, items, nitems,   \
-                     l2rank, step, basis, qv_off, qa_off, qv, qa, overflow, errp)
-  if (wp == 16) { if (dtype == 0) DLS_L2E(16, float); else DLS_L2E(16, double); }
-  else { if (dtype == 0) DLS_L2E(32, float); else DLS_L2E(32, double); }
+  for (int64_t off = 0; off < nitems; off += kL2LaunchItems) {
+    const int64_t n = std::min<int64_t>(nitems - off, kL2LaunchItems);
+    const dim3 g{unsigned(n)}, bl{256};
+    const Item* it = items + off;
+    double* ep = errp + off;
+#define DLS_L2E(WPV, TV)                                                                                   \
+  hipLaunchKernelGGL((k_l2_encode<WPV, TV>), g, bl, 0, s, static_cast<const TV*>(F), dims, desc, it, n, \
+                     l2rank, step, basis, qv_off, qa_off, qv, qa, overflow, ep)
+    if (wp == 16) { if (dtype == 0) DLS_L2E(16, float); else DLS_L2E(16, double); }
+    else { if (dtype == 0) DLS_L2E(32, float); else DLS_L2E(32, double); }
 #undef DLS_L2E
+  }
   return hipGetLastError();
 }
 
@@ -541,14 +553,17 @@ hipError_t launch_l2_decode(int wp, int dtype, void* F, const Dims& dims, const 
                             int64_t nitems, const uint8_t* l2rank, const double* step, const int64_t* qv_off,
                             const int64_t* qa_off, const uint8_t* qv, const uint8_t* qa, hipStream_t s) {
   if (nitems == 0) return hipSuccess;
-  if (nitems > int64_t(INT32_MAX)) return hipErrorInvalidValue;
-  const dim3 g{unsigned(nitems)}, bl{256};
-#define DLS_L2D(WPV, TV)                                                                                            \
-  hipLaunchKernelGGL((k_l2_decode<WPV, TV>), g, bl, 0, s, static_cast<TV*>(F), dims, desc, items, nitems, l2rank,  \
-                     step, qv_off, qa_off, qv, qa)
-  if (wp == 16) { if (dtype == 0) DLS_L2D(16, float); else DLS_L2D(16, double); }
-  else { if (dtype == 0) DLS_L2D(32, float); else DLS_L2D(32, double); }
+  for (int64_t off = 0; off < nitems; off += kL2LaunchItems) {
+    const int64_t n = std::min<int64_t>(nitems - off, kL2LaunchItems);
+    const dim3 g{unsigned(n)}, bl{256};
+    const Item* it = items + off;
+#define DLS_L2D(WPV, TV)                                                                                          \
+  hipLaunchKernelGGL((k_l2_decode<WPV, TV>), g, bl, 0, s, static_cast<TV*>(F), dims, desc, it, n, l2rank, step, \
+                     qv_off, qa_off, qv, qa)
+    if (wp == 16) { if (dtype == 0) DLS_L2D(16, float); else DLS_L2D(16, double); }
+    else { if (dtype == 0) DLS_L2D(32, float); else DLS_L2D(32, double); }
 #undef DLS_L2D
+  }
   return hipGetLastError();
 }
 

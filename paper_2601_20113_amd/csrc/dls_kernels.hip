@@ -816,6 +816,10 @@ hipError_t launch_totals(const int64_t* qv_off, const int64_t* qv_size, const in
   return hipGetLastError();
 }
 
+// Workgroups per dispatch of the one-team-per-slice launches: a dispatch's
+// work-items (workgroups x threads) must stay below 2^32.
+constexpr int64_t kDecodeLaunchItems = int64_t(1) << 23;
+
 hipError_t launch_gram(int wp, int dtype, bool bf16, const void* F, const Dims& dims, const BlockDesc* desc,
                        const Item* items, int64_t nitems, const GramSplit* split, double* gpart, hipStream_t s) {
   if (nitems == 0) return hipSuccess;
@@ -824,23 +828,40 @@ hipError_t launch_gram(int wp, int dtype, bool bf16, const void* F, const Dims& 
   // slices do and the small ones share workgroups, one wave each
   const int32_t* list = split ? split->large : nullptr;
   const int64_t nlarge = split ? split->nlarge : nitems;
-  const dim3 g{unsigned(nlarge)}, gs{unsigned(split ? (split->nsmall + 3) / 4 : 0)};
-#define DLS_GRAM(WPV, TV, BFV)                                                                              \
-  do {                                                                                                      \
-    if (nlarge)                                                                                             \
-      hipLaunchKernelGGL((k_gram<WPV, TV, BFV>), g, bl, 0, s, (const TV*)F, dims, desc, items, list, gpart); \
-    if (split && split->nsmall)                                                                             \
-      hipLaunchKernelGGL((k_gram_wave<WPV, TV, BFV>), gs, bl, 0, s, (const TV*)F, dims, desc, items,        \
-                         split->small, split->nsmall, gpart);                                               \
-  } while (0)
-  if (wp == 16) {
-    if (dtype == 0) { if (bf16) DLS_GRAM(16, float, true); else DLS_GRAM(16, float, false); }
-    else { if (bf16) DLS_GRAM(16, double, true); else DLS_GRAM(16, double, false); }
-  } else {
-    if (dtype == 0) { if (bf16) DLS_GRAM(32, float, true); else DLS_GRAM(32, float, false); }
-    else { if (bf16) DLS_GRAM(32, double, true); else DLS_GRAM(32, double, false); }
-  }
+  const int64_t nsmall = split ? split->nsmall : 0;
+  // launches of at most kDecodeLaunchItems workgroups (a dispatch holds
+  // under 2^32 work-items) over consecutive ranges of the lists; without a
+  // list the items (and their Gram partials) are shifted instead
+  for (int64_t off = 0; off < nlarge; off += kDecodeLaunchItems) {
+    const dim3 g{unsigned(std::min<int64_t>(nlarge - off, kDecodeLaunchItems))};
+    const Item* it = list ? items : items + off;
+    const int32_t* li = list ? list + off : nullptr;
+    double* gp = list ? gpart : gpart + off * wp * wp;
+#define DLS_GRAM(WPV, TV, BFV) hipLaunchKernelGGL((k_gram<WPV, TV, BFV>), g, bl, 0, s, (const TV*)F, dims, desc, it, li, gp)
+    if (wp == 16) {
+      if (dtype == 0) { if (bf16) DLS_GRAM(16, float, true); else DLS_GRAM(16, float, false); }
+      else { if (bf16) DLS_GRAM(16, double, true); else DLS_GRAM(16, double, false); }
+    } else {
+      if (dtype == 0) { if (bf16) DLS_GRAM(32, float, true); else DLS_GRAM(32, float, false); }
+      else { if (bf16) DLS_GRAM(32, double, true); else DLS_GRAM(32, double, false); }
+    }
 #undef DLS_GRAM
+  }
+  for (int64_t off = 0; off < nsmall; off += 4 * kDecodeLaunchItems) {
+    const int64_t n = std::min<int64_t>(nsmall - off, 4 * kDecodeLaunchItems);
+    const dim3 gs{unsigned((n + 3) / 4)};
+    const int32_t* li = split->small + off;
+#define DLS_GRAMW(WPV, TV, BFV) \
+  hipLaunchKernelGGL((k_gram_wave<WPV, TV, BFV>), gs, bl, 0, s, (const TV*)F, dims, desc, items, li, n, gpart)
+    if (wp == 16) {
+      if (dtype == 0) { if (bf16) DLS_GRAMW(16, float, true); else DLS_GRAMW(16, float, false); }
+      else { if (bf16) DLS_GRAMW(16, double, true); else DLS_GRAMW(16, double, false); }
+    } else {
+      if (dtype == 0) { if (bf16) DLS_GRAMW(32, float, true); else DLS_GRAMW(32, float, false); }
+      else { if (bf16) DLS_GRAMW(32, double, true); else DLS_GRAMW(32, double, false); }
+    }
+#undef DLS_GRAMW
+  }
   return hipGetLastError();
 }
 
@@ -908,10 +929,6 @@ hipError_t launch_alloc_deferred(const int32_t* list, const unsigned int* count,
                      qa_size, counters, qv_base, qa_base, qv_off, qa_off);
   return hipGetLastError();
 }
-
-// Workgroups per dispatch of the one-team-per-slice launches: a dispatch's
-// work-items (workgroups x threads) must stay below 2^32.
-constexpr int64_t kDecodeLaunchItems = int64_t(1) << 23;
 
 int encode_small_limit(int wp, int dtype) { return (wp == 16 && dtype == 0) ? 16 * 4 : 64 * 2; }
 

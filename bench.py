@@ -266,6 +266,65 @@ def train_model(cfg, log):
     return model
 
 
+def run_learned(log, n_train=200000, reps=7):
+    """The learned warm start at its configured size: the network trained on
+    n_train blocks that the plain GPU method encodes from config-1 fields
+    (seed A = 100000 + i), evaluated on 256 unseen config-1 fields (seed B =
+    200000 + i) against the plain eigensolve and a fixed (non-learned) guess
+    of the same warm start; eigensolve-stage times are medians of `reps`
+    encodes."""
+    import numpy as np
+    import torch
+    import paper_2601_20113_amd as dls
+    from paper_2601_20113_amd import train as T
+    t0 = time.perf_counter()
+    nf = (n_train + 127) // 128
+    model, data, losses = T.fit(np.arange(100000, 100000 + nf), epochs=12, batch=512, lr=2e-3, seed=1)
+    train_s = time.perf_counter() - t0
+    f, eps = T.c1_fields(np.arange(200000, 200256))
+    nv, nt, nz, ny, nx = f.shape
+    t = torch.from_numpy(f).cuda()
+    base = dict(nx=nx, ny=ny, nz=nz, nt=nt, nvars=nv, dtype="f64", px=8, py=8, pz=1, window=16, eps=eps)
+    enc = dls.Encoder()
+
+    def timed(p):
+        enc.encode(t, p)
+        ms = []
+        for _ in range(reps):
+            enc.encode(t, p)
+            ms.append(enc.info().stage_ms[2])
+        inf = enc.info()
+        ranks = dls.d2h(inf.d_rank, inf.nblocks).copy()
+        return float(np.median(ms)), inf, ranks, len(enc.finalize())
+
+    ms_p, inf_p, r_p, n_p = timed(dls.Params(**base))
+    enc.set_model(model, 2, margin=1)
+    ms_l, inf_l, r_l, n_l = timed(dls.Params(**base, learned=True))
+    fixed = dls.Model()
+    P = np.zeros(dls.NPARAM, np.float32)
+    ob3 = 80 * 128 + 128 + 128 * 128 + 128 + 128 * 272
+    P[ob3 + 2] = 10.0  # rank 3 for every block, the identity's first columns as the guess
+    for k in range(16):
+        P[ob3 + 16 + 17 * k] = 1.0
+    fixed.set(P, np.concatenate([np.zeros(16), np.ones(16)]).astype(np.float32))
+    enc.set_model(fixed, 2, margin=0)
+    ms_f, inf_f, r_f, n_f = timed(dls.Params(**base, learned=True))
+    enc.close()
+    nb = int(inf_p.nblocks)
+    e = {"workload": "config 4: MLP 3 x 128, trained on %d labelled blocks of config-1 fields (seed A), "
+                     "evaluated on 256 config-1 fields (seed B, %d blocks)" % (int(data["feat"].shape[0]), nb),
+         "train_s": round(train_s, 2), "loss_first": round(losses[0], 4), "loss_last": round(losses[-1], 4),
+         "eigen_ms": {"plain": round(ms_p, 4), "learned": round(ms_l, 4), "fixed_guess": round(ms_f, 4)},
+         "warm_accepted": {"learned": int(inf_l.nwarm_accept), "fixed_guess": int(inf_f.nwarm_accept)},
+         "rank_agreement_with_plain": round(float(np.mean(r_p == r_l)), 4),
+         "mean_rank": {"plain": round(float(np.mean(r_p)), 3), "learned": round(float(np.mean(r_l)), 3),
+                       "fixed_guess": round(float(np.mean(r_f)), 3)},
+         "compression_ratio": {"plain": round(f.nbytes / n_p, 3), "learned": round(f.nbytes / n_l, 3),
+                               "fixed_guess": round(f.nbytes / n_f, 3)}}
+    log("learned (config 4): %s" % e)
+    return e
+
+
 def run_form(field, cfg, eps, form, steps, warmup, model, log):
     """Time `steps` encodes (after `warmup`) between device synchronizations;
     returns the wall time per step and the averages of the library's own
@@ -608,6 +667,8 @@ def main():
                     help="NRMSE targets of the L2-bounded mode measured on the headline field (empty: skip)")
     ap.add_argument("--no-global", action="store_true",
                     help="skip the global-basis mode (its throughput and the basis study)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned warm start at its configured training size")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 4 GiB device-to-device copy twice (the reference the "
                          "HBM byte counters are scaled by) and exit")
@@ -748,6 +809,11 @@ def main():
         torch.cuda.empty_cache()
         out["global"] = run_global(min(args.steps, 3), 1, args.no_ratio, log)
         field = None
+
+    if not args.no_learned:
+        field = None
+        torch.cuda.empty_cache()
+        out["learned"] = run_learned(log)
 
     # the drift variant: every mode's phase advances per step, so windows
     # have ranks above 1 (the literal generator is rank 1 in time)

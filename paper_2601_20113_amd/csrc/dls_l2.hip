@@ -92,7 +92,11 @@ __global__ __launch_bounds__(256) void k_l2_gram(const T* __restrict__ F, Dims d
                                                  const Item* __restrict__ items, int64_t nitems,
                                                  double* __restrict__ gpart, double* __restrict__ fsq) {
   constexpr int NT = WP == 16 ? 1 : 3;  // tiles 00 (and 01, 11)
-  __shared__ f64x4 red[4][NT][64];
+  constexpr int LDR = 68;                // staged row: 64 points + 4 floats of padding
+  constexpr size_t kStage = size_t(4) * WP * LDR * sizeof(float);
+  constexpr size_t kRed = size_t(4) * NT * 64 * sizeof(f64x4);
+  __shared__ __align__(16) char smem[kStage > kRed ? kStage : kRed];
+  f64x4 (*red)[NT][64] = reinterpret_cast<f64x4 (*)[NT][64]>(smem);
   __shared__ double fred[4];
   const int64_t i = blockIdx.x;
   if (i >= nitems) return;
@@ -111,22 +115,80 @@ __global__ __launch_bounds__(256) void k_l2_gram(const T* __restrict__ F, Dims d
 #pragma unroll
   for (int a = 0; a < NT; ++a) acc[a] = f64x4{0.0, 0.0, 0.0, 0.0};
   double fs = 0.0;
-  for (int c = wave * 16; c < it.np; c += 64) {
-    const int pb = c + 4 * slot;
-    double x0[4], x1[4];
-    l2_load4(row0, it.p0, pb, it.np, cont, px, py, dims.nx, nxy, x0);
-    if (WP == 32) l2_load4(row1, it.p0, pb, it.np, cont, px, py, dims.nx, nxy, x1);
+  if (sizeof(T) == 4 && cont) {
+    // FP32 rows of 4-aligned points: each load instruction covers 4 time
+    // rows x 64 consecutive points of a chunk (full cache lines), CPW chunks'
+    // loads issued together; a chunk goes through LDS into the MFMA operand
+    // layout (lane (slot, t): row t, points 16 j + 4 slot + e of the chunk,
+    // MFMA 4 j + e)
+    constexpr int CPW = WP == 16 ? 4 : 2;
+    float* stage = reinterpret_cast<float*>(smem) + wave * WP * LDR;
+    const int lr = lane >> 4, lp = 4 * (lane & 15);
+    for (int c0 = wave; c0 * 64 < it.np; c0 += 4 * CPW) {
+      float4 raw[CPW][WP / 4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      fs += isfinite(x0[j]) ? x0[j] * x0[j] : 0.0;
-      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[j], x0[j], acc[0], 0, 0, 0);
-      if (WP == 32) {
-        fs += isfinite(x1[j]) ? x1[j] * x1[j] : 0.0;
-        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[j], x1[j], acc[1], 0, 0, 0);
-        acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[j], x1[j], acc[2], 0, 0, 0);
+      for (int u = 0; u < CPW; ++u) {
+        const int ps = (c0 + 4 * u) * 64 + lp;
+        const bool okp = ps < it.np;
+        const int64_t off = point_off(it.p0 + (okp ? ps : 0), px, py, dims.nx, nxy);
+#pragma unroll
+        for (int g = 0; g < WP / 4; ++g) {
+          const int tt = 4 * g + lr;
+          raw[u][g] = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (okp && tt < W)
+            raw[u][g] = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(base) +
+                                                         int64_t(tt) * tstride + off);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < CPW; ++u) {
+        if ((c0 + 4 * u) * 64 >= it.np) continue;
+#pragma unroll
+        for (int g = 0; g < WP / 4; ++g)
+          *reinterpret_cast<float4*>(stage + (4 * g + lr) * LDR + lp) = raw[u][g];
+        wave_sync();
+        double v0[16], v1[16];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float4 a4 = *reinterpret_cast<const float4*>(stage + t * LDR + 16 * j + 4 * slot);
+          v0[4 * j] = a4.x; v0[4 * j + 1] = a4.y; v0[4 * j + 2] = a4.z; v0[4 * j + 3] = a4.w;
+          if (WP == 32) {
+            const float4 b4 = *reinterpret_cast<const float4*>(stage + (16 + t) * LDR + 16 * j + 4 * slot);
+            v1[4 * j] = b4.x; v1[4 * j + 1] = b4.y; v1[4 * j + 2] = b4.z; v1[4 * j + 3] = b4.w;
+          }
+        }
+        wave_sync();
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          fs += isfinite(v0[m]) ? v0[m] * v0[m] : 0.0;
+          acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(v0[m], v0[m], acc[0], 0, 0, 0);
+          if (WP == 32) {
+            fs += isfinite(v1[m]) ? v1[m] * v1[m] : 0.0;
+            acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(v0[m], v1[m], acc[1], 0, 0, 0);
+            acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(v1[m], v1[m], acc[2], 0, 0, 0);
+          }
+        }
+      }
+    }
+  } else {
+    for (int c = wave * 16; c < it.np; c += 64) {
+      const int pb = c + 4 * slot;
+      double x0[4], x1[4];
+      l2_load4(row0, it.p0, pb, it.np, cont, px, py, dims.nx, nxy, x0);
+      if (WP == 32) l2_load4(row1, it.p0, pb, it.np, cont, px, py, dims.nx, nxy, x1);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        fs += isfinite(x0[j]) ? x0[j] * x0[j] : 0.0;
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[j], x0[j], acc[0], 0, 0, 0);
+        if (WP == 32) {
+          fs += isfinite(x1[j]) ? x1[j] * x1[j] : 0.0;
+          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[j], x1[j], acc[1], 0, 0, 0);
+          acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[j], x1[j], acc[2], 0, 0, 0);
+        }
       }
     }
   }
+  __syncthreads();  // every wave is done with its staging area before it becomes `red`
 #pragma unroll
   for (int a = 0; a < NT; ++a) red[wave][a][lane] = acc[a];
   fs = wave_sum(fs);

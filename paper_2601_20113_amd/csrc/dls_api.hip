@@ -776,7 +776,7 @@ dls_status global_encode(dls_ctx* ctx, const void* d_field, const Problem& p, co
   }
   HIP_TRY(ctx->gb_tgt.ensure(size_t(p.nvars) * 8));
   HIP_TRY(ctx->gb_cv.ensure(size_t(p.nvars) * 8));
-  HIP_TRY(ctx->gb_part.ensure((size_t(p.nvars) + 2) * kGbParts * 8));
+  HIP_TRY(ctx->gb_part.ensure((size_t(p.nvars) * kGbSumParts + 2 * kGbParts) * 8));
   HIP_TRY(ctx->gb_norm.ensure(16));
   HIP_TRY(ctx->gb_tot.ensure(32));
   HIP_TRY(ctx->gb_phi.ensure(size_t(p.nvars) * M * M * 8));
@@ -787,7 +787,7 @@ dls_status global_encode(dls_ctx* ctx, const void* d_field, const Problem& p, co
   // bases
   ctx->jacobi_sweeps = ctx->jacobi_unconverged = 0;
   HIP_TRY(hipEventRecord(ctx->evj[0], s));
-  double* normpart = ctx->gb_part.as<double>() + size_t(p.nvars) * kGbParts;
+  double* normpart = ctx->gb_part.as<double>() + size_t(p.nvars) * kGbSumParts;
   for (int v = 0; v < p.nvars; ++v) {
     double* phi = ctx->gb_phi.as<double>() + size_t(v) * M * M;
     if (p.basis == DLS_BASIS_COSINE) {

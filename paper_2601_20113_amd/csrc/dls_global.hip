@@ -73,9 +73,15 @@ __global__ __launch_bounds__(256) void k_gb_sumsq(const T* __restrict__ F, int64
   const int v = blockIdx.y;
   const T* f = F + int64_t(v) * per_var;
   double s = 0.0;
-  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < per_var; i += int64_t(gridDim.x) * 256) {
-    const double x = double(f[i]);
-    if (isfinite(x)) s += x * x;
+  // four loads in flight per thread, added in index order
+  const int64_t stride = int64_t(gridDim.x) * 256;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < per_var; i += 4 * stride) {
+    double x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[u] = i + u * stride < per_var ? double(f[i + u * stride]) : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (isfinite(x[u])) s += x[u] * x[u];
   }
   red[threadIdx.x] = s;
   __syncthreads();
@@ -844,12 +850,12 @@ __global__ __launch_bounds__(256) void k_gb_decode(T* __restrict__ F, Dims dims,
 
 hipError_t launch_gb_budget(int dtype, const void* F, int64_t per_var, int nvars, const double* target,
                             double* part, double* cv, hipStream_t s) {
-  const dim3 g{unsigned(kGbParts), unsigned(nvars)};
+  const dim3 g{unsigned(kGbSumParts), unsigned(nvars)};
   if (dtype == 0)
     hipLaunchKernelGGL(k_gb_sumsq<float>, g, dim3{256}, 0, s, static_cast<const float*>(F), per_var, part);
   else
     hipLaunchKernelGGL(k_gb_sumsq<double>, g, dim3{256}, 0, s, static_cast<const double*>(F), per_var, part);
-  hipLaunchKernelGGL(k_gb_budget, dim3{unsigned((nvars + 63) / 64)}, dim3{64}, 0, s, part, int(kGbParts), target,
+  hipLaunchKernelGGL(k_gb_budget, dim3{unsigned((nvars + 63) / 64)}, dim3{64}, 0, s, part, int(kGbSumParts), target,
                      per_var, nvars, cv);
   return hipGetLastError();
 }

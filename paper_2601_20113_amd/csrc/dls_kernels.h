@@ -205,6 +205,9 @@ constexpr int kL2Raw = 255;
 // (0xFFFF = raw), a step exponent and a slot of 8 M bytes (kept indices u16
 // at 0, coefficients int32 at 4 M, or the raw values) compacted afterwards.
 constexpr int kGbParts = 256;
+// partial sums per variable of the field's sum of squares (enough
+// workgroups to keep HBM busy; the partials are added in a fixed order)
+constexpr int kGbSumParts = 2048;
 constexpr int kGbRaw = 0xFFFF;
 constexpr int kGbMaxM = 1024;
 hipError_t launch_gb_budget(int dtype, const void* F, int64_t per_var, int nvars, const double* target,

@@ -31,10 +31,12 @@
 //   k_gb_cosine                the DCT-II tensor basis
 //   k_gb_project               alpha = U Phi on the FP64 matrix cores
 //   k_gb_select                per patch: order, count, grooming, exact check
-//   k_gb_patch64               the same with the coefficients, one wave per
-//                              patch of at most 64 points
+//   k_gb_patch64               the same with the coefficients, one team of
+//                              16, 32 or 64 lanes per patch of at most that
+//                              many points
 //   k_gb_compact               the per-patch slots into packed arrays
-//   k_gb_decode                the decoder
+//   k_gb_decode                the decoder (teams as above, or a workgroup
+//                              per patch above 64 points)
 //
 // Compiled with -ffp-contract=off: encoder and decoder must round the
 // reconstruction identically.

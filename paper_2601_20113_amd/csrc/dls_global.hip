@@ -617,15 +617,17 @@ __global__ __launch_bounds__(256) void k_gb_select(const T* __restrict__ F, Dims
 // u_k (points broadcast from LDS in order, FP64 FMA), then its position in
 // the magnitude order (|alpha| descending, index ascending: the number of
 // keys before its own), where it writes its coefficient; the energy rule
-// runs as the sequential recurrence over the sorted values (broadcast from
-// LDS); the kept set is a ballot over basis indices, its ascending list
+// comes from a suffix scan of the sorted values' squares over the team,
+// checked against the sequential recurrence's rounding (which runs when the
+// check fails); the kept set is a ballot over basis indices, its ascending list
 // positions come from the lanes below; the decoder's values are summed over
 // the kept indices in ascending order.  Every cross-lane step is confined
 // to the team (ballots masked to its lanes, sums over its lanes), and every
 // branch that leaves a loop is taken by a whole team.  Same slot layout as
-// k_gb_select.
+// k_gb_select.  Registers are capped for six waves per SIMD (LDS holds
+// seven workgroups per compute unit).
 template <typename T, int S>
-__global__ __launch_bounds__(256) void k_gb_patch64(const T* __restrict__ F, Dims dims,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_gb_patch64(const T* __restrict__ F, Dims dims,
                                                     const BlockDesc* __restrict__ desc, int64_t nb0, int64_t nb1,
                                                     const double* __restrict__ phi_g, const double* __restrict__ cv,
                                                     int px, int py, int M, int32_t* __restrict__ count,
@@ -673,20 +675,54 @@ __global__ __launch_bounds__(256) void k_gb_patch64(const T* __restrict__ F, Dim
     const double key = tl < M ? fabs(a) : -1.0;
     tq[wave][lane] = key;
     wave_sync();
+    // The keys' bit patterns, read as signed 64-bit integers, order like the
+    // keys (all >= 0 but the padding's -1).  While the points' keys are
+    // distinct, the count of larger ones is the position: each point claims
+    // its slot (in xs, free once the coefficients are formed), and a slot
+    // claimed twice or a NaN key sends the team to the count with the index
+    // rule.
+    const long long ik = __double_as_longlong(key);
     int mypos = 0;
 #pragma unroll 8
-    for (int j = 0; j < S; ++j) {
-      const double kj = tq[wave][tb + j];
-      mypos += (kj > key || (kj == key && j < tl)) ? 1 : 0;
+    for (int j = 0; j < S; ++j) mypos += __double_as_longlong(tq[wave][tb + j]) > ik ? 1 : 0;
+    int* own = reinterpret_cast<int*>(&xs[wave][0]);
+    if (tl < M) own[tb + mypos] = tl;
+    wave_sync();
+    if ((__ballot(tl < M && (own[tb + mypos] != tl || isnan(key))) & tmask) != 0) {
+      mypos = 0;
+#pragma unroll 8
+      for (int j = 0; j < S; ++j) {
+        const double kj = tq[wave][tb + j];
+        mypos += (kj > key || (kj == key && j < tl)) ? 1 : 0;
+      }
     }
     sa[wave][tb + mypos] = a;
     wave_sync();
-    // the energy rule: tail from the end, the same recurrence in every lane
-    // of the team, eight sorted values loaded ahead of their additions
+    // the energy rule: n is one more than the last sorted position whose tail
+    // (the squares from it to the end, added from the end one by one)
+    // exceeds tau.  A suffix scan over the team gives every tail at once in
+    // another summation order.  Over the same rounded squares (at most 64)
+    // the two orders differ by at most (63 + 6) u of the total (u = 2^-53),
+    // so a margin of 2^-44 (total + tau) also covers the rounding of
+    // tau +- margin: when no scanned tail lies within it of tau, both orders
+    // put the same positions above tau, and the sequential tails, never
+    // decreasing towards the front, make that set the first n positions.
+    // Otherwise (and for a non-finite total) the recurrence runs as written.
     const double tau = kGbTailShare * e2;
+    const double sv = tl < M ? sa[wave][lane] : 0.0;
+    double tail = sv * sv;
+#pragma unroll
+    for (int o = 1; o < S; o <<= 1) {
+      const double y = __shfl_down(tail, o, S);
+      if (tl + o < S) tail += y;
+    }
+    const double total = __shfl(tail, tb, 64);
+    const double margin = 0x1p-44 * (total + tau);
+    const unsigned long long above = __ballot(tail > tau + margin) & tmask;
+    const bool fast = isfinite(total) && above == (__ballot(tail > tau - margin) & tmask);
+    int n = fast ? __popcll(above) : 0;
     double t = 0.0;
-    int n = 0;
-    bool found = false;
+    bool found = fast;
     for (int j0 = M - 1; j0 >= 0 && !found; j0 -= 8) {
       double v[8];
 #pragma unroll

@@ -673,22 +673,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
     // lane counts the keys that precede its own, which is its position in
     // that total order, and places its coefficient there
     const double key = tl < M ? fabs(a) : -1.0;
-    tq[wave][lane] = key;
+    // The high word of a key's bit pattern, read as a signed integer, never
+    // orders two keys against their order (all are >= 0 but the padding's
+    // -1).  While the points' high words are distinct, the count of larger
+    // ones is the position: each point claims its slot, and a slot claimed
+    // twice (equal high words) or a NaN key sends the team to the count on
+    // the full keys with the index rule.  Words and claims live in xs, free
+    // once the coefficients are formed.
+    int* xw = reinterpret_cast<int*>(&xs[wave][0]);
+    const int hk = __double2hiint(key);
+    xw[64 + lane] = hk;
     wave_sync();
-    // The keys' bit patterns, read as signed 64-bit integers, order like the
-    // keys (all >= 0 but the padding's -1).  While the points' keys are
-    // distinct, the count of larger ones is the position: each point claims
-    // its slot (in xs, free once the coefficients are formed), and a slot
-    // claimed twice or a NaN key sends the team to the count with the index
-    // rule.
-    const long long ik = __double_as_longlong(key);
     int mypos = 0;
-#pragma unroll 8
-    for (int j = 0; j < S; ++j) mypos += __double_as_longlong(tq[wave][tb + j]) > ik ? 1 : 0;
-    int* own = reinterpret_cast<int*>(&xs[wave][0]);
-    if (tl < M) own[tb + mypos] = tl;
+#pragma unroll 16
+    for (int j = 0; j < S; ++j) mypos += xw[64 + tb + j] > hk ? 1 : 0;
+    if (tl < M) xw[tb + mypos] = tl;
     wave_sync();
-    if ((__ballot(tl < M && (own[tb + mypos] != tl || isnan(key))) & tmask) != 0) {
+    if ((__ballot(tl < M && (xw[tb + mypos] != tl || isnan(key))) & tmask) != 0) {
+      tq[wave][lane] = key;
+      wave_sync();
       mypos = 0;
 #pragma unroll 8
       for (int j = 0; j < S; ++j) {

@@ -1144,7 +1144,7 @@ dls_status global_decompress(const uint8_t* in, const StreamHeader& h, const Pla
   HIP_TRY(hipMemcpy(raw.p, g.raw.data(), g.raw.size(), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(phi.p, g.phi.data(), g.phi.size() * 8, hipMemcpyHostToDevice));
   const Dims dims{p.nx, p.ny, p.nz, p.nt};
-  HIP_TRY(launch_gb_decode(p.dtype, d_out, dims, desc.as<BlockDesc>(), nb, phi.as<double>(), p.px, p.py, M,
+  HIP_TRY(launch_gb_decode(p.dtype, d_out, dims, desc.as<BlockDesc>(), nb, p.nvars, phi.as<double>(), p.px, p.py, M,
                            cnt.as<int32_t>(), kexp.as<int32_t>(), ioff.as<int64_t>(), roff.as<int64_t>(),
                            idx.as<uint16_t>(), q.as<int32_t>(), raw.as<uint8_t>(), s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -1967,7 +1967,7 @@ dls_status dls_decode(dls_ctx* ctx, void* d_out, size_t out_bytes, void* stream)
   }
   if (p.flags & DLS_GLOBAL) {
     HIP_TRY(launch_gb_decode(p.dtype, d_out, dims, ctx->desc.as<BlockDesc>(), int64_t(ctx->plan.blocks.size()),
-                             ctx->gb_phi.as<double>(), p.px, p.py, ctx->gb_M, ctx->gb_count.as<int32_t>(),
+                             p.nvars, ctx->gb_phi.as<double>(), p.px, p.py, ctx->gb_M, ctx->gb_count.as<int32_t>(),
                              ctx->gb_kexp.as<int32_t>(), ctx->gb_idx_off.as<int64_t>(), ctx->gb_raw_off.as<int64_t>(),
                              ctx->gb_idx.as<uint16_t>(), ctx->gb_q.as<int32_t>(), ctx->gb_raw.as<uint8_t>(), s));
     return DLS_OK;

@@ -35,8 +35,9 @@
 //                              16, 32 or 64 lanes per patch of at most that
 //                              many points
 //   k_gb_compact               the per-patch slots into packed arrays
-//   k_gb_decode                the decoder (teams as above, or a workgroup
-//                              per patch above 64 points)
+//   k_gb_decode64              the decoder for patches of at most 64 points
+//                              (persistent, Phi in LDS, teams as above)
+//   k_gb_decode                the decoder, a workgroup per patch above 64
 //
 // Compiled with -ffp-contract=off: encoder and decoder must round the
 // reconstruction identically.
@@ -849,8 +850,8 @@ __global__ __launch_bounds__(256) void k_gb_compact(const BlockDesc* __restrict_
 // work-item count (workgroups x 256) must stay below 2^32.
 constexpr int64_t kGbLaunchGroups = int64_t(1) << 23;
 
-// The decoder: one team of S lanes per patch-snapshot (S = 256, or 64, 32,
-// 16 for patches of at most that many points), 256 / S per workgroup.
+// The decoder: one team of S lanes per patch-snapshot, 256 / S per
+// workgroup (launched with S = 256 for patches above 64 points).
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_gb_decode(T* __restrict__ F, Dims dims, const BlockDesc* __restrict__ desc,
                                                    int64_t nblocks, const double* __restrict__ phi_all, int px, int py,
@@ -884,6 +885,61 @@ __global__ __launch_bounds__(256) void k_gb_decode(T* __restrict__ F, Dims dims,
     double acc = 0.0;
     for (int j = 0; j < c; ++j) acc = acc + phi[int64_t(k) * M + li[j]] * (double(lq[j]) * dd);
     F[fidx(dims, d.var, d.t0, d.z0 + kz, d.y0 + jy, d.x0 + ix)] = T(acc);
+  }
+}
+
+// The decoder for patches of at most 64 points: persistent like
+// k_gb_patch64, one launch per variable with its Phi staged once per
+// workgroup in LDS (FP64, rows padded to M + 1), one team of S lanes per
+// patch-snapshot.  The team's lanes load the kept list (indices, and the
+// quantised coefficients times the grid step) into LDS, then team lane k
+// sums its point's terms over the list in order, the arithmetic of
+// k_gb_decode.
+template <typename T, int S>
+__global__ __launch_bounds__(256) void k_gb_decode64(T* __restrict__ F, Dims dims, const BlockDesc* __restrict__ desc,
+                                                     int64_t nb0, int64_t nb1, const double* __restrict__ phi_g,
+                                                     int px, int py, int M, const int32_t* __restrict__ count,
+                                                     const int32_t* __restrict__ kexp,
+                                                     const int64_t* __restrict__ idx_off,
+                                                     const int64_t* __restrict__ raw_off,
+                                                     const uint16_t* __restrict__ idx, const int32_t* __restrict__ q,
+                                                     const uint8_t* __restrict__ raw) {
+  constexpr int NTM = 64 / S;  // teams per wave
+  __shared__ double phi[S * (S + 1)];
+  __shared__ double kv[4][64];
+  __shared__ int kc[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tb = S == 64 ? 0 : lane & ~(S - 1), tl = lane - tb;
+  const int ld = M + 1;
+  for (int e = threadIdx.x; e < M * M; e += 256) phi[(e / M) * ld + e % M] = phi_g[e];
+  __syncthreads();
+  const int ix = tl % px, jy = (tl / px) % py, kz = tl / (px * py);
+  for (int64_t b0 = nb0 + (int64_t(blockIdx.x) * 4 + wave) * NTM; b0 < nb1; b0 += int64_t(gridDim.x) * 4 * NTM) {
+    const int64_t b = b0 + tb / S;
+    if (b >= nb1) continue;  // a whole team (the wave's last teams)
+    const BlockDesc d = desc[b];
+    const int c = count[b];
+    if (c == kGbRaw) {
+      if (tl < d.m) {
+        const int rx = tl % d.px(), ry = (tl / d.px()) % d.py(), rz = tl / (d.px() * d.py());
+        F[fidx(dims, d.var, d.t0, d.z0 + rz, d.y0 + ry, d.x0 + rx)] =
+            reinterpret_cast<const T*>(raw + raw_off[b])[tl];
+      }
+      continue;
+    }
+    const double dd = ldexp(1.0, kexp[b]);
+    if (tl < c) {
+      const int64_t o = idx_off[b];
+      kc[wave][lane] = idx[o + tl];
+      kv[wave][lane] = double(q[o + tl]) * dd;
+    }
+    wave_sync();
+    if (tl < M && ix < d.px() && jy < d.py() && kz < d.pz()) {
+      double acc = 0.0;
+      for (int j = 0; j < c; ++j) acc = acc + phi[tl * ld + kc[wave][tb + j]] * kv[wave][tb + j];
+      F[fidx(dims, d.var, d.t0, d.z0 + kz, d.y0 + jy, d.x0 + ix)] = T(acc);
+    }
+    wave_sync();  // the list is read before the team's next patch writes it
   }
 }
 
@@ -1047,26 +1103,41 @@ hipError_t launch_gb_compact(const BlockDesc* desc, int64_t nblocks, int M, cons
 }
 
 hipError_t launch_gb_decode(int dtype, void* F, const Dims& dims, const BlockDesc* desc, int64_t nblocks,
-                            const double* phi, int px, int py, int M, const int32_t* count, const int32_t* kexp,
-                            const int64_t* idx_off, const int64_t* raw_off, const uint16_t* idx, const int32_t* q,
-                            const uint8_t* raw, hipStream_t s) {
+                            int nvars, const double* phi, int px, int py, int M, const int32_t* count,
+                            const int32_t* kexp, const int64_t* idx_off, const int64_t* raw_off,
+                            const uint16_t* idx, const int32_t* q, const uint8_t* raw, hipStream_t s) {
   if (nblocks == 0) return hipSuccess;
-  const int S = M <= 16 ? 16 : (M <= 32 ? 32 : (M <= 64 ? 64 : 256));
-  const int64_t per_wg = 256 / S, per_launch = kGbLaunchGroups * per_wg;
+  if (M <= 64) {
+    // blocks are variable-major (the plan's order), nblocks / nvars each
+    if (nvars <= 0 || nblocks % nvars != 0) return hipErrorInvalidValue;
+    const int64_t nbv = nblocks / nvars;
+    const int S = M <= 16 ? 16 : (M <= 32 ? 32 : 64);
+    const int64_t per_wg = 4 * (64 / S);
+    const dim3 g{unsigned(std::min<int64_t>((nbv + per_wg - 1) / per_wg, 4096))};
+    for (int v = 0; v < nvars; ++v) {
+      const double* pv = phi + int64_t(v) * M * M;
+#define DLS_GBD(TV, SV)                                                                                         \
+  hipLaunchKernelGGL((k_gb_decode64<TV, SV>), g, dim3{256}, 0, s, static_cast<TV*>(F), dims, desc, v * nbv,    \
+                     (v + 1) * nbv, pv, px, py, M, count, kexp, idx_off, raw_off, idx, q, raw)
+      if (dtype == 0) {
+        if (S == 16) DLS_GBD(float, 16); else if (S == 32) DLS_GBD(float, 32); else DLS_GBD(float, 64);
+      } else {
+        if (S == 16) DLS_GBD(double, 16); else if (S == 32) DLS_GBD(double, 32); else DLS_GBD(double, 64);
+      }
+#undef DLS_GBD
+    }
+    return hipGetLastError();
+  }
+  const int64_t per_wg = 1, per_launch = kGbLaunchGroups * per_wg;
   for (int64_t off = 0; off < nblocks; off += per_launch) {
     const int64_t n = std::min<int64_t>(nblocks - off, per_launch);
     const dim3 g{unsigned((n + per_wg - 1) / per_wg)};
-#define DLS_GBD(TV, SV)                                                                                        \
-  hipLaunchKernelGGL((k_gb_decode<TV, SV>), g, dim3{256}, 0, s, static_cast<TV*>(F), dims, desc, nblocks, phi, \
-                     px, py, M, count, kexp, idx_off, raw_off, idx, q, raw, off)
-    if (dtype == 0) {
-      if (S == 16) DLS_GBD(float, 16); else if (S == 32) DLS_GBD(float, 32);
-      else if (S == 64) DLS_GBD(float, 64); else DLS_GBD(float, 256);
-    } else {
-      if (S == 16) DLS_GBD(double, 16); else if (S == 32) DLS_GBD(double, 32);
-      else if (S == 64) DLS_GBD(double, 64); else DLS_GBD(double, 256);
-    }
-#undef DLS_GBD
+    if (dtype == 0)
+      hipLaunchKernelGGL((k_gb_decode<float, 256>), g, dim3{256}, 0, s, static_cast<float*>(F), dims, desc, nblocks,
+                         phi, px, py, M, count, kexp, idx_off, raw_off, idx, q, raw, off);
+    else
+      hipLaunchKernelGGL((k_gb_decode<double, 256>), g, dim3{256}, 0, s, static_cast<double*>(F), dims, desc,
+                         nblocks, phi, px, py, M, count, kexp, idx_off, raw_off, idx, q, raw, off);
   }
   return hipGetLastError();
 }

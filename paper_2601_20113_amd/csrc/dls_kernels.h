@@ -237,9 +237,9 @@ hipError_t launch_gb_compact(const BlockDesc* desc, int64_t nblocks, int M, cons
                              const int64_t* idx_off, const int64_t* raw_off, int esize, uint16_t* idx_out,
                              int32_t* q_out, uint8_t* raw_out, hipStream_t s);
 hipError_t launch_gb_decode(int dtype, void* F, const Dims& dims, const BlockDesc* desc, int64_t nblocks,
-                            const double* phi, int px, int py, int M, const int32_t* count, const int32_t* kexp,
-                            const int64_t* idx_off, const int64_t* raw_off, const uint16_t* idx, const int32_t* q,
-                            const uint8_t* raw, hipStream_t s);
+                            int nvars, const double* phi, int px, int py, int M, const int32_t* count,
+                            const int32_t* kexp, const int64_t* idx_off, const int64_t* raw_off,
+                            const uint16_t* idx, const int32_t* q, const uint8_t* raw, hipStream_t s);
 hipError_t launch_l2_gram(int wp, int dtype, const void* F, const Dims& dims, const BlockDesc* desc,
                           const Item* items, int64_t nitems, double* gpart, double* fsq, hipStream_t s);
 // range: per variable its slice range [range[2v], range[2v + 1]); part:

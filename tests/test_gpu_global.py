@@ -149,7 +149,12 @@ CASES = ([("blobs_f64_64x64x8_p8", k, t) for k in ("svd", "cosine", "random") fo
          + [("blobs_f32_80x72x3_p16", k, 1e-3) for k in ("svd", "cosine", "random")]
          + [("blobs_f64_40x35x3_p5", k, 1e-3) for k in ("svd", "cosine")]
          + [("blobs_f32_70x45x4_p4", k, t) for k in ("svd", "random") for t in (1e-2, 1e-3)]
-         + [("blobs_f64_31x26x3_p3", k, 1e-3) for k in ("svd", "cosine")])
+         + [("blobs_f64_31x26x3_p3", k, 1e-3) for k in ("svd", "cosine")]
+         # a tight target on padded patches (25 points in teams of 32, 9 in
+         # 16): on some patches the dropped-energy share is so small against
+         # the patch's energy that the team scan's guard sends them to the
+         # sequential recurrence (4 and 1 patches by the oracle's figures)
+         + [(nm, "svd", 1e-6) for nm in ("blobs_f64_40x35x3_p5", "blobs_f64_31x26x3_p3")])
 
 
 @pytest.mark.parametrize("name,kind,target", CASES, ids=["%s-%s-%g" % c for c in CASES])

@@ -890,13 +890,14 @@ __global__ __launch_bounds__(256) void k_gb_decode(T* __restrict__ F, Dims dims,
 
 // The decoder for patches of at most 64 points: persistent like
 // k_gb_patch64, one launch per variable with its Phi staged once per
-// workgroup in LDS (FP64, rows padded to M + 1), one team of S lanes per
-// patch-snapshot.  The team's lanes load the kept list (indices, and the
+// workgroup of 16 wavefronts in LDS (FP64, rows padded to M + 1: two
+// workgroups fill a compute unit's 32 wavefront slots), one team of S lanes
+// per patch-snapshot.  The team's lanes load the kept list (indices, and the
 // quantised coefficients times the grid step) into LDS, then team lane k
 // sums its point's terms over the list in order, the arithmetic of
 // k_gb_decode.
 template <typename T, int S>
-__global__ __launch_bounds__(256) void k_gb_decode64(T* __restrict__ F, Dims dims, const BlockDesc* __restrict__ desc,
+__global__ __launch_bounds__(1024) void k_gb_decode64(T* __restrict__ F, Dims dims, const BlockDesc* __restrict__ desc,
                                                      int64_t nb0, int64_t nb1, const double* __restrict__ phi_g,
                                                      int px, int py, int M, const int32_t* __restrict__ count,
                                                      const int32_t* __restrict__ kexp,
@@ -906,15 +907,15 @@ __global__ __launch_bounds__(256) void k_gb_decode64(T* __restrict__ F, Dims dim
                                                      const uint8_t* __restrict__ raw) {
   constexpr int NTM = 64 / S;  // teams per wave
   __shared__ double phi[S * (S + 1)];
-  __shared__ double kv[4][64];
-  __shared__ int kc[4][64];
+  __shared__ double kv[16][64];
+  __shared__ int kc[16][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tb = S == 64 ? 0 : lane & ~(S - 1), tl = lane - tb;
   const int ld = M + 1;
-  for (int e = threadIdx.x; e < M * M; e += 256) phi[(e / M) * ld + e % M] = phi_g[e];
+  for (int e = threadIdx.x; e < M * M; e += 1024) phi[(e / M) * ld + e % M] = phi_g[e];
   __syncthreads();
   const int ix = tl % px, jy = (tl / px) % py, kz = tl / (px * py);
-  for (int64_t b0 = nb0 + (int64_t(blockIdx.x) * 4 + wave) * NTM; b0 < nb1; b0 += int64_t(gridDim.x) * 4 * NTM) {
+  for (int64_t b0 = nb0 + (int64_t(blockIdx.x) * 16 + wave) * NTM; b0 < nb1; b0 += int64_t(gridDim.x) * 16 * NTM) {
     const int64_t b = b0 + tb / S;
     if (b >= nb1) continue;  // a whole team (the wave's last teams)
     const BlockDesc d = desc[b];
@@ -1112,12 +1113,12 @@ hipError_t launch_gb_decode(int dtype, void* F, const Dims& dims, const BlockDes
     if (nvars <= 0 || nblocks % nvars != 0) return hipErrorInvalidValue;
     const int64_t nbv = nblocks / nvars;
     const int S = M <= 16 ? 16 : (M <= 32 ? 32 : 64);
-    const int64_t per_wg = 4 * (64 / S);
-    const dim3 g{unsigned(std::min<int64_t>((nbv + per_wg - 1) / per_wg, 4096))};
+    const int64_t per_wg = 16 * (64 / S);
+    const dim3 g{unsigned(std::min<int64_t>((nbv + per_wg - 1) / per_wg, 2048))};
     for (int v = 0; v < nvars; ++v) {
       const double* pv = phi + int64_t(v) * M * M;
 #define DLS_GBD(TV, SV)                                                                                         \
-  hipLaunchKernelGGL((k_gb_decode64<TV, SV>), g, dim3{256}, 0, s, static_cast<TV*>(F), dims, desc, v * nbv,    \
+  hipLaunchKernelGGL((k_gb_decode64<TV, SV>), g, dim3{1024}, 0, s, static_cast<TV*>(F), dims, desc, v * nbv,    \
                      (v + 1) * nbv, pv, px, py, M, count, kexp, idx_off, raw_off, idx, q, raw)
       if (dtype == 0) {
         if (S == 16) DLS_GBD(float, 16); else if (S == 32) DLS_GBD(float, 32); else DLS_GBD(float, 64);

@@ -95,13 +95,23 @@ __global__ __launch_bounds__(256) void k_gb_sumsq(const T* __restrict__ F, int64
   if (threadIdx.x == 0) part[int64_t(v) * gridDim.x + blockIdx.x] = red[0];
 }
 
-__global__ void k_gb_budget(const double* __restrict__ part, int nparts, const double* __restrict__ target,
-                            int64_t per_var, int nvars, double* __restrict__ cv) {
-  const int v = int(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (v >= nvars) return;
+// One workgroup per variable: each thread adds its strided share of the
+// partials in order, then a fixed tree (one thread per variable adding the
+// 2048 partials in sequence took ~150 us).
+__global__ __launch_bounds__(256) void k_gb_budget(const double* __restrict__ part, int nparts,
+                                                   const double* __restrict__ target, int64_t per_var, int nvars,
+                                                   double* __restrict__ cv) {
+  __shared__ double red[256];
+  const int v = blockIdx.x;
   double s = 0.0;
-  for (int j = 0; j < nparts; ++j) s += part[int64_t(v) * nparts + j];
-  cv[v] = target[v] * target[v] * s / double(per_var);
+  for (int j = threadIdx.x; j < nparts; j += 256) s += part[int64_t(v) * nparts + j];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (int(threadIdx.x) < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) cv[v] = target[v] * target[v] * red[0] / double(per_var);
 }
 
 // Q[s][i] (S x M, FP64): kind 0 -- the patch of snapshot 0 at the sample's
@@ -953,8 +963,8 @@ hipError_t launch_gb_budget(int dtype, const void* F, int64_t per_var, int nvars
     hipLaunchKernelGGL(k_gb_sumsq<float>, g, dim3{256}, 0, s, static_cast<const float*>(F), per_var, part);
   else
     hipLaunchKernelGGL(k_gb_sumsq<double>, g, dim3{256}, 0, s, static_cast<const double*>(F), per_var, part);
-  hipLaunchKernelGGL(k_gb_budget, dim3{unsigned((nvars + 63) / 64)}, dim3{64}, 0, s, part, int(kGbSumParts), target,
-                     per_var, nvars, cv);
+  hipLaunchKernelGGL(k_gb_budget, dim3{unsigned(nvars)}, dim3{256}, 0, s, part, int(kGbSumParts), target, per_var,
+                     nvars, cv);
   return hipGetLastError();
 }
 
